@@ -1,0 +1,248 @@
+"""FP64 kernel-independent FMM and its discrete adjoint -- TEST INFRASTRUCTURE ONLY.
+
+Follows the four steps of Section 2.2 in order:
+
+1. octree (``tree.build_tree``) and lists (``tree.build_lists``);
+2. upward pass, fine to coarse: a leaf's upward check potential comes from
+   its points, a parent's from its children's equivalent densities (M2M);
+   the upward equivalent density is UC2E applied to the check potential;
+3. downward pass, coarse to fine, from level 2: the downward check potential
+   of a box sums the V-list equivalent densities (M2L), the X-list points and
+   (from level 3) the parent's downward equivalent density (L2L); the
+   downward equivalent density is DC2E applied to it;
+4. leaf evaluation: for a target in leaf B, the downward density of B (from
+   level 2), the upward densities of the W-list boxes and the points of the
+   U-list leaves (pairs at distance zero skipped).
+
+Sources carry a monopole s_j and optionally a dipole m_j (the dipole sources
+are what the adjoint needs); targets receive the potential, E = -grad and, on
+request, the Hessian of the potential.
+
+The discrete adjoint (``vjp``) uses that the discrete operator u = A(x) q is
+symmetric under the chosen surfaces (uc and de coincide, ue and dc coincide,
+DC2E = UC2E^T, M2M and L2L are transposes, V-list pairs come in +-d, W and X
+are transposes, P2P is symmetric): for L = sum ubar.u + Ebar.E,
+    qbar = psi,   xbar_k = -ubar_k E_k - H_k Ebar_k + q_k grad psi(x_k),
+psi being the FMM of monopoles ubar and dipoles Ebar and H the FMM Hessian of
+the forward potential.  Both are plain calls of the forward sweep.
+"""
+from __future__ import annotations
+
+import dataclasses
+from collections import defaultdict
+from typing import Optional
+
+import numpy as np
+
+from . import pairsum
+from .direct import KERNELS, hess_times
+from .operators import (RHO_DC, RHO_DE, RHO_UC, RHO_UE, TAU, Operators, field_matrices,
+                        hessian_matrices, kernel_matrix, surface)
+from .tree import Lists, Tree, build_lists, build_tree
+
+
+@dataclasses.dataclass
+class Plan:
+    tree: Tree
+    lists: Lists
+    kernel: str
+    c: float
+    p: int
+    tau: float
+    ops: Operators
+    x: np.ndarray            # sorted positions [N,3] FP64
+
+    @property
+    def n(self):
+        return self.x.shape[0]
+
+    def with_positions(self, x_caller: np.ndarray) -> "Plan":
+        """Same (frozen) tree, lists and operators; new positions."""
+        xs = np.asarray(x_caller, dtype=np.float64)[self.tree.perm]
+        return dataclasses.replace(self, x=xs)
+
+
+def plan(x, kernel="laplace", p=6, leaf_size=128, adaptive=True, max_depth=21, root=None,
+         tau=TAU) -> Plan:
+    x = np.asarray(x, dtype=np.float64)
+    t = build_tree(x, leaf_size, adaptive, max_depth, root)
+    L = build_lists(t)
+    c = KERNELS[kernel]
+    return Plan(t, L, kernel, c, p, tau, Operators(p, c, t.s, tau), x[t.perm])
+
+
+def _octant(anchor):
+    return int(((anchor[0] & 1) << 2) | ((anchor[1] & 1) << 1) | (anchor[2] & 1))
+
+
+def upward(P: Plan, s: np.ndarray, m: Optional[np.ndarray]) -> np.ndarray:
+    """Upward equivalent densities phi_u [B, n] (zero above level 2)."""
+    t, ops, c = P.tree, P.ops, P.c
+    phi = np.zeros((t.nboxes, ops.n))
+    for l in range(t.depth, 1, -1):
+        w = ops.w(l)
+        boxes = np.arange(t.level_start[l], t.level_start[l + 1])
+        psi = np.zeros((boxes.shape[0], ops.n))
+        for r, b in enumerate(boxes):
+            if not t.is_leaf[b]:
+                continue
+            b0, b1 = t.begin[b], t.end[b]
+            uc = surface(P.p, RHO_UC, t.center(b), w)
+            psi[r] = kernel_matrix(uc, P.x[b0:b1], c) @ s[b0:b1]
+            if m is not None:
+                G = field_matrices(uc, P.x[b0:b1], c)
+                psi[r] -= sum(G[a] @ m[b0:b1, a] for a in range(3))
+        for o in range(8):
+            ch = t.children[boxes, o]
+            rows = np.nonzero(ch >= 0)[0]
+            if rows.size:
+                psi[rows] += phi[ch[rows]] @ ops.m2m(l, o).T
+        phi[boxes] = psi @ ops.uc2e(l).T
+    return phi
+
+
+def downward(P: Plan, s, m, phi_u, needed: np.ndarray) -> np.ndarray:
+    """Downward equivalent densities phi_d [B, n] for the boxes flagged in ``needed``."""
+    t, ops, c, L = P.tree, P.ops, P.c, P.lists
+    phi = np.zeros((t.nboxes, ops.n))
+    for l in range(2, t.depth + 1):
+        w = ops.w(l)
+        boxes = np.arange(t.level_start[l], t.level_start[l + 1])
+        boxes = boxes[needed[boxes]]
+        if boxes.size == 0:
+            continue
+        psi = np.zeros((boxes.shape[0], ops.n))
+        # V list, grouped by the offset between source and target
+        groups = defaultdict(lambda: ([], []))
+        for r, b in enumerate(boxes):
+            for a in L.V[b]:
+                d = tuple(int(v) for v in (t.anchor[a] - t.anchor[b]))
+                groups[d][0].append(r)
+                groups[d][1].append(a)
+        for d, (rows, srcs) in groups.items():
+            np.add.at(psi, np.array(rows), phi_u[np.array(srcs)] @ ops.m2l(l, d).T)
+        # X list: source points straight onto the downward check surface
+        for r, b in enumerate(boxes):
+            if not L.X[b]:
+                continue
+            dc = surface(P.p, RHO_DC, t.center(b), w)
+            for a in L.X[b]:
+                a0, a1 = t.begin[a], t.end[a]
+                psi[r] += kernel_matrix(dc, P.x[a0:a1], c) @ s[a0:a1]
+                if m is not None:
+                    G = field_matrices(dc, P.x[a0:a1], c)
+                    psi[r] -= sum(G[k] @ m[a0:a1, k] for k in range(3))
+        # L2L from the parent
+        if l >= 3:
+            par = t.parent[boxes]
+            octs = np.array([_octant(t.anchor[b]) for b in boxes])
+            for o in range(8):
+                rows = np.nonzero(octs == o)[0]
+                if rows.size:
+                    psi[rows] += phi[par[rows]] @ ops.l2l(l - 1, o).T
+        phi[boxes] = psi @ ops.dc2e(l).T
+    return phi
+
+
+def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
+    """FMM outputs at sorted targets (all points by default).
+
+    Returns (u [nt], E [nt,3], H [nt,6] or None) for the sorted indices ``targets``.
+    """
+    t, ops, c, L = P.tree, P.ops, P.c, P.lists
+    s = np.asarray(s, dtype=np.float64)
+    m = None if m is None else np.asarray(m, dtype=np.float64)
+    if targets is None:
+        targets = np.arange(P.n)
+    targets = np.asarray(targets, dtype=np.int64)
+    nt = targets.shape[0]
+    leaves = t.leaves()
+    # leaf of each sorted point
+    leaf_of = np.empty(P.n, dtype=np.int64)
+    for b in leaves:
+        leaf_of[t.begin[b]:t.end[b]] = b
+    tleaf = leaf_of[targets]
+    # boxes whose downward density is needed: ancestors of the target leaves
+    needed = np.zeros(t.nboxes, dtype=bool)
+    for b in np.unique(tleaf):
+        a = int(b)
+        while a >= 0 and not needed[a]:
+            needed[a] = True
+            a = int(t.parent[a])
+    phi_u = upward(P, s, m)
+    phi_d = downward(P, s, m, phi_u, needed)
+
+    u = np.zeros(nt)
+    E = np.zeros((nt, 3))
+    H = np.zeros((nt, 6)) if hess else None
+    order = np.argsort(tleaf, kind="stable")
+    bounds = np.nonzero(np.diff(tleaf[order]))[0] + 1
+    for grp in np.split(order, bounds):
+        if grp.size == 0:
+            continue
+        b = int(tleaf[grp[0]])
+        xt = P.x[targets[grp]]
+        surf, dens = [], []
+        lb = int(t.level[b])
+        if lb >= 2:
+            surf.append(surface(P.p, RHO_DE, t.center(b), ops.w(lb)))
+            dens.append(phi_d[b])
+        for a in L.W[b]:
+            surf.append(surface(P.p, RHO_UE, t.center(a), ops.w(int(t.level[a]))))
+            dens.append(phi_u[a])
+        if not surf:
+            continue
+        S = np.concatenate(surf)
+        D = np.concatenate(dens)
+        u[grp] += kernel_matrix(xt, S, c) @ D
+        G = field_matrices(xt, S, c)
+        for k in range(3):
+            E[grp, k] += G[k] @ D
+        if hess:
+            Hm = hessian_matrices(xt, S, c)
+            for k in range(6):
+                H[grp, k] += Hm[k] @ D
+    uoff, uidx = L.csr("U")
+    un, En, Hn = pairsum.p2p(targets, tleaf, t.begin, t.end, uoff, uidx, P.x, s, m, c, hess)
+    u += un
+    E += En
+    if hess:
+        H += Hn
+    return u, E, H
+
+
+def forward(P: Plan, q, targets=None):
+    """Potential and field in caller order (or at caller indices ``targets``)."""
+    q = np.asarray(q, dtype=np.float64)
+    inv = np.empty_like(P.tree.perm)
+    inv[P.tree.perm] = np.arange(P.n)
+    qs = q[P.tree.perm]
+    if targets is None:
+        u, E, _ = evaluate_sorted(P, qs)
+        out_u = np.empty(P.n)
+        out_E = np.empty((P.n, 3))
+        out_u[P.tree.perm] = u
+        out_E[P.tree.perm] = E
+        return out_u, out_E
+    u, E, _ = evaluate_sorted(P, qs, targets=inv[np.asarray(targets)])
+    return u, E
+
+
+def vjp(P: Plan, q, ubar, Ebar):
+    """Exact vector-Jacobian product of the discrete map (q, x) -> (u, E), frozen tree.
+
+    Returns (qbar [N], xbar [N,3]) in caller order.
+    """
+    perm = P.tree.perm
+    qs = np.asarray(q, dtype=np.float64)[perm]
+    us = np.asarray(ubar, dtype=np.float64)[perm]
+    Es = np.asarray(Ebar, dtype=np.float64).reshape(-1, 3)[perm]
+    _, E, H = evaluate_sorted(P, qs, hess=True)
+    psi, Epsi, _ = evaluate_sorted(P, us, Es)
+    qbar_s = psi
+    xbar_s = -us[:, None] * E - hess_times(H, Es) - qs[:, None] * Epsi
+    qbar = np.empty(P.n)
+    xbar = np.empty((P.n, 3))
+    qbar[perm] = qbar_s
+    xbar[perm] = xbar_s
+    return qbar, xbar

@@ -1,0 +1,144 @@
+"""Pins for the oracle's operators and FMM sweep (CPU only).
+
+KIFMM is an approximation, so it is pinned by what must hold exactly (a
+single leaf is the direct sum; the discrete operator is symmetric, linear and
+scale-covariant; pseudoinverses are projectors; transposition identities of
+the surfaces) and by its approach to the exact direct sum as p grows.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import direct, kifmm
+from oracle import operators as O
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_surface_count_matches_p4_56():
+    assert O.n_surface(4) == 56 == O.surface_grid(4).shape[0]
+    for p in (2, 3, 5, 6, 8):
+        g = O.surface_grid(p)
+        assert g.shape[0] == O.n_surface(p)
+        assert np.all((g.min(axis=1) == 0) | (g.max(axis=1) == 1))
+
+
+@pytest.mark.parametrize("p", [4, 6])
+def test_pseudoinverse_is_projector_and_transposes(p):
+    ops = O.Operators(p, direct.KERNELS["laplace"], 1.0)
+    for l in (2, 3):
+        w = ops.w(l)
+        A = O.kernel_matrix(O.surface(p, O.RHO_UC, 0, w), O.surface(p, O.RHO_UE, 0, w), ops.c)
+        P = ops.uc2e(l) @ A
+        np.testing.assert_allclose(P @ P, P, atol=1e-6)
+        # DC2E is built independently from K(dc, de); the surfaces make it UC2E^T
+        np.testing.assert_allclose(ops.dc2e(l), ops.uc2e(l).T, rtol=0,
+                                   atol=1e-6 * np.abs(ops.uc2e(l)).max())
+        # scale covariance: K at side w/2 is 2 K at side w, so the inverse halves
+        np.testing.assert_allclose(ops.uc2e(l + 1), ops.uc2e(l) / 2, rtol=0,
+                                   atol=1e-6 * np.abs(ops.uc2e(l)).max())
+        for o in range(8):
+            np.testing.assert_allclose(ops.l2l(l, o), ops.m2m(l, o).T, rtol=1e-14)
+        for d in [(2, 0, 0), (3, -1, 2), (-2, -2, -3)]:
+            md = tuple(-v for v in d)
+            np.testing.assert_allclose(ops.m2l(l, d), ops.m2l(l, md).T, rtol=1e-14)
+
+
+def test_equivalent_density_reproduces_far_field():
+    # P2M + UC2E of a box's points, evaluated beyond the check surface
+    p, c = 6, direct.KERNELS["laplace"]
+    ops = O.Operators(p, c, 1.0)
+    rng = np.random.default_rng(0)
+    w = ops.w(3)
+    pts = (rng.random((100, 3)) - 0.5) * w
+    q = rng.standard_normal(100)
+    psi = O.kernel_matrix(O.surface(p, O.RHO_UC, 0, w), pts, c) @ q
+    phi = ops.uc2e(3) @ psi
+    far = rng.standard_normal((50, 3))
+    far *= (2.5 * w / np.abs(far).max(axis=1))[:, None]
+    ref = O.kernel_matrix(far, pts, c) @ q
+    approx = O.kernel_matrix(far, O.surface(p, O.RHO_UE, 0, w), c) @ phi
+    assert rel(approx, ref) < 1e-5
+
+
+def test_single_leaf_is_direct_sum():
+    w = workloads.make(4, n=100)
+    P = kifmm.plan(w.positions, "laplace", 6, 128)
+    u, E = kifmm.forward(P, w.charges)
+    ud, Ed, _ = direct.potential_field(w.positions, w.charges)
+    np.testing.assert_allclose(u, ud, rtol=1e-12)
+    np.testing.assert_allclose(E, Ed, rtol=1e-11)
+
+
+def test_error_decays_with_order():
+    w = workloads.make(1, n=2048)
+    ud, Ed, _ = direct.potential_field(w.positions, w.charges)
+    errs = []
+    for p in (2, 3, 4, 5, 6):
+        P = kifmm.plan(w.positions, "laplace", p, 32, False, 21, w.root)
+        u, E = kifmm.forward(P, w.charges)
+        errs.append(rel(E, Ed))
+    assert all(errs[i + 1] < 0.5 * errs[i] for i in range(len(errs) - 1)), errs
+    assert errs[-1] < 2e-5
+
+
+def test_cfg1_accuracy_p4():
+    w = workloads.make(1)
+    P = kifmm.plan(w.positions, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, w.root)
+    u, E = kifmm.forward(P, w.charges)
+    ud, Ed, _ = direct.potential_field(w.positions, w.charges)
+    assert rel(u, ud) < 3e-4 and rel(E, Ed) < 5e-4
+
+
+def test_adaptive_accuracy_and_reciprocity():
+    w = workloads.make(2, n=6000)
+    P = kifmm.plan(w.positions, "laplace", 6, 32, True, 21, w.root)
+    assert sum(len(x) for x in P.lists.X) > 0
+    u, E = kifmm.forward(P, w.charges)
+    ud, Ed, _ = direct.potential_field(w.positions, w.charges)
+    assert rel(u, ud) < 2e-5 and rel(E, Ed) < 2e-5
+    rng = np.random.default_rng(1)
+    q2 = rng.standard_normal(w.n)
+    u2, _ = kifmm.forward(P, q2)
+    # q1^T A q2 = q2^T A q1: the discrete operator is symmetric
+    a, b = np.dot(w.charges, u2), np.dot(q2, u)
+    assert abs(a - b) <= 1e-10 * max(abs(a), np.linalg.norm(w.charges) * np.linalg.norm(u2))
+    # linearity
+    u3, E3 = kifmm.forward(P, 2.0 * w.charges - 3.0 * q2)
+    _, E2 = kifmm.forward(P, q2)
+    np.testing.assert_allclose(E3, 2 * E - 3 * E2, rtol=0, atol=1e-9 * np.abs(E3).max())
+
+
+def test_scaling_covariance():
+    w = workloads.make(4, n=3000)
+    P1 = kifmm.plan(w.positions, "laplace", 4, 32, True, 21, ((0, 0, 0), 1.0))
+    P2 = kifmm.plan(2.0 * w.positions, "laplace", 4, 32, True, 21, ((0, 0, 0), 2.0))
+    np.testing.assert_array_equal(P1.tree.perm, P2.tree.perm)
+    np.testing.assert_array_equal(P1.tree.begin, P2.tree.begin)
+    u1, E1 = kifmm.forward(P1, w.charges)
+    u2, E2 = kifmm.forward(P2, w.charges)
+    np.testing.assert_allclose(u2, u1 / 2, rtol=1e-9)
+    np.testing.assert_allclose(E2, E1 / 4, rtol=1e-9, atol=1e-12 * np.abs(E1).max())
+
+
+def test_gravity_plummer_accuracy():
+    w = workloads.make(5, n=5000)
+    P = kifmm.plan(w.positions, w.kernel, 6, 64, True, w.max_depth, w.root)
+    u, E = kifmm.forward(P, w.charges)
+    ud, Ed, _ = direct.potential_field(w.positions, w.charges, "gravity")
+    assert rel(u, ud) < 1e-5 and rel(E, Ed) < 2e-5
+    # unit masses attract: the potential is negative everywhere
+    assert np.all(u < 0)
+
+
+def test_sampled_targets_match_full_evaluation():
+    w = workloads.make(2, n=5000)
+    P = kifmm.plan(w.positions, "laplace", 4, 32, True, 21, w.root)
+    u, E = kifmm.forward(P, w.charges)
+    idx = np.random.default_rng(2).choice(w.n, 97, replace=False)
+    us, Es = kifmm.forward(P, w.charges, targets=idx)
+    # same arithmetic up to BLAS blocking of differently sized batches
+    np.testing.assert_allclose(us, u[idx], rtol=0, atol=1e-11 * np.abs(u).max())
+    np.testing.assert_allclose(Es, E[idx], rtol=0, atol=1e-11 * np.abs(E).max())

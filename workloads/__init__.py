@@ -1,0 +1,234 @@
+"""Seeded synthetic inputs for the KIFMM hot path.
+
+This module only draws random numbers and lays out particle sets; it holds
+none of the method's arithmetic.  Both the CPU oracle (in tests) and the GPU
+library (in tests, ``smoke()`` and ``bench.py``) take their inputs from here,
+so that the two sides see bit-identical positions and charges.
+
+Every position and charge is rounded to FP32 and handed out as FP64, so the
+FP32 GPU path and the FP64 oracle start from the same numbers.
+
+The five workloads stand in for the paper's application examples (Section 3:
+charged particles in a box, dipole clumps, clumped platelets, gravitational
+collapse); the paper uses no public dataset.
+
+  cfg1  Laplace, uniform unit cube, charges U[-1,1], p=4, leaf 64, uniform tree
+  cfg2  Laplace, 60 % uniform + 40 % in 20 Gaussian clusters (sigma 0.02),
+        charges N(0,1) with the mean removed, p=6, leaf 128, adaptive tree
+  cfg3  rigid clumps of 8 pebbles on the corners of a cube of edge 0.6 R,
+        R lognormal(ln 0.003, 0.3) rescaled to 30 % bounding-sphere volume
+        fraction, random rotations, random sequential addition packing,
+        pebble charges N(0,1), p=6, leaf 128, adaptive tree
+  cfg4  Laplace, uniform unit cube, charges N(0,1), p=6, leaf 128, adaptive;
+        adjoint loss target built from charges + 0.1 N(0,1)
+  cfg5  gravity, Plummer sphere (a = 0.1, truncated at r = 10 a), unit
+        masses, p=8, leaf 256, adaptive tree, depth <= 12, root [-1,1)^3
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["Workload", "make", "FULL_N", "SEED_BASE", "round_f32", "uniform_cube",
+           "clustered", "plummer", "clumps", "adjoint_target_charges"]
+
+SEED_BASE = 9478
+FULL_N = {1: 4096, 2: 1_048_576, 3: 1_600_000, 4: 524_288, 5: 8_388_608}
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    positions: np.ndarray            # [N,3] float64, FP32-representable
+    charges: np.ndarray              # [N] float64, FP32-representable
+    kernel: str                      # "laplace" or "gravity"
+    p: int
+    leaf_size: int
+    adaptive: bool
+    max_depth: int
+    root: Optional[tuple]            # (lo[3], side) or None for automatic
+    clump_offsets: Optional[np.ndarray] = None   # [C+1] int64, CSR over caller order
+    clump_centers: Optional[np.ndarray] = None   # [C,3] float64
+
+    @property
+    def n(self) -> int:
+        return int(self.positions.shape[0])
+
+
+def round_f32(a: np.ndarray) -> np.ndarray:
+    """Round to the nearest FP32 value and return it as FP64."""
+    return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def _rng(cfg: int, seed: Optional[int]) -> np.random.Generator:
+    return np.random.default_rng(SEED_BASE + cfg if seed is None else seed)
+
+
+def uniform_cube(rng: np.random.Generator, n: int) -> np.ndarray:
+    x = round_f32(rng.random((n, 3)))
+    return np.minimum(x, np.nextafter(1.0, 0.0))   # stay inside [0,1)
+
+
+def clustered(rng: np.random.Generator, n: int, n_clusters: int = 20,
+              sigma: float = 0.02, frac_uniform: float = 0.6) -> np.ndarray:
+    nu = int(round(frac_uniform * n))
+    nc = n - nu
+    xu = rng.random((nu, 3))
+    centres = rng.random((n_clusters, 3))
+    which = rng.integers(0, n_clusters, size=nc)
+    xc = centres[which] + sigma * rng.standard_normal((nc, 3))
+    bad = np.any((xc < 0.0) | (xc >= 1.0), axis=1)
+    while bad.any():                        # resample the tails back into the cube
+        k = int(bad.sum())
+        xc[bad] = centres[which[bad]] + sigma * rng.standard_normal((k, 3))
+        bad = np.any((xc < 0.0) | (xc >= 1.0), axis=1)
+    x = np.concatenate([xu, xc], axis=0)
+    x = round_f32(x)
+    return np.minimum(x, np.nextafter(1.0, 0.0))
+
+
+def plummer(rng: np.random.Generator, n: int, a: float = 0.1, rmax: float = 1.0) -> np.ndarray:
+    out = np.empty((0, 3))
+    while out.shape[0] < n:
+        m = int((n - out.shape[0]) * 1.05) + 16
+        u = rng.random(m)
+        u = u[u > 0.0]
+        r = a / np.sqrt(u ** (-2.0 / 3.0) - 1.0)
+        r = r[r <= rmax]
+        d = rng.standard_normal((r.shape[0], 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        out = np.concatenate([out, d * r[:, None]], axis=0)
+    return round_f32(out[:n])
+
+
+def _random_rotations(rng: np.random.Generator, k: int) -> np.ndarray:
+    """Uniform random rotation matrices from uniform unit quaternions (Shoemake)."""
+    u1, u2, u3 = rng.random(k), rng.random(k), rng.random(k)
+    a = np.sqrt(1.0 - u1)
+    b = np.sqrt(u1)
+    w = a * np.sin(2 * np.pi * u2)
+    x = a * np.cos(2 * np.pi * u2)
+    y = b * np.sin(2 * np.pi * u3)
+    z = b * np.cos(2 * np.pi * u3)
+    R = np.empty((k, 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - z * w)
+    R[:, 0, 2] = 2 * (x * z + y * w)
+    R[:, 1, 0] = 2 * (x * y + z * w)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - x * w)
+    R[:, 2, 0] = 2 * (x * z - y * w)
+    R[:, 2, 1] = 2 * (y * z + x * w)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def _rsa_pack(rng: np.random.Generator, radii: np.ndarray, max_tries: int = 2000) -> np.ndarray:
+    """Random sequential addition of spheres (largest first) inside the unit cube.
+
+    Returns the centres in the order of ``radii``.  A uniform cell grid of side
+    2*max(radii) bounds the overlap checks to the 27 neighbouring cells.
+    """
+    order = np.argsort(-radii, kind="stable")
+    rmax = float(radii.max())
+    cell = 2.0 * rmax
+    g = max(1, int(1.0 / cell))
+    cell = 1.0 / g
+    buckets: dict = {}
+    cen = np.zeros((radii.shape[0], 3))
+    placed_c = []
+    placed_r = []
+    for idx in order:
+        r = float(radii[idx])
+        ok = False
+        for _ in range(max_tries):
+            c = r + (1.0 - 2.0 * r) * rng.random(3)
+            ci = np.minimum((c / cell).astype(int), g - 1)
+            cand = []
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dz in (-1, 0, 1):
+                        lst = buckets.get((ci[0] + dx, ci[1] + dy, ci[2] + dz))
+                        if lst:
+                            cand.extend(lst)
+            if cand:
+                cc = np.asarray([placed_c[j] for j in cand])
+                rr = np.asarray([placed_r[j] for j in cand])
+                if np.any(np.sum((cc - c) ** 2, axis=1) < (rr + r) ** 2):
+                    continue
+            ok = True
+            break
+        if not ok:
+            raise RuntimeError("random sequential addition did not converge")
+        j = len(placed_c)
+        placed_c.append(c)
+        placed_r.append(r)
+        buckets.setdefault((int(ci[0]), int(ci[1]), int(ci[2])), []).append(j)
+        cen[idx] = c
+    return cen
+
+
+def clumps(rng: np.random.Generator, n_clumps: int, phi: float = 0.30,
+           mu: float = math.log(0.003), sigma: float = 0.3):
+    """Rigid 8-pebble clumps (cube corners, edge 0.6 R) packed at volume fraction phi.
+
+    The drawn radii are rescaled by (phi / phi_drawn)^(1/3) so that the bounding
+    spheres fill the requested fraction of the unit cube.
+    Returns (positions [8C,3], offsets [C+1], centres [C,3]).
+    """
+    R = rng.lognormal(mu, sigma, size=n_clumps)
+    phi_drawn = float(np.sum(4.0 / 3.0 * np.pi * R ** 3))
+    R = R * (phi / phi_drawn) ** (1.0 / 3.0)
+    centres = _rsa_pack(rng, R)
+    rot = _random_rotations(rng, n_clumps)
+    corners = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)],
+                       dtype=np.float64) * 0.3
+    local = corners[None, :, :] * R[:, None, None]                 # [C,8,3]
+    pts = centres[:, None, :] + np.einsum("cij,ckj->cki", rot, local)
+    pos = round_f32(pts.reshape(-1, 3))
+    pos = np.clip(pos, 0.0, np.nextafter(1.0, 0.0))
+    offsets = np.arange(0, 8 * n_clumps + 1, 8, dtype=np.int64)
+    return pos, offsets, round_f32(centres)
+
+
+def adjoint_target_charges(charges: np.ndarray, seed: int) -> np.ndarray:
+    """Charges perturbed by 0.1 * N(0,1); the field they produce is the loss target."""
+    rng = np.random.default_rng(seed)
+    return round_f32(charges + 0.1 * rng.standard_normal(charges.shape[0]))
+
+
+def make(cfg: int, n: Optional[int] = None, seed: Optional[int] = None) -> Workload:
+    """Build workload ``cfg`` (1..5) with ``n`` points (default: the full size)."""
+    rng = _rng(cfg, seed)
+    N = FULL_N[cfg] if n is None else int(n)
+    if cfg == 1:
+        x = uniform_cube(rng, N)
+        q = round_f32(rng.uniform(-1.0, 1.0, N))
+        return Workload("cfg1_uniform_p4", x, q, "laplace", 4, 64, False, 21,
+                        ((0.0, 0.0, 0.0), 1.0))
+    if cfg == 2:
+        x = clustered(rng, N)
+        q = rng.standard_normal(N)
+        q = round_f32(q - q.mean())
+        return Workload("cfg2_clustered_p6", x, q, "laplace", 6, 128, True, 21,
+                        ((0.0, 0.0, 0.0), 1.0))
+    if cfg == 3:
+        C = max(1, N // 8)
+        x, off, cen = clumps(rng, C)
+        q = round_f32(rng.standard_normal(x.shape[0]))
+        return Workload("cfg3_clumps_p6", x, q, "laplace", 6, 128, True, 21,
+                        ((0.0, 0.0, 0.0), 1.0), off, cen)
+    if cfg == 4:
+        x = uniform_cube(rng, N)
+        q = round_f32(rng.standard_normal(N))
+        return Workload("cfg4_uniform_p6", x, q, "laplace", 6, 128, True, 21,
+                        ((0.0, 0.0, 0.0), 1.0))
+    if cfg == 5:
+        x = plummer(rng, N)
+        q = np.ones(N)
+        return Workload("cfg5_plummer_p8", x, q, "gravity", 8, 256, True, 12,
+                        ((-1.0, -1.0, -1.0), 2.0))
+    raise ValueError(f"unknown workload {cfg}")
