@@ -1,0 +1,203 @@
+/*
+ * kifmm.h -- C ABI of the MI355X KIFMM library (libkifmm.so).
+ *
+ * The library evaluates the long-range sum of the paper's eq. (1) with
+ * sources equal to targets (Section 2.2): for N points x_i with scalar
+ * charges q_i (the per-particle charge attribute of Section 2.4),
+ *
+ *     u_i = sum_{j : x_j != x_i} K(x_i - x_j) q_j,     E_i = -grad u (x_i),
+ *
+ * with K(r) = c/|r|; c = 1/(4 pi) for the Laplace/Coulomb kernel (the force
+ * q_i E_i is eq. (3)) and c = -1 for gravity with G = 1 (m_i E_i is the
+ * attractive force of eq. (4)).  The sum is approximated by the
+ * kernel-independent fast multipole method of Section 2.2: an octree with at
+ * most M points per leaf, an upward pass (P2M, M2M), a downward pass (M2L,
+ * L2L, plus the adaptive-tree X list) and a leaf evaluation (L2P, the W list
+ * and the near-field P2P), with densities on equivalent surfaces and
+ * translation matrices computed from the kernel.
+ *
+ * Conventions for every entry point
+ *  - All array pointers are DEVICE pointers (HIP global memory) unless the
+ *    comment says "host".  Arrays are dense, row-major, in the caller's point
+ *    order: positions [N][3] double, charges [N] float, field [N][3] float.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    kifmm_setup* synchronises that stream (tree sizes are read back); all
+ *    other calls are asynchronous on it.  One handle must not be used from
+ *    two streams at once.
+ *  - The caller owns every argument buffer; the library keeps no pointer to
+ *    them after the call's work has run on the stream.  The handle owns its
+ *    device copies of the positions, the tree, the lists, the operators and
+ *    the work space, all freed by kifmm_destroy.
+ *  - Outputs are overwritten, never accumulated into.
+ *  - Every int-returning call returns KIFMM_OK (0) or a negative status; no
+ *    C++ exception crosses the ABI.  After an error the handle (if one was
+ *    returned) stays valid for kifmm_destroy.  kifmm_status_string gives a
+ *    message for the last error of the calling thread.
+ */
+#ifndef KIFMM_H
+#define KIFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kifmm_plan* kifmm_handle;
+
+enum kifmm_kernel {
+    KIFMM_LAPLACE = 0,   /* K = 1/(4 pi r): Coulomb, eq. (3) */
+    KIFMM_GRAVITY = 1    /* K = -1/r, G = 1: gravity, eq. (4) */
+};
+
+enum kifmm_precision {
+    KIFMM_FP32 = 0,        /* every far-field product in FP32 (MFMA f32) */
+    KIFMM_SPLIT_BF16 = 1   /* M2L products as bf16 hi/lo splits (three bf16 MFMA
+                              products, FP32 accumulation); all else FP32 */
+};
+
+enum kifmm_status {
+    KIFMM_OK = 0,
+    KIFMM_ERR_ARG = -1,     /* null required pointer, N < 1, p outside 2..8,
+                               leaf_size < 1, max_depth outside 0..21, unknown
+                               kernel or precision, bad root side */
+    KIFMM_ERR_INPUT = -2,   /* non-finite position, point outside the explicit
+                               root, non-monotone clump offsets */
+    KIFMM_ERR_OOM = -3,     /* device allocation failed */
+    KIFMM_ERR_HIP = -4,     /* a HIP runtime error (message kept) */
+    KIFMM_ERR_STATE = -5    /* null handle or an unusable handle */
+};
+
+typedef struct {
+    int adaptive;          /* 1 (default): a box is a leaf when it holds <= leaf_size
+                              points or sits at max_depth.  0: every box at depth
+                              min(max_depth, min{L : leaf_size 8^L >= N}) is a leaf. */
+    int max_depth;         /* deepest level, 0..21 (default 21 = key resolution) */
+    int precision;         /* enum kifmm_precision (default KIFMM_FP32) */
+    double pinv_rtol;      /* singular values below pinv_rtol * sigma_1 are dropped
+                              from the check-to-equivalent pseudoinverses (1e-7) */
+    int explicit_root;     /* 0 (default): root cube from the bounding box; 1: use
+                              root_lo/root_side */
+    double root_lo[3];     /* root corner; must lie on the root_side/4096 grid */
+    double root_side;      /* power of two; every point must satisfy
+                              root_lo <= x <= root_lo + root_side */
+    int profile;           /* 1: record per-phase HIP events on the stream
+                              (kifmm_get_phase_times) */
+} kifmm_options;
+
+/* Fill *opts with the defaults listed above. */
+void kifmm_default_options(kifmm_options* opts);
+
+/*
+ * Build a plan: root cube, Morton keys, radix sort, octree (Section 2.2,
+ * leaves with at most leaf_size = M points), interaction lists, and the
+ * FP64 operator precompute (cached per kernel, p and pinv_rtol).
+ *   positions  device, [N][3] double, caller order; rounded to FP32 for the
+ *              floating-point work, used in FP64 for the integer keys.
+ *   N          number of points (>= 1).
+ *   kernel     enum kifmm_kernel.
+ *   p          surface order 2..8: n = 6 (p-1)^2 + 2 samples per surface.
+ *   leaf_size  M >= 1.
+ *   opts       nullable (defaults).
+ *   out        host; receives the handle (NULL on failure before allocation).
+ * Synchronises `stream`.
+ */
+int kifmm_setup(const double* positions, int64_t N, int kernel, int p, int leaf_size,
+                kifmm_handle* out);
+int kifmm_setup_ex(const double* positions, int64_t N, int kernel, int p, int leaf_size,
+                   const kifmm_options* opts, void* stream, kifmm_handle* out);
+
+/*
+ * Rebuild the tree and lists of an existing plan for new positions (same N,
+ * kernel, p, leaf size and options); work space is reused where it fits.
+ * This is the per-call re-tree of particles that move between long-range
+ * evaluations (Section 2.4).  Synchronises `stream`.
+ */
+int kifmm_rebuild(kifmm_handle h, const double* positions, void* stream);
+
+/* Select the M2L precision (enum kifmm_precision) for later calls. */
+int kifmm_set_precision(kifmm_handle h, int precision);
+
+/*
+ * Forward evaluation (Section 2.2, all four steps after the tree):
+ *   charges    device [N] float, caller order.
+ *   potential  device [N] float or NULL.
+ *   field      device [N][3] float (E = -grad u) or NULL.
+ */
+int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float* field,
+                   void* stream);
+
+/*
+ * Vector-Jacobian product of the discrete map (q, x) -> (u, E) of
+ * kifmm_evaluate at the plan's positions with the tree frozen: given
+ * grad_potential = dL/du and grad_field = dL/dE (either may be NULL = 0),
+ * writes grad_charges = dL/dq [N] and grad_positions = dL/dx [N][3] (either
+ * may be NULL).  Implemented as the transposed sweep: the forward densities
+ * are recomputed, and a second sweep carries monopole (dL/du) and dipole
+ * (dL/dE) sources; the plan's operators are symmetric, so the transposed
+ * sweep reuses them.
+ */
+int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_potential,
+                   const float* grad_field, float* grad_charges, float* grad_positions,
+                   void* stream);
+
+/*
+ * Clump aggregation (Section 2.4): pebble forces F_k = q_k E_k are summed
+ * per clump, F_c = sum F_k and T_c = sum (x_k - X_c) x F_k, in FP64, over the
+ * pebbles of each clump in caller order (deterministic).
+ *   charges        device [N] float, field device [N][3] float (from
+ *                  kifmm_evaluate), both caller order.
+ *   clump_offsets  device [C+1] int64, CSR over caller order, offsets[0] = 0,
+ *                  non-decreasing, offsets[C] <= N (else KIFMM_ERR_INPUT,
+ *                  detected on the host after a copy of the offsets).
+ *   centers        device [C][3] double, the reference point X_c of each clump.
+ *   force, torque  device [C][3] double.
+ * The pebble positions are the plan's.
+ */
+int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field,
+                       const int64_t* clump_offsets, int64_t C, const double* centers,
+                       double* force, double* torque, void* stream);
+
+/*
+ * Sizes of the plan (host out[10]): boxes, leaves, depth, V-list pairs,
+ * near-field point pairs (P2P, self pairs included), W-list pairs, X-list
+ * pairs, U-list leaf pairs, N, surface points n.
+ */
+int kifmm_get_counts(kifmm_handle h, int64_t out[10]);
+
+/*
+ * Copy the tree to HOST buffers (each may be NULL), sized by kifmm_get_counts:
+ *   keys [N] uint64 sorted Morton keys, perm [N] int64 (sorted position ->
+ *   caller index), level/anchor/begin/end/parent/is_leaf per box (anchor is
+ *   [B][3]; boxes are numbered level by level in Morton order), root[4] =
+ *   (lo_x, lo_y, lo_z, side).  Synchronises the handle's last stream.
+ */
+int kifmm_copy_tree(kifmm_handle h, uint64_t* keys, int64_t* perm, int32_t* level,
+                    int32_t* anchor, int64_t* begin, int64_t* end, int64_t* parent,
+                    int8_t* is_leaf, double* root);
+
+/*
+ * Copy one interaction list (which = 'U', 'V', 'W' or 'X') as host CSR over
+ * boxes: offsets [B+1] int64, indices [pairs] int64 (source boxes, ascending
+ * within a row).  Pass offsets only (indices NULL) to size the second call.
+ */
+int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indices);
+
+/*
+ * Per-phase device times in ms of the last evaluate/backward (host out[n]):
+ * 0 P2M, 1 upward M2M+UC2E, 2 P2L, 3 M2L, 4 L2L+DC2E, 5 L2P+M2P, 6 P2P,
+ * 7 whole call.  Needs opts.profile = 1; returns the number written.
+ */
+int kifmm_get_phase_times(kifmm_handle h, float* out, int n);
+
+/* Release the handle and everything it owns (NULL is accepted). */
+void kifmm_destroy(kifmm_handle h);
+
+/* Message for a status code (with detail for the calling thread's last error). */
+const char* kifmm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KIFMM_H */

@@ -1,0 +1,361 @@
+// C ABI of the library: argument checks, plan lifetime and the order of the
+// kernel launches of one evaluation (Section 2.2: tree, upward pass, downward
+// pass, leaf evaluation), its transposed sweep, and the clump aggregation of
+// Section 2.4.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "common.h"
+
+using namespace kifmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        f();
+        return KIFMM_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return KIFMM_ERR_OOM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return KIFMM_ERR_STATE;
+    }
+}
+
+void check_options(const kifmm_options& o) {
+    if (o.max_depth < 0 || o.max_depth > kBits) throw Error(KIFMM_ERR_ARG, "max_depth must be in 0..21");
+    if (o.precision != KIFMM_FP32 && o.precision != KIFMM_SPLIT_BF16) throw Error(KIFMM_ERR_ARG, "unknown precision");
+    if (!(o.pinv_rtol > 0.0 && o.pinv_rtol < 1.0)) throw Error(KIFMM_ERR_ARG, "pinv_rtol must be in (0, 1)");
+    if (o.explicit_root) {
+        int e = 0;
+        double m = frexp(o.root_side, &e);
+        if (!(o.root_side > 0.0) || m != 0.5) throw Error(KIFMM_ERR_ARG, "root_side must be a power of two");
+        for (int d = 0; d < 3; ++d) {
+            double g = o.root_lo[d] * 4096.0 / o.root_side;
+            if (!isfinite(g) || g != floor(g)) throw Error(KIFMM_ERR_ARG, "root_lo must lie on the root_side/4096 grid");
+        }
+    }
+}
+
+void alloc_densities(kifmm_plan* P, hipStream_t s) {
+    size_t bytes = size_t(2) * size_t(P->B) * P->npad * 4;
+    for (DBuf* b : {&P->psi_u, &P->phi_u, &P->psi_d, &P->phi_d}) {
+        bool fresh = b->cap < bytes;
+        b->ensure(bytes);
+        if (fresh) KIFMM_HIP(hipMemsetAsync(b->p, 0, b->cap, s));
+    }
+    P->far.ensure(size_t(P->N) * 10 * 4);
+}
+
+kifmm_plan* checked(kifmm_handle h) {
+    if (!h) throw Error(KIFMM_ERR_STATE, "null handle");
+    if (h->B <= 0) throw Error(KIFMM_ERR_STATE, "handle has no tree");
+    return h;
+}
+
+void begin_phases(kifmm_plan* P, hipStream_t s) {
+    if (!P->opt.profile) return;
+    if (!P->events.made) {
+        for (auto& e : P->events.ev) KIFMM_HIP(hipEventCreate(&e));
+        P->events.made = true;
+    }
+    KIFMM_HIP(hipEventRecord(P->events.ev[0], s));
+}
+
+}  // namespace
+
+namespace kifmm {
+void record_phase(kifmm_plan* P, int idx, hipStream_t s) {
+    if (!P->opt.profile || !P->events.made) return;
+    KIFMM_HIP(hipEventRecord(P->events.ev[idx + 1], s));
+}
+}  // namespace kifmm
+
+extern "C" {
+
+void kifmm_default_options(kifmm_options* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->adaptive = 1;
+    o->max_depth = kBits;
+    o->precision = KIFMM_FP32;
+    o->pinv_rtol = 1e-7;
+    o->explicit_root = 0;
+    o->root_side = 1.0;
+    o->profile = 0;
+}
+
+int kifmm_setup_ex(const double* positions, int64_t N, int kernel, int p, int leaf_size, const kifmm_options* opts,
+                   void* stream, kifmm_handle* out) {
+    kifmm_plan* P = nullptr;
+    int rc = guarded([&] {
+        if (!out) throw Error(KIFMM_ERR_ARG, "null output handle pointer");
+        *out = nullptr;
+        if (!positions) throw Error(KIFMM_ERR_ARG, "null positions");
+        if (N < 1 || N >= (int64_t(1) << 31)) throw Error(KIFMM_ERR_ARG, "N must be in 1..2^31-1");
+        if (kernel != KIFMM_LAPLACE && kernel != KIFMM_GRAVITY) throw Error(KIFMM_ERR_ARG, "unknown kernel");
+        if (p < 2 || p > 8) throw Error(KIFMM_ERR_ARG, "p must be in 2..8");
+        if (leaf_size < 1) throw Error(KIFMM_ERR_ARG, "leaf_size must be >= 1");
+        kifmm_options o;
+        kifmm_default_options(&o);
+        if (opts) o = *opts;
+        check_options(o);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P = new kifmm_plan();
+        P->kernel = kernel;
+        P->c = kernel == KIFMM_LAPLACE ? 1.0 / (4.0 * M_PI) : -1.0;
+        P->p = p;
+        P->leaf = leaf_size;
+        P->opt = o;
+        P->N = N;
+        P->ops = &get_operators(p, o.pinv_rtol);
+        P->n = P->ops->n;
+        P->npad = P->ops->npad;
+        P->last_stream = s;
+        build_tree(P, positions, s);
+        alloc_densities(P, s);
+        KIFMM_HIP(hipStreamSynchronize(s));
+        *out = P;
+    });
+    if (rc != KIFMM_OK && P) {
+        delete P;
+        if (out) *out = nullptr;
+    }
+    return rc;
+}
+
+int kifmm_setup(const double* positions, int64_t N, int kernel, int p, int leaf_size, kifmm_handle* out) {
+    return kifmm_setup_ex(positions, N, kernel, p, leaf_size, nullptr, nullptr, out);
+}
+
+int kifmm_rebuild(kifmm_handle h, const double* positions, void* stream) {
+    return guarded([&] {
+        if (!h) throw Error(KIFMM_ERR_STATE, "null handle");
+        if (!positions) throw Error(KIFMM_ERR_ARG, "null positions");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        h->last_stream = s;
+        h->B = 0;
+        build_tree(h, positions, s);
+        alloc_densities(h, s);
+        KIFMM_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int kifmm_set_precision(kifmm_handle h, int precision) {
+    return guarded([&] {
+        if (!h) throw Error(KIFMM_ERR_STATE, "null handle");
+        if (precision != KIFMM_FP32 && precision != KIFMM_SPLIT_BF16) throw Error(KIFMM_ERR_ARG, "unknown precision");
+        h->opt.precision = precision;
+    });
+}
+
+int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float* field, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!charges) throw Error(KIFMM_ERR_ARG, "null charges");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        begin_phases(P, s);
+        launch_gather(P, charges, nullptr, nullptr, false, s);
+        run_sweep(P, 0, false, s, true);
+        run_far_eval(P, false, nullptr, s);
+        record_phase(P, 5, s);
+        launch_p2p_forward(P, potential, field, s);
+        record_phase(P, 6, s);
+        P->has_phase = P->opt.profile ? 1 : 0;
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_potential, const float* grad_field,
+                   float* grad_charges, float* grad_positions, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!charges) throw Error(KIFMM_ERR_ARG, "null charges");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        begin_phases(P, s);
+        launch_gather(P, charges, grad_potential, grad_field, true, s);
+        run_sweep(P, 0, false, s, false);
+        run_sweep(P, 1, true, s, false);
+        run_far_eval(P, true, nullptr, s);
+        for (int k = 0; k < 6; ++k) record_phase(P, k, s);
+        launch_p2p_backward(P, grad_charges, grad_positions, s);
+        record_phase(P, 6, s);
+        P->has_phase = P->opt.profile ? 2 : 0;
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field, const int64_t* clump_offsets,
+                       int64_t C, const double* centers, double* force, double* torque, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (C < 0) throw Error(KIFMM_ERR_ARG, "negative clump count");
+        if (C == 0) return;
+        if (!charges || !field || !clump_offsets || !centers || !force || !torque)
+            throw Error(KIFMM_ERR_ARG, "null pointer argument");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        std::vector<int64_t> off(size_t(C) + 1);
+        KIFMM_HIP(hipMemcpyAsync(off.data(), clump_offsets, off.size() * 8, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipStreamSynchronize(s));
+        if (off[0] != 0 || off[size_t(C)] > P->N) throw Error(KIFMM_ERR_INPUT, "clump offsets out of range");
+        for (int64_t c = 0; c < C; ++c)
+            if (off[size_t(c) + 1] < off[size_t(c)]) throw Error(KIFMM_ERR_INPUT, "clump offsets not monotone");
+        launch_clump_reduce(P, charges, field, clump_offsets, C, centers, force, torque, s);
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_get_counts(kifmm_handle h, int64_t out[10]) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!out) throw Error(KIFMM_ERR_ARG, "null output");
+        for (int k = 0; k < 10; ++k) out[k] = P->counts[k];
+    });
+}
+
+int kifmm_copy_tree(kifmm_handle h, uint64_t* keys, int64_t* perm, int32_t* level, int32_t* anchor, int64_t* begin,
+                    int64_t* end, int64_t* parent, int8_t* is_leaf, double* root) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        hipStream_t s = P->last_stream;
+        KIFMM_HIP(hipStreamSynchronize(s));
+        const int64_t N = P->N, B = P->B;
+        if (keys) KIFMM_HIP(hipMemcpy(keys, P->keys.p, size_t(N) * 8, hipMemcpyDeviceToHost));
+        if (perm) {
+            std::vector<int> t(static_cast<size_t>(N));
+            KIFMM_HIP(hipMemcpy(t.data(), P->perm.p, size_t(N) * 4, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < N; ++i) perm[i] = t[size_t(i)];
+        }
+        if (level || anchor) {
+            std::vector<int4> a(static_cast<size_t>(B));
+            KIFMM_HIP(hipMemcpy(a.data(), P->bx_anchor.p, size_t(B) * 16, hipMemcpyDeviceToHost));
+            for (int64_t b = 0; b < B; ++b) {
+                if (level) level[b] = a[size_t(b)].w;
+                if (anchor) {
+                    anchor[3 * b] = a[size_t(b)].x;
+                    anchor[3 * b + 1] = a[size_t(b)].y;
+                    anchor[3 * b + 2] = a[size_t(b)].z;
+                }
+            }
+        }
+        if (begin || end) {
+            std::vector<int2> r(static_cast<size_t>(B));
+            KIFMM_HIP(hipMemcpy(r.data(), P->bx_range.p, size_t(B) * 8, hipMemcpyDeviceToHost));
+            for (int64_t b = 0; b < B; ++b) {
+                if (begin) begin[b] = r[size_t(b)].x;
+                if (end) end[b] = r[size_t(b)].y;
+            }
+        }
+        if (parent) {
+            std::vector<int> t(static_cast<size_t>(B));
+            KIFMM_HIP(hipMemcpy(t.data(), P->bx_parent.p, size_t(B) * 4, hipMemcpyDeviceToHost));
+            for (int64_t b = 0; b < B; ++b) parent[b] = t[size_t(b)];
+        }
+        if (is_leaf) {
+            std::vector<int> t(static_cast<size_t>(B));
+            KIFMM_HIP(hipMemcpy(t.data(), P->bx_leaf.p, size_t(B) * 4, hipMemcpyDeviceToHost));
+            for (int64_t b = 0; b < B; ++b) is_leaf[b] = int8_t(t[size_t(b)]);
+        }
+        if (root) {
+            root[0] = P->lo[0];
+            root[1] = P->lo[1];
+            root[2] = P->lo[2];
+            root[3] = P->side;
+        }
+    });
+}
+
+int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indices) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!offsets) throw Error(KIFMM_ERR_ARG, "null offsets");
+        KIFMM_HIP(hipStreamSynchronize(P->last_stream));
+        const int64_t B = P->B;
+        std::vector<int> off(size_t(B) + 1), idx;
+        if (which == 'U' || which == 'W' || which == 'X') {
+            const DBuf& o = which == 'U' ? P->u_off : which == 'W' ? P->w_off : P->x_off;
+            const DBuf& ix = which == 'U' ? P->u_idx : which == 'W' ? P->w_idx : P->x_idx;
+            KIFMM_HIP(hipMemcpy(off.data(), o.p, off.size() * 4, hipMemcpyDeviceToHost));
+            idx.resize(size_t(off[size_t(B)]));
+            if (!idx.empty()) KIFMM_HIP(hipMemcpy(idx.data(), ix.p, idx.size() * 4, hipMemcpyDeviceToHost));
+        } else if (which == 'V') {
+            int64_t b2 = P->depth >= 2 ? P->lev[2].start : B;
+            std::vector<int> vd(size_t(B - b2) * kVPerOct);
+            if (!vd.empty()) KIFMM_HIP(hipMemcpy(vd.data(), P->vdense.p, vd.size() * 4, hipMemcpyDeviceToHost));
+            off[0] = 0;
+            for (int64_t b = 0; b < B; ++b) {
+                if (b >= b2) {
+                    size_t at = idx.size();
+                    for (int j = 0; j < kVPerOct; ++j) {
+                        int v = vd[size_t(b - b2) * kVPerOct + j];
+                        if (v >= 0) idx.push_back(v);
+                    }
+                    std::sort(idx.begin() + at, idx.end());
+                }
+                off[size_t(b) + 1] = int(idx.size());
+            }
+        } else {
+            throw Error(KIFMM_ERR_ARG, "list must be one of U, V, W, X");
+        }
+        for (int64_t b = 0; b <= B; ++b) offsets[b] = off[size_t(b)];
+        if (indices)
+            for (size_t k = 0; k < idx.size(); ++k) indices[k] = idx[k];
+    });
+}
+
+int kifmm_get_phase_times(kifmm_handle h, float* out, int n) {
+    int written = 0;
+    int rc = guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!out) throw Error(KIFMM_ERR_ARG, "null output");
+        if (!P->has_phase || !P->events.made) return;
+        KIFMM_HIP(hipEventSynchronize(P->events.ev[7]));
+        float ms[8] = {};
+        for (int k = 0; k < 7; ++k) KIFMM_HIP(hipEventElapsedTime(&ms[k], P->events.ev[k], P->events.ev[k + 1]));
+        KIFMM_HIP(hipEventElapsedTime(&ms[7], P->events.ev[0], P->events.ev[7]));
+        for (int k = 0; k < std::min(n, 8); ++k) out[k] = ms[k];
+        written = std::min(n, 8);
+    });
+    return rc == KIFMM_OK ? written : rc;
+}
+
+void kifmm_destroy(kifmm_handle h) {
+    if (!h) return;
+    if (h->last_stream || true) (void)hipStreamSynchronize(h->last_stream);
+    if (h->events.made)
+        for (auto& e : h->events.ev) (void)hipEventDestroy(e);
+    delete h;
+}
+
+const char* kifmm_status_string(int status) {
+    static thread_local std::string msg;
+    const char* base = "unknown status";
+    switch (status) {
+        case KIFMM_OK: base = "ok"; break;
+        case KIFMM_ERR_ARG: base = "invalid argument"; break;
+        case KIFMM_ERR_INPUT: base = "invalid input data"; break;
+        case KIFMM_ERR_OOM: base = "out of device memory"; break;
+        case KIFMM_ERR_HIP: base = "HIP runtime error"; break;
+        case KIFMM_ERR_STATE: base = "invalid handle or state"; break;
+    }
+    msg = base;
+    if (status != KIFMM_OK && !g_err.empty()) msg += ": " + g_err;
+    return msg.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/kifmm.h"
+
+namespace kifmm {
+
+constexpr int kBits = 21;              // key bits per axis
+constexpr int kNumV = 316;             // far offsets in [-3,3]^3 minus [-1,1]^3
+constexpr int kVPerOct = 189;          // V-list offsets reachable from one octant
+constexpr int kMaxLevels = 22;
+
+// Error carrying a status code; caught at the ABI.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define KIFMM_HIP(call)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::kifmm::Error(e_ == hipErrorOutOfMemory ? KIFMM_ERR_OOM : KIFMM_ERR_HIP, \
+                                 std::string(#call) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+// Grow-only device buffer.
+struct DBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    // Make room for `bytes` (contents are not preserved).
+    void* ensure(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        if (bytes > cap) {
+            release();
+            size_t b = (bytes + 255) & ~size_t(255);
+            KIFMM_HIP(hipMalloc(&p, b));
+            cap = b;
+        }
+        return p;
+    }
+    // Grow keeping the first `keep` bytes.
+    void* grow(size_t bytes, size_t keep, hipStream_t s) {
+        if (bytes <= cap) return p;
+        size_t b = ((bytes + bytes / 2) + 255) & ~size_t(255);
+        void* q = nullptr;
+        KIFMM_HIP(hipMalloc(&q, b));
+        if (p && keep) KIFMM_HIP(hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, s));
+        if (p) {
+            KIFMM_HIP(hipStreamSynchronize(s));
+            (void)hipFree(p);
+        }
+        p = q;
+        cap = b;
+        return p;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Operators of one (p, pinv_rtol): built on the host in FP64, stored in FP32
+// (and bf16 hi/lo for M2L) on the device.  Unit-box coordinates, kernel 1/r.
+struct Operators {
+    int p = 0, n = 0, npad = 0, rank = 0;
+    double tau = 0;
+    DBuf surf;         // float4 [2][npad]: rho=1.05 surface, rho=2.95 surface (w = 0)
+    DBuf uc2e_w1;      // float [npad][npad]  Sigma^-1 U^T          (UC2E = V W1)
+    DBuf uc2e_v;       // float [npad][npad]  V
+    DBuf dc2e_w1;      // float [npad][npad]  Sigma^-1 V^T          (DC2E = UC2E^T = U W1d)
+    DBuf dc2e_v;       // float [npad][npad]  U
+    DBuf m2m;          // float [8][npad][npad]
+    DBuf l2l;          // float [8][npad][npad] (includes the factor 1/2 of the child width)
+    DBuf m2l;          // float [316][npad][npad]
+    DBuf m2l_hi;       // bf16  [316][npad][npad]
+    DBuf m2l_lo;       // bf16  [316][npad][npad]
+    std::vector<double> sigma;   // singular values of K(uc, ue), descending
+};
+
+// Returns the (cached, process-wide) operators for this device.
+const Operators& get_operators(int p, double tau);
+
+// Host FP64 one-sided Jacobi SVD of a square row-major matrix A (n x n):
+// A = U diag(S) V^T, S descending.  U, V row-major n x n.
+void jacobi_svd(int n, const double* A, double* U, double* S, double* V);
+
+// Surfaces in unit-box coordinates: boundary points of the p^3 grid,
+// i slowest, k fastest, scaled by rho about the centre.
+std::vector<double> unit_surface(int p, double rho);
+
+struct LevelInfo {
+    int64_t start = 0, count = 0;     // boxes of this level: [start, start+count)
+    int64_t nl_start = 0, nl_count = 0;  // non-leaf boxes of this level in nonleaf[]
+};
+
+struct PhaseEvents {
+    hipEvent_t ev[9] = {};
+    bool made = false;
+};
+
+}  // namespace kifmm
+
+// The plan behind a kifmm_handle.
+struct kifmm_plan {
+    int kernel = 0;
+    double c = 0;
+    int p = 0, n = 0, npad = 0, leaf = 0;
+    kifmm_options opt{};
+    int64_t N = 0;
+    double lo[3] = {0, 0, 0}, side = 1;
+    int depth = 0;
+    int64_t B = 0, nleaves = 0;
+    std::vector<kifmm::LevelInfo> lev;
+    int64_t counts[10] = {};
+    hipStream_t last_stream = nullptr;
+    const kifmm::Operators* ops = nullptr;
+
+    // points
+    kifmm::DBuf x64;        // double [N][3] caller order (copy)
+    kifmm::DBuf xs;         // float4 [N] sorted (x, y, z, 0)
+    kifmm::DBuf perm;       // int32 [N] sorted -> caller
+    kifmm::DBuf keys;       // uint64 [N] sorted
+    // boxes
+    kifmm::DBuf bx_anchor;  // int4 [B] (ax, ay, az, level)
+    kifmm::DBuf bx_range;   // int2 [B] (begin, end)
+    kifmm::DBuf bx_parent;  // int32 [B]
+    kifmm::DBuf bx_child;   // int2 [B] (first child, child mask)
+    kifmm::DBuf bx_leaf;    // int32 [B] 0/1
+    kifmm::DBuf bx_mkey;    // uint64 [B] Morton key of the anchor at the box's level
+    kifmm::DBuf nonleaf;    // int32 [.] non-leaf boxes, level by level
+    kifmm::DBuf leaves;     // int32 [nleaves] leaf boxes
+    // lists
+    kifmm::DBuf coll;       // int32 [B][27]
+    kifmm::DBuf cal;        // int32 [B][26] coarse adjacent leaves (-1 padded)
+    kifmm::DBuf vdense;     // int32 [B - start(2)][189] V sources by octant-local offset slot
+    kifmm::DBuf u_off, u_idx, w_off, w_idx, x_off, x_idx;   // CSR over boxes, int32
+    kifmm::DBuf xboxes;     // int32 boxes with a non-empty X list
+    int64_t n_xboxes = 0;
+    // densities: [rhs][B][npad]
+    kifmm::DBuf psi_u, phi_u, psi_d, phi_d;
+    // per-evaluation work
+    kifmm::DBuf pts;        // float4 [N] sorted (x, y, z, q)
+    kifmm::DBuf src2;       // float4 [N] sorted (ubar, Ebar) for the adjoint sweep
+    kifmm::DBuf far;        // float [N][4] or [N][12] far-field partials (sorted)
+    // scratch
+    kifmm::DBuf tmp_a, tmp_b, tmp_c, tmp_d, tmp_e, tmp_f, scan_tmp, flag;
+    kifmm::PhaseEvents events;
+    float phase_ms[8] = {};
+    int has_phase = 0;
+};
+
+namespace kifmm {
+
+// ---- tree.hip
+void build_tree(kifmm_plan* P, const double* positions, hipStream_t s);
+// ---- farfield.hip
+void run_sweep(kifmm_plan* P, int rhs, bool dipole, hipStream_t s, bool record);
+void run_far_eval(kifmm_plan* P, bool backward, const float* ebar_sorted_unused, hipStream_t s);
+// ---- nearfield.hip
+void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const float* gfield,
+                   bool adjoint, hipStream_t s);
+void launch_p2p_forward(kifmm_plan* P, float* potential, float* field, hipStream_t s);
+void launch_p2p_backward(kifmm_plan* P, float* gq, float* gx, hipStream_t s);
+// ---- clump.hip
+void launch_clump_reduce(kifmm_plan* P, const float* q, const float* E, const int64_t* off, int64_t C,
+                         const double* centers, double* F, double* T, hipStream_t s);
+// ---- api.cpp
+void record_phase(kifmm_plan* P, int idx, hipStream_t s);
+
+}  // namespace kifmm

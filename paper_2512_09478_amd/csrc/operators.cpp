@@ -1,0 +1,239 @@
+// FP64 operator precompute (host) and its upload to the device.
+//
+// Section 2.2 describes the far field of a box by a density on samples of an
+// equivalent surface and the M2M, L2L and M2L operators as matrices computed
+// automatically from the kernel.  Everything here is built once per (p, tau)
+// in unit-box coordinates for the kernel 1/r; the homogeneity of 1/r makes
+// the operators level independent (a box of side w scales K by 1/w, which the
+// sweep folds into its normalised check potentials), and the kernel constant
+// c cancels between a check potential and its pseudoinverse, so it is applied
+// only to the final outputs.
+//
+// Surfaces: boundary points of the p^3 grid, rho = 1.05 (upward equivalent =
+// downward check) and rho = 2.95 (upward check = downward equivalent).  With
+// these the downward check-to-equivalent map is the transpose of the upward
+// one, L2L is the transpose of M2M, and M2L(-d) = M2L(d)^T, which is what
+// makes the transposed (adjoint) sweep reuse the forward operators.
+//
+// Check-to-equivalent: truncated SVD of K(uc, ue) (one-sided Jacobi, FP64),
+// singular values below tau * sigma_1 dropped, applied in factored form
+// V (Sigma^-1 U^T psi) so that FP32 rounding stays inside the kept subspace.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <tuple>
+
+#include "common.h"
+
+namespace kifmm {
+
+std::vector<double> unit_surface(int p, double rho) {
+    std::vector<double> out;
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j)
+            for (int k = 0; k < p; ++k) {
+                bool bnd = std::min(i, std::min(j, k)) == 0 || std::max(i, std::max(j, k)) == p - 1;
+                if (!bnd) continue;
+                out.push_back(rho * (double(i) / (p - 1) - 0.5));
+                out.push_back(rho * (double(j) / (p - 1) - 0.5));
+                out.push_back(rho * (double(k) / (p - 1) - 0.5));
+            }
+    return out;
+}
+
+void jacobi_svd(int n, const double* A, double* U, double* S, double* V) {
+    // Columns of G = A V are rotated pairwise until mutually orthogonal; then
+    // sigma_j = |g_j| and u_j = g_j / sigma_j.  Column-major working copies.
+    std::vector<double> G(size_t(n) * n), W(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) G[size_t(j) * n + i] = A[size_t(i) * n + j];
+    for (int j = 0; j < n; ++j) W[size_t(j) * n + j] = 1.0;
+    for (int sweep = 0; sweep < 80; ++sweep) {
+        int rotations = 0;
+        for (int p = 0; p < n - 1; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                double* gp = &G[size_t(p) * n];
+                double* gq = &G[size_t(q) * n];
+                double a = 0, b = 0, g = 0;
+                for (int i = 0; i < n; ++i) {
+                    a += gp[i] * gp[i];
+                    b += gq[i] * gq[i];
+                    g += gp[i] * gq[i];
+                }
+                if (g == 0.0 || fabs(g) <= 1e-15 * sqrt(a * b)) continue;
+                ++rotations;
+                double zeta = (b - a) / (2.0 * g);
+                double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                double cs = 1.0 / sqrt(1.0 + t * t);
+                double sn = cs * t;
+                for (int i = 0; i < n; ++i) {
+                    double x = gp[i], y = gq[i];
+                    gp[i] = cs * x - sn * y;
+                    gq[i] = sn * x + cs * y;
+                }
+                double* wp = &W[size_t(p) * n];
+                double* wq = &W[size_t(q) * n];
+                for (int i = 0; i < n; ++i) {
+                    double x = wp[i], y = wq[i];
+                    wp[i] = cs * x - sn * y;
+                    wq[i] = sn * x + cs * y;
+                }
+            }
+        }
+        if (rotations == 0) break;
+    }
+    std::vector<double> sig(n);
+    for (int j = 0; j < n; ++j) {
+        double s = 0;
+        for (int i = 0; i < n; ++i) s += G[size_t(j) * n + i] * G[size_t(j) * n + i];
+        sig[j] = sqrt(s);
+    }
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return sig[a] > sig[b]; });
+    for (int r = 0; r < n; ++r) {
+        int j = ord[r];
+        S[r] = sig[j];
+        for (int i = 0; i < n; ++i) {
+            U[size_t(i) * n + r] = sig[j] > 0 ? G[size_t(j) * n + i] / sig[j] : 0.0;
+            V[size_t(i) * n + r] = W[size_t(j) * n + i];
+        }
+    }
+}
+
+namespace {
+
+uint16_t bf16_rne(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return uint16_t(u >> 16);
+}
+
+float bf16_to_float(uint16_t h) {
+    uint32_t u = uint32_t(h) << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+double inv_dist(const double* a, const double* b) {
+    double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+    return 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+}
+
+void upload(DBuf& buf, const void* host, size_t bytes) {
+    buf.ensure(bytes);
+    KIFMM_HIP(hipMemcpy(buf.p, host, bytes, hipMemcpyHostToDevice));
+}
+
+std::unique_ptr<Operators> build_operators(int p, double tau) {
+    auto op = std::make_unique<Operators>();
+    const int n = 6 * (p - 1) * (p - 1) + 2;
+    const int np = (n + 31) / 32 * 32;
+    op->p = p;
+    op->n = n;
+    op->npad = np;
+    op->tau = tau;
+    std::vector<double> sin = unit_surface(p, 1.05);   // ue = dc
+    std::vector<double> sout = unit_surface(p, 2.95);  // uc = de
+
+    // surfaces for the kernels
+    std::vector<float> surf(size_t(2) * np * 4, 0.0f);
+    for (int i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            surf[size_t(i) * 4 + d] = float(sin[3 * i + d]);
+            surf[size_t(np + i) * 4 + d] = float(sout[3 * i + d]);
+        }
+    upload(op->surf, surf.data(), surf.size() * 4);
+
+    // K(uc, ue) and its truncated pseudoinverse, factored
+    std::vector<double> K(size_t(n) * n), U(size_t(n) * n), V(size_t(n) * n), S(n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) K[size_t(i) * n + j] = inv_dist(&sout[3 * i], &sin[3 * j]);
+    jacobi_svd(n, K.data(), U.data(), S.data(), V.data());
+    int k = 0;
+    while (k < n && S[k] >= tau * S[0]) ++k;
+    op->rank = k;
+    op->sigma.assign(S.begin(), S.end());
+    std::vector<float> w1u(size_t(np) * np, 0.f), vu(size_t(np) * np, 0.f);
+    std::vector<float> w1d(size_t(np) * np, 0.f), vd(size_t(np) * np, 0.f);
+    for (int r = 0; r < k; ++r)
+        for (int i = 0; i < n; ++i) {
+            w1u[size_t(r) * np + i] = float(U[size_t(i) * n + r] / S[r]);
+            vu[size_t(i) * np + r] = float(V[size_t(i) * n + r]);
+            w1d[size_t(r) * np + i] = float(V[size_t(i) * n + r] / S[r]);
+            vd[size_t(i) * np + r] = float(U[size_t(i) * n + r]);
+        }
+    upload(op->uc2e_w1, w1u.data(), w1u.size() * 4);
+    upload(op->uc2e_v, vu.data(), vu.size() * 4);
+    upload(op->dc2e_w1, w1d.data(), w1d.size() * 4);
+    upload(op->dc2e_v, vd.data(), vd.size() * 4);
+
+    // M2M (parent uc <- child ue) and L2L (child dc <- parent de), parent units
+    std::vector<float> m2m(size_t(8) * np * np, 0.f), l2l(size_t(8) * np * np, 0.f);
+    for (int o = 0; o < 8; ++o) {
+        double dlt[3] = {0.5 * (((o >> 2) & 1) - 0.5), 0.5 * (((o >> 1) & 1) - 0.5), 0.5 * ((o & 1) - 0.5)};
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double ce[3], cc[3];
+                for (int d = 0; d < 3; ++d) {
+                    ce[d] = dlt[d] + 0.5 * sin[3 * j + d];      // child ue
+                    cc[d] = dlt[d] + 0.5 * sin[3 * i + d];      // child dc
+                }
+                m2m[(size_t(o) * np + i) * np + j] = float(inv_dist(&sout[3 * i], ce));
+                l2l[(size_t(o) * np + i) * np + j] = float(0.5 * inv_dist(cc, &sout[3 * j]));
+            }
+    }
+    upload(op->m2m, m2m.data(), m2m.size() * 4);
+    upload(op->l2l, l2l.data(), l2l.size() * 4);
+
+    // M2L for the 316 far offsets, lexicographic (dx, dy, dz)
+    std::vector<float> m2l(size_t(kNumV) * np * np, 0.f);
+    std::vector<uint16_t> hi(size_t(kNumV) * np * np, 0), lo(size_t(kNumV) * np * np, 0);
+    int m = 0;
+    for (int dx = -3; dx <= 3; ++dx)
+        for (int dy = -3; dy <= 3; ++dy)
+            for (int dz = -3; dz <= 3; ++dz) {
+                if (std::max(abs(dx), std::max(abs(dy), abs(dz))) <= 1) continue;
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        double src[3] = {dx + sin[3 * j], dy + sin[3 * j + 1], dz + sin[3 * j + 2]};
+                        double v = inv_dist(&sin[3 * i], src);
+                        size_t at = (size_t(m) * np + i) * np + j;
+                        m2l[at] = float(v);
+                        uint16_t h = bf16_rne(float(v));
+                        hi[at] = h;
+                        lo[at] = bf16_rne(float(v - double(bf16_to_float(h))));
+                    }
+                ++m;
+            }
+    upload(op->m2l, m2l.data(), m2l.size() * 4);
+    upload(op->m2l_hi, hi.data(), hi.size() * 2);
+    upload(op->m2l_lo, lo.data(), lo.size() * 2);
+    return op;
+}
+
+}  // namespace
+
+const Operators& get_operators(int p, double tau) {
+    // Kept until the process ends (never destroyed: the HIP runtime may be gone
+    // by the time static destructors run).
+    static std::mutex mu;
+    static auto* cache = new std::map<std::tuple<int, int, double>, std::unique_ptr<Operators>>();
+    int dev = 0;
+    KIFMM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_tuple(dev, p, tau);
+    auto it = cache->find(key);
+    if (it == cache->end()) it = cache->emplace(key, build_operators(p, tau)).first;
+    return *it->second;
+}
+
+}  // namespace kifmm

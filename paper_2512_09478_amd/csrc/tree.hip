@@ -1,0 +1,902 @@
+// Octree and interaction lists on the GPU (Section 2.2, first step: an
+// octree whose leaves hold at most M points; the near and far zones that the
+// passes use).  All integer work is exact and deterministic:
+//
+//   root cube -> FP64 quantisation to 21-bit cells -> 63-bit Morton keys ->
+//   stable LSD radix sort of (key, index) -> level-by-level split of the
+//   sorted key runs -> colleagues by binary search on per-level box keys ->
+//   V list as a dense table per octant-local offset slot, coarse adjacent
+//   leaves top-down, X lists, and U/W by transposition; every CSR row is
+//   sorted ascending.
+#include <algorithm>
+
+#include "common.h"
+
+namespace kifmm {
+
+namespace {
+
+constexpr int TB = 256;
+inline int nblocks(int64_t n, int per = TB) { return int((n + per - 1) / per); }
+
+struct LevelTable {
+    int start[kMaxLevels + 1];
+    int count[kMaxLevels + 1];
+};
+
+__device__ inline uint64_t spread21(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ inline uint64_t morton3(uint64_t x, uint64_t y, uint64_t z) {
+    return (spread21(x) << 2) | (spread21(y) << 1) | spread21(z);
+}
+
+__device__ inline uint64_t lane_lt_mask() {
+    unsigned l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// ----------------------------------------------------------------- bbox
+__global__ void k_bbox(const double* __restrict__ x, int64_t N, double* __restrict__ part,
+                       int* __restrict__ bad) {
+    __shared__ double s[6][TB];
+    double mn[3] = {1e308, 1e308, 1e308}, mx[3] = {-1e308, -1e308, -1e308};
+    int nb = 0;
+    for (int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x; i < N; i += int64_t(gridDim.x) * TB) {
+        for (int d = 0; d < 3; ++d) {
+            double v = x[3 * i + d];
+            if (!isfinite(v)) nb = 1;
+            mn[d] = fmin(mn[d], v);
+            mx[d] = fmax(mx[d], v);
+        }
+    }
+    if (nb) atomicOr(bad, 1);
+    for (int d = 0; d < 3; ++d) {
+        s[d][threadIdx.x] = mn[d];
+        s[3 + d][threadIdx.x] = mx[d];
+    }
+    __syncthreads();
+    for (int w = TB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int d = 0; d < 3; ++d) {
+                s[d][threadIdx.x] = fmin(s[d][threadIdx.x], s[d][threadIdx.x + w]);
+                s[3 + d][threadIdx.x] = fmax(s[3 + d][threadIdx.x], s[3 + d][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// ----------------------------------------------------------------- keys
+// k_d = clamp(floor((x_d - lo_d) * 2^21 / s), 0, 2^21 - 1): one rounded FP64
+// subtraction and an exact power-of-two scaling, as on the host side of any
+// checker, so the keys are bit-reproducible.
+__global__ void k_keys(const double* __restrict__ x, int64_t N, double lo0, double lo1, double lo2,
+                       double scale, double side, int check_root, uint64_t* __restrict__ keys,
+                       uint32_t* __restrict__ idx, int* __restrict__ bad) {
+    int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x;
+    if (i >= N) return;
+    const double lo[3] = {lo0, lo1, lo2};
+    uint64_t k[3];
+    int b = 0;
+    for (int d = 0; d < 3; ++d) {
+        double v = x[3 * i + d];
+        if (!isfinite(v)) b = 1;
+        if (check_root && (v < lo[d] || v > lo[d] + side)) b = 1;
+        double f = floor(__dmul_rn(__dsub_rn(v, lo[d]), scale));
+        f = fmin(fmax(f, 0.0), double((1 << kBits) - 1));
+        k[d] = b ? 0 : uint64_t(f);
+    }
+    if (b) atomicOr(bad, 1);
+    keys[i] = morton3(k[0], k[1], k[2]);
+    idx[i] = uint32_t(i);
+}
+
+// ----------------------------------------------------------------- scan
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = TB * SCAN_ITEMS;
+
+template <class T>
+__device__ T block_exclusive_scan(T v, T* total) {
+    __shared__ T sh[TB];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < TB; off <<= 1) {
+        T t = threadIdx.x >= off ? sh[threadIdx.x - off] : T(0);
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    T incl = sh[threadIdx.x];
+    *total = sh[TB - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+template <class T>
+__global__ void k_scan_tiles(const T* __restrict__ in, T* __restrict__ out, int64_t n, T* __restrict__ sums) {
+    int64_t base = blockIdx.x * int64_t(SCAN_TILE) + threadIdx.x * SCAN_ITEMS;
+    T v[SCAN_ITEMS];
+    T run = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : T(0);
+        T t = v[k];
+        v[k] = run;
+        run += t;
+    }
+    T total;
+    T off = block_exclusive_scan<T>(run, &total);
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) out[base + k] = v[k] + off;
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+template <class T>
+__global__ void k_scan_add(T* __restrict__ out, int64_t n, const T* __restrict__ sums) {
+    int64_t base = blockIdx.x * int64_t(SCAN_TILE) + threadIdx.x * SCAN_ITEMS;
+    T a = sums[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) out[base + k] += a;
+}
+
+// Exclusive scan of n values (in may equal out).  The tile sums of nested
+// levels live in four equal slabs of P->scan_tmp, sized at the top level.
+template <class T>
+void exclusive_scan(kifmm_plan* P, const T* in, T* out, int64_t n, hipStream_t s, int depth = 0) {
+    if (n <= 0) return;
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (depth == 0) P->scan_tmp.ensure(4 * (size_t(nb) * 8 + 256));
+    if (depth >= 4) throw Error(KIFMM_ERR_STATE, "scan too deep");
+    size_t slab = (P->scan_tmp.cap / 4) & ~size_t(255);
+    T* sums = reinterpret_cast<T*>(P->scan_tmp.as<char>() + size_t(depth) * slab);
+    hipLaunchKernelGGL(k_scan_tiles<T>, dim3(unsigned(nb)), dim3(TB), 0, s, in, out, n, sums);
+    if (nb > 1) {
+        exclusive_scan<T>(P, sums, sums, nb, s, depth + 1);
+        hipLaunchKernelGGL(k_scan_add<T>, dim3(unsigned(nb)), dim3(TB), 0, s, out, n, sums);
+    }
+}
+
+// ----------------------------------------------------------------- radix sort
+constexpr int RS_ITEMS = 16;
+constexpr int RS_WAVE_ITEMS = 64 * RS_ITEMS;   // 1024 keys per wave
+constexpr int RS_TILE = 4 * RS_WAVE_ITEMS;     // 4096 keys per block
+
+__global__ void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                          uint32_t* __restrict__ hist, int nblk) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = blockIdx.x * int64_t(RS_TILE);
+    for (int k = threadIdx.x; k < RS_TILE; k += TB) {
+        int64_t i = base + k;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: wave w owns the contiguous quarter [w*1024, (w+1)*1024) of
+// the block's tile and walks it in 16 rounds of 64 keys; peers with equal
+// digits are found with eight ballots, so ranks follow the input order.
+__global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                    const uint32_t* __restrict__ vin,
+                                                    uint64_t* __restrict__ kout,
+                                                    uint32_t* __restrict__ vout, int64_t n, int shift,
+                                                    const uint32_t* __restrict__ off, int nblk) {
+    __shared__ uint32_t cnt[4][256];
+    __shared__ uint32_t base[4][256];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t b0 = blockIdx.x * int64_t(RS_TILE) + w * int64_t(RS_WAVE_ITEMS);
+    uint64_t k[RS_ITEMS];
+    uint32_t v[RS_ITEMS];
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = b0 + r * 64 + lane;
+        k[r] = i < n ? kin[i] : 0;
+        v[r] = i < n ? vin[i] : 0;
+    }
+    for (int d = threadIdx.x; d < 4 * 256; d += TB) (&cnt[0][0])[d] = 0;
+    __syncthreads();
+    const uint64_t lt = lane_lt_mask();
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = b0 + r * 64 + lane;
+        bool valid = i < n;
+        uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+        for (int bt = 0; bt < 8; ++bt) {
+            uint64_t m = __ballot((dg >> bt) & 1u);
+            peers &= ((dg >> bt) & 1u) ? m : ~m;
+        }
+        if (valid && (peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
+    }
+    __syncthreads();
+    {
+        int d = threadIdx.x;
+        uint32_t run = off[int64_t(d) * nblk + blockIdx.x];
+        for (int ww = 0; ww < 4; ++ww) {
+            base[ww][d] = run;
+            run += cnt[ww][d];
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = b0 + r * 64 + lane;
+        bool valid = i < n;
+        uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+        for (int bt = 0; bt < 8; ++bt) {
+            uint64_t m = __ballot((dg >> bt) & 1u);
+            peers &= ((dg >> bt) & 1u) ? m : ~m;
+        }
+        uint32_t pos = 0;
+        if (valid) pos = base[w][dg] + uint32_t(__popcll(peers & lt));
+        __builtin_amdgcn_wave_barrier();
+        if (valid) {
+            kout[pos] = k[r];
+            vout[pos] = v[r];
+            if ((peers & lt) == 0) base[w][dg] += uint32_t(__popcll(peers));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+void radix_sort(kifmm_plan* P, uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n,
+                int bits, hipStream_t s) {
+    int nblk = int((n + RS_TILE - 1) / RS_TILE);
+    P->tmp_f.ensure(size_t(256) * nblk * 4);
+    uint32_t* hist = P->tmp_f.as<uint32_t>();
+    uint64_t *ka = keys, *kb = ktmp;
+    uint32_t *va = vals, *vb = vtmp;
+    int passes = (bits + 7) / 8;
+    for (int ps = 0; ps < passes; ++ps) {
+        int shift = 8 * ps;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(TB), 0, s, ka, n, shift, hist, nblk);
+        exclusive_scan<uint32_t>(P, hist, hist, int64_t(256) * nblk, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(TB), 0, s, ka, va, kb, vb, n, shift, hist, nblk);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        KIFMM_HIP(hipMemcpyAsync(keys, ka, n * 8, hipMemcpyDeviceToDevice, s));
+        KIFMM_HIP(hipMemcpyAsync(vals, va, n * 4, hipMemcpyDeviceToDevice, s));
+    }
+}
+
+// ----------------------------------------------------------------- tree levels
+// For each non-leaf parent at level l: child boundaries in its sorted key run
+// (the level-(l+1) digit is non-decreasing inside the run).
+__global__ void k_split(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
+                        const int2* __restrict__ range, int* __restrict__ bounds /*[nf][9]*/,
+                        int* __restrict__ nch, int* __restrict__ nnl, int leaf_size, int adaptive,
+                        int max_depth, int Lu) {
+    int f = blockIdx.x * TB + threadIdx.x;
+    if (f >= nf) return;
+    int2 r = range[front[f]];
+    int shift = 3 * (kBits - (l + 1));
+    int* bd = bounds + 9 * f;
+    bd[0] = r.x;
+    bd[8] = r.y;
+    for (int o = 1; o < 8; ++o) {
+        int lo = r.x, hi = r.y;   // first index with digit >= o
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (int((keys[mid] >> shift) & 7ull) < o) lo = mid + 1;
+            else hi = mid;
+        }
+        bd[o] = lo;
+    }
+    int c = 0, nl = 0;
+    for (int o = 0; o < 8; ++o) {
+        int cnt = bd[o + 1] - bd[o];
+        if (cnt > 0) {
+            ++c;
+            bool leaf = adaptive ? (cnt <= leaf_size || l + 1 == max_depth) : (l + 1 == Lu);
+            if (!leaf) ++nl;
+        }
+    }
+    nch[f] = c;
+    nnl[f] = nl;
+}
+
+__global__ void k_emit(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
+                       const int* __restrict__ bounds, const int* __restrict__ choff,
+                       const int* __restrict__ nloff, int child_start, int nl_base,
+                       int4* __restrict__ anchor, int2* __restrict__ range, int* __restrict__ parent,
+                       int2* __restrict__ child, int* __restrict__ leafflag, uint64_t* __restrict__ mkey,
+                       int* __restrict__ nonleaf, int leaf_size, int adaptive, int max_depth, int Lu) {
+    int f = blockIdx.x * TB + threadIdx.x;
+    if (f >= nf) return;
+    int P = front[f];
+    int4 a = anchor[P];
+    const int* bd = bounds + 9 * f;
+    int c = child_start + choff[f];
+    int first = c, mask = 0;
+    int nl = nl_base + nloff[f];
+    int shift = 3 * (kBits - (l + 1));
+    for (int o = 0; o < 8; ++o) {
+        int cnt = bd[o + 1] - bd[o];
+        if (cnt <= 0) continue;
+        mask |= 1 << o;
+        bool leaf = adaptive ? (cnt <= leaf_size || l + 1 == max_depth) : (l + 1 == Lu);
+        anchor[c] = make_int4(2 * a.x + ((o >> 2) & 1), 2 * a.y + ((o >> 1) & 1), 2 * a.z + (o & 1), l + 1);
+        range[c] = make_int2(bd[o], bd[o + 1]);
+        parent[c] = P;
+        child[c] = make_int2(-1, 0);
+        leafflag[c] = leaf ? 1 : 0;
+        mkey[c] = keys[bd[o]] >> shift;
+        if (!leaf) nonleaf[nl++] = c;
+        ++c;
+    }
+    child[P] = make_int2(first, mask);
+}
+
+__global__ void k_root(int N, int leaf, int4* anchor, int2* range, int* parent, int2* child, int* leafflag,
+                       uint64_t* mkey, int* nonleaf) {
+    anchor[0] = make_int4(0, 0, 0, 0);
+    range[0] = make_int2(0, N);
+    parent[0] = -1;
+    child[0] = make_int2(-1, 0);
+    leafflag[0] = leaf;
+    mkey[0] = 0;
+    if (!leaf) nonleaf[0] = 0;
+}
+
+__global__ void k_gather_pos(const double* __restrict__ x, const uint32_t* __restrict__ idx, int64_t N,
+                             float4* __restrict__ xs, int* __restrict__ perm) {
+    int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x;
+    if (i >= N) return;
+    uint32_t j = idx[i];
+    xs[i] = make_float4(float(x[3 * size_t(j)]), float(x[3 * size_t(j) + 1]), float(x[3 * size_t(j) + 2]), 0.f);
+    perm[i] = int(j);
+}
+
+// ----------------------------------------------------------------- lists
+__device__ inline bool adjacent_boxes(int4 a, int4 b) {
+    // closed cubes on the finest integer grid touch or overlap
+    int sa = kBits - a.w, sb = kBits - b.w;
+    int ax0 = a.x << sa, ay0 = a.y << sa, az0 = a.z << sa, ea = 1 << sa;
+    int bx0 = b.x << sb, by0 = b.y << sb, bz0 = b.z << sb, eb = 1 << sb;
+    return ax0 <= bx0 + eb && bx0 <= ax0 + ea && ay0 <= by0 + eb && by0 <= ay0 + ea && az0 <= bz0 + eb &&
+           bz0 <= az0 + ea;
+}
+
+__device__ inline int find_box(const uint64_t* __restrict__ mkey, int start, int count, uint64_t key) {
+    int lo = start, hi = start + count;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (mkey[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < start + count && mkey[lo] == key) ? lo : -1;
+}
+
+__global__ void k_colleagues(int B, const int4* __restrict__ anchor, const uint64_t* __restrict__ mkey,
+                             LevelTable lt, int* __restrict__ coll) {
+    int b = blockIdx.x * TB + threadIdx.x;
+    if (b >= B) return;
+    int4 a = anchor[b];
+    int l = a.w;
+    int lim = 1 << l;
+    for (int d = 0; d < 27; ++d) {
+        int x = a.x + d / 9 - 1, y = a.y + (d / 3) % 3 - 1, z = a.z + d % 3 - 1;
+        int id = -1;
+        if (x >= 0 && y >= 0 && z >= 0 && x < lim && y < lim && z < lim)
+            id = find_box(mkey, lt.start[l], lt.count[l], morton3(x, y, z));
+        coll[27 * int64_t(b) + d] = id;
+    }
+}
+
+// V-list slots of an octant: (colleague direction D in 0..26, child octant o')
+// pairs whose offset d = 2 (D - 1) + o' - o is not adjacent, ordered by the
+// lexicographic index of d among the 316 far offsets.
+struct VTable {
+    unsigned char D[8][kVPerOct];
+    unsigned char oc[8][kVPerOct];
+    short op[8][kVPerOct];
+};
+
+__global__ void k_vdense(int b0, int nb, const int4* __restrict__ anchor, const int* __restrict__ parent,
+                         const int2* __restrict__ child, const int* __restrict__ leafflag,
+                         const int* __restrict__ coll, const VTable* __restrict__ vt, int* __restrict__ vd) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nb) return;
+    int b = b0 + i;
+    int4 a = anchor[b];
+    int o = ((a.x & 1) << 2) | ((a.y & 1) << 1) | (a.z & 1);
+    int P = parent[b];
+    const int* cp = coll + 27 * int64_t(P);
+    int* out = vd + int64_t(i) * kVPerOct;
+    for (int j = 0; j < kVPerOct; ++j) {
+        int Q = cp[vt->D[o][j]];
+        int src = -1;
+        if (Q >= 0 && !leafflag[Q]) {
+            int2 c = child[Q];
+            int oc = vt->oc[o][j];
+            if ((c.y >> oc) & 1) src = c.x + __popc(c.y & ((1 << oc) - 1));
+        }
+        out[j] = src;
+    }
+}
+
+// Coarse adjacent leaves: leaves of a coarser level adjacent to b; at most 26.
+__global__ void k_cal(int b0, int nb, const int4* __restrict__ anchor, const int* __restrict__ parent,
+                      const int* __restrict__ leafflag, const int* __restrict__ coll, int* __restrict__ cal,
+                      int* __restrict__ bad) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nb) return;
+    int b = b0 + i;
+    int4 ab = anchor[b];
+    int P = parent[b];
+    int cnt = 0;
+    int* out = cal + 26 * int64_t(b);
+    for (int d = 0; d < 27; ++d) {
+        int Q = coll[27 * int64_t(P) + d];
+        if (Q >= 0 && leafflag[Q] && adjacent_boxes(anchor[Q], ab)) {
+            if (cnt < 26) out[cnt] = Q;
+            ++cnt;
+        }
+    }
+    for (int k = 0; k < 26; ++k) {
+        int Q = cal[26 * int64_t(P) + k];
+        if (Q < 0) break;
+        if (adjacent_boxes(anchor[Q], ab)) {
+            if (cnt < 26) out[cnt] = Q;
+            ++cnt;
+        }
+    }
+    if (cnt > 26) atomicOr(bad, 2);
+    for (int k = cnt; k < 26; ++k) out[k] = -1;
+}
+
+// X(b), level >= 2: leaves adjacent to parent(b) of its level or coarser that
+// are not adjacent to b.  mode 0 counts, mode 1 fills.
+__global__ void k_xlist(int b0, int nb, const int4* __restrict__ anchor, const int* __restrict__ parent,
+                        const int* __restrict__ leafflag, const int* __restrict__ coll,
+                        const int* __restrict__ cal, int* __restrict__ cnt_or_off, int* __restrict__ idx,
+                        int mode) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nb) return;
+    int b = b0 + i;
+    int4 ab = anchor[b];
+    int P = parent[b];
+    int c = 0;
+    int at = mode ? cnt_or_off[b] : 0;
+    for (int d = 0; d < 27; ++d) {
+        int Q = coll[27 * int64_t(P) + d];
+        if (Q >= 0 && leafflag[Q] && !adjacent_boxes(anchor[Q], ab)) {
+            if (mode) idx[at + c] = Q;
+            ++c;
+        }
+    }
+    for (int k = 0; k < 26; ++k) {
+        int Q = cal[26 * int64_t(P) + k];
+        if (Q < 0) break;
+        if (!adjacent_boxes(anchor[Q], ab)) {
+            if (mode) idx[at + c] = Q;
+            ++c;
+        }
+    }
+    if (!mode) cnt_or_off[b] = c;
+}
+
+// U(b) own part: leaf colleagues (b included) and coarse adjacent leaves.
+__global__ void k_ulist_own(int B, const int* __restrict__ leafflag, const int* __restrict__ coll,
+                            const int* __restrict__ cal, int* __restrict__ cnt_or_off, int* __restrict__ idx,
+                            int* __restrict__ cursor, int mode) {
+    int b = blockIdx.x * TB + threadIdx.x;
+    if (b >= B || !leafflag[b]) return;
+    int c = 0;
+    int at = mode ? cnt_or_off[b] : 0;
+    for (int d = 0; d < 27; ++d) {
+        int Q = coll[27 * int64_t(b) + d];
+        if (Q >= 0 && leafflag[Q]) {
+            if (mode) idx[at + c] = Q;
+            ++c;
+        }
+    }
+    for (int k = 0; k < 26; ++k) {
+        int Q = cal[26 * int64_t(b) + k];
+        if (Q < 0) break;
+        if (mode) idx[at + c] = Q;
+        ++c;
+    }
+    if (mode) cursor[b] = at + c;
+    else cnt_or_off[b] = c;
+}
+
+// U(b) finer part: every leaf A lists b in cal[A]  ->  A in U(b).
+__global__ void k_ulist_fine(int B, const int* __restrict__ leafflag, const int* __restrict__ cal,
+                             int* __restrict__ cnt, int* __restrict__ idx, int* __restrict__ cursor, int mode) {
+    int a = blockIdx.x * TB + threadIdx.x;
+    if (a >= B || !leafflag[a]) return;
+    for (int k = 0; k < 26; ++k) {
+        int b = cal[26 * int64_t(a) + k];
+        if (b < 0) break;
+        if (mode) idx[atomicAdd(&cursor[b], 1)] = a;
+        else atomicAdd(&cnt[b], 1);
+    }
+}
+
+// W(b) = {A : b in X(A)}.
+__global__ void k_wlist(int b0, int nb, const int* __restrict__ xoff, const int* __restrict__ xidx,
+                        int* __restrict__ cnt, int* __restrict__ idx, int* __restrict__ cursor, int mode) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nb) return;
+    int A = b0 + i;
+    for (int k = xoff[A]; k < xoff[A + 1]; ++k) {
+        int b = xidx[k];
+        if (mode) idx[atomicAdd(&cursor[b], 1)] = A;
+        else atomicAdd(&cnt[b], 1);
+    }
+}
+
+__global__ void k_sort_rows(int B, const int* __restrict__ off, int* __restrict__ idx) {
+    int b = blockIdx.x * TB + threadIdx.x;
+    if (b >= B) return;
+    int s = off[b], e = off[b + 1];
+    for (int i = s + 1; i < e; ++i) {
+        int v = idx[i];
+        int j = i - 1;
+        while (j >= s && idx[j] > v) {
+            idx[j + 1] = idx[j];
+            --j;
+        }
+        idx[j + 1] = v;
+    }
+}
+
+__global__ void k_copy_int(const int* __restrict__ a, int* __restrict__ b, int n) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+__global__ void k_flags(int B, const int* __restrict__ leafflag, const int* __restrict__ xcnt, int b2,
+                        int* __restrict__ fl, int* __restrict__ fx) {
+    int b = blockIdx.x * TB + threadIdx.x;
+    if (b >= B) return;
+    fl[b] = leafflag[b];
+    fx[b] = (b >= b2 && xcnt[b + 1] > xcnt[b]) ? 1 : 0;
+}
+
+__global__ void k_compact(int B, const int* __restrict__ flag, const int* __restrict__ off, int* __restrict__ out) {
+    int b = blockIdx.x * TB + threadIdx.x;
+    if (b >= B) return;
+    if (flag[b]) out[off[b]] = b;
+}
+
+// Counts: V pairs, P2P point pairs (self pairs included), from the lists.
+__global__ void k_counts(int B, int b2, int nv, const int* __restrict__ vd, const int* __restrict__ leafflag,
+                         const int2* __restrict__ range, const int* __restrict__ uoff,
+                         const int* __restrict__ uidx, unsigned long long* __restrict__ out) {
+    int b = blockIdx.x * TB + threadIdx.x;
+    unsigned long long v = 0, pp = 0;
+    if (b < B) {
+        if (b >= b2)
+            for (int j = 0; j < kVPerOct; ++j) v += vd[int64_t(b - b2) * kVPerOct + j] >= 0;
+        if (leafflag[b]) {
+            int2 r = range[b];
+            unsigned long long nt = r.y - r.x;
+            for (int k = uoff[b]; k < uoff[b + 1]; ++k) {
+                int2 ra = range[uidx[k]];
+                pp += nt * (unsigned long long)(ra.y - ra.x);
+            }
+        }
+    }
+    if (v) atomicAdd(&out[0], v);
+    if (pp) atomicAdd(&out[1], pp);
+}
+
+}  // namespace
+
+// Host: the V-slot table, built once.
+static const VTable& vtable_host() {
+    static VTable t;
+    static bool made = false;
+    if (!made) {
+        for (int o = 0; o < 8; ++o) {
+            int ob[3] = {(o >> 2) & 1, (o >> 1) & 1, o & 1};
+            // enumerate offsets in lexicographic order, pick those reachable from octant o
+            int m = 0, j = 0;
+            for (int dx = -3; dx <= 3; ++dx)
+                for (int dy = -3; dy <= 3; ++dy)
+                    for (int dz = -3; dz <= 3; ++dz) {
+                        if (std::max(abs(dx), std::max(abs(dy), abs(dz))) <= 1) continue;
+                        int d[3] = {dx, dy, dz};
+                        bool ok = true;
+                        int Dd[3], oc[3];
+                        for (int k = 0; k < 3; ++k) {
+                            int v = d[k] + ob[k];         // = 2 (D-1) + o'
+                            int oo = ((v % 2) + 2) % 2;
+                            int DD = (v - oo) / 2 + 1;
+                            if (DD < 0 || DD > 2) ok = false;
+                            Dd[k] = DD;
+                            oc[k] = oo;
+                        }
+                        if (ok) {
+                            t.D[o][j] = (unsigned char)(Dd[0] * 9 + Dd[1] * 3 + Dd[2]);
+                            t.oc[o][j] = (unsigned char)((oc[0] << 2) | (oc[1] << 1) | oc[2]);
+                            t.op[o][j] = short(m);
+                            ++j;
+                        }
+                        ++m;
+                    }
+            if (j != kVPerOct) throw Error(KIFMM_ERR_STATE, "V table size");
+        }
+        made = true;
+    }
+    return t;
+}
+
+const void* vtable_host_ptr() { return &vtable_host(); }
+
+static int read_int(const int* dptr, hipStream_t s) {
+    int v = 0;
+    KIFMM_HIP(hipMemcpyAsync(&v, dptr, 4, hipMemcpyDeviceToHost, s));
+    KIFMM_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
+    const int64_t N = P->N;
+    const kifmm_options& o = P->opt;
+    // positions copy
+    P->x64.ensure(size_t(N) * 24);
+    KIFMM_HIP(hipMemcpyAsync(P->x64.p, positions, size_t(N) * 24, hipMemcpyDeviceToDevice, s));
+    P->flag.ensure(64);
+    int* bad = P->flag.as<int>();
+    KIFMM_HIP(hipMemsetAsync(bad, 0, 64, s));
+
+    // root cube
+    if (o.explicit_root) {
+        for (int d = 0; d < 3; ++d) P->lo[d] = o.root_lo[d];
+        P->side = o.root_side;
+    } else {
+        int nb = std::min<int64_t>(1024, (N + TB - 1) / TB);
+        P->tmp_a.ensure(size_t(nb) * 6 * 8);
+        hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(TB), 0, s, P->x64.as<double>(), N, P->tmp_a.as<double>(), bad);
+        std::vector<double> part(size_t(nb) * 6);
+        int hbad = 0;
+        KIFMM_HIP(hipMemcpyAsync(part.data(), P->tmp_a.p, part.size() * 8, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipStreamSynchronize(s));
+        if (hbad) throw Error(KIFMM_ERR_INPUT, "non-finite position");
+        double mn[3] = {1e308, 1e308, 1e308}, mx[3] = {-1e308, -1e308, -1e308};
+        for (int b = 0; b < nb; ++b)
+            for (int d = 0; d < 3; ++d) {
+                mn[d] = std::min(mn[d], part[6 * b + d]);
+                mx[d] = std::max(mx[d], part[6 * b + 3 + d]);
+            }
+        double ext = std::max(mx[0] - mn[0], std::max(mx[1] - mn[1], mx[2] - mn[2]));
+        double sd = 1.0;
+        if (ext > 0) {
+            int e = 0;
+            double m = frexp(ext * (1.0 + ldexp(1.0, -10)), &e);
+            sd = (m == 0.5) ? ldexp(1.0, e - 1) : ldexp(1.0, e);
+        }
+        P->side = sd;
+        for (int d = 0; d < 3; ++d) P->lo[d] = floor(mn[d] * 4096.0 / sd) * sd / 4096.0;
+    }
+
+    // keys and sort
+    P->keys.ensure(size_t(N) * 8);
+    P->tmp_b.ensure(size_t(N) * 4);   // idx
+    P->tmp_c.ensure(size_t(N) * 8);   // key tmp
+    P->tmp_d.ensure(size_t(N) * 4);   // idx tmp
+    uint64_t* keys = P->keys.as<uint64_t>();
+    uint32_t* idx = P->tmp_b.as<uint32_t>();
+    double scale = ldexp(1.0, kBits) / P->side;
+    hipLaunchKernelGGL(k_keys, dim3(nblocks(N)), dim3(TB), 0, s, P->x64.as<double>(), N, P->lo[0], P->lo[1],
+                       P->lo[2], scale, P->side, o.explicit_root, keys, idx, bad);
+    if (read_int(bad, s)) throw Error(KIFMM_ERR_INPUT, o.explicit_root ? "non-finite position or point outside the explicit root" : "non-finite position");
+    radix_sort(P, keys, idx, P->tmp_c.as<uint64_t>(), P->tmp_d.as<uint32_t>(), N, 63, s);
+    P->xs.ensure(size_t(N) * 16);
+    P->perm.ensure(size_t(N) * 4);
+    hipLaunchKernelGGL(k_gather_pos, dim3(nblocks(N)), dim3(TB), 0, s, P->x64.as<double>(), idx, N,
+                       P->xs.as<float4>(), P->perm.as<int>());
+
+    // levels
+    int Lu = 0;
+    while (Lu < o.max_depth && double(P->leaf) * pow(8.0, Lu) < double(N)) ++Lu;
+    int64_t cap = std::max<int64_t>(1024, 4 * (N / std::max(1, P->leaf)) + 64);
+    auto ensure_boxes = [&](int64_t need, int64_t keep) {
+        P->bx_anchor.grow(size_t(need) * 16, size_t(keep) * 16, s);
+        P->bx_range.grow(size_t(need) * 8, size_t(keep) * 8, s);
+        P->bx_parent.grow(size_t(need) * 4, size_t(keep) * 4, s);
+        P->bx_child.grow(size_t(need) * 8, size_t(keep) * 8, s);
+        P->bx_leaf.grow(size_t(need) * 4, size_t(keep) * 4, s);
+        P->bx_mkey.grow(size_t(need) * 8, size_t(keep) * 8, s);
+        P->nonleaf.grow(size_t(need) * 4, size_t(keep) * 4, s);
+    };
+    ensure_boxes(cap, 0);
+    int root_leaf = o.adaptive ? (N <= P->leaf || o.max_depth == 0) : (Lu == 0);
+    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, int(N), root_leaf, P->bx_anchor.as<int4>(),
+                       P->bx_range.as<int2>(), P->bx_parent.as<int>(), P->bx_child.as<int2>(),
+                       P->bx_leaf.as<int>(), P->bx_mkey.as<uint64_t>(), P->nonleaf.as<int>());
+    P->lev.clear();
+    LevelInfo L0;
+    L0.start = 0;
+    L0.count = 1;
+    L0.nl_start = 0;
+    L0.nl_count = root_leaf ? 0 : 1;
+    P->lev.push_back(L0);
+    int64_t total = 1, nl_total = L0.nl_count;
+    for (int l = 0;; ++l) {
+        const LevelInfo cur = P->lev[l];
+        if (cur.nl_count == 0) break;
+        int nf = int(cur.nl_count);
+        P->tmp_a.ensure(size_t(nf) * 9 * 4 + size_t(nf) * 16 + 64);
+        int* bounds = P->tmp_a.as<int>();
+        int* nch = bounds + 9 * nf;
+        int* nnl = nch + nf + 1;
+        // tmp_e holds the scans (nf+1 each)
+        P->tmp_e.ensure(size_t(nf + 1) * 8 + 64);
+        int* choff = P->tmp_e.as<int>();
+        int* nloff = choff + nf + 1;
+        const int* front = P->nonleaf.as<int>() + cur.nl_start;
+        hipLaunchKernelGGL(k_split, dim3(nblocks(nf)), dim3(TB), 0, s, front, nf, l, keys, P->bx_range.as<int2>(),
+                           bounds, nch, nnl, P->leaf, o.adaptive, o.max_depth, Lu);
+        KIFMM_HIP(hipMemsetAsync(nch + nf, 0, 4, s));
+        KIFMM_HIP(hipMemsetAsync(nnl + nf, 0, 4, s));
+        exclusive_scan<int>(P, nch, choff, nf + 1, s);
+        exclusive_scan<int>(P, nnl, nloff, nf + 1, s);
+        int tot[2];
+        KIFMM_HIP(hipMemcpyAsync(&tot[0], choff + nf, 4, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipMemcpyAsync(&tot[1], nloff + nf, 4, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipStreamSynchronize(s));
+        LevelInfo nx;
+        nx.start = total;
+        nx.count = tot[0];
+        nx.nl_start = nl_total;
+        nx.nl_count = tot[1];
+        if (total + nx.count > cap) {
+            int64_t ncap = std::max<int64_t>(2 * cap, total + nx.count + 64);
+            ensure_boxes(ncap, total);
+            cap = ncap;
+            front = P->nonleaf.as<int>() + cur.nl_start;
+        }
+        hipLaunchKernelGGL(k_emit, dim3(nblocks(nf)), dim3(TB), 0, s, front, nf, l, keys, bounds, choff, nloff,
+                           int(nx.start), int(nx.nl_start), P->bx_anchor.as<int4>(), P->bx_range.as<int2>(),
+                           P->bx_parent.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(),
+                           P->bx_mkey.as<uint64_t>(), P->nonleaf.as<int>(), P->leaf, o.adaptive, o.max_depth, Lu);
+        total += nx.count;
+        nl_total += nx.nl_count;
+        P->lev.push_back(nx);
+        if (int(P->lev.size()) > kMaxLevels) throw Error(KIFMM_ERR_STATE, "tree deeper than the key resolution");
+    }
+    P->B = total;
+    P->depth = int(P->lev.size()) - 1;
+    const int B = int(total);
+    const int b2 = P->depth >= 2 ? int(P->lev[2].start) : B;
+
+    LevelTable lt{};
+    for (int l = 0; l <= P->depth; ++l) {
+        lt.start[l] = int(P->lev[l].start);
+        lt.count[l] = int(P->lev[l].count);
+    }
+    // colleagues
+    P->coll.ensure(size_t(B) * 27 * 4);
+    hipLaunchKernelGGL(k_colleagues, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_anchor.as<int4>(),
+                       P->bx_mkey.as<uint64_t>(), lt, P->coll.as<int>());
+    // V dense table
+    static DBuf* vt_dev = nullptr;   // per process, small
+    if (!vt_dev) {
+        vt_dev = new DBuf();
+        vt_dev->ensure(sizeof(VTable));
+        KIFMM_HIP(hipMemcpy(vt_dev->p, &vtable_host(), sizeof(VTable), hipMemcpyHostToDevice));
+    }
+    int nvb = B - b2;
+    P->vdense.ensure(size_t(std::max(nvb, 1)) * kVPerOct * 4);
+    if (nvb > 0)
+        hipLaunchKernelGGL(k_vdense, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
+                           P->bx_parent.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->coll.as<int>(),
+                           vt_dev->as<VTable>(), P->vdense.as<int>());
+    // coarse adjacent leaves, top-down
+    P->cal.ensure(size_t(B) * 26 * 4);
+    KIFMM_HIP(hipMemsetAsync(P->cal.p, 0xff, size_t(B) * 26 * 4, s));
+    for (int l = 1; l <= P->depth; ++l)
+        hipLaunchKernelGGL(k_cal, dim3(nblocks(P->lev[l].count)), dim3(TB), 0, s, int(P->lev[l].start),
+                           int(P->lev[l].count), P->bx_anchor.as<int4>(), P->bx_parent.as<int>(),
+                           P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), bad);
+    // X lists (rows over all boxes; only level >= 2 non-empty)
+    P->x_off.ensure(size_t(B + 1) * 4);
+    int* xoff = P->x_off.as<int>();
+    KIFMM_HIP(hipMemsetAsync(xoff, 0, size_t(B + 1) * 4, s));
+    if (nvb > 0)
+        hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
+                           P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
+                           (int*)nullptr, 0);
+    exclusive_scan<int>(P, xoff, xoff, B + 1, s);
+    int nx = read_int(xoff + B, s);
+    P->x_idx.ensure(size_t(std::max(nx, 1)) * 4);
+    if (nvb > 0 && nx > 0) {
+        hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
+                           P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
+                           P->x_idx.as<int>(), 1);
+        hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(B)), dim3(TB), 0, s, B, xoff, P->x_idx.as<int>());
+    }
+    // U lists
+    P->u_off.ensure(size_t(B + 1) * 4);
+    int* uoff = P->u_off.as<int>();
+    P->tmp_e.ensure(size_t(B + 1) * 4 * 2);
+    int* cursor = P->tmp_e.as<int>();
+    int* fcnt = cursor + (B + 1);
+    KIFMM_HIP(hipMemsetAsync(uoff, 0, size_t(B + 1) * 4, s));
+    KIFMM_HIP(hipMemsetAsync(fcnt, 0, size_t(B + 1) * 4, s));
+    hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
+                       P->cal.as<int>(), uoff, (int*)nullptr, (int*)nullptr, 0);
+    hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
+                       uoff, (int*)nullptr, (int*)nullptr, 0);
+    exclusive_scan<int>(P, uoff, uoff, B + 1, s);
+    int nu = read_int(uoff + B, s);
+    P->u_idx.ensure(size_t(std::max(nu, 1)) * 4);
+    hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
+                       P->cal.as<int>(), uoff, P->u_idx.as<int>(), cursor, 1);
+    hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
+                       (int*)nullptr, P->u_idx.as<int>(), cursor, 1);
+    hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(B)), dim3(TB), 0, s, B, uoff, P->u_idx.as<int>());
+    // W lists = transpose of X
+    P->w_off.ensure(size_t(B + 1) * 4);
+    int* woff = P->w_off.as<int>();
+    KIFMM_HIP(hipMemsetAsync(woff, 0, size_t(B + 1) * 4, s));
+    if (nvb > 0)
+        hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(), woff,
+                           (int*)nullptr, (int*)nullptr, 0);
+    exclusive_scan<int>(P, woff, woff, B + 1, s);
+    int nw = read_int(woff + B, s);
+    P->w_idx.ensure(size_t(std::max(nw, 1)) * 4);
+    if (nvb > 0 && nw > 0) {
+        hipLaunchKernelGGL(k_copy_int, dim3(nblocks(B + 1)), dim3(TB), 0, s, woff, cursor, B + 1);
+        hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(),
+                           (int*)nullptr, P->w_idx.as<int>(), cursor, 1);
+        hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(B)), dim3(TB), 0, s, B, woff, P->w_idx.as<int>());
+    }
+    // leaf list and X-box list
+    P->tmp_f.ensure(size_t(B + 1) * 4 * 4);
+    int* fl = P->tmp_f.as<int>();
+    int* fx = fl + (B + 1);
+    int* ol = fx + (B + 1);
+    int* ox = ol + (B + 1);
+    hipLaunchKernelGGL(k_flags, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), xoff, b2, fl, fx);
+    KIFMM_HIP(hipMemsetAsync(fl + B, 0, 4, s));
+    KIFMM_HIP(hipMemsetAsync(fx + B, 0, 4, s));
+    exclusive_scan<int>(P, fl, ol, B + 1, s);
+    exclusive_scan<int>(P, fx, ox, B + 1, s);
+    int nl = read_int(ol + B, s);
+    int nxb = read_int(ox + B, s);
+    P->nleaves = nl;
+    P->n_xboxes = nxb;
+    P->leaves.ensure(size_t(std::max(nl, 1)) * 4);
+    P->xboxes.ensure(size_t(std::max(nxb, 1)) * 4);
+    hipLaunchKernelGGL(k_compact, dim3(nblocks(B)), dim3(TB), 0, s, B, fl, ol, P->leaves.as<int>());
+    hipLaunchKernelGGL(k_compact, dim3(nblocks(B)), dim3(TB), 0, s, B, fx, ox, P->xboxes.as<int>());
+    // counts
+    P->tmp_a.ensure(64);
+    unsigned long long* dc = P->tmp_a.as<unsigned long long>();
+    KIFMM_HIP(hipMemsetAsync(dc, 0, 16, s));
+    hipLaunchKernelGGL(k_counts, dim3(nblocks(B)), dim3(TB), 0, s, B, b2, nvb, P->vdense.as<int>(),
+                       P->bx_leaf.as<int>(), P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), dc);
+    unsigned long long hc[2];
+    int hbad = 0;
+    KIFMM_HIP(hipMemcpyAsync(hc, dc, 16, hipMemcpyDeviceToHost, s));
+    KIFMM_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+    KIFMM_HIP(hipStreamSynchronize(s));
+    if (hbad & 2) throw Error(KIFMM_ERR_STATE, "more than 26 coarse adjacent leaves");
+    P->counts[0] = B;
+    P->counts[1] = nl;
+    P->counts[2] = P->depth;
+    P->counts[3] = int64_t(hc[0]);
+    P->counts[4] = int64_t(hc[1]);
+    P->counts[5] = nw;
+    P->counts[6] = nx;
+    P->counts[7] = nu;
+    P->counts[8] = N;
+    P->counts[9] = P->n;
+}
+
+}  // namespace kifmm

@@ -1,0 +1,192 @@
+"""Python front end: a plan handle and the autograd wrapper.
+
+Torch provides device memory and the stream; every step of the evaluation runs
+in libkifmm.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import KifmmError, Options, check
+
+KERNELS = {"laplace": _lib.KIFMM_LAPLACE, "coulomb": _lib.KIFMM_LAPLACE, "gravity": _lib.KIFMM_GRAVITY}
+PRECISIONS = {"fp32": _lib.KIFMM_FP32, "split_bf16": _lib.KIFMM_SPLIT_BF16}
+PHASES = ["p2m", "up", "p2l", "m2l", "down", "far", "p2p", "total"]
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.contiguous()
+
+
+class Plan:
+    """KIFMM plan for N points: tree, lists and operators on the device."""
+
+    def __init__(self, positions: torch.Tensor, kernel: str = "laplace", p: int = 6, leaf_size: int = 128,
+                 adaptive: bool = True, max_depth: int = 21, precision: str = "fp32",
+                 pinv_rtol: float = 1e-7, root=None, profile: bool = False, stream=None):
+        L = _lib.lib()
+        self.n = int(positions.shape[0])
+        self.positions = _need(positions, torch.float64, (self.n, 3), "positions")
+        self.kernel = kernel
+        self.p = p
+        self.leaf_size = leaf_size
+        opt = Options()
+        L.kifmm_default_options(ctypes.byref(opt))
+        opt.adaptive = int(bool(adaptive))
+        opt.max_depth = int(max_depth)
+        opt.precision = PRECISIONS[precision]
+        opt.pinv_rtol = float(pinv_rtol)
+        opt.profile = int(bool(profile))
+        if root is not None:
+            opt.explicit_root = 1
+            for d in range(3):
+                opt.root_lo[d] = float(root[0][d])
+            opt.root_side = float(root[1])
+        h = ctypes.c_void_p()
+        check(L.kifmm_setup_ex(_ptr(self.positions), self.n, KERNELS[kernel], int(p), int(leaf_size),
+                               ctypes.byref(opt), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().kifmm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if not self._h or not self._h.value:
+            raise KifmmError(-5, "plan is closed")
+        return self._h
+
+    # -- calls
+    def rebuild(self, positions: torch.Tensor, stream=None):
+        self.positions = _need(positions, torch.float64, (self.n, 3), "positions")
+        check(_lib.lib().kifmm_rebuild(self.handle, _ptr(self.positions), _stream(stream)))
+
+    def set_precision(self, precision: str):
+        check(_lib.lib().kifmm_set_precision(self.handle, PRECISIONS[precision]))
+
+    def evaluate(self, charges: torch.Tensor, potential=True, field=True, stream=None):
+        q = _need(charges, torch.float32, (self.n,), "charges")
+        u = torch.empty(self.n, dtype=torch.float32, device=q.device) if potential else None
+        E = torch.empty((self.n, 3), dtype=torch.float32, device=q.device) if field else None
+        check(_lib.lib().kifmm_evaluate(self.handle, _ptr(q), _ptr(u), _ptr(E), _stream(stream)))
+        return u, E
+
+    def backward(self, charges, grad_potential=None, grad_field=None, stream=None):
+        q = _need(charges, torch.float32, (self.n,), "charges")
+        gu = None if grad_potential is None else _need(grad_potential, torch.float32, (self.n,), "grad_potential")
+        gE = None if grad_field is None else _need(grad_field, torch.float32, (self.n, 3), "grad_field")
+        gq = torch.empty(self.n, dtype=torch.float32, device=q.device)
+        gx = torch.empty((self.n, 3), dtype=torch.float32, device=q.device)
+        check(_lib.lib().kifmm_backward(self.handle, _ptr(q), _ptr(gu), _ptr(gE), _ptr(gq), _ptr(gx),
+                                        _stream(stream)))
+        return gq, gx
+
+    def clump_reduce(self, charges, field, offsets, centers, stream=None):
+        C = int(offsets.shape[0]) - 1
+        q = _need(charges, torch.float32, (self.n,), "charges")
+        E = _need(field, torch.float32, (self.n, 3), "field")
+        off = _need(offsets, torch.int64, (C + 1,), "offsets")
+        cen = _need(centers, torch.float64, (C, 3), "centers")
+        F = torch.empty((C, 3), dtype=torch.float64, device=q.device)
+        T = torch.empty((C, 3), dtype=torch.float64, device=q.device)
+        check(_lib.lib().kifmm_clump_reduce(self.handle, _ptr(q), _ptr(E), _ptr(off), C, _ptr(cen), _ptr(F),
+                                            _ptr(T), _stream(stream)))
+        return F, T
+
+    # -- introspection
+    def counts(self) -> dict:
+        out = (ctypes.c_int64 * 10)()
+        check(_lib.lib().kifmm_get_counts(self.handle, out))
+        keys = ["boxes", "leaves", "depth", "v_pairs", "p2p_pairs", "w_pairs", "x_pairs", "u_pairs", "n",
+                "surface_points"]
+        return dict(zip(keys, [int(v) for v in out]))
+
+    def tree(self) -> dict:
+        c = self.counts()
+        N, B = c["n"], c["boxes"]
+        keys = np.empty(N, dtype=np.uint64)
+        perm = np.empty(N, dtype=np.int64)
+        level = np.empty(B, dtype=np.int32)
+        anchor = np.empty((B, 3), dtype=np.int32)
+        begin = np.empty(B, dtype=np.int64)
+        end = np.empty(B, dtype=np.int64)
+        parent = np.empty(B, dtype=np.int64)
+        leaf = np.empty(B, dtype=np.int8)
+        root = np.empty(4, dtype=np.float64)
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        check(_lib.lib().kifmm_copy_tree(self.handle, p(keys), p(perm), p(level), p(anchor), p(begin), p(end),
+                                         p(parent), p(leaf), p(root)))
+        return dict(keys=keys, perm=perm, level=level, anchor=anchor, begin=begin, end=end, parent=parent,
+                    is_leaf=leaf.astype(bool), lo=root[:3].copy(), side=float(root[3]))
+
+    def list_csr(self, which: str):
+        B = self.counts()["boxes"]
+        off = np.empty(B + 1, dtype=np.int64)
+        L = _lib.lib()
+        check(L.kifmm_copy_list(self.handle, which.encode(), off.ctypes.data_as(ctypes.c_void_p), None))
+        idx = np.empty(int(off[-1]), dtype=np.int64)
+        check(L.kifmm_copy_list(self.handle, which.encode(), off.ctypes.data_as(ctypes.c_void_p),
+                                idx.ctypes.data_as(ctypes.c_void_p) if idx.size else None))
+        return off, idx
+
+    def phase_times(self) -> dict:
+        out = (ctypes.c_float * 8)()
+        n = check(_lib.lib().kifmm_get_phase_times(self.handle, out, 8))
+        return {PHASES[k]: float(out[k]) for k in range(n)}
+
+
+class KifmmFunction(torch.autograd.Function):
+    """(charges, positions) -> (potential, field) with the library's adjoint as backward.
+
+    ``positions`` must be the tensor the plan was built from (the tree is
+    frozen at those positions); its gradient is returned in float64.
+    """
+
+    @staticmethod
+    def forward(ctx, charges, positions, plan: Plan):
+        if positions.data_ptr() != plan.positions.data_ptr():
+            raise ValueError("positions must be the tensor the plan was built from")
+        u, E = plan.evaluate(charges)
+        ctx.plan = plan
+        ctx.save_for_backward(charges)
+        return u, E
+
+    @staticmethod
+    def backward(ctx, gu, gE):
+        (charges,) = ctx.saved_tensors
+        gu = None if gu is None else gu.contiguous().float()
+        gE = None if gE is None else gE.contiguous().float()
+        gq, gx = ctx.plan.backward(charges, gu, gE)
+        return gq, gx.to(torch.float64), None
+
+
+def kifmm(charges, positions, plan: Plan):
+    return KifmmFunction.apply(charges, positions, plan)
