@@ -98,7 +98,7 @@ def cpu_baseline(seconds_target=20.0):
     """FP64 oracle forward + adjoint on a bounded sample of the same workload."""
     import workloads
     from oracle import kifmm
-    n = 16384
+    n = 65536
     w = workloads.make(2, n=n)
     rng = np.random.default_rng(5)
     ub = rng.standard_normal(n)
