@@ -56,6 +56,7 @@ void alloc_densities(kifmm_plan* P, hipStream_t s) {
         b->ensure(bytes);
         if (fresh) KIFMM_HIP(hipMemsetAsync(b->p, 0, b->cap, s));
     }
+    P->psi_m.ensure(size_t(kM2LSplit) * bytes);
     P->far.ensure(size_t(P->N) * 10 * 4);
 }
 
@@ -169,7 +170,7 @@ int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float
         P->last_stream = s;
         begin_phases(P, s);
         launch_gather(P, charges, nullptr, nullptr, false, s);
-        run_sweep(P, 0, false, s, true);
+        run_sweep(P, 1, s, true);
         run_far_eval(P, false, nullptr, s);
         record_phase(P, 5, s);
         launch_p2p_forward(P, potential, field, s);
@@ -188,8 +189,7 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
         P->last_stream = s;
         begin_phases(P, s);
         launch_gather(P, charges, grad_potential, grad_field, true, s);
-        run_sweep(P, 0, false, s, false);
-        run_sweep(P, 1, true, s, false);
+        run_sweep(P, 2, s, false);
         run_far_eval(P, true, nullptr, s);
         for (int k = 0; k < 6; ++k) record_phase(P, k, s);
         launch_p2p_backward(P, grad_charges, grad_positions, s);

@@ -16,6 +16,7 @@ constexpr int kBits = 21;              // key bits per axis
 constexpr int kNumV = 316;             // far offsets in [-3,3]^3 minus [-1,1]^3
 constexpr int kVPerOct = 189;          // V-list offsets reachable from one octant
 constexpr int kMaxLevels = 22;
+constexpr int kM2LSplit = 4;          // M2L V slots split over this many blocks per tile
 
 // Error carrying a status code; caught at the ABI.
 struct Error : std::runtime_error {
@@ -85,9 +86,8 @@ struct Operators {
     DBuf dc2e_v;       // float [npad][npad]  U
     DBuf m2m;          // float [8][npad][npad]
     DBuf l2l;          // float [8][npad][npad] (includes the factor 1/2 of the child width)
-    DBuf m2l;          // float [316][npad][npad]
-    DBuf m2l_hi;       // bf16  [316][npad][npad]
-    DBuf m2l_lo;       // bf16  [316][npad][npad]
+    DBuf m2l_f32;      // [316][npad/32 chunks][npad/16 row blocks][2][64] x 16 B (FP32 fragments)
+    DBuf m2l_bf16;     // same shape, bf16 hi half then lo half
     std::vector<double> sigma;   // singular values of K(uc, ue), descending
 };
 
@@ -149,9 +149,13 @@ struct kifmm_plan {
     kifmm::DBuf vdense;     // int32 [B - start(2)][189] V sources by octant-local offset slot
     kifmm::DBuf u_off, u_idx, w_off, w_idx, x_off, x_idx;   // CSR over boxes, int32
     kifmm::DBuf xboxes;     // int32 boxes with a non-empty X list
+    kifmm::DBuf items_near, items_far;   // int2 (leaf, first target) work items, heaviest first
+    kifmm::DBuf item_tmp;
+    int64_t n_items = 0;
     int64_t n_xboxes = 0;
     // densities: [rhs][B][npad]
     kifmm::DBuf psi_u, phi_u, psi_d, phi_d;
+    kifmm::DBuf psi_m;      // M2L partial check potentials [kM2LSplit][rhs][B][npad]
     // per-evaluation work
     kifmm::DBuf pts;        // float4 [N] sorted (x, y, z, q)
     kifmm::DBuf src2;       // float4 [N] sorted (ubar, Ebar) for the adjoint sweep
@@ -168,7 +172,7 @@ namespace kifmm {
 // ---- tree.hip
 void build_tree(kifmm_plan* P, const double* positions, hipStream_t s);
 // ---- farfield.hip
-void run_sweep(kifmm_plan* P, int rhs, bool dipole, hipStream_t s, bool record);
+void run_sweep(kifmm_plan* P, int nrhs, hipStream_t s, bool record);
 void run_far_eval(kifmm_plan* P, bool backward, const float* ebar_sorted_unused, hipStream_t s);
 // ---- nearfield.hip
 void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const float* gfield,

@@ -308,46 +308,208 @@ struct VOps {
     short op[8][kVPerOct];
 };
 
-template <int NP, bool SPLIT>
-__global__ __launch_bounds__(256) void k_m2l(TaskTable tt, const int* __restrict__ nonleaf,
-                                             const int2* __restrict__ child, const int* __restrict__ vdense,
-                                             int b2, const VOps* __restrict__ vops,
-                                             const float* __restrict__ phi_u, float* __restrict__ psi_d,
-                                             const float* __restrict__ m2l, const __bf16* __restrict__ m2l_hi,
-                                             const __bf16* __restrict__ m2l_lo) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Hardware dispatch sends block b to XCD b % 8; give every XCD a contiguous
+// range of logical tiles so that neighbouring tiles share that XCD's L2.
+__device__ inline int xcd_remap(int b, int nb) {
+    const int q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+__device__ inline int next_slot(const unsigned* mk, int j) {
+    for (int k = j + 1; k < kVPerOct;) {
+        unsigned w = mk[k >> 5] >> (k & 31);
+        if (w) return k + __builtin_ctz(w);
+        k = (k | 31) + 1;
+    }
+    return kVPerOct;
+}
+
+__device__ inline v8bf as_bf8(uint4 u) {
+    v8bf r;
+    __builtin_memcpy(&r, &u, 16);
+    return r;
+}
+
+__device__ inline void load8(float* b, const float* __restrict__ p) {
+    if (p) {
+        float4 b0 = *reinterpret_cast<const float4*>(p);
+        float4 b1 = *reinterpret_cast<const float4*>(p + 4);
+        b[0] = b0.x; b[1] = b0.y; b[2] = b0.z; b[3] = b0.w;
+        b[4] = b1.x; b[5] = b1.y; b[6] = b1.z; b[7] = b1.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b[i] = 0.f;
+    }
+}
+
+// M2L over the V lists of all levels >= 2 in one launch.  A block owns the
+// targets at octant o of 4*TG*16 consecutive non-leaf parents (TG = CB/nrhs
+// column blocks of 16 targets per wave, each with nrhs right-hand sides), so
+// every target of the block uses the same operator in V slot j.  The block
+// walks the slots that any of its targets uses; each operator is streamed in
+// 32-column chunks (fragment order, NP/16*128 words) through a double-buffered
+// LDS tile shared by the four waves, while the next chunk and the next source
+// columns are already in flight.
+template <int NP, bool SPLIT, int CB>
+__global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, int nsplit, int nrhs,
+                                             const int* __restrict__ nonleaf, const int2* __restrict__ child,
+                                             const int* __restrict__ vdense, int b2, const VOps* __restrict__ vops,
+                                             const float* __restrict__ phi_u, const float* __restrict__ psi_d,
+                                             float* __restrict__ psi_m, size_t rhs_stride, size_t split_stride,
+                                             const uint4* __restrict__ ops) {
+    constexpr int RB = NP / 16, KC = NP / 32, WORDS = RB * 128, PER = WORDS / 256;
+    __shared__ uint4 lds[2][WORDS];
+    __shared__ unsigned vmask[6];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
+    const int lid = xcd_remap(blockIdx.x, nblk);
+    const int split = lid / ntile, bid = lid % ntile;
+    const int j_lo = split * kVPerOct / nsplit, j_hi = (split + 1) * kVPerOct / nsplit;
     int e = 0;
-    while (e + 1 < tt.nlev && int(blockIdx.x) >= tt.first[e + 1]) ++e;
-    int local = blockIdx.x - tt.first[e];
-    int o = local % 8;
-    int grp = local / 8;
-    int slot = (grp * WAVES + wave) * 16 + (lane & 15);
-    int t = -1;
-    if (slot < tt.nl_count[e]) {
-        int Pb = nonleaf[tt.nl_start[e] + slot];
-        int2 ch = child[Pb];
-        if ((ch.y >> o) & 1) t = ch.x + __popc(ch.y & ((1 << o) - 1));
+    while (e + 1 < tt.nlev && bid >= tt.first[e + 1]) ++e;
+    const int local = bid - tt.first[e];
+    const int o = local % 8, grp = local / 8;
+    const int TG = CB / nrhs;
+    int tgt[CB];
+    const float* bsrc[CB];
+    const int* vrow[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int tg = cb / nrhs;
+        const int slot = ((grp * WAVES + wave) * TG + tg) * 16 + (lane & 15);
+        int t = -1;
+        if (slot < tt.nl_count[e]) {
+            const int2 ch = child[nonleaf[tt.nl_start[e] + slot]];
+            if ((ch.y >> o) & 1) t = ch.x + __popc(ch.y & ((1 << o) - 1));
+        }
+        tgt[cb] = t;
+        vrow[cb] = t >= 0 ? vdense + size_t(t - b2) * kVPerOct : nullptr;
+        bsrc[cb] = phi_u + size_t(cb % nrhs) * rhs_stride;
     }
-    if (!__ballot(t >= 0)) return;
-    v4f acc[NP / 16];
-    load_acc<NP>(acc, t >= 0 ? psi_d + size_t(t) * NP : nullptr, lane);
-    const int* vrow = t >= 0 ? vdense + size_t(t - b2) * kVPerOct : nullptr;
-    for (int j = 0; j < kVPerOct; ++j) {
-        int src = vrow ? vrow[j] : -1;
-        if (!__ballot(src >= 0)) continue;
-        int m = vops->op[o][j];
-        const float* bcol = src >= 0 ? phi_u + size_t(src) * NP : nullptr;
-        if (SPLIT)
-            gemm_bf16x3<NP>(acc, m2l_hi + size_t(m) * NP * NP, m2l_lo + size_t(m) * NP * NP, bcol, lane);
-        else
-            gemm_f32<NP>(acc, m2l + size_t(m) * NP * NP, bcol, lane);
+    if (tid < 6) vmask[tid] = 0;
+    __syncthreads();
+    {
+        unsigned m6[6] = {0, 0, 0, 0, 0, 0};
+        for (int cb = 0; cb < CB; cb += nrhs)
+            if (vrow[cb])
+                for (int j = j_lo; j < j_hi; ++j)
+                    if (vrow[cb][j] >= 0) m6[j >> 5] |= 1u << (j & 31);
+        for (int w = 0; w < 6; ++w)
+            if (m6[w]) atomicOr(&vmask[w], m6[w]);
     }
-    store_acc<NP>(acc, t >= 0 ? psi_d + size_t(t) * NP : nullptr, lane);
+    __syncthreads();
+    unsigned mk[6];
+#pragma unroll
+    for (int w = 0; w < 6; ++w) mk[w] = vmask[w];
+    int j = next_slot(mk, -1);   // block-uniform; kVPerOct when this slot range is empty
+    // split 0 starts from the X-list check potential, the others from zero
+    v4f acc[CB][RB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+        load_acc<NP>(acc[cb],
+                     (split == 0 && tgt[cb] >= 0) ? psi_d + size_t(cb % nrhs) * rhs_stride + size_t(tgt[cb]) * NP
+                                                  : nullptr,
+                     lane);
+    const int g8 = 8 * (lane >> 4);
+    int kc = 0;
+    uint4 areg[PER];
+    float breg[CB][8];
+    const float* col[CB];
+    if (j < kVPerOct) {
+        const uint4* a = ops + (size_t(vops->op[o][j]) * KC + kc) * WORDS;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) areg[i] = a[i * 256 + tid];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int src = vrow[cb] ? vrow[cb][j] : -1;
+            col[cb] = src >= 0 ? bsrc[cb] + size_t(src) * NP : nullptr;
+            load8(breg[cb], col[cb] ? col[cb] + g8 : nullptr);
+        }
+    }
+    int buf = 0;
+    while (j < kVPerOct) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) lds[buf][i * 256 + tid] = areg[i];
+        __syncthreads();
+        float cur[CB][8];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cur[cb][i] = breg[cb][i];
+        // advance and prefetch the next (slot, chunk)
+        int nkc = kc + 1, nj = j;
+        if (nkc == KC) {
+            nkc = 0;
+            nj = next_slot(mk, j);
+        }
+        if (nj < kVPerOct) {
+            const uint4* a = ops + (size_t(vops->op[o][nj]) * KC + nkc) * WORDS;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) areg[i] = a[i * 256 + tid];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                if (nj != j) {
+                    const int src = vrow[cb] ? vrow[cb][nj] : -1;
+                    col[cb] = src >= 0 ? bsrc[cb] + size_t(src) * NP : nullptr;
+                }
+                load8(breg[cb], col[cb] ? col[cb] + nkc * 32 + g8 : nullptr);
+            }
+        }
+        // compute chunk (j, kc)
+        const uint4* L = lds[buf];
+        if (SPLIT) {
+            v8bf bh[CB], bl[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    __bf16 h = (__bf16)cur[cb][i];
+                    bh[cb][i] = h;
+                    bl[cb][i] = (__bf16)(cur[cb][i] - (float)h);
+                }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const v8bf ah = as_bf8(L[rb * 128 + lane]);
+                const v8bf al = as_bf8(L[rb * 128 + 64 + lane]);
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    v4f c = acc[cb][rb];
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], c, 0, 0, 0);
+                    acc[cb][rb] = c;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const uint4 u0 = L[rb * 128 + lane];
+                const uint4 u1 = L[rb * 128 + 64 + lane];
+                const float a[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
+                                    __uint_as_float(u0.w), __uint_as_float(u1.x), __uint_as_float(u1.y),
+                                    __uint_as_float(u1.z), __uint_as_float(u1.w)};
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    v4f c = acc[cb][rb];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], cur[cb][i], c, 0, 0, 0);
+                    acc[cb][rb] = c;
+                }
+            }
+        }
+        buf ^= 1;
+        j = nj;
+        kc = nkc;
+    }
+    float* out = psi_m + size_t(split) * split_stride;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+        store_acc<NP>(acc[cb], tgt[cb] >= 0 ? out + size_t(cb % nrhs) * rhs_stride + size_t(tgt[cb]) * NP : nullptr,
+                      lane);
 }
 
 // ------------------------------------------------------------------ downward: L2L + DC2E
 template <int NP>
-__global__ __launch_bounds__(256) void k_down(int nl_start, int nl_count, int has_l2l,
+__global__ __launch_bounds__(256) void k_down(int nsplit, size_t split_stride, int nl_start, int nl_count, int has_l2l,
                                               const int* __restrict__ nonleaf, const int2* __restrict__ child,
                                               const float* __restrict__ psi_d, float* __restrict__ phi_d,
                                               const float* __restrict__ l2l, const float* __restrict__ w1,
@@ -365,6 +527,12 @@ __global__ __launch_bounds__(256) void k_down(int nl_start, int nl_count, int ha
     if (!__ballot(t >= 0)) return;
     v4f acc[NP / 16];
     load_acc<NP>(acc, t >= 0 ? psi_d + size_t(t) * NP : nullptr, lane);
+    for (int sp = 1; sp < nsplit; ++sp) {
+        v4f part[NP / 16];
+        load_acc<NP>(part, t >= 0 ? psi_d + sp * split_stride + size_t(t) * NP : nullptr, lane);
+#pragma unroll
+        for (int rb = 0; rb < NP / 16; ++rb) acc[rb] += part[rb];
+    }
     if (has_l2l) gemm_f32<NP>(acc, l2l + size_t(o) * NP * NP, t >= 0 ? phi_d + size_t(Pb) * NP : nullptr, lane);
     c2e_apply<NP>(acc, w1, vm, lane);
     store_acc<NP>(acc, t >= 0 ? phi_d + size_t(t) * NP : nullptr, lane);
@@ -373,129 +541,125 @@ __global__ __launch_bounds__(256) void k_down(int nl_start, int nl_count, int ha
 // ------------------------------------------------------------------ leaf evaluation: L2P + M2P
 // Forward: (u, E) per target.  Backward: from the forward densities E and H.v
 // (v = Ebar of the target), from the adjoint densities psi and E_psi.
+// One wave per target leaf; small leaves give each target S lanes (as in the
+// near field) that split the surface points and are summed by shuffles.
 struct FarOut {
     float* u;      // forward: float4 [N] (u, Ex, Ey, Ez) sorted
     float* b;      // backward: float [10][N] (E1 xyz, HE xyz, psi, Epsi xyz) sorted
 };
 
+__device__ inline int far_lanes(int nt) { return nt <= 8 ? 8 : nt <= 16 ? 4 : nt <= 32 ? 2 : 1; }
+
+__device__ inline float far_sum(float v, int S) {
+    for (int off = 1; off < S; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Work item = (leaf, first target), up to 64 targets, launched heaviest first.
+// The sources (the leaf's own downward density from level 2, then its W-list
+// upward densities) are dealt to the four waves in turn; densities and the
+// unit surfaces are read straight from L2.  Wave partial sums are added in a
+// fixed order.
 template <int NP, bool BWD>
-__global__ __launch_bounds__(128) void k_far(const int* __restrict__ leaves, int b2,
+__global__ __launch_bounds__(256) void k_far(const int2* __restrict__ items, int b2,
                                              const int4* __restrict__ anchor, const int2* __restrict__ range,
                                              const int* __restrict__ woff, const int* __restrict__ widx,
                                              const float4* __restrict__ pts, const float4* __restrict__ src2,
                                              const float* __restrict__ phi_d, const float* __restrict__ phi_u,
                                              size_t rhs_stride, const float4* __restrict__ surf, int n,
                                              BoxGeom geo, float cst, int64_t N, FarOut out) {
-    __shared__ float dens[2][NP];
-    __shared__ float4 sf[NP];
-    const int b = leaves[blockIdx.x];
-    const int4 ab = anchor[b];
-    const int2 r = range[b];
-    for (int t0 = r.x; t0 < r.y; t0 += blockDim.x) {
-        const int i = t0 + threadIdx.x;
-        const bool act = i < r.y;
-        float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
-        float4 eb = (BWD && act) ? src2[i] : make_float4(0, 0, 0, 0);
-        // accumulators (true units without c)
-        float u = 0, ex = 0, ey = 0, ez = 0;          // forward u,E  | backward E1
-        float hx = 0, hy = 0, hz = 0;                 // backward H.Ebar (forward density)
-        float ps = 0, px = 0, py = 0, pz = 0;         // backward psi, E_psi (adjoint density)
-        int nsrc = (ab.w >= 2 && b >= b2 ? 1 : 0) + (woff[b + 1] - woff[b]);
-        for (int k = 0; k < nsrc; ++k) {
-            int A;
-            const float4* S;
-            const float* D;
-            if (ab.w >= 2 && k == 0) {
-                A = b;
-                S = surf + NP;      // downward equivalent surface
-                D = phi_d;
-            } else {
-                A = widx[woff[b] + k - (ab.w >= 2 ? 1 : 0)];
-                S = surf;           // upward equivalent surface
-                D = phi_u;
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < NP; e += blockDim.x) {
-                dens[0][e] = D[size_t(A) * NP + e];
-                if (BWD) dens[1][e] = D[rhs_stride + size_t(A) * NP + e];
-                sf[e] = S[e];
-            }
-            __syncthreads();
-            float c[3], invw, w;
-            box_frame(geo, anchor[A], c, invw, w);
-            float xx = (x.x - c[0]) * invw, xy = (x.y - c[1]) * invw, xz = (x.z - c[2]) * invw;
-            float su = 0, sx = 0, sy = 0, sz = 0, shx = 0, shy = 0, shz = 0, s2u = 0, s2x = 0, s2y = 0, s2z = 0;
-            float vx = eb.y * invw, vy = eb.z * invw, vz = eb.w * invw;   // unused in forward
-            if (act) {
-                for (int e = 0; e < n; ++e) {
-                    float4 s = sf[e];
-                    float dx = xx - s.x, dy = xy - s.y, dz = xz - s.z;
-                    float ri = rsq(dx * dx + dy * dy + dz * dz);
-                    float ri3 = ri * ri * ri;
-                    float f = dens[0][e];
-                    if (!BWD) {
-                        su += f * ri;
-                        float g = f * ri3;
-                        sx += g * dx;
-                        sy += g * dy;
-                        sz += g * dz;
-                    } else {
-                        float g = f * ri3;
-                        sx += g * dx;
-                        sy += g * dy;
-                        sz += g * dz;
-                        // H(r) v = 3 r (r.v) / r^5 - v / r^3   (v = Ebar in box units)
-                        float ri5 = ri3 * ri * ri;
-                        float rv = dx * vx + dy * vy + dz * vz;
-                        float h3 = 3.f * f * rv * ri5;
-                        shx += h3 * dx - g * vx;
-                        shy += h3 * dy - g * vy;
-                        shz += h3 * dz - g * vz;
-                        float f2 = dens[1][e];
-                        float g2 = f2 * ri3;
-                        s2u += f2 * ri;
-                        s2x += g2 * dx;
-                        s2y += g2 * dy;
-                        s2z += g2 * dz;
-                    }
-                }
-            }
-            float iw2 = invw * invw;
+    constexpr int NV = BWD ? 10 : 4;
+    __shared__ float red[4][NV][64];
+    const int2 it = items[blockIdx.x];
+    const int b = it.x;
+    const int nt = min(64, range[b].y - it.y);
+    const int S = far_lanes(nt);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int slice = lane & (S - 1);
+    const int i = it.y + lane / S;
+    const bool act = lane / S < nt;
+    const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
+    const float4 eb = (BWD && act) ? src2[i] : make_float4(0, 0, 0, 0);
+    const int self = b >= b2 ? 1 : 0;
+    const int nsrc = self + (woff[b + 1] - woff[b]);
+    // forward: u, E | backward: E1 xyz, H.Ebar xyz, psi, E_psi xyz
+    float v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = 0.f;
+    for (int k = w; k < nsrc; k += 4) {
+        const bool own = self && k == 0;
+        const int A = own ? b : widx[woff[b] + k - self];
+        const float* D = (own ? phi_d : phi_u) + size_t(A) * NP;
+        const float4* SF = own ? surf + NP : surf;   // downward (2.95) or upward (1.05) equivalent surface
+        float c[3], invw, wd;
+        box_frame(geo, anchor[A], c, invw, wd);
+        const float xx = (x.x - c[0]) * invw, xy = (x.y - c[1]) * invw, xz = (x.z - c[2]) * invw;
+        const float vx = eb.y * invw, vy = eb.z * invw, vz = eb.w * invw;   // Ebar in box units
+        float su = 0, sx = 0, sy = 0, sz = 0, shx = 0, shy = 0, shz = 0, s2u = 0, s2x = 0, s2y = 0, s2z = 0;
+#pragma unroll 4
+        for (int e = slice; e < n; e += S) {
+            const float4 sp = SF[e];
+            const float dx = xx - sp.x, dy = xy - sp.y, dz = xz - sp.z;
+            const float ri = rsq(dx * dx + dy * dy + dz * dz);
+            const float ri3 = ri * ri * ri;
+            const float f = D[e];
+            const float g = f * ri3;
+            sx += g * dx;
+            sy += g * dy;
+            sz += g * dz;
             if (!BWD) {
-                u += su * invw;
-                ex += sx * iw2;
-                ey += sy * iw2;
-                ez += sz * iw2;
+                su += f * ri;
             } else {
-                ex += sx * iw2;
-                ey += sy * iw2;
-                ez += sz * iw2;
-                // v was scaled by invw, so H.v picks up invw^3 / invw = invw^2 ... times invw: see below
-                hx += shx * iw2;
-                hy += shy * iw2;
-                hz += shz * iw2;
-                ps += s2u * invw;
-                px += s2x * iw2;
-                py += s2y * iw2;
-                pz += s2z * iw2;
+                // H(r) v = 3 r (r.v) / r^5 - v / r^3
+                const float ri5 = ri3 * ri * ri;
+                const float rv = dx * vx + dy * vy + dz * vz;
+                const float h3 = 3.f * f * rv * ri5;
+                shx += h3 * dx - g * vx;
+                shy += h3 * dy - g * vy;
+                shz += h3 * dz - g * vz;
+                const float f2 = D[rhs_stride + e];
+                const float g2 = f2 * ri3;
+                s2u += f2 * ri;
+                s2x += g2 * dx;
+                s2y += g2 * dy;
+                s2z += g2 * dz;
             }
         }
-        if (act) {
-            if (!BWD) {
-                reinterpret_cast<float4*>(out.u)[i] = make_float4(cst * u, cst * ex, cst * ey, cst * ez);
-            } else {
-                float* o = out.b;
-                o[0 * N + i] = cst * ex;
-                o[1 * N + i] = cst * ey;
-                o[2 * N + i] = cst * ez;
-                o[3 * N + i] = cst * hx;
-                o[4 * N + i] = cst * hy;
-                o[5 * N + i] = cst * hz;
-                o[6 * N + i] = cst * ps;
-                o[7 * N + i] = cst * px;
-                o[8 * N + i] = cst * py;
-                o[9 * N + i] = cst * pz;
-            }
+        // true units: potential c/w, field c/w^2, Hessian c/w^3 (v already carries one 1/w)
+        const float iw2 = invw * invw;
+        if (!BWD) {
+            v[0] += su * invw;
+            v[1] += sx * iw2;
+            v[2] += sy * iw2;
+            v[3] += sz * iw2;
+        } else {
+            v[0] += sx * iw2;
+            v[1] += sy * iw2;
+            v[2] += sz * iw2;
+            v[3] += shx * iw2;
+            v[4] += shy * iw2;
+            v[5] += shz * iw2;
+            v[6] += s2u * invw;
+            v[7] += s2x * iw2;
+            v[8] += s2y * iw2;
+            v[9] += s2z * iw2;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = far_sum(v[q], S);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[w][q][lane] = v[q];
+    __syncthreads();
+    if (w == 0 && act && slice == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            v[q] = cst * (((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane]);
+        if (!BWD) {
+            reinterpret_cast<float4*>(out.u)[i] = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 10; ++q) out.b[q * N + i] = v[q];
         }
     }
 }
@@ -535,51 +699,35 @@ const VOps& vops_host() {
     return v;
 }
 
+constexpr int M2L_CB = 2;
+constexpr int M2L_SPLIT = kM2LSplit;
+
+const VOps* vops_device() {
+    static DBuf* d = nullptr;
+    if (!d) {
+        d = new DBuf();
+        d->ensure(sizeof(VOps));
+        KIFMM_HIP(hipMemcpy(d->p, &vops_host(), sizeof(VOps), hipMemcpyHostToDevice));
+    }
+    return d->as<VOps>();
+}
+
+// M2L for all levels; nrhs = 2 treats densities rhs 0 and 1 together (the
+// two columns share the target, the source and the operator), otherwise the
+// densities of right-hand side `rhs`.
 template <int NP>
-void sweep_impl(kifmm_plan* P, int rhs, bool dipole, hipStream_t s, bool rec) {
+void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
     const Operators& op = *P->ops;
-    const int B = int(P->B);
-    const size_t stride = size_t(B) * NP;
-    float* psi_u = P->psi_u.as<float>() + rhs * stride;
-    float* phi_u = P->phi_u.as<float>() + rhs * stride;
-    float* psi_d = P->psi_d.as<float>() + rhs * stride;
-    float* phi_d = P->phi_d.as<float>() + rhs * stride;
-    BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
-    const float4* pts = P->pts.as<float4>();
-    const float4* src2 = dipole ? P->src2.as<float4>() : nullptr;
-    const float4* surf = op.surf.as<float4>();
     const int depth = P->depth;
-    if (depth < 2) {
-        if (rec) for (int k = 0; k < 5; ++k) record_phase(P, k, s);
-        return;
-    }
+    if (depth < 2) return;
     const int b2 = int(P->lev[2].start);
-    int tpb = std::min(320, (NP + 63) / 64 * 64);
-    // P2M
-    hipLaunchKernelGGL(k_p2m<NP>, dim3(unsigned(P->nleaves)), dim3(tpb), 0, s, P->leaves.as<int>(), int(P->nleaves),
-                       b2, P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), pts, src2, surf, op.n, geo, psi_u);
-    if (rec) record_phase(P, 0, s);
-    // upward M2M + UC2E, deepest level first
-    for (int l = depth; l >= 2; --l) {
-        int nb = int(P->lev[l].count);
-        hipLaunchKernelGGL(k_up<NP>, dim3(nblk(nb, WAVES * 16)), dim3(WAVES * 64), 0, s, int(P->lev[l].start), nb,
-                           P->bx_child.as<int2>(), P->bx_leaf.as<int>(), psi_u, phi_u, op.m2m.as<float>(),
-                           op.uc2e_w1.as<float>(), op.uc2e_v.as<float>());
-    }
-    if (rec) record_phase(P, 1, s);
-    // downward check potentials: zero, X list, V list
-    size_t nz = size_t(B - b2) * NP;
-    hipLaunchKernelGGL(k_fill0, dim3(unsigned((nz + 255) / 256)), dim3(256), 0, s, psi_d + size_t(b2) * NP, nz);
-    if (P->n_xboxes > 0)
-        hipLaunchKernelGGL(k_p2l<NP>, dim3(unsigned(P->n_xboxes)), dim3(tpb), 0, s, P->xboxes.as<int>(),
-                           P->x_off.as<int>(), P->x_idx.as<int>(), P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), pts,
-                           src2, surf, op.n, geo, psi_d);
-    if (rec) record_phase(P, 2, s);
+    const int TG = M2L_CB / nrhs;
+    const int per_block = WAVES * TG * 16;
     TaskTable tt{};
     int blocks = 0;
     for (int l = 2; l <= depth; ++l) {
         const LevelInfo& pl = P->lev[l - 1];
-        int groups = nblk(pl.nl_count, WAVES * 16);
+        int groups = nblk(pl.nl_count, per_block);
         tt.first[tt.nlev] = blocks;
         tt.level[tt.nlev] = l;
         tt.nl_start[tt.nlev] = int(pl.nl_start);
@@ -588,31 +736,84 @@ void sweep_impl(kifmm_plan* P, int rhs, bool dipole, hipStream_t s, bool rec) {
         tt.nlev++;
         blocks += groups * 8;
     }
-    static DBuf* vops_dev = nullptr;
-    if (!vops_dev) {
-        vops_dev = new DBuf();
-        vops_dev->ensure(sizeof(VOps));
-        KIFMM_HIP(hipMemcpy(vops_dev->p, &vops_host(), sizeof(VOps), hipMemcpyHostToDevice));
+    if (blocks == 0) return;
+    const size_t stride = size_t(P->B) * NP;
+    const size_t sstride = 2 * stride;
+    const float* phi_u = P->phi_u.as<float>() + size_t(rhs) * stride;
+    const float* psi_d = P->psi_d.as<float>() + size_t(rhs) * stride;
+    float* psi_m = P->psi_m.as<float>() + size_t(rhs) * stride;
+    const int total = blocks * M2L_SPLIT;
+    if (P->opt.precision == KIFMM_SPLIT_BF16)
+        hipLaunchKernelGGL((k_m2l<NP, true, M2L_CB>), dim3(total), dim3(WAVES * 64), 0, s, tt, total, blocks,
+                           M2L_SPLIT, nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2,
+                           vops_device(), phi_u, psi_d, psi_m, stride, sstride, op.m2l_bf16.as<uint4>());
+    else
+        hipLaunchKernelGGL((k_m2l<NP, false, M2L_CB>), dim3(total), dim3(WAVES * 64), 0, s, tt, total, blocks,
+                           M2L_SPLIT, nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2,
+                           vops_device(), phi_u, psi_d, psi_m, stride, sstride, op.m2l_f32.as<uint4>());
+}
+
+// One sweep over the tree.  nrhs = 1: the charges (monopoles).  nrhs = 2:
+// right-hand side 0 = the charges, 1 = the adjoint sources (monopoles dL/du,
+// dipoles dL/dE); M2L then carries both columns through each operator load.
+template <int NP>
+void sweep_impl(kifmm_plan* P, int nrhs, hipStream_t s, bool rec) {
+    const Operators& op = *P->ops;
+    const int B = int(P->B);
+    const size_t stride = size_t(B) * NP;
+    BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
+    const float4* pts = P->pts.as<float4>();
+    const float4* surf = op.surf.as<float4>();
+    const int depth = P->depth;
+    if (depth < 2) {
+        if (rec) for (int k = 0; k < 5; ++k) record_phase(P, k, s);
+        return;
     }
-    if (blocks > 0) {
-        if (P->opt.precision == KIFMM_SPLIT_BF16)
-            hipLaunchKernelGGL((k_m2l<NP, true>), dim3(blocks), dim3(WAVES * 64), 0, s, tt, P->nonleaf.as<int>(),
-                               P->bx_child.as<int2>(), P->vdense.as<int>(), b2, vops_dev->as<VOps>(), phi_u, psi_d,
-                               op.m2l.as<float>(), op.m2l_hi.as<__bf16>(), op.m2l_lo.as<__bf16>());
-        else
-            hipLaunchKernelGGL((k_m2l<NP, false>), dim3(blocks), dim3(WAVES * 64), 0, s, tt, P->nonleaf.as<int>(),
-                               P->bx_child.as<int2>(), P->vdense.as<int>(), b2, vops_dev->as<VOps>(), phi_u, psi_d,
-                               op.m2l.as<float>(), op.m2l_hi.as<__bf16>(), op.m2l_lo.as<__bf16>());
+    const int b2 = int(P->lev[2].start);
+    const int tpb = std::min(320, (NP + 63) / 64 * 64);
+    // P2M
+    for (int r = 0; r < nrhs; ++r)
+        hipLaunchKernelGGL(k_p2m<NP>, dim3(unsigned(P->nleaves)), dim3(tpb), 0, s, P->leaves.as<int>(),
+                           int(P->nleaves), b2, P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), pts,
+                           r ? P->src2.as<float4>() : nullptr, surf, op.n, geo, P->psi_u.as<float>() + r * stride);
+    if (rec) record_phase(P, 0, s);
+    // upward M2M + UC2E, deepest level first
+    for (int r = 0; r < nrhs; ++r)
+        for (int l = depth; l >= 2; --l) {
+            int nb = int(P->lev[l].count);
+            hipLaunchKernelGGL(k_up<NP>, dim3(nblk(nb, WAVES * 16)), dim3(WAVES * 64), 0, s, int(P->lev[l].start),
+                               nb, P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->psi_u.as<float>() + r * stride,
+                               P->phi_u.as<float>() + r * stride, op.m2m.as<float>(), op.uc2e_w1.as<float>(),
+                               op.uc2e_v.as<float>());
+        }
+    if (rec) record_phase(P, 1, s);
+    // downward check potentials: zero, X list
+    for (int r = 0; r < nrhs; ++r) {
+        float* psi_d = P->psi_d.as<float>() + r * stride;
+        size_t nz = size_t(B - b2) * NP;
+        hipLaunchKernelGGL(k_fill0, dim3(unsigned((nz + 255) / 256)), dim3(256), 0, s, psi_d + size_t(b2) * NP, nz);
+        if (P->n_xboxes > 0)
+            hipLaunchKernelGGL(k_p2l<NP>, dim3(unsigned(P->n_xboxes)), dim3(tpb), 0, s, P->xboxes.as<int>(),
+                               P->x_off.as<int>(), P->x_idx.as<int>(), P->bx_anchor.as<int4>(),
+                               P->bx_range.as<int2>(), pts, r ? P->src2.as<float4>() : nullptr, surf, op.n, geo,
+                               psi_d);
     }
+    if (rec) record_phase(P, 2, s);
+    // V list
+    launch_m2l<NP>(P, nrhs, 0, s);
     if (rec) record_phase(P, 3, s);
-    for (int l = 2; l <= depth; ++l) {
-        const LevelInfo& pl = P->lev[l - 1];
-        int groups = nblk(pl.nl_count, WAVES * 16);
-        if (groups == 0) continue;
-        hipLaunchKernelGGL(k_down<NP>, dim3(groups * 8), dim3(WAVES * 64), 0, s, int(pl.nl_start), int(pl.nl_count),
-                           l >= 3 ? 1 : 0, P->nonleaf.as<int>(), P->bx_child.as<int2>(), psi_d, phi_d,
-                           op.l2l.as<float>(), op.dc2e_w1.as<float>(), op.dc2e_v.as<float>());
-    }
+    // L2L + DC2E, coarse to fine
+    for (int r = 0; r < nrhs; ++r)
+        for (int l = 2; l <= depth; ++l) {
+            const LevelInfo& pl = P->lev[l - 1];
+            int groups = nblk(pl.nl_count, WAVES * 16);
+            if (groups == 0) continue;
+            hipLaunchKernelGGL(k_down<NP>, dim3(groups * 8), dim3(WAVES * 64), 0, s, M2L_SPLIT, 2 * stride,
+                               int(pl.nl_start), int(pl.nl_count), l >= 3 ? 1 : 0, P->nonleaf.as<int>(),
+                               P->bx_child.as<int2>(), P->psi_m.as<float>() + r * stride,
+                               P->phi_d.as<float>() + r * stride,
+                               op.l2l.as<float>(), op.dc2e_w1.as<float>(), op.dc2e_v.as<float>());
+        }
     if (rec) record_phase(P, 4, s);
 }
 
@@ -624,12 +825,12 @@ void far_impl(kifmm_plan* P, bool bwd, hipStream_t s) {
     FarOut fo{P->far.as<float>(), P->far.as<float>()};
     size_t stride = size_t(P->B) * NP;
     if (bwd)
-        hipLaunchKernelGGL((k_far<NP, true>), dim3(unsigned(P->nleaves)), dim3(128), 0, s, P->leaves.as<int>(), b2,
+        hipLaunchKernelGGL((k_far<NP, true>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(), b2,
                            P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->w_off.as<int>(), P->w_idx.as<int>(),
                            P->pts.as<float4>(), P->src2.as<float4>(), P->phi_d.as<float>(), P->phi_u.as<float>(),
                            stride, op.surf.as<float4>(), op.n, geo, float(P->c), P->N, fo);
     else
-        hipLaunchKernelGGL((k_far<NP, false>), dim3(unsigned(P->nleaves)), dim3(128), 0, s, P->leaves.as<int>(), b2,
+        hipLaunchKernelGGL((k_far<NP, false>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(), b2,
                            P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->w_off.as<int>(), P->w_idx.as<int>(),
                            P->pts.as<float4>(), (const float4*)nullptr, P->phi_d.as<float>(), P->phi_u.as<float>(),
                            stride, op.surf.as<float4>(), op.n, geo, float(P->c), P->N, fo);
@@ -637,14 +838,14 @@ void far_impl(kifmm_plan* P, bool bwd, hipStream_t s) {
 
 }  // namespace
 
-void run_sweep(kifmm_plan* P, int rhs, bool dipole, hipStream_t s, bool record) {
+void run_sweep(kifmm_plan* P, int nrhs, hipStream_t s, bool record) {
     switch (P->npad) {
-        case 32: sweep_impl<32>(P, rhs, dipole, s, record); break;
-        case 64: sweep_impl<64>(P, rhs, dipole, s, record); break;
-        case 128: sweep_impl<128>(P, rhs, dipole, s, record); break;
-        case 160: sweep_impl<160>(P, rhs, dipole, s, record); break;
-        case 224: sweep_impl<224>(P, rhs, dipole, s, record); break;
-        case 320: sweep_impl<320>(P, rhs, dipole, s, record); break;
+        case 32: sweep_impl<32>(P, nrhs, s, record); break;
+        case 64: sweep_impl<64>(P, nrhs, s, record); break;
+        case 128: sweep_impl<128>(P, nrhs, s, record); break;
+        case 160: sweep_impl<160>(P, nrhs, s, record); break;
+        case 224: sweep_impl<224>(P, nrhs, s, record); break;
+        case 320: sweep_impl<320>(P, nrhs, s, record); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }

@@ -133,6 +133,35 @@ void upload(DBuf& buf, const void* host, size_t bytes) {
     KIFMM_HIP(hipMemcpy(buf.p, host, bytes, hipMemcpyHostToDevice));
 }
 
+// MFMA fragment order of an np x np row-major operator for the gathered
+// products: chunk kc (32 columns), row block rb (16 rows), half h, lane l
+// (row 16 rb + l%16, columns 32 kc + 8 (l/16) + ...).  FP32: half h holds
+// columns +4h..+4h+3.  bf16: half 0 holds the 8 hi parts, half 1 the lo parts.
+// Each (operator, chunk) is a contiguous block of np/16 * 128 16-byte words.
+void frag_f32(const float* A, int np, uint32_t* out) {
+    const int RB = np / 16, KC = np / 32;
+    for (int kc = 0; kc < KC; ++kc)
+        for (int rb = 0; rb < RB; ++rb)
+            for (int h = 0; h < 2; ++h)
+                for (int l = 0; l < 64; ++l) {
+                    size_t w = ((size_t(kc) * RB + rb) * 2 + h) * 64 + l;
+                    const float* src = A + size_t(rb * 16 + (l & 15)) * np + kc * 32 + 8 * (l >> 4) + 4 * h;
+                    memcpy(out + 4 * w, src, 16);
+                }
+}
+
+void frag_bf16(const uint16_t* hi, const uint16_t* lo, int np, uint16_t* out) {
+    const int RB = np / 16, KC = np / 32;
+    for (int kc = 0; kc < KC; ++kc)
+        for (int rb = 0; rb < RB; ++rb)
+            for (int h = 0; h < 2; ++h)
+                for (int l = 0; l < 64; ++l) {
+                    size_t w = ((size_t(kc) * RB + rb) * 2 + h) * 64 + l;
+                    const uint16_t* src = (h ? lo : hi) + size_t(rb * 16 + (l & 15)) * np + kc * 32 + 8 * (l >> 4);
+                    memcpy(out + 8 * w, src, 16);
+                }
+}
+
 std::unique_ptr<Operators> build_operators(int p, double tau) {
     auto op = std::make_unique<Operators>();
     const int n = 6 * (p - 1) * (p - 1) + 2;
@@ -214,9 +243,17 @@ std::unique_ptr<Operators> build_operators(int p, double tau) {
                     }
                 ++m;
             }
-    upload(op->m2l, m2l.data(), m2l.size() * 4);
-    upload(op->m2l_hi, hi.data(), hi.size() * 2);
-    upload(op->m2l_lo, lo.data(), lo.size() * 2);
+    {
+        const size_t per = size_t(np) * np;
+        std::vector<uint32_t> f32(size_t(kNumV) * per);
+        std::vector<uint16_t> f16(size_t(kNumV) * per * 2);
+        for (int mm = 0; mm < kNumV; ++mm) {
+            frag_f32(&m2l[mm * per], np, &f32[mm * per]);
+            frag_bf16(&hi[mm * per], &lo[mm * per], np, &f16[mm * per * 2]);
+        }
+        upload(op->m2l_f32, f32.data(), f32.size() * 4);
+        upload(op->m2l_bf16, f16.data(), f16.size() * 2);
+    }
     return op;
 }
 

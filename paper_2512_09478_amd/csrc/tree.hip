@@ -592,6 +592,51 @@ __global__ void k_counts(int B, int b2, int nv, const int* __restrict__ vd, cons
     if (pp) atomicAdd(&out[1], pp);
 }
 
+// Leaf work items of at most 64 targets, with cost estimates for ordering
+// the near-field and leaf-evaluation launches heaviest first.
+__global__ void k_item_count(int nl, const int* __restrict__ leaves, const int2* __restrict__ range,
+                             int* __restrict__ cnt) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nl) return;
+    int2 r = range[leaves[i]];
+    cnt[i] = (r.y - r.x + 63) / 64;
+}
+
+__global__ void k_item_fill(int nl, const int* __restrict__ leaves, const int2* __restrict__ range,
+                            const int* __restrict__ uoff, const int* __restrict__ uidx, const int* __restrict__ woff,
+                            int b2, const int* __restrict__ off, int2* __restrict__ items,
+                            uint64_t* __restrict__ key_near, uint64_t* __restrict__ key_far,
+                            uint32_t* __restrict__ id_near, uint32_t* __restrict__ id_far) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= nl) return;
+    const int b = leaves[i];
+    const int2 r = range[b];
+    unsigned long long src = 0;
+    for (int k = uoff[b]; k < uoff[b + 1]; ++k) {
+        int2 ra = range[uidx[k]];
+        src += ra.y - ra.x;
+    }
+    const unsigned long long nfar = (b >= b2 ? 1 : 0) + (woff[b + 1] - woff[b]);
+    for (int c = 0, at = off[i]; r.x + 64 * c < r.y; ++c, ++at) {
+        const int t0 = r.x + 64 * c;
+        const unsigned long long nt = min(64, r.y - t0);
+        items[at] = make_int2(b, t0);
+        unsigned long long cn = nt * src, cf = nt * nfar * 64;
+        key_near[at] = 0xffffffffull - min(cn, 0xffffffffull);
+        key_far[at] = 0xffffffffull - min(cf, 0xffffffffull);
+        id_near[at] = uint32_t(at);
+        id_far[at] = uint32_t(at);
+    }
+}
+
+__global__ void k_item_gather(int n, const int2* __restrict__ items, const uint32_t* __restrict__ idn,
+                              const uint32_t* __restrict__ idf, int2* __restrict__ near, int2* __restrict__ far) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    near[i] = items[idn[i]];
+    far[i] = items[idf[i]];
+}
+
 }  // namespace
 
 // Host: the V-slot table, built once.
@@ -875,6 +920,35 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     P->xboxes.ensure(size_t(std::max(nxb, 1)) * 4);
     hipLaunchKernelGGL(k_compact, dim3(nblocks(B)), dim3(TB), 0, s, B, fl, ol, P->leaves.as<int>());
     hipLaunchKernelGGL(k_compact, dim3(nblocks(B)), dim3(TB), 0, s, B, fx, ox, P->xboxes.as<int>());
+    // leaf work items, heaviest first
+    {
+        P->tmp_a.ensure(size_t(nl + 1) * 8 + 64);
+        int* icnt = P->tmp_a.as<int>();
+        int* ioff = icnt + (nl + 1);
+        hipLaunchKernelGGL(k_item_count, dim3(nblocks(nl)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
+                           P->bx_range.as<int2>(), icnt);
+        KIFMM_HIP(hipMemsetAsync(icnt + nl, 0, 4, s));
+        exclusive_scan<int>(P, icnt, ioff, nl + 1, s);
+        int ni = read_int(ioff + nl, s);
+        P->n_items = ni;
+        P->item_tmp.ensure(size_t(ni) * (8 + 8 + 8 + 4 + 4 + 4 + 4) + 1024);
+        char* base = P->item_tmp.as<char>();
+        int2* items = reinterpret_cast<int2*>(base);
+        uint64_t* kn = reinterpret_cast<uint64_t*>(base + size_t(ni) * 8);
+        uint64_t* kf = kn + ni;
+        uint32_t* idn = reinterpret_cast<uint32_t*>(kf + ni);
+        uint32_t* idf = idn + ni;
+        uint32_t* vtmp = idf + ni;
+        P->tmp_c.ensure(size_t(ni) * 8);
+        hipLaunchKernelGGL(k_item_fill, dim3(nblocks(nl)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
+                           P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), woff, b2, ioff, items, kn, kf, idn, idf);
+        radix_sort(P, kn, idn, P->tmp_c.as<uint64_t>(), vtmp, ni, 32, s);
+        radix_sort(P, kf, idf, P->tmp_c.as<uint64_t>(), vtmp, ni, 32, s);
+        P->items_near.ensure(size_t(ni) * 8);
+        P->items_far.ensure(size_t(ni) * 8);
+        hipLaunchKernelGGL(k_item_gather, dim3(nblocks(ni)), dim3(TB), 0, s, ni, items, idn, idf,
+                           P->items_near.as<int2>(), P->items_far.as<int2>());
+    }
     // counts
     P->tmp_a.ensure(64);
     unsigned long long* dc = P->tmp_a.as<unsigned long long>();
