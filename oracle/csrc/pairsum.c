@@ -58,7 +58,7 @@ void oracle_direct(int64_t nt, const double* xt, int64_t ns, const double* ys,
                    const double* s, const double* m, double c,
                    double* u, double* e, double* h)
 {
-    #pragma omp parallel for schedule(dynamic, 16)
+    #pragma omp parallel for schedule(dynamic, 16) if (nt * ns > 200000)
     for (int64_t i = 0; i < nt; ++i) {
         double ui = 0.0, ei[3] = {0.0, 0.0, 0.0}, hi[6] = {0, 0, 0, 0, 0, 0};
         for (int64_t j = 0; j < ns; ++j)

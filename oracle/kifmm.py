@@ -88,10 +88,8 @@ def upward(P: Plan, s: np.ndarray, m: Optional[np.ndarray]) -> np.ndarray:
                 continue
             b0, b1 = t.begin[b], t.end[b]
             uc = surface(P.p, RHO_UC, t.center(b), w)
-            psi[r] = kernel_matrix(uc, P.x[b0:b1], c) @ s[b0:b1]
-            if m is not None:
-                G = field_matrices(uc, P.x[b0:b1], c)
-                psi[r] -= sum(G[a] @ m[b0:b1, a] for a in range(3))
+            # psi = K(uc, x_B) s_B (- the dipole part), summed point by point in C
+            psi[r] = pairsum.direct(uc, P.x[b0:b1], s[b0:b1], None if m is None else m[b0:b1], c)[0]
         for o in range(8):
             ch = t.children[boxes, o]
             rows = np.nonzero(ch >= 0)[0]
@@ -128,10 +126,7 @@ def downward(P: Plan, s, m, phi_u, needed: np.ndarray) -> np.ndarray:
             dc = surface(P.p, RHO_DC, t.center(b), w)
             for a in L.X[b]:
                 a0, a1 = t.begin[a], t.end[a]
-                psi[r] += kernel_matrix(dc, P.x[a0:a1], c) @ s[a0:a1]
-                if m is not None:
-                    G = field_matrices(dc, P.x[a0:a1], c)
-                    psi[r] -= sum(G[k] @ m[a0:a1, k] for k in range(3))
+                psi[r] += pairsum.direct(dc, P.x[a0:a1], s[a0:a1], None if m is None else m[a0:a1], c)[0]
         # L2L from the parent
         if l >= 3:
             par = t.parent[boxes]
@@ -228,19 +223,30 @@ def forward(P: Plan, q, targets=None):
     return u, E
 
 
-def vjp(P: Plan, q, ubar, Ebar):
+def vjp(P: Plan, q, ubar, Ebar, targets=None):
     """Exact vector-Jacobian product of the discrete map (q, x) -> (u, E), frozen tree.
 
-    Returns (qbar [N], xbar [N,3]) in caller order.
+    Returns (qbar, xbar) in caller order: [N], [N,3], or at the caller indices
+    ``targets`` only (every entry of the product is an evaluation at one point).
     """
     perm = P.tree.perm
     qs = np.asarray(q, dtype=np.float64)[perm]
     us = np.asarray(ubar, dtype=np.float64)[perm]
     Es = np.asarray(Ebar, dtype=np.float64).reshape(-1, 3)[perm]
-    _, E, H = evaluate_sorted(P, qs, hess=True)
-    psi, Epsi, _ = evaluate_sorted(P, us, Es)
+    if targets is None:
+        ts = None
+        sel = slice(None)
+    else:
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(P.n)
+        ts = inv[np.asarray(targets)]
+        sel = ts
+    _, E, H = evaluate_sorted(P, qs, targets=ts, hess=True)
+    psi, Epsi, _ = evaluate_sorted(P, us, Es, targets=ts)
     qbar_s = psi
-    xbar_s = -us[:, None] * E - hess_times(H, Es) - qs[:, None] * Epsi
+    xbar_s = -us[sel, None] * E - hess_times(H, Es[sel]) - qs[sel, None] * Epsi
+    if targets is not None:
+        return qbar_s, xbar_s
     qbar = np.empty(P.n)
     xbar = np.empty((P.n, 3))
     qbar[perm] = qbar_s

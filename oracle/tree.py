@@ -135,8 +135,8 @@ def build_tree(x: np.ndarray, leaf_size: int, adaptive: bool = True, max_depth: 
     keys = keys[perm]
     Lu = uniform_depth(n, leaf_size, max_depth)
 
-    def prefix(d):
-        return keys >> np.uint64(3 * (BITS - d))
+    def prefix(d, b0, b1):
+        return keys[b0:b1] >> np.uint64(3 * (BITS - d))
 
     level, anchor, begin, end, parent, is_leaf = [], [], [], [], [], []
     level_start = [0]
@@ -159,7 +159,7 @@ def build_tree(x: np.ndarray, leaf_size: int, adaptive: bool = True, max_depth: 
             parent.append(par)
             is_leaf.append(leaf)
             if not leaf:
-                pre = prefix(d + 1)[b0:b1]
+                pre = prefix(d + 1, b0, b1)
                 starts = np.concatenate([[0], np.nonzero(pre[1:] != pre[:-1])[0] + 1, [cnt]])
                 for t in range(len(starts) - 1):
                     c0, c1 = b0 + int(starts[t]), b0 + int(starts[t + 1])
@@ -232,6 +232,16 @@ def build_lists(tree: Tree) -> Lists:
     lookup = {}
     for b in range(B):
         lookup[(int(tree.level[b]),) + tuple(int(v) for v in tree.anchor[b])] = b
+    # closed finest-grid extents of every box as plain ints (same test as adjacent())
+    sh = (BITS - tree.level)[:, None]
+    lo_all = (tree.anchor << sh).tolist()
+    hi_all = ((tree.anchor << sh) + (1 << sh)).tolist()
+    ext = [(l[0], l[1], l[2], h[0], h[1], h[2]) for l, h in zip(lo_all, hi_all)]
+
+    def adj(a, b):
+        ea, eb = ext[a], ext[b]
+        return (ea[0] <= eb[3] and eb[0] <= ea[3] and ea[1] <= eb[4] and eb[1] <= ea[4]
+                and ea[2] <= eb[5] and eb[2] <= ea[5])
 
     def colleagues(b):
         l = int(tree.level[b])
@@ -258,7 +268,7 @@ def build_lists(tree: Tree) -> Lists:
             p = int(tree.parent[b])
             for c in coll[p]:
                 for ch in tree.children[c]:
-                    if ch >= 0 and not adjacent(tree, int(ch), b):
+                    if ch >= 0 and not adj(int(ch), b):
                         V[b].append(int(ch))
         if not tree.is_leaf[b]:
             continue
@@ -270,7 +280,7 @@ def build_lists(tree: Tree) -> Lists:
                 if ch < 0:
                     continue
                 ch = int(ch)
-                if adjacent(tree, ch, b):
+                if adj(ch, b):
                     if tree.is_leaf[ch]:
                         u.add(ch)
                     else:
@@ -287,7 +297,7 @@ def build_lists(tree: Tree) -> Lists:
         a = int(tree.parent[b])
         while a >= 0:
             for c in coll[a]:
-                if tree.is_leaf[c] and adjacent(tree, c, b):
+                if tree.is_leaf[c] and adj(c, b):
                     u.add(c)
             a = int(tree.parent[a])
         U[b] = sorted(u)

@@ -80,12 +80,14 @@ struct Operators {
     int p = 0, n = 0, npad = 0, rank = 0;
     double tau = 0;
     DBuf surf;         // float4 [2][npad]: rho=1.05 surface, rho=2.95 surface (w = 0)
-    DBuf uc2e_w1;      // float [npad][npad]  Sigma^-1 U^T          (UC2E = V W1)
-    DBuf uc2e_v;       // float [npad][npad]  V
-    DBuf dc2e_w1;      // float [npad][npad]  Sigma^-1 V^T          (DC2E = UC2E^T = U W1d)
-    DBuf dc2e_v;       // float [npad][npad]  U
-    DBuf m2m;          // float [8][npad][npad]
-    DBuf l2l;          // float [8][npad][npad] (includes the factor 1/2 of the child width)
+    // check-to-equivalent factors in chain order ([ob][rb][64] x 16 B):
+    DBuf uc2e_w1;      // Sigma^-1 U^T          (UC2E = V W1)
+    DBuf uc2e_v;       // V
+    DBuf dc2e_w1;      // Sigma^-1 V^T          (DC2E = UC2E^T = U W1d)
+    DBuf dc2e_v;       // U
+    // translations in gather-fragment order ([op][kc][rb][2][64] x 16 B):
+    DBuf m2m;          // 8 octants: parent uc <- child ue
+    DBuf l2l;          // 8 octants: child dc <- parent de (includes the factor 1/2 of the child width)
     DBuf m2l_f32;      // [316][npad/32 chunks][npad/16 row blocks][2][64] x 16 B (FP32 fragments)
     DBuf m2l_bf16;     // same shape, bf16 hi half then lo half
     std::vector<double> sigma;   // singular values of K(uc, ue), descending
@@ -156,6 +158,7 @@ struct kifmm_plan {
     // densities: [rhs][B][npad]
     kifmm::DBuf psi_u, phi_u, psi_d, phi_d;
     kifmm::DBuf psi_m;      // M2L partial check potentials [kM2LSplit][rhs][B][npad]
+    int m2l_split_used = kifmm::kM2LSplit;
     // per-evaluation work
     kifmm::DBuf pts;        // float4 [N] sorted (x, y, z, q)
     kifmm::DBuf src2;       // float4 [N] sorted (ubar, Ebar) for the adjoint sweep

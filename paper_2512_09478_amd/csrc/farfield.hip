@@ -21,6 +21,8 @@
 // factors of a check-to-equivalent map without leaving registers.  The split
 // path uses v_mfma_f32_16x16x32_bf16 with operands hi = bf16(x),
 // lo = bf16(x - hi) and D += Ahi Bhi + Ahi Blo + Alo Bhi in FP32.
+#include <stdlib.h>
+
 #include <algorithm>
 
 #include "common.h"
@@ -269,31 +271,6 @@ __global__ void k_p2l(const int* __restrict__ xboxes, const int* __restrict__ xo
     }
 }
 
-// ------------------------------------------------------------------ upward: M2M + UC2E
-template <int NP>
-__global__ __launch_bounds__(256) void k_up(int b0, int nb, const int2* __restrict__ child,
-                                            const int* __restrict__ leafflag, const float* __restrict__ psi_u,
-                                            float* __restrict__ phi_u, const float* __restrict__ m2m,
-                                            const float* __restrict__ w1, const float* __restrict__ vm) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int t0 = (blockIdx.x * WAVES + wave) * 16;
-    if (t0 >= nb) return;
-    const int t = t0 + (lane & 15) < nb ? b0 + t0 + (lane & 15) : -1;
-    const bool leaf = t >= 0 && leafflag[t];
-    v4f acc[NP / 16];
-    load_acc<NP>(acc, leaf ? psi_u + size_t(t) * NP : nullptr, lane);
-    int2 ch = (t >= 0 && !leaf) ? child[t] : make_int2(-1, 0);
-    if (__ballot(ch.y != 0)) {
-        for (int o = 0; o < 8; ++o) {
-            int src = ((ch.y >> o) & 1) ? ch.x + __popc(ch.y & ((1 << o) - 1)) : -1;
-            if (!__ballot(src >= 0)) continue;
-            gemm_f32<NP>(acc, m2m + size_t(o) * NP * NP, src >= 0 ? phi_u + size_t(src) * NP : nullptr, lane);
-        }
-    }
-    c2e_apply<NP>(acc, w1, vm, lane);
-    store_acc<NP>(acc, t >= 0 ? phi_u + size_t(t) * NP : nullptr, lane);
-}
-
 // ------------------------------------------------------------------ M2L
 struct TaskTable {
     int nlev;
@@ -361,13 +338,16 @@ __global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, 
     __shared__ uint4 lds[2][WORDS];
     __shared__ unsigned vmask[6];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
+    // logical tile order (split, octant, level, parent group): the blocks an XCD
+    // runs together share one window of operators and neighbouring sources
     const int lid = xcd_remap(blockIdx.x, nblk);
-    const int split = lid / ntile, bid = lid % ntile;
+    const int split = lid / ntile, rest = lid % ntile;
+    const int ngroups = ntile / 8;
+    const int o = rest / ngroups, bid = rest % ngroups;
     const int j_lo = split * kVPerOct / nsplit, j_hi = (split + 1) * kVPerOct / nsplit;
     int e = 0;
     while (e + 1 < tt.nlev && bid >= tt.first[e + 1]) ++e;
-    const int local = bid - tt.first[e];
-    const int o = local % 8, grp = local / 8;
+    const int grp = bid - tt.first[e];
     const int TG = CB / nrhs;
     int tgt[CB];
     const float* bsrc[CB];
@@ -507,35 +487,199 @@ __global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, 
                       lane);
 }
 
-// ------------------------------------------------------------------ downward: L2L + DC2E
-template <int NP>
-__global__ __launch_bounds__(256) void k_down(int nsplit, size_t split_stride, int nl_start, int nl_count, int has_l2l,
-                                              const int* __restrict__ nonleaf, const int2* __restrict__ child,
-                                              const float* __restrict__ psi_d, float* __restrict__ phi_d,
-                                              const float* __restrict__ l2l, const float* __restrict__ w1,
-                                              const float* __restrict__ vm) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int o = blockIdx.x % 8;
-    int grp = blockIdx.x / 8;
-    int slot = (grp * WAVES + wave) * 16 + (lane & 15);
-    int t = -1, Pb = -1;
-    if (slot < nl_count) {
-        Pb = nonleaf[nl_start + slot];
-        int2 ch = child[Pb];
-        if ((ch.y >> o) & 1) t = ch.x + __popc(ch.y & ((1 << o) - 1));
-    }
-    if (!__ballot(t >= 0)) return;
-    v4f acc[NP / 16];
-    load_acc<NP>(acc, t >= 0 ? psi_d + size_t(t) * NP : nullptr, lane);
-    for (int sp = 1; sp < nsplit; ++sp) {
-        v4f part[NP / 16];
-        load_acc<NP>(part, t >= 0 ? psi_d + sp * split_stride + size_t(t) * NP : nullptr, lane);
+// ------------------------------------------------------------------ upward and downward translations
+// Upward (UP): for the boxes of one level, psi = P2M result (leaves) or
+// sum_o M2M[o] phi_u(child o) (non-leaves), then phi_u = V (W1 psi).
+// Downward: for the children at octant o of non-leaf parents, psi = the summed
+// M2L partials (+ X list) + L2L[o] phi_d(parent) (from level 3), then
+// phi_d = U (W1d psi).
+// The block's four waves (CB column blocks of 16 boxes each) share every
+// operator chunk, streamed through a double-buffered LDS tile: gather chunks
+// (32 columns of a translation, B = gathered densities) and chain chunks (one
+// 16-row output block of a check-to-equivalent factor, B = the accumulator).
+template <int NP, int CB, bool UP>
+__global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl_start, int nl_count, int has_l2l,
+                                                const int* __restrict__ nonleaf, const int2* __restrict__ child,
+                                                const int* __restrict__ leafflag, const float* __restrict__ psi_in,
+                                                int nsplit, size_t split_stride, const float* __restrict__ gsrc,
+                                                float* __restrict__ out, const uint4* __restrict__ gops,
+                                                const uint4* __restrict__ w1c, const uint4* __restrict__ vc) {
+    constexpr int RB = NP / 16, KC = NP / 32, GW = RB * 128, CW = RB * 64, PER = GW / 256, CPER = CW / 256;
+    __shared__ uint4 lds[2][GW];
+    __shared__ int sflag;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
+    const int bid = xcd_remap(blockIdx.x, nblk);
+    const int g8 = 8 * (lane >> 4);
+    int tgt[CB], par[CB], cmask[CB], cfirst[CB];
+    int o = 0;
 #pragma unroll
-        for (int rb = 0; rb < NP / 16; ++rb) acc[rb] += part[rb];
+    for (int cb = 0; cb < CB; ++cb) {
+        tgt[cb] = -1;
+        par[cb] = -1;
+        cmask[cb] = 0;
+        cfirst[cb] = 0;
+        if (UP) {
+            const int idx = ((bid * WAVES + wave) * CB + cb) * 16 + (lane & 15);
+            if (idx < nb) {
+                tgt[cb] = b0 + idx;
+                if (!leafflag[tgt[cb]]) {
+                    const int2 ch = child[tgt[cb]];
+                    cfirst[cb] = ch.x;
+                    cmask[cb] = ch.y;
+                }
+            }
+        } else {
+            o = bid % 8;
+            const int slot = (((bid / 8) * WAVES + wave) * CB + cb) * 16 + (lane & 15);
+            if (slot < nl_count) {
+                const int Pb = nonleaf[nl_start + slot];
+                const int2 ch = child[Pb];
+                if ((ch.y >> o) & 1) {
+                    tgt[cb] = ch.x + __popc(ch.y & ((1 << o) - 1));
+                    par[cb] = Pb;
+                }
+            }
+        }
     }
-    if (has_l2l) gemm_f32<NP>(acc, l2l + size_t(o) * NP * NP, t >= 0 ? phi_d + size_t(Pb) * NP : nullptr, lane);
-    c2e_apply<NP>(acc, w1, vm, lane);
-    store_acc<NP>(acc, t >= 0 ? phi_d + size_t(t) * NP : nullptr, lane);
+    // which gather terms the block needs
+    if (tid == 0) sflag = 0;
+    __syncthreads();
+    {
+        int f = 0;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) f |= UP ? cmask[cb] : (tgt[cb] >= 0 ? 1 : 0);
+        if (f) atomicOr(&sflag, f);
+    }
+    __syncthreads();
+    const int flags = sflag;
+    if (!UP && !flags) return;   // block-uniform: no target in this tile
+    const int gterms = UP ? __popc(flags) : (has_l2l ? 1 : 0);
+    // initial check potential
+    v4f acc[CB][RB], tmp[CB][RB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        if (UP) {
+            load_acc<NP>(acc[cb], (tgt[cb] >= 0 && !cmask[cb]) ? psi_in + size_t(tgt[cb]) * NP : nullptr, lane);
+        } else {
+            load_acc<NP>(acc[cb], tgt[cb] >= 0 ? psi_in + size_t(tgt[cb]) * NP : nullptr, lane);
+            for (int sp = 1; sp < nsplit; ++sp) {
+                load_acc<NP>(tmp[cb], tgt[cb] >= 0 ? psi_in + sp * split_stride + size_t(tgt[cb]) * NP : nullptr,
+                             lane);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) acc[cb][rb] += tmp[cb][rb];
+            }
+        }
+    }
+    const int nsteps = gterms * KC + 2 * RB;
+    // operator chunk and source column of a step
+    auto term_op = [&](int ti) -> int {
+        if (!UP) return o;
+        int f = flags;
+        for (int k = 0; k < ti; ++k) f &= f - 1;
+        return __builtin_ctz(f);
+    };
+    auto chunk_ptr = [&](int st, int& words) -> const uint4* {
+        if (st < gterms * KC) {
+            words = GW;
+            return gops + (size_t(term_op(st / KC)) * KC + (st % KC)) * GW;
+        }
+        const int c = st - gterms * KC;
+        words = CW;
+        return (c < RB ? w1c : vc) + size_t(c % RB) * CW;
+    };
+    auto col_ptr = [&](int st, int cb) -> const float* {
+        const int op = term_op(st / KC);
+        int src = -1;
+        if (UP) {
+            if ((cmask[cb] >> op) & 1) src = cfirst[cb] + __popc(cmask[cb] & ((1 << op) - 1));
+        } else {
+            src = par[cb];
+        }
+        return src >= 0 ? gsrc + size_t(src) * NP + (st % KC) * 32 + g8 : nullptr;
+    };
+    uint4 areg[PER];
+    float breg[CB][8];
+    // load the operator chunk (and the gathered columns) of step st into registers
+    auto prefetch = [&](int st) {
+        if (st >= nsteps) return;
+        int words;
+        const uint4* a = chunk_ptr(st, words);
+#pragma unroll
+        for (int i = 0; i < PER; ++i)
+            if (i * 256 < words) areg[i] = a[i * 256 + tid];
+        if (st < gterms * KC)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) load8(breg[cb], col_ptr(st, cb));
+    };
+    auto publish = [&](int buf, int words) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i)
+            if (i * 256 < words) lds[buf][i * 256 + tid] = areg[i];
+        __syncthreads();
+    };
+    prefetch(0);
+    int buf = 0, st = 0;
+    // translations (gather chunks)
+    for (; st < gterms * KC; ++st) {
+        publish(buf, GW);
+        float cur[CB][8];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cur[cb][i] = breg[cb][i];
+        prefetch(st + 1);
+        const uint4* L = lds[buf];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const uint4 u0 = L[rb * 128 + lane];
+            const uint4 u1 = L[rb * 128 + 64 + lane];
+            const float a[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
+                                __uint_as_float(u0.w), __uint_as_float(u1.x), __uint_as_float(u1.y),
+                                __uint_as_float(u1.z), __uint_as_float(u1.w)};
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                v4f c = acc[cb][rb];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], cur[cb][i], c, 0, 0, 0);
+                acc[cb][rb] = c;
+            }
+        }
+        buf ^= 1;
+    }
+    // one output block of a chained factor: dst[ob] = sum_rb A[ob][rb] src[rb]
+    auto chain_block = [&](const uint4* L, v4f (&src)[CB][RB], int cb) -> v4f {
+        v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const uint4 u = L[rb * 64 + lane];
+            const v4f T = src[cb][rb];
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.x), T[0], cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.y), T[1], cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.z), T[2], cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.w), T[3], cc, 0, 0, 0);
+        }
+        return cc;
+    };
+    // W1: tmp = W1 acc
+#pragma unroll
+    for (int ob = 0; ob < RB; ++ob, ++st) {
+        publish(buf, CW);
+        prefetch(st + 1);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) tmp[cb][ob] = chain_block(lds[buf], acc, cb);
+        buf ^= 1;
+    }
+    // V: acc = V tmp
+#pragma unroll
+    for (int ob = 0; ob < RB; ++ob, ++st) {
+        publish(buf, CW);
+        prefetch(st + 1);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[cb][ob] = chain_block(lds[buf], tmp, cb);
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) store_acc<NP>(acc[cb], tgt[cb] >= 0 ? out + size_t(tgt[cb]) * NP : nullptr, lane);
 }
 
 // ------------------------------------------------------------------ leaf evaluation: L2P + M2P
@@ -701,6 +845,7 @@ const VOps& vops_host() {
 
 constexpr int M2L_CB = 2;
 constexpr int M2L_SPLIT = kM2LSplit;
+constexpr int UD_CB = 1;      // column blocks per wave in the up/down translation kernels
 
 const VOps* vops_device() {
     static DBuf* d = nullptr;
@@ -721,7 +866,10 @@ void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
     const int depth = P->depth;
     if (depth < 2) return;
     const int b2 = int(P->lev[2].start);
-    const int TG = M2L_CB / nrhs;
+    static const int cbsel = getenv("KIFMM_TUNE_M2L_CB") ? atoi(getenv("KIFMM_TUNE_M2L_CB")) : M2L_CB;
+    static const int nsplit = std::max(1, std::min(M2L_SPLIT, getenv("KIFMM_TUNE_M2L_SPLIT") ? atoi(getenv("KIFMM_TUNE_M2L_SPLIT")) : M2L_SPLIT));
+    P->m2l_split_used = nsplit;
+    const int TG = cbsel / nrhs;
     const int per_block = WAVES * TG * 16;
     TaskTable tt{};
     int blocks = 0;
@@ -734,23 +882,29 @@ void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
         tt.nl_count[tt.nlev] = int(pl.nl_count);
         tt.groups[tt.nlev] = groups;
         tt.nlev++;
-        blocks += groups * 8;
+        blocks += groups;
     }
+    blocks *= 8;
     if (blocks == 0) return;
     const size_t stride = size_t(P->B) * NP;
     const size_t sstride = 2 * stride;
     const float* phi_u = P->phi_u.as<float>() + size_t(rhs) * stride;
     const float* psi_d = P->psi_d.as<float>() + size_t(rhs) * stride;
     float* psi_m = P->psi_m.as<float>() + size_t(rhs) * stride;
-    const int total = blocks * M2L_SPLIT;
-    if (P->opt.precision == KIFMM_SPLIT_BF16)
-        hipLaunchKernelGGL((k_m2l<NP, true, M2L_CB>), dim3(total), dim3(WAVES * 64), 0, s, tt, total, blocks,
-                           M2L_SPLIT, nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2,
-                           vops_device(), phi_u, psi_d, psi_m, stride, sstride, op.m2l_bf16.as<uint4>());
-    else
-        hipLaunchKernelGGL((k_m2l<NP, false, M2L_CB>), dim3(total), dim3(WAVES * 64), 0, s, tt, total, blocks,
-                           M2L_SPLIT, nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2,
-                           vops_device(), phi_u, psi_d, psi_m, stride, sstride, op.m2l_f32.as<uint4>());
+    const int total = blocks * nsplit;
+#define KIFMM_M2L_LAUNCH(SPL, CBV, OPS)                                                                          \
+    hipLaunchKernelGGL((k_m2l<NP, SPL, CBV>), dim3(total), dim3(WAVES * 64), 0, s, tt, total, blocks, nsplit,  \
+                       nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2, vops_device(), \
+                       phi_u, psi_d, psi_m, stride, sstride, OPS)
+    const bool split = P->opt.precision == KIFMM_SPLIT_BF16;
+    if (cbsel == 4) {
+        if (split) KIFMM_M2L_LAUNCH(true, 4, op.m2l_bf16.as<uint4>());
+        else KIFMM_M2L_LAUNCH(false, 4, op.m2l_f32.as<uint4>());
+    } else {
+        if (split) KIFMM_M2L_LAUNCH(true, 2, op.m2l_bf16.as<uint4>());
+        else KIFMM_M2L_LAUNCH(false, 2, op.m2l_f32.as<uint4>());
+    }
+#undef KIFMM_M2L_LAUNCH
 }
 
 // One sweep over the tree.  nrhs = 1: the charges (monopoles).  nrhs = 2:
@@ -780,11 +934,13 @@ void sweep_impl(kifmm_plan* P, int nrhs, hipStream_t s, bool rec) {
     // upward M2M + UC2E, deepest level first
     for (int r = 0; r < nrhs; ++r)
         for (int l = depth; l >= 2; --l) {
-            int nb = int(P->lev[l].count);
-            hipLaunchKernelGGL(k_up<NP>, dim3(nblk(nb, WAVES * 16)), dim3(WAVES * 64), 0, s, int(P->lev[l].start),
-                               nb, P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->psi_u.as<float>() + r * stride,
-                               P->phi_u.as<float>() + r * stride, op.m2m.as<float>(), op.uc2e_w1.as<float>(),
-                               op.uc2e_v.as<float>());
+            const int nb = int(P->lev[l].count);
+            const int blocks = nblk(nb, WAVES * UD_CB * 16);
+            hipLaunchKernelGGL((k_updown<NP, UD_CB, true>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks,
+                               int(P->lev[l].start), nb, 0, 0, 0, P->nonleaf.as<int>(), P->bx_child.as<int2>(),
+                               P->bx_leaf.as<int>(), P->psi_u.as<float>() + r * stride, 1, size_t(0),
+                               P->phi_u.as<float>() + r * stride, P->phi_u.as<float>() + r * stride,
+                               op.m2m.as<uint4>(), op.uc2e_w1.as<uint4>(), op.uc2e_v.as<uint4>());
         }
     if (rec) record_phase(P, 1, s);
     // downward check potentials: zero, X list
@@ -806,13 +962,14 @@ void sweep_impl(kifmm_plan* P, int nrhs, hipStream_t s, bool rec) {
     for (int r = 0; r < nrhs; ++r)
         for (int l = 2; l <= depth; ++l) {
             const LevelInfo& pl = P->lev[l - 1];
-            int groups = nblk(pl.nl_count, WAVES * 16);
-            if (groups == 0) continue;
-            hipLaunchKernelGGL(k_down<NP>, dim3(groups * 8), dim3(WAVES * 64), 0, s, M2L_SPLIT, 2 * stride,
+            const int blocks = nblk(pl.nl_count, WAVES * UD_CB * 16) * 8;
+            if (blocks == 0) continue;
+            hipLaunchKernelGGL((k_updown<NP, UD_CB, false>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, 0, 0,
                                int(pl.nl_start), int(pl.nl_count), l >= 3 ? 1 : 0, P->nonleaf.as<int>(),
-                               P->bx_child.as<int2>(), P->psi_m.as<float>() + r * stride,
-                               P->phi_d.as<float>() + r * stride,
-                               op.l2l.as<float>(), op.dc2e_w1.as<float>(), op.dc2e_v.as<float>());
+                               P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->psi_m.as<float>() + r * stride,
+                               P->m2l_split_used, 2 * stride, P->phi_d.as<float>() + r * stride,
+                               P->phi_d.as<float>() + r * stride, op.l2l.as<uint4>(), op.dc2e_w1.as<uint4>(),
+                               op.dc2e_v.as<uint4>());
         }
     if (rec) record_phase(P, 4, s);
 }

@@ -162,6 +162,20 @@ void frag_bf16(const uint16_t* hi, const uint16_t* lo, int np, uint16_t* out) {
                 }
 }
 
+// Chain order of an np x np operator whose right factor is a result still in
+// MFMA accumulator layout: output block ob, k block rb, lane l holds
+// A[16 ob + l%16][16 rb + 4 (l/16) .. +3].  One output block is a contiguous
+// chunk of np/16 * 64 16-byte words.
+void frag_chain(const float* A, int np, uint32_t* out) {
+    const int RB = np / 16;
+    for (int ob = 0; ob < RB; ++ob)
+        for (int rb = 0; rb < RB; ++rb)
+            for (int l = 0; l < 64; ++l) {
+                size_t w = (size_t(ob) * RB + rb) * 64 + l;
+                memcpy(out + 4 * w, A + size_t(ob * 16 + (l & 15)) * np + rb * 16 + 4 * (l >> 4), 16);
+            }
+}
+
 std::unique_ptr<Operators> build_operators(int p, double tau) {
     auto op = std::make_unique<Operators>();
     const int n = 6 * (p - 1) * (p - 1) + 2;
@@ -200,10 +214,17 @@ std::unique_ptr<Operators> build_operators(int p, double tau) {
             w1d[size_t(r) * np + i] = float(V[size_t(i) * n + r] / S[r]);
             vd[size_t(i) * np + r] = float(U[size_t(i) * n + r]);
         }
-    upload(op->uc2e_w1, w1u.data(), w1u.size() * 4);
-    upload(op->uc2e_v, vu.data(), vu.size() * 4);
-    upload(op->dc2e_w1, w1d.data(), w1d.size() * 4);
-    upload(op->dc2e_v, vd.data(), vd.size() * 4);
+    {
+        std::vector<uint32_t> c(size_t(np) * np);
+        frag_chain(w1u.data(), np, c.data());
+        upload(op->uc2e_w1, c.data(), c.size() * 4);
+        frag_chain(vu.data(), np, c.data());
+        upload(op->uc2e_v, c.data(), c.size() * 4);
+        frag_chain(w1d.data(), np, c.data());
+        upload(op->dc2e_w1, c.data(), c.size() * 4);
+        frag_chain(vd.data(), np, c.data());
+        upload(op->dc2e_v, c.data(), c.size() * 4);
+    }
 
     // M2M (parent uc <- child ue) and L2L (child dc <- parent de), parent units
     std::vector<float> m2m(size_t(8) * np * np, 0.f), l2l(size_t(8) * np * np, 0.f);
@@ -220,8 +241,16 @@ std::unique_ptr<Operators> build_operators(int p, double tau) {
                 l2l[(size_t(o) * np + i) * np + j] = float(0.5 * inv_dist(cc, &sout[3 * j]));
             }
     }
-    upload(op->m2m, m2m.data(), m2m.size() * 4);
-    upload(op->l2l, l2l.data(), l2l.size() * 4);
+    {
+        const size_t per = size_t(np) * np;
+        std::vector<uint32_t> fm(8 * per), fl(8 * per);
+        for (int o = 0; o < 8; ++o) {
+            frag_f32(&m2m[o * per], np, &fm[o * per]);
+            frag_f32(&l2l[o * per], np, &fl[o * per]);
+        }
+        upload(op->m2m, fm.data(), fm.size() * 4);
+        upload(op->l2l, fl.data(), fl.size() * 4);
+    }
 
     // M2L for the 316 far offsets, lexicographic (dx, dy, dz)
     std::vector<float> m2l(size_t(kNumV) * np * np, 0.f);

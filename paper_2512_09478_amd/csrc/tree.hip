@@ -536,18 +536,35 @@ __global__ void k_wlist(int b0, int nb, const int* __restrict__ xoff, const int*
     }
 }
 
-__global__ void k_sort_rows(int B, const int* __restrict__ off, int* __restrict__ idx) {
-    int b = blockIdx.x * TB + threadIdx.x;
-    if (b >= B) return;
-    int s = off[b], e = off[b + 1];
-    for (int i = s + 1; i < e; ++i) {
-        int v = idx[i];
-        int j = i - 1;
-        while (j >= s && idx[j] > v) {
-            idx[j + 1] = idx[j];
-            --j;
+// Sort each CSR row ascending (entries of a row are distinct).  One wave per
+// row: rows of up to SORT_CAP entries are placed by rank (the number of
+// smaller entries) through LDS; longer rows fall back to one lane.
+constexpr int SORT_CAP = 1024;
+
+__global__ __launch_bounds__(64) void k_sort_rows(int B, const int* __restrict__ off, int* __restrict__ idx) {
+    __shared__ int v[SORT_CAP];
+    const int b = blockIdx.x;
+    const int s = off[b], e = off[b + 1], len = e - s;
+    if (len <= 1) return;
+    if (len <= SORT_CAP) {
+        for (int k = threadIdx.x; k < len; k += 64) v[k] = idx[s + k];
+        __syncthreads();
+        for (int k = threadIdx.x; k < len; k += 64) {
+            const int x = v[k];
+            int rank = 0;
+            for (int m = 0; m < len; ++m) rank += v[m] < x;
+            idx[s + rank] = x;
         }
-        idx[j + 1] = v;
+    } else if (threadIdx.x == 0) {
+        for (int i = s + 1; i < e; ++i) {
+            int x = idx[i];
+            int j = i - 1;
+            while (j >= s && idx[j] > x) {
+                idx[j + 1] = idx[j];
+                --j;
+            }
+            idx[j + 1] = x;
+        }
     }
 }
 
@@ -863,7 +880,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
                            P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
                            P->x_idx.as<int>(), 1);
-        hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(B)), dim3(TB), 0, s, B, xoff, P->x_idx.as<int>());
+        hipLaunchKernelGGL(k_sort_rows, dim3(B), dim3(64), 0, s, B, xoff, P->x_idx.as<int>());
     }
     // U lists
     P->u_off.ensure(size_t(B + 1) * 4);
@@ -884,7 +901,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                        P->cal.as<int>(), uoff, P->u_idx.as<int>(), cursor, 1);
     hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
                        (int*)nullptr, P->u_idx.as<int>(), cursor, 1);
-    hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(B)), dim3(TB), 0, s, B, uoff, P->u_idx.as<int>());
+    hipLaunchKernelGGL(k_sort_rows, dim3(B), dim3(64), 0, s, B, uoff, P->u_idx.as<int>());
     // W lists = transpose of X
     P->w_off.ensure(size_t(B + 1) * 4);
     int* woff = P->w_off.as<int>();
@@ -899,7 +916,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         hipLaunchKernelGGL(k_copy_int, dim3(nblocks(B + 1)), dim3(TB), 0, s, woff, cursor, B + 1);
         hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(),
                            (int*)nullptr, P->w_idx.as<int>(), cursor, 1);
-        hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(B)), dim3(TB), 0, s, B, woff, P->w_idx.as<int>());
+        hipLaunchKernelGGL(k_sort_rows, dim3(B), dim3(64), 0, s, B, woff, P->w_idx.as<int>());
     }
     // leaf list and X-box list
     P->tmp_f.ensure(size_t(B + 1) * 4 * 4);

@@ -126,48 +126,77 @@ def _random_rotations(rng: np.random.Generator, k: int) -> np.ndarray:
     return R
 
 
-def _rsa_pack(rng: np.random.Generator, radii: np.ndarray, max_tries: int = 2000) -> np.ndarray:
+def _rsa_pack(rng: np.random.Generator, radii: np.ndarray, batch: int = 1024,
+              max_rounds: int = 4000, cap: int = 160) -> np.ndarray:
     """Random sequential addition of spheres (largest first) inside the unit cube.
 
-    Returns the centres in the order of ``radii``.  A uniform cell grid of side
-    2*max(radii) bounds the overlap checks to the 27 neighbouring cells.
+    Spheres are taken in groups (at most ``batch``, radii within 5 % of the
+    group's largest) in decreasing radius; a group is placed completely before
+    the next one starts.  Each round proposes one uniform position for every
+    unplaced sphere of the group and accepts a proposal when it overlaps
+    neither a placed sphere nor an earlier proposal accepted in the same round.
+    A uniform cell grid of side >= 2*max(radii) (at most ``cap`` spheres per
+    cell) bounds the overlap checks.  Returns the centres in the order of
+    ``radii``.
     """
     order = np.argsort(-radii, kind="stable")
     rmax = float(radii.max())
-    cell = 2.0 * rmax
-    g = max(1, int(1.0 / cell))
+    g = max(1, int(1.0 / (2.0 * rmax)))
     cell = 1.0 / g
-    buckets: dict = {}
-    cen = np.zeros((radii.shape[0], 3))
-    placed_c = []
-    placed_r = []
-    for idx in order:
-        r = float(radii[idx])
-        ok = False
-        for _ in range(max_tries):
-            c = r + (1.0 - 2.0 * r) * rng.random(3)
-            ci = np.minimum((c / cell).astype(int), g - 1)
-            cand = []
-            for dx in (-1, 0, 1):
-                for dy in (-1, 0, 1):
-                    for dz in (-1, 0, 1):
-                        lst = buckets.get((ci[0] + dx, ci[1] + dy, ci[2] + dz))
-                        if lst:
-                            cand.extend(lst)
-            if cand:
-                cc = np.asarray([placed_c[j] for j in cand])
-                rr = np.asarray([placed_r[j] for j in cand])
-                if np.any(np.sum((cc - c) ** 2, axis=1) < (rr + r) ** 2):
-                    continue
-            ok = True
-            break
-        if not ok:
-            raise RuntimeError("random sequential addition did not converge")
-        j = len(placed_c)
-        placed_c.append(c)
-        placed_r.append(r)
-        buckets.setdefault((int(ci[0]), int(ci[1]), int(ci[2])), []).append(j)
-        cen[idx] = c
+    n = radii.shape[0]
+    cen = np.zeros((n, 3))
+    # grid[cell, k] = placement slot of the k-th sphere in that cell
+    grid = np.full((g * g * g + 1, cap), n, dtype=np.int64)   # row g^3 is an empty sentinel
+    gcnt = np.zeros(g * g * g + 1, dtype=np.int64)
+    pc = np.full((n + 1, 3), 1e9)         # slot n is a far-away sentinel
+    pr = np.zeros(n + 1)
+    npl = 0
+    offs = np.array([(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+    groups = []
+    i = 0
+    while i < n:
+        j = i + 1
+        while j < n and j - i < batch and radii[order[j]] >= 0.95 * radii[order[i]]:
+            j += 1
+        groups.append(order[i:j])
+        i = j
+    for grp in groups:
+        todo = np.asarray(grp)
+        rounds = 0
+        while todo.size:
+            rounds += 1
+            if rounds > max_rounds:
+                raise RuntimeError("random sequential addition did not converge")
+            r = radii[todo]
+            c = r[:, None] + (1.0 - 2.0 * r[:, None]) * rng.random((todo.size, 3))
+            ci = np.minimum((c / cell).astype(np.int64), g - 1)
+            nb = ci[:, None, :] + offs[None, :, :]                      # [K,27,3]
+            inside = np.all((nb >= 0) & (nb < g), axis=2)
+            cid = np.where(inside, (nb[..., 0] * g + nb[..., 1]) * g + nb[..., 2], g * g * g)
+            m = max(1, int(gcnt.max()))
+            slots = grid[cid][:, :, :m].reshape(todo.size, -1)           # [K, 27*m]
+            d2 = np.sum((pc[slots] - c[:, None, :]) ** 2, axis=2)
+            ok = ~np.any(d2 < (pr[slots] + r[:, None]) ** 2, axis=1)
+            # proposals of this round against the earlier accepted ones (in order)
+            acc = []
+            for t in np.nonzero(ok)[0]:
+                if acc:
+                    a = np.asarray(acc)
+                    if np.any(np.sum((c[a] - c[t]) ** 2, axis=1) < (r[a] + r[t]) ** 2):
+                        ok[t] = False
+                        continue
+                acc.append(t)
+            for t in acc:
+                q = int((ci[t, 0] * g + ci[t, 1]) * g + ci[t, 2])
+                if gcnt[q] >= cap:
+                    raise RuntimeError("packing grid cell overflow")
+                grid[q, gcnt[q]] = npl
+                gcnt[q] += 1
+                pc[npl] = c[t]
+                pr[npl] = r[t]
+                npl += 1
+                cen[todo[t]] = c[t]
+            todo = todo[~ok]
     return cen
 
 
