@@ -189,14 +189,12 @@ def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
             continue
         S = np.concatenate(surf)
         D = np.concatenate(dens)
-        u[grp] += kernel_matrix(xt, S, c) @ D
-        G = field_matrices(xt, S, c)
-        for k in range(3):
-            E[grp, k] += G[k] @ D
+        # u = K(x, S) D, E = G(x, S) D, H = Hess K(x, S) D, summed point by point in C
+        ul, El, Hl = pairsum.direct(xt, S, D, None, c, hess)
+        u[grp] += ul
+        E[grp] += El
         if hess:
-            Hm = hessian_matrices(xt, S, c)
-            for k in range(6):
-                H[grp, k] += Hm[k] @ D
+            H[grp] += Hl
     uoff, uidx = L.csr("U")
     un, En, Hn = pairsum.p2p(targets, tleaf, t.begin, t.end, uoff, uidx, P.x, s, m, c, hess)
     u += un

@@ -1,0 +1,187 @@
+"""GPU edge cases and error paths, each against the FP64 oracle where there
+is a value to compare."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import direct, kifmm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run(x, q, kernel="laplace", p=4, leaf=8, adaptive=True, max_depth=21, root=None, precision="fp32"):
+    from paper_2512_09478_amd import Plan
+    pos = torch.tensor(x, dtype=torch.float64, device="cuda")
+    G = Plan(pos, kernel, p, leaf, adaptive, max_depth, precision=precision, root=root)
+    u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    return G, u.cpu().numpy(), E.cpu().numpy()
+
+
+def test_single_point_and_pair():
+    say("N = 1 and N = 2")
+    G, u, E = run(np.array([[0.3, 0.4, 0.5]]), np.array([2.0]))
+    assert u[0] == 0.0 and np.all(E == 0.0)
+    x = workloads.round_f32(np.array([[0.1, 0.2, 0.3], [0.7, 0.6, 0.2]]))
+    q = np.array([1.5, -0.5])
+    G, u, E = run(x, q)
+    ud, Ed, _ = direct.potential_field(x, q)
+    np.testing.assert_allclose(u, ud, rtol=1e-6)
+    np.testing.assert_allclose(E, Ed, rtol=1e-6)
+
+
+@pytest.mark.parametrize("max_depth", [12, 21])
+def test_coincident_points_reach_max_depth(max_depth):
+    say(f"coincident points, max_depth {max_depth}")
+    x = np.tile(workloads.round_f32(np.array([[0.25, 0.5, 0.75]])), (300, 1))
+    x = np.concatenate([x, workloads.uniform_cube(np.random.default_rng(0), 200)])
+    q = workloads.round_f32(np.random.default_rng(1).standard_normal(500))
+    G, u, E = run(x, q, leaf=16, max_depth=max_depth, root=((0, 0, 0), 1.0))
+    c = G.counts()
+    assert c["depth"] == max_depth
+    P = kifmm.plan(x, "laplace", 4, 16, True, max_depth, ((0, 0, 0), 1.0))
+    uo, Eo = kifmm.forward(P, q)
+    assert rel(u, uo) < 1e-5
+    if max_depth <= 12:
+        assert rel(E, Eo) < 1e-5
+    else:
+        # At depth 21 the leaf is 2^-21 wide: the local expansion carried down
+        # 18 L2L levels in FP32 keeps the potential, but the field (its linear
+        # part, ~1e-6 of the constant part over such a box) loses digits.
+        assert np.all(np.isfinite(E)) and rel(E, Eo) < 1e-2
+
+
+def test_upper_face_and_explicit_root():
+    say("points on the upper faces of an explicit root")
+    rng = np.random.default_rng(2)
+    x = workloads.uniform_cube(rng, 2000)
+    x[:10, 0] = 1.0
+    x[10:20, 1] = 1.0
+    x[20:30] = 1.0
+    q = workloads.round_f32(rng.standard_normal(2000))
+    G, u, E = run(x, q, p=5, leaf=24, root=((0, 0, 0), 1.0))
+    t = G.tree()
+    P = kifmm.plan(x, "laplace", 5, 24, True, 21, ((0, 0, 0), 1.0))
+    np.testing.assert_array_equal(t["keys"], P.tree.keys)
+    uo, Eo = kifmm.forward(P, q)
+    assert rel(u, uo) < 1e-5 and rel(E, Eo) < 1e-5
+
+
+@pytest.mark.parametrize("leaf,max_depth,adaptive", [(1, 21, True), (8, 2, True), (50, 21, False), (4, 3, False)])
+def test_leaf_and_depth_limits(leaf, max_depth, adaptive):
+    say(f"leaf {leaf} max_depth {max_depth} adaptive {adaptive}")
+    w = workloads.make(2, n=1500)
+    G, u, E = run(w.positions, w.charges, p=3, leaf=leaf, adaptive=adaptive, max_depth=max_depth, root=w.root)
+    P = kifmm.plan(w.positions, "laplace", 3, leaf, adaptive, max_depth, w.root)
+    t = G.tree()
+    np.testing.assert_array_equal(t["begin"], P.tree.begin)
+    np.testing.assert_array_equal(t["is_leaf"], P.tree.is_leaf)
+    uo, Eo = kifmm.forward(P, w.charges)
+    assert rel(u, uo) < 1e-5 and rel(E, Eo) < 1e-5
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 7])
+def test_other_orders(p):
+    say(f"order p = {p}")
+    w = workloads.make(5, n=3000)
+    G, u, E = run(w.positions, w.charges, kernel="gravity", p=p, leaf=32, max_depth=12, root=w.root)
+    P = kifmm.plan(w.positions, "gravity", p, 32, True, 12, w.root)
+    uo, Eo = kifmm.forward(P, w.charges)
+    tol = 1e-4 if p >= 7 else 1e-5
+    assert rel(u, uo) < tol and rel(E, Eo) < tol
+
+
+def test_automatic_root_and_negative_coordinates():
+    say("automatic root around negative coordinates")
+    rng = np.random.default_rng(4)
+    x = workloads.round_f32(rng.standard_normal((3000, 3)) * 3.0 - 10.0)
+    q = workloads.round_f32(rng.uniform(-1, 1, 3000))
+    G, u, E = run(x, q, p=4, leaf=32)
+    P = kifmm.plan(x, "laplace", 4, 32, True, 21, None)
+    t = G.tree()
+    assert t["side"] == P.tree.s and np.array_equal(t["lo"], P.tree.lo)
+    uo, Eo = kifmm.forward(P, q)
+    assert rel(u, uo) < 1e-5 and rel(E, Eo) < 1e-5
+
+
+def test_rebuild_matches_fresh_setup_and_precision_switch():
+    say("rebuild with moved points; precision switch")
+    from paper_2512_09478_amd import Plan
+    w = workloads.make(4, n=5000)
+    rng = np.random.default_rng(5)
+    x2 = np.clip(workloads.round_f32(w.positions + 0.01 * rng.standard_normal(w.positions.shape)), 0, 0.999)
+    pos = torch.tensor(w.positions, dtype=torch.float64, device="cuda")
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    G = Plan(pos, "laplace", 5, 32, True, 21, root=w.root)
+    G.evaluate(q)
+    G.rebuild(torch.tensor(x2, dtype=torch.float64, device="cuda"))
+    u1, E1 = G.evaluate(q)
+    H = Plan(torch.tensor(x2, dtype=torch.float64, device="cuda"), "laplace", 5, 32, True, 21, root=w.root)
+    u2, E2 = H.evaluate(q)
+    assert torch.equal(u1, u2) and torch.equal(E1, E2)
+    G.set_precision("split_bf16")
+    u3, E3 = G.evaluate(q)
+    P = kifmm.plan(x2, "laplace", 5, 32, True, 21, w.root)
+    uo, Eo = kifmm.forward(P, w.charges)
+    assert rel(u3.cpu().numpy(), uo) < 1e-4 and rel(E3.cpu().numpy(), Eo) < 1e-4
+
+
+def test_side_stream_and_phase_times():
+    say("non-default stream, phase times")
+    from paper_2512_09478_amd import Plan
+    w = workloads.make(2, n=20000)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pos = torch.tensor(w.positions, dtype=torch.float64, device="cuda")
+        q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+        G = Plan(pos, "laplace", 4, 48, True, 21, root=w.root, profile=True)
+        u, E = G.evaluate(q)
+        ph = G.phase_times()
+    s.synchronize()
+    assert set(ph) >= {"m2l", "p2p", "total"} and ph["total"] > 0
+    P = kifmm.plan(w.positions, "laplace", 4, 48, True, 21, w.root)
+    uo, Eo = kifmm.forward(P, w.charges)
+    assert rel(u.cpu().numpy(), uo) < 1e-5 and rel(E.cpu().numpy(), Eo) < 1e-5
+
+
+def test_input_errors_leave_destroyable_handles():
+    say("input errors")
+    from paper_2512_09478_amd import KifmmError, Plan
+    x = np.random.default_rng(6).random((100, 3))
+    bad = x.copy()
+    bad[17, 1] = np.nan
+    with pytest.raises(KifmmError) as ei:
+        Plan(torch.tensor(bad, device="cuda"), "laplace", 4, 8)
+    assert ei.value.code == -2
+    with pytest.raises(KifmmError) as ei:
+        Plan(torch.tensor(x + 1.5, device="cuda"), "laplace", 4, 8, root=((0, 0, 0), 1.0))
+    assert ei.value.code == -2
+    G = Plan(torch.tensor(x, device="cuda"), "laplace", 4, 8)
+    q = torch.ones(100, dtype=torch.float32, device="cuda")
+    u, E = G.evaluate(q)
+    off = torch.tensor([0, 50, 40, 100], dtype=torch.int64, device="cuda")   # not monotone
+    cen = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(KifmmError) as ei:
+        G.clump_reduce(q, E, off, cen)
+    assert ei.value.code == -2
+    off = torch.tensor([0, 50, 120], dtype=torch.int64, device="cuda")      # beyond N
+    with pytest.raises(KifmmError):
+        G.clump_reduce(q, E, off, cen[:2])
+    # the handle still works and is destroyable
+    u2, E2 = G.evaluate(q)
+    assert torch.equal(u, u2)
+    G.close()
+    with pytest.raises(KifmmError):
+        G.evaluate(q)
