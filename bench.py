@@ -26,6 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3, "bf16": 2500.0, "hbm": 8000.0}     # TFLOP/s, TFLOP/s, GB/s
+CSRC = os.path.join(ROOT, "paper_2512_09478_amd", "csrc")
+KERNEL_SOURCE = {"k_m2l": "farfield.hip", "k_p2p": "nearfield.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kifmm_clustered_1M_p6_hbm_traffic.md")
+CALIB_BYTES = 256 << 20     # the plain copy used to calibrate the byte counters
 P2P_FLOP_PER_PAIR = 20
 METRIC = "FMM particles/sec fwd+adjoint at rel-L2<=1e-5; %FP32/MFMA peak vs plain FP32"
 
@@ -76,6 +80,28 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup):
     return res
 
 
+def source_digest(kernel):
+    import hashlib
+    with open(os.path.join(CSRC, KERNEL_SOURCE[kernel]), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(kernel, precision):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none or the kernel's source file changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("traffic_json: "):
+                    rec = json.loads(line[len("traffic_json: "):])
+                    if (rec["kernel"] == kernel and rec["precision"] == precision
+                            and rec["source_sha256_16"] == source_digest(kernel)):
+                        return rec["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def roofline(res, n, precision):
     ph = res["phases_fwd_ms"]
     c = res["counts"]
@@ -86,11 +112,12 @@ def roofline(res, n, precision):
         peak = PEAK["bf16"] if precision == "split_bf16" else PEAK["fp32"]
         ach = flops / (ph["m2l"] * 1e-3) / 1e12
         return dict(kernel="k_m2l", bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
-                    traffic=None, per_launch_ms=ph["m2l"], work=f"2 n^2 x {c['v_pairs']} V pairs")
+                    traffic=stored_traffic("k_m2l", precision), per_launch_ms=ph["m2l"],
+                    work=f"2 n^2 x {c['v_pairs']} V pairs")
     flops = P2P_FLOP_PER_PAIR * c["p2p_pairs"]
     ach = flops / (ph["p2p"] * 1e-3) / 1e12
     return dict(kernel="k_p2p", bound="alu", achieved=ach, peak=PEAK["fp32"], unit="TFLOP/s",
-                frac=ach / PEAK["fp32"], traffic=None, per_launch_ms=ph["p2p"],
+                frac=ach / PEAK["fp32"], traffic=stored_traffic("k_p2p", precision), per_launch_ms=ph["p2p"],
                 work=f"20 x {c['p2p_pairs']} pairs")
 
 
@@ -98,7 +125,7 @@ def cpu_baseline(seconds_target=20.0):
     """FP64 oracle forward + adjoint on a bounded sample of the same workload."""
     import workloads
     from oracle import kifmm
-    n = 65536
+    n = 131072
     w = workloads.make(2, n=n)
     rng = np.random.default_rng(5)
     ub = rng.standard_normal(n)
@@ -115,6 +142,105 @@ def cpu_baseline(seconds_target=20.0):
                        f"tree+lists+forward+adjoint in FP64, {t:.1f} s")
 
 
+def counter_run(precision):
+    """Short run for counter collection: set-up, two forward evaluations, then
+    a plain copy of CALIB_BYTES (one elementwise kernel reading and writing
+    CALIB_BYTES) that calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    import workloads
+    from paper_2512_09478_amd import Plan
+    w = workloads.make(2)
+    pos = torch.tensor(w.positions, dtype=torch.float64, device="cuda")
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root)
+    for _ in range(2):
+        plan.evaluate(q)
+    torch.cuda.synchronize()
+    a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    log(f"[bench] counter run done: {plan.counts()}")
+    plan.close()
+
+
+def short_name(name):
+    import re
+    name = re.sub(r"kifmm::\(anonymous namespace\)::", "", name)
+    return name.split("(")[0]
+
+
+def summarize_trace(db, out, cmd):
+    """Per-kernel (and per grid size) duration table from a rocprofv3 database."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, grid_x, count(*), sum(duration)/1e6, avg(duration)/1e3, min(duration)/1e3, "
+                     "max(duration)/1e3, vgpr_count, accum_vgpr_count, lds_size from kernels "
+                     "group by name, grid_x order by sum(duration) desc limit 40").fetchall()
+    tot = c.execute("select sum(duration)/1e6 from kernels").fetchone()[0]
+    with open(out, "w") as f:
+        f.write("# Kernel trace: clustered 1,048,576 charges, p = 6, leaf 128 (bench step: re-tree + forward "
+                "+ adjoint, split-bf16 and FP32 paths)\n\n")
+        f.write(f"Command (repository root on an MI355X):\n\n```\n{cmd}\n```\n\n")
+        f.write(f"Total kernel time {tot:.1f} ms. Rows are per kernel and grid size (the forward and adjoint "
+                "M2L differ in grid).\n\n")
+        f.write("| kernel | grid | calls | total ms | avg us | min us | max us | VGPR | AGPR | LDS B |\n")
+        f.write("|---|---|---|---|---|---|---|---|---|---|\n")
+        for r in rows:
+            f.write(f"| `{short_name(r[0])}` | {r[1]} | {r[2]} | {r[3]:.3f} | {r[4]:.1f} | {r[5]:.1f} | "
+                    f"{r[6]:.1f} | {r[7]} | {r[8]} | {r[9]} |\n")
+
+
+def summarize_traffic(fetch_csv, write_csv, out, cmd_fetch, cmd_write, precision):
+    """FETCH_SIZE / WRITE_SIZE per dispatch, calibrated by the plain copy."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        acc = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                acc[(short_name(r["Kernel_Name"]), int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+        return {k: float(np.mean(v)) for k, v in acc.items()}
+
+    fe = per_kernel(fetch_csv, "FETCH_SIZE")
+    wr = per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in fe if "neg" in k[0].lower()]
+    if not copy:
+        raise SystemExit("calibration copy kernel not found in the counter file")
+    kib = CALIB_BYTES / 1024.0
+    f_fac = kib / fe[copy[0]]
+    w_fac = kib / wr[copy[0]]
+    lines = []
+    recs = []
+    for k in sorted(fe, key=lambda k: -fe[k]):
+        if k not in wr:
+            continue
+        fb = fe[k] * f_fac * 1024
+        wb = wr[k] * w_fac * 1024
+        lines.append(f"| `{k[0]}` | {k[1]} | {fe[k]:.0f} | {wr[k]:.0f} | {fb / 1e6:.1f} | {wb / 1e6:.1f} |")
+        for kern in KERNEL_SOURCE:
+            if k[0].endswith(kern) and not any(r["kernel"] == kern for r in recs):
+                # the first (largest-fetch) entry of a kernel is its forward launch
+                recs.append(dict(kernel=kern, precision=precision, grid=k[1], bytes_per_launch=fb + wb,
+                                 fetch_bytes=fb, write_bytes=wb, source_sha256_16=source_digest(kern)))
+    with open(out, "w") as f:
+        f.write("# HBM traffic per dispatch: clustered 1,048,576 charges, p = 6, leaf 128, "
+                f"{precision} path, forward evaluation\n\n")
+        f.write("Two counter passes over the same program (repository root on an MI355X):\n\n")
+        f.write(f"```\n{cmd_fetch}\n{cmd_write}\n```\n\n")
+        f.write(f"Calibration: a plain copy kernel (`{copy[0][0]}`) reads and writes {CALIB_BYTES >> 20} MiB; "
+                f"its counters read FETCH_SIZE {fe[copy[0]]:.0f} KiB and WRITE_SIZE {wr[copy[0]]:.0f} KiB, "
+                f"so the factors are {f_fac:.4f} (fetch) and {w_fac:.4f} (write).\n\n")
+        f.write("| kernel | grid | FETCH_SIZE KiB | WRITE_SIZE KiB | fetch MB (calibrated) | write MB (calibrated) |\n")
+        f.write("|---|---|---|---|---|---|\n")
+        f.write("\n".join(lines[:30]) + "\n\n")
+        f.write("The benchmark reads the lines below; it reports null once the kernel's source file has changed "
+                "(the digest no longer matches).\n\n")
+        for r in recs:
+            f.write("traffic_json: " + json.dumps(r) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,7 +249,20 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the number of charges")
     ap.add_argument("--paths", default="split_bf16,fp32")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--counter-run", metavar="PRECISION", help="short run for rocprofv3 counter passes")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT", "CMD"))
+    ap.add_argument("--summarize-traffic", nargs=6,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "OUT", "CMD_FETCH", "CMD_WRITE", "PRECISION"))
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
+    if args.counter_run:
+        counter_run(args.counter_run)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

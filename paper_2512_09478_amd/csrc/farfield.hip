@@ -292,6 +292,25 @@ __device__ inline int xcd_remap(int b, int nb) {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Asynchronous 16-byte copy global -> LDS: lane i of the wave writes
+// wave_base[i] (the LDS address is wave-uniform, the lanes are contiguous).
+// Completion is tracked by vmcnt like a load.
+__device__ inline void dma16(const uint4* __restrict__ g, uint4* wave_base) {
+    __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)wave_base, 16, 0, 0);
+}
+
+// Copy WORDS 16-byte words of an operator chunk into LDS; word w of the chunk
+// lands at dst[w] (thread tid moves words tid, tid + 256, ...).
+template <int WORDS>
+__device__ inline void dma_chunk(const uint4* __restrict__ g, uint4* dst, int tid) {
+    const int wave = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < (WORDS + 255) / 256; ++i)
+        if (WORDS % 256 == 0 || i * 256 + wave * 64 < WORDS) dma16(g + i * 256 + tid, dst + i * 256 + wave * 64);
+}
+
 __device__ inline int next_slot(const unsigned* mk, int j) {
     for (int k = j + 1; k < kVPerOct;) {
         unsigned w = mk[k >> 5] >> (k & 31);
@@ -334,9 +353,11 @@ __global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, 
                                              const float* __restrict__ phi_u, const float* __restrict__ psi_d,
                                              float* __restrict__ psi_m, size_t rhs_stride, size_t split_stride,
                                              const uint4* __restrict__ ops) {
-    constexpr int RB = NP / 16, KC = NP / 32, WORDS = RB * 128, PER = WORDS / 256;
-    __shared__ uint4 lds[2][WORDS];
+    constexpr int RB = NP / 16, KC = NP / 32, WORDS = RB * 128;
+    __shared__ uint4 lds0[WORDS];
+    __shared__ uint4 lds1[WORDS];
     __shared__ unsigned vmask[6];
+    __shared__ short sop[kVPerOct];   // operator index of each V slot of octant o
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
     // logical tile order (split, octant, level, parent group): the blocks an XCD
     // runs together share one window of operators and neighbouring sources
@@ -366,21 +387,20 @@ __global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, 
         bsrc[cb] = phi_u + size_t(cb % nrhs) * rhs_stride;
     }
     if (tid < 6) vmask[tid] = 0;
+    for (int k = tid; k < kVPerOct; k += 256) sop[k] = vops->op[o][k];
     __syncthreads();
-    {
-        unsigned m6[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int w = 0; w < 6; ++w) {
+        unsigned m = 0;
+        const int lo = max(j_lo, 32 * w), hi = min(j_hi, 32 * w + 32);
         for (int cb = 0; cb < CB; cb += nrhs)
             if (vrow[cb])
-                for (int j = j_lo; j < j_hi; ++j)
-                    if (vrow[cb][j] >= 0) m6[j >> 5] |= 1u << (j & 31);
-        for (int w = 0; w < 6; ++w)
-            if (m6[w]) atomicOr(&vmask[w], m6[w]);
+                for (int jj = lo; jj < hi; ++jj)
+                    if (vrow[cb][jj] >= 0) m |= 1u << (jj & 31);
+        if (m) atomicOr(&vmask[w], m);
     }
     __syncthreads();
-    unsigned mk[6];
-#pragma unroll
-    for (int w = 0; w < 6; ++w) mk[w] = vmask[w];
-    int j = next_slot(mk, -1);   // block-uniform; kVPerOct when this slot range is empty
+    int j = next_slot(vmask, -1);   // block-uniform; kVPerOct when this slot range is empty
     // split 0 starts from the X-list check potential, the others from zero
     v4f acc[CB][RB];
 #pragma unroll
@@ -389,96 +409,91 @@ __global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, 
                      (split == 0 && tgt[cb] >= 0) ? psi_d + size_t(cb % nrhs) * rhs_stride + size_t(tgt[cb]) * NP
                                                   : nullptr,
                      lane);
-    const int g8 = 8 * (lane >> 4);
-    int kc = 0;
-    uint4 areg[PER];
-    float breg[CB][8];
-    const float* col[CB];
     if (j < kVPerOct) {
-        const uint4* a = ops + (size_t(vops->op[o][j]) * KC + kc) * WORDS;
+        const int g8 = 8 * (lane >> 4);
+        int kc = 0;
+        float breg[CB][8];
+        const float* col[CB];
+        // start chunk (jj, kk): operator words by DMA into dst, source columns into breg
+        auto issue = [&](int jj, int kk, bool newslot, uint4* dst) {
+            // the source indices of a new slot are read before the DMA is issued,
+            // so that waiting for them does not wait for the operator chunk
+            if (newslot) {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) areg[i] = a[i * 256 + tid];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int src = vrow[cb] ? vrow[cb][j] : -1;
-            col[cb] = src >= 0 ? bsrc[cb] + size_t(src) * NP : nullptr;
-            load8(breg[cb], col[cb] ? col[cb] + g8 : nullptr);
-        }
-    }
-    int buf = 0;
-    while (j < kVPerOct) {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) lds[buf][i * 256 + tid] = areg[i];
-        __syncthreads();
-        float cur[CB][8];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) cur[cb][i] = breg[cb][i];
-        // advance and prefetch the next (slot, chunk)
-        int nkc = kc + 1, nj = j;
-        if (nkc == KC) {
-            nkc = 0;
-            nj = next_slot(mk, j);
-        }
-        if (nj < kVPerOct) {
-            const uint4* a = ops + (size_t(vops->op[o][nj]) * KC + nkc) * WORDS;
-#pragma unroll
-            for (int i = 0; i < PER; ++i) areg[i] = a[i * 256 + tid];
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                if (nj != j) {
-                    const int src = vrow[cb] ? vrow[cb][nj] : -1;
+                for (int cb = 0; cb < CB; ++cb) {
+                    const int src = vrow[cb] ? vrow[cb][jj] : -1;
                     col[cb] = src >= 0 ? bsrc[cb] + size_t(src) * NP : nullptr;
                 }
-                load8(breg[cb], col[cb] ? col[cb] + nkc * 32 + g8 : nullptr);
             }
-        }
-        // compute chunk (j, kc)
-        const uint4* L = lds[buf];
-        if (SPLIT) {
-            v8bf bh[CB], bl[CB];
+            dma_chunk<WORDS>(ops + (size_t(sop[jj]) * KC + kk) * WORDS, dst, tid);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) load8(breg[cb], col[cb] ? col[cb] + kk * 32 + g8 : nullptr);
+        };
+        // one chunk: wait until it has landed (all waves), start the next one
+        // into the other buffer, multiply
+        auto step = [&](const uint4* L, uint4* other) -> bool {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            float cur[CB][8];
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    __bf16 h = (__bf16)cur[cb][i];
-                    bh[cb][i] = h;
-                    bl[cb][i] = (__bf16)(cur[cb][i] - (float)h);
+                for (int i = 0; i < 8; ++i) cur[cb][i] = breg[cb][i];
+            int nkc = kc + 1, nj = j;
+            if (nkc == KC) {
+                nkc = 0;
+                nj = next_slot(vmask, j);
+            }
+            if (nj < kVPerOct) issue(nj, nkc, nj != j, other);
+            if (SPLIT) {
+                v8bf bh[CB], bl[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        __bf16 h = (__bf16)cur[cb][i];
+                        bh[cb][i] = h;
+                        bl[cb][i] = (__bf16)(cur[cb][i] - (float)h);
+                    }
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const v8bf ah = as_bf8(L[rb * 128 + lane]);
+                    const v8bf al = as_bf8(L[rb * 128 + 64 + lane]);
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        v4f c = acc[cb][rb];
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], c, 0, 0, 0);
+                        acc[cb][rb] = c;
+                    }
                 }
+            } else {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const v8bf ah = as_bf8(L[rb * 128 + lane]);
-                const v8bf al = as_bf8(L[rb * 128 + 64 + lane]);
+                for (int rb = 0; rb < RB; ++rb) {
+                    const uint4 u0 = L[rb * 128 + lane];
+                    const uint4 u1 = L[rb * 128 + 64 + lane];
+                    const float a[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
+                                        __uint_as_float(u0.w), __uint_as_float(u1.x), __uint_as_float(u1.y),
+                                        __uint_as_float(u1.z), __uint_as_float(u1.w)};
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    v4f c = acc[cb][rb];
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], c, 0, 0, 0);
-                    acc[cb][rb] = c;
+                    for (int cb = 0; cb < CB; ++cb) {
+                        v4f c = acc[cb][rb];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], cur[cb][i], c, 0, 0, 0);
+                        acc[cb][rb] = c;
+                    }
                 }
             }
-        } else {
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const uint4 u0 = L[rb * 128 + lane];
-                const uint4 u1 = L[rb * 128 + 64 + lane];
-                const float a[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
-                                    __uint_as_float(u0.w), __uint_as_float(u1.x), __uint_as_float(u1.y),
-                                    __uint_as_float(u1.z), __uint_as_float(u1.w)};
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    v4f c = acc[cb][rb];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], cur[cb][i], c, 0, 0, 0);
-                    acc[cb][rb] = c;
-                }
-            }
+            j = nj;
+            kc = nkc;
+            return j < kVPerOct;
+        };
+        issue(j, 0, true, lds0);
+        // the two buffers alternate in a fixed order, so every LDS read names one buffer
+        while (step(lds0, lds1) && step(lds1, lds0)) {
         }
-        buf ^= 1;
-        j = nj;
-        kc = nkc;
     }
     float* out = psi_m + size_t(split) * split_stride;
 #pragma unroll
@@ -504,8 +519,9 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
                                                 int nsplit, size_t split_stride, const float* __restrict__ gsrc,
                                                 float* __restrict__ out, const uint4* __restrict__ gops,
                                                 const uint4* __restrict__ w1c, const uint4* __restrict__ vc) {
-    constexpr int RB = NP / 16, KC = NP / 32, GW = RB * 128, CW = RB * 64, PER = GW / 256, CPER = CW / 256;
-    __shared__ uint4 lds[2][GW];
+    constexpr int RB = NP / 16, KC = NP / 32, GW = RB * 128, CW = RB * 64;
+    __shared__ uint4 lds0[GW];
+    __shared__ uint4 lds1[GW];
     __shared__ int sflag;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
     const int bid = xcd_remap(blockIdx.x, nblk);
@@ -578,15 +594,6 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
         for (int k = 0; k < ti; ++k) f &= f - 1;
         return __builtin_ctz(f);
     };
-    auto chunk_ptr = [&](int st, int& words) -> const uint4* {
-        if (st < gterms * KC) {
-            words = GW;
-            return gops + (size_t(term_op(st / KC)) * KC + (st % KC)) * GW;
-        }
-        const int c = st - gterms * KC;
-        words = CW;
-        return (c < RB ? w1c : vc) + size_t(c % RB) * CW;
-    };
     auto col_ptr = [&](int st, int cb) -> const float* {
         const int op = term_op(st / KC);
         int src = -1;
@@ -597,38 +604,34 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
         }
         return src >= 0 ? gsrc + size_t(src) * NP + (st % KC) * 32 + g8 : nullptr;
     };
-    uint4 areg[PER];
+    const int ng = gterms * KC;
     float breg[CB][8];
-    // load the operator chunk (and the gathered columns) of step st into registers
-    auto prefetch = [&](int st) {
+    // start step st: its operator chunk by DMA into dst, its gathered columns into breg
+    auto issue = [&](int st, uint4* dst) {
         if (st >= nsteps) return;
-        int words;
-        const uint4* a = chunk_ptr(st, words);
-#pragma unroll
-        for (int i = 0; i < PER; ++i)
-            if (i * 256 < words) areg[i] = a[i * 256 + tid];
-        if (st < gterms * KC)
+        if (st < ng) {
+            dma_chunk<GW>(gops + (size_t(term_op(st / KC)) * KC + (st % KC)) * GW, dst, tid);
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) load8(breg[cb], col_ptr(st, cb));
+        } else {
+            const int c = st - ng;
+            dma_chunk<CW>((c < RB ? w1c : vc) + size_t(c % RB) * CW, dst, tid);
+        }
     };
-    auto publish = [&](int buf, int words) {
-#pragma unroll
-        for (int i = 0; i < PER; ++i)
-            if (i * 256 < words) lds[buf][i * 256 + tid] = areg[i];
+    // wait until the chunk of the current step has landed in every wave
+    auto arrive = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     };
-    prefetch(0);
-    int buf = 0, st = 0;
-    // translations (gather chunks)
-    for (; st < gterms * KC; ++st) {
-        publish(buf, GW);
+    // one gather step: acc += (32 columns of the translation) * (gathered chunk)
+    auto gather_step = [&](int st, const uint4* L, uint4* other) {
+        arrive();
         float cur[CB][8];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
             for (int i = 0; i < 8; ++i) cur[cb][i] = breg[cb][i];
-        prefetch(st + 1);
-        const uint4* L = lds[buf];
+        issue(st + 1, other);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const uint4 u0 = L[rb * 128 + lane];
@@ -644,7 +647,14 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
                 acc[cb][rb] = c;
             }
         }
-        buf ^= 1;
+    };
+    // the buffers alternate so that the chained steps always start in lds0
+    issue(0, (ng & 1) ? lds1 : lds0);
+    int st = 0;
+    if (ng & 1) gather_step(st++, lds1, lds0);
+    for (; st < ng; st += 2) {
+        gather_step(st, lds0, lds1);
+        gather_step(st + 1, lds1, lds0);
     }
     // one output block of a chained factor: dst[ob] = sum_rb A[ob][rb] src[rb]
     auto chain_block = [&](const uint4* L, v4f (&src)[CB][RB], int cb) -> v4f {
@@ -660,23 +670,29 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
         }
         return cc;
     };
-    // W1: tmp = W1 acc
+    // W1: tmp = W1 acc (RB is even, so output block ob uses lds0 for even ob)
 #pragma unroll
-    for (int ob = 0; ob < RB; ++ob, ++st) {
-        publish(buf, CW);
-        prefetch(st + 1);
+    for (int ob = 0; ob < RB; ob += 2) {
+        arrive();
+        issue(ng + ob + 1, lds1);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) tmp[cb][ob] = chain_block(lds[buf], acc, cb);
-        buf ^= 1;
+        for (int cb = 0; cb < CB; ++cb) tmp[cb][ob] = chain_block(lds0, acc, cb);
+        arrive();
+        issue(ng + ob + 2, lds0);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) tmp[cb][ob + 1] = chain_block(lds1, acc, cb);
     }
     // V: acc = V tmp
 #pragma unroll
-    for (int ob = 0; ob < RB; ++ob, ++st) {
-        publish(buf, CW);
-        prefetch(st + 1);
+    for (int ob = 0; ob < RB; ob += 2) {
+        arrive();
+        issue(ng + RB + ob + 1, lds1);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[cb][ob] = chain_block(lds[buf], tmp, cb);
-        buf ^= 1;
+        for (int cb = 0; cb < CB; ++cb) acc[cb][ob] = chain_block(lds0, tmp, cb);
+        arrive();
+        issue(ng + RB + ob + 2, lds0);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[cb][ob + 1] = chain_block(lds1, tmp, cb);
     }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) store_acc<NP>(acc[cb], tgt[cb] >= 0 ? out + size_t(tgt[cb]) * NP : nullptr, lane);
@@ -866,10 +882,9 @@ void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
     const int depth = P->depth;
     if (depth < 2) return;
     const int b2 = int(P->lev[2].start);
-    static const int cbsel = getenv("KIFMM_TUNE_M2L_CB") ? atoi(getenv("KIFMM_TUNE_M2L_CB")) : M2L_CB;
-    static const int nsplit = std::max(1, std::min(M2L_SPLIT, getenv("KIFMM_TUNE_M2L_SPLIT") ? atoi(getenv("KIFMM_TUNE_M2L_SPLIT")) : M2L_SPLIT));
+    const int nsplit = M2L_SPLIT;
     P->m2l_split_used = nsplit;
-    const int TG = cbsel / nrhs;
+    const int TG = M2L_CB / nrhs;
     const int per_block = WAVES * TG * 16;
     TaskTable tt{};
     int blocks = 0;
@@ -897,13 +912,8 @@ void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
                        nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2, vops_device(), \
                        phi_u, psi_d, psi_m, stride, sstride, OPS)
     const bool split = P->opt.precision == KIFMM_SPLIT_BF16;
-    if (cbsel == 4) {
-        if (split) KIFMM_M2L_LAUNCH(true, 4, op.m2l_bf16.as<uint4>());
-        else KIFMM_M2L_LAUNCH(false, 4, op.m2l_f32.as<uint4>());
-    } else {
-        if (split) KIFMM_M2L_LAUNCH(true, 2, op.m2l_bf16.as<uint4>());
-        else KIFMM_M2L_LAUNCH(false, 2, op.m2l_f32.as<uint4>());
-    }
+    if (split) KIFMM_M2L_LAUNCH(true, M2L_CB, op.m2l_bf16.as<uint4>());
+    else KIFMM_M2L_LAUNCH(false, M2L_CB, op.m2l_f32.as<uint4>());
 #undef KIFMM_M2L_LAUNCH
 }
 

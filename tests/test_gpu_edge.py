@@ -42,25 +42,35 @@ def test_single_point_and_pair():
     np.testing.assert_allclose(E, Ed, rtol=1e-6)
 
 
-@pytest.mark.parametrize("max_depth", [12, 21])
+@pytest.mark.parametrize("max_depth", [6, 12, 21])
 def test_coincident_points_reach_max_depth(max_depth):
+    """300 coincident charges on a box corner force a chain of single-child
+    boxes down to max_depth.  Their field then comes from the leaf's local
+    expansion alone (the coincident pairs are skipped, no near field): a
+    relative representation error delta of that expansion becomes a field
+    error of about delta |u| / w over a leaf of width w = 2^-depth.  The FP64
+    method's own field there drifts with depth for that reason (truncation),
+    and the FP32 path adds delta ~ eps32 times the conditioning of the
+    downward densities.  The bound on the coincident field is that product with
+    a conditioning factor of 64 (measured: 15 at depth 12, 27 at depth 21,
+    p = 4); every other output keeps the 1e-5 bound."""
     say(f"coincident points, max_depth {max_depth}")
-    x = np.tile(workloads.round_f32(np.array([[0.25, 0.5, 0.75]])), (300, 1))
+    nc = 300
+    x = np.tile(workloads.round_f32(np.array([[0.25, 0.5, 0.75]])), (nc, 1))
     x = np.concatenate([x, workloads.uniform_cube(np.random.default_rng(0), 200)])
-    q = workloads.round_f32(np.random.default_rng(1).standard_normal(500))
+    q = workloads.round_f32(np.random.default_rng(1).standard_normal(nc + 200))
     G, u, E = run(x, q, leaf=16, max_depth=max_depth, root=((0, 0, 0), 1.0))
     c = G.counts()
     assert c["depth"] == max_depth
     P = kifmm.plan(x, "laplace", 4, 16, True, max_depth, ((0, 0, 0), 1.0))
     uo, Eo = kifmm.forward(P, q)
     assert rel(u, uo) < 1e-5
-    if max_depth <= 12:
-        assert rel(E, Eo) < 1e-5
-    else:
-        # At depth 21 the leaf is 2^-21 wide: the local expansion carried down
-        # 18 L2L levels in FP32 keeps the potential, but the field (its linear
-        # part, ~1e-6 of the constant part over such a box) loses digits.
-        assert np.all(np.isfinite(E)) and rel(E, Eo) < 1e-2
+    assert rel(E[nc:], Eo[nc:]) < 1e-5
+    eps32 = float(np.finfo(np.float32).eps) / 2
+    bound = 64 * eps32 * np.abs(uo[:nc]).max() / 2.0 ** -max_depth
+    err = np.abs(E[:nc] - Eo[:nc]).max()
+    say(f"  coincident field |dE| {err:.3e}, bound {bound:.3e}")
+    assert np.all(np.isfinite(E)) and err <= bound
 
 
 def test_upper_face_and_explicit_root():
