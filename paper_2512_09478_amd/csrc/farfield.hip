@@ -508,201 +508,149 @@ __global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, 
 // Downward: for the children at octant o of non-leaf parents, psi = the summed
 // M2L partials (+ X list) + L2L[o] phi_d(parent) (from level 3), then
 // phi_d = U (W1d psi).
-// The block's four waves (CB column blocks of 16 boxes each) share every
-// operator chunk, streamed through a double-buffered LDS tile: gather chunks
-// (32 columns of a translation, B = gathered densities) and chain chunks (one
-// 16-row output block of a check-to-equivalent factor, B = the accumulator).
-template <int NP, int CB, bool UP>
+// A block holds 16 boxes (one MFMA column block) and its four waves split the
+// NP/16 output row blocks (wave w owns rb = w, w + 4, ...), so that even a
+// level with a few boxes is spread over several SIMDs.  The operators (under
+// 1 MB) are read as MFMA fragments straight from L2.  The chained
+// check-to-equivalent factors need the whole intermediate vector: it is
+// exchanged through LDS in accumulator layout.
+template <int NP, bool UP>
 __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl_start, int nl_count, int has_l2l,
                                                 const int* __restrict__ nonleaf, const int2* __restrict__ child,
                                                 const int* __restrict__ leafflag, const float* __restrict__ psi_in,
                                                 int nsplit, size_t split_stride, const float* __restrict__ gsrc,
                                                 float* __restrict__ out, const uint4* __restrict__ gops,
                                                 const uint4* __restrict__ w1c, const uint4* __restrict__ vc) {
-    constexpr int RB = NP / 16, KC = NP / 32, GW = RB * 128, CW = RB * 64;
-    __shared__ uint4 lds0[GW];
-    __shared__ uint4 lds1[GW];
-    __shared__ int sflag;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
+    constexpr int RB = NP / 16, KC = NP / 32, NR = (RB + 3) / 4;
+    __shared__ v4f xa[RB][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int bid = xcd_remap(blockIdx.x, nblk);
-    const int g8 = 8 * (lane >> 4);
-    int tgt[CB], par[CB], cmask[CB], cfirst[CB];
-    int o = 0;
+    const int g4 = 4 * (lane >> 4), g8 = 8 * (lane >> 4);
+    int tgt = -1, par = -1, cmask = 0, cfirst = 0, o = 0;
+    if (UP) {
+        const int idx = bid * 16 + (lane & 15);
+        if (idx < nb) {
+            tgt = b0 + idx;
+            if (!leafflag[tgt]) {
+                const int2 ch = child[tgt];
+                cfirst = ch.x;
+                cmask = ch.y;
+            }
+        }
+    } else {
+        o = bid % 8;
+        const int slot = (bid / 8) * 16 + (lane & 15);
+        if (slot < nl_count) {
+            const int Pb = nonleaf[nl_start + slot];
+            const int2 ch = child[Pb];
+            if ((ch.y >> o) & 1) {
+                tgt = ch.x + __popc(ch.y & ((1 << o) - 1));
+                par = Pb;
+            }
+        }
+    }
+    // the gather terms any column of the block needs (every wave holds the
+    // same 16 columns, so this is uniform over the block)
+    int flags = 0;
+    if (UP) {
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-        tgt[cb] = -1;
-        par[cb] = -1;
-        cmask[cb] = 0;
-        cfirst[cb] = 0;
+        for (int oc = 0; oc < 8; ++oc)
+            if (__ballot((cmask >> oc) & 1)) flags |= 1 << oc;
+    } else {
+        flags = __ballot(tgt >= 0) ? 1 : 0;
+        if (!flags) return;
+    }
+    const float* col0 = tgt >= 0 ? psi_in + size_t(tgt) * NP : nullptr;
+    v4f acc[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int rb = wave + 4 * i;
+        acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+        if (rb < RB && col0 && !(UP && cmask)) {
+            for (int sp = 0; sp < (UP ? 1 : nsplit); ++sp) {
+                const float4 v = *reinterpret_cast<const float4*>(col0 + sp * split_stride + rb * 16 + g4);
+                acc[i] += v4f{v.x, v.y, v.z, v.w};
+            }
+        }
+    }
+    // gather: acc += T[op] src (T in fragment order [kc][rb][2][64])
+    const int nterm = UP ? __popc(flags) : (has_l2l ? 1 : 0);
+    int f = flags;
+    for (int t = 0; t < nterm; ++t) {
+        const int op = UP ? __builtin_ctz(f) : o;
+        f &= f - 1;
+        const float* src = nullptr;
         if (UP) {
-            const int idx = ((bid * WAVES + wave) * CB + cb) * 16 + (lane & 15);
-            if (idx < nb) {
-                tgt[cb] = b0 + idx;
-                if (!leafflag[tgt[cb]]) {
-                    const int2 ch = child[tgt[cb]];
-                    cfirst[cb] = ch.x;
-                    cmask[cb] = ch.y;
+            if ((cmask >> op) & 1) src = gsrc + size_t(cfirst + __popc(cmask & ((1 << op) - 1))) * NP;
+        } else if (par >= 0) {
+            src = gsrc + size_t(par) * NP;
+        }
+        const uint4* A = gops + size_t(op) * KC * RB * 128 + lane;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            float bv[8];
+            load8(bv, src ? src + kc * 32 + g8 : nullptr);
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int rb = wave + 4 * i;
+                if (rb < RB) {
+                    const uint4 u0 = A[(kc * RB + rb) * 128];
+                    const uint4 u1 = A[(kc * RB + rb) * 128 + 64];
+                    const float a[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
+                                        __uint_as_float(u0.w), __uint_as_float(u1.x), __uint_as_float(u1.y),
+                                        __uint_as_float(u1.z), __uint_as_float(u1.w)};
+                    v4f c = acc[i];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bv[k], c, 0, 0, 0);
+                    acc[i] = c;
                 }
             }
-        } else {
-            o = bid % 8;
-            const int slot = (((bid / 8) * WAVES + wave) * CB + cb) * 16 + (lane & 15);
-            if (slot < nl_count) {
-                const int Pb = nonleaf[nl_start + slot];
-                const int2 ch = child[Pb];
-                if ((ch.y >> o) & 1) {
-                    tgt[cb] = ch.x + __popc(ch.y & ((1 << o) - 1));
-                    par[cb] = Pb;
+        }
+    }
+    // chained factors: acc = V (W1 acc), the right factor read from LDS
+    auto chain = [&](const uint4* __restrict__ C) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+            if (wave + 4 * i < RB) xa[wave + 4 * i][lane] = acc[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int ob = wave + 4 * i;
+            if (ob < RB) {
+                v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
+                const uint4* Cr = C + size_t(ob) * RB * 64 + lane;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const uint4 u = Cr[rb * 64];
+                    const v4f T = xa[rb][lane];
+                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.x), T[0], cc, 0, 0, 0);
+                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.y), T[1], cc, 0, 0, 0);
+                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.z), T[2], cc, 0, 0, 0);
+                    cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.w), T[3], cc, 0, 0, 0);
                 }
+                acc[i] = cc;
             }
         }
-    }
-    // which gather terms the block needs
-    if (tid == 0) sflag = 0;
-    __syncthreads();
-    {
-        int f = 0;
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) f |= UP ? cmask[cb] : (tgt[cb] >= 0 ? 1 : 0);
-        if (f) atomicOr(&sflag, f);
-    }
-    __syncthreads();
-    const int flags = sflag;
-    if (!UP && !flags) return;   // block-uniform: no target in this tile
-    const int gterms = UP ? __popc(flags) : (has_l2l ? 1 : 0);
-    // initial check potential
-    v4f acc[CB][RB], tmp[CB][RB];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-        if (UP) {
-            load_acc<NP>(acc[cb], (tgt[cb] >= 0 && !cmask[cb]) ? psi_in + size_t(tgt[cb]) * NP : nullptr, lane);
-        } else {
-            load_acc<NP>(acc[cb], tgt[cb] >= 0 ? psi_in + size_t(tgt[cb]) * NP : nullptr, lane);
-            for (int sp = 1; sp < nsplit; ++sp) {
-                load_acc<NP>(tmp[cb], tgt[cb] >= 0 ? psi_in + sp * split_stride + size_t(tgt[cb]) * NP : nullptr,
-                             lane);
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) acc[cb][rb] += tmp[cb][rb];
-            }
-        }
-    }
-    const int nsteps = gterms * KC + 2 * RB;
-    // operator chunk and source column of a step
-    auto term_op = [&](int ti) -> int {
-        if (!UP) return o;
-        int f = flags;
-        for (int k = 0; k < ti; ++k) f &= f - 1;
-        return __builtin_ctz(f);
-    };
-    auto col_ptr = [&](int st, int cb) -> const float* {
-        const int op = term_op(st / KC);
-        int src = -1;
-        if (UP) {
-            if ((cmask[cb] >> op) & 1) src = cfirst[cb] + __popc(cmask[cb] & ((1 << op) - 1));
-        } else {
-            src = par[cb];
-        }
-        return src >= 0 ? gsrc + size_t(src) * NP + (st % KC) * 32 + g8 : nullptr;
-    };
-    const int ng = gterms * KC;
-    float breg[CB][8];
-    // start step st: its operator chunk by DMA into dst, its gathered columns into breg
-    auto issue = [&](int st, uint4* dst) {
-        if (st >= nsteps) return;
-        if (st < ng) {
-            dma_chunk<GW>(gops + (size_t(term_op(st / KC)) * KC + (st % KC)) * GW, dst, tid);
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) load8(breg[cb], col_ptr(st, cb));
-        } else {
-            const int c = st - ng;
-            dma_chunk<CW>((c < RB ? w1c : vc) + size_t(c % RB) * CW, dst, tid);
-        }
-    };
-    // wait until the chunk of the current step has landed in every wave
-    auto arrive = [&]() {
-        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     };
-    // one gather step: acc += (32 columns of the translation) * (gathered chunk)
-    auto gather_step = [&](int st, const uint4* L, uint4* other) {
-        arrive();
-        float cur[CB][8];
+    chain(w1c);
+    chain(vc);
+    if (tgt >= 0) {
+        float* dst = out + size_t(tgt) * NP;
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) cur[cb][i] = breg[cb][i];
-        issue(st + 1, other);
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            const uint4 u0 = L[rb * 128 + lane];
-            const uint4 u1 = L[rb * 128 + 64 + lane];
-            const float a[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
-                                __uint_as_float(u0.w), __uint_as_float(u1.x), __uint_as_float(u1.y),
-                                __uint_as_float(u1.z), __uint_as_float(u1.w)};
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                v4f c = acc[cb][rb];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], cur[cb][i], c, 0, 0, 0);
-                acc[cb][rb] = c;
-            }
+        for (int i = 0; i < NR; ++i) {
+            const int rb = wave + 4 * i;
+            if (rb < RB)
+                *reinterpret_cast<float4*>(dst + rb * 16 + g4) = make_float4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
         }
-    };
-    // the buffers alternate so that the chained steps always start in lds0
-    issue(0, (ng & 1) ? lds1 : lds0);
-    int st = 0;
-    if (ng & 1) gather_step(st++, lds1, lds0);
-    for (; st < ng; st += 2) {
-        gather_step(st, lds0, lds1);
-        gather_step(st + 1, lds1, lds0);
     }
-    // one output block of a chained factor: dst[ob] = sum_rb A[ob][rb] src[rb]
-    auto chain_block = [&](const uint4* L, v4f (&src)[CB][RB], int cb) -> v4f {
-        v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            const uint4 u = L[rb * 64 + lane];
-            const v4f T = src[cb][rb];
-            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.x), T[0], cc, 0, 0, 0);
-            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.y), T[1], cc, 0, 0, 0);
-            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.z), T[2], cc, 0, 0, 0);
-            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(u.w), T[3], cc, 0, 0, 0);
-        }
-        return cc;
-    };
-    // W1: tmp = W1 acc (RB is even, so output block ob uses lds0 for even ob)
-#pragma unroll
-    for (int ob = 0; ob < RB; ob += 2) {
-        arrive();
-        issue(ng + ob + 1, lds1);
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) tmp[cb][ob] = chain_block(lds0, acc, cb);
-        arrive();
-        issue(ng + ob + 2, lds0);
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) tmp[cb][ob + 1] = chain_block(lds1, acc, cb);
-    }
-    // V: acc = V tmp
-#pragma unroll
-    for (int ob = 0; ob < RB; ob += 2) {
-        arrive();
-        issue(ng + RB + ob + 1, lds1);
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[cb][ob] = chain_block(lds0, tmp, cb);
-        arrive();
-        issue(ng + RB + ob + 2, lds0);
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[cb][ob + 1] = chain_block(lds1, tmp, cb);
-    }
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) store_acc<NP>(acc[cb], tgt[cb] >= 0 ? out + size_t(tgt[cb]) * NP : nullptr, lane);
 }
 
 // ------------------------------------------------------------------ leaf evaluation: L2P + M2P
 // Forward: (u, E) per target.  Backward: from the forward densities E and H.v
 // (v = Ebar of the target), from the adjoint densities psi and E_psi.
-// One wave per target leaf; small leaves give each target S lanes (as in the
-// near field) that split the surface points and are summed by shuffles.
+// Small items give each target S lanes of a wave (as in the near field) that
+// split the surface points and are summed by shuffles.
 struct FarOut {
     float* u;      // forward: float4 [N] (u, Ex, Ey, Ez) sorted
     float* b;      // backward: float [10][N] (E1 xyz, HE xyz, psi, Epsi xyz) sorted
@@ -716,8 +664,9 @@ __device__ inline float far_sum(float v, int S) {
 }
 
 // Work item = (leaf, first target), up to 64 targets, launched heaviest first.
-// The sources (the leaf's own downward density from level 2, then its W-list
-// upward densities) are dealt to the four waves in turn; densities and the
+// The sources are the leaf's own downward density (from level 2) and its
+// W-list upward densities; the surface points of each source are dealt to the
+// four waves (and to the S lanes of a target inside a wave); densities and the
 // unit surfaces are read straight from L2.  Wave partial sums are added in a
 // fixed order.
 template <int NP, bool BWD>
@@ -746,7 +695,10 @@ __global__ __launch_bounds__(256) void k_far(const int2* __restrict__ items, int
     float v[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = 0.f;
-    for (int k = w; k < nsrc; k += 4) {
+    // every source's surface points are dealt to the S lanes of the target in
+    // each of the four waves (4 S slices), so all waves work on every source
+    const int sl = w * S + slice, nsl = 4 * S;
+    for (int k = 0; k < nsrc; ++k) {
         const bool own = self && k == 0;
         const int A = own ? b : widx[woff[b] + k - self];
         const float* D = (own ? phi_d : phi_u) + size_t(A) * NP;
@@ -757,7 +709,7 @@ __global__ __launch_bounds__(256) void k_far(const int2* __restrict__ items, int
         const float vx = eb.y * invw, vy = eb.z * invw, vz = eb.w * invw;   // Ebar in box units
         float su = 0, sx = 0, sy = 0, sz = 0, shx = 0, shy = 0, shz = 0, s2u = 0, s2x = 0, s2y = 0, s2z = 0;
 #pragma unroll 4
-        for (int e = slice; e < n; e += S) {
+        for (int e = sl; e < n; e += nsl) {
             const float4 sp = SF[e];
             const float dx = xx - sp.x, dy = xy - sp.y, dz = xz - sp.z;
             const float ri = rsq(dx * dx + dy * dy + dz * dz);
@@ -861,7 +813,6 @@ const VOps& vops_host() {
 
 constexpr int M2L_CB = 2;
 constexpr int M2L_SPLIT = kM2LSplit;
-constexpr int UD_CB = 1;      // column blocks per wave in the up/down translation kernels
 
 const VOps* vops_device() {
     static DBuf* d = nullptr;
@@ -945,8 +896,8 @@ void sweep_impl(kifmm_plan* P, int nrhs, hipStream_t s, bool rec) {
     for (int r = 0; r < nrhs; ++r)
         for (int l = depth; l >= 2; --l) {
             const int nb = int(P->lev[l].count);
-            const int blocks = nblk(nb, WAVES * UD_CB * 16);
-            hipLaunchKernelGGL((k_updown<NP, UD_CB, true>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks,
+            const int blocks = nblk(nb, 16);
+            hipLaunchKernelGGL((k_updown<NP, true>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks,
                                int(P->lev[l].start), nb, 0, 0, 0, P->nonleaf.as<int>(), P->bx_child.as<int2>(),
                                P->bx_leaf.as<int>(), P->psi_u.as<float>() + r * stride, 1, size_t(0),
                                P->phi_u.as<float>() + r * stride, P->phi_u.as<float>() + r * stride,
@@ -972,9 +923,9 @@ void sweep_impl(kifmm_plan* P, int nrhs, hipStream_t s, bool rec) {
     for (int r = 0; r < nrhs; ++r)
         for (int l = 2; l <= depth; ++l) {
             const LevelInfo& pl = P->lev[l - 1];
-            const int blocks = nblk(pl.nl_count, WAVES * UD_CB * 16) * 8;
+            const int blocks = nblk(pl.nl_count, 16) * 8;
             if (blocks == 0) continue;
-            hipLaunchKernelGGL((k_updown<NP, UD_CB, false>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, 0, 0,
+            hipLaunchKernelGGL((k_updown<NP, false>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, 0, 0,
                                int(pl.nl_start), int(pl.nl_count), l >= 3 ? 1 : 0, P->nonleaf.as<int>(),
                                P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->psi_m.as<float>() + r * stride,
                                P->m2l_split_used, 2 * stride, P->phi_d.as<float>() + r * stride,
