@@ -43,7 +43,7 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup):
     plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root,
                 profile=True)
     counts = plan.counts()
-    phases = []
+    phases, phases_adj = [], []
 
     def step(record):
         plan.rebuild(pos)
@@ -51,6 +51,8 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup):
         if record:
             phases.append(plan.phase_times())
         gq, gx = plan.backward(q, gu, gE)
+        if record:
+            phases_adj.append(plan.phase_times())
         return u, E, gq, gx
 
     for _ in range(warmup):
@@ -74,8 +76,9 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup):
     torch.cuda.synchronize()
     d = time.perf_counter()
     ph = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+    pha = {k: float(np.mean([p[k] for p in phases_adj])) for k in phases_adj[0]}
     res = dict(ms_per_step=1e3 * t, t_tree_ms=1e3 * (b - a), t_fwd_ms=1e3 * (c - b), t_adj_ms=1e3 * (d - c),
-               phases_fwd_ms=ph, counts=counts, outputs=[o.detach() for o in out])
+               phases_fwd_ms=ph, phases_adj_ms=pha, counts=counts, outputs=[o.detach() for o in out])
     plan.close()
     return res
 
@@ -282,7 +285,8 @@ def main():
         paths[prec] = run_path(Plan, w, pos, q, gu, gE, prec, args.steps, args.warmup)
         r = paths[prec]
         log(f"[bench] {prec}: {r['ms_per_step']:.3f} ms/step  tree {r['t_tree_ms']:.2f} fwd {r['t_fwd_ms']:.2f} "
-            f"adj {r['t_adj_ms']:.2f}  phases {json.dumps({k: round(v, 3) for k, v in r['phases_fwd_ms'].items()})}")
+            f"adj {r['t_adj_ms']:.2f}  phases {json.dumps({k: round(v, 3) for k, v in r['phases_fwd_ms'].items()})}"
+            f"  adjoint {json.dumps({k: round(v, 3) for k, v in r['phases_adj_ms'].items()})}")
     head = "split_bf16" if "split_bf16" in paths else next(iter(paths))
     H = paths[head]
     ops_n = H["counts"]["surface_points"]
@@ -312,7 +316,8 @@ def main():
         "roofline": roofline(H, ops_n, head),
         "paths": {k: {"particles_per_s": n / (v["ms_per_step"] * 1e-3), "ms_per_step": v["ms_per_step"],
                       "t_tree_ms": v["t_tree_ms"], "t_fwd_ms": v["t_fwd_ms"], "t_adj_ms": v["t_adj_ms"],
-                      "phases_fwd_ms": v["phases_fwd_ms"], "roofline": roofline(v, ops_n, k)}
+                      "phases_fwd_ms": v["phases_fwd_ms"], "phases_adj_ms": v["phases_adj_ms"],
+                      "roofline": roofline(v, ops_n, k)}
                   for k, v in paths.items()},
         "counts": H["counts"],
         "split_vs_fp32_rel_l2": agree,

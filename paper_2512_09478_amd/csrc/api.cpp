@@ -189,9 +189,9 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
         P->last_stream = s;
         begin_phases(P, s);
         launch_gather(P, charges, grad_potential, grad_field, true, s);
-        run_sweep(P, 2, s, false);
+        run_sweep(P, 2, s, true);
         run_far_eval(P, true, nullptr, s);
-        for (int k = 0; k < 6; ++k) record_phase(P, k, s);
+        record_phase(P, 5, s);
         launch_p2p_backward(P, grad_charges, grad_positions, s);
         record_phase(P, 6, s);
         P->has_phase = P->opt.profile ? 2 : 0;

@@ -573,37 +573,67 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
             }
         }
     }
-    // gather: acc += T[op] src (T in fragment order [kc][rb][2][64])
+    // gather: acc += T[op] src (T in fragment order [kc][rb][2][64]); the
+    // steps (term, 32-column chunk) run with the next step's fragments and
+    // source values already in flight
     const int nterm = UP ? __popc(flags) : (has_l2l ? 1 : 0);
-    int f = flags;
-    for (int t = 0; t < nterm; ++t) {
-        const int op = UP ? __builtin_ctz(f) : o;
-        f &= f - 1;
+    const int nst = nterm * KC;
+    auto step_src = [&](int st, const uint4*& A, const float*& b) {
+        const int t = st / KC, kc = st % KC;
+        int op = o;
+        if (UP) {
+            int f = flags;
+            for (int k = 0; k < t; ++k) f &= f - 1;
+            op = __builtin_ctz(f);
+        }
         const float* src = nullptr;
         if (UP) {
             if ((cmask >> op) & 1) src = gsrc + size_t(cfirst + __popc(cmask & ((1 << op) - 1))) * NP;
         } else if (par >= 0) {
             src = gsrc + size_t(par) * NP;
         }
-        const uint4* A = gops + size_t(op) * KC * RB * 128 + lane;
+        A = gops + (size_t(op) * KC + kc) * RB * 128 + lane;
+        b = src ? src + kc * 32 + g8 : nullptr;
+    };
+    uint4 an[NR][2];
+    float bn[8];
+    auto fetch = [&](int st) {
+        const uint4* A;
+        const float* b;
+        step_src(st, A, b);
+        load8(bn, b);
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            float bv[8];
-            load8(bv, src ? src + kc * 32 + g8 : nullptr);
+        for (int i = 0; i < NR; ++i) {
+            const int rb = wave + 4 * i;
+            if (rb < RB) {
+                an[i][0] = A[rb * 128];
+                an[i][1] = A[rb * 128 + 64];
+            }
+        }
+    };
+    if (nst > 0) fetch(0);
+    for (int st = 0; st < nst; ++st) {
+        uint4 ac[NR][2];
+        float bc[8];
 #pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                const int rb = wave + 4 * i;
-                if (rb < RB) {
-                    const uint4 u0 = A[(kc * RB + rb) * 128];
-                    const uint4 u1 = A[(kc * RB + rb) * 128 + 64];
-                    const float a[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
-                                        __uint_as_float(u0.w), __uint_as_float(u1.x), __uint_as_float(u1.y),
-                                        __uint_as_float(u1.z), __uint_as_float(u1.w)};
-                    v4f c = acc[i];
+        for (int i = 0; i < NR; ++i) {
+            ac[i][0] = an[i][0];
+            ac[i][1] = an[i][1];
+        }
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bv[k], c, 0, 0, 0);
-                    acc[i] = c;
-                }
+        for (int k = 0; k < 8; ++k) bc[k] = bn[k];
+        if (st + 1 < nst) fetch(st + 1);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (wave + 4 * i < RB) {
+                const float a[8] = {__uint_as_float(ac[i][0].x), __uint_as_float(ac[i][0].y),
+                                    __uint_as_float(ac[i][0].z), __uint_as_float(ac[i][0].w),
+                                    __uint_as_float(ac[i][1].x), __uint_as_float(ac[i][1].y),
+                                    __uint_as_float(ac[i][1].z), __uint_as_float(ac[i][1].w)};
+                v4f c = acc[i];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bc[k], c, 0, 0, 0);
+                acc[i] = c;
             }
         }
     }
@@ -665,73 +695,79 @@ __device__ inline float far_sum(float v, int S) {
 
 // Work item = (leaf, first target), up to 64 targets, launched heaviest first.
 // The sources are the leaf's own downward density (from level 2) and its
-// W-list upward densities; the surface points of each source are dealt to the
-// four waves (and to the S lanes of a target inside a wave); densities and the
-// unit surfaces are read straight from L2.  Wave partial sums are added in a
-// fixed order.
-template <int NP, bool BWD>
-__global__ __launch_bounds__(256) void k_far(const int2* __restrict__ items, int b2,
-                                             const int4* __restrict__ anchor, const int2* __restrict__ range,
-                                             const int* __restrict__ woff, const int* __restrict__ widx,
-                                             const float4* __restrict__ pts, const float4* __restrict__ src2,
-                                             const float* __restrict__ phi_d, const float* __restrict__ phi_u,
-                                             size_t rhs_stride, const float4* __restrict__ surf, int n,
-                                             BoxGeom geo, float cst, int64_t N, FarOut out) {
-    constexpr int NV = BWD ? 10 : 4;
-    __shared__ float red[4][NV][64];
-    const int2 it = items[blockIdx.x];
-    const int b = it.x;
-    const int nt = min(64, range[b].y - it.y);
-    const int S = far_lanes(nt);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// W-list upward densities.  Each source is staged in LDS as (surface point,
+// density) in box units, padded to NP entries with zero density at a real
+// surface point; its NP entries are dealt to the four waves and to the S
+// lanes of a target inside a wave (4 S slices, static trip count).  No
+// distance vanishes: the targets are inside the leaf, the downward surface
+// lies outside it and a W-list box is separated from the leaf by at least its
+// own width.  Wave partial sums are added in a fixed order.
+template <int NP, bool BWD, int S>
+__device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const int4* __restrict__ anchor,
+                                         const int* __restrict__ woff, const int* __restrict__ widx,
+                                         const float4* __restrict__ pts, const float4* __restrict__ src2,
+                                         const float* __restrict__ phi_d, const float* __restrict__ phi_u,
+                                         size_t rhs_stride, const float4* __restrict__ surf, int n,
+                                         const BoxGeom& geo, float cst, int64_t N, FarOut out, float4* stage,
+                                         float* stage2, float* red) {
+    constexpr int NV = BWD ? 10 : 4, NSL = 4 * S, ITER = NP / NSL;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, tid = threadIdx.x;
     const int slice = lane & (S - 1);
-    const int i = it.y + lane / S;
+    const int i = first + lane / S;
     const bool act = lane / S < nt;
     const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
     const float4 eb = (BWD && act) ? src2[i] : make_float4(0, 0, 0, 0);
     const int self = b >= b2 ? 1 : 0;
     const int nsrc = self + (woff[b + 1] - woff[b]);
+    const int sl = w * S + slice;
     // forward: u, E | backward: E1 xyz, H.Ebar xyz, psi, E_psi xyz
     float v[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = 0.f;
-    // every source's surface points are dealt to the S lanes of the target in
-    // each of the four waves (4 S slices), so all waves work on every source
-    const int sl = w * S + slice, nsl = 4 * S;
     for (int k = 0; k < nsrc; ++k) {
         const bool own = self && k == 0;
         const int A = own ? b : widx[woff[b] + k - self];
         const float* D = (own ? phi_d : phi_u) + size_t(A) * NP;
         const float4* SF = own ? surf + NP : surf;   // downward (2.95) or upward (1.05) equivalent surface
+        __syncthreads();   // the previous source is no longer read
+        for (int t = tid; t < NP; t += 256) {
+            const bool real = t < n;
+            const float4 sp = SF[real ? t : 0];
+            stage[t] = make_float4(sp.x, sp.y, sp.z, real ? D[t] : 0.f);
+            if (BWD) stage2[t] = real ? D[rhs_stride + t] : 0.f;
+        }
+        __syncthreads();
         float c[3], invw, wd;
         box_frame(geo, anchor[A], c, invw, wd);
         const float xx = (x.x - c[0]) * invw, xy = (x.y - c[1]) * invw, xz = (x.z - c[2]) * invw;
         const float vx = eb.y * invw, vy = eb.z * invw, vz = eb.w * invw;   // Ebar in box units
         float su = 0, sx = 0, sy = 0, sz = 0, shx = 0, shy = 0, shz = 0, s2u = 0, s2x = 0, s2y = 0, s2z = 0;
-#pragma unroll 4
-        for (int e = sl; e < n; e += nsl) {
-            const float4 sp = SF[e];
+#pragma unroll
+        for (int m = 0; m < ITER; ++m) {
+            const int e = sl + NSL * m;
+            const float4 sp = stage[e];
             const float dx = xx - sp.x, dy = xy - sp.y, dz = xz - sp.z;
-            const float ri = rsq(dx * dx + dy * dy + dz * dz);
-            const float ri3 = ri * ri * ri;
-            const float f = D[e];
-            const float g = f * ri3;
+            const float ri = __frsqrt_rn(dx * dx + dy * dy + dz * dz);
+            const float f = sp.w;
+            const float fr = f * ri;
+            const float ri2 = ri * ri;
+            const float g = fr * ri2;
             sx += g * dx;
             sy += g * dy;
             sz += g * dz;
             if (!BWD) {
-                su += f * ri;
+                su += fr;
             } else {
                 // H(r) v = 3 r (r.v) / r^5 - v / r^3
-                const float ri5 = ri3 * ri * ri;
                 const float rv = dx * vx + dy * vy + dz * vz;
-                const float h3 = 3.f * f * rv * ri5;
+                const float h3 = 3.f * g * rv * ri2;
                 shx += h3 * dx - g * vx;
                 shy += h3 * dy - g * vy;
                 shz += h3 * dz - g * vz;
-                const float f2 = D[rhs_stride + e];
-                const float g2 = f2 * ri3;
-                s2u += f2 * ri;
+                const float f2 = stage2[e];
+                const float fr2 = f2 * ri;
+                const float g2 = fr2 * ri2;
+                s2u += fr2;
                 s2x += g2 * dx;
                 s2y += g2 * dy;
                 s2z += g2 * dz;
@@ -761,12 +797,13 @@ __global__ __launch_bounds__(256) void k_far(const int2* __restrict__ items, int
     for (int q = 0; q < NV; ++q) v[q] = far_sum(v[q], S);
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NV; ++q) red[w][q][lane] = v[q];
+    for (int q = 0; q < NV; ++q) red[(w * NV + q) * 64 + lane] = v[q];
     __syncthreads();
     if (w == 0 && act && slice == 0) {
 #pragma unroll
         for (int q = 0; q < NV; ++q)
-            v[q] = cst * (((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane]);
+            v[q] = cst * (((red[q * 64 + lane] + red[(NV + q) * 64 + lane]) + red[(2 * NV + q) * 64 + lane]) +
+                          red[(3 * NV + q) * 64 + lane]);
         if (!BWD) {
             reinterpret_cast<float4*>(out.u)[i] = make_float4(v[0], v[1], v[2], v[3]);
         } else {
@@ -774,6 +811,33 @@ __global__ __launch_bounds__(256) void k_far(const int2* __restrict__ items, int
             for (int q = 0; q < 10; ++q) out.b[q * N + i] = v[q];
         }
     }
+}
+
+template <int NP, bool BWD>
+__global__ __launch_bounds__(256) void k_far(const int2* __restrict__ items, int b2,
+                                             const int4* __restrict__ anchor, const int2* __restrict__ range,
+                                             const int* __restrict__ woff, const int* __restrict__ widx,
+                                             const float4* __restrict__ pts, const float4* __restrict__ src2,
+                                             const float* __restrict__ phi_d, const float* __restrict__ phi_u,
+                                             size_t rhs_stride, const float4* __restrict__ surf, int n,
+                                             BoxGeom geo, float cst, int64_t N, FarOut out) {
+    constexpr int NV = BWD ? 10 : 4;
+    __shared__ float red[4 * NV * 64];
+    __shared__ float4 stage[NP];
+    __shared__ float stage2[BWD ? NP : 1];
+    const int2 it = items[blockIdx.x];
+    const int b = it.x;
+    const int nt = min(64, range[b].y - it.y);
+#define KIFMM_FAR_ITEM(SV)                                                                                        \
+    far_item<NP, BWD, SV>(b, it.y, nt, b2, anchor, woff, widx, pts, src2, phi_d, phi_u, rhs_stride, surf, n, geo, \
+                          cst, N, out, stage, stage2, red)
+    switch (far_lanes(nt)) {
+    case 8: KIFMM_FAR_ITEM(8); break;
+    case 4: KIFMM_FAR_ITEM(4); break;
+    case 2: KIFMM_FAR_ITEM(2); break;
+    default: KIFMM_FAR_ITEM(1); break;
+    }
+#undef KIFMM_FAR_ITEM
 }
 
 __global__ void k_fill0(float* __restrict__ p, size_t n) {
