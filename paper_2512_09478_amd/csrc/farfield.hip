@@ -347,7 +347,7 @@ __device__ inline void load8(float* b, const float* __restrict__ p) {
 // LDS tile shared by the four waves, while the next chunk and the next source
 // columns are already in flight.
 template <int NP, bool SPLIT, int CB>
-__global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, int nsplit, int nrhs,
+__global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntile, int nsplit, int nrhs,
                                              const int* __restrict__ nonleaf, const int2* __restrict__ child,
                                              const int* __restrict__ vdense, int b2, const VOps* __restrict__ vops,
                                              const float* __restrict__ phi_u, const float* __restrict__ psi_d,
@@ -414,20 +414,23 @@ __global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, 
         int kc = 0;
         float breg[CB][8];
         const float* col[CB];
+        // source index of each column at the slot after the current one, read
+        // one slot ahead so that a slot change never waits for it
+        int pre[CB];
+        auto read_pre = [&](int jj) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) pre[cb] = (vrow[cb] && jj < kVPerOct) ? vrow[cb][jj] : -1;
+        };
         // start chunk (jj, kk): operator words by DMA into dst, source columns into breg
         auto issue = [&](int jj, int kk, bool newslot, uint4* dst) {
-            // the source indices of a new slot are read before the DMA is issued,
-            // so that waiting for them does not wait for the operator chunk
             if (newslot) {
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    const int src = vrow[cb] ? vrow[cb][jj] : -1;
-                    col[cb] = src >= 0 ? bsrc[cb] + size_t(src) * NP : nullptr;
-                }
+                for (int cb = 0; cb < CB; ++cb) col[cb] = pre[cb] >= 0 ? bsrc[cb] + size_t(pre[cb]) * NP : nullptr;
             }
             dma_chunk<WORDS>(ops + (size_t(sop[jj]) * KC + kk) * WORDS, dst, tid);
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) load8(breg[cb], col[cb] ? col[cb] + kk * 32 + g8 : nullptr);
+            if (newslot) read_pre(next_slot(vmask, jj));
         };
         // one chunk: wait until it has landed (all waves), start the next one
         // into the other buffer, multiply
@@ -490,6 +493,7 @@ __global__ __launch_bounds__(256) void k_m2l(TaskTable tt, int nblk, int ntile, 
             kc = nkc;
             return j < kVPerOct;
         };
+        read_pre(j);
         issue(j, 0, true, lds0);
         // the two buffers alternate in a fixed order, so every LDS read names one buffer
         while (step(lds0, lds1) && step(lds1, lds0)) {
