@@ -132,10 +132,15 @@ int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float
  * kifmm_evaluate at the plan's positions with the tree frozen: given
  * grad_potential = dL/du and grad_field = dL/dE (either may be NULL = 0),
  * writes grad_charges = dL/dq [N] and grad_positions = dL/dx [N][3] (either
- * may be NULL).  Implemented as the transposed sweep: the forward densities
- * are recomputed, and a second sweep carries monopole (dL/du) and dipole
- * (dL/dE) sources; the plan's operators are symmetric, so the transposed
- * sweep reuses them.
+ * may be NULL).  Implemented as the transposed sweep: a sweep carries
+ * monopole (dL/du) and dipole (dL/dE) sources beside the forward densities;
+ * the plan's operators are symmetric, so the transposed sweep reuses them.
+ *   charges  device [N] float, caller order: the forward densities are
+ *            recomputed for these charges; or NULL: the charges and forward
+ *            densities of the last kifmm_evaluate (or kifmm_backward with
+ *            charges) on this handle are reused, which saves the forward
+ *            sweep.  NULL after setup, kifmm_rebuild or kifmm_set_precision
+ *            (before the next evaluation) is KIFMM_ERR_STATE.
  */
 int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_potential,
                    const float* grad_field, float* grad_charges, float* grad_positions,

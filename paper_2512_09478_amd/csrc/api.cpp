@@ -148,6 +148,7 @@ int kifmm_rebuild(kifmm_handle h, const double* positions, void* stream) {
         hipStream_t s = static_cast<hipStream_t>(stream);
         h->last_stream = s;
         h->B = 0;
+        h->fwd_valid = false;
         build_tree(h, positions, s);
         alloc_densities(h, s);
         KIFMM_HIP(hipStreamSynchronize(s));
@@ -159,6 +160,7 @@ int kifmm_set_precision(kifmm_handle h, int precision) {
         if (!h) throw Error(KIFMM_ERR_STATE, "null handle");
         if (precision != KIFMM_FP32 && precision != KIFMM_SPLIT_BF16) throw Error(KIFMM_ERR_ARG, "unknown precision");
         h->opt.precision = precision;
+        h->fwd_valid = false;
     });
 }
 
@@ -169,13 +171,15 @@ int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float
         hipStream_t s = static_cast<hipStream_t>(stream);
         P->last_stream = s;
         begin_phases(P, s);
+        P->fwd_valid = false;
         launch_gather(P, charges, nullptr, nullptr, false, s);
-        run_sweep(P, 1, s, true);
+        run_sweep(P, 0, 1, s, true);
         run_far_eval(P, false, nullptr, s);
         record_phase(P, 5, s);
         launch_p2p_forward(P, potential, field, s);
         record_phase(P, 6, s);
         P->has_phase = P->opt.profile ? 1 : 0;
+        P->fwd_valid = true;
         KIFMM_HIP(hipGetLastError());
     });
 }
@@ -184,12 +188,18 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
                    float* grad_charges, float* grad_positions, void* stream) {
     return guarded([&] {
         kifmm_plan* P = checked(h);
-        if (!charges) throw Error(KIFMM_ERR_ARG, "null charges");
+        if (!charges && !P->fwd_valid)
+            throw Error(KIFMM_ERR_STATE, "no forward evaluation to reuse (null charges after setup, rebuild or "
+                                         "a precision change)");
         hipStream_t s = static_cast<hipStream_t>(stream);
         P->last_stream = s;
         begin_phases(P, s);
+        // null charges: the charges, sorted points and densities of the last
+        // forward pass are still in place and only the adjoint sources are swept
+        if (charges) P->fwd_valid = false;
         launch_gather(P, charges, grad_potential, grad_field, true, s);
-        run_sweep(P, 2, s, true);
+        run_sweep(P, charges ? 0 : 1, 2, s, true);
+        P->fwd_valid = true;
         run_far_eval(P, true, nullptr, s);
         record_phase(P, 5, s);
         launch_p2p_backward(P, grad_charges, grad_positions, s);

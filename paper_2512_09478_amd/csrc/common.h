@@ -168,6 +168,7 @@ struct kifmm_plan {
     kifmm::PhaseEvents events;
     float phase_ms[8] = {};
     int has_phase = 0;
+    bool fwd_valid = false;   // densities of right-hand side 0 and pts hold the last forward pass
 };
 
 namespace kifmm {
@@ -175,7 +176,7 @@ namespace kifmm {
 // ---- tree.hip
 void build_tree(kifmm_plan* P, const double* positions, hipStream_t s);
 // ---- farfield.hip
-void run_sweep(kifmm_plan* P, int nrhs, hipStream_t s, bool record);
+void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record);
 void run_far_eval(kifmm_plan* P, bool backward, const float* ebar_sorted_unused, hipStream_t s);
 // ---- nearfield.hip
 void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const float* gfield,

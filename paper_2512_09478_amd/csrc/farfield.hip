@@ -936,11 +936,11 @@ void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
 #undef KIFMM_M2L_LAUNCH
 }
 
-// One sweep over the tree.  nrhs = 1: the charges (monopoles).  nrhs = 2:
-// right-hand side 0 = the charges, 1 = the adjoint sources (monopoles dL/du,
-// dipoles dL/dE); M2L then carries both columns through each operator load.
+// One sweep over the tree for the right-hand sides r0 .. r1-1: 0 = the
+// charges (monopoles), 1 = the adjoint sources (monopoles dL/du, dipoles
+// dL/dE).  With both, M2L carries the two columns through each operator load.
 template <int NP>
-void sweep_impl(kifmm_plan* P, int nrhs, hipStream_t s, bool rec) {
+void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec) {
     const Operators& op = *P->ops;
     const int B = int(P->B);
     const size_t stride = size_t(B) * NP;
@@ -955,13 +955,13 @@ void sweep_impl(kifmm_plan* P, int nrhs, hipStream_t s, bool rec) {
     const int b2 = int(P->lev[2].start);
     const int tpb = std::min(320, (NP + 63) / 64 * 64);
     // P2M
-    for (int r = 0; r < nrhs; ++r)
+    for (int r = r0; r < r1; ++r)
         hipLaunchKernelGGL(k_p2m<NP>, dim3(unsigned(P->nleaves)), dim3(tpb), 0, s, P->leaves.as<int>(),
                            int(P->nleaves), b2, P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), pts,
                            r ? P->src2.as<float4>() : nullptr, surf, op.n, geo, P->psi_u.as<float>() + r * stride);
     if (rec) record_phase(P, 0, s);
     // upward M2M + UC2E, deepest level first
-    for (int r = 0; r < nrhs; ++r)
+    for (int r = r0; r < r1; ++r)
         for (int l = depth; l >= 2; --l) {
             const int nb = int(P->lev[l].count);
             const int blocks = nblk(nb, 16);
@@ -973,7 +973,7 @@ void sweep_impl(kifmm_plan* P, int nrhs, hipStream_t s, bool rec) {
         }
     if (rec) record_phase(P, 1, s);
     // downward check potentials: zero, X list
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = r0; r < r1; ++r) {
         float* psi_d = P->psi_d.as<float>() + r * stride;
         size_t nz = size_t(B - b2) * NP;
         hipLaunchKernelGGL(k_fill0, dim3(unsigned((nz + 255) / 256)), dim3(256), 0, s, psi_d + size_t(b2) * NP, nz);
@@ -985,10 +985,14 @@ void sweep_impl(kifmm_plan* P, int nrhs, hipStream_t s, bool rec) {
     }
     if (rec) record_phase(P, 2, s);
     // V list
-    launch_m2l<NP>(P, nrhs, 0, s);
+    if (r1 - r0 == 2) {
+        launch_m2l<NP>(P, 2, 0, s);
+    } else {
+        for (int r = r0; r < r1; ++r) launch_m2l<NP>(P, 1, r, s);
+    }
     if (rec) record_phase(P, 3, s);
     // L2L + DC2E, coarse to fine
-    for (int r = 0; r < nrhs; ++r)
+    for (int r = r0; r < r1; ++r)
         for (int l = 2; l <= depth; ++l) {
             const LevelInfo& pl = P->lev[l - 1];
             const int blocks = nblk(pl.nl_count, 16) * 8;
@@ -1024,14 +1028,14 @@ void far_impl(kifmm_plan* P, bool bwd, hipStream_t s) {
 
 }  // namespace
 
-void run_sweep(kifmm_plan* P, int nrhs, hipStream_t s, bool record) {
+void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record) {
     switch (P->npad) {
-        case 32: sweep_impl<32>(P, nrhs, s, record); break;
-        case 64: sweep_impl<64>(P, nrhs, s, record); break;
-        case 128: sweep_impl<128>(P, nrhs, s, record); break;
-        case 160: sweep_impl<160>(P, nrhs, s, record); break;
-        case 224: sweep_impl<224>(P, nrhs, s, record); break;
-        case 320: sweep_impl<320>(P, nrhs, s, record); break;
+        case 32: sweep_impl<32>(P, r0, r1, s, record); break;
+        case 64: sweep_impl<64>(P, r0, r1, s, record); break;
+        case 128: sweep_impl<128>(P, r0, r1, s, record); break;
+        case 160: sweep_impl<160>(P, r0, r1, s, record); break;
+        case 224: sweep_impl<224>(P, r0, r1, s, record); break;
+        case 320: sweep_impl<320>(P, r0, r1, s, record); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }

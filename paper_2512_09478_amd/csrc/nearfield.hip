@@ -217,9 +217,11 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
 void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const float* gfield, bool adjoint,
                    hipStream_t s) {
     const int64_t N = P->N;
-    P->pts.ensure(size_t(N) * 16);
-    hipLaunchKernelGGL(k_gather, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, N, P->xs.as<float4>(),
-                       P->perm.as<int>(), charges, P->pts.as<float4>());
+    if (charges) {
+        P->pts.ensure(size_t(N) * 16);
+        hipLaunchKernelGGL(k_gather, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, N, P->xs.as<float4>(),
+                           P->perm.as<int>(), charges, P->pts.as<float4>());
+    }
     if (adjoint) {
         P->src2.ensure(size_t(N) * 16);
         hipLaunchKernelGGL(k_gather_adj, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, N, P->perm.as<int>(), gpot,

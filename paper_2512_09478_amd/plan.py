@@ -65,6 +65,10 @@ class Plan:
         check(L.kifmm_setup_ex(_ptr(self.positions), self.n, KERNELS[kernel], int(p), int(leaf_size),
                                ctypes.byref(opt), _stream(stream), ctypes.byref(h)))
         self._h = h
+        # changes whenever the forward state held by the library changes; None
+        # while there is no reusable forward pass
+        self._fwd_token = None
+        self._calls = 0
 
     # -- lifetime
     def close(self):
@@ -87,26 +91,42 @@ class Plan:
     # -- calls
     def rebuild(self, positions: torch.Tensor, stream=None):
         self.positions = _need(positions, torch.float64, (self.n, 3), "positions")
+        self._fwd_token = None
         check(_lib.lib().kifmm_rebuild(self.handle, _ptr(self.positions), _stream(stream)))
 
     def set_precision(self, precision: str):
+        self._fwd_token = None
         check(_lib.lib().kifmm_set_precision(self.handle, PRECISIONS[precision]))
+
+    def _new_forward_state(self):
+        self._calls += 1
+        self._fwd_token = self._calls
+        return self._fwd_token
 
     def evaluate(self, charges: torch.Tensor, potential=True, field=True, stream=None):
         q = _need(charges, torch.float32, (self.n,), "charges")
         u = torch.empty(self.n, dtype=torch.float32, device=q.device) if potential else None
         E = torch.empty((self.n, 3), dtype=torch.float32, device=q.device) if field else None
+        self._fwd_token = None
         check(_lib.lib().kifmm_evaluate(self.handle, _ptr(q), _ptr(u), _ptr(E), _stream(stream)))
+        self._new_forward_state()
         return u, E
 
     def backward(self, charges, grad_potential=None, grad_field=None, stream=None):
-        q = _need(charges, torch.float32, (self.n,), "charges")
+        """dL/dq, dL/dx.  ``charges=None`` reuses the charges and forward
+        densities of the last evaluate on this plan (no forward sweep)."""
+        q = None if charges is None else _need(charges, torch.float32, (self.n,), "charges")
         gu = None if grad_potential is None else _need(grad_potential, torch.float32, (self.n,), "grad_potential")
         gE = None if grad_field is None else _need(grad_field, torch.float32, (self.n, 3), "grad_field")
-        gq = torch.empty(self.n, dtype=torch.float32, device=q.device)
-        gx = torch.empty((self.n, 3), dtype=torch.float32, device=q.device)
+        dev = self.positions.device
+        gq = torch.empty(self.n, dtype=torch.float32, device=dev)
+        gx = torch.empty((self.n, 3), dtype=torch.float32, device=dev)
+        if q is not None:
+            self._fwd_token = None
         check(_lib.lib().kifmm_backward(self.handle, _ptr(q), _ptr(gu), _ptr(gE), _ptr(gq), _ptr(gx),
                                         _stream(stream)))
+        if q is not None:
+            self._new_forward_state()
         return gq, gx
 
     def clump_reduce(self, charges, field, offsets, centers, stream=None):
@@ -176,6 +196,7 @@ class KifmmFunction(torch.autograd.Function):
             raise ValueError("positions must be the tensor the plan was built from")
         u, E = plan.evaluate(charges)
         ctx.plan = plan
+        ctx.token = plan._fwd_token
         ctx.save_for_backward(charges)
         return u, E
 
@@ -184,7 +205,10 @@ class KifmmFunction(torch.autograd.Function):
         (charges,) = ctx.saved_tensors
         gu = None if gu is None else gu.contiguous().float()
         gE = None if gE is None else gE.contiguous().float()
-        gq, gx = ctx.plan.backward(charges, gu, gE)
+        # the library still holds this forward pass unless the plan has been
+        # used since; autograd forbids in-place changes of the saved charges
+        same = ctx.token is not None and ctx.plan._fwd_token == ctx.token
+        gq, gx = ctx.plan.backward(None if same else charges, gu, gE)
         return gq, gx.to(torch.float64), None
 
 

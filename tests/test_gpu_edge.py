@@ -192,6 +192,13 @@ def test_input_errors_leave_destroyable_handles():
     # the handle still works and is destroyable
     u2, E2 = G.evaluate(q)
     assert torch.equal(u, u2)
+    # an adjoint that reuses the forward pass needs one since the last rebuild
+    G.rebuild(torch.tensor(x, device="cuda"))
+    with pytest.raises(KifmmError) as ei:
+        G.backward(None, q, None)
+    assert ei.value.code == -5
+    G.evaluate(q)
+    G.backward(None, q, None)
     G.close()
     with pytest.raises(KifmmError):
         G.evaluate(q)

@@ -143,6 +143,14 @@ def test_backward_parity(built, precision):
     eq, ex = rel(gq.cpu().numpy(), qo), rel(gx.cpu().numpy(), xo)
     say(f"  rel-L2 qbar {eq:.3e}  xbar {ex:.3e}")
     assert eq <= TOL[precision] and ex <= TOL[precision]
+    # reusing the forward pass of evaluate (null charges) gives the same product
+    G.evaluate(q)
+    gq2, gx2 = G.backward(None, torch.tensor(ub, dtype=torch.float32, device="cuda"),
+                          torch.tensor(Eb, dtype=torch.float32, device="cuda"))
+    d = max(rel(gq2.cpu().numpy(), gq.cpu().numpy().astype(np.float64)),
+            rel(gx2.cpu().numpy(), gx.cpu().numpy().astype(np.float64)))
+    say(f"  reused forward pass: max rel difference {d:.3e}")
+    assert d <= 1e-6
 
 
 def test_clump_reduce_parity(built):
