@@ -57,7 +57,7 @@ void alloc_densities(kifmm_plan* P, hipStream_t s) {
         if (fresh) KIFMM_HIP(hipMemsetAsync(b->p, 0, b->cap, s));
     }
     P->psi_m.ensure(size_t(kM2LSplit) * bytes);
-    P->far.ensure(size_t(P->N) * 10 * 4);
+    P->far.ensure(size_t(P->N) * 16);
 }
 
 kifmm_plan* checked(kifmm_handle h) {

@@ -438,10 +438,15 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             float cur[CB][8];
+            // a column block none of whose targets has a source in this slot
+            // (a gap in the tree) skips its products; the test is wave-uniform
+            bool live[CB];
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
+            for (int cb = 0; cb < CB; ++cb) {
+                live[cb] = __ballot(col[cb] != nullptr) != 0;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) cur[cb][i] = breg[cb][i];
+            }
             int nkc = kc + 1, nj = j;
             if (nkc == KC) {
                 nkc = 0;
@@ -464,6 +469,7 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
                     const v8bf al = as_bf8(L[rb * 128 + 64 + lane]);
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
+                        if (!live[cb]) continue;
                         v4f c = acc[cb][rb];
                         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], c, 0, 0, 0);
                         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], c, 0, 0, 0);
@@ -481,6 +487,7 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
                                         __uint_as_float(u1.z), __uint_as_float(u1.w)};
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
+                        if (!live[cb]) continue;
                         v4f c = acc[cb][rb];
 #pragma unroll
                         for (int i = 0; i < 8; ++i)
@@ -681,13 +688,13 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
 }
 
 // ------------------------------------------------------------------ leaf evaluation: L2P + M2P
-// Forward: (u, E) per target.  Backward: from the forward densities E and H.v
-// (v = Ebar of the target), from the adjoint densities psi and E_psi.
+// Forward: (u, E) per target.  Backward: the far part of the adjoint
+// combination xbar = -ubar E - H Ebar - q E_psi and of qbar = psi, from the
+// forward (E, H) and adjoint (psi, E_psi) equivalent densities.
 // Small items give each target S lanes of a wave (as in the near field) that
 // split the surface points and are summed by shuffles.
 struct FarOut {
-    float* u;      // forward: float4 [N] (u, Ex, Ey, Ez) sorted
-    float* b;      // backward: float [10][N] (E1 xyz, HE xyz, psi, Epsi xyz) sorted
+    float* u;      // float4 [N] sorted: forward (u, Ex, Ey, Ez), backward (xbar xyz, psi)
 };
 
 __device__ inline int far_lanes(int nt) { return nt <= 8 ? 8 : nt <= 16 ? 4 : nt <= 32 ? 2 : 1; }
@@ -714,7 +721,7 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
                                          size_t rhs_stride, const float4* __restrict__ surf, int n,
                                          const BoxGeom& geo, float cst, int64_t N, FarOut out, float4* stage,
                                          float* stage2, float* red) {
-    constexpr int NV = BWD ? 10 : 4, NSL = 4 * S, ITER = NP / NSL;
+    constexpr int NV = 4, NSL = 4 * S, ITER = NP / NSL;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, tid = threadIdx.x;
     const int slice = lane & (S - 1);
     const int i = first + lane / S;
@@ -724,7 +731,7 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
     const int self = b >= b2 ? 1 : 0;
     const int nsrc = self + (woff[b + 1] - woff[b]);
     const int sl = w * S + slice;
-    // forward: u, E | backward: E1 xyz, H.Ebar xyz, psi, E_psi xyz
+    // forward: (u, E) | backward: (xbar, psi) of the adjoint combination
     float v[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = 0.f;
@@ -745,7 +752,12 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
         box_frame(geo, anchor[A], c, invw, wd);
         const float xx = (x.x - c[0]) * invw, xy = (x.y - c[1]) * invw, xz = (x.z - c[2]) * invw;
         const float vx = eb.y * invw, vy = eb.z * invw, vz = eb.w * invw;   // Ebar in box units
-        float su = 0, sx = 0, sy = 0, sz = 0, shx = 0, shy = 0, shz = 0, s2u = 0, s2x = 0, s2y = 0, s2z = 0;
+        const float uk = eb.x, qk = x.w;
+        // forward: su, (sx, sy, sz) = potential and field sums.  Backward, with
+        // f1 the forward and f2 the adjoint density: xbar = -ubar_k E1 - H Ebar_k
+        // - q_k E_psi summed as r [-(ubar_k f1 + q_k f2)/r^3 - 3 f1 (r.v)/r^5]
+        // + (f1/r^3) v, v = Ebar_k / w; psi = sum f2/r.
+        float su = 0, sx = 0, sy = 0, sz = 0, ss = 0;
 #pragma unroll
         for (int m = 0; m < ITER; ++m) {
             const int e = sl + NSL * m;
@@ -753,31 +765,27 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
             const float dx = xx - sp.x, dy = xy - sp.y, dz = xz - sp.z;
             const float ri = __frsqrt_rn(dx * dx + dy * dy + dz * dz);
             const float f = sp.w;
-            const float fr = f * ri;
             const float ri2 = ri * ri;
-            const float g = fr * ri2;
-            sx += g * dx;
-            sy += g * dy;
-            sz += g * dz;
             if (!BWD) {
+                const float fr = f * ri;
+                const float g = fr * ri2;
                 su += fr;
+                sx += g * dx;
+                sy += g * dy;
+                sz += g * dz;
             } else {
-                // H(r) v = 3 r (r.v) / r^5 - v / r^3
-                const float rv = dx * vx + dy * vy + dz * vz;
-                const float h3 = 3.f * g * rv * ri2;
-                shx += h3 * dx - g * vx;
-                shy += h3 * dy - g * vy;
-                shz += h3 * dz - g * vz;
                 const float f2 = stage2[e];
-                const float fr2 = f2 * ri;
-                const float g2 = fr2 * ri2;
-                s2u += fr2;
-                s2x += g2 * dx;
-                s2y += g2 * dy;
-                s2z += g2 * dz;
+                const float ri3 = ri2 * ri;
+                const float rv = dx * vx + dy * vy + dz * vz;
+                const float coef = -ri3 * (uk * f + qk * f2) - 3.f * f * rv * ri3 * ri2;
+                sx += coef * dx;
+                sy += coef * dy;
+                sz += coef * dz;
+                ss += f * ri3;
+                su += f2 * ri;
             }
         }
-        // true units: potential c/w, field c/w^2, Hessian c/w^3 (v already carries one 1/w)
+        // true units: potential c/w, field and position gradient c/w^2
         const float iw2 = invw * invw;
         if (!BWD) {
             v[0] += su * invw;
@@ -785,16 +793,10 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
             v[2] += sy * iw2;
             v[3] += sz * iw2;
         } else {
-            v[0] += sx * iw2;
-            v[1] += sy * iw2;
-            v[2] += sz * iw2;
-            v[3] += shx * iw2;
-            v[4] += shy * iw2;
-            v[5] += shz * iw2;
-            v[6] += s2u * invw;
-            v[7] += s2x * iw2;
-            v[8] += s2y * iw2;
-            v[9] += s2z * iw2;
+            v[0] += (sx + ss * vx) * iw2;
+            v[1] += (sy + ss * vy) * iw2;
+            v[2] += (sz + ss * vz) * iw2;
+            v[3] += su * invw;
         }
     }
 #pragma unroll
@@ -808,12 +810,7 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
         for (int q = 0; q < NV; ++q)
             v[q] = cst * (((red[q * 64 + lane] + red[(NV + q) * 64 + lane]) + red[(2 * NV + q) * 64 + lane]) +
                           red[(3 * NV + q) * 64 + lane]);
-        if (!BWD) {
-            reinterpret_cast<float4*>(out.u)[i] = make_float4(v[0], v[1], v[2], v[3]);
-        } else {
-#pragma unroll
-            for (int q = 0; q < 10; ++q) out.b[q * N + i] = v[q];
-        }
+        reinterpret_cast<float4*>(out.u)[i] = make_float4(v[0], v[1], v[2], v[3]);
     }
 }
 
@@ -825,7 +822,7 @@ __global__ __launch_bounds__(256) void k_far(const int2* __restrict__ items, int
                                              const float* __restrict__ phi_d, const float* __restrict__ phi_u,
                                              size_t rhs_stride, const float4* __restrict__ surf, int n,
                                              BoxGeom geo, float cst, int64_t N, FarOut out) {
-    constexpr int NV = BWD ? 10 : 4;
+    constexpr int NV = 4;
     __shared__ float red[4 * NV * 64];
     __shared__ float4 stage[NP];
     __shared__ float stage2[BWD ? NP : 1];
@@ -1012,7 +1009,7 @@ void far_impl(kifmm_plan* P, bool bwd, hipStream_t s) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
     const int b2 = P->depth >= 2 ? int(P->lev[2].start) : int(P->B);
-    FarOut fo{P->far.as<float>(), P->far.as<float>()};
+    FarOut fo{P->far.as<float>()};
     size_t stride = size_t(P->B) * NP;
     if (bwd)
         hipLaunchKernelGGL((k_far<NP, true>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(), b2,

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
                                                  float* __restrict__ gx) {
     __shared__ float4 sh[NF_STAGE];
     __shared__ float4 sh2[NF_STAGE];
-    __shared__ float red[4][10][64];
+    __shared__ float red[4][8][64];
     const int2 it = items[blockIdx.x];
     const int b = it.x;
     const int nt = min(64, range[b].y - it.y);
@@ -164,50 +164,49 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
     const bool act = lane / S < nt;
     const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
     const float4 a = act ? src2[i] : make_float4(0, 0, 0, 0);
-    // e1 xyz, H.Ebar xyz, psi, E_psi xyz
-    float v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // The adjoint combination xbar_k = -ubar_k E_k - H_k Ebar_k - q_k E_psi,k
+    // is summed pair by pair (r = x_k - y_j, c applied at the end):
+    //   xbar += r [-(ubar_k q_j + q_k ubar_j)/r^3 - 3 (q_j r.Ebar_k - q_k r.Ebar_j)/r^5]
+    //           + (q_j Ebar_k - q_k Ebar_j)/r^3,
+    // with the target's Ebar_k taken out of the sum: v = (X xyz, S, T xyz, psi)
+    // and xbar = X + S Ebar_k - q_k T;  qbar = psi = sum ubar_j/r - r.Ebar_j/r^3.
+    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const float uk = a.x, qk = x.w;
     stream_sources(uoff, uidx, range, b, pts, src2, sh, sh2, [&](int m) {
         for (int j = w * S + slice; j < m; j += 4 * S) {
             const float4 y = sh[j];
             const float4 bj = sh2[j];
             const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
             const float ri = rsq(dx * dx + dy * dy + dz * dz);
-            const float ri3 = ri * ri * ri;
-            const float ri5 = ri3 * ri * ri;
-            // field of q_j and H(r) Ebar_k
-            const float g = y.w * ri3;
-            v[0] += g * dx;
-            v[1] += g * dy;
-            v[2] += g * dz;
+            const float ri2 = ri * ri;
+            const float ri3 = ri2 * ri;
+            const float ri5 = ri3 * ri2;
             const float rk = dx * a.y + dy * a.z + dz * a.w;
-            const float h3 = 3.f * y.w * rk * ri5;
-            v[3] += h3 * dx - g * a.y;
-            v[4] += h3 * dy - g * a.z;
-            v[5] += h3 * dz - g * a.w;
-            // psi and E_psi of (ubar_j, Ebar_j):  psi = ubar K - Ebar.G,  E_psi = ubar G - H Ebar
             const float rj = dx * bj.y + dy * bj.z + dz * bj.w;
-            v[6] += bj.x * ri - rj * ri3;
-            const float gh = bj.x * ri3 - 3.f * rj * ri5;
-            v[7] += gh * dx + bj.y * ri3;
-            v[8] += gh * dy + bj.z * ri3;
-            v[9] += gh * dz + bj.w * ri3;
+            const float t1 = uk * y.w + qk * bj.x;
+            const float t2 = y.w * rk - qk * rj;
+            const float coef = -ri3 * t1 - 3.f * ri5 * t2;
+            v[0] += coef * dx;
+            v[1] += coef * dy;
+            v[2] += coef * dz;
+            v[3] += y.w * ri3;
+            v[4] += bj.y * ri3;
+            v[5] += bj.z * ri3;
+            v[6] += bj.w * ri3;
+            v[7] += bj.x * ri - rj * ri3;
         }
     });
 #pragma unroll
-    for (int q = 0; q < 10; ++q) v[q] = lane_sum(v[q], S);
-    wave_reduce<10>(v, red);
+    for (int q = 0; q < 8; ++q) v[q] = lane_sum(v[q], S);
+    wave_reduce<8>(v, red);
     if (w == 0 && act && slice == 0) {
-        const float E1x = far[0 * N + i] + cst * v[0], E1y = far[1 * N + i] + cst * v[1],
-                    E1z = far[2 * N + i] + cst * v[2];
-        const float Hx = far[3 * N + i] + cst * v[3], Hy = far[4 * N + i] + cst * v[4], Hz = far[5 * N + i] + cst * v[5];
-        const float Ps = far[6 * N + i] + cst * v[6];
-        const float Px = far[7 * N + i] + cst * v[7], Py = far[8 * N + i] + cst * v[8], Pz = far[9 * N + i] + cst * v[9];
+        const float4 f = reinterpret_cast<const float4*>(far)[i];   // far part: xbar xyz, psi
         const int j = perm[i];
-        if (gq) gq[j] = Ps;
+        if (gq) gq[j] = f.w + cst * v[7];
         if (gx) {
-            gx[3 * size_t(j)] = -a.x * E1x - Hx - x.w * Px;
-            gx[3 * size_t(j) + 1] = -a.x * E1y - Hy - x.w * Py;
-            gx[3 * size_t(j) + 2] = -a.x * E1z - Hz - x.w * Pz;
+            gx[3 * size_t(j)] = f.x + cst * (v[0] + v[3] * a.y - qk * v[4]);
+            gx[3 * size_t(j) + 1] = f.y + cst * (v[1] + v[3] * a.z - qk * v[5]);
+            gx[3 * size_t(j) + 2] = f.z + cst * (v[2] + v[3] * a.w - qk * v[6]);
         }
     }
 }
