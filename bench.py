@@ -222,8 +222,9 @@ def summarize_traffic(fetch_csv, write_csv, out, cmd_fetch, cmd_write, precision
         fb = fe[k] * f_fac * 1024
         wb = wr[k] * w_fac * 1024
         lines.append(f"| `{k[0]}` | {k[1]} | {fe[k]:.0f} | {wr[k]:.0f} | {fb / 1e6:.1f} | {wb / 1e6:.1f} |")
+        base = k[0].split("<")[0].split()[-1]
         for kern in KERNEL_SOURCE:
-            if k[0].endswith(kern) and not any(r["kernel"] == kern for r in recs):
+            if base == kern and not any(r["kernel"] == kern for r in recs):
                 # the first (largest-fetch) entry of a kernel is its forward launch
                 recs.append(dict(kernel=kern, precision=precision, grid=k[1], bytes_per_launch=fb + wb,
                                  fetch_bytes=fb, write_bytes=wb, source_sha256_16=source_digest(kern)))
