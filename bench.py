@@ -5,6 +5,8 @@ Laplace workload (60 % uniform + 40 % in 20 Gaussian clusters, p = 6, leaf 128,
 adaptive octree): re-tree at the positions (keys, sort, octree, lists), the
 forward evaluation (u, E) and the adjoint (dL/dq, dL/dx for given dL/du,
 dL/dE).  Inputs are resident in HBM before the timed region starts.
+``--workload k`` measures the other generators the same way (the clump
+workload adds the per-clump force and torque to the step).
 
 Prints one JSON line.  The headline path is the split-bf16 M2L (all else
 FP32); the plain FP32 path is measured beside it.  The roofline object is for
@@ -38,16 +40,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+WORKLOADS = {
+    1: "uniform Laplace charges in the unit cube, q ~ U[-1,1], p=4, leaf 64, uniform octree",
+    2: "clustered Laplace charges (60% uniform + 40% in 20 Gaussian clusters sigma=0.02, N(0,1) charges "
+       "mean removed), p=6, leaf 128, adaptive octree",
+    3: "rigid clumps of 8 pebbles (cube corners, edge 0.6R, lognormal R, 30% packing), N(0,1) pebble charges, "
+       "p=6, leaf 128, adaptive octree, per-clump force and torque",
+    4: "uniform Laplace charges in the unit cube, q ~ N(0,1), p=6, leaf 128, adaptive octree",
+    5: "Plummer sphere (a=0.1, r<=10a) of unit masses, gravity, p=8, leaf 256, adaptive octree depth<=12",
+}
+CPU_SAMPLE = {1: 4096, 2: 131072, 3: 131072, 4: 131072, 5: 65536}
+
+
 def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup):
     import torch
     plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root,
                 profile=True)
     counts = plan.counts()
     phases, phases_adj = [], []
+    clumps = None
+    if w.clump_offsets is not None:
+        clumps = (torch.tensor(w.clump_offsets, device="cuda"), torch.tensor(w.clump_centers, device="cuda"))
 
     def step(record):
         plan.rebuild(pos)
         u, E = plan.evaluate(q)
+        if clumps is not None:
+            plan.clump_reduce(q, E, *clumps)
         if record:
             phases.append(plan.phase_times())
         gq, gx = plan.backward(None, gu, gE)   # adjoint of the evaluation just made
@@ -124,12 +143,12 @@ def roofline(res, n, precision):
                 work=f"20 x {c['p2p_pairs']} pairs")
 
 
-def cpu_baseline(seconds_target=20.0):
+def cpu_baseline(k):
     """FP64 oracle forward + adjoint on a bounded sample of the same workload."""
     import workloads
     from oracle import kifmm
-    n = 131072
-    w = workloads.make(2, n=n)
+    w = workloads.make(k, n=CPU_SAMPLE[k])
+    n = w.n
     rng = np.random.default_rng(5)
     ub = rng.standard_normal(n)
     Eb = rng.standard_normal((n, 3))
@@ -141,7 +160,7 @@ def cpu_baseline(seconds_target=20.0):
     threads = os.environ.get("OMP_NUM_THREADS")
     cores = int(threads) if threads else (os.cpu_count() or 1)
     return dict(value=n / t, unit="particles/s", cores=cores, kind="oracle",
-                sample=f"clustered workload generator at N={n} (same p, leaf, tree rules): "
+                sample=f"the same workload generator at N={n} (same p, leaf, tree rules): "
                        f"tree+lists+forward+adjoint in FP64, {t:.1f} s")
 
 
@@ -251,6 +270,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="override the number of charges")
+    ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOADS),
+                    help="workload generator (2 = the clustered 1M headline)")
     ap.add_argument("--paths", default="split_bf16,fp32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counter-run", metavar="PRECISION", help="short run for rocprofv3 counter passes")
@@ -273,7 +294,7 @@ def main():
     import torch
     import workloads
     from paper_2512_09478_amd import Plan
-    w = workloads.make(2, n=args.n)
+    w = workloads.make(args.workload, n=args.n)
     n = w.n
     pos = torch.tensor(w.positions, dtype=torch.float64, device="cuda")
     q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
@@ -310,10 +331,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (M2L bf16x3 split, FP32 accumulate)" if head == "split_bf16" else "f32",
         "data": "synthetic",
-        "config": {"workload": "clustered Laplace charges (60% uniform + 40% in 20 Gaussian clusters "
-                               "sigma=0.02, N(0,1) charges mean removed), p=6, leaf 128, adaptive octree; "
-                               "step = re-tree + forward + adjoint",
-                   "n": n, "p": w.p, "leaf_size": w.leaf_size, "path": head},
+        "config": {"workload": WORKLOADS[args.workload] + "; step = re-tree + forward + adjoint",
+                   "name": w.name, "n": n, "p": w.p, "leaf_size": w.leaf_size, "path": head},
         "roofline": roofline(H, ops_n, head),
         "paths": {k: {"particles_per_s": n / (v["ms_per_step"] * 1e-3), "ms_per_step": v["ms_per_step"],
                       "t_tree_ms": v["t_tree_ms"], "t_fwd_ms": v["t_fwd_ms"], "t_adj_ms": v["t_adj_ms"],
@@ -325,7 +344,7 @@ def main():
     }
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     for v in paths.values():
         v.pop("outputs", None)
     print(json.dumps(out), flush=True)

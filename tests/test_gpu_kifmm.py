@@ -19,11 +19,11 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
 # the Plummer/gravity workload at p = 8 is specified at 1e-4 for both paths
-TOL_CFG = {5: {"fp32": 1e-4, "split_bf16": 1e-4}}
+TOL_WORKLOAD = {5: {"fp32": 1e-4, "split_bf16": 1e-4}}
 
 
-def tol(cfg, precision):
-    return TOL_CFG.get(cfg, TOL)[precision]
+def tol(k, precision):
+    return TOL_WORKLOAD.get(k, TOL)[precision]
 
 
 def rel(a, b):
@@ -46,7 +46,7 @@ def oracle_plan(w, leaf=None, p=None):
     return kifmm.plan(w.positions, w.kernel, p or w.p, leaf or w.leaf_size, w.adaptive, w.max_depth, w.root)
 
 
-# (cfg, n, leaf, p): shapes of the five workloads at sizes the oracle runs in seconds;
+# (k, n, leaf, p): shapes of the five workloads at sizes the oracle runs in seconds;
 # every case spans several levels, has partially filled (ragged) leaves, and the
 # adaptive ones have non-empty W and X lists.
 CASES = [
@@ -64,10 +64,10 @@ def built():
     return k
 
 
-@pytest.mark.parametrize("cfg,n,leaf,p", CASES)
-def test_tree_and_lists_bit_exact(built, cfg, n, leaf, p):
-    say(f"tree parity cfg{cfg} n={n} leaf={leaf}")
-    w = workloads.make(cfg, n=n)
+@pytest.mark.parametrize("k,n,leaf,p", CASES)
+def test_tree_and_lists_bit_exact(built, k, n, leaf, p):
+    say(f"tree parity workload {k} n={n} leaf={leaf}")
+    w = workloads.make(k, n=n)
     G = gpu_plan(w, leaf, p=p)
     t = G.tree()
     O = oracle_plan(w, leaf, p)
@@ -92,10 +92,10 @@ def test_tree_and_lists_bit_exact(built, cfg, n, leaf, p):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
-@pytest.mark.parametrize("cfg,n,leaf,p", CASES)
-def test_forward_parity(built, cfg, n, leaf, p, precision):
-    say(f"forward parity cfg{cfg} n={n} leaf={leaf} p={p} {precision}")
-    w = workloads.make(cfg, n=n)
+@pytest.mark.parametrize("k,n,leaf,p", CASES)
+def test_forward_parity(built, k, n, leaf, p, precision):
+    say(f"forward parity workload {k} n={n} leaf={leaf} p={p} {precision}")
+    w = workloads.make(k, n=n)
     G = gpu_plan(w, leaf, precision, p=p)
     q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
     u, E = G.evaluate(q)
@@ -104,7 +104,7 @@ def test_forward_parity(built, cfg, n, leaf, p, precision):
     uo, Eo = kifmm.forward(O, w.charges)
     eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
     say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
-    assert eu <= tol(cfg, precision) and eE <= tol(cfg, precision)
+    assert eu <= tol(k, precision) and eE <= tol(k, precision)
 
 
 def test_single_leaf_is_direct_sum(built):

@@ -84,7 +84,7 @@ def test_error_decays_with_order():
     assert errs[-1] < 2e-5
 
 
-def test_cfg1_accuracy_p4():
+def test_uniform_4096_accuracy_p4():
     w = workloads.make(1)
     P = kifmm.plan(w.positions, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, w.root)
     u, E = kifmm.forward(P, w.charges)

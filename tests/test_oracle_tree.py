@@ -54,9 +54,9 @@ def test_sort_is_stable_by_key_then_index():
     np.testing.assert_array_equal(t.perm, ref)
 
 
-@pytest.mark.parametrize("cfg,n,leaf", [(1, 4096, 64), (2, 20000, 64), (5, 20000, 32)])
-def test_tree_invariants(cfg, n, leaf):
-    w = workloads.make(cfg, n=n)
+@pytest.mark.parametrize("k,n,leaf", [(1, 4096, 64), (2, 20000, 64), (5, 20000, 32)])
+def test_tree_invariants(k, n, leaf):
+    w = workloads.make(k, n=n)
     t = T.build_tree(w.positions, leaf, w.adaptive, w.max_depth, w.root)
     # every point in exactly one leaf
     cover = np.zeros(n, dtype=int)
@@ -80,7 +80,7 @@ def test_tree_invariants(cfg, n, leaf):
         assert np.all(k == t.anchor[b])
 
 
-def test_uniform_cfg1_shape():
+def test_uniform_4096_shape():
     w = workloads.make(1)
     t = T.build_tree(w.positions, w.leaf_size, w.adaptive, w.max_depth, w.root)
     assert t.nboxes == 73 and t.is_leaf.sum() == 64 and t.depth == 2
@@ -126,9 +126,9 @@ def _coverage(t, L):
     return cnt
 
 
-@pytest.mark.parametrize("cfg,n,leaf", [(1, 4096, 64), (2, 6000, 32), (5, 6000, 16)])
-def test_lists_cover_every_pair_exactly_once(cfg, n, leaf):
-    w = workloads.make(cfg, n=n)
+@pytest.mark.parametrize("k,n,leaf", [(1, 4096, 64), (2, 6000, 32), (5, 6000, 16)])
+def test_lists_cover_every_pair_exactly_once(k, n, leaf):
+    w = workloads.make(k, n=n)
     t = T.build_tree(w.positions, leaf, w.adaptive, w.max_depth, w.root)
     L = T.build_lists(t)
     cnt = _coverage(t, L)
@@ -155,7 +155,7 @@ def test_list_definitions_by_brute_force():
             assert not T.adjacent(t, A, B) and T.adjacent(t, A, int(t.parent[B]))
 
 
-def test_cfg1_list_counts_closed_form():
+def test_uniform_4096_list_counts_closed_form():
     # uniform depth 2: 64 leaves; adjacent pairs = (sum over a 4-cell axis of 3,2,2,3... ) ^3
     # per axis: cells 0..3 have 2,3,3,2 neighbours incl. self -> 10; 10^3 = 1000 U pairs;
     # every other ordered pair is a V pair: 64^2 - 1000 = 3096.

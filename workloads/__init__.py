@@ -12,16 +12,16 @@ The five workloads stand in for the paper's application examples (Section 3:
 charged particles in a box, dipole clumps, clumped platelets, gravitational
 collapse); the paper uses no public dataset.
 
-  cfg1  Laplace, uniform unit cube, charges U[-1,1], p=4, leaf 64, uniform tree
-  cfg2  Laplace, 60 % uniform + 40 % in 20 Gaussian clusters (sigma 0.02),
+  1  Laplace, uniform unit cube, charges U[-1,1], p=4, leaf 64, uniform tree
+  2  Laplace, 60 % uniform + 40 % in 20 Gaussian clusters (sigma 0.02),
         charges N(0,1) with the mean removed, p=6, leaf 128, adaptive tree
-  cfg3  rigid clumps of 8 pebbles on the corners of a cube of edge 0.6 R,
+  3  rigid clumps of 8 pebbles on the corners of a cube of edge 0.6 R,
         R lognormal(ln 0.003, 0.3) rescaled to 30 % bounding-sphere volume
         fraction, random rotations, random sequential addition packing,
         pebble charges N(0,1), p=6, leaf 128, adaptive tree
-  cfg4  Laplace, uniform unit cube, charges N(0,1), p=6, leaf 128, adaptive;
+  4  Laplace, uniform unit cube, charges N(0,1), p=6, leaf 128, adaptive;
         adjoint loss target built from charges + 0.1 N(0,1)
-  cfg5  gravity, Plummer sphere (a = 0.1, truncated at r = 10 a), unit
+  5  gravity, Plummer sphere (a = 0.1, truncated at r = 10 a), unit
         masses, p=8, leaf 256, adaptive tree, depth <= 12, root [-1,1)^3
 """
 from __future__ import annotations
@@ -63,8 +63,8 @@ def round_f32(a: np.ndarray) -> np.ndarray:
     return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
 
 
-def _rng(cfg: int, seed: Optional[int]) -> np.random.Generator:
-    return np.random.default_rng(SEED_BASE + cfg if seed is None else seed)
+def _rng(k: int, seed: Optional[int]) -> np.random.Generator:
+    return np.random.default_rng(SEED_BASE + k if seed is None else seed)
 
 
 def uniform_cube(rng: np.random.Generator, n: int) -> np.ndarray:
@@ -229,35 +229,35 @@ def adjoint_target_charges(charges: np.ndarray, seed: int) -> np.ndarray:
     return round_f32(charges + 0.1 * rng.standard_normal(charges.shape[0]))
 
 
-def make(cfg: int, n: Optional[int] = None, seed: Optional[int] = None) -> Workload:
-    """Build workload ``cfg`` (1..5) with ``n`` points (default: the full size)."""
-    rng = _rng(cfg, seed)
-    N = FULL_N[cfg] if n is None else int(n)
-    if cfg == 1:
+def make(k: int, n: Optional[int] = None, seed: Optional[int] = None) -> Workload:
+    """Build workload ``k`` (1..5) with ``n`` points (default: the full size)."""
+    rng = _rng(k, seed)
+    N = FULL_N[k] if n is None else int(n)
+    if k == 1:
         x = uniform_cube(rng, N)
         q = round_f32(rng.uniform(-1.0, 1.0, N))
-        return Workload("cfg1_uniform_p4", x, q, "laplace", 4, 64, False, 21,
+        return Workload("uniform_4096_p4", x, q, "laplace", 4, 64, False, 21,
                         ((0.0, 0.0, 0.0), 1.0))
-    if cfg == 2:
+    if k == 2:
         x = clustered(rng, N)
         q = rng.standard_normal(N)
         q = round_f32(q - q.mean())
-        return Workload("cfg2_clustered_p6", x, q, "laplace", 6, 128, True, 21,
+        return Workload("clustered_1M_p6", x, q, "laplace", 6, 128, True, 21,
                         ((0.0, 0.0, 0.0), 1.0))
-    if cfg == 3:
+    if k == 3:
         C = max(1, N // 8)
         x, off, cen = clumps(rng, C)
         q = round_f32(rng.standard_normal(x.shape[0]))
-        return Workload("cfg3_clumps_p6", x, q, "laplace", 6, 128, True, 21,
+        return Workload("clumps_200k_p6", x, q, "laplace", 6, 128, True, 21,
                         ((0.0, 0.0, 0.0), 1.0), off, cen)
-    if cfg == 4:
+    if k == 4:
         x = uniform_cube(rng, N)
         q = round_f32(rng.standard_normal(N))
-        return Workload("cfg4_uniform_p6", x, q, "laplace", 6, 128, True, 21,
+        return Workload("uniform_524k_p6", x, q, "laplace", 6, 128, True, 21,
                         ((0.0, 0.0, 0.0), 1.0))
-    if cfg == 5:
+    if k == 5:
         x = plummer(rng, N)
         q = np.ones(N)
-        return Workload("cfg5_plummer_p8", x, q, "gravity", 8, 256, True, 12,
+        return Workload("plummer_8M_p8", x, q, "gravity", 8, 256, True, 12,
                         ((-1.0, -1.0, -1.0), 2.0))
-    raise ValueError(f"unknown workload {cfg}")
+    raise ValueError(f"unknown workload {k}")
