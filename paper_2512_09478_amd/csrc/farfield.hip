@@ -186,37 +186,42 @@ __device__ inline void c2e_apply(v4f* acc, const float* __restrict__ W1, const f
 
 // ------------------------------------------------------------------ P2M / P2L
 // Check potential of leaf points on a surface of box `b` (normalised):
-// psi[i] = sum_j q_j K1(s_i - x'_j) - (1/w) Ebar_j . G1(s_i - x'_j)   (dipole part optional)
+// psi[i] = sum_j q_j K1(s_i - x'_j) - (1/w) Ebar_j . G1(s_i - x'_j)   (dipole part optional).
+// A block has 2 NP threads: thread (slice, i) takes check point i and every
+// other staged source point; the two slices are added in a fixed order.  No
+// distance vanishes: the points of a leaf lie inside the upward check surface
+// of their box, and an X-list leaf is separated from the downward check
+// surface of its target box.
 template <int NP>
 __device__ void points_to_surface(float& acc, const float4* __restrict__ pts, const float4* __restrict__ src2,
-                                  int j0, int j1, const float c[3], float invw, float4 s, bool active,
+                                  int j0, int j1, const float c[3], float invw, float4 s, bool active, int slice,
                                   float4* sh, float4* sh2) {
     for (int base = j0; base < j1; base += 256) {
-        int m = min(256, j1 - base);
+        const int m = min(256, j1 - base);
         __syncthreads();
         for (int k = threadIdx.x; k < m; k += blockDim.x) {
-            float4 p = pts[base + k];
+            const float4 p = pts[base + k];
             sh[k] = make_float4((p.x - c[0]) * invw, (p.y - c[1]) * invw, (p.z - c[2]) * invw, p.w);
             if (src2) {
-                float4 a = src2[base + k];
+                const float4 a = src2[base + k];
                 sh2[k] = make_float4(a.x, a.y * invw, a.z * invw, a.w * invw);
             }
         }
         __syncthreads();
         if (active) {
             if (!src2) {
-                for (int k = 0; k < m; ++k) {
-                    float4 p = sh[k];
-                    float dx = s.x - p.x, dy = s.y - p.y, dz = s.z - p.z;
-                    acc += p.w * rsq(dx * dx + dy * dy + dz * dz);
+                for (int k = slice; k < m; k += 2) {
+                    const float4 p = sh[k];
+                    const float dx = s.x - p.x, dy = s.y - p.y, dz = s.z - p.z;
+                    acc += p.w * __frsqrt_rn(dx * dx + dy * dy + dz * dz);
                 }
             } else {
-                for (int k = 0; k < m; ++k) {
-                    float4 p = sh[k];
-                    float4 a = sh2[k];
-                    float dx = s.x - p.x, dy = s.y - p.y, dz = s.z - p.z;
-                    float ri = rsq(dx * dx + dy * dy + dz * dz);
-                    float ri3 = ri * ri * ri;
+                for (int k = slice; k < m; k += 2) {
+                    const float4 p = sh[k];
+                    const float4 a = sh2[k];
+                    const float dx = s.x - p.x, dy = s.y - p.y, dz = s.z - p.z;
+                    const float ri = __frsqrt_rn(dx * dx + dy * dy + dz * dz);
+                    const float ri3 = ri * ri * ri;
                     acc += a.x * ri - (a.y * dx + a.z * dy + a.w * dz) * ri3;
                 }
             }
@@ -224,51 +229,62 @@ __device__ void points_to_surface(float& acc, const float4* __restrict__ pts, co
     }
 }
 
+// slice 1 hands its partial sum to slice 0 (fixed order), which returns the total
 template <int NP>
-__global__ void k_p2m(const int* __restrict__ leaves, int nleaves, int b2, const int4* __restrict__ anchor,
-                      const int2* __restrict__ range, const float4* __restrict__ pts,
-                      const float4* __restrict__ src2, const float4* __restrict__ surf, int n, BoxGeom geo,
-                      float* __restrict__ psi_u) {
-    __shared__ float4 sh[256];
-    __shared__ float4 sh2[256];
-    int b = leaves[blockIdx.x];
-    if (b < b2) return;   // leaves above level 2 have no far field
-    int4 a = anchor[b];
-    float c[3], invw, w;
-    box_frame(geo, a, c, invw, w);
-    int2 r = range[b];
-    for (int i0 = 0; i0 < NP; i0 += blockDim.x) {
-        int i = i0 + threadIdx.x;
-        bool act = i < n;
-        float4 s = act ? surf[NP + i] : make_float4(0, 0, 0, 0);   // upward check surface
-        float acc = 0.f;
-        points_to_surface<NP>(acc, pts, src2, r.x, r.y, c, invw, s, act, sh, sh2);
-        if (i < NP) psi_u[size_t(b) * NP + i] = act ? acc : 0.f;
-    }
+__device__ inline float add_slices(float acc, int i, int slice, float* red) {
+    __syncthreads();
+    if (slice == 1) red[i] = acc;
+    __syncthreads();
+    return slice == 0 ? acc + red[i] : 0.f;
 }
 
 template <int NP>
-__global__ void k_p2l(const int* __restrict__ xboxes, const int* __restrict__ xoff, const int* __restrict__ xidx,
-                      const int4* __restrict__ anchor, const int2* __restrict__ range,
-                      const float4* __restrict__ pts, const float4* __restrict__ src2,
-                      const float4* __restrict__ surf, int n, BoxGeom geo, float* __restrict__ psi_d) {
+__global__ __launch_bounds__(2 * NP) void k_p2m(const int* __restrict__ leaves, int nleaves, int b2,
+                                                const int4* __restrict__ anchor, const int2* __restrict__ range,
+                                                const float4* __restrict__ pts, const float4* __restrict__ src2,
+                                                const float4* __restrict__ surf, int n, BoxGeom geo,
+                                                float* __restrict__ psi_u) {
     __shared__ float4 sh[256];
     __shared__ float4 sh2[256];
-    int b = xboxes[blockIdx.x];
-    int4 a = anchor[b];
+    __shared__ float red[NP];
+    const int b = leaves[blockIdx.x];
+    if (b < b2) return;   // leaves above level 2 have no far field
+    const int4 a = anchor[b];
     float c[3], invw, w;
     box_frame(geo, a, c, invw, w);
-    for (int i0 = 0; i0 < NP; i0 += blockDim.x) {
-        int i = i0 + threadIdx.x;
-        bool act = i < n;
-        float4 s = act ? surf[i] : make_float4(0, 0, 0, 0);   // downward check surface
-        float acc = 0.f;
-        for (int k = xoff[b]; k < xoff[b + 1]; ++k) {
-            int2 r = range[xidx[k]];
-            points_to_surface<NP>(acc, pts, src2, r.x, r.y, c, invw, s, act, sh, sh2);
-        }
-        if (i < NP) psi_d[size_t(b) * NP + i] = act ? acc : 0.f;
+    const int2 r = range[b];
+    const int i = threadIdx.x % NP, slice = threadIdx.x / NP;
+    const bool act = i < n;
+    const float4 s = act ? surf[NP + i] : make_float4(0, 0, 0, 0);   // upward check surface
+    float acc = 0.f;
+    points_to_surface<NP>(acc, pts, src2, r.x, r.y, c, invw, s, act, slice, sh, sh2);
+    acc = add_slices<NP>(acc, i, slice, red);
+    if (slice == 0) psi_u[size_t(b) * NP + i] = act ? acc : 0.f;
+}
+
+template <int NP>
+__global__ __launch_bounds__(2 * NP) void k_p2l(const int* __restrict__ xboxes, const int* __restrict__ xoff,
+                                                const int* __restrict__ xidx, const int4* __restrict__ anchor,
+                                                const int2* __restrict__ range, const float4* __restrict__ pts,
+                                                const float4* __restrict__ src2, const float4* __restrict__ surf,
+                                                int n, BoxGeom geo, float* __restrict__ psi_d) {
+    __shared__ float4 sh[256];
+    __shared__ float4 sh2[256];
+    __shared__ float red[NP];
+    const int b = xboxes[blockIdx.x];
+    const int4 a = anchor[b];
+    float c[3], invw, w;
+    box_frame(geo, a, c, invw, w);
+    const int i = threadIdx.x % NP, slice = threadIdx.x / NP;
+    const bool act = i < n;
+    const float4 s = act ? surf[i] : make_float4(0, 0, 0, 0);   // downward check surface
+    float acc = 0.f;
+    for (int k = xoff[b]; k < xoff[b + 1]; ++k) {
+        const int2 r = range[xidx[k]];
+        points_to_surface<NP>(acc, pts, src2, r.x, r.y, c, invw, s, act, slice, sh, sh2);
     }
+    acc = add_slices<NP>(acc, i, slice, red);
+    if (slice == 0) psi_d[size_t(b) * NP + i] = act ? acc : 0.f;
 }
 
 // ------------------------------------------------------------------ M2L
@@ -950,7 +966,7 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec) {
         return;
     }
     const int b2 = int(P->lev[2].start);
-    const int tpb = std::min(320, (NP + 63) / 64 * 64);
+    const int tpb = 2 * NP;   // P2M / P2L: two slices of NP threads
     // P2M
     for (int r = r0; r < r1; ++r)
         hipLaunchKernelGGL(k_p2m<NP>, dim3(unsigned(P->nleaves)), dim3(tpb), 0, s, P->leaves.as<int>(),

@@ -376,20 +376,21 @@ __device__ inline int find_box(const uint64_t* __restrict__ mkey, int start, int
     return (lo < start + count && mkey[lo] == key) ? lo : -1;
 }
 
+// One thread per (box, direction): a binary search for the neighbour's key
+// among the boxes of the same level.
 __global__ void k_colleagues(int B, const int4* __restrict__ anchor, const uint64_t* __restrict__ mkey,
                              LevelTable lt, int* __restrict__ coll) {
-    int b = blockIdx.x * TB + threadIdx.x;
-    if (b >= B) return;
-    int4 a = anchor[b];
-    int l = a.w;
-    int lim = 1 << l;
-    for (int d = 0; d < 27; ++d) {
-        int x = a.x + d / 9 - 1, y = a.y + (d / 3) % 3 - 1, z = a.z + d % 3 - 1;
-        int id = -1;
-        if (x >= 0 && y >= 0 && z >= 0 && x < lim && y < lim && z < lim)
-            id = find_box(mkey, lt.start[l], lt.count[l], morton3(x, y, z));
-        coll[27 * int64_t(b) + d] = id;
-    }
+    const int64_t g = int64_t(blockIdx.x) * TB + threadIdx.x;
+    if (g >= int64_t(B) * 27) return;
+    const int b = int(g / 27), d = int(g % 27);
+    const int4 a = anchor[b];
+    const int l = a.w;
+    const int lim = 1 << l;
+    const int x = a.x + d / 9 - 1, y = a.y + (d / 3) % 3 - 1, z = a.z + d % 3 - 1;
+    int id = -1;
+    if (x >= 0 && y >= 0 && z >= 0 && x < lim && y < lim && z < lim)
+        id = find_box(mkey, lt.start[l], lt.count[l], morton3(x, y, z));
+    coll[g] = id;
 }
 
 // V-list slots of an octant: (colleague direction D in 0..26, child octant o')
@@ -401,23 +402,24 @@ struct VTable {
     short op[8][kVPerOct];
 };
 
+// One wave per box, the lanes over its 189 slots (coalesced rows).
 __global__ void k_vdense(int b0, int nb, const int4* __restrict__ anchor, const int* __restrict__ parent,
                          const int2* __restrict__ child, const int* __restrict__ leafflag,
                          const int* __restrict__ coll, const VTable* __restrict__ vt, int* __restrict__ vd) {
-    int i = blockIdx.x * TB + threadIdx.x;
+    const int64_t g = int64_t(blockIdx.x) * TB + threadIdx.x;
+    const int i = int(g >> 6), lane = int(g & 63);
     if (i >= nb) return;
-    int b = b0 + i;
-    int4 a = anchor[b];
-    int o = ((a.x & 1) << 2) | ((a.y & 1) << 1) | (a.z & 1);
-    int P = parent[b];
-    const int* cp = coll + 27 * int64_t(P);
+    const int b = b0 + i;
+    const int4 a = anchor[b];
+    const int o = ((a.x & 1) << 2) | ((a.y & 1) << 1) | (a.z & 1);
+    const int* cp = coll + 27 * int64_t(parent[b]);
     int* out = vd + int64_t(i) * kVPerOct;
-    for (int j = 0; j < kVPerOct; ++j) {
-        int Q = cp[vt->D[o][j]];
+    for (int j = lane; j < kVPerOct; j += 64) {
+        const int Q = cp[vt->D[o][j]];
         int src = -1;
         if (Q >= 0 && !leafflag[Q]) {
-            int2 c = child[Q];
-            int oc = vt->oc[o][j];
+            const int2 c = child[Q];
+            const int oc = vt->oc[o][j];
             if ((c.y >> oc) & 1) src = c.x + __popc(c.y & ((1 << oc) - 1));
         }
         out[j] = src;
@@ -588,24 +590,35 @@ __global__ void k_compact(int B, const int* __restrict__ flag, const int* __rest
 }
 
 // Counts: V pairs, P2P point pairs (self pairs included), from the lists.
-__global__ void k_counts(int B, int b2, int nv, const int* __restrict__ vd, const int* __restrict__ leafflag,
-                         const int2* __restrict__ range, const int* __restrict__ uoff,
-                         const int* __restrict__ uidx, unsigned long long* __restrict__ out) {
+// V pairs: a grid-stride count over the dense table, one atomic per block.
+__global__ void k_count_v(int64_t n, const int* __restrict__ vd, unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[TB / 64];
+    unsigned long long c = 0;
+    for (int64_t g = int64_t(blockIdx.x) * TB + threadIdx.x; g < n; g += int64_t(gridDim.x) * TB) c += vd[g] >= 0;
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < TB / 64; ++k) t += part[k];
+        if (t) atomicAdd(&out[0], t);
+    }
+}
+
+// Near-field point pairs of each leaf.
+__global__ void k_counts(int B, const int* __restrict__ leafflag, const int2* __restrict__ range,
+                         const int* __restrict__ uoff, const int* __restrict__ uidx,
+                         unsigned long long* __restrict__ out) {
     int b = blockIdx.x * TB + threadIdx.x;
-    unsigned long long v = 0, pp = 0;
-    if (b < B) {
-        if (b >= b2)
-            for (int j = 0; j < kVPerOct; ++j) v += vd[int64_t(b - b2) * kVPerOct + j] >= 0;
-        if (leafflag[b]) {
-            int2 r = range[b];
-            unsigned long long nt = r.y - r.x;
-            for (int k = uoff[b]; k < uoff[b + 1]; ++k) {
-                int2 ra = range[uidx[k]];
-                pp += nt * (unsigned long long)(ra.y - ra.x);
-            }
+    unsigned long long pp = 0;
+    if (b < B && leafflag[b]) {
+        int2 r = range[b];
+        unsigned long long nt = r.y - r.x;
+        for (int k = uoff[b]; k < uoff[b + 1]; ++k) {
+            int2 ra = range[uidx[k]];
+            pp += nt * (unsigned long long)(ra.y - ra.x);
         }
     }
-    if (v) atomicAdd(&out[0], v);
     if (pp) atomicAdd(&out[1], pp);
 }
 
@@ -638,9 +651,10 @@ __global__ void k_item_fill(int nl, const int* __restrict__ leaves, const int2* 
         const int t0 = r.x + 64 * c;
         const unsigned long long nt = min(64, r.y - t0);
         items[at] = make_int2(b, t0);
-        unsigned long long cn = nt * src, cf = nt * nfar * 64;
-        key_near[at] = 0xffffffffull - min(cn, 0xffffffffull);
-        key_far[at] = 0xffffffffull - min(cf, 0xffffffffull);
+        const unsigned long long cn = nt * src, cf = nt * nfar * 64;
+        // heaviest first: 16-bit keys, descending in log2(cost) (2^-11 steps)
+        key_near[at] = 0xffffull - min(0xffffull, (unsigned long long)(log2(double(cn) + 1.0) * 2048.0));
+        key_far[at] = 0xffffull - min(0xffffull, (unsigned long long)(log2(double(cf) + 1.0) * 2048.0));
         id_near[at] = uint32_t(at);
         id_far[at] = uint32_t(at);
     }
@@ -843,7 +857,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     }
     // colleagues
     P->coll.ensure(size_t(B) * 27 * 4);
-    hipLaunchKernelGGL(k_colleagues, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_anchor.as<int4>(),
+    hipLaunchKernelGGL(k_colleagues, dim3(nblocks(int64_t(B) * 27)), dim3(TB), 0, s, B, P->bx_anchor.as<int4>(),
                        P->bx_mkey.as<uint64_t>(), lt, P->coll.as<int>());
     // V dense table
     static DBuf* vt_dev = nullptr;   // per process, small
@@ -855,7 +869,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     int nvb = B - b2;
     P->vdense.ensure(size_t(std::max(nvb, 1)) * kVPerOct * 4);
     if (nvb > 0)
-        hipLaunchKernelGGL(k_vdense, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
+        hipLaunchKernelGGL(k_vdense, dim3(nblocks(int64_t(nvb) * 64)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
                            P->bx_parent.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->coll.as<int>(),
                            vt_dev->as<VTable>(), P->vdense.as<int>());
     // coarse adjacent leaves, top-down
@@ -959,8 +973,8 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         P->tmp_c.ensure(size_t(ni) * 8);
         hipLaunchKernelGGL(k_item_fill, dim3(nblocks(nl)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
                            P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), woff, b2, ioff, items, kn, kf, idn, idf);
-        radix_sort(P, kn, idn, P->tmp_c.as<uint64_t>(), vtmp, ni, 32, s);
-        radix_sort(P, kf, idf, P->tmp_c.as<uint64_t>(), vtmp, ni, 32, s);
+        radix_sort(P, kn, idn, P->tmp_c.as<uint64_t>(), vtmp, ni, 16, s);
+        radix_sort(P, kf, idf, P->tmp_c.as<uint64_t>(), vtmp, ni, 16, s);
         P->items_near.ensure(size_t(ni) * 8);
         P->items_far.ensure(size_t(ni) * 8);
         hipLaunchKernelGGL(k_item_gather, dim3(nblocks(ni)), dim3(TB), 0, s, ni, items, idn, idf,
@@ -970,8 +984,11 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     P->tmp_a.ensure(64);
     unsigned long long* dc = P->tmp_a.as<unsigned long long>();
     KIFMM_HIP(hipMemsetAsync(dc, 0, 16, s));
-    hipLaunchKernelGGL(k_counts, dim3(nblocks(B)), dim3(TB), 0, s, B, b2, nvb, P->vdense.as<int>(),
-                       P->bx_leaf.as<int>(), P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), dc);
+    if (nvb > 0)
+        hipLaunchKernelGGL(k_count_v, dim3(std::min(1024, nblocks(int64_t(nvb) * kVPerOct))), dim3(TB), 0, s,
+                           int64_t(nvb) * kVPerOct, P->vdense.as<int>(), dc);
+    hipLaunchKernelGGL(k_counts, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->bx_range.as<int2>(),
+                       uoff, P->u_idx.as<int>(), dc);
     unsigned long long hc[2];
     int hbad = 0;
     KIFMM_HIP(hipMemcpyAsync(hc, dc, 16, hipMemcpyDeviceToHost, s));
