@@ -346,7 +346,7 @@ int kifmm_get_phase_times(kifmm_handle h, float* out, int n) {
 
 void kifmm_destroy(kifmm_handle h) {
     if (!h) return;
-    if (h->last_stream || true) (void)hipStreamSynchronize(h->last_stream);
+    (void)hipStreamSynchronize(h->last_stream);
     if (h->events.made)
         for (auto& e : h->events.ev) (void)hipEventDestroy(e);
     delete h;

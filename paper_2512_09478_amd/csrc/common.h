@@ -33,6 +33,22 @@ struct Error : std::runtime_error {
     } while (0)
 
 // Grow-only device buffer.
+// A few pinned host words for the small device-to-host reads of the tree
+// build (allocated once per plan with hipHostMalloc, freed with the plan).
+struct HostWords {
+    void* p = nullptr;
+    HostWords() = default;
+    HostWords(const HostWords&) = delete;
+    HostWords& operator=(const HostWords&) = delete;
+    ~HostWords() {
+        if (p) (void)hipHostFree(p);
+    }
+    unsigned long long* get() {
+        if (!p) KIFMM_HIP(hipHostMalloc(&p, 512, hipHostMallocDefault));
+        return static_cast<unsigned long long*>(p);
+    }
+};
+
 struct DBuf {
     void* p = nullptr;
     size_t cap = 0;
@@ -130,6 +146,7 @@ struct kifmm_plan {
     int64_t counts[10] = {};
     hipStream_t last_stream = nullptr;
     const kifmm::Operators* ops = nullptr;
+    kifmm::HostWords host;   // pinned words for small read-backs
 
     // points
     kifmm::DBuf x64;        // double [N][3] caller order (copy)

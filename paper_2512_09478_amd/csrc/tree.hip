@@ -271,37 +271,67 @@ void radix_sort(kifmm_plan* P, uint64_t* keys, uint32_t* vals, uint64_t* ktmp, u
 // ----------------------------------------------------------------- tree levels
 // For each non-leaf parent at level l: child boundaries in its sorted key run
 // (the level-(l+1) digit is non-decreasing inside the run).
+// One wave per front box.  Lane group g (lanes 9g .. 9g+8, g < 7) finds child
+// boundary o = g + 1, the first index of the box's key run whose octant digit
+// at level l + 1 is >= o: every step samples 9 points of the group's interval
+// and keeps the tenth that holds the boundary (exact once the interval has
+// fewer than 10 entries).
 __global__ void k_split(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
                         const int2* __restrict__ range, int* __restrict__ bounds /*[nf][9]*/,
                         int* __restrict__ nch, int* __restrict__ nnl, int leaf_size, int adaptive,
                         int max_depth, int Lu) {
-    int f = blockIdx.x * TB + threadIdx.x;
-    if (f >= nf) return;
-    int2 r = range[front[f]];
-    int shift = 3 * (kBits - (l + 1));
-    int* bd = bounds + 9 * f;
+    const int64_t gid = int64_t(blockIdx.x) * TB + threadIdx.x;
+    const int f = int(gid >> 6), lane = int(gid & 63);
+    if (f >= nf) return;   // uniform over the wave
+    const int2 r = range[front[f]];
+    const int shift = 3 * (kBits - (l + 1));
+    const int grp = lane / 9, k = lane % 9;
+    const int o = grp + 1;
+    int lo = r.x, hi = r.y;   // the boundary lies in [lo, hi]
+    // sample j of the interval [lo, lo + len)
+    auto sample = [&](int j, int len) -> int { return len >= 10 ? lo + int(int64_t(len) * (j + 1) / 10) : lo + j; };
+    while (__ballot(grp < 7 && hi > lo)) {
+        const int len = hi - lo;
+        const bool act = grp < 7 && len > 0;
+        const bool valid = act && (len >= 10 || k < len);
+        bool pred = false;
+        if (valid) pred = int((keys[sample(k, len)] >> shift) & 7ull) >= o;
+        const unsigned long long m = __ballot(pred);
+        if (act) {
+            const unsigned gm = unsigned(m >> (9 * grp)) & 0x1ffu;
+            if (len < 10) {
+                lo = gm ? lo + __builtin_ctz(gm) : hi;
+                hi = lo;
+            } else if (gm) {
+                const int ks = __builtin_ctz(gm);
+                const int nlo = ks ? sample(ks - 1, len) + 1 : lo;
+                hi = sample(ks, len);
+                lo = nlo;
+            } else {
+                lo = sample(8, len) + 1;
+            }
+        }
+    }
+    int bd[9];
     bd[0] = r.x;
     bd[8] = r.y;
-    for (int o = 1; o < 8; ++o) {
-        int lo = r.x, hi = r.y;   // first index with digit >= o
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (int((keys[mid] >> shift) & 7ull) < o) lo = mid + 1;
-            else hi = mid;
+#pragma unroll
+    for (int q = 1; q < 8; ++q) bd[q] = __shfl(lo, 9 * (q - 1), 64);
+    if (lane == 0) {
+        int* out = bounds + 9 * f;
+        int c = 0, nl = 0;
+        for (int q = 0; q < 9; ++q) out[q] = bd[q];
+        for (int q = 0; q < 8; ++q) {
+            const int cnt = bd[q + 1] - bd[q];
+            if (cnt > 0) {
+                ++c;
+                const bool leaf = adaptive ? (cnt <= leaf_size || l + 1 == max_depth) : (l + 1 == Lu);
+                if (!leaf) ++nl;
+            }
         }
-        bd[o] = lo;
+        nch[f] = c;
+        nnl[f] = nl;
     }
-    int c = 0, nl = 0;
-    for (int o = 0; o < 8; ++o) {
-        int cnt = bd[o + 1] - bd[o];
-        if (cnt > 0) {
-            ++c;
-            bool leaf = adaptive ? (cnt <= leaf_size || l + 1 == max_depth) : (l + 1 == Lu);
-            if (!leaf) ++nl;
-        }
-    }
-    nch[f] = c;
-    nnl[f] = nl;
 }
 
 __global__ void k_emit(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
@@ -711,10 +741,18 @@ static const VTable& vtable_host() {
 
 const void* vtable_host_ptr() { return &vtable_host(); }
 
-static int read_int(const int* dptr, hipStream_t s) {
-    int v = 0;
-    KIFMM_HIP(hipMemcpyAsync(&v, dptr, 4, hipMemcpyDeviceToHost, s));
+// Read device ints through the plan's pinned words (one copy each, one wait).
+static void read_ints(kifmm_plan* P, hipStream_t s, std::initializer_list<const int*> src, int* dst) {
+    int* h = reinterpret_cast<int*>(P->host.get());
+    int k = 0;
+    for (const int* d : src) KIFMM_HIP(hipMemcpyAsync(h + k++, d, 4, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < k; ++i) dst[i] = h[i];
+}
+
+static int read_int(kifmm_plan* P, const int* dptr, hipStream_t s) {
+    int v = 0;
+    read_ints(P, s, {dptr}, &v);
     return v;
 }
 
@@ -769,7 +807,8 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     double scale = ldexp(1.0, kBits) / P->side;
     hipLaunchKernelGGL(k_keys, dim3(nblocks(N)), dim3(TB), 0, s, P->x64.as<double>(), N, P->lo[0], P->lo[1],
                        P->lo[2], scale, P->side, o.explicit_root, keys, idx, bad);
-    if (read_int(bad, s)) throw Error(KIFMM_ERR_INPUT, o.explicit_root ? "non-finite position or point outside the explicit root" : "non-finite position");
+    // a flagged point gets key 0, so the build below stays in bounds; the flag
+    // is read with the final counts
     radix_sort(P, keys, idx, P->tmp_c.as<uint64_t>(), P->tmp_d.as<uint32_t>(), N, 63, s);
     P->xs.ensure(size_t(N) * 16);
     P->perm.ensure(size_t(N) * 4);
@@ -815,16 +854,14 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         int* choff = P->tmp_e.as<int>();
         int* nloff = choff + nf + 1;
         const int* front = P->nonleaf.as<int>() + cur.nl_start;
-        hipLaunchKernelGGL(k_split, dim3(nblocks(nf)), dim3(TB), 0, s, front, nf, l, keys, P->bx_range.as<int2>(),
+        hipLaunchKernelGGL(k_split, dim3(nblocks(int64_t(nf) * 64)), dim3(TB), 0, s, front, nf, l, keys, P->bx_range.as<int2>(),
                            bounds, nch, nnl, P->leaf, o.adaptive, o.max_depth, Lu);
         KIFMM_HIP(hipMemsetAsync(nch + nf, 0, 4, s));
         KIFMM_HIP(hipMemsetAsync(nnl + nf, 0, 4, s));
         exclusive_scan<int>(P, nch, choff, nf + 1, s);
         exclusive_scan<int>(P, nnl, nloff, nf + 1, s);
         int tot[2];
-        KIFMM_HIP(hipMemcpyAsync(&tot[0], choff + nf, 4, hipMemcpyDeviceToHost, s));
-        KIFMM_HIP(hipMemcpyAsync(&tot[1], nloff + nf, 4, hipMemcpyDeviceToHost, s));
-        KIFMM_HIP(hipStreamSynchronize(s));
+        read_ints(P, s, {choff + nf, nloff + nf}, tot);
         LevelInfo nx;
         nx.start = total;
         nx.count = tot[0];
@@ -888,7 +925,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                            P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
                            (int*)nullptr, 0);
     exclusive_scan<int>(P, xoff, xoff, B + 1, s);
-    int nx = read_int(xoff + B, s);
+    int nx = read_int(P, xoff + B, s);
     P->x_idx.ensure(size_t(std::max(nx, 1)) * 4);
     if (nvb > 0 && nx > 0) {
         hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
@@ -909,7 +946,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
                        uoff, (int*)nullptr, (int*)nullptr, 0);
     exclusive_scan<int>(P, uoff, uoff, B + 1, s);
-    int nu = read_int(uoff + B, s);
+    int nu = read_int(P, uoff + B, s);
     P->u_idx.ensure(size_t(std::max(nu, 1)) * 4);
     hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
                        P->cal.as<int>(), uoff, P->u_idx.as<int>(), cursor, 1);
@@ -924,7 +961,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(), woff,
                            (int*)nullptr, (int*)nullptr, 0);
     exclusive_scan<int>(P, woff, woff, B + 1, s);
-    int nw = read_int(woff + B, s);
+    int nw = read_int(P, woff + B, s);
     P->w_idx.ensure(size_t(std::max(nw, 1)) * 4);
     if (nvb > 0 && nw > 0) {
         hipLaunchKernelGGL(k_copy_int, dim3(nblocks(B + 1)), dim3(TB), 0, s, woff, cursor, B + 1);
@@ -943,8 +980,9 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     KIFMM_HIP(hipMemsetAsync(fx + B, 0, 4, s));
     exclusive_scan<int>(P, fl, ol, B + 1, s);
     exclusive_scan<int>(P, fx, ox, B + 1, s);
-    int nl = read_int(ol + B, s);
-    int nxb = read_int(ox + B, s);
+    int nlx[2];
+    read_ints(P, s, {ol + B, ox + B}, nlx);
+    const int nl = nlx[0], nxb = nlx[1];
     P->nleaves = nl;
     P->n_xboxes = nxb;
     P->leaves.ensure(size_t(std::max(nl, 1)) * 4);
@@ -960,7 +998,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                            P->bx_range.as<int2>(), icnt);
         KIFMM_HIP(hipMemsetAsync(icnt + nl, 0, 4, s));
         exclusive_scan<int>(P, icnt, ioff, nl + 1, s);
-        int ni = read_int(ioff + nl, s);
+        int ni = read_int(P, ioff + nl, s);
         P->n_items = ni;
         P->item_tmp.ensure(size_t(ni) * (8 + 8 + 8 + 4 + 4 + 4 + 4) + 1024);
         char* base = P->item_tmp.as<char>();
@@ -989,11 +1027,15 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                            int64_t(nvb) * kVPerOct, P->vdense.as<int>(), dc);
     hipLaunchKernelGGL(k_counts, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->bx_range.as<int2>(),
                        uoff, P->u_idx.as<int>(), dc);
-    unsigned long long hc[2];
-    int hbad = 0;
-    KIFMM_HIP(hipMemcpyAsync(hc, dc, 16, hipMemcpyDeviceToHost, s));
-    KIFMM_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+    unsigned long long* hw = P->host.get();
+    KIFMM_HIP(hipMemcpyAsync(hw, dc, 16, hipMemcpyDeviceToHost, s));
+    KIFMM_HIP(hipMemcpyAsync(hw + 2, bad, 4, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipStreamSynchronize(s));
+    const unsigned long long hc[2] = {hw[0], hw[1]};
+    const int hbad = int(hw[2] & 0xffffffffull);
+    if (hbad & 1)
+        throw Error(KIFMM_ERR_INPUT, o.explicit_root ? "non-finite position or point outside the explicit root"
+                                                     : "non-finite position");
     if (hbad & 2) throw Error(KIFMM_ERR_STATE, "more than 26 coarse adjacent leaves");
     P->counts[0] = B;
     P->counts[1] = nl;
