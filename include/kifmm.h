@@ -22,8 +22,11 @@
  *    order: positions [N][3] double, charges [N] float, field [N][3] float.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    kifmm_setup* synchronises that stream (tree sizes are read back); all
- *    other calls are asynchronous on it.  One handle must not be used from
- *    two streams at once.
+ *    other calls are asynchronous on it.  kifmm_evaluate and kifmm_backward
+ *    run the near field on a second stream owned by the handle, forked from
+ *    and joined back to `stream` with events, so their results are ordered
+ *    on `stream` as if everything ran there.  One handle must not be used
+ *    from two streams at once.
  *  - The caller owns every argument buffer; the library keeps no pointer to
  *    them after the call's work has run on the stream.  The handle owns its
  *    device copies of the positions, the tree, the lists, the operators and
@@ -190,7 +193,8 @@ int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indic
 
 /*
  * Per-phase device times in ms of the last evaluate/backward (host out[n]):
- * 0 P2M, 1 upward M2M+UC2E, 2 P2L, 3 M2L, 4 L2L+DC2E, 5 L2P+M2P, 6 P2P,
+ * 0 P2M, 1 upward M2M+UC2E, 2 P2L, 3 M2L, 4 L2L+DC2E, 5 L2P+M2P (with the
+ * final combination), 6 P2P (on the near-field stream, concurrent with 0-4),
  * 7 whole call.  Needs opts.profile = 1; returns the number written.
  */
 int kifmm_get_phase_times(kifmm_handle h, float* out, int n);

@@ -57,7 +57,7 @@ void alloc_densities(kifmm_plan* P, hipStream_t s) {
         if (fresh) KIFMM_HIP(hipMemsetAsync(b->p, 0, b->cap, s));
     }
     P->psi_m.ensure(size_t(kM2LSplit) * bytes);
-    P->far.ensure(size_t(P->N) * 16);
+    P->nearv.ensure(size_t(P->N) * 16);
 }
 
 kifmm_plan* checked(kifmm_handle h) {
@@ -70,9 +70,32 @@ void begin_phases(kifmm_plan* P, hipStream_t s) {
     if (!P->opt.profile) return;
     if (!P->events.made) {
         for (auto& e : P->events.ev) KIFMM_HIP(hipEventCreate(&e));
+        for (auto& e : P->events.p2p) KIFMM_HIP(hipEventCreate(&e));
         P->events.made = true;
     }
     KIFMM_HIP(hipEventRecord(P->events.ev[0], s));
+}
+
+// The near field does not depend on the far-field sweep: it runs on the side
+// stream, forked from `s` after P2M (so that the sweep's first kernel is not
+// queued behind it) and joined back before the leaf evaluation, which adds it
+// to the far field.
+void fork_near(kifmm_plan* P, bool backward, hipStream_t s) {
+    P->nearq.make();
+    hipStream_t t = P->nearq.s;
+    KIFMM_HIP(hipEventRecord(P->nearq.fork, s));
+    KIFMM_HIP(hipStreamWaitEvent(t, P->nearq.fork, 0));
+    const bool prof = P->opt.profile && P->events.made;
+    if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[0], t));
+    if (backward) launch_p2p_backward(P, t);
+    else launch_p2p_forward(P, t);
+    if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[1], t));
+    KIFMM_HIP(hipEventRecord(P->nearq.join, t));
+}
+
+void join_near(kifmm_plan* P, hipStream_t s) {
+    KIFMM_HIP(hipStreamWaitEvent(s, P->nearq.join, 0));
+    record_phase(P, 5, s);
 }
 
 }  // namespace
@@ -173,10 +196,9 @@ int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float
         begin_phases(P, s);
         P->fwd_valid = false;
         launch_gather(P, charges, nullptr, nullptr, false, s);
-        run_sweep(P, 0, 1, s, true);
-        run_far_eval(P, false, nullptr, s);
-        record_phase(P, 5, s);
-        launch_p2p_forward(P, potential, field, s);
+        run_sweep(P, 0, 1, s, true, [&] { fork_near(P, false, s); });
+        join_near(P, s);
+        run_far_eval(P, false, potential, field, s);
         record_phase(P, 6, s);
         P->has_phase = P->opt.profile ? 1 : 0;
         P->fwd_valid = true;
@@ -198,11 +220,10 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
         // forward pass are still in place and only the adjoint sources are swept
         if (charges) P->fwd_valid = false;
         launch_gather(P, charges, grad_potential, grad_field, true, s);
-        run_sweep(P, charges ? 0 : 1, 2, s, true);
+        run_sweep(P, charges ? 0 : 1, 2, s, true, [&] { fork_near(P, true, s); });
         P->fwd_valid = true;
-        run_far_eval(P, true, nullptr, s);
-        record_phase(P, 5, s);
-        launch_p2p_backward(P, grad_charges, grad_positions, s);
+        join_near(P, s);
+        run_far_eval(P, true, grad_charges, grad_positions, s);
         record_phase(P, 6, s);
         P->has_phase = P->opt.profile ? 2 : 0;
         KIFMM_HIP(hipGetLastError());
@@ -335,8 +356,11 @@ int kifmm_get_phase_times(kifmm_handle h, float* out, int n) {
         if (!out) throw Error(KIFMM_ERR_ARG, "null output");
         if (!P->has_phase || !P->events.made) return;
         KIFMM_HIP(hipEventSynchronize(P->events.ev[7]));
+        KIFMM_HIP(hipEventSynchronize(P->events.p2p[1]));
         float ms[8] = {};
-        for (int k = 0; k < 7; ++k) KIFMM_HIP(hipEventElapsedTime(&ms[k], P->events.ev[k], P->events.ev[k + 1]));
+        for (int k = 0; k < 5; ++k) KIFMM_HIP(hipEventElapsedTime(&ms[k], P->events.ev[k], P->events.ev[k + 1]));
+        KIFMM_HIP(hipEventElapsedTime(&ms[5], P->events.ev[6], P->events.ev[7]));
+        KIFMM_HIP(hipEventElapsedTime(&ms[6], P->events.p2p[0], P->events.p2p[1]));
         KIFMM_HIP(hipEventElapsedTime(&ms[7], P->events.ev[0], P->events.ev[7]));
         for (int k = 0; k < std::min(n, 8); ++k) out[k] = ms[k];
         written = std::min(n, 8);
@@ -347,8 +371,10 @@ int kifmm_get_phase_times(kifmm_handle h, float* out, int n) {
 void kifmm_destroy(kifmm_handle h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->last_stream);
-    if (h->events.made)
+    if (h->events.made) {
         for (auto& e : h->events.ev) (void)hipEventDestroy(e);
+        for (auto& e : h->events.p2p) (void)hipEventDestroy(e);
+    }
     delete h;
 }
 

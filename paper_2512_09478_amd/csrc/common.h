@@ -6,6 +6,7 @@
 
 #include <stdexcept>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/kifmm.h"
@@ -125,9 +126,36 @@ struct LevelInfo {
     int64_t nl_start = 0, nl_count = 0;  // non-leaf boxes of this level in nonleaf[]
 };
 
+// Phase events: ev[0] start, ev[1..5] after P2M, upward, P2L, M2L, downward
+// on the caller's stream, ev[6] after it has joined the near-field stream,
+// ev[7] after the leaf evaluation; p2p[0..1] around the near field on the
+// side stream.
 struct PhaseEvents {
-    hipEvent_t ev[9] = {};
+    hipEvent_t ev[8] = {};
+    hipEvent_t p2p[2] = {};
     bool made = false;
+};
+
+// The second stream the near field runs on, forked from and joined to the
+// caller's stream with events (default priority).
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    SideStream() = default;
+    SideStream(const SideStream&) = delete;
+    SideStream& operator=(const SideStream&) = delete;
+    ~SideStream() {
+        if (s) (void)hipStreamSynchronize(s);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (s) (void)hipStreamDestroy(s);
+    }
+    void make() {
+        if (s) return;
+        KIFMM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        KIFMM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        KIFMM_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    }
 };
 
 }  // namespace kifmm
@@ -179,10 +207,11 @@ struct kifmm_plan {
     // per-evaluation work
     kifmm::DBuf pts;        // float4 [N] sorted (x, y, z, q)
     kifmm::DBuf src2;       // float4 [N] sorted (ubar, Ebar) for the adjoint sweep
-    kifmm::DBuf far;        // float [N][4] or [N][12] far-field partials (sorted)
+    kifmm::DBuf nearv;      // float4 [N] sorted near-field part: (u, E) or (xbar, qbar)
     // scratch
     kifmm::DBuf tmp_a, tmp_b, tmp_c, tmp_d, tmp_e, tmp_f, scan_tmp, flag;
     kifmm::PhaseEvents events;
+    kifmm::SideStream nearq;   // near-field stream
     float phase_ms[8] = {};
     int has_phase = 0;
     bool fwd_valid = false;   // densities of right-hand side 0 and pts hold the last forward pass
@@ -193,13 +222,15 @@ namespace kifmm {
 // ---- tree.hip
 void build_tree(kifmm_plan* P, const double* positions, hipStream_t s);
 // ---- farfield.hip
-void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record);
-void run_far_eval(kifmm_plan* P, bool backward, const float* ebar_sorted_unused, hipStream_t s);
+void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between);
+// leaf evaluation; adds the near-field part and writes the caller-order
+// outputs (forward: potential, field; backward: grad_charges, grad_positions)
+void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s);
 // ---- nearfield.hip
 void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const float* gfield,
                    bool adjoint, hipStream_t s);
-void launch_p2p_forward(kifmm_plan* P, float* potential, float* field, hipStream_t s);
-void launch_p2p_backward(kifmm_plan* P, float* gq, float* gx, hipStream_t s);
+void launch_p2p_forward(kifmm_plan* P, hipStream_t s);
+void launch_p2p_backward(kifmm_plan* P, hipStream_t s);
 // ---- clump.hip
 void launch_clump_reduce(kifmm_plan* P, const float* q, const float* E, const int64_t* off, int64_t C,
                          const double* centers, double* F, double* T, hipStream_t s);

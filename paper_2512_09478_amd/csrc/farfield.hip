@@ -25,6 +25,8 @@
 
 #include <algorithm>
 
+#include <functional>
+
 #include "common.h"
 
 namespace kifmm {
@@ -710,7 +712,10 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
 // Small items give each target S lanes of a wave (as in the near field) that
 // split the surface points and are summed by shuffles.
 struct FarOut {
-    float* u;      // float4 [N] sorted: forward (u, Ex, Ey, Ez), backward (xbar xyz, psi)
+    const float4* nearv;   // sorted near-field part: forward (u, E), backward (xbar, psi)
+    const int* perm;       // sorted position -> caller index
+    float* a;              // forward: potential [N] | backward: grad_charges [N] (either may be null)
+    float* b;              // forward: field [N][3]  | backward: grad_positions [N][3]
 };
 
 __device__ inline int far_lanes(int nt) { return nt <= 8 ? 8 : nt <= 16 ? 4 : nt <= 32 ? 2 : 1; }
@@ -826,7 +831,24 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
         for (int q = 0; q < NV; ++q)
             v[q] = cst * (((red[q * 64 + lane] + red[(NV + q) * 64 + lane]) + red[(2 * NV + q) * 64 + lane]) +
                           red[(3 * NV + q) * 64 + lane]);
-        reinterpret_cast<float4*>(out.u)[i] = make_float4(v[0], v[1], v[2], v[3]);
+        // far + near, written in caller order
+        const float4 nr = out.nearv[i];
+        const size_t j = size_t(out.perm[i]);
+        if (!BWD) {
+            if (out.a) out.a[j] = v[0] + nr.x;
+            if (out.b) {
+                out.b[3 * j] = v[1] + nr.y;
+                out.b[3 * j + 1] = v[2] + nr.z;
+                out.b[3 * j + 2] = v[3] + nr.w;
+            }
+        } else {
+            if (out.a) out.a[j] = v[3] + nr.w;
+            if (out.b) {
+                out.b[3 * j] = v[0] + nr.x;
+                out.b[3 * j + 1] = v[1] + nr.y;
+                out.b[3 * j + 2] = v[2] + nr.z;
+            }
+        }
     }
 }
 
@@ -952,8 +974,9 @@ void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
 // One sweep over the tree for the right-hand sides r0 .. r1-1: 0 = the
 // charges (monopoles), 1 = the adjoint sources (monopoles dL/du, dipoles
 // dL/dE).  With both, M2L carries the two columns through each operator load.
+// `between` runs after P2M (the caller forks the near field there).
 template <int NP>
-void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec) {
+void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const std::function<void()>& between) {
     const Operators& op = *P->ops;
     const int B = int(P->B);
     const size_t stride = size_t(B) * NP;
@@ -962,7 +985,9 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec) {
     const float4* surf = op.surf.as<float4>();
     const int depth = P->depth;
     if (depth < 2) {
-        if (rec) for (int k = 0; k < 5; ++k) record_phase(P, k, s);
+        if (rec) record_phase(P, 0, s);
+        between();
+        if (rec) for (int k = 1; k < 5; ++k) record_phase(P, k, s);
         return;
     }
     const int b2 = int(P->lev[2].start);
@@ -973,6 +998,7 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec) {
                            int(P->nleaves), b2, P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), pts,
                            r ? P->src2.as<float4>() : nullptr, surf, op.n, geo, P->psi_u.as<float>() + r * stride);
     if (rec) record_phase(P, 0, s);
+    between();
     // upward M2M + UC2E, deepest level first
     for (int r = r0; r < r1; ++r)
         for (int l = depth; l >= 2; --l) {
@@ -1021,11 +1047,11 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec) {
 }
 
 template <int NP>
-void far_impl(kifmm_plan* P, bool bwd, hipStream_t s) {
+void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
     const int b2 = P->depth >= 2 ? int(P->lev[2].start) : int(P->B);
-    FarOut fo{P->far.as<float>()};
+    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), out_a, out_b};
     size_t stride = size_t(P->B) * NP;
     if (bwd)
         hipLaunchKernelGGL((k_far<NP, true>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(), b2,
@@ -1041,26 +1067,26 @@ void far_impl(kifmm_plan* P, bool bwd, hipStream_t s) {
 
 }  // namespace
 
-void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record) {
+void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between) {
     switch (P->npad) {
-        case 32: sweep_impl<32>(P, r0, r1, s, record); break;
-        case 64: sweep_impl<64>(P, r0, r1, s, record); break;
-        case 128: sweep_impl<128>(P, r0, r1, s, record); break;
-        case 160: sweep_impl<160>(P, r0, r1, s, record); break;
-        case 224: sweep_impl<224>(P, r0, r1, s, record); break;
-        case 320: sweep_impl<320>(P, r0, r1, s, record); break;
+        case 32: sweep_impl<32>(P, r0, r1, s, record, between); break;
+        case 64: sweep_impl<64>(P, r0, r1, s, record, between); break;
+        case 128: sweep_impl<128>(P, r0, r1, s, record, between); break;
+        case 160: sweep_impl<160>(P, r0, r1, s, record, between); break;
+        case 224: sweep_impl<224>(P, r0, r1, s, record, between); break;
+        case 320: sweep_impl<320>(P, r0, r1, s, record, between); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }
 
-void run_far_eval(kifmm_plan* P, bool backward, const float*, hipStream_t s) {
+void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s) {
     switch (P->npad) {
-        case 32: far_impl<32>(P, backward, s); break;
-        case 64: far_impl<64>(P, backward, s); break;
-        case 128: far_impl<128>(P, backward, s); break;
-        case 160: far_impl<160>(P, backward, s); break;
-        case 224: far_impl<224>(P, backward, s); break;
-        case 320: far_impl<320>(P, backward, s); break;
+        case 32: far_impl<32>(P, backward, out_a, out_b, s); break;
+        case 64: far_impl<64>(P, backward, out_a, out_b, s); break;
+        case 128: far_impl<128>(P, backward, out_a, out_b, s); break;
+        case 160: far_impl<160>(P, backward, out_a, out_b, s); break;
+        case 224: far_impl<224>(P, backward, out_a, out_b, s); break;
+        case 320: far_impl<320>(P, backward, out_a, out_b, s); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }

@@ -1,5 +1,6 @@
 // Near field (Section 2.2, last step: the contributions of points in the near
-// zone) and the final combination with the far field.
+// zone), written sorted as a float4 per point; the leaf-evaluation kernel adds
+// it to the far field and writes the caller-order outputs.
 //
 // Work items of at most 64 targets of one leaf, launched heaviest first; four
 // waves per item split the sources.  An item with nt <= 32 targets gives each
@@ -95,119 +96,105 @@ __device__ inline void wave_reduce(float (&v)[NV], float (*red)[NV][64]) {
 // Work item = (leaf, first target): up to 64 targets.  The four waves of the
 // block take interleaved groups of the staged sources; within a wave each
 // target has S lanes.
-__global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, const int2* __restrict__ range,
+__global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int n_items, const int2* __restrict__ range,
                                              const int* __restrict__ uoff, const int* __restrict__ uidx,
-                                             const float4* __restrict__ pts, const float4* __restrict__ far,
-                                             const int* __restrict__ perm, float cst, float* __restrict__ pot,
-                                             float* __restrict__ field) {
+                                             const float4* __restrict__ pts, float cst, float4* __restrict__ nearv) {
     __shared__ float4 sh[NF_STAGE];
     __shared__ float red[4][4][64];
-    const int2 it = items[blockIdx.x];
-    const int b = it.x;
-    const int nt = min(64, range[b].y - it.y);
-    const int S = lanes_per_target(nt);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int slice = lane & (S - 1);
-    const int i = it.y + lane / S;
-    const bool act = lane / S < nt;
-    const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
-    float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
-    stream_sources(uoff, uidx, range, b, pts, nullptr, sh, nullptr, [&](int m) {
+    // the grid strides over the items (launched with one block per item)
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int2 it = items[item];
+        const int b = it.x;
+        const int nt = min(64, range[b].y - it.y);
+        const int S = lanes_per_target(nt);
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int slice = lane & (S - 1);
+        const int i = it.y + lane / S;
+        const bool act = lane / S < nt;
+        const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
+        float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
+        stream_sources(uoff, uidx, range, b, pts, nullptr, sh, nullptr, [&](int m) {
 #pragma unroll 4
-        for (int j = w * S + slice; j < m; j += 4 * S) {
-            const float4 y = sh[j];
-            const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
-            const float ri = rsq(dx * dx + dy * dy + dz * dz);
-            const float qr = y.w * ri;
-            const float qr3 = qr * ri * ri;
-            v[0] += qr;
-            v[1] += qr3 * dx;
-            v[2] += qr3 * dy;
-            v[3] += qr3 * dz;
-        }
-    });
+            for (int j = w * S + slice; j < m; j += 4 * S) {
+                const float4 y = sh[j];
+                const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
+                const float ri = rsq(dx * dx + dy * dy + dz * dz);
+                const float qr = y.w * ri;
+                const float qr3 = qr * ri * ri;
+                v[0] += qr;
+                v[1] += qr3 * dx;
+                v[2] += qr3 * dy;
+                v[3] += qr3 * dz;
+            }
+        });
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = lane_sum(v[q], S);
-    wave_reduce<4>(v, red);
-    if (w == 0 && act && slice == 0) {
-        const float4 f = far[i];
-        const int j = perm[i];
-        if (pot) pot[j] = f.x + cst * v[0];
-        if (field) {
-            field[3 * size_t(j)] = f.y + cst * v[1];
-            field[3 * size_t(j) + 1] = f.z + cst * v[2];
-            field[3 * size_t(j) + 2] = f.w + cst * v[3];
-        }
+        for (int q = 0; q < 4; ++q) v[q] = lane_sum(v[q], S);
+        wave_reduce<4>(v, red);
+        if (w == 0 && act && slice == 0) nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
     }
 }
 
-// Backward near field and the combination
+// Backward near field, summed directly as the near part of the combination
 //   qbar_k = psi_k,  xbar_k = -ubar_k E_k - H_k Ebar_k - q_k E_psi,k
 // where E, H come from the charges q and psi, E_psi from monopoles ubar and
 // dipoles Ebar (psi = sum ubar K - Ebar . G).
-__global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items, const int2* __restrict__ range,
+__global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items, int n_items, const int2* __restrict__ range,
                                                  const int* __restrict__ uoff, const int* __restrict__ uidx,
                                                  const float4* __restrict__ pts, const float4* __restrict__ src2,
-                                                 const float* __restrict__ far, int64_t N,
-                                                 const int* __restrict__ perm, float cst, float* __restrict__ gq,
-                                                 float* __restrict__ gx) {
+                                                 float cst, float4* __restrict__ nearv) {
     __shared__ float4 sh[NF_STAGE];
     __shared__ float4 sh2[NF_STAGE];
     __shared__ float red[4][8][64];
-    const int2 it = items[blockIdx.x];
-    const int b = it.x;
-    const int nt = min(64, range[b].y - it.y);
-    const int S = lanes_per_target(nt);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int slice = lane & (S - 1);
-    const int i = it.y + lane / S;
-    const bool act = lane / S < nt;
-    const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
-    const float4 a = act ? src2[i] : make_float4(0, 0, 0, 0);
-    // The adjoint combination xbar_k = -ubar_k E_k - H_k Ebar_k - q_k E_psi,k
-    // is summed pair by pair (r = x_k - y_j, c applied at the end):
-    //   xbar += r [-(ubar_k q_j + q_k ubar_j)/r^3 - 3 (q_j r.Ebar_k - q_k r.Ebar_j)/r^5]
-    //           + (q_j Ebar_k - q_k Ebar_j)/r^3,
-    // with the target's Ebar_k taken out of the sum: v = (X xyz, S, T xyz, psi)
-    // and xbar = X + S Ebar_k - q_k T;  qbar = psi = sum ubar_j/r - r.Ebar_j/r^3.
-    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const float uk = a.x, qk = x.w;
-    stream_sources(uoff, uidx, range, b, pts, src2, sh, sh2, [&](int m) {
-        for (int j = w * S + slice; j < m; j += 4 * S) {
-            const float4 y = sh[j];
-            const float4 bj = sh2[j];
-            const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
-            const float ri = rsq(dx * dx + dy * dy + dz * dz);
-            const float ri2 = ri * ri;
-            const float ri3 = ri2 * ri;
-            const float ri5 = ri3 * ri2;
-            const float rk = dx * a.y + dy * a.z + dz * a.w;
-            const float rj = dx * bj.y + dy * bj.z + dz * bj.w;
-            const float t1 = uk * y.w + qk * bj.x;
-            const float t2 = y.w * rk - qk * rj;
-            const float coef = -ri3 * t1 - 3.f * ri5 * t2;
-            v[0] += coef * dx;
-            v[1] += coef * dy;
-            v[2] += coef * dz;
-            v[3] += y.w * ri3;
-            v[4] += bj.y * ri3;
-            v[5] += bj.z * ri3;
-            v[6] += bj.w * ri3;
-            v[7] += bj.x * ri - rj * ri3;
-        }
-    });
+    // the grid strides over the items (launched with one block per item)
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int2 it = items[item];
+        const int b = it.x;
+        const int nt = min(64, range[b].y - it.y);
+        const int S = lanes_per_target(nt);
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int slice = lane & (S - 1);
+        const int i = it.y + lane / S;
+        const bool act = lane / S < nt;
+        const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
+        const float4 a = act ? src2[i] : make_float4(0, 0, 0, 0);
+        // The adjoint combination xbar_k = -ubar_k E_k - H_k Ebar_k - q_k E_psi,k
+        // is summed pair by pair (r = x_k - y_j, c applied at the end):
+        //   xbar += r [-(ubar_k q_j + q_k ubar_j)/r^3 - 3 (q_j r.Ebar_k - q_k r.Ebar_j)/r^5]
+        //           + (q_j Ebar_k - q_k Ebar_j)/r^3,
+        // with the target's Ebar_k taken out of the sum: v = (X xyz, S, T xyz, psi)
+        // and xbar = X + S Ebar_k - q_k T;  qbar = psi = sum ubar_j/r - r.Ebar_j/r^3.
+        float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const float uk = a.x, qk = x.w;
+        stream_sources(uoff, uidx, range, b, pts, src2, sh, sh2, [&](int m) {
+            for (int j = w * S + slice; j < m; j += 4 * S) {
+                const float4 y = sh[j];
+                const float4 bj = sh2[j];
+                const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
+                const float ri = rsq(dx * dx + dy * dy + dz * dz);
+                const float ri2 = ri * ri;
+                const float ri3 = ri2 * ri;
+                const float ri5 = ri3 * ri2;
+                const float rk = dx * a.y + dy * a.z + dz * a.w;
+                const float rj = dx * bj.y + dy * bj.z + dz * bj.w;
+                const float t1 = uk * y.w + qk * bj.x;
+                const float t2 = y.w * rk - qk * rj;
+                const float coef = -ri3 * t1 - 3.f * ri5 * t2;
+                v[0] += coef * dx;
+                v[1] += coef * dy;
+                v[2] += coef * dz;
+                v[3] += y.w * ri3;
+                v[4] += bj.y * ri3;
+                v[5] += bj.z * ri3;
+                v[6] += bj.w * ri3;
+                v[7] += bj.x * ri - rj * ri3;
+            }
+        });
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = lane_sum(v[q], S);
-    wave_reduce<8>(v, red);
-    if (w == 0 && act && slice == 0) {
-        const float4 f = reinterpret_cast<const float4*>(far)[i];   // far part: xbar xyz, psi
-        const int j = perm[i];
-        if (gq) gq[j] = f.w + cst * v[7];
-        if (gx) {
-            gx[3 * size_t(j)] = f.x + cst * (v[0] + v[3] * a.y - qk * v[4]);
-            gx[3 * size_t(j) + 1] = f.y + cst * (v[1] + v[3] * a.z - qk * v[5]);
-            gx[3 * size_t(j) + 2] = f.z + cst * (v[2] + v[3] * a.w - qk * v[6]);
-        }
+        for (int q = 0; q < 8; ++q) v[q] = lane_sum(v[q], S);
+        wave_reduce<8>(v, red);
+        if (w == 0 && act && slice == 0)
+            nearv[i] = make_float4(cst * (v[0] + v[3] * a.y - qk * v[4]), cst * (v[1] + v[3] * a.z - qk * v[5]),
+                                   cst * (v[2] + v[3] * a.w - qk * v[6]), cst * v[7]);
     }
 }
 
@@ -228,16 +215,16 @@ void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const
     }
 }
 
-void launch_p2p_forward(kifmm_plan* P, float* potential, float* field, hipStream_t s) {
-    hipLaunchKernelGGL(k_p2p, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(), P->bx_range.as<int2>(),
-                       P->u_off.as<int>(), P->u_idx.as<int>(), P->pts.as<float4>(), P->far.as<float4>(),
-                       P->perm.as<int>(), float(P->c), potential, field);
+void launch_p2p_forward(kifmm_plan* P, hipStream_t s) {
+    hipLaunchKernelGGL(k_p2p, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(), int(P->n_items),
+                       P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), P->pts.as<float4>(),
+                       float(P->c), P->nearv.as<float4>());
 }
 
-void launch_p2p_backward(kifmm_plan* P, float* gq, float* gx, hipStream_t s) {
+void launch_p2p_backward(kifmm_plan* P, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p_bwd, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
-                       P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), P->pts.as<float4>(),
-                       P->src2.as<float4>(), P->far.as<float>(), P->N, P->perm.as<int>(), float(P->c), gq, gx);
+                       int(P->n_items), P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), P->pts.as<float4>(),
+                       P->src2.as<float4>(), float(P->c), P->nearv.as<float4>());
 }
 
 }  // namespace kifmm
