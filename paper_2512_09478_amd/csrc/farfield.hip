@@ -456,15 +456,10 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             float cur[CB][8];
-            // a column block none of whose targets has a source in this slot
-            // (a gap in the tree) skips its products; the test is wave-uniform
-            bool live[CB];
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                live[cb] = __ballot(col[cb] != nullptr) != 0;
+            for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
                 for (int i = 0; i < 8; ++i) cur[cb][i] = breg[cb][i];
-            }
             int nkc = kc + 1, nj = j;
             if (nkc == KC) {
                 nkc = 0;
@@ -481,13 +476,18 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
                         bh[cb][i] = h;
                         bl[cb][i] = (__bf16)(cur[cb][i] - (float)h);
                     }
+                // the fragments of row block rb + 1 are read while rb multiplies
+                uint4 nh = L[lane], nl = L[64 + lane];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
-                    const v8bf ah = as_bf8(L[rb * 128 + lane]);
-                    const v8bf al = as_bf8(L[rb * 128 + 64 + lane]);
+                    const v8bf ah = as_bf8(nh);
+                    const v8bf al = as_bf8(nl);
+                    if (rb + 1 < RB) {
+                        nh = L[(rb + 1) * 128 + lane];
+                        nl = L[(rb + 1) * 128 + 64 + lane];
+                    }
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
-                        if (!live[cb]) continue;
                         v4f c = acc[cb][rb];
                         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], c, 0, 0, 0);
                         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], c, 0, 0, 0);
@@ -505,7 +505,6 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
                                         __uint_as_float(u1.z), __uint_as_float(u1.w)};
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
-                        if (!live[cb]) continue;
                         v4f c = acc[cb][rb];
 #pragma unroll
                         for (int i = 0; i < 8; ++i)
