@@ -335,6 +335,9 @@ def main():
                    "name": w.name, "n": n, "p": w.p, "leaf_size": w.leaf_size, "path": head},
         "roofline": roofline(H, ops_n, head),
         "paths": {k: {"particles_per_s": n / (v["ms_per_step"] * 1e-3), "ms_per_step": v["ms_per_step"],
+                      "particles_per_s_without_tree": n / ((v["t_fwd_ms"] + v["t_adj_ms"]) * 1e-3),
+                      "particles_per_s_forward": n / (v["t_fwd_ms"] * 1e-3),
+                      "particles_per_s_adjoint": n / (v["t_adj_ms"] * 1e-3),
                       "t_tree_ms": v["t_tree_ms"], "t_fwd_ms": v["t_fwd_ms"], "t_adj_ms": v["t_adj_ms"],
                       "phases_fwd_ms": v["phases_fwd_ms"], "phases_adj_ms": v["phases_adj_ms"],
                       "roofline": roofline(v, ops_n, k)}

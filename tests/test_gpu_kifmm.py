@@ -117,6 +117,26 @@ def test_single_leaf_is_direct_sum(built):
     assert rel(u.cpu().numpy(), ud) < 1e-6 and rel(E.cpu().numpy(), Ed) < 1e-6
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_identical_charges_far_field_dominated(built, precision):
+    """The uniform 4,096-point shape with every charge 1 (the identical
+    particles of Section 3.1): the potential is dominated by the far field, so
+    this is a strict check of the far-field path.  Against the oracle at the
+    path's tolerance; against the direct sum at the method's own accuracy."""
+    say(f"identical charges {precision}")
+    w = workloads.make(1)
+    q1 = np.ones(w.n)
+    G = gpu_plan(w, precision=precision)
+    u, E = G.evaluate(torch.ones(w.n, dtype=torch.float32, device="cuda"))
+    u, E = u.cpu().numpy(), E.cpu().numpy()
+    uo, Eo = kifmm.forward(oracle_plan(w), q1)
+    eu, eE = rel(u, uo), rel(E, Eo)
+    ud, Ed, _ = direct.potential_field(w.positions, q1)
+    say(f"  vs oracle: u {eu:.2e} E {eE:.2e}; vs direct sum: u {rel(u, ud):.2e} E {rel(E, Ed):.2e}")
+    assert eu <= TOL[precision] and eE <= TOL[precision]
+    assert rel(u, ud) < 1e-3 and rel(E, Ed) < 1e-2
+
+
 def test_deterministic_repeat(built):
     say("repeatability")
     w = workloads.make(2, n=8000)

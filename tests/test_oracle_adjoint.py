@@ -95,3 +95,65 @@ def test_clump_in_uniform_field_has_torque_p_cross_E():
     p = 2 * l * d
     np.testing.assert_allclose(F[0], 0.0, atol=1e-15)
     np.testing.assert_allclose(Tq[0], np.cross(p, E0), rtol=1e-14)
+
+
+def _clump_case(seed=7, C=5, per=(1, 4)):
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(per[0], per[1] + 1, C)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    N = int(off[-1]) + 3          # three pebbles outside every clump
+    x = rng.standard_normal((N, 3))
+    q = rng.standard_normal(N)
+    E = rng.standard_normal((N, 3))
+    cen = rng.standard_normal((C, 3))
+    return x, q, E, off, cen
+
+
+def test_clump_vjp_matches_central_differences():
+    # L = Fbar.F + Tbar.T is bilinear in (q, E) and affine in x and X for fixed
+    # (q, E): central differences are exact up to rounding.
+    x, q, E, off, cen = _clump_case()
+    C = len(off) - 1
+    rng = np.random.default_rng(8)
+    Fb = rng.standard_normal((C, 3))
+    Tb = rng.standard_normal((C, 3))
+
+    def L(x_, q_, E_, c_):
+        F, T = clump.clump_reduce(x_, q_, E_, off, c_)
+        return float(np.sum(Fb * F) + np.sum(Tb * T))
+
+    qb, Eb, xb, Xb = clump.clump_vjp(x, q, E, off, cen, Fb, Tb)
+    h = 1e-6
+    for k in range(x.shape[0]):
+        dq = np.zeros_like(q)
+        dq[k] = h
+        assert abs((L(x, q + dq, E, cen) - L(x, q - dq, E, cen)) / (2 * h) - qb[k]) < 1e-7
+        for d in range(3):
+            dE = np.zeros_like(E)
+            dE[k, d] = h
+            assert abs((L(x, q, E + dE, cen) - L(x, q, E - dE, cen)) / (2 * h) - Eb[k, d]) < 1e-7
+            dx = np.zeros_like(x)
+            dx[k, d] = h
+            assert abs((L(x + dx, q, E, cen) - L(x - dx, q, E, cen)) / (2 * h) - xb[k, d]) < 1e-7
+    for c in range(C):
+        for d in range(3):
+            dc = np.zeros_like(cen)
+            dc[c, d] = h
+            assert abs((L(x, q, E, cen + dc) - L(x, q, E, cen - dc)) / (2 * h) - Xb[c, d]) < 1e-7
+    # pebbles outside every clump receive nothing
+    n_in = int(off[-1])
+    assert not qb[n_in:].any() and not Eb[n_in:].any() and not xb[n_in:].any()
+
+
+def test_clump_vjp_single_pebble_closed_form():
+    # one pebble at r from the centre in a field E, torque-only loss along z:
+    # T_z = q (r_x E_y - r_y E_x), so dL/dx = q (E_y, -E_x, 0) and dL/dq = T_z / q
+    x = np.array([[0.3, -0.2, 0.5]])
+    cen = np.zeros((1, 3))
+    q = np.array([2.0])
+    E = np.array([[1.0, 4.0, -3.0]])
+    qb, Eb, xb, Xb = clump.clump_vjp(x, q, E, np.array([0, 1]), cen, np.zeros((1, 3)), np.array([[0, 0, 1.0]]))
+    np.testing.assert_allclose(xb[0], [2 * 4.0, -2 * 1.0, 0.0])
+    np.testing.assert_allclose(qb[0], 0.3 * 4.0 - (-0.2) * 1.0)
+    np.testing.assert_allclose(Eb[0], 2.0 * np.array([0.2, 0.3, 0.0]))   # q (z x r)
+    np.testing.assert_allclose(Xb[0], -xb[0])
