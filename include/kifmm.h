@@ -167,6 +167,25 @@ int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field,
                        double* force, double* torque, void* stream);
 
 /*
+ * Backward of kifmm_clump_reduce (the vector-Jacobian product of the Section
+ * 2.4 aggregation) for given dL/dF_c and dL/dT_c, with r_k = x_k - X_c:
+ *   grad_charges[k]   = dL/dF_c . E_k + dL/dT_c . (r_k x E_k)
+ *   grad_field[k]     = q_k (dL/dF_c + dL/dT_c x r_k)
+ *   grad_positions[k] = q_k (E_k x dL/dT_c)
+ *   grad_centers[c]   = - sum_{k in c} grad_positions[k]
+ * Arguments as for kifmm_clump_reduce; grad_force, grad_torque: device [C][3]
+ * double (either may be NULL = 0); grad_charges [N] float, grad_field [N][3]
+ * float, grad_positions [N][3] float, grad_centers [C][3] double (each may be
+ * NULL).  These are the direct parts: the charge and position gradients of
+ * the whole map (q, x) -> (F_c, T_c) add kifmm_backward with grad_field as its
+ * dL/dE.  Pebbles after offsets[C] get zeros.  FP64 arithmetic, caller order.
+ */
+int kifmm_clump_backward(kifmm_handle h, const float* charges, const float* field,
+                         const int64_t* clump_offsets, int64_t C, const double* centers,
+                         const double* grad_force, const double* grad_torque, float* grad_charges,
+                         float* grad_field, float* grad_positions, double* grad_centers, void* stream);
+
+/*
  * Sizes of the plan (host out[10]): boxes, leaves, depth, V-list pairs,
  * near-field point pairs (P2P, self pairs included), W-list pairs, X-list
  * pairs, U-list leaf pairs, N, surface points n.

@@ -230,6 +230,23 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
     });
 }
 
+}  // extern "C"
+
+namespace {
+// Copies the CSR offsets to the host and checks them; returns offsets[C].
+int64_t check_offsets(kifmm_plan* P, const int64_t* clump_offsets, int64_t C, hipStream_t s) {
+    std::vector<int64_t> off(size_t(C) + 1);
+    KIFMM_HIP(hipMemcpyAsync(off.data(), clump_offsets, off.size() * 8, hipMemcpyDeviceToHost, s));
+    KIFMM_HIP(hipStreamSynchronize(s));
+    if (off[0] != 0 || off[size_t(C)] > P->N) throw Error(KIFMM_ERR_INPUT, "clump offsets out of range");
+    for (int64_t c = 0; c < C; ++c)
+        if (off[size_t(c) + 1] < off[size_t(c)]) throw Error(KIFMM_ERR_INPUT, "clump offsets not monotone");
+    return off[size_t(C)];
+}
+}  // namespace
+
+extern "C" {
+
 int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field, const int64_t* clump_offsets,
                        int64_t C, const double* centers, double* force, double* torque, void* stream) {
     return guarded([&] {
@@ -240,13 +257,26 @@ int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field,
             throw Error(KIFMM_ERR_ARG, "null pointer argument");
         hipStream_t s = static_cast<hipStream_t>(stream);
         P->last_stream = s;
-        std::vector<int64_t> off(size_t(C) + 1);
-        KIFMM_HIP(hipMemcpyAsync(off.data(), clump_offsets, off.size() * 8, hipMemcpyDeviceToHost, s));
-        KIFMM_HIP(hipStreamSynchronize(s));
-        if (off[0] != 0 || off[size_t(C)] > P->N) throw Error(KIFMM_ERR_INPUT, "clump offsets out of range");
-        for (int64_t c = 0; c < C; ++c)
-            if (off[size_t(c) + 1] < off[size_t(c)]) throw Error(KIFMM_ERR_INPUT, "clump offsets not monotone");
+        check_offsets(P, clump_offsets, C, s);
         launch_clump_reduce(P, charges, field, clump_offsets, C, centers, force, torque, s);
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_clump_backward(kifmm_handle h, const float* charges, const float* field, const int64_t* clump_offsets,
+                         int64_t C, const double* centers, const double* grad_force, const double* grad_torque,
+                         float* grad_charges, float* grad_field, float* grad_positions, double* grad_centers,
+                         void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (C < 0) throw Error(KIFMM_ERR_ARG, "negative clump count");
+        if (!charges || !field || (C > 0 && (!clump_offsets || !centers)))
+            throw Error(KIFMM_ERR_ARG, "null pointer argument");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        const int64_t covered = C > 0 ? check_offsets(P, clump_offsets, C, s) : 0;
+        launch_clump_backward(P, charges, field, clump_offsets, C, covered, centers, grad_force, grad_torque,
+                              grad_charges, grad_field, grad_positions, grad_centers, s);
         KIFMM_HIP(hipGetLastError());
     });
 }

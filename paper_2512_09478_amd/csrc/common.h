@@ -234,6 +234,9 @@ void launch_p2p_backward(kifmm_plan* P, hipStream_t s);
 // ---- clump.hip
 void launch_clump_reduce(kifmm_plan* P, const float* q, const float* E, const int64_t* off, int64_t C,
                          const double* centers, double* F, double* T, hipStream_t s);
+void launch_clump_backward(kifmm_plan* P, const float* q, const float* E, const int64_t* off, int64_t C,
+                           int64_t covered, const double* centers, const double* Fb, const double* Tb, float* qb,
+                           float* Eb, float* xb, double* Xb, hipStream_t s);
 // ---- api.cpp
 void record_phase(kifmm_plan* P, int idx, hipStream_t s);
 

@@ -141,6 +141,24 @@ class Plan:
                                             _ptr(T), _stream(stream)))
         return F, T
 
+    def clump_backward(self, charges, field, offsets, centers, grad_force=None, grad_torque=None, stream=None):
+        """Direct parts of the clump VJP: (dL/dq, dL/dE, dL/dx, dL/dX_c)."""
+        C = int(offsets.shape[0]) - 1
+        q = _need(charges, torch.float32, (self.n,), "charges")
+        E = _need(field, torch.float32, (self.n, 3), "field")
+        off = _need(offsets, torch.int64, (C + 1,), "offsets")
+        cen = _need(centers, torch.float64, (C, 3), "centers")
+        Fb = None if grad_force is None else _need(grad_force, torch.float64, (C, 3), "grad_force")
+        Tb = None if grad_torque is None else _need(grad_torque, torch.float64, (C, 3), "grad_torque")
+        dev = q.device
+        qb = torch.empty(self.n, dtype=torch.float32, device=dev)
+        Eb = torch.empty((self.n, 3), dtype=torch.float32, device=dev)
+        xb = torch.empty((self.n, 3), dtype=torch.float32, device=dev)
+        Xb = torch.empty((C, 3), dtype=torch.float64, device=dev)
+        check(_lib.lib().kifmm_clump_backward(self.handle, _ptr(q), _ptr(E), _ptr(off), C, _ptr(cen), _ptr(Fb),
+                                              _ptr(Tb), _ptr(qb), _ptr(Eb), _ptr(xb), _ptr(Xb), _stream(stream)))
+        return qb, Eb, xb, Xb
+
     # -- introspection
     def counts(self) -> dict:
         out = (ctypes.c_int64 * 10)()
@@ -214,3 +232,32 @@ class KifmmFunction(torch.autograd.Function):
 
 def kifmm(charges, positions, plan: Plan):
     return KifmmFunction.apply(charges, positions, plan)
+
+
+class ClumpFunction(torch.autograd.Function):
+    """(charges, field, positions, centers) -> per-clump (force, torque) with
+    the library's backward; compose with ``kifmm`` for the field, so that the
+    gradient of a clump loss reaches the charges and positions through both
+    the aggregation and the FMM adjoint."""
+
+    @staticmethod
+    def forward(ctx, charges, field, positions, centers, plan: Plan, offsets):
+        if positions.data_ptr() != plan.positions.data_ptr():
+            raise ValueError("positions must be the tensor the plan was built from")
+        F, T = plan.clump_reduce(charges, field, offsets, centers)
+        ctx.plan = plan
+        ctx.offsets = offsets
+        ctx.save_for_backward(charges, field, centers)
+        return F, T
+
+    @staticmethod
+    def backward(ctx, gF, gT):
+        charges, field, centers = ctx.saved_tensors
+        gF = None if gF is None else gF.contiguous().double()
+        gT = None if gT is None else gT.contiguous().double()
+        qb, Eb, xb, Xb = ctx.plan.clump_backward(charges, field.detach(), ctx.offsets, centers, gF, gT)
+        return qb, Eb, xb.to(torch.float64), Xb, None, None
+
+
+def clump_reduce(charges, field, positions, centers, plan: Plan, offsets):
+    return ClumpFunction.apply(charges, field, positions, centers, plan, offsets)

@@ -187,3 +187,62 @@ def test_clump_reduce_parity(built):
                                 E.cpu().numpy().astype(np.float64), w.clump_offsets, w.clump_centers)
     np.testing.assert_allclose(F.cpu().numpy(), Fo, rtol=1e-12, atol=1e-12 * np.abs(Fo).max())
     np.testing.assert_allclose(T.cpu().numpy(), To, rtol=1e-12, atol=1e-12 * np.abs(To).max())
+
+
+def test_clump_backward_parity(built):
+    """The clump aggregation's vector-Jacobian product against the oracle's, on
+    the field the GPU computed (both sides take it as input)."""
+    say("clump backward")
+    from oracle import clump
+    w = workloads.make(3, n=4000)
+    G = gpu_plan(w, 32, p=4)
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    u, E = G.evaluate(q)
+    C = len(w.clump_offsets) - 1
+    rng = np.random.default_rng(31)
+    Fb = rng.standard_normal((C, 3))
+    Tb = rng.standard_normal((C, 3))
+    off = torch.tensor(w.clump_offsets, device="cuda")
+    cen = torch.tensor(w.clump_centers, device="cuda")
+    qb, Eb, xb, Xb = G.clump_backward(q, E, off, cen, torch.tensor(Fb, device="cuda"),
+                                      torch.tensor(Tb, device="cuda"))
+    qo, Eo, xo, Xo = clump.clump_vjp(w.positions, np.asarray(w.charges, np.float32).astype(np.float64),
+                                     E.cpu().numpy().astype(np.float64), w.clump_offsets, w.clump_centers, Fb, Tb)
+    # FP64 arithmetic rounded once to FP32 (per-pebble outputs) or kept in FP64
+    for got, ref in ((qb, qo), (Eb, Eo), (xb, xo)):
+        assert rel(got.cpu().numpy(), ref) < 1e-6
+    assert rel(Xb.cpu().numpy(), Xo) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_clump_loss_gradient_through_fmm(built, precision):
+    """Autograd of a linear loss on the clump forces and torques, through the
+    aggregation and the FMM adjoint, against the oracle: the oracle's clump VJP
+    gives dL/dE, the oracle KIFMM VJP of that dL/dE, and the direct parts add."""
+    say(f"clump loss gradient {precision}")
+    from oracle import clump
+    from paper_2512_09478_amd import clump_reduce as creduce
+    from paper_2512_09478_amd import kifmm as kop
+    w = workloads.make(3, n=4000)
+    G = gpu_plan(w, 32, precision, p=4)
+    C = len(w.clump_offsets) - 1
+    rng = np.random.default_rng(32)
+    a = rng.standard_normal((C, 3))
+    b = rng.standard_normal((C, 3))
+    pos = G.positions.requires_grad_(True)
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda", requires_grad=True)
+    off = torch.tensor(w.clump_offsets, device="cuda")
+    cen = torch.tensor(w.clump_centers, device="cuda", requires_grad=True)
+    u, E = kop(q, pos, G)
+    F, T = creduce(q, E, pos, cen, G, off)
+    loss = (F * torch.tensor(a, device="cuda")).sum() + (T * torch.tensor(b, device="cuda")).sum()
+    loss.backward()
+    O = oracle_plan(w, 32, 4)
+    _, Eo = kifmm.forward(O, w.charges)
+    qd, Ed, xd, Xd = clump.clump_vjp(w.positions, w.charges, Eo, w.clump_offsets, w.clump_centers, a, b)
+    qf, xf = kifmm.vjp(O, w.charges, np.zeros(w.n), Ed)
+    eq = rel(q.grad.cpu().numpy(), qd + qf)
+    ex = rel(pos.grad.cpu().numpy(), xd + xf)
+    eX = rel(cen.grad.cpu().numpy(), Xd)
+    say(f"  rel-L2 dL/dq {eq:.3e} dL/dx {ex:.3e} dL/dX {eX:.3e}")
+    assert eq <= TOL[precision] and ex <= TOL[precision] and eX <= TOL[precision]
