@@ -52,10 +52,19 @@ WORKLOADS = {
 CPU_SAMPLE = {1: 4096, 2: 131072, 3: 131072, 4: 131072, 5: 65536}
 
 
-def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup):
+def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0):
     import torch
     plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root,
                 profile=True)
+    lo, hi = None, None
+    if move > 0:
+        # particles drift between long-range calls (the DEM loop): each step
+        # moves every position by N(0, move^2) per axis, kept inside the root
+        pos = pos.clone()
+        rlo = torch.tensor(w.root[0], dtype=torch.float64, device="cuda")
+        lo, hi = rlo, rlo + w.root[1] * (1 - 2.0 ** -20)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(2512)
     counts = plan.counts()
     phases, phases_adj = [], []
     clumps = None
@@ -63,6 +72,10 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup):
         clumps = (torch.tensor(w.clump_offsets, device="cuda"), torch.tensor(w.clump_centers, device="cuda"))
 
     def step(record):
+        if move > 0:
+            pos.add_(torch.randn(pos.shape, generator=gen, dtype=pos.dtype, device=pos.device), alpha=move)
+            torch.maximum(pos, lo, out=pos)
+            torch.minimum(pos, hi, out=pos)
         plan.rebuild(pos)
         u, E = plan.evaluate(q)
         if clumps is not None:
@@ -272,6 +285,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the number of charges")
     ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOADS),
                     help="workload generator (2 = the clustered 1M headline)")
+    ap.add_argument("--move", type=float, default=0.0,
+                    help="per-step random displacement (std per axis) of every particle before the re-tree")
     ap.add_argument("--paths", default="split_bf16,fp32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counter-run", metavar="PRECISION", help="short run for rocprofv3 counter passes")
@@ -304,7 +319,7 @@ def main():
     paths = {}
     for prec in args.paths.split(","):
         log(f"[bench] {prec}: N={n} steps={args.steps} warmup={args.warmup}")
-        paths[prec] = run_path(Plan, w, pos, q, gu, gE, prec, args.steps, args.warmup)
+        paths[prec] = run_path(Plan, w, pos, q, gu, gE, prec, args.steps, args.warmup, args.move)
         r = paths[prec]
         log(f"[bench] {prec}: {r['ms_per_step']:.3f} ms/step  tree {r['t_tree_ms']:.2f} fwd {r['t_fwd_ms']:.2f} "
             f"adj {r['t_adj_ms']:.2f}  phases {json.dumps({k: round(v, 3) for k, v in r['phases_fwd_ms'].items()})}"
@@ -331,7 +346,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (M2L bf16x3 split, FP32 accumulate)" if head == "split_bf16" else "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload] + "; step = re-tree + forward + adjoint",
+        "config": {"workload": WORKLOADS[args.workload] + "; step = re-tree + forward + adjoint"
+                               + (f"; particles move by N(0, {args.move}^2) per axis each step" if args.move else ""),
                    "name": w.name, "n": n, "p": w.p, "leaf_size": w.leaf_size, "path": head},
         "roofline": roofline(H, ops_n, head),
         "paths": {k: {"particles_per_s": n / (v["ms_per_step"] * 1e-3), "ms_per_step": v["ms_per_step"],

@@ -221,6 +221,27 @@ def forward(P: Plan, q, targets=None):
     return u, E
 
 
+def forward_dipoles(P: Plan, q, m, targets=None):
+    """Potential and field of monopoles q and dipoles m (a dipole m at y makes
+    psi(x) = -m . G(x - y)), in caller order or at caller indices ``targets``;
+    the same sweep as the charges, with the dipole part in every point-to-
+    surface and point-to-point sum."""
+    perm = P.tree.perm
+    qs = np.zeros(P.n) if q is None else np.asarray(q, dtype=np.float64)[perm]
+    ms = np.asarray(m, dtype=np.float64).reshape(-1, 3)[perm]
+    if targets is None:
+        u, E, _ = evaluate_sorted(P, qs, ms)
+        out_u = np.empty(P.n)
+        out_E = np.empty((P.n, 3))
+        out_u[perm] = u
+        out_E[perm] = E
+        return out_u, out_E
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(P.n)
+    u, E, _ = evaluate_sorted(P, qs, ms, targets=inv[np.asarray(targets)])
+    return u, E
+
+
 def vjp(P: Plan, q, ubar, Ebar, targets=None):
     """Exact vector-Jacobian product of the discrete map (q, x) -> (u, E), frozen tree.
 

@@ -142,3 +142,27 @@ def test_sampled_targets_match_full_evaluation():
     # same arithmetic up to BLAS blocking of differently sized batches
     np.testing.assert_allclose(us, u[idx], rtol=0, atol=1e-11 * np.abs(u).max())
     np.testing.assert_allclose(Es, E[idx], rtol=0, atol=1e-11 * np.abs(E).max())
+
+
+def test_dipole_sources_accuracy_and_linearity():
+    # monopoles plus dipoles on the clustered shape: the KIFMM sweep with dipole
+    # parts converges to the direct sum, and the map is linear in (q, m)
+    w = workloads.make(2, n=3000)
+    rng = np.random.default_rng(41)
+    m = rng.standard_normal((w.n, 3)) * 1e-3
+    P = kifmm.plan(w.positions, "laplace", 6, 48, True, 21, w.root)
+    u, E = kifmm.forward_dipoles(P, w.charges, m)
+    ud, Ed = direct.dipole_potential_field(w.positions, w.charges, m)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 1e-5
+    assert np.linalg.norm(E - Ed) / np.linalg.norm(Ed) < 1e-4
+    u1, E1 = kifmm.forward_dipoles(P, None, m)
+    u2, E2 = kifmm.forward(P, w.charges)
+    # FP64 rounding carried through the truncated pseudoinverse (amplification
+    # up to 1/tau = 1e7) bounds the difference by about 1e-9 of the largest value
+    np.testing.assert_allclose(u1 + u2, u, rtol=0, atol=1e-9 * np.abs(u).max())
+    np.testing.assert_allclose(E1 + E2, E, rtol=0, atol=1e-9 * np.abs(E).max())
+    # a lone dipole field: sampled targets equal the full evaluation
+    t = np.array([3, 77, 2999])
+    ut, Et = kifmm.forward_dipoles(P, None, m, targets=t)
+    np.testing.assert_allclose(ut, u1[t], rtol=0, atol=1e-11 * np.abs(u1).max())
+    np.testing.assert_allclose(Et, E1[t], rtol=0, atol=1e-11 * np.abs(E1).max())
