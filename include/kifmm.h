@@ -131,6 +131,21 @@ int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float
                    void* stream);
 
 /*
+ * Forward evaluation with dipole sources (the dipole granulates that eq. (1)
+ * with other kernels covers): every point carries a charge q_j (or none) and
+ * a dipole m_j, a dipole at y making psi(x) = -m . G(x - y), G = -grad K:
+ *   u_i = sum_{j : x_j != x_i} [q_j K(x_i - x_j) - m_j . G(x_i - x_j)],  E = -grad u.
+ *   charges    device [N] float or NULL (= 0), caller order.
+ *   dipoles    device [N][3] float, caller order.
+ *   potential, field as for kifmm_evaluate.
+ * The same sweep as kifmm_evaluate, with the dipole parts in every point-to-
+ * surface and point-to-point sum.  Afterwards kifmm_backward needs its
+ * charges (the reused forward pass is gone).
+ */
+int kifmm_evaluate_dipoles(kifmm_handle h, const float* charges, const float* dipoles, float* potential,
+                           float* field, void* stream);
+
+/*
  * Vector-Jacobian product of the discrete map (q, x) -> (u, E) of
  * kifmm_evaluate at the plan's positions with the tree frozen: given
  * grad_potential = dL/du and grad_field = dL/dE (either may be NULL = 0),

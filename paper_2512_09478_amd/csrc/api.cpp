@@ -76,18 +76,21 @@ void begin_phases(kifmm_plan* P, hipStream_t s) {
     KIFMM_HIP(hipEventRecord(P->events.ev[0], s));
 }
 
+enum NearKind { NEAR_FORWARD, NEAR_BACKWARD, NEAR_DIPOLES };
+
 // The near field does not depend on the far-field sweep: it runs on the side
 // stream, forked from `s` after P2M (so that the sweep's first kernel is not
 // queued behind it) and joined back before the leaf evaluation, which adds it
 // to the far field.
-void fork_near(kifmm_plan* P, bool backward, hipStream_t s) {
+void fork_near(kifmm_plan* P, NearKind kind, hipStream_t s) {
     P->nearq.make();
     hipStream_t t = P->nearq.s;
     KIFMM_HIP(hipEventRecord(P->nearq.fork, s));
     KIFMM_HIP(hipStreamWaitEvent(t, P->nearq.fork, 0));
     const bool prof = P->opt.profile && P->events.made;
     if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[0], t));
-    if (backward) launch_p2p_backward(P, t);
+    if (kind == NEAR_BACKWARD) launch_p2p_backward(P, t);
+    else if (kind == NEAR_DIPOLES) launch_p2p_dipoles(P, t);
     else launch_p2p_forward(P, t);
     if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[1], t));
     KIFMM_HIP(hipEventRecord(P->nearq.join, t));
@@ -196,12 +199,34 @@ int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float
         begin_phases(P, s);
         P->fwd_valid = false;
         launch_gather(P, charges, nullptr, nullptr, false, s);
-        run_sweep(P, 0, 1, s, true, [&] { fork_near(P, false, s); });
+        run_sweep(P, 0, 1, s, true, [&] { fork_near(P, NEAR_FORWARD, s); });
         join_near(P, s);
         run_far_eval(P, false, potential, field, s);
         record_phase(P, 6, s);
         P->has_phase = P->opt.profile ? 1 : 0;
         P->fwd_valid = true;
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_evaluate_dipoles(kifmm_handle h, const float* charges, const float* dipoles, float* potential,
+                           float* field, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!dipoles) throw Error(KIFMM_ERR_ARG, "null dipoles");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        begin_phases(P, s);
+        // the sources go through the adjoint right-hand side (1): monopoles and
+        // dipoles; the sorted points' charges are overwritten, so a later
+        // kifmm_backward must pass its charges
+        P->fwd_valid = false;
+        launch_gather(P, charges, charges, dipoles, true, s, true);
+        run_sweep(P, 1, 2, s, true, [&] { fork_near(P, NEAR_DIPOLES, s); });
+        join_near(P, s);
+        run_far_eval(P, false, potential, field, s, 1);
+        record_phase(P, 6, s);
+        P->has_phase = P->opt.profile ? 3 : 0;
         KIFMM_HIP(hipGetLastError());
     });
 }
@@ -220,7 +245,7 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
         // forward pass are still in place and only the adjoint sources are swept
         if (charges) P->fwd_valid = false;
         launch_gather(P, charges, grad_potential, grad_field, true, s);
-        run_sweep(P, charges ? 0 : 1, 2, s, true, [&] { fork_near(P, true, s); });
+        run_sweep(P, charges ? 0 : 1, 2, s, true, [&] { fork_near(P, NEAR_BACKWARD, s); });
         P->fwd_valid = true;
         join_near(P, s);
         run_far_eval(P, true, grad_charges, grad_positions, s);

@@ -225,12 +225,15 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s);
 void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between);
 // leaf evaluation; adds the near-field part and writes the caller-order
 // outputs (forward: potential, field; backward: grad_charges, grad_positions)
-void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s);
+void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs = 0);
 // ---- nearfield.hip
+// sorted points (x, y, z, q) when `charges` is given or `points` is set (q = 0
+// for null charges), and for `adjoint` the sorted (gpot, gfield) sources
 void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const float* gfield,
-                   bool adjoint, hipStream_t s);
+                   bool adjoint, hipStream_t s, bool points = false);
 void launch_p2p_forward(kifmm_plan* P, hipStream_t s);
 void launch_p2p_backward(kifmm_plan* P, hipStream_t s);
+void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s);
 // ---- clump.hip
 void launch_clump_reduce(kifmm_plan* P, const float* q, const float* E, const int64_t* off, int64_t C,
                          const double* centers, double* F, double* T, hipStream_t s);

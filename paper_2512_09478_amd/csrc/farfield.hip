@@ -1046,7 +1046,7 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
 }
 
 template <int NP>
-void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s) {
+void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s, int rhs) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
     const int b2 = P->depth >= 2 ? int(P->lev[2].start) : int(P->B);
@@ -1060,8 +1060,9 @@ void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s
     else
         hipLaunchKernelGGL((k_far<NP, false>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(), b2,
                            P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->w_off.as<int>(), P->w_idx.as<int>(),
-                           P->pts.as<float4>(), (const float4*)nullptr, P->phi_d.as<float>(), P->phi_u.as<float>(),
-                           stride, op.surf.as<float4>(), op.n, geo, float(P->c), P->N, fo);
+                           P->pts.as<float4>(), (const float4*)nullptr, P->phi_d.as<float>() + rhs * stride,
+                           P->phi_u.as<float>() + rhs * stride, stride, op.surf.as<float4>(), op.n, geo, float(P->c),
+                           P->N, fo);
 }
 
 }  // namespace
@@ -1078,14 +1079,14 @@ void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const 
     }
 }
 
-void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s) {
+void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs) {
     switch (P->npad) {
-        case 32: far_impl<32>(P, backward, out_a, out_b, s); break;
-        case 64: far_impl<64>(P, backward, out_a, out_b, s); break;
-        case 128: far_impl<128>(P, backward, out_a, out_b, s); break;
-        case 160: far_impl<160>(P, backward, out_a, out_b, s); break;
-        case 224: far_impl<224>(P, backward, out_a, out_b, s); break;
-        case 320: far_impl<320>(P, backward, out_a, out_b, s); break;
+        case 32: far_impl<32>(P, backward, out_a, out_b, s, rhs); break;
+        case 64: far_impl<64>(P, backward, out_a, out_b, s, rhs); break;
+        case 128: far_impl<128>(P, backward, out_a, out_b, s, rhs); break;
+        case 160: far_impl<160>(P, backward, out_a, out_b, s, rhs); break;
+        case 224: far_impl<224>(P, backward, out_a, out_b, s, rhs); break;
+        case 320: far_impl<320>(P, backward, out_a, out_b, s, rhs); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }

@@ -26,7 +26,7 @@ __global__ void k_gather(int64_t N, const float4* __restrict__ xs, const int* __
     int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
     if (i >= N) return;
     float4 x = xs[i];
-    x.w = q[perm[i]];
+    x.w = q ? q[perm[i]] : 0.f;
     pts[i] = x;
 }
 
@@ -134,6 +134,50 @@ __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int
     }
 }
 
+// Near field of monopoles q_j and dipoles m_j (src2 = (q, m) sorted):
+//   u += q_j/r - m_j.r/r^3,  E = -grad u += r (q_j/r^3 - 3 m_j.r/r^5) + m_j/r^3.
+__global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items, int n_items,
+                                                 const int2* __restrict__ range, const int* __restrict__ uoff,
+                                                 const int* __restrict__ uidx, const float4* __restrict__ pts,
+                                                 const float4* __restrict__ src2, float cst,
+                                                 float4* __restrict__ nearv) {
+    __shared__ float4 sh[NF_STAGE];
+    __shared__ float4 sh2[NF_STAGE];
+    __shared__ float red[4][4][64];
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int2 it = items[item];
+        const int b = it.x;
+        const int nt = min(64, range[b].y - it.y);
+        const int S = lanes_per_target(nt);
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int slice = lane & (S - 1);
+        const int i = it.y + lane / S;
+        const bool act = lane / S < nt;
+        const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
+        float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
+        stream_sources(uoff, uidx, range, b, pts, src2, sh, sh2, [&](int m) {
+            for (int j = w * S + slice; j < m; j += 4 * S) {
+                const float4 y = sh[j];
+                const float4 bj = sh2[j];
+                const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
+                const float ri = rsq(dx * dx + dy * dy + dz * dz);
+                const float ri2 = ri * ri;
+                const float ri3 = ri2 * ri;
+                const float rj = dx * bj.y + dy * bj.z + dz * bj.w;
+                v[0] += bj.x * ri - rj * ri3;
+                const float gh = bj.x * ri3 - 3.f * rj * ri3 * ri2;
+                v[1] += gh * dx + bj.y * ri3;
+                v[2] += gh * dy + bj.z * ri3;
+                v[3] += gh * dz + bj.w * ri3;
+            }
+        });
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = lane_sum(v[q], S);
+        wave_reduce<4>(v, red);
+        if (w == 0 && act && slice == 0) nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
+    }
+}
+
 // Backward near field, summed directly as the near part of the combination
 //   qbar_k = psi_k,  xbar_k = -ubar_k E_k - H_k Ebar_k - q_k E_psi,k
 // where E, H come from the charges q and psi, E_psi from monopoles ubar and
@@ -201,9 +245,9 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
 }  // namespace
 
 void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const float* gfield, bool adjoint,
-                   hipStream_t s) {
+                   hipStream_t s, bool points) {
     const int64_t N = P->N;
-    if (charges) {
+    if (charges || points) {
         P->pts.ensure(size_t(N) * 16);
         hipLaunchKernelGGL(k_gather, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, N, P->xs.as<float4>(),
                            P->perm.as<int>(), charges, P->pts.as<float4>());
@@ -219,6 +263,12 @@ void launch_p2p_forward(kifmm_plan* P, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(), int(P->n_items),
                        P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), P->pts.as<float4>(),
                        float(P->c), P->nearv.as<float4>());
+}
+
+void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s) {
+    hipLaunchKernelGGL(k_p2p_dip, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
+                       int(P->n_items), P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(),
+                       P->pts.as<float4>(), P->src2.as<float4>(), float(P->c), P->nearv.as<float4>());
 }
 
 void launch_p2p_backward(kifmm_plan* P, hipStream_t s) {

@@ -112,6 +112,16 @@ class Plan:
         self._new_forward_state()
         return u, E
 
+    def evaluate_dipoles(self, charges, dipoles, potential=True, field=True, stream=None):
+        """u, E of charges (or None) and point dipoles m at the plan's points."""
+        q = None if charges is None else _need(charges, torch.float32, (self.n,), "charges")
+        m = _need(dipoles, torch.float32, (self.n, 3), "dipoles")
+        u = torch.empty(self.n, dtype=torch.float32, device=m.device) if potential else None
+        E = torch.empty((self.n, 3), dtype=torch.float32, device=m.device) if field else None
+        self._fwd_token = None
+        check(_lib.lib().kifmm_evaluate_dipoles(self.handle, _ptr(q), _ptr(m), _ptr(u), _ptr(E), _stream(stream)))
+        return u, E
+
     def backward(self, charges, grad_potential=None, grad_field=None, stream=None):
         """dL/dq, dL/dx.  ``charges=None`` reuses the charges and forward
         densities of the last evaluate on this plan (no forward sweep)."""

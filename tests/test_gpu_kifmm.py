@@ -137,6 +137,34 @@ def test_identical_charges_far_field_dominated(built, precision):
     assert rel(u, ud) < 1e-3 and rel(E, Ed) < 1e-2
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_dipole_forward_parity(built, precision):
+    # monopoles plus point dipoles on the clustered shape, then dipoles alone;
+    # the dipole moments are scaled so both parts carry comparable weight
+    say(f"dipole forward parity {precision}")
+    w = workloads.make(2, n=8000)
+    rng = np.random.default_rng(43)
+    m = workloads.round_f32(rng.standard_normal((w.n, 3)) * 2e-3)
+    G = gpu_plan(w, 48, precision, p=6)
+    O = oracle_plan(w, 48, 6)
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    md = torch.tensor(m, dtype=torch.float32, device="cuda")
+    for charges, qo in ((q, w.charges), (None, None)):
+        u, E = G.evaluate_dipoles(charges, md)
+        uo, Eo = kifmm.forward_dipoles(O, qo, m)
+        eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
+        say(f"  charges={'yes' if charges is not None else 'no'}  rel-L2 u {eu:.3e}  E {eE:.3e}")
+        assert eu <= TOL[precision] and eE <= TOL[precision]
+    # the dipole pass overwrote the stored forward state: backward needs charges
+    from paper_2512_09478_amd import KifmmError
+    with pytest.raises(KifmmError):
+        G.backward(None, torch.ones(w.n, dtype=torch.float32, device="cuda"), None)
+    # and an ordinary evaluation afterwards is unaffected
+    u2, E2 = G.evaluate(q)
+    uo2, Eo2 = kifmm.forward(O, w.charges)
+    assert rel(u2.cpu().numpy(), uo2) <= TOL[precision] and rel(E2.cpu().numpy(), Eo2) <= TOL[precision]
+
+
 def test_deterministic_repeat(built):
     say("repeatability")
     w = workloads.make(2, n=8000)
