@@ -72,10 +72,11 @@ void oracle_direct(int64_t nt, const double* xt, int64_t ns, const double* ys,
 /* Near field over U lists.  Target t is point tidx[t] of the sorted arrays and
  * lies in leaf tleaf[t]; its sources are the points of every leaf A in
  * U(tleaf[t]) = uidx[uoff[tleaf[t]] .. uoff[tleaf[t]+1]), each leaf A holding
- * sorted points begin[A] .. end[A]. */
+ * sorted points begin[A] .. end[A].  With periodic images, entry k of the
+ * lists moves its leaf's points by ushift[3k .. 3k+2] (NULL: no shifts). */
 void oracle_p2p(int64_t nt, const int64_t* tidx, const int64_t* tleaf,
                 const int64_t* begin, const int64_t* end,
-                const int64_t* uoff, const int64_t* uidx,
+                const int64_t* uoff, const int64_t* uidx, const double* ushift,
                 const double* x, const double* s, const double* m, double c,
                 double* u, double* e, double* h)
 {
@@ -86,8 +87,15 @@ void oracle_p2p(int64_t nt, const int64_t* tidx, const int64_t* tleaf,
         double ut = 0.0, et[3] = {0.0, 0.0, 0.0}, ht[6] = {0, 0, 0, 0, 0, 0};
         for (int64_t k = uoff[L]; k < uoff[L + 1]; ++k) {
             int64_t A = uidx[k];
-            for (int64_t j = begin[A]; j < end[A]; ++j)
-                one_pair(xt, x + 3 * j, s[j], m ? m + 3 * j : NULL, c, &ut, et, h ? ht : NULL);
+            for (int64_t j = begin[A]; j < end[A]; ++j) {
+                double y[3] = {x[3 * j], x[3 * j + 1], x[3 * j + 2]};
+                if (ushift) {
+                    y[0] += ushift[3 * k];
+                    y[1] += ushift[3 * k + 1];
+                    y[2] += ushift[3 * k + 2];
+                }
+                one_pair(xt, y, s[j], m ? m + 3 * j : NULL, c, &ut, et, h ? ht : NULL);
+            }
         }
         if (u) u[t] = ut;
         if (e) { e[3 * t] = et[0]; e[3 * t + 1] = et[1]; e[3 * t + 2] = et[2]; }

@@ -38,7 +38,8 @@ from . import pairsum
 from .direct import KERNELS, hess_times
 from .operators import (RHO_DC, RHO_DE, RHO_UC, RHO_UE, TAU, Operators, field_matrices,
                         hessian_matrices, kernel_matrix, surface)
-from .tree import Lists, Tree, build_lists, build_tree
+from .periodic import lattice_far, moment_correction
+from .tree import Lists, Tree, build_lists, build_tree, decode
 
 
 @dataclasses.dataclass
@@ -51,6 +52,7 @@ class Plan:
     tau: float
     ops: Operators
     x: np.ndarray            # sorted positions [N,3] FP64
+    periodic: bool = False   # the root cube tiles space (Laplace, Ewald sum)
 
     @property
     def n(self):
@@ -63,12 +65,38 @@ class Plan:
 
 
 def plan(x, kernel="laplace", p=6, leaf_size=128, adaptive=True, max_depth=21, root=None,
-         tau=TAU) -> Plan:
+         tau=TAU, periodic=False) -> Plan:
+    """``periodic``: the explicit root cube ``root`` = (lo, side) is the unit
+    cell of a periodic system (Laplace only; every point inside the cell)."""
     x = np.asarray(x, dtype=np.float64)
+    if periodic and (root is None or kernel != "laplace"):
+        raise ValueError("periodic sums need the Laplace kernel and the cell as an explicit root")
     t = build_tree(x, leaf_size, adaptive, max_depth, root)
-    L = build_lists(t)
+    L = build_lists(t, periodic)
     c = KERNELS[kernel]
-    return Plan(t, L, kernel, c, p, tau, Operators(p, c, t.s, tau), x[t.perm])
+    return Plan(t, L, kernel, c, p, tau, Operators(p, c, t.s, tau), x[t.perm], periodic)
+
+
+def _lowest(P: Plan) -> int:
+    """Coarsest level with far-field interactions: 2 in free space; 0 when
+    periodic (the root receives the images beyond its neighbours)."""
+    return 0 if P.periodic else 2
+
+
+def _image(P: Plan, e):
+    """(box, displacement in length units) of a list entry."""
+    b, sh = decode(e)
+    return b, sh * P.tree.s
+
+
+def lattice_operator(P: Plan) -> np.ndarray:
+    """Root downward check potential from the root upward density for all
+    images at cube distance >= 2: c F(dc_i - ue_j), F the harmonic lattice kernel."""
+    t = P.tree
+    dc = surface(P.p, RHO_DC, 0, t.s)
+    ue = surface(P.p, RHO_UE, 0, t.s)
+    r = (dc[:, None, :] - ue[None, :, :]).reshape(-1, 3)
+    return P.c * lattice_far(r, t.s).reshape(dc.shape[0], ue.shape[0])
 
 
 def _octant(anchor):
@@ -76,10 +104,10 @@ def _octant(anchor):
 
 
 def upward(P: Plan, s: np.ndarray, m: Optional[np.ndarray]) -> np.ndarray:
-    """Upward equivalent densities phi_u [B, n] (zero above level 2)."""
+    """Upward equivalent densities phi_u [B, n] (zero above the coarsest far-field level)."""
     t, ops, c = P.tree, P.ops, P.c
     phi = np.zeros((t.nboxes, ops.n))
-    for l in range(t.depth, 1, -1):
+    for l in range(t.depth, _lowest(P) - 1, -1):
         w = ops.w(l)
         boxes = np.arange(t.level_start[l], t.level_start[l + 1])
         psi = np.zeros((boxes.shape[0], ops.n))
@@ -103,7 +131,8 @@ def downward(P: Plan, s, m, phi_u, needed: np.ndarray) -> np.ndarray:
     """Downward equivalent densities phi_d [B, n] for the boxes flagged in ``needed``."""
     t, ops, c, L = P.tree, P.ops, P.c, P.lists
     phi = np.zeros((t.nboxes, ops.n))
-    for l in range(2, t.depth + 1):
+    l0 = _lowest(P)
+    for l in range(l0, t.depth + 1):
         w = ops.w(l)
         boxes = np.arange(t.level_start[l], t.level_start[l + 1])
         boxes = boxes[needed[boxes]]
@@ -113,8 +142,9 @@ def downward(P: Plan, s, m, phi_u, needed: np.ndarray) -> np.ndarray:
         # V list, grouped by the offset between source and target
         groups = defaultdict(lambda: ([], []))
         for r, b in enumerate(boxes):
-            for a in L.V[b]:
-                d = tuple(int(v) for v in (t.anchor[a] - t.anchor[b]))
+            for e in L.V[b]:
+                a, sh = decode(e)
+                d = tuple(int(v) for v in (t.anchor[a] + sh * (1 << l) - t.anchor[b]))
                 groups[d][0].append(r)
                 groups[d][1].append(a)
         for d, (rows, srcs) in groups.items():
@@ -124,11 +154,15 @@ def downward(P: Plan, s, m, phi_u, needed: np.ndarray) -> np.ndarray:
             if not L.X[b]:
                 continue
             dc = surface(P.p, RHO_DC, t.center(b), w)
-            for a in L.X[b]:
+            for e in L.X[b]:
+                a, disp = _image(P, e)
                 a0, a1 = t.begin[a], t.end[a]
-                psi[r] += pairsum.direct(dc, P.x[a0:a1], s[a0:a1], None if m is None else m[a0:a1], c)[0]
+                psi[r] += pairsum.direct(dc, P.x[a0:a1] + disp, s[a0:a1], None if m is None else m[a0:a1], c)[0]
+        # periodic root: every image beyond the root's neighbours
+        if l == 0 and P.periodic:
+            psi += phi_u[boxes] @ lattice_operator(P).T
         # L2L from the parent
-        if l >= 3:
+        if l > l0:
             par = t.parent[boxes]
             octs = np.array([_octant(t.anchor[b]) for b in boxes])
             for o in range(8):
@@ -179,11 +213,12 @@ def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
         xt = P.x[targets[grp]]
         surf, dens = [], []
         lb = int(t.level[b])
-        if lb >= 2:
+        if lb >= _lowest(P):
             surf.append(surface(P.p, RHO_DE, t.center(b), ops.w(lb)))
             dens.append(phi_d[b])
-        for a in L.W[b]:
-            surf.append(surface(P.p, RHO_UE, t.center(a), ops.w(int(t.level[a]))))
+        for e in L.W[b]:
+            a, disp = _image(P, e)
+            surf.append(surface(P.p, RHO_UE, t.center(a) + disp, ops.w(int(t.level[a]))))
             dens.append(phi_u[a])
         if not surf:
             continue
@@ -195,12 +230,26 @@ def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
         E[grp] += El
         if hess:
             H[grp] += Hl
-    uoff, uidx = L.csr("U")
-    un, En, Hn = pairsum.p2p(targets, tleaf, t.begin, t.end, uoff, uidx, P.x, s, m, c, hess)
+    uoff, uenc = L.csr("U")
+    uidx = np.array([decode(e)[0] for e in uenc], dtype=np.int64)
+    ushift = None
+    if P.periodic:
+        ushift = np.array([decode(e)[1] * t.s for e in uenc], dtype=np.float64).reshape(-1, 3)
+    un, En, Hn = pairsum.p2p(targets, tleaf, t.begin, t.end, uoff, uidx, P.x, s, m, c, hess, ushift)
     u += un
     E += En
     if hess:
         H += Hn
+    if P.periodic:
+        # the non-harmonic part of the periodic kernel, summed in closed form
+        # (relative to the cell centre)
+        o = t.lo + 0.5 * t.s
+        uc, Ec = moment_correction(P.x[targets] - o, P.x - o, s, m, t.s, c)
+        u += uc
+        E += Ec
+        if hess:
+            # grad grad of (2 pi c / 3V) Q |x|^2
+            H[:, :3] += 4.0 * np.pi * c / (3.0 * t.s ** 3) * s.sum()
     return u, E, H
 
 

@@ -40,7 +40,7 @@ def _load():
             D = ctypes.c_double
             lib.oracle_direct.argtypes = [I, P, I, P, P, P, D, P, P, P]
             lib.oracle_direct.restype = None
-            lib.oracle_p2p.argtypes = [I, P, P, P, P, P, P, P, P, P, D, P, P, P]
+            lib.oracle_p2p.argtypes = [I, P, P, P, P, P, P, P, P, P, P, D, P, P, P]
             lib.oracle_p2p.restype = None
             _lib = lib
     return _lib
@@ -74,18 +74,20 @@ def direct(xt, ys, s, m=None, c=1.0, hess=False):
     return u, e, h
 
 
-def p2p(tidx, tleaf, begin, end, uoff, uidx, x, s, m=None, c=1.0, hess=False):
-    """Near-field sums over U lists for the sorted targets ``tidx``."""
+def p2p(tidx, tleaf, begin, end, uoff, uidx, x, s, m=None, c=1.0, hess=False, ushift=None):
+    """Near-field sums over U lists for the sorted targets ``tidx`` (``ushift``:
+    optional [len(uidx), 3] displacement of each list entry's points)."""
     lib = _load()
     i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)
     tidx, tleaf, begin, end, uoff, uidx = map(i64, (tidx, tleaf, begin, end, uoff, uidx))
     x = _c64(x, (-1, 3))
     s = _c64(s, (-1,))
     m = _c64(m, (-1, 3))
+    ushift = _c64(ushift, (-1, 3))
     nt = tidx.shape[0]
     u = np.zeros(nt)
     e = np.zeros((nt, 3))
     h = np.zeros((nt, 6)) if hess else None
-    lib.oracle_p2p(nt, _p(tidx), _p(tleaf), _p(begin), _p(end), _p(uoff), _p(uidx),
+    lib.oracle_p2p(nt, _p(tidx), _p(tleaf), _p(begin), _p(end), _p(uoff), _p(uidx), _p(ushift),
                    _p(x), _p(s), _p(m), float(c), _p(u), _p(e), _p(h))
     return u, e, h

@@ -212,6 +212,25 @@ def v_offset_index(d) -> int:
     raise ValueError("not a far offset")
 
 
+# A list entry names a box and, with periodic images, which image of it:
+# entry = box + code << SHIFT_BITS, the image shift s in {-1,0,1}^3 (in root
+# widths) coded as code = (9 (sx+1) + 3 (sy+1) + (sz+1) + 14) mod 27, so that
+# the unshifted image has code 0 and free-space lists are plain box indices.
+SHIFT_BITS = 26
+
+
+def encode(box: int, s) -> int:
+    raw = 9 * (int(s[0]) + 1) + 3 * (int(s[1]) + 1) + (int(s[2]) + 1)
+    return int(box) + (((raw + 14) % 27) << SHIFT_BITS)
+
+
+def decode(e: int):
+    """(box, shift as an int array of 3) of a list entry."""
+    e = int(e)
+    raw = ((e >> SHIFT_BITS) + 13) % 27
+    return e & ((1 << SHIFT_BITS) - 1), np.array([raw // 9 - 1, (raw // 3) % 3 - 1, raw % 3 - 1], dtype=np.int64)
+
+
 @dataclasses.dataclass
 class Lists:
     U: List[list]          # per box (empty unless leaf)
@@ -227,7 +246,10 @@ class Lists:
         return off, idx
 
 
-def build_lists(tree: Tree) -> Lists:
+def build_lists(tree: Tree, periodic: bool = False) -> Lists:
+    """U, V, W, X of every box.  With ``periodic`` the root cube tiles space:
+    neighbours wrap around at every level and each entry carries the image
+    shift of its box (Section 2.4 allows periodic boundaries)."""
     B = tree.nboxes
     lookup = {}
     for b in range(B):
@@ -238,22 +260,30 @@ def build_lists(tree: Tree) -> Lists:
     hi_all = ((tree.anchor << sh) + (1 << sh)).tolist()
     ext = [(l[0], l[1], l[2], h[0], h[1], h[2]) for l, h in zip(lo_all, hi_all)]
 
-    def adj(a, b):
+    def adj(a, sa, b):
+        """Image sa of box a touches box b (unshifted)."""
         ea, eb = ext[a], ext[b]
-        return (ea[0] <= eb[3] and eb[0] <= ea[3] and ea[1] <= eb[4] and eb[1] <= ea[4]
-                and ea[2] <= eb[5] and eb[2] <= ea[5])
+        o = [int(v) * NCELL for v in sa]
+        return (ea[0] + o[0] <= eb[3] and eb[0] <= ea[3] + o[0] and ea[1] + o[1] <= eb[4]
+                and eb[1] <= ea[4] + o[1] and ea[2] + o[2] <= eb[5] and eb[2] <= ea[5] + o[2])
 
     def colleagues(b):
+        """(box, image shift) of the same-level boxes touching b, b included."""
         l = int(tree.level[b])
         a = tree.anchor[b]
+        lim = 1 << l
         out = []
         for dx in (-1, 0, 1):
             for dy in (-1, 0, 1):
                 for dz in (-1, 0, 1):
-                    key = (l, int(a[0]) + dx, int(a[1]) + dy, int(a[2]) + dz)
-                    c = lookup.get(key)
+                    g = [int(a[0]) + dx, int(a[1]) + dy, int(a[2]) + dz]
+                    s = [0, 0, 0]
+                    if periodic:
+                        s = [v // lim for v in g]        # floor division: -1, 0 or 1
+                        g = [v % lim for v in g]
+                    c = lookup.get((l, g[0], g[1], g[2]))
                     if c is not None:
-                        out.append(c)
+                        out.append((c, tuple(s)))
         return out
 
     U = [[] for _ in range(B)]
@@ -264,47 +294,48 @@ def build_lists(tree: Tree) -> Lists:
 
     for b in range(B):
         l = int(tree.level[b])
-        if l >= 2:
+        if l >= 1:
             p = int(tree.parent[b])
-            for c in coll[p]:
+            for c, sc in coll[p]:
                 for ch in tree.children[c]:
-                    if ch >= 0 and not adj(int(ch), b):
-                        V[b].append(int(ch))
+                    if ch >= 0 and not adj(int(ch), sc, b):
+                        V[b].append(encode(int(ch), sc))
         if not tree.is_leaf[b]:
             continue
         # same-level and finer adjacent leaves, and W, by descending the colleagues
         u, w = set(), set()
 
-        def descend(a):
+        def descend(a, sa):
             for ch in tree.children[a]:
                 if ch < 0:
                     continue
                 ch = int(ch)
-                if adj(ch, b):
+                if adj(ch, sa, b):
                     if tree.is_leaf[ch]:
-                        u.add(ch)
+                        u.add(encode(ch, sa))
                     else:
-                        descend(ch)
+                        descend(ch, sa)
                 else:
-                    w.add(ch)
+                    w.add(encode(ch, sa))
 
-        for c in coll[b]:
+        for c, sc in coll[b]:
             if tree.is_leaf[c]:
-                u.add(c)
+                u.add(encode(c, sc))
             else:
-                descend(c)
+                descend(c, sc)
         # coarser adjacent leaves are colleagues of an ancestor
         a = int(tree.parent[b])
         while a >= 0:
-            for c in coll[a]:
-                if tree.is_leaf[c] and adj(c, b):
-                    u.add(c)
+            for c, sc in coll[a]:
+                if tree.is_leaf[c] and adj(c, sc, b):
+                    u.add(encode(c, sc))
             a = int(tree.parent[a])
         U[b] = sorted(u)
         W[b] = sorted(w)
     for b in range(B):
-        for a in W[b]:
-            X[a].append(b)
+        for e in W[b]:
+            a, sa = decode(e)
+            X[a].append(encode(b, -sa))
     for b in range(B):
         V[b].sort()
         X[b].sort()
