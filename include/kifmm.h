@@ -86,6 +86,19 @@ typedef struct {
                               root_lo <= x <= root_lo + root_side */
     int profile;           /* 1: record per-phase HIP events on the stream
                               (kifmm_get_phase_times) */
+    int periodic;          /* 1: the explicit root cube is the unit cell of a
+                              system periodic in x, y and z (Section 2.4); Laplace
+                              kernel only, explicit_root required, every point
+                              inside the cell.  The potential is the lattice sum
+                              read as the Ewald sum with conducting boundary (no
+                              surface term); for a cell with net charge the
+                              uniform neutralising background is implied.  Images
+                              within one cell come from the lists (entries carry
+                              the image shift, see kifmm_copy_list), images
+                              further away from a root lattice operator, and the
+                              non-harmonic part of the periodic kernel from the
+                              sources' moments in closed form.  0 (default): free
+                              space. */
 } kifmm_options;
 
 /* Fill *opts with the defaults listed above. */
@@ -222,6 +235,10 @@ int kifmm_copy_tree(kifmm_handle h, uint64_t* keys, int64_t* perm, int32_t* leve
  * Copy one interaction list (which = 'U', 'V', 'W' or 'X') as host CSR over
  * boxes: offsets [B+1] int64, indices [pairs] int64 (source boxes, ascending
  * within a row).  Pass offsets only (indices NULL) to size the second call.
+ * Periodic plans: an entry names box (entry & (2^26 - 1)) shifted by s root
+ * widths, s in {-1,0,1}^3 coded in entry >> 26 as (9 (sx+1) + 3 (sy+1) +
+ * (sz+1) + 14) mod 27 (0 = unshifted, so free-space entries are plain box
+ * indices); rows ascend in the coded value.
  */
 int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indices);
 

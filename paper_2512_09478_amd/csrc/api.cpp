@@ -38,6 +38,7 @@ void check_options(const kifmm_options& o) {
     if (o.max_depth < 0 || o.max_depth > kBits) throw Error(KIFMM_ERR_ARG, "max_depth must be in 0..21");
     if (o.precision != KIFMM_FP32 && o.precision != KIFMM_SPLIT_BF16) throw Error(KIFMM_ERR_ARG, "unknown precision");
     if (!(o.pinv_rtol > 0.0 && o.pinv_rtol < 1.0)) throw Error(KIFMM_ERR_ARG, "pinv_rtol must be in (0, 1)");
+    if (o.periodic && !o.explicit_root) throw Error(KIFMM_ERR_ARG, "a periodic plan needs the cell as an explicit root");
     if (o.explicit_root) {
         int e = 0;
         double m = frexp(o.root_side, &e);
@@ -58,6 +59,10 @@ void alloc_densities(kifmm_plan* P, hipStream_t s) {
     }
     P->psi_m.ensure(size_t(kM2LSplit) * bytes);
     P->nearv.ensure(size_t(P->N) * 16);
+    if (P->periodic) {
+        P->mom.ensure(2 * 16 * sizeof(double));
+        P->mom_part.ensure(size_t(kMomentBlocks) * 16 * sizeof(double));
+    }
 }
 
 kifmm_plan* checked(kifmm_handle h) {
@@ -133,6 +138,8 @@ int kifmm_setup_ex(const double* positions, int64_t N, int kernel, int p, int le
         if (!positions) throw Error(KIFMM_ERR_ARG, "null positions");
         if (N < 1 || N >= (int64_t(1) << 31)) throw Error(KIFMM_ERR_ARG, "N must be in 1..2^31-1");
         if (kernel != KIFMM_LAPLACE && kernel != KIFMM_GRAVITY) throw Error(KIFMM_ERR_ARG, "unknown kernel");
+        if (opts && opts->periodic && kernel != KIFMM_LAPLACE)
+            throw Error(KIFMM_ERR_ARG, "periodic sums are defined for the Laplace kernel only");
         if (p < 2 || p > 8) throw Error(KIFMM_ERR_ARG, "p must be in 2..8");
         if (leaf_size < 1) throw Error(KIFMM_ERR_ARG, "leaf_size must be >= 1");
         kifmm_options o;
@@ -147,7 +154,9 @@ int kifmm_setup_ex(const double* positions, int64_t N, int kernel, int p, int le
         P->leaf = leaf_size;
         P->opt = o;
         P->N = N;
+        P->periodic = o.periodic != 0;
         P->ops = &get_operators(p, o.pinv_rtol);
+        if (P->periodic) (void)get_lattice_operator(p, o.pinv_rtol);
         P->n = P->ops->n;
         P->npad = P->ops->npad;
         P->last_stream = s;
@@ -380,16 +389,34 @@ int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indic
             idx.resize(size_t(off[size_t(B)]));
             if (!idx.empty()) KIFMM_HIP(hipMemcpy(idx.data(), ix.p, idx.size() * 4, hipMemcpyDeviceToHost));
         } else if (which == 'V') {
-            int64_t b2 = P->depth >= 2 ? P->lev[2].start : B;
+            const int64_t b2 = P->bfar;
             std::vector<int> vd(size_t(B - b2) * kVPerOct);
             if (!vd.empty()) KIFMM_HIP(hipMemcpy(vd.data(), P->vdense.p, vd.size() * 4, hipMemcpyDeviceToHost));
+            std::vector<int4> anc;
+            if (P->periodic) {
+                anc.resize(size_t(B));
+                KIFMM_HIP(hipMemcpy(anc.data(), P->bx_anchor.p, anc.size() * sizeof(int4), hipMemcpyDeviceToHost));
+            }
             off[0] = 0;
             for (int64_t b = 0; b < B; ++b) {
                 if (b >= b2) {
                     size_t at = idx.size();
                     for (int j = 0; j < kVPerOct; ++j) {
                         int v = vd[size_t(b - b2) * kVPerOct + j];
-                        if (v >= 0) idx.push_back(v);
+                        if (v < 0) continue;
+                        if (P->periodic) {
+                            // the slot's cell a + d wraps around the root: record the image shift
+                            const int4 a = anc[size_t(b)];
+                            const int o = ((a.x & 1) << 2) | ((a.y & 1) << 1) | (a.z & 1);
+                            int d[3];
+                            v_slot_offset(o, j, d);
+                            const int lim = 1 << a.w;
+                            const int g[3] = {a.x + d[0], a.y + d[1], a.z + d[2]};
+                            int sh[3];
+                            for (int k = 0; k < 3; ++k) sh[k] = g[k] < 0 ? -1 : (g[k] >= lim ? 1 : 0);
+                            v = img_encode(v, sh[0], sh[1], sh[2]);
+                        }
+                        idx.push_back(v);
                     }
                     std::sort(idx.begin() + at, idx.end());
                 }

@@ -18,6 +18,7 @@ constexpr int kNumV = 316;             // far offsets in [-3,3]^3 minus [-1,1]^3
 constexpr int kVPerOct = 189;          // V-list offsets reachable from one octant
 constexpr int kMaxLevels = 22;
 constexpr int kM2LSplit = 4;          // M2L V slots split over this many blocks per tile
+constexpr int kMomentBlocks = 256;    // blocks of the periodic moment reduction
 
 // Error carrying a status code; caught at the ABI.
 struct Error : std::runtime_error {
@@ -32,6 +33,31 @@ struct Error : std::runtime_error {
             throw ::kifmm::Error(e_ == hipErrorOutOfMemory ? KIFMM_ERR_OOM : KIFMM_ERR_HIP, \
                                  std::string(#call) + ": " + hipGetErrorString(e_));      \
     } while (0)
+
+// List entries with periodic images: entry = box | code << kShiftBits, the
+// image shift s in {-1,0,1}^3 (in root widths) coded as
+// (9 (sx+1) + 3 (sy+1) + (sz+1) + 14) mod 27, so that the unshifted image has
+// code 0 and free-space entries are plain box indices.
+constexpr int kShiftBits = 26;
+constexpr int kBoxMask = (1 << kShiftBits) - 1;
+
+__host__ __device__ inline int img_encode(int box, int sx, int sy, int sz) {
+    const int raw = 9 * (sx + 1) + 3 * (sy + 1) + (sz + 1);
+    return box | (((raw + 14) % 27) << kShiftBits);
+}
+__host__ __device__ inline int img_box(int e) { return e & kBoxMask; }
+__host__ __device__ inline void img_shift(int e, int& sx, int& sy, int& sz) {
+    const int raw = ((e >> kShiftBits) + 13) % 27;
+    sx = raw / 9 - 1;
+    sy = (raw / 3) % 3 - 1;
+    sz = raw % 3 - 1;
+}
+// the same box seen from the other side: shift negated
+__host__ __device__ inline int img_flip(int e) {
+    int sx, sy, sz;
+    img_shift(e, sx, sy, sz);
+    return img_encode(img_box(e), -sx, -sy, -sz);
+}
 
 // Grow-only device buffer.
 // A few pinned host words for the small device-to-host reads of the tree
@@ -108,7 +134,13 @@ struct Operators {
     DBuf m2l_f32;      // [316][npad/32 chunks][npad/16 row blocks][2][64] x 16 B (FP32 fragments)
     DBuf m2l_bf16;     // same shape, bf16 hi half then lo half
     std::vector<double> sigma;   // singular values of K(uc, ue), descending
+    std::vector<double> svd_u, svd_v;   // its singular vectors (n x n row-major, FP64)
 };
+
+// Periodic root operator (unit cell, FP64 [n][n] row-major on the device):
+// the root downward equivalent density from the root upward density for
+// every image at cube distance two or more, DC2E F(dc - ue).
+const DBuf& get_lattice_operator(int p, double tau);
 
 // Returns the (cached, process-wide) operators for this device.
 const Operators& get_operators(int p, double tau);
@@ -170,6 +202,8 @@ struct kifmm_plan {
     double lo[3] = {0, 0, 0}, side = 1;
     int depth = 0;
     int64_t B = 0, nleaves = 0;
+    bool periodic = false;  // the root cube is the unit cell of a periodic system
+    int64_t bfar = 0;       // first box with a downward density (level 2, or the root when periodic)
     std::vector<kifmm::LevelInfo> lev;
     int64_t counts[10] = {};
     hipStream_t last_stream = nullptr;
@@ -208,6 +242,8 @@ struct kifmm_plan {
     kifmm::DBuf pts;        // float4 [N] sorted (x, y, z, q)
     kifmm::DBuf src2;       // float4 [N] sorted (ubar, Ebar) for the adjoint sweep
     kifmm::DBuf nearv;      // float4 [N] sorted near-field part: (u, E) or (xbar, qbar)
+    kifmm::DBuf mom;        // periodic: double [rhs][16] source moments about the cell centre
+    kifmm::DBuf mom_part;   // their per-block partial sums
     // scratch
     kifmm::DBuf tmp_a, tmp_b, tmp_c, tmp_d, tmp_e, tmp_f, scan_tmp, flag;
     kifmm::PhaseEvents events;
@@ -221,6 +257,8 @@ namespace kifmm {
 
 // ---- tree.hip
 void build_tree(kifmm_plan* P, const double* positions, hipStream_t s);
+// offset (in box widths) from a box at octant o to the source of its V slot j
+void v_slot_offset(int o, int j, int d[3]);
 // ---- farfield.hip
 void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between);
 // leaf evaluation; adds the near-field part and writes the caller-order

@@ -43,11 +43,16 @@ struct BoxGeom {
     double side;
 };
 
-__device__ inline void box_frame(const BoxGeom& g, int4 a, float c[3], float& invw, float& w) {
+// Centre (FP64 to FP32), width and inverse width of a box; `sgn` times the
+// image shift of list entry e (whole root widths) is added to the centre.
+__device__ inline void box_frame(const BoxGeom& g, int4 a, float c[3], float& invw, float& w, int e = 0,
+                                 int sgn = 1) {
+    int sx, sy, sz;
+    img_shift(e, sx, sy, sz);
     double wd = ldexp(g.side, -a.w);
-    c[0] = float(g.lo[0] + (double(a.x) + 0.5) * wd);
-    c[1] = float(g.lo[1] + (double(a.y) + 0.5) * wd);
-    c[2] = float(g.lo[2] + (double(a.z) + 0.5) * wd);
+    c[0] = float(g.lo[0] + (double(a.x) + 0.5) * wd + sgn * sx * g.side);
+    c[1] = float(g.lo[1] + (double(a.y) + 0.5) * wd + sgn * sy * g.side);
+    c[2] = float(g.lo[2] + (double(a.z) + 0.5) * wd + sgn * sz * g.side);
     w = float(wd);
     invw = float(ldexp(1.0, a.w) / g.side);
 }
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(2 * NP) void k_p2m(const int* __restrict__ leaves, 
     __shared__ float4 sh2[256];
     __shared__ float red[NP];
     const int b = leaves[blockIdx.x];
-    if (b < b2) return;   // leaves above level 2 have no far field
+    if (b < b2) return;   // leaves above the first far-field level have no far field
     const int4 a = anchor[b];
     float c[3], invw, w;
     box_frame(geo, a, c, invw, w);
@@ -275,14 +280,16 @@ __global__ __launch_bounds__(2 * NP) void k_p2l(const int* __restrict__ xboxes, 
     __shared__ float red[NP];
     const int b = xboxes[blockIdx.x];
     const int4 a = anchor[b];
-    float c[3], invw, w;
-    box_frame(geo, a, c, invw, w);
     const int i = threadIdx.x % NP, slice = threadIdx.x / NP;
     const bool act = i < n;
     const float4 s = act ? surf[i] : make_float4(0, 0, 0, 0);   // downward check surface
     float acc = 0.f;
     for (int k = xoff[b]; k < xoff[b + 1]; ++k) {
-        const int2 r = range[xidx[k]];
+        const int e = xidx[k];
+        const int2 r = range[img_box(e)];
+        // a source image shifted by +s cell widths is the target frame shifted by -s
+        float c[3], invw, w;
+        box_frame(geo, a, c, invw, w, e, -1);
         points_to_surface<NP>(acc, pts, src2, r.x, r.y, c, invw, s, act, slice, sh, sh2);
     }
     acc = add_slices<NP>(acc, i, slice, red);
@@ -715,7 +722,26 @@ struct FarOut {
     const int* perm;       // sorted position -> caller index
     float* a;              // forward: potential [N] | backward: grad_charges [N] (either may be null)
     float* b;              // forward: field [N][3]  | backward: grad_positions [N][3]
+    // periodic: source moments (Q, M, S2, D, D.y) about the cell centre o of
+    // the evaluated right-hand side (backward: the forward charges, then the
+    // adjoint sources 16 doubles further), null in free space; k1 = 2 pi c / (3 V)
+    const double* mom;
+    double o[3];
+    double k1;
 };
+
+// The non-harmonic part k1 |x - y|^2 of the periodic kernel summed over the
+// sources in closed form, at y (relative to the cell centre): potential and
+// field of monopoles s_j and dipoles m_j with moments
+//   Q = sum s, M = sum s y, S2 = sum s |y|^2, D = sum m, DY = sum m . y.
+__device__ inline void moment_terms(const double* m, double k1, const double y[3], double& u, double E[3]) {
+    const double Q = m[0], S2 = m[4], DY = m[8];
+    const double yy = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    const double ym = y[0] * m[1] + y[1] * m[2] + y[2] * m[3];
+    const double yd = y[0] * m[5] + y[1] * m[6] + y[2] * m[7];
+    u = k1 * (Q * yy - 2.0 * ym + S2 + 2.0 * yd - 2.0 * DY);
+    for (int d = 0; d < 3; ++d) E[d] = 2.0 * k1 * (m[1 + d] - m[5 + d] - Q * y[d]);
+}
 
 __device__ inline int far_lanes(int nt) { return nt <= 8 ? 8 : nt <= 16 ? 4 : nt <= 32 ? 2 : 1; }
 
@@ -725,8 +751,8 @@ __device__ inline float far_sum(float v, int S) {
 }
 
 // Work item = (leaf, first target), up to 64 targets, launched heaviest first.
-// The sources are the leaf's own downward density (from level 2) and its
-// W-list upward densities.  Each source is staged in LDS as (surface point,
+// The sources are the leaf's own downward density (from the first far-field
+// level) and its W-list upward densities (at their image positions).  Each source is staged in LDS as (surface point,
 // density) in box units, padded to NP entries with zero density at a real
 // surface point; its NP entries are dealt to the four waves and to the S
 // lanes of a target inside a wave (4 S slices, static trip count).  No
@@ -757,7 +783,8 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
     for (int q = 0; q < NV; ++q) v[q] = 0.f;
     for (int k = 0; k < nsrc; ++k) {
         const bool own = self && k == 0;
-        const int A = own ? b : widx[woff[b] + k - self];
+        const int e = own ? b : widx[woff[b] + k - self];
+        const int A = img_box(e);
         const float* D = (own ? phi_d : phi_u) + size_t(A) * NP;
         const float4* SF = own ? surf + NP : surf;   // downward (2.95) or upward (1.05) equivalent surface
         __syncthreads();   // the previous source is no longer read
@@ -769,7 +796,7 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
         }
         __syncthreads();
         float c[3], invw, wd;
-        box_frame(geo, anchor[A], c, invw, wd);
+        box_frame(geo, anchor[A], c, invw, wd, e);
         const float xx = (x.x - c[0]) * invw, xy = (x.y - c[1]) * invw, xz = (x.z - c[2]) * invw;
         const float vx = eb.y * invw, vy = eb.z * invw, vz = eb.w * invw;   // Ebar in box units
         const float uk = eb.x, qk = x.w;
@@ -830,6 +857,25 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
         for (int q = 0; q < NV; ++q)
             v[q] = cst * (((red[q * 64 + lane] + red[(NV + q) * 64 + lane]) + red[(2 * NV + q) * 64 + lane]) +
                           red[(3 * NV + q) * 64 + lane]);
+        if (out.mom) {
+            // periodic: the moment terms, added to the far part in FP64
+            const double y[3] = {double(x.x) - out.o[0], double(x.y) - out.o[1], double(x.z) - out.o[2]};
+            double u0, E0[3];
+            moment_terms(out.mom, out.k1, y, u0, E0);
+            if (!BWD) {
+                v[0] = float(double(v[0]) + u0);
+                for (int d = 0; d < 3; ++d) v[1 + d] = float(double(v[1 + d]) + E0[d]);
+            } else {
+                // xbar -= ubar E + H Ebar + q E_psi with H = 2 k1 Q I; qbar += psi
+                double u1, E1[3];
+                moment_terms(out.mom + 16, out.k1, y, u1, E1);
+                const double eb3[3] = {eb.y, eb.z, eb.w};
+                for (int d = 0; d < 3; ++d)
+                    v[d] = float(double(v[d]) - double(eb.x) * E0[d] - 2.0 * out.k1 * out.mom[0] * eb3[d] -
+                                 double(x.w) * E1[d]);
+                v[3] = float(double(v[3]) + u1);
+            }
+        }
         // far + near, written in caller order
         const float4 nr = out.nearv[i];
         const size_t j = size_t(out.perm[i]);
@@ -876,6 +922,62 @@ __global__ __launch_bounds__(256) void k_far(const int2* __restrict__ items, int
     default: KIFMM_FAR_ITEM(1); break;
     }
 #undef KIFMM_FAR_ITEM
+}
+
+// Periodic moments of one right-hand side (sources s = pts.w, or with `src2`
+// monopoles src2.x and dipoles src2.yzw) about the cell centre o, in FP64:
+// per-block partials in a fixed order, then one block sums the partials.
+__global__ __launch_bounds__(256) void k_moments(int64_t N, const float4* __restrict__ pts,
+                                                 const float4* __restrict__ src2, double ox, double oy, double oz,
+                                                 double* __restrict__ part) {
+    __shared__ double red[9][256];
+    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256) {
+        const float4 p = pts[i];
+        const double y[3] = {double(p.x) - ox, double(p.y) - oy, double(p.z) - oz};
+        double sj = p.w, m[3] = {0, 0, 0};
+        if (src2) {
+            const float4 t = src2[i];
+            sj = t.x;
+            m[0] = t.y;
+            m[1] = t.z;
+            m[2] = t.w;
+        }
+        a[0] += sj;
+        for (int d = 0; d < 3; ++d) a[1 + d] += sj * y[d];
+        a[4] += sj * (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+        for (int d = 0; d < 3; ++d) a[5 + d] += m[d];
+        a[8] += m[0] * y[0] + m[1] * y[1] + m[2] * y[2];
+    }
+    for (int q = 0; q < 9; ++q) red[q][threadIdx.x] = a[q];
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < 9; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 9) part[size_t(blockIdx.x) * 16 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_moments_sum(const double* __restrict__ part, int nb, double* __restrict__ mom) {
+    const int q = threadIdx.x;
+    if (q >= 16) return;
+    double t = 0.0;
+    if (q < 9)
+        for (int b = 0; b < nb; ++b) t += part[size_t(b) * 16 + q];
+    mom[q] = t;
+}
+
+// Periodic root: downward equivalent density from the root upward density,
+// phi_d = R phi_u with R = DC2E F (FP64 [n][n]); padded entries are zero.
+__global__ void k_lattice(const double* __restrict__ R, int n, int np, const float* __restrict__ phi_u,
+                          float* __restrict__ phi_d) {
+    const int i = threadIdx.x;
+    if (i >= np) return;
+    double acc = 0.0;
+    if (i < n)
+        for (int j = 0; j < n; ++j) acc += R[size_t(i) * n + j] * double(phi_u[j]);
+    phi_d[i] = float(acc);
 }
 
 __global__ void k_fill0(float* __restrict__ p, size_t n) {
@@ -926,6 +1028,12 @@ const VOps* vops_device() {
     return d->as<VOps>();
 }
 
+// Coarsest level with V lists: 2 in free space, 1 when periodic (the children
+// of the root see the images of its neighbours); the root itself then
+// receives the farther images through the lattice operator.
+int first_v_level(const kifmm_plan* P) { return P->periodic ? 1 : 2; }
+int first_down_level(const kifmm_plan* P) { return P->periodic ? 0 : 2; }
+
 // M2L for all levels; nrhs = 2 treats densities rhs 0 and 1 together (the
 // two columns share the target, the source and the operator), otherwise the
 // densities of right-hand side `rhs`.
@@ -933,15 +1041,16 @@ template <int NP>
 void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
     const Operators& op = *P->ops;
     const int depth = P->depth;
-    if (depth < 2) return;
-    const int b2 = int(P->lev[2].start);
+    const int lv = first_v_level(P);
+    if (depth < lv) return;
+    const int b2 = int(P->bfar);
     const int nsplit = M2L_SPLIT;
     P->m2l_split_used = nsplit;
     const int TG = M2L_CB / nrhs;
     const int per_block = WAVES * TG * 16;
     TaskTable tt{};
     int blocks = 0;
-    for (int l = 2; l <= depth; ++l) {
+    for (int l = lv; l <= depth; ++l) {
         const LevelInfo& pl = P->lev[l - 1];
         int groups = nblk(pl.nl_count, per_block);
         tt.first[tt.nlev] = blocks;
@@ -983,13 +1092,24 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
     const float4* pts = P->pts.as<float4>();
     const float4* surf = op.surf.as<float4>();
     const int depth = P->depth;
-    if (depth < 2) {
+    const int ld = first_down_level(P);
+    if (P->periodic) {
+        // moments of every right-hand side for the closed-form part of the kernel
+        for (int r = r0; r < r1; ++r) {
+            hipLaunchKernelGGL(k_moments, dim3(kMomentBlocks), dim3(256), 0, s, int64_t(P->N), pts,
+                               r ? P->src2.as<float4>() : nullptr, P->lo[0] + 0.5 * P->side,
+                               P->lo[1] + 0.5 * P->side, P->lo[2] + 0.5 * P->side, P->mom_part.as<double>());
+            hipLaunchKernelGGL(k_moments_sum, dim3(1), dim3(64), 0, s, P->mom_part.as<double>(), kMomentBlocks,
+                               P->mom.as<double>() + 16 * r);
+        }
+    }
+    if (depth < ld) {
         if (rec) record_phase(P, 0, s);
         between();
         if (rec) for (int k = 1; k < 5; ++k) record_phase(P, k, s);
         return;
     }
-    const int b2 = int(P->lev[2].start);
+    const int b2 = int(P->bfar);
     const int tpb = 2 * NP;   // P2M / P2L: two slices of NP threads
     // P2M
     for (int r = r0; r < r1; ++r)
@@ -1000,7 +1120,7 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
     between();
     // upward M2M + UC2E, deepest level first
     for (int r = r0; r < r1; ++r)
-        for (int l = depth; l >= 2; --l) {
+        for (int l = depth; l >= ld; --l) {
             const int nb = int(P->lev[l].count);
             const int blocks = nblk(nb, 16);
             hipLaunchKernelGGL((k_updown<NP, true>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks,
@@ -1009,6 +1129,13 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
                                P->phi_u.as<float>() + r * stride, P->phi_u.as<float>() + r * stride,
                                op.m2m.as<uint4>(), op.uc2e_w1.as<uint4>(), op.uc2e_v.as<uint4>());
         }
+    // periodic root: every image beyond the root's neighbours
+    if (P->periodic) {
+        const DBuf& R = get_lattice_operator(P->p, P->opt.pinv_rtol);
+        for (int r = r0; r < r1; ++r)
+            hipLaunchKernelGGL(k_lattice, dim3(1), dim3(NP), 0, s, R.as<double>(), op.n, NP,
+                               P->phi_u.as<float>() + r * stride, P->phi_d.as<float>() + r * stride);
+    }
     if (rec) record_phase(P, 1, s);
     // downward check potentials: zero, X list
     for (int r = r0; r < r1; ++r) {
@@ -1031,12 +1158,12 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
     if (rec) record_phase(P, 3, s);
     // L2L + DC2E, coarse to fine
     for (int r = r0; r < r1; ++r)
-        for (int l = 2; l <= depth; ++l) {
+        for (int l = first_v_level(P); l <= depth; ++l) {
             const LevelInfo& pl = P->lev[l - 1];
             const int blocks = nblk(pl.nl_count, 16) * 8;
             if (blocks == 0) continue;
             hipLaunchKernelGGL((k_updown<NP, false>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, 0, 0,
-                               int(pl.nl_start), int(pl.nl_count), l >= 3 ? 1 : 0, P->nonleaf.as<int>(),
+                               int(pl.nl_start), int(pl.nl_count), l > ld ? 1 : 0, P->nonleaf.as<int>(),
                                P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->psi_m.as<float>() + r * stride,
                                P->m2l_split_used, 2 * stride, P->phi_d.as<float>() + r * stride,
                                P->phi_d.as<float>() + r * stride, op.l2l.as<uint4>(), op.dc2e_w1.as<uint4>(),
@@ -1049,8 +1176,13 @@ template <int NP>
 void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s, int rhs) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
-    const int b2 = P->depth >= 2 ? int(P->lev[2].start) : int(P->B);
-    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), out_a, out_b};
+    const int b2 = int(P->bfar);
+    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), out_a, out_b, nullptr, {0, 0, 0}, 0.0};
+    if (P->periodic) {
+        fo.mom = P->mom.as<double>() + (bwd ? 0 : 16 * rhs);
+        for (int d = 0; d < 3; ++d) fo.o[d] = P->lo[d] + 0.5 * P->side;
+        fo.k1 = 2.0 * M_PI * P->c / (3.0 * P->side * P->side * P->side);
+    }
     size_t stride = size_t(P->B) * NP;
     if (bwd)
         hipLaunchKernelGGL((k_far<NP, true>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(), b2,

@@ -45,10 +45,12 @@ __device__ inline int lanes_per_target(int nt) { return nt <= 8 ? 8 : nt <= 16 ?
 
 // Stream the points of U(b) through LDS, all four waves staging together;
 // calls body(m) after each batch of m staged points.  Block-uniform control.
+// A periodic image of a leaf is staged moved by its shift times the cell side.
 template <class Body>
 __device__ inline void stream_sources(const int* __restrict__ uoff, const int* __restrict__ uidx,
                                       const int2* __restrict__ range, int b, const float4* __restrict__ pts,
-                                      const float4* __restrict__ src2, float4* sh, float4* sh2, Body body) {
+                                      const float4* __restrict__ src2, float cell, float4* sh, float4* sh2,
+                                      Body body) {
     int k = uoff[b];
     const int kend = uoff[b + 1];
     int pos = 0;
@@ -56,10 +58,15 @@ __device__ inline void stream_sources(const int* __restrict__ uoff, const int* _
         __syncthreads();
         int m = 0;
         while (k < kend && m < NF_STAGE) {
-            const int2 ra = range[uidx[k]];
+            const int e = uidx[k];
+            const int2 ra = range[img_box(e)];
+            int sx, sy, sz;
+            img_shift(e, sx, sy, sz);
+            const float ox = sx * cell, oy = sy * cell, oz = sz * cell;
             const int take = min(ra.y - ra.x - pos, NF_STAGE - m);
             for (int q = threadIdx.x; q < take; q += 256) {
-                sh[m + q] = pts[ra.x + pos + q];
+                const float4 p = pts[ra.x + pos + q];
+                sh[m + q] = make_float4(p.x + ox, p.y + oy, p.z + oz, p.w);
                 if (src2) sh2[m + q] = src2[ra.x + pos + q];
             }
             m += take;
@@ -98,7 +105,8 @@ __device__ inline void wave_reduce(float (&v)[NV], float (*red)[NV][64]) {
 // target has S lanes.
 __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int n_items, const int2* __restrict__ range,
                                              const int* __restrict__ uoff, const int* __restrict__ uidx,
-                                             const float4* __restrict__ pts, float cst, float4* __restrict__ nearv) {
+                                             const float4* __restrict__ pts, float cst, float cell,
+                                             float4* __restrict__ nearv) {
     __shared__ float4 sh[NF_STAGE];
     __shared__ float red[4][4][64];
     // the grid strides over the items (launched with one block per item)
@@ -113,7 +121,7 @@ __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int
         const bool act = lane / S < nt;
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
-        stream_sources(uoff, uidx, range, b, pts, nullptr, sh, nullptr, [&](int m) {
+        stream_sources(uoff, uidx, range, b, pts, nullptr, cell, sh, nullptr, [&](int m) {
 #pragma unroll 4
             for (int j = w * S + slice; j < m; j += 4 * S) {
                 const float4 y = sh[j];
@@ -139,7 +147,7 @@ __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int
 __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items, int n_items,
                                                  const int2* __restrict__ range, const int* __restrict__ uoff,
                                                  const int* __restrict__ uidx, const float4* __restrict__ pts,
-                                                 const float4* __restrict__ src2, float cst,
+                                                 const float4* __restrict__ src2, float cst, float cell,
                                                  float4* __restrict__ nearv) {
     __shared__ float4 sh[NF_STAGE];
     __shared__ float4 sh2[NF_STAGE];
@@ -155,7 +163,7 @@ __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items,
         const bool act = lane / S < nt;
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
-        stream_sources(uoff, uidx, range, b, pts, src2, sh, sh2, [&](int m) {
+        stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
             for (int j = w * S + slice; j < m; j += 4 * S) {
                 const float4 y = sh[j];
                 const float4 bj = sh2[j];
@@ -185,7 +193,7 @@ __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items,
 __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items, int n_items, const int2* __restrict__ range,
                                                  const int* __restrict__ uoff, const int* __restrict__ uidx,
                                                  const float4* __restrict__ pts, const float4* __restrict__ src2,
-                                                 float cst, float4* __restrict__ nearv) {
+                                                 float cst, float cell, float4* __restrict__ nearv) {
     __shared__ float4 sh[NF_STAGE];
     __shared__ float4 sh2[NF_STAGE];
     __shared__ float red[4][8][64];
@@ -209,7 +217,7 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
         // and xbar = X + S Ebar_k - q_k T;  qbar = psi = sum ubar_j/r - r.Ebar_j/r^3.
         float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         const float uk = a.x, qk = x.w;
-        stream_sources(uoff, uidx, range, b, pts, src2, sh, sh2, [&](int m) {
+        stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
             for (int j = w * S + slice; j < m; j += 4 * S) {
                 const float4 y = sh[j];
                 const float4 bj = sh2[j];
@@ -262,19 +270,19 @@ void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const
 void launch_p2p_forward(kifmm_plan* P, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(), int(P->n_items),
                        P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), P->pts.as<float4>(),
-                       float(P->c), P->nearv.as<float4>());
+                       float(P->c), float(P->side), P->nearv.as<float4>());
 }
 
 void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p_dip, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
                        int(P->n_items), P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(),
-                       P->pts.as<float4>(), P->src2.as<float4>(), float(P->c), P->nearv.as<float4>());
+                       P->pts.as<float4>(), P->src2.as<float4>(), float(P->c), float(P->side), P->nearv.as<float4>());
 }
 
 void launch_p2p_backward(kifmm_plan* P, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p_bwd, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
                        int(P->n_items), P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), P->pts.as<float4>(),
-                       P->src2.as<float4>(), float(P->c), P->nearv.as<float4>());
+                       P->src2.as<float4>(), float(P->c), float(P->side), P->nearv.as<float4>());
 }
 
 }  // namespace kifmm

@@ -205,6 +205,8 @@ std::unique_ptr<Operators> build_operators(int p, double tau) {
     while (k < n && S[k] >= tau * S[0]) ++k;
     op->rank = k;
     op->sigma.assign(S.begin(), S.end());
+    op->svd_u = U;
+    op->svd_v = V;
     std::vector<float> w1u(size_t(np) * np, 0.f), vu(size_t(np) * np, 0.f);
     std::vector<float> w1d(size_t(np) * np, 0.f), vd(size_t(np) * np, 0.f);
     for (int r = 0; r < k; ++r)
@@ -286,7 +288,100 @@ std::unique_ptr<Operators> build_operators(int p, double tau) {
     return op;
 }
 
+// Harmonic lattice kernel of a unit cell (V = 1) for a unit charge: the
+// Ewald Green's function with the images |n|_inf <= 1 removed and without its
+// non-harmonic part 2 pi |r|^2 / 3,
+//   F(r) = sum_{|n|_inf >= 2} erfc(a R)/R - sum_{|n|_inf <= 1} erf(a R)/R
+//        + 8 pi sum_{k in a half space} exp(-k^2 / (4 a^2)) / k^2 cos(k . r)
+//        - pi / a^2 - 2 pi |r|^2 / 3,       R = |r + n|, k = 2 pi m,
+// for all (i, j) pairs of the surface points x_i - y_j.  The splitting a = 4
+// makes both sums converge below 1e-16 with |n|_inf <= 3 and |m|_inf <= 9 for
+// |r|_inf <= 1.05.  The reciprocal sum factorises over the two point sets.
+std::vector<double> lattice_kernel(const std::vector<double>& xs, const std::vector<double>& ys, int n) {
+    const double a = 4.0;
+    const int nimg = 3, mmax = 9;
+    std::vector<double> F(size_t(n) * n, 0.0);
+    const double c0 = 2.0 * a / sqrt(M_PI);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double r[3] = {xs[3 * i] - ys[3 * j], xs[3 * i + 1] - ys[3 * j + 1], xs[3 * i + 2] - ys[3 * j + 2]};
+            double acc = 0.0;
+            for (int nx = -nimg; nx <= nimg; ++nx)
+                for (int ny = -nimg; ny <= nimg; ++ny)
+                    for (int nz = -nimg; nz <= nimg; ++nz) {
+                        const double dx = r[0] + nx, dy = r[1] + ny, dz = r[2] + nz;
+                        const double R = sqrt(dx * dx + dy * dy + dz * dz);
+                        const bool nearimg = std::max(abs(nx), std::max(abs(ny), abs(nz))) <= 1;
+                        if (nearimg) acc -= R > 0.0 ? erf(a * R) / R : c0;
+                        else acc += erfc(a * R) / R;
+                    }
+            F[size_t(i) * n + j] = acc - M_PI / (a * a) -
+                                   2.0 * M_PI / 3.0 * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        }
+    // reciprocal part: cos(k.(x - y)) = cos(k.x) cos(k.y) + sin(k.x) sin(k.y)
+    std::vector<double> wk, cx, sx, cy, sy;
+    for (int mx = 0; mx <= mmax; ++mx)
+        for (int my = -mmax; my <= mmax; ++my)
+            for (int mz = -mmax; mz <= mmax; ++mz) {
+                if (mx == 0 && (my < 0 || (my == 0 && mz <= 0))) continue;   // one of each +-m, m != 0
+                const double kx = 2 * M_PI * mx, ky = 2 * M_PI * my, kz = 2 * M_PI * mz;
+                const double k2 = kx * kx + ky * ky + kz * kz;
+                wk.push_back(8.0 * M_PI * exp(-k2 / (4.0 * a * a)) / k2);
+                for (int i = 0; i < n; ++i) {
+                    const double px = kx * xs[3 * i] + ky * xs[3 * i + 1] + kz * xs[3 * i + 2];
+                    const double py = kx * ys[3 * i] + ky * ys[3 * i + 1] + kz * ys[3 * i + 2];
+                    cx.push_back(cos(px));
+                    sx.push_back(sin(px));
+                    cy.push_back(cos(py));
+                    sy.push_back(sin(py));
+                }
+            }
+    const size_t K = wk.size();
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (size_t k = 0; k < K; ++k)
+                acc += wk[k] * (cx[k * n + i] * cy[k * n + j] + sx[k * n + i] * sy[k * n + j]);
+            F[size_t(i) * n + j] += acc;
+        }
+    return F;
+}
+
 }  // namespace
+
+const DBuf& get_lattice_operator(int p, double tau) {
+    static std::mutex mu;
+    static auto* cache = new std::map<std::tuple<int, int, double>, std::unique_ptr<DBuf>>();
+    const Operators& op = get_operators(p, tau);
+    int dev = 0;
+    KIFMM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_tuple(dev, p, tau);
+    auto it = cache->find(key);
+    if (it != cache->end()) return *it->second;
+    const int n = op.n, k = op.rank;
+    // the root's downward check surface is its upward equivalent surface (rho = 1.05)
+    std::vector<double> srf = unit_surface(p, 1.05);
+    std::vector<double> T = lattice_kernel(srf, srf, n);
+    // DC2E = U Sigma^-1 V^T (truncated): R = U (Sigma^-1 (V^T T))
+    std::vector<double> W(size_t(k) * n, 0.0), R(size_t(n) * n, 0.0);
+    for (int r = 0; r < k; ++r)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int l = 0; l < n; ++l) acc += op.svd_v[size_t(l) * n + r] * T[size_t(l) * n + j];
+            W[size_t(r) * n + j] = acc / op.sigma[r];
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int r = 0; r < k; ++r) acc += op.svd_u[size_t(i) * n + r] * W[size_t(r) * n + j];
+            R[size_t(i) * n + j] = acc;
+        }
+    auto buf = std::make_unique<DBuf>();
+    upload(*buf, R.data(), R.size() * sizeof(double));
+    it = cache->emplace(key, std::move(buf)).first;
+    return *it->second;
+}
 
 const Operators& get_operators(int p, double tau) {
     // Kept until the process ends (never destroyed: the HIP runtime may be gone

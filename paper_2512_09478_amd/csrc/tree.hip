@@ -387,10 +387,14 @@ __global__ void k_gather_pos(const double* __restrict__ x, const uint32_t* __res
 }
 
 // ----------------------------------------------------------------- lists
-__device__ inline bool adjacent_boxes(int4 a, int4 b) {
-    // closed cubes on the finest integer grid touch or overlap
+// Closed cubes on the finest integer grid touch or overlap: box b and the
+// image of box a that list entry e names (shifted by whole root widths).
+__device__ inline bool adjacent_image(int4 a, int e, int4 b) {
+    int sx, sy, sz;
+    img_shift(e, sx, sy, sz);
+    const int L = 1 << kBits;
     int sa = kBits - a.w, sb = kBits - b.w;
-    int ax0 = a.x << sa, ay0 = a.y << sa, az0 = a.z << sa, ea = 1 << sa;
+    int ax0 = (a.x << sa) + sx * L, ay0 = (a.y << sa) + sy * L, az0 = (a.z << sa) + sz * L, ea = 1 << sa;
     int bx0 = b.x << sb, by0 = b.y << sb, bz0 = b.z << sb, eb = 1 << sb;
     return ax0 <= bx0 + eb && bx0 <= ax0 + ea && ay0 <= by0 + eb && by0 <= ay0 + ea && az0 <= bz0 + eb &&
            bz0 <= az0 + ea;
@@ -407,19 +411,30 @@ __device__ inline int find_box(const uint64_t* __restrict__ mkey, int start, int
 }
 
 // One thread per (box, direction): a binary search for the neighbour's key
-// among the boxes of the same level.
+// among the boxes of the same level.  Periodic: the neighbour cell wraps
+// around the root and the entry records the image shift.
 __global__ void k_colleagues(int B, const int4* __restrict__ anchor, const uint64_t* __restrict__ mkey,
-                             LevelTable lt, int* __restrict__ coll) {
+                             LevelTable lt, int periodic, int* __restrict__ coll) {
     const int64_t g = int64_t(blockIdx.x) * TB + threadIdx.x;
     if (g >= int64_t(B) * 27) return;
     const int b = int(g / 27), d = int(g % 27);
     const int4 a = anchor[b];
     const int l = a.w;
     const int lim = 1 << l;
-    const int x = a.x + d / 9 - 1, y = a.y + (d / 3) % 3 - 1, z = a.z + d % 3 - 1;
+    int x = a.x + d / 9 - 1, y = a.y + (d / 3) % 3 - 1, z = a.z + d % 3 - 1;
     int id = -1;
-    if (x >= 0 && y >= 0 && z >= 0 && x < lim && y < lim && z < lim)
+    if (periodic) {
+        const int sx = x < 0 ? -1 : (x >= lim ? 1 : 0);
+        const int sy = y < 0 ? -1 : (y >= lim ? 1 : 0);
+        const int sz = z < 0 ? -1 : (z >= lim ? 1 : 0);
+        x -= sx * lim;
+        y -= sy * lim;
+        z -= sz * lim;
+        const int f = find_box(mkey, lt.start[l], lt.count[l], morton3(x, y, z));
+        if (f >= 0) id = img_encode(f, sx, sy, sz);
+    } else if (x >= 0 && y >= 0 && z >= 0 && x < lim && y < lim && z < lim) {
         id = find_box(mkey, lt.start[l], lt.count[l], morton3(x, y, z));
+    }
     coll[g] = id;
 }
 
@@ -442,10 +457,16 @@ __global__ void k_vdense(int b0, int nb, const int4* __restrict__ anchor, const 
     const int b = b0 + i;
     const int4 a = anchor[b];
     const int o = ((a.x & 1) << 2) | ((a.y & 1) << 1) | (a.z & 1);
-    const int* cp = coll + 27 * int64_t(parent[b]);
     int* out = vd + int64_t(i) * kVPerOct;
+    if (parent[b] < 0) {   // the (periodic) root: no V list
+        for (int j = lane; j < kVPerOct; j += 64) out[j] = -1;
+        return;
+    }
+    const int* cp = coll + 27 * int64_t(parent[b]);
     for (int j = lane; j < kVPerOct; j += 64) {
-        const int Q = cp[vt->D[o][j]];
+        // the slot fixes the offset; an image's shift needs no record
+        const int Qe = cp[vt->D[o][j]];
+        const int Q = Qe >= 0 ? img_box(Qe) : -1;
         int src = -1;
         if (Q >= 0 && !leafflag[Q]) {
             const int2 c = child[Q];
@@ -469,7 +490,7 @@ __global__ void k_cal(int b0, int nb, const int4* __restrict__ anchor, const int
     int* out = cal + 26 * int64_t(b);
     for (int d = 0; d < 27; ++d) {
         int Q = coll[27 * int64_t(P) + d];
-        if (Q >= 0 && leafflag[Q] && adjacent_boxes(anchor[Q], ab)) {
+        if (Q >= 0 && leafflag[img_box(Q)] && adjacent_image(anchor[img_box(Q)], Q, ab)) {
             if (cnt < 26) out[cnt] = Q;
             ++cnt;
         }
@@ -477,7 +498,7 @@ __global__ void k_cal(int b0, int nb, const int4* __restrict__ anchor, const int
     for (int k = 0; k < 26; ++k) {
         int Q = cal[26 * int64_t(P) + k];
         if (Q < 0) break;
-        if (adjacent_boxes(anchor[Q], ab)) {
+        if (adjacent_image(anchor[img_box(Q)], Q, ab)) {
             if (cnt < 26) out[cnt] = Q;
             ++cnt;
         }
@@ -499,9 +520,13 @@ __global__ void k_xlist(int b0, int nb, const int4* __restrict__ anchor, const i
     int P = parent[b];
     int c = 0;
     int at = mode ? cnt_or_off[b] : 0;
+    if (P < 0) {   // the (periodic) root
+        if (!mode) cnt_or_off[b] = 0;
+        return;
+    }
     for (int d = 0; d < 27; ++d) {
         int Q = coll[27 * int64_t(P) + d];
-        if (Q >= 0 && leafflag[Q] && !adjacent_boxes(anchor[Q], ab)) {
+        if (Q >= 0 && leafflag[img_box(Q)] && !adjacent_image(anchor[img_box(Q)], Q, ab)) {
             if (mode) idx[at + c] = Q;
             ++c;
         }
@@ -509,7 +534,7 @@ __global__ void k_xlist(int b0, int nb, const int4* __restrict__ anchor, const i
     for (int k = 0; k < 26; ++k) {
         int Q = cal[26 * int64_t(P) + k];
         if (Q < 0) break;
-        if (!adjacent_boxes(anchor[Q], ab)) {
+        if (!adjacent_image(anchor[img_box(Q)], Q, ab)) {
             if (mode) idx[at + c] = Q;
             ++c;
         }
@@ -527,7 +552,7 @@ __global__ void k_ulist_own(int B, const int* __restrict__ leafflag, const int* 
     int at = mode ? cnt_or_off[b] : 0;
     for (int d = 0; d < 27; ++d) {
         int Q = coll[27 * int64_t(b) + d];
-        if (Q >= 0 && leafflag[Q]) {
+        if (Q >= 0 && leafflag[img_box(Q)]) {
             if (mode) idx[at + c] = Q;
             ++c;
         }
@@ -542,15 +567,17 @@ __global__ void k_ulist_own(int B, const int* __restrict__ leafflag, const int* 
     else cnt_or_off[b] = c;
 }
 
-// U(b) finer part: every leaf A lists b in cal[A]  ->  A in U(b).
+// U(b) finer part: every leaf A lists b in cal[A]  ->  A in U(b) (an image
+// of b seen from A is A seen from b with the shift negated).
 __global__ void k_ulist_fine(int B, const int* __restrict__ leafflag, const int* __restrict__ cal,
                              int* __restrict__ cnt, int* __restrict__ idx, int* __restrict__ cursor, int mode) {
     int a = blockIdx.x * TB + threadIdx.x;
     if (a >= B || !leafflag[a]) return;
     for (int k = 0; k < 26; ++k) {
-        int b = cal[26 * int64_t(a) + k];
-        if (b < 0) break;
-        if (mode) idx[atomicAdd(&cursor[b], 1)] = a;
+        int e = cal[26 * int64_t(a) + k];
+        if (e < 0) break;
+        const int b = img_box(e);
+        if (mode) idx[atomicAdd(&cursor[b], 1)] = img_flip((e & ~kBoxMask) | a);
         else atomicAdd(&cnt[b], 1);
     }
 }
@@ -562,8 +589,9 @@ __global__ void k_wlist(int b0, int nb, const int* __restrict__ xoff, const int*
     if (i >= nb) return;
     int A = b0 + i;
     for (int k = xoff[A]; k < xoff[A + 1]; ++k) {
-        int b = xidx[k];
-        if (mode) idx[atomicAdd(&cursor[b], 1)] = A;
+        const int e = xidx[k];
+        const int b = img_box(e);
+        if (mode) idx[atomicAdd(&cursor[b], 1)] = img_flip((e & ~kBoxMask) | A);
         else atomicAdd(&cnt[b], 1);
     }
 }
@@ -645,7 +673,7 @@ __global__ void k_counts(int B, const int* __restrict__ leafflag, const int2* __
         int2 r = range[b];
         unsigned long long nt = r.y - r.x;
         for (int k = uoff[b]; k < uoff[b + 1]; ++k) {
-            int2 ra = range[uidx[k]];
+            int2 ra = range[img_box(uidx[k])];
             pp += nt * (unsigned long long)(ra.y - ra.x);
         }
     }
@@ -673,7 +701,7 @@ __global__ void k_item_fill(int nl, const int* __restrict__ leaves, const int2* 
     const int2 r = range[b];
     unsigned long long src = 0;
     for (int k = uoff[b]; k < uoff[b + 1]; ++k) {
-        int2 ra = range[uidx[k]];
+        int2 ra = range[img_box(uidx[k])];
         src += ra.y - ra.x;
     }
     const unsigned long long nfar = (b >= b2 ? 1 : 0) + (woff[b + 1] - woff[b]);
@@ -740,6 +768,13 @@ static const VTable& vtable_host() {
 }
 
 const void* vtable_host_ptr() { return &vtable_host(); }
+
+void v_slot_offset(int o, int j, int d[3]) {
+    const VTable& t = vtable_host();
+    const int D = t.D[o][j], oc = t.oc[o][j];
+    const int Dv[3] = {D / 9, (D / 3) % 3, D % 3};
+    for (int k = 0; k < 3; ++k) d[k] = 2 * (Dv[k] - 1) + ((oc >> (2 - k)) & 1) - ((o >> (2 - k)) & 1);
+}
 
 // Read device ints through the plan's pinned words (one copy each, one wait).
 static void read_ints(kifmm_plan* P, hipStream_t s, std::initializer_list<const int*> src, int* dst) {
@@ -885,7 +920,10 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     P->B = total;
     P->depth = int(P->lev.size()) - 1;
     const int B = int(total);
-    const int b2 = P->depth >= 2 ? int(P->lev[2].start) : B;
+    if (P->periodic && B > kBoxMask) throw Error(KIFMM_ERR_INPUT, "too many boxes for periodic list entries");
+    // first box with a downward density: level 2 in free space, the root when periodic
+    const int b2 = P->periodic ? 0 : (P->depth >= 2 ? int(P->lev[2].start) : B);
+    P->bfar = b2;
 
     LevelTable lt{};
     for (int l = 0; l <= P->depth; ++l) {
@@ -895,7 +933,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     // colleagues
     P->coll.ensure(size_t(B) * 27 * 4);
     hipLaunchKernelGGL(k_colleagues, dim3(nblocks(int64_t(B) * 27)), dim3(TB), 0, s, B, P->bx_anchor.as<int4>(),
-                       P->bx_mkey.as<uint64_t>(), lt, P->coll.as<int>());
+                       P->bx_mkey.as<uint64_t>(), lt, P->periodic ? 1 : 0, P->coll.as<int>());
     // V dense table
     static DBuf* vt_dev = nullptr;   // per process, small
     if (!vt_dev) {
@@ -916,7 +954,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         hipLaunchKernelGGL(k_cal, dim3(nblocks(P->lev[l].count)), dim3(TB), 0, s, int(P->lev[l].start),
                            int(P->lev[l].count), P->bx_anchor.as<int4>(), P->bx_parent.as<int>(),
                            P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), bad);
-    // X lists (rows over all boxes; only level >= 2 non-empty)
+    // X lists (rows over all boxes; non-empty from the first far-field level)
     P->x_off.ensure(size_t(B + 1) * 4);
     int* xoff = P->x_off.as<int>();
     KIFMM_HIP(hipMemsetAsync(xoff, 0, size_t(B + 1) * 4, s));

@@ -42,7 +42,8 @@ class Plan:
 
     def __init__(self, positions: torch.Tensor, kernel: str = "laplace", p: int = 6, leaf_size: int = 128,
                  adaptive: bool = True, max_depth: int = 21, precision: str = "fp32",
-                 pinv_rtol: float = 1e-7, root=None, profile: bool = False, stream=None):
+                 pinv_rtol: float = 1e-7, root=None, profile: bool = False, stream=None,
+                 periodic: bool = False):
         L = _lib.lib()
         self.n = int(positions.shape[0])
         self.positions = _need(positions, torch.float64, (self.n, 3), "positions")
@@ -56,6 +57,8 @@ class Plan:
         opt.precision = PRECISIONS[precision]
         opt.pinv_rtol = float(pinv_rtol)
         opt.profile = int(bool(profile))
+        opt.periodic = int(bool(periodic))
+        self.periodic = bool(periodic)
         if root is not None:
             opt.explicit_root = 1
             for d in range(3):

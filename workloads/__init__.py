@@ -23,6 +23,12 @@ collapse); the paper uses no public dataset.
         adjoint loss target built from charges + 0.1 N(0,1)
   5  gravity, Plummer sphere (a = 0.1, truncated at r = 10 a), unit
         masses, p=8, leaf 256, adaptive tree, depth <= 12, root [-1,1)^3
+  6  periodic unit cell (Laplace): co-oriented hexagonal two-layer
+        platelets of 2 x 547 pebbles (N = 14 rings, spacing 0.01), one
+        layer charged +1 and the other -1 (zero net charge, a dipole each),
+        placed at random without overlap and wrapped into the cell, p=6,
+        leaf 64, adaptive tree (the periodic platelet example of Section 3
+        has 50 such platelets)
 """
 from __future__ import annotations
 
@@ -33,10 +39,10 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["Workload", "make", "FULL_N", "SEED_BASE", "round_f32", "uniform_cube",
-           "clustered", "plummer", "clumps", "adjoint_target_charges"]
+           "clustered", "plummer", "clumps", "platelets", "adjoint_target_charges"]
 
 SEED_BASE = 9478
-FULL_N = {1: 4096, 2: 1_048_576, 3: 1_600_000, 4: 524_288, 5: 8_388_608}
+FULL_N = {1: 4096, 2: 1_048_576, 3: 1_600_000, 4: 524_288, 5: 8_388_608, 6: 54_700}
 
 
 @dataclasses.dataclass
@@ -223,6 +229,51 @@ def clumps(rng: np.random.Generator, n_clumps: int, phi: float = 0.30,
     return pos, offsets, round_f32(centres)
 
 
+def _hex_layer(rings: int, spacing: float) -> np.ndarray:
+    """Triangular-lattice points within hexagonal distance rings-1 of the origin (z = 0)."""
+    m = rings - 1
+    pts = []
+    for i in range(-m, m + 1):
+        for j in range(-m, m + 1):
+            if abs(i + j) <= m:
+                pts.append((spacing * (i + 0.5 * j), spacing * (math.sqrt(3.0) / 2.0) * j, 0.0))
+    return np.array(pts, dtype=np.float64)
+
+
+def platelets(rng: np.random.Generator, n_platelets: int, rings: int = 14, spacing: float = 0.01):
+    """Co-oriented two-layer close-packed platelets in the periodic unit cell.
+
+    Layer A at height 0 carries +1, layer B (shifted to the hollow sites, at
+    height spacing * sqrt(2/3)) carries -1.  Centres are drawn uniformly and
+    rejected while a platelet's bounding cylinder overlaps another's under
+    the minimum-image convention.  Returns (positions [2 k n_platelets, 3]
+    in [0, 1), charges).
+    """
+    a = _hex_layer(rings, spacing)
+    b = a + np.array([0.5 * spacing, spacing / (2.0 * math.sqrt(3.0)), spacing * math.sqrt(2.0 / 3.0)])
+    rad = spacing * (rings - 1) + spacing      # bounding radius, with margin
+    thick = 2.0 * spacing * math.sqrt(2.0 / 3.0) + spacing
+    cen = []
+    while len(cen) < n_platelets:
+        c = rng.random(3)
+        ok = True
+        for d in cen:
+            dd = c - d
+            dd -= np.round(dd)
+            if math.hypot(dd[0], dd[1]) < 2.0 * rad and abs(dd[2]) < thick:
+                ok = False
+                break
+        if ok:
+            cen.append(c)
+    cen = np.array(cen)
+    one = np.concatenate([a, b])
+    pos = (cen[:, None, :] + one[None, :, :]).reshape(-1, 3) % 1.0
+    pos = round_f32(pos)
+    pos = np.where(pos >= 1.0, 0.0, pos)
+    q = np.tile(np.concatenate([np.ones(a.shape[0]), -np.ones(b.shape[0])]), n_platelets)
+    return pos, q
+
+
 def adjoint_target_charges(charges: np.ndarray, seed: int) -> np.ndarray:
     """Charges perturbed by 0.1 * N(0,1); the field they produce is the loss target."""
     rng = np.random.default_rng(seed)
@@ -230,7 +281,8 @@ def adjoint_target_charges(charges: np.ndarray, seed: int) -> np.ndarray:
 
 
 def make(k: int, n: Optional[int] = None, seed: Optional[int] = None) -> Workload:
-    """Build workload ``k`` (1..5) with ``n`` points (default: the full size)."""
+    """Build workload ``k`` (1..6) with ``n`` points (default: the full size; the
+    platelet cell rounds down to whole platelets and is periodic)."""
     rng = _rng(k, seed)
     N = FULL_N[k] if n is None else int(n)
     if k == 1:
@@ -260,4 +312,9 @@ def make(k: int, n: Optional[int] = None, seed: Optional[int] = None) -> Workloa
         q = np.ones(N)
         return Workload("plummer_8M_p8", x, q, "gravity", 8, 256, True, 12,
                         ((-1.0, -1.0, -1.0), 2.0))
+    if k == 6:
+        per = 2 * (1 + 3 * 14 * 13)
+        x, q = platelets(rng, max(1, N // per))
+        return Workload("platelets_periodic_p6", x, q, "laplace", 6, 64, True, 21,
+                        ((0.0, 0.0, 0.0), 1.0))
     raise ValueError(f"unknown workload {k}")
