@@ -48,14 +48,16 @@ WORKLOADS = {
        "p=6, leaf 128, adaptive octree, per-clump force and torque",
     4: "uniform Laplace charges in the unit cube, q ~ N(0,1), p=6, leaf 128, adaptive octree",
     5: "Plummer sphere (a=0.1, r<=10a) of unit masses, gravity, p=8, leaf 256, adaptive octree depth<=12",
+    6: "periodic unit cell: 50 co-oriented two-layer hexagonal platelets of 2x547 pebbles charged +1/-1, "
+       "Laplace lattice sum (Ewald convention), p=6, leaf 64, adaptive octree",
 }
-CPU_SAMPLE = {1: 4096, 2: 131072, 3: 131072, 4: 131072, 5: 65536}
+CPU_SAMPLE = {1: 4096, 2: 131072, 3: 131072, 4: 131072, 5: 65536, 6: 8752}
 
 
 def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0):
     import torch
     plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root,
-                profile=True)
+                profile=True, periodic=w.periodic)
     lo, hi = None, None
     if move > 0:
         # particles drift between long-range calls (the DEM loop): each step
@@ -74,6 +76,9 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0):
     def step(record):
         if move > 0:
             pos.add_(torch.randn(pos.shape, generator=gen, dtype=pos.dtype, device=pos.device), alpha=move)
+            if w.periodic:
+                # a particle leaving the cell re-enters through the opposite face
+                pos.sub_(lo).remainder_(w.root[1]).add_(lo)
             torch.maximum(pos, lo, out=pos)
             torch.minimum(pos, hi, out=pos)
         plan.rebuild(pos)
@@ -166,7 +171,8 @@ def cpu_baseline(k):
     ub = rng.standard_normal(n)
     Eb = rng.standard_normal((n, 3))
     t0 = time.perf_counter()
-    P = kifmm.plan(w.positions, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, w.root)
+    P = kifmm.plan(w.positions, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, w.root,
+                   periodic=w.periodic)
     kifmm.forward(P, w.charges)
     kifmm.vjp(P, w.charges, ub, Eb)
     t = time.perf_counter() - t0

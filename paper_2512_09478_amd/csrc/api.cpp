@@ -57,7 +57,9 @@ void alloc_densities(kifmm_plan* P, hipStream_t s) {
         b->ensure(bytes);
         if (fresh) KIFMM_HIP(hipMemsetAsync(b->p, 0, b->cap, s));
     }
-    P->psi_m.ensure(size_t(kM2LSplit) * bytes);
+    // small trees get more M2L partial buffers (see launch_m2l)
+    P->m2l_split_cap = bytes <= (size_t(64) << 20) ? kM2LSplitMax : kM2LSplit;
+    P->psi_m.ensure(size_t(P->m2l_split_cap) * bytes);
     P->nearv.ensure(size_t(P->N) * 16);
     if (P->periodic) {
         P->mom.ensure(2 * 16 * sizeof(double));

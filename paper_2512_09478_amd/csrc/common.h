@@ -18,6 +18,8 @@ constexpr int kNumV = 316;             // far offsets in [-3,3]^3 minus [-1,1]^3
 constexpr int kVPerOct = 189;          // V-list offsets reachable from one octant
 constexpr int kMaxLevels = 22;
 constexpr int kM2LSplit = 4;          // M2L V slots split over this many blocks per tile
+constexpr int kM2LSplitMax = 16;      // ... and up to this many for small trees
+constexpr int kM2LFill = 2048;        // M2L blocks wanted before the split stops growing
 constexpr int kMomentBlocks = 256;    // blocks of the periodic moment reduction
 
 // Error carrying a status code; caught at the ABI.
@@ -236,8 +238,9 @@ struct kifmm_plan {
     int64_t n_xboxes = 0;
     // densities: [rhs][B][npad]
     kifmm::DBuf psi_u, phi_u, psi_d, phi_d;
-    kifmm::DBuf psi_m;      // M2L partial check potentials [kM2LSplit][rhs][B][npad]
+    kifmm::DBuf psi_m;      // M2L partial check potentials [split][rhs][B][npad]
     int m2l_split_used = kifmm::kM2LSplit;
+    int m2l_split_cap = kifmm::kM2LSplit;   // partial buffers allocated
     // per-evaluation work
     kifmm::DBuf pts;        // float4 [N] sorted (x, y, z, q)
     kifmm::DBuf src2;       // float4 [N] sorted (ubar, Ebar) for the adjoint sweep

@@ -1044,8 +1044,6 @@ void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
     const int lv = first_v_level(P);
     if (depth < lv) return;
     const int b2 = int(P->bfar);
-    const int nsplit = M2L_SPLIT;
-    P->m2l_split_used = nsplit;
     const int TG = M2L_CB / nrhs;
     const int per_block = WAVES * TG * 16;
     TaskTable tt{};
@@ -1063,6 +1061,11 @@ void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
     }
     blocks *= 8;
     if (blocks == 0) return;
+    // A small tree has few tiles: split the V slots further so that the chip
+    // fills and each block's chain of operator chunks is shorter.
+    int nsplit = M2L_SPLIT;
+    while (nsplit < P->m2l_split_cap && blocks * nsplit < kM2LFill) nsplit *= 2;
+    P->m2l_split_used = nsplit;
     const size_t stride = size_t(P->B) * NP;
     const size_t sstride = 2 * stride;
     const float* phi_u = P->phi_u.as<float>() + size_t(rhs) * stride;

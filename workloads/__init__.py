@@ -58,6 +58,7 @@ class Workload:
     root: Optional[tuple]            # (lo[3], side) or None for automatic
     clump_offsets: Optional[np.ndarray] = None   # [C+1] int64, CSR over caller order
     clump_centers: Optional[np.ndarray] = None   # [C,3] float64
+    periodic: bool = False           # the root cube is the unit cell of a periodic system
 
     @property
     def n(self) -> int:
@@ -316,5 +317,5 @@ def make(k: int, n: Optional[int] = None, seed: Optional[int] = None) -> Workloa
         per = 2 * (1 + 3 * 14 * 13)
         x, q = platelets(rng, max(1, N // per))
         return Workload("platelets_periodic_p6", x, q, "laplace", 6, 64, True, 21,
-                        ((0.0, 0.0, 0.0), 1.0))
+                        ((0.0, 0.0, 0.0), 1.0), periodic=True)
     raise ValueError(f"unknown workload {k}")
