@@ -11,9 +11,11 @@
  *     H(r) = grad grad K = c (3 r r^T / |r|^5 - I / |r|^3)
  * A source j carries a monopole s_j and optionally a dipole m_j; the field it
  * makes is  psi(x) = s_j K(r) - m_j . G(r).  Outputs at a target are
- *     u = psi,   E = -grad psi = s_j G(r) - H(r) m_j,   Hess = s_j H(r)
- * (the Hessian is only formed for monopole sources).  Pairs at distance
- * exactly zero (the self pair and coincident points) are skipped.
+ *     u = psi,   E = -grad psi = s_j G(r) - H(r) m_j,   Hess = grad grad psi,
+ * the dipole part of the Hessian being the derivative of -m . G:
+ *     c [3 (m_a r_b + m_b r_a + (m.r) delta_ab) / |r|^5 - 15 (m.r) r_a r_b / |r|^7].
+ * Pairs at distance exactly zero (the self pair and coincident points) are
+ * skipped.
  *
  * Everything is a straight double loop; OpenMP only splits the targets.
  */
@@ -50,6 +52,17 @@ static void one_pair(const double* xt, const double* ys, double s, const double*
         e[0] -= c * (3.0 * r0 * mr * ri5 - m[0] * ri3);
         e[1] -= c * (3.0 * r1 * mr * ri5 - m[1] * ri3);
         e[2] -= c * (3.0 * r2 * mr * ri5 - m[2] * ri3);
+        if (h) {
+            double ri7 = ri5 * ri * ri;
+            double r[3] = {r0, r1, r2};
+            static const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+            for (int k = 0; k < 6; ++k) {
+                int a = A[k], b = B[k];
+                double t = 3.0 * (m[a] * r[b] + m[b] * r[a] + (a == b ? mr : 0.0)) * ri5
+                           - 15.0 * mr * r[a] * r[b] * ri7;
+                h[k] += c * t;
+            }
+        }
     }
 }
 

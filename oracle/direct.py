@@ -34,12 +34,13 @@ def potential_field(x, q, kernel="laplace", targets=None, hess=False):
     return pairsum.direct(xt, x, q, None, KERNELS[kernel], hess)
 
 
-def dipole_potential_field(x, q, m, kernel="laplace"):
-    """u, E of monopoles q (or none) and dipoles m by direct sum."""
+def dipole_potential_field(x, q, m, kernel="laplace", grad=False):
+    """u, E of monopoles q (or none) and dipoles m by direct sum; with ``grad``
+    also dE_a/dx_b = -Hess u (xx, yy, zz, xy, xz, yz)."""
     x = np.asarray(x, dtype=np.float64)
     s = np.zeros(x.shape[0]) if q is None else q
-    u, E, _ = pairsum.direct(x, x, s, np.asarray(m, dtype=np.float64).reshape(-1, 3), KERNELS[kernel], False)
-    return u, E
+    u, E, H = pairsum.direct(x, x, s, np.asarray(m, dtype=np.float64).reshape(-1, 3), KERNELS[kernel], grad)
+    return (u, E, -H) if grad else (u, E)
 
 
 def energy(x, q, kernel="laplace"):

@@ -270,25 +270,30 @@ def forward(P: Plan, q, targets=None):
     return u, E
 
 
-def forward_dipoles(P: Plan, q, m, targets=None):
-    """Potential and field of monopoles q and dipoles m (a dipole m at y makes
-    psi(x) = -m . G(x - y)), in caller order or at caller indices ``targets``;
-    the same sweep as the charges, with the dipole part in every point-to-
-    surface and point-to-point sum."""
+def forward_dipoles(P: Plan, q, m, targets=None, grad=False):
+    """Potential and field of monopoles q (or none) and dipoles m (or none; a
+    dipole m at y makes psi(x) = -m . G(x - y)), in caller order or at caller
+    indices ``targets``; the same sweep as the charges, with the dipole part in
+    every point-to-surface and point-to-point sum.  With ``grad`` also the
+    field gradient dE_a/dx_b = -Hess u (xx, yy, zz, xy, xz, yz)."""
     perm = P.tree.perm
     qs = np.zeros(P.n) if q is None else np.asarray(q, dtype=np.float64)[perm]
-    ms = np.asarray(m, dtype=np.float64).reshape(-1, 3)[perm]
+    ms = None if m is None else np.asarray(m, dtype=np.float64).reshape(-1, 3)[perm]
     if targets is None:
-        u, E, _ = evaluate_sorted(P, qs, ms)
+        u, E, H = evaluate_sorted(P, qs, ms, hess=grad)
         out_u = np.empty(P.n)
         out_E = np.empty((P.n, 3))
         out_u[perm] = u
         out_E[perm] = E
-        return out_u, out_E
+        if not grad:
+            return out_u, out_E
+        out_G = np.empty((P.n, 6))
+        out_G[perm] = -H
+        return out_u, out_E, out_G
     inv = np.empty_like(perm)
     inv[perm] = np.arange(P.n)
-    u, E, _ = evaluate_sorted(P, qs, ms, targets=inv[np.asarray(targets)])
-    return u, E
+    u, E, H = evaluate_sorted(P, qs, ms, targets=inv[np.asarray(targets)], hess=grad)
+    return (u, E, -H) if grad else (u, E)
 
 
 def vjp(P: Plan, q, ubar, Ebar, targets=None):

@@ -137,3 +137,30 @@ def test_direct_vjp_matches_finite_differences():
         d2 = (L(q, xp2) - L(q, xm2)) / h
         rich = (4 * d2 - d1) / 3
         assert rich == pytest.approx(xb[k, a], rel=1e-7)
+
+
+def test_dipole_field_gradient_matches_differences_and_is_traceless():
+    # dE/dx of monopoles plus dipoles: central differences of the field at
+    # displaced targets (Richardson), and zero trace (harmonic away from sources)
+    from oracle import pairsum
+    rng = np.random.default_rng(31)
+    ys = rng.random((40, 3))
+    s = rng.standard_normal(40)
+    m = rng.standard_normal((40, 3))
+    xt = rng.random((5, 3)) + 1.5          # targets away from the sources
+    c = 1.0 / (4.0 * np.pi)
+    _, _, H = pairsum.direct(xt, ys, s, m, c, True)
+    G = -H
+    comps = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+
+    def field(x):
+        return pairsum.direct(x, ys, s, m, c, False)[1]
+
+    h = 1e-3
+    for k, (a, b) in enumerate(comps):
+        e = np.zeros(3)
+        e[b] = h
+        d1 = (field(xt + e)[:, a] - field(xt - e)[:, a]) / (2 * h)
+        d2 = (field(xt + e / 2)[:, a] - field(xt - e / 2)[:, a]) / h
+        np.testing.assert_allclose((4 * d2 - d1) / 3, G[:, k], rtol=1e-7, atol=1e-9 * np.abs(G).max())
+    np.testing.assert_allclose(G[:, 0] + G[:, 1] + G[:, 2], 0.0, atol=1e-12 * np.abs(G).max())

@@ -166,3 +166,23 @@ def test_dipole_sources_accuracy_and_linearity():
     ut, Et = kifmm.forward_dipoles(P, None, m, targets=t)
     np.testing.assert_allclose(ut, u1[t], rtol=0, atol=1e-11 * np.abs(u1).max())
     np.testing.assert_allclose(Et, E1[t], rtol=0, atol=1e-11 * np.abs(E1).max())
+
+
+def test_field_gradient_accuracy_with_dipoles():
+    # dE/dx of monopoles plus dipoles through the sweep (monopole equivalent
+    # densities, dipole parts in the near field) against the direct sum
+    w = workloads.make(2, n=3000)
+    rng = np.random.default_rng(42)
+    m = rng.standard_normal((w.n, 3)) * 1e-3
+    P = kifmm.plan(w.positions, "laplace", 6, 48, True, 21, w.root)
+    u, E, G = kifmm.forward_dipoles(P, w.charges, m, grad=True)
+    ud, Ed, Gd = direct.dipole_potential_field(w.positions, w.charges, m, grad=True)
+    assert np.linalg.norm(G - Gd) / np.linalg.norm(Gd) < 1e-5
+    # p = 8 is closer (the method converges in p)
+    P8 = kifmm.plan(w.positions, "laplace", 8, 48, True, 21, w.root)
+    _, _, G8 = kifmm.forward_dipoles(P8, w.charges, m, grad=True)
+    assert np.linalg.norm(G8 - Gd) < 0.3 * np.linalg.norm(G - Gd)
+    # no dipoles: the same call on the charges alone
+    u0, E0, G0 = kifmm.forward_dipoles(P, w.charges, None, grad=True)
+    uf, Ef = kifmm.forward(P, w.charges)
+    np.testing.assert_allclose(u0, uf, rtol=0, atol=1e-12 * np.abs(uf).max())
