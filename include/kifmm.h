@@ -159,6 +159,26 @@ int kifmm_evaluate_dipoles(kifmm_handle h, const float* charges, const float* di
                            float* field, void* stream);
 
 /*
+ * Forward evaluation with the field gradient, for the force on a dipole
+ * (F = (m . grad) E for a curl-free field) and the other outputs of the
+ * "other kernels" of eq. (1):
+ *   charges     device [N] float or NULL, caller order.
+ *   dipoles     device [N][3] float or NULL (at least one of the two given);
+ *               a dipole m at y makes psi(x) = -m . G(x - y), as above.
+ *   potential   device [N] float or NULL.
+ *   field       device [N][3] float (E = -grad u) or NULL.
+ *   field_grad  device [N][6] float or NULL: dE_a/dx_b = -d2u/dx_a dx_b,
+ *               components (xx, yy, zz, xy, xz, yz).
+ * The sweep of kifmm_evaluate (or of kifmm_evaluate_dipoles with dipoles);
+ * the leaf evaluation also differentiates the equivalent densities and the
+ * near field sums the pair Hessians.  Periodic plans add the moment term
+ * (-4 pi c Q / (3 V) on the diagonal).  Afterwards kifmm_backward needs its
+ * charges.
+ */
+int kifmm_evaluate_gradient(kifmm_handle h, const float* charges, const float* dipoles, float* potential,
+                            float* field, float* field_grad, void* stream);
+
+/*
  * Vector-Jacobian product of the discrete map (q, x) -> (u, E) of
  * kifmm_evaluate at the plan's positions with the tree frozen: given
  * grad_potential = dL/du and grad_field = dL/dE (either may be NULL = 0),

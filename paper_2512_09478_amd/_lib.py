@@ -34,8 +34,8 @@ _lock = threading.Lock()
 _lib = None
 
 EXPORTS = ["kifmm_default_options", "kifmm_setup", "kifmm_setup_ex", "kifmm_rebuild", "kifmm_set_precision",
-           "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_backward", "kifmm_clump_reduce",
-           "kifmm_clump_backward", "kifmm_get_counts",
+           "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient", "kifmm_backward",
+           "kifmm_clump_reduce", "kifmm_clump_backward", "kifmm_get_counts",
            "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times", "kifmm_destroy", "kifmm_status_string"]
 
 
@@ -58,6 +58,7 @@ def lib():
             L.kifmm_set_precision.argtypes = [H, I]
             L.kifmm_evaluate.argtypes = [H, P, P, P, P]
             L.kifmm_evaluate_dipoles.argtypes = [H, P, P, P, P, P]
+            L.kifmm_evaluate_gradient.argtypes = [H, P, P, P, P, P, P]
             L.kifmm_backward.argtypes = [H, P, P, P, P, P, P]
             L.kifmm_clump_reduce.argtypes = [H, P, P, P, I64, P, P, P, P]
             L.kifmm_clump_backward.argtypes = [H, P, P, P, I64, P, P, P, P, P, P, P, P]
@@ -70,7 +71,8 @@ def lib():
             L.kifmm_status_string.argtypes = [I]
             L.kifmm_status_string.restype = ctypes.c_char_p
             for name in ("kifmm_setup", "kifmm_setup_ex", "kifmm_rebuild", "kifmm_set_precision",
-                         "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_backward", "kifmm_clump_reduce",
+                         "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient", "kifmm_backward",
+                         "kifmm_clump_reduce",
                          "kifmm_clump_backward",
                          "kifmm_get_counts",
                          "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times"):

@@ -83,7 +83,7 @@ void begin_phases(kifmm_plan* P, hipStream_t s) {
     KIFMM_HIP(hipEventRecord(P->events.ev[0], s));
 }
 
-enum NearKind { NEAR_FORWARD, NEAR_BACKWARD, NEAR_DIPOLES };
+enum NearKind { NEAR_FORWARD, NEAR_BACKWARD, NEAR_DIPOLES, NEAR_GRAD, NEAR_GRAD_DIPOLES };
 
 // The near field does not depend on the far-field sweep: it runs on the side
 // stream, forked from `s` after P2M (so that the sweep's first kernel is not
@@ -98,6 +98,7 @@ void fork_near(kifmm_plan* P, NearKind kind, hipStream_t s) {
     if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[0], t));
     if (kind == NEAR_BACKWARD) launch_p2p_backward(P, t);
     else if (kind == NEAR_DIPOLES) launch_p2p_dipoles(P, t);
+    else if (kind == NEAR_GRAD || kind == NEAR_GRAD_DIPOLES) launch_p2p_gradient(P, kind == NEAR_GRAD_DIPOLES, t);
     else launch_p2p_forward(P, t);
     if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[1], t));
     KIFMM_HIP(hipEventRecord(P->nearq.join, t));
@@ -236,6 +237,29 @@ int kifmm_evaluate_dipoles(kifmm_handle h, const float* charges, const float* di
         run_sweep(P, 1, 2, s, true, [&] { fork_near(P, NEAR_DIPOLES, s); });
         join_near(P, s);
         run_far_eval(P, false, potential, field, s, 1);
+        record_phase(P, 6, s);
+        P->has_phase = P->opt.profile ? 3 : 0;
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_evaluate_gradient(kifmm_handle h, const float* charges, const float* dipoles, float* potential,
+                            float* field, float* field_grad, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!charges && !dipoles) throw Error(KIFMM_ERR_ARG, "null charges and dipoles");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        begin_phases(P, s);
+        P->fwd_valid = false;
+        // with dipoles the sources go through right-hand side 1 (as in
+        // kifmm_evaluate_dipoles), otherwise through 0
+        const int rhs = dipoles ? 1 : 0;
+        launch_gather(P, charges, charges, dipoles, dipoles != nullptr, s, true);
+        run_sweep(P, rhs, rhs + 1, s, true,
+                  [&] { fork_near(P, dipoles ? NEAR_GRAD_DIPOLES : NEAR_GRAD, s); });
+        join_near(P, s);
+        run_far_grad(P, potential, field, field_grad, s, rhs);
         record_phase(P, 6, s);
         P->has_phase = P->opt.profile ? 3 : 0;
         KIFMM_HIP(hipGetLastError());

@@ -245,6 +245,7 @@ struct kifmm_plan {
     kifmm::DBuf pts;        // float4 [N] sorted (x, y, z, q)
     kifmm::DBuf src2;       // float4 [N] sorted (ubar, Ebar) for the adjoint sweep
     kifmm::DBuf nearv;      // float4 [N] sorted near-field part: (u, E) or (xbar, qbar)
+    kifmm::DBuf nearg;      // float [N][6] sorted near-field part of dE/dx (gradient calls only)
     kifmm::DBuf mom;        // periodic: double [rhs][16] source moments about the cell centre
     kifmm::DBuf mom_part;   // their per-block partial sums
     // scratch
@@ -267,6 +268,8 @@ void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const 
 // leaf evaluation; adds the near-field part and writes the caller-order
 // outputs (forward: potential, field; backward: grad_charges, grad_positions)
 void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs = 0);
+// leaf evaluation with the field gradient (densities of right-hand side rhs)
+void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs);
 // ---- nearfield.hip
 // sorted points (x, y, z, q) when `charges` is given or `points` is set (q = 0
 // for null charges), and for `adjoint` the sorted (gpot, gfield) sources
@@ -275,6 +278,8 @@ void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const
 void launch_p2p_forward(kifmm_plan* P, hipStream_t s);
 void launch_p2p_backward(kifmm_plan* P, hipStream_t s);
 void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s);
+// u, E and dE/dx of monopoles (pts.w, or src2.x with `dipoles`) and dipoles (src2.yzw)
+void launch_p2p_gradient(kifmm_plan* P, bool dipoles, hipStream_t s);
 // ---- clump.hip
 void launch_clump_reduce(kifmm_plan* P, const float* q, const float* E, const int64_t* off, int64_t C,
                          const double* centers, double* F, double* T, hipStream_t s);

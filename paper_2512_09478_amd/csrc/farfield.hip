@@ -980,6 +980,137 @@ __global__ void k_lattice(const double* __restrict__ R, int n, int np, const flo
     phi_d[i] = float(acc);
 }
 
+// Leaf evaluation with the field gradient: (u, E, dE/dx) from the leaf's own
+// downward density and its W-list upward densities (monopole densities only),
+// dE_a/dx_b = sum f (delta_ab / r^3 - 3 r_a r_b / r^5), plus the near part
+// (nearv, nearg) and, periodic, the moment terms (dE/dx = -2 k1 Q I).  One
+// item per block, four waves over the surface points and S lanes per target.
+template <int NP, int S>
+__device__ __forceinline__ void far_grad_item(int b, int first, int nt, int b2, const int4* __restrict__ anchor,
+                                              const int* __restrict__ woff, const int* __restrict__ widx,
+                                              const float4* __restrict__ pts, const float* __restrict__ phi_d,
+                                              const float* __restrict__ phi_u, const float4* __restrict__ surf,
+                                              int n, const BoxGeom& geo, float cst, FarOut out,
+                                              const float* __restrict__ nearg, float* __restrict__ grad,
+                                              float4* stage, float* red) {
+    constexpr int NV = 10, NSL = 4 * S, ITER = NP / NSL;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, tid = threadIdx.x;
+    const int slice = lane & (S - 1);
+    const int i = first + lane / S;
+    const bool act = lane / S < nt;
+    const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
+    const int self = b >= b2 ? 1 : 0;
+    const int nsrc = self + (woff[b + 1] - woff[b]);
+    const int sl = w * S + slice;
+    float v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = 0.f;
+    for (int k = 0; k < nsrc; ++k) {
+        const bool own = self && k == 0;
+        const int e = own ? b : widx[woff[b] + k - self];
+        const int A = img_box(e);
+        const float* D = (own ? phi_d : phi_u) + size_t(A) * NP;
+        const float4* SF = own ? surf + NP : surf;
+        __syncthreads();
+        for (int t = tid; t < NP; t += 256) {
+            const bool real = t < n;
+            const float4 sp = SF[real ? t : 0];
+            stage[t] = make_float4(sp.x, sp.y, sp.z, real ? D[t] : 0.f);
+        }
+        __syncthreads();
+        float c[3], invw, wd;
+        box_frame(geo, anchor[A], c, invw, wd, e);
+        const float xx = (x.x - c[0]) * invw, xy = (x.y - c[1]) * invw, xz = (x.z - c[2]) * invw;
+        float a[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) a[q] = 0.f;
+#pragma unroll
+        for (int m = 0; m < ITER; ++m) {
+            const float4 sp = stage[sl + NSL * m];
+            const float dx = xx - sp.x, dy = xy - sp.y, dz = xz - sp.z;
+            const float ri = __frsqrt_rn(dx * dx + dy * dy + dz * dz);
+            const float ri2 = ri * ri;
+            const float fr = sp.w * ri;
+            const float g = fr * ri2;
+            const float h = 3.f * g * ri2;
+            a[0] += fr;
+            a[1] += g * dx;
+            a[2] += g * dy;
+            a[3] += g * dz;
+            a[4] += g - h * dx * dx;
+            a[5] += g - h * dy * dy;
+            a[6] += g - h * dz * dz;
+            a[7] -= h * dx * dy;
+            a[8] -= h * dx * dz;
+            a[9] -= h * dy * dz;
+        }
+        // true units: potential 1/w, field 1/w^2, gradient 1/w^3
+        const float iw2 = invw * invw, iw3 = iw2 * invw;
+        v[0] += a[0] * invw;
+#pragma unroll
+        for (int q = 1; q < 4; ++q) v[q] += a[q] * iw2;
+#pragma unroll
+        for (int q = 4; q < NV; ++q) v[q] += a[q] * iw3;
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = far_sum(v[q], S);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[(w * NV + q) * 64 + lane] = v[q];
+    __syncthreads();
+    if (w == 0 && act && slice == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            v[q] = cst * (((red[q * 64 + lane] + red[(NV + q) * 64 + lane]) + red[(2 * NV + q) * 64 + lane]) +
+                          red[(3 * NV + q) * 64 + lane]);
+        if (out.mom) {
+            const double y[3] = {double(x.x) - out.o[0], double(x.y) - out.o[1], double(x.z) - out.o[2]};
+            double u0, E0[3];
+            moment_terms(out.mom, out.k1, y, u0, E0);
+            v[0] = float(double(v[0]) + u0);
+            for (int d = 0; d < 3; ++d) {
+                v[1 + d] = float(double(v[1 + d]) + E0[d]);
+                v[4 + d] = float(double(v[4 + d]) - 2.0 * out.k1 * out.mom[0]);
+            }
+        }
+        const float4 nr = out.nearv[i];
+        const size_t j = size_t(out.perm[i]);
+        if (out.a) out.a[j] = v[0] + nr.x;
+        if (out.b) {
+            out.b[3 * j] = v[1] + nr.y;
+            out.b[3 * j + 1] = v[2] + nr.z;
+            out.b[3 * j + 2] = v[3] + nr.w;
+        }
+        if (grad)
+            for (int q = 0; q < 6; ++q) grad[6 * j + q] = v[4 + q] + nearg[6 * size_t(i) + q];
+    }
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_far_grad(const int2* __restrict__ items, int b2,
+                                                  const int4* __restrict__ anchor, const int2* __restrict__ range,
+                                                  const int* __restrict__ woff, const int* __restrict__ widx,
+                                                  const float4* __restrict__ pts, const float* __restrict__ phi_d,
+                                                  const float* __restrict__ phi_u, const float4* __restrict__ surf,
+                                                  int n, BoxGeom geo, float cst, FarOut out,
+                                                  const float* __restrict__ nearg, float* __restrict__ grad) {
+    __shared__ float red[4 * 10 * 64];
+    __shared__ float4 stage[NP];
+    const int2 it = items[blockIdx.x];
+    const int b = it.x;
+    const int nt = min(64, range[b].y - it.y);
+#define KIFMM_FARG_ITEM(SV)                                                                                      \
+    far_grad_item<NP, SV>(b, it.y, nt, b2, anchor, woff, widx, pts, phi_d, phi_u, surf, n, geo, cst, out, nearg, \
+                          grad, stage, red)
+    switch (far_lanes(nt)) {
+    case 8: KIFMM_FARG_ITEM(8); break;
+    case 4: KIFMM_FARG_ITEM(4); break;
+    case 2: KIFMM_FARG_ITEM(2); break;
+    default: KIFMM_FARG_ITEM(1); break;
+    }
+#undef KIFMM_FARG_ITEM
+}
+
 __global__ void k_fill0(float* __restrict__ p, size_t n) {
     size_t i = blockIdx.x * size_t(256) + threadIdx.x;
     if (i < n) p[i] = 0.f;
@@ -1200,7 +1331,37 @@ void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s
                            P->N, fo);
 }
 
+template <int NP>
+void far_grad_impl(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs) {
+    const Operators& op = *P->ops;
+    BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
+    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), pot, field, nullptr, {0, 0, 0}, 0.0};
+    if (P->periodic) {
+        fo.mom = P->mom.as<double>() + 16 * rhs;
+        for (int d = 0; d < 3; ++d) fo.o[d] = P->lo[d] + 0.5 * P->side;
+        fo.k1 = 2.0 * M_PI * P->c / (3.0 * P->side * P->side * P->side);
+    }
+    const size_t stride = size_t(P->B) * NP;
+    hipLaunchKernelGGL((k_far_grad<NP>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(),
+                       int(P->bfar), P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->w_off.as<int>(),
+                       P->w_idx.as<int>(), P->pts.as<float4>(), P->phi_d.as<float>() + rhs * stride,
+                       P->phi_u.as<float>() + rhs * stride, op.surf.as<float4>(), op.n, geo, float(P->c), fo,
+                       P->nearg.as<float>(), grad);
+}
+
 }  // namespace
+
+void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs) {
+    switch (P->npad) {
+        case 32: far_grad_impl<32>(P, pot, field, grad, s, rhs); break;
+        case 64: far_grad_impl<64>(P, pot, field, grad, s, rhs); break;
+        case 128: far_grad_impl<128>(P, pot, field, grad, s, rhs); break;
+        case 160: far_grad_impl<160>(P, pot, field, grad, s, rhs); break;
+        case 224: far_grad_impl<224>(P, pot, field, grad, s, rhs); break;
+        case 320: far_grad_impl<320>(P, pot, field, grad, s, rhs); break;
+        default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
+    }
+}
 
 void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between) {
     switch (P->npad) {

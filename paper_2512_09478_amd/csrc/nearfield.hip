@@ -186,6 +186,68 @@ __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items,
     }
 }
 
+// Near field with the field gradient, of monopoles (src2.x, or pts.w without
+// src2) and dipoles (src2.yzw): u, E and dE_a/dx_b = -Hess u, the dipole
+// part of the Hessian being 3 (m_a r_b + m_b r_a + (m.r) delta_ab)/r^5
+// - 15 (m.r) r_a r_b / r^7.  (u, E) go to nearv, dE/dx (xx yy zz xy xz yz)
+// to nearg.
+__global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items, int n_items,
+                                                  const int2* __restrict__ range, const int* __restrict__ uoff,
+                                                  const int* __restrict__ uidx, const float4* __restrict__ pts,
+                                                  const float4* __restrict__ src2, float cst, float cell,
+                                                  float4* __restrict__ nearv, float* __restrict__ nearg) {
+    __shared__ float4 sh[NF_STAGE];
+    __shared__ float4 sh2[NF_STAGE];
+    __shared__ float red[4][10][64];
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int2 it = items[item];
+        const int b = it.x;
+        const int nt = min(64, range[b].y - it.y);
+        const int S = lanes_per_target(nt);
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int slice = lane & (S - 1);
+        const int i = it.y + lane / S;
+        const bool act = lane / S < nt;
+        const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
+        float v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // u, E xyz, dE/dx xx yy zz xy xz yz
+        stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
+            for (int j = w * S + slice; j < m; j += 4 * S) {
+                const float4 y = sh[j];
+                const float4 bj = src2 ? sh2[j] : make_float4(y.w, 0.f, 0.f, 0.f);
+                const float d[3] = {x.x - y.x, x.y - y.y, x.z - y.z};
+                const float ri = rsq(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                const float ri2 = ri * ri;
+                const float ri3 = ri2 * ri;
+                const float ri5 = ri3 * ri2;
+                const float mr = d[0] * bj.y + d[1] * bj.z + d[2] * bj.w;
+                const float mv[3] = {bj.y, bj.z, bj.w};
+                v[0] += bj.x * ri - mr * ri3;
+                const float gh = bj.x * ri3 - 3.f * mr * ri5;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) v[1 + a] += gh * d[a] + mv[a] * ri3;
+                // dE_a/dx_b = q (delta_ab/r^3 - 3 d_a d_b/r^5) - dipole Hessian
+                const float t3 = 3.f * bj.x * ri5, t15 = 15.f * mr * ri5 * ri2;
+                constexpr int A[6] = {0, 1, 2, 0, 0, 1}, Bc[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const int a = A[k], c = Bc[k];
+                    float t = -t3 * d[a] * d[c] - 3.f * ri5 * (mv[a] * d[c] + mv[c] * d[a]) + t15 * d[a] * d[c];
+                    if (a == c) t += bj.x * ri3 - 3.f * mr * ri5;
+                    v[4 + k] += t;
+                }
+            }
+        });
+#pragma unroll
+        for (int q = 0; q < 10; ++q) v[q] = lane_sum(v[q], S);
+        wave_reduce<10>(v, red);
+        if (w == 0 && act && slice == 0) {
+            nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) nearg[6 * size_t(i) + k] = cst * v[4 + k];
+        }
+    }
+}
+
 // Backward near field, summed directly as the near part of the combination
 //   qbar_k = psi_k,  xbar_k = -ubar_k E_k - H_k Ebar_k - q_k E_psi,k
 // where E, H come from the charges q and psi, E_psi from monopoles ubar and
@@ -277,6 +339,14 @@ void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p_dip, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
                        int(P->n_items), P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(),
                        P->pts.as<float4>(), P->src2.as<float4>(), float(P->c), float(P->side), P->nearv.as<float4>());
+}
+
+void launch_p2p_gradient(kifmm_plan* P, bool dipoles, hipStream_t s) {
+    P->nearg.ensure(size_t(P->N) * 24);
+    hipLaunchKernelGGL(k_p2p_grad, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
+                       int(P->n_items), P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(),
+                       P->pts.as<float4>(), dipoles ? P->src2.as<float4>() : nullptr, float(P->c), float(P->side),
+                       P->nearv.as<float4>(), P->nearg.as<float>());
 }
 
 void launch_p2p_backward(kifmm_plan* P, hipStream_t s) {

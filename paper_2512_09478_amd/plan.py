@@ -125,6 +125,19 @@ class Plan:
         check(_lib.lib().kifmm_evaluate_dipoles(self.handle, _ptr(q), _ptr(m), _ptr(u), _ptr(E), _stream(stream)))
         return u, E
 
+    def evaluate_gradient(self, charges=None, dipoles=None, potential=True, field=True, stream=None):
+        """u, E and dE/dx ([N,6]: xx, yy, zz, xy, xz, yz) of charges and/or point dipoles."""
+        q = None if charges is None else _need(charges, torch.float32, (self.n,), "charges")
+        m = None if dipoles is None else _need(dipoles, torch.float32, (self.n, 3), "dipoles")
+        dev = self.positions.device
+        u = torch.empty(self.n, dtype=torch.float32, device=dev) if potential else None
+        E = torch.empty((self.n, 3), dtype=torch.float32, device=dev) if field else None
+        G = torch.empty((self.n, 6), dtype=torch.float32, device=dev)
+        self._fwd_token = None
+        check(_lib.lib().kifmm_evaluate_gradient(self.handle, _ptr(q), _ptr(m), _ptr(u), _ptr(E), _ptr(G),
+                                                 _stream(stream)))
+        return u, E, G
+
     def backward(self, charges, grad_potential=None, grad_field=None, stream=None):
         """dL/dq, dL/dx.  ``charges=None`` reuses the charges and forward
         densities of the last evaluate on this plan (no forward sweep)."""

@@ -63,6 +63,7 @@ def test_argument_errors_without_gpu(L):
     # null handles
     assert L.kifmm_evaluate(None, dummy, None, None, None) == -5
     assert L.kifmm_evaluate_dipoles(None, dummy, dummy, None, None, None) == -5
+    assert L.kifmm_evaluate_gradient(None, dummy, None, None, None, None, None) == -5
     assert L.kifmm_backward(None, dummy, None, None, None, None, None) == -5
     assert L.kifmm_clump_reduce(None, dummy, dummy, dummy, 1, dummy, dummy, dummy, None) == -5
     assert L.kifmm_clump_backward(None, dummy, dummy, dummy, 1, dummy, None, None, None, None, None, None,

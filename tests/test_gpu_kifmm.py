@@ -165,6 +165,45 @@ def test_dipole_forward_parity(built, precision):
     assert rel(u2.cpu().numpy(), uo2) <= TOL[precision] and rel(E2.cpu().numpy(), Eo2) <= TOL[precision]
 
 
+@pytest.mark.parametrize("with_charges,with_dipoles", [(True, False), (True, True), (False, True)])
+def test_field_gradient_parity(built, with_charges, with_dipoles):
+    # u, E and dE/dx of charges and/or dipoles against the oracle's sweep
+    say(f"field gradient charges={with_charges} dipoles={with_dipoles}")
+    w = workloads.make(2, n=8000)
+    rng = np.random.default_rng(44)
+    m = workloads.round_f32(rng.standard_normal((w.n, 3)) * 2e-3)
+    G = gpu_plan(w, 48, "split_bf16", p=6)
+    O = oracle_plan(w, 48, 6)
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda") if with_charges else None
+    md = torch.tensor(m, dtype=torch.float32, device="cuda") if with_dipoles else None
+    u, E, Gr = G.evaluate_gradient(q, md)
+    uo, Eo, Go = kifmm.forward_dipoles(O, w.charges if with_charges else None, m if with_dipoles else None,
+                                       grad=True)
+    eu, eE, eG = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo), rel(Gr.cpu().numpy(), Go)
+    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}  dE/dx {eG:.3e}")
+    assert eu <= TOL["split_bf16"] and eE <= TOL["split_bf16"] and eG <= TOL["split_bf16"]
+    # the potential and field equal those of the plain calls
+    if with_dipoles:
+        u2, E2 = G.evaluate_dipoles(q, md)
+    else:
+        u2, E2 = G.evaluate(q)
+    assert rel(u.cpu().numpy(), u2.cpu().numpy().astype(np.float64)) <= 1e-6
+    assert rel(E.cpu().numpy(), E2.cpu().numpy().astype(np.float64)) <= 1e-6
+
+
+def test_field_gradient_fp32_parity(built):
+    say("field gradient fp32")
+    w = workloads.make(4, n=9000)
+    G = gpu_plan(w, 32, "fp32", p=6)
+    O = oracle_plan(w, 32, 6)
+    u, E, Gr = G.evaluate_gradient(torch.tensor(w.charges, dtype=torch.float32, device="cuda"))
+    uo, Eo, Go = kifmm.forward_dipoles(O, w.charges, None, grad=True)
+    eG = rel(Gr.cpu().numpy(), Go)
+    say(f"  rel-L2 dE/dx {eG:.3e}")
+    assert rel(u.cpu().numpy(), uo) <= TOL["fp32"] and rel(E.cpu().numpy(), Eo) <= TOL["fp32"]
+    assert eG <= TOL["fp32"]
+
+
 def test_deterministic_repeat(built):
     say("repeatability")
     w = workloads.make(2, n=8000)

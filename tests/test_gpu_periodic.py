@@ -146,6 +146,19 @@ def test_periodic_dipoles_parity(built):
     assert eu <= TOL["fp32"] and eE <= TOL["fp32"]
 
 
+def test_periodic_field_gradient_parity(built):
+    say("periodic field gradient")
+    x, q, G, O = plans("clusters")
+    rng = np.random.default_rng(7)
+    m = workloads.round_f32(rng.standard_normal((x.shape[0], 3)) * 3e-3)
+    u, E, Gr = G.evaluate_gradient(torch.tensor(q, dtype=torch.float32, device="cuda"),
+                                   torch.tensor(m, dtype=torch.float32, device="cuda"))
+    uo, Eo, Go = kifmm.forward_dipoles(O, q, m, grad=True)
+    eu, eE, eG = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo), rel(Gr.cpu().numpy(), Go)
+    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}  dE/dx {eG:.3e}")
+    assert eu <= TOL["fp32"] and eE <= TOL["fp32"] and eG <= TOL["fp32"]
+
+
 @pytest.mark.parametrize("n,leaf", [(20, 64), (300, 64)])
 def test_periodic_shallow_trees(built, n, leaf):
     # a root leaf (its own 27 images in U) and a depth-1 tree (V lists at level 1 only)
