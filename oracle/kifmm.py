@@ -89,14 +89,21 @@ def _image(P: Plan, e):
     return b, sh * P.tree.s
 
 
+_LATTICE = {}
+
+
 def lattice_operator(P: Plan) -> np.ndarray:
     """Root downward check potential from the root upward density for all
-    images at cube distance >= 2: c F(dc_i - ue_j), F the harmonic lattice kernel."""
+    images at cube distance >= 2: c F(dc_i - ue_j), F the harmonic lattice
+    kernel (kept per (p, cell side, c) for the process)."""
     t = P.tree
-    dc = surface(P.p, RHO_DC, 0, t.s)
-    ue = surface(P.p, RHO_UE, 0, t.s)
-    r = (dc[:, None, :] - ue[None, :, :]).reshape(-1, 3)
-    return P.c * lattice_far(r, t.s).reshape(dc.shape[0], ue.shape[0])
+    key = (P.p, float(t.s), float(P.c))
+    if key not in _LATTICE:
+        dc = surface(P.p, RHO_DC, 0, t.s)
+        ue = surface(P.p, RHO_UE, 0, t.s)
+        r = (dc[:, None, :] - ue[None, :, :]).reshape(-1, 3)
+        _LATTICE[key] = P.c * lattice_far(r, t.s).reshape(dc.shape[0], ue.shape[0])
+    return _LATTICE[key]
 
 
 def _octant(anchor):
