@@ -175,6 +175,27 @@ def test_periodic_shallow_trees(built, n, leaf):
     assert eu <= 1e-5 and eE <= 1e-5
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_periodic_uniform_tree(built, precision):
+    # every leaf at depth 2 (4 x 4 x 4 leaves): neighbours wrap at every face
+    say(f"periodic uniform tree {precision}")
+    from paper_2512_09478_amd import Plan
+    w = workloads.make(1, n=4096)
+    q = workloads.round_f32(w.charges - w.charges.mean())
+    G = Plan(torch.tensor(w.positions, dtype=torch.float64, device="cuda"), "laplace", 4, 64, False, 21,
+             precision=precision, root=CELL, periodic=True)
+    O = kifmm.plan(w.positions, "laplace", 4, 64, False, 21, CELL, periodic=True)
+    for which in "UVWX":
+        off, idx = G.list_csr(which)
+        ooff, oidx = O.lists.csr(which)
+        np.testing.assert_array_equal(idx, oidx, err_msg=which)
+    u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
+    uo, Eo = kifmm.forward(O, q)
+    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
+    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
+    assert eu <= TOL[precision] and eE <= TOL[precision]
+
+
 def test_periodic_argument_errors(built):
     from paper_2512_09478_amd import KifmmError, Plan
     x = torch.rand((50, 3), dtype=torch.float64, device="cuda")

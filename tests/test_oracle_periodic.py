@@ -247,3 +247,16 @@ def test_periodic_adjoint_exact_differences():
         d2 = (at(h / 2) - at(-h / 2)) / h
         fd = (4 * d2 - d1) / 3
         assert abs(fd - xb[k, a]) <= 1e-6 * max(1.0, np.abs(xb).max())
+
+
+def test_periodic_uniform_tree_list_sizes_closed_form():
+    # a full uniform tree of depth 2 in a periodic cell: every box below the
+    # root sees 8 x 27 - 27 = 189 far children of its parent's 27 neighbour
+    # images, every leaf its 27 neighbour images, and there is no W or X
+    x = np.random.default_rng(15).random((4096, 3))
+    t = T.build_tree(x, 64, False, 21, CELL)
+    L = T.build_lists(t, periodic=True)
+    assert t.depth == 2 and t.nboxes == 73
+    assert all(len(L.V[b]) == (189 if b > 0 else 0) for b in range(t.nboxes))
+    assert all(len(L.U[b]) == 27 for b in t.leaves())
+    assert sum(len(r) for r in L.W) == 0 and sum(len(r) for r in L.X) == 0
