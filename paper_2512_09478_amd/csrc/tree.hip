@@ -963,9 +963,14 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                            P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
                            (int*)nullptr, 0);
     exclusive_scan<int>(P, xoff, xoff, B + 1, s);
-    int nx = read_int(P, xoff + B, s);
-    P->x_idx.ensure(size_t(std::max(nx, 1)) * 4);
-    if (nvb > 0 && nx > 0) {
+    // List storage is sized by bounds, so that no size is read back here:
+    // X(b) <= 26 leaf colleagues of the parent + 26 coarse adjacent leaves of
+    // the parent; U(b) <= 27 + 26 of its own, and the finer part adds one
+    // entry per coarse-adjacent entry of a finer leaf (<= 26 per box); W is X
+    // transposed.  The sizes themselves are read with the final counts.
+    const size_t xcap = size_t(std::max(nvb, 1)) * 52, ucap = size_t(B) * (53 + 26);
+    P->x_idx.ensure(xcap * 4);
+    if (nvb > 0) {
         hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
                            P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
                            P->x_idx.as<int>(), 1);
@@ -984,8 +989,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
                        uoff, (int*)nullptr, (int*)nullptr, 0);
     exclusive_scan<int>(P, uoff, uoff, B + 1, s);
-    int nu = read_int(P, uoff + B, s);
-    P->u_idx.ensure(size_t(std::max(nu, 1)) * 4);
+    P->u_idx.ensure(ucap * 4);
     hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
                        P->cal.as<int>(), uoff, P->u_idx.as<int>(), cursor, 1);
     hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
@@ -999,9 +1003,8 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(), woff,
                            (int*)nullptr, (int*)nullptr, 0);
     exclusive_scan<int>(P, woff, woff, B + 1, s);
-    int nw = read_int(P, woff + B, s);
-    P->w_idx.ensure(size_t(std::max(nw, 1)) * 4);
-    if (nvb > 0 && nw > 0) {
+    P->w_idx.ensure(xcap * 4);
+    if (nvb > 0) {
         hipLaunchKernelGGL(k_copy_int, dim3(nblocks(B + 1)), dim3(TB), 0, s, woff, cursor, B + 1);
         hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(),
                            (int*)nullptr, P->w_idx.as<int>(), cursor, 1);
@@ -1068,9 +1071,14 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     unsigned long long* hw = P->host.get();
     KIFMM_HIP(hipMemcpyAsync(hw, dc, 16, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipMemcpyAsync(hw + 2, bad, 4, hipMemcpyDeviceToHost, s));
+    int* hl = reinterpret_cast<int*>(hw + 3);   // list sizes: X, U, W
+    KIFMM_HIP(hipMemcpyAsync(hl, xoff + B, 4, hipMemcpyDeviceToHost, s));
+    KIFMM_HIP(hipMemcpyAsync(hl + 1, uoff + B, 4, hipMemcpyDeviceToHost, s));
+    KIFMM_HIP(hipMemcpyAsync(hl + 2, woff + B, 4, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipStreamSynchronize(s));
     const unsigned long long hc[2] = {hw[0], hw[1]};
     const int hbad = int(hw[2] & 0xffffffffull);
+    const int nx = hl[0], nu = hl[1], nw = hl[2];
     if (hbad & 1)
         throw Error(KIFMM_ERR_INPUT, o.explicit_root ? "non-finite position or point outside the explicit root"
                                                      : "non-finite position");
