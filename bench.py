@@ -202,6 +202,7 @@ def counter_run(precision):
     torch.neg(a, out=b)
     torch.cuda.synchronize()
     log(f"[bench] counter run done: {plan.counts()}")
+    print(json.dumps({"counts": plan.counts(), "precision": precision}), flush=True)
     plan.close()
 
 
@@ -230,6 +231,79 @@ def summarize_trace(db, out, cmd):
         for r in rows:
             f.write(f"| `{short_name(r[0])}` | {r[1]} | {r[2]} | {r[3]:.3f} | {r[4]:.1f} | {r[5]:.1f} | "
                     f"{r[6]:.1f} | {r[7]} | {r[8]} | {r[9]} |\n")
+
+
+def summarize_counters(csv_a, counts_json, out, cmd_a):
+    """Matrix-core utilisation and instruction counts of the dominant kernels
+    from one counter pass over --counter-run (the counts line that run prints
+    gives the P2P pair and M2L V-pair numbers)."""
+    import csv
+    from collections import defaultdict
+    counts = None
+    for line in open(counts_json):
+        line = line.strip()
+        if line.startswith("{") and '"counts"' in line:
+            counts = json.loads(line)
+    if counts is None:
+        raise SystemExit("no counts line in " + counts_json)
+    c = counts["counts"]
+    acc = defaultdict(lambda: defaultdict(list))
+    dur = defaultdict(list)
+    seen = set()
+    for r in csv.DictReader(open(csv_a)):
+        k = (short_name(r["Kernel_Name"]), int(r["Grid_Size"]))
+        acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        if r["Dispatch_Id"] not in seen:
+            seen.add(r["Dispatch_Id"])
+            dur[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    mean = {k: {n: float(np.mean(v)) for n, v in d.items()} for k, d in acc.items()}
+    simds = 256 * 4
+    xcds = 8   # GRBM_GUI_ACTIVE of a dispatch is summed over the eight XCDs
+    rows = []
+    for k in sorted(mean, key=lambda k: -float(np.mean(dur[k]))):
+        m = mean[k]
+        t = float(np.mean(dur[k]))
+        if "GRBM_GUI_ACTIVE" not in m or t < 20e-6:
+            continue
+        gui = m["GRBM_GUI_ACTIVE"]
+        mfma = m.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) * xcds / (gui * simds) if gui else 0.0
+        rows.append((k, t, mfma, m.get("SQ_INSTS_VALU", 0.0), m.get("SQ_INSTS_MFMA", 0.0)))
+    n = c["surface_points"]
+    nl = "\n"
+    with open(out, "w") as f:
+        f.write("# Matrix-core utilisation and instruction counts: clustered 1,048,576 charges, p = 6, "
+                f"leaf 128, {counts['precision']} path, forward evaluation" + nl + nl)
+        f.write("One counter pass over the program (repository root on an MI355X):" + nl + nl)
+        f.write("```" + nl + cmd_a + nl + "```" + nl + nl)
+        f.write("MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE / 8), per dispatch "
+                "and averaged over the dispatches of a kernel and grid: the busy cycles are summed over the "
+                "SIMDs, and GRBM_GUI_ACTIVE is summed over the eight XCDs (it reads about 8 x the kernel's "
+                "duration in cycles).  The instruction columns are wave-level instruction counts per "
+                "dispatch.  Durations are those of the counter run." + nl + nl)
+        f.write("| kernel | grid | avg us | MFMA busy | VALU instructions | MFMA instructions |" + nl)
+        f.write("|---|---|---|---|---|---|" + nl)
+        for (k, t, mf, iv, im) in rows[:16]:
+            f.write(f"| `{k[0]}` | {k[1]} | {t * 1e6:.1f} | {mf:.3f} | {iv:.4g} | {im:.4g} |" + nl)
+        m2l = [r for r in rows if r[0][0].startswith("void k_m2l")]
+        p2p = [r for r in rows if r[0][0] == "k_p2p"]
+        f.write(nl + "Achieved rates in this run (algorithmic work over the dispatch's own duration):" + nl + nl)
+        if m2l:
+            t = m2l[0][1]
+            fl = 2.0 * n * n * c["v_pairs"]
+            ex = m2l[0][4] * 2 * 16 * 16 * 32   # every M2L MFMA of the split path is a 16x16x32 bf16 product
+            f.write(f"* `k_m2l`: {c['v_pairs']:,} V pairs x 2 x {n}^2 = {fl / 1e9:.1f} GFLOP in {t * 1e3:.3f} ms "
+                    f"= {fl / t / 1e12:.1f} TFLOP/s useful ({fl / t / 2.5e15 * 100:.1f} % of the bf16 dense "
+                    f"peak); executed {m2l[0][4]:.4g} bf16 16x16x32 MFMAs = {ex / 1e12:.2f} TFLOP, "
+                    f"{ex / t / 1e15:.2f} PFLOP/s ({ex / t / 2.5e15 * 100:.1f} % of 2.5 PFLOP/s: three products "
+                    f"per split product, padding to {((n + 31) // 32) * 32} rows, slots walked for a block's "
+                    f"union of targets); MFMA busy {m2l[0][2] * 100:.1f} %." + nl)
+        if p2p:
+            t = p2p[0][1]
+            fl = 20.0 * c["p2p_pairs"]
+            f.write(f"* `k_p2p`: {c['p2p_pairs']:,} pairs x 20 FLOP = {fl / 1e9:.1f} GFLOP in {t * 1e3:.3f} ms = "
+                    f"{fl / t / 1e12:.1f} TFLOP/s FP32 ({fl / t / 157.3e12 * 100:.1f} % of 157.3 TFLOP/s); "
+                    f"{p2p[0][3] * 64 / max(1, c['p2p_pairs']):.1f} VALU instructions per pair (each lane "
+                    "takes one pair per pass of the inner loop)." + nl)
 
 
 def summarize_traffic(fetch_csv, write_csv, out, cmd_fetch, cmd_write, precision):
@@ -297,11 +371,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counter-run", metavar="PRECISION", help="short run for rocprofv3 counter passes")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT", "CMD"))
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("CSV", "COUNTS_LOG", "OUT", "CMD"))
     ap.add_argument("--summarize-traffic", nargs=6,
                     metavar=("FETCH_CSV", "WRITE_CSV", "OUT", "CMD_FETCH", "CMD_WRITE", "PRECISION"))
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
