@@ -126,15 +126,17 @@ def source_digest(kernel):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic(kernel, precision):
+def stored_traffic(kernel, precision, workload, n):
     """HBM bytes per launch from the committed counter summary, or None when
-    there is none or the kernel's source file changed since it was taken."""
+    there is none for this kernel, path and workload, or the kernel's source
+    file changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             for line in f:
                 if line.startswith("traffic_json: "):
                     rec = json.loads(line[len("traffic_json: "):])
                     if (rec["kernel"] == kernel and rec["precision"] == precision
+                            and rec.get("workload") == workload and rec.get("n") == n
                             and rec["source_sha256_16"] == source_digest(kernel)):
                         return rec["bytes_per_launch"]
     except (OSError, ValueError, KeyError):
@@ -142,7 +144,7 @@ def stored_traffic(kernel, precision):
     return None
 
 
-def roofline(res, n, precision):
+def roofline(res, n, precision, workload, npts):
     ph = res["phases_fwd_ms"]
     c = res["counts"]
     cand = {"m2l": ph["m2l"], "p2p": ph["p2p"]}
@@ -152,12 +154,13 @@ def roofline(res, n, precision):
         peak = PEAK["bf16"] if precision == "split_bf16" else PEAK["fp32"]
         ach = flops / (ph["m2l"] * 1e-3) / 1e12
         return dict(kernel="k_m2l", bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
-                    traffic=stored_traffic("k_m2l", precision), per_launch_ms=ph["m2l"],
+                    traffic=stored_traffic("k_m2l", precision, workload, npts), per_launch_ms=ph["m2l"],
                     work=f"2 n^2 x {c['v_pairs']} V pairs")
     flops = P2P_FLOP_PER_PAIR * c["p2p_pairs"]
     ach = flops / (ph["p2p"] * 1e-3) / 1e12
     return dict(kernel="k_p2p", bound="alu", achieved=ach, peak=PEAK["fp32"], unit="TFLOP/s",
-                frac=ach / PEAK["fp32"], traffic=stored_traffic("k_p2p", precision), per_launch_ms=ph["p2p"],
+                frac=ach / PEAK["fp32"], traffic=stored_traffic("k_p2p", precision, workload, npts),
+                per_launch_ms=ph["p2p"],
                 work=f"20 x {c['p2p_pairs']} pairs")
 
 
@@ -181,6 +184,10 @@ def cpu_baseline(k):
     return dict(value=n / t, unit="particles/s", cores=cores, kind="oracle",
                 sample=f"the same workload generator at N={n} (same p, leaf, tree rules): "
                        f"tree+lists+forward+adjoint in FP64, {t:.1f} s")
+
+
+# the workload --counter-run evaluates (its name and size, as recorded with the counters)
+COUNTER_WORKLOAD = ("clustered_1M_p6", 1_048_576)
 
 
 def counter_run(precision):
@@ -338,7 +345,8 @@ def summarize_traffic(fetch_csv, write_csv, out, cmd_fetch, cmd_write, precision
         for kern in KERNEL_SOURCE:
             if base == kern and not any(r["kernel"] == kern for r in recs):
                 # the first (largest-fetch) entry of a kernel is its forward launch
-                recs.append(dict(kernel=kern, precision=precision, grid=k[1], bytes_per_launch=fb + wb,
+                recs.append(dict(kernel=kern, precision=precision, workload=COUNTER_WORKLOAD[0],
+                                 n=COUNTER_WORKLOAD[1], grid=k[1], bytes_per_launch=fb + wb,
                                  fetch_bytes=fb, write_bytes=wb, source_sha256_16=source_digest(kern)))
     with open(out, "w") as f:
         f.write("# HBM traffic per dispatch: clustered 1,048,576 charges, p = 6, leaf 128, "
@@ -411,6 +419,8 @@ def main():
     head = "split_bf16" if "split_bf16" in paths else next(iter(paths))
     H = paths[head]
     ops_n = H["counts"]["surface_points"]
+    # stored counter traffic applies to the static workload it was taken on only
+    wkey = w.name + ("+move" if args.move else "")
     agree = {}
     if "fp32" in paths and "split_bf16" in paths:
         for name, i in (("u", 0), ("E", 1), ("qbar", 2), ("xbar", 3)):
@@ -433,14 +443,14 @@ def main():
         "config": {"workload": WORKLOADS[args.workload] + "; step = re-tree + forward + adjoint"
                                + (f"; particles move by N(0, {args.move}^2) per axis each step" if args.move else ""),
                    "name": w.name, "n": n, "p": w.p, "leaf_size": w.leaf_size, "path": head},
-        "roofline": roofline(H, ops_n, head),
+        "roofline": roofline(H, ops_n, head, wkey, n),
         "paths": {k: {"particles_per_s": n / (v["ms_per_step"] * 1e-3), "ms_per_step": v["ms_per_step"],
                       "particles_per_s_without_tree": n / ((v["t_fwd_ms"] + v["t_adj_ms"]) * 1e-3),
                       "particles_per_s_forward": n / (v["t_fwd_ms"] * 1e-3),
                       "particles_per_s_adjoint": n / (v["t_adj_ms"] * 1e-3),
                       "t_tree_ms": v["t_tree_ms"], "t_fwd_ms": v["t_fwd_ms"], "t_adj_ms": v["t_adj_ms"],
                       "phases_fwd_ms": v["phases_fwd_ms"], "phases_adj_ms": v["phases_adj_ms"],
-                      "roofline": roofline(v, ops_n, k)}
+                      "roofline": roofline(v, ops_n, k, wkey, n)}
                   for k, v in paths.items()},
         "counts": H["counts"],
         "split_vs_fp32_rel_l2": agree,
