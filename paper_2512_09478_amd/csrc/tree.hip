@@ -246,8 +246,98 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__
     }
 }
 
+// The whole sort of at most RS_TILE keys in one block: each pass ranks the
+// keys as k_rs_scatter does (wave w owns the quarter [w*1024, (w+1)*1024),
+// peers by ballots), takes the digit offsets from the block's own counts and
+// scatters into LDS, from where the next pass reloads its quarter.
+__global__ __launch_bounds__(256) void k_rs_block(uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, int n,
+                                                  int passes) {
+    __shared__ uint64_t sk[RS_TILE];
+    __shared__ uint32_t sv[RS_TILE];
+    __shared__ uint32_t cnt[4][256];
+    __shared__ uint32_t base[4][256];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int b0 = w * RS_WAVE_ITEMS;
+    uint64_t k[RS_ITEMS];
+    uint32_t v[RS_ITEMS];
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int i = b0 + r * 64 + lane;
+        k[r] = i < n ? keys[i] : 0;
+        v[r] = i < n ? vals[i] : 0;
+    }
+    const uint64_t lt = lane_lt_mask();
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = 8 * ps;
+        for (int d = threadIdx.x; d < 4 * 256; d += TB) (&cnt[0][0])[d] = 0;
+        __syncthreads();
+        for (int r = 0; r < RS_ITEMS; ++r) {
+            const bool valid = b0 + r * 64 + lane < n;
+            const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+            for (int bt = 0; bt < 8; ++bt) {
+                const uint64_t m = __ballot((dg >> bt) & 1u);
+                peers &= ((dg >> bt) & 1u) ? m : ~m;
+            }
+            if (valid && (peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
+        }
+        __syncthreads();
+        {
+            // digit-major, then wave: base[w][d] = (keys with a smaller digit)
+            // + (keys with digit d in earlier quarters)
+            const int d = threadIdx.x;
+            const uint32_t t = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+            uint32_t total;
+            uint32_t run = block_exclusive_scan<uint32_t>(t, &total);
+            for (int ww = 0; ww < 4; ++ww) {
+                base[ww][d] = run;
+                run += cnt[ww][d];
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < RS_ITEMS; ++r) {
+            const bool valid = b0 + r * 64 + lane < n;
+            const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+            for (int bt = 0; bt < 8; ++bt) {
+                const uint64_t m = __ballot((dg >> bt) & 1u);
+                peers &= ((dg >> bt) & 1u) ? m : ~m;
+            }
+            uint32_t pos = 0;
+            if (valid) pos = base[w][dg] + uint32_t(__popcll(peers & lt));
+            __builtin_amdgcn_wave_barrier();
+            if (valid) {
+                sk[pos] = k[r];
+                sv[pos] = v[r];
+                if ((peers & lt) == 0) base[w][dg] += uint32_t(__popcll(peers));
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        for (int r = 0; r < RS_ITEMS; ++r) {
+            const int i = b0 + r * 64 + lane;
+            if (i < n) {
+                k[r] = sk[i];
+                v[r] = sv[i];
+            }
+        }
+        __syncthreads();
+    }
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int i = b0 + r * 64 + lane;
+        if (i < n) {
+            keys[i] = k[r];
+            vals[i] = v[r];
+        }
+    }
+}
+
 void radix_sort(kifmm_plan* P, uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n,
                 int bits, hipStream_t s) {
+    if (n <= 0) return;
+    if (n <= RS_TILE) {   // one block, one launch
+        hipLaunchKernelGGL(k_rs_block, dim3(1), dim3(TB), 0, s, keys, vals, int(n), (bits + 7) / 8);
+        return;
+    }
     int nblk = int((n + RS_TILE - 1) / RS_TILE);
     P->tmp_f.ensure(size_t(256) * nblk * 4);
     uint32_t* hist = P->tmp_f.as<uint32_t>();
@@ -276,12 +366,15 @@ void radix_sort(kifmm_plan* P, uint64_t* keys, uint32_t* vals, uint64_t* ktmp, u
 // at level l + 1 is >= o: every step samples 9 points of the group's interval
 // and keeps the tenth that holds the boundary (exact once the interval has
 // fewer than 10 entries).
+// Writes per front box its child count c and non-leaf child count n packed
+// as c | n << 32 (and a zero at index nf, so that one exclusive scan of nf + 1
+// values gives both offsets).
 __global__ void k_split(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
                         const int2* __restrict__ range, int* __restrict__ bounds /*[nf][9]*/,
-                        int* __restrict__ nch, int* __restrict__ nnl, int leaf_size, int adaptive,
-                        int max_depth, int Lu) {
+                        unsigned long long* __restrict__ cnt, int leaf_size, int adaptive, int max_depth, int Lu) {
     const int64_t gid = int64_t(blockIdx.x) * TB + threadIdx.x;
     const int f = int(gid >> 6), lane = int(gid & 63);
+    if (gid == 0) cnt[nf] = 0;
     if (f >= nf) return;   // uniform over the wave
     const int2 r = range[front[f]];
     const int shift = 3 * (kBits - (l + 1));
@@ -329,14 +422,13 @@ __global__ void k_split(const int* __restrict__ front, int nf, int l, const uint
                 if (!leaf) ++nl;
             }
         }
-        nch[f] = c;
-        nnl[f] = nl;
+        cnt[f] = (unsigned long long)c | ((unsigned long long)nl << 32);
     }
 }
 
 __global__ void k_emit(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
-                       const int* __restrict__ bounds, const int* __restrict__ choff,
-                       const int* __restrict__ nloff, int child_start, int nl_base,
+                       const int* __restrict__ bounds, const unsigned long long* __restrict__ off,
+                       int child_start, int nl_base,
                        int4* __restrict__ anchor, int2* __restrict__ range, int* __restrict__ parent,
                        int2* __restrict__ child, int* __restrict__ leafflag, uint64_t* __restrict__ mkey,
                        int* __restrict__ nonleaf, int leaf_size, int adaptive, int max_depth, int Lu) {
@@ -345,9 +437,10 @@ __global__ void k_emit(const int* __restrict__ front, int nf, int l, const uint6
     int P = front[f];
     int4 a = anchor[P];
     const int* bd = bounds + 9 * f;
-    int c = child_start + choff[f];
+    const unsigned long long of = off[f];   // child offset | non-leaf offset << 32
+    int c = child_start + int(of & 0xffffffffull);
     int first = c, mask = 0;
-    int nl = nl_base + nloff[f];
+    int nl = nl_base + int(of >> 32);
     int shift = 3 * (kBits - (l + 1));
     for (int o = 0; o < 8; ++o) {
         int cnt = bd[o + 1] - bd[o];
@@ -495,7 +588,8 @@ __global__ void k_cal(int b0, int nb, const int4* __restrict__ anchor, const int
             ++cnt;
         }
     }
-    for (int k = 0; k < 26; ++k) {
+    // (the root has no coarse adjacent leaves; its row is never written)
+    for (int k = 0; P > 0 && k < 26; ++k) {
         int Q = cal[26 * int64_t(P) + k];
         if (Q < 0) break;
         if (adjacent_image(anchor[img_box(Q)], Q, ab)) {
@@ -531,7 +625,7 @@ __global__ void k_xlist(int b0, int nb, const int4* __restrict__ anchor, const i
             ++c;
         }
     }
-    for (int k = 0; k < 26; ++k) {
+    for (int k = 0; P > 0 && k < 26; ++k) {
         int Q = cal[26 * int64_t(P) + k];
         if (Q < 0) break;
         if (!adjacent_image(anchor[img_box(Q)], Q, ab)) {
@@ -557,7 +651,7 @@ __global__ void k_ulist_own(int B, const int* __restrict__ leafflag, const int* 
             ++c;
         }
     }
-    for (int k = 0; k < 26; ++k) {
+    for (int k = 0; b > 0 && k < 26; ++k) {
         int Q = cal[26 * int64_t(b) + k];
         if (Q < 0) break;
         if (mode) idx[at + c] = Q;
@@ -572,7 +666,7 @@ __global__ void k_ulist_own(int B, const int* __restrict__ leafflag, const int* 
 __global__ void k_ulist_fine(int B, const int* __restrict__ leafflag, const int* __restrict__ cal,
                              int* __restrict__ cnt, int* __restrict__ idx, int* __restrict__ cursor, int mode) {
     int a = blockIdx.x * TB + threadIdx.x;
-    if (a >= B || !leafflag[a]) return;
+    if (a >= B || a == 0 || !leafflag[a]) return;   // a root leaf has no coarse adjacent leaves
     for (int k = 0; k < 26; ++k) {
         int e = cal[26 * int64_t(a) + k];
         if (e < 0) break;
@@ -636,6 +730,7 @@ __global__ void k_copy_int(const int* __restrict__ a, int* __restrict__ b, int n
 __global__ void k_flags(int B, const int* __restrict__ leafflag, const int* __restrict__ xcnt, int b2,
                         int* __restrict__ fl, int* __restrict__ fx) {
     int b = blockIdx.x * TB + threadIdx.x;
+    if (b == B) fl[B] = fx[B] = 0;   // the scans' last entries
     if (b >= B) return;
     fl[b] = leafflag[b];
     fx[b] = (b >= b2 && xcnt[b + 1] > xcnt[b]) ? 1 : 0;
@@ -685,6 +780,7 @@ __global__ void k_counts(int B, const int* __restrict__ leafflag, const int2* __
 __global__ void k_item_count(int nl, const int* __restrict__ leaves, const int2* __restrict__ range,
                              int* __restrict__ cnt) {
     int i = blockIdx.x * TB + threadIdx.x;
+    if (i == nl) cnt[nl] = 0;   // the scan's last entry
     if (i >= nl) return;
     int2 r = range[leaves[i]];
     cnt[i] = (r.y - r.x + 63) / 64;
@@ -880,35 +976,32 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         const LevelInfo cur = P->lev[l];
         if (cur.nl_count == 0) break;
         int nf = int(cur.nl_count);
-        P->tmp_a.ensure(size_t(nf) * 9 * 4 + size_t(nf) * 16 + 64);
+        const size_t bwords = (size_t(nf) * 9 + 1) & ~size_t(1);   // 8-byte aligned after the bounds
+        P->tmp_a.ensure(bwords * 4 + size_t(nf + 1) * 8 + 64);
         int* bounds = P->tmp_a.as<int>();
-        int* nch = bounds + 9 * nf;
-        int* nnl = nch + nf + 1;
-        // tmp_e holds the scans (nf+1 each)
+        unsigned long long* cnt = reinterpret_cast<unsigned long long*>(bounds + bwords);
+        // tmp_e holds the scan (nf+1 packed offsets)
         P->tmp_e.ensure(size_t(nf + 1) * 8 + 64);
-        int* choff = P->tmp_e.as<int>();
-        int* nloff = choff + nf + 1;
+        unsigned long long* off = P->tmp_e.as<unsigned long long>();
         const int* front = P->nonleaf.as<int>() + cur.nl_start;
-        hipLaunchKernelGGL(k_split, dim3(nblocks(int64_t(nf) * 64)), dim3(TB), 0, s, front, nf, l, keys, P->bx_range.as<int2>(),
-                           bounds, nch, nnl, P->leaf, o.adaptive, o.max_depth, Lu);
-        KIFMM_HIP(hipMemsetAsync(nch + nf, 0, 4, s));
-        KIFMM_HIP(hipMemsetAsync(nnl + nf, 0, 4, s));
-        exclusive_scan<int>(P, nch, choff, nf + 1, s);
-        exclusive_scan<int>(P, nnl, nloff, nf + 1, s);
-        int tot[2];
-        read_ints(P, s, {choff + nf, nloff + nf}, tot);
+        hipLaunchKernelGGL(k_split, dim3(nblocks(int64_t(nf) * 64)), dim3(TB), 0, s, front, nf, l, keys,
+                           P->bx_range.as<int2>(), bounds, cnt, P->leaf, o.adaptive, o.max_depth, Lu);
+        exclusive_scan<unsigned long long>(P, cnt, off, nf + 1, s);
+        unsigned long long* hw = P->host.get();
+        KIFMM_HIP(hipMemcpyAsync(hw, off + nf, 8, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipStreamSynchronize(s));
         LevelInfo nx;
         nx.start = total;
-        nx.count = tot[0];
+        nx.count = int64_t(hw[0] & 0xffffffffull);
         nx.nl_start = nl_total;
-        nx.nl_count = tot[1];
+        nx.nl_count = int64_t(hw[0] >> 32);
         if (total + nx.count > cap) {
             int64_t ncap = std::max<int64_t>(2 * cap, total + nx.count + 64);
             ensure_boxes(ncap, total);
             cap = ncap;
             front = P->nonleaf.as<int>() + cur.nl_start;
         }
-        hipLaunchKernelGGL(k_emit, dim3(nblocks(nf)), dim3(TB), 0, s, front, nf, l, keys, bounds, choff, nloff,
+        hipLaunchKernelGGL(k_emit, dim3(nblocks(nf)), dim3(TB), 0, s, front, nf, l, keys, bounds, off,
                            int(nx.start), int(nx.nl_start), P->bx_anchor.as<int4>(), P->bx_range.as<int2>(),
                            P->bx_parent.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(),
                            P->bx_mkey.as<uint64_t>(), P->nonleaf.as<int>(), P->leaf, o.adaptive, o.max_depth, Lu);
@@ -948,8 +1041,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                            P->bx_parent.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->coll.as<int>(),
                            vt_dev->as<VTable>(), P->vdense.as<int>());
     // coarse adjacent leaves, top-down
-    P->cal.ensure(size_t(B) * 26 * 4);
-    KIFMM_HIP(hipMemsetAsync(P->cal.p, 0xff, size_t(B) * 26 * 4, s));
+    P->cal.ensure(size_t(B) * 26 * 4);   // every row below the root is written by k_cal
     for (int l = 1; l <= P->depth; ++l)
         hipLaunchKernelGGL(k_cal, dim3(nblocks(P->lev[l].count)), dim3(TB), 0, s, int(P->lev[l].start),
                            int(P->lev[l].count), P->bx_anchor.as<int4>(), P->bx_parent.as<int>(),
@@ -1016,9 +1108,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     int* fx = fl + (B + 1);
     int* ol = fx + (B + 1);
     int* ox = ol + (B + 1);
-    hipLaunchKernelGGL(k_flags, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), xoff, b2, fl, fx);
-    KIFMM_HIP(hipMemsetAsync(fl + B, 0, 4, s));
-    KIFMM_HIP(hipMemsetAsync(fx + B, 0, 4, s));
+    hipLaunchKernelGGL(k_flags, dim3(nblocks(B + 1)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), xoff, b2, fl, fx);
     exclusive_scan<int>(P, fl, ol, B + 1, s);
     exclusive_scan<int>(P, fx, ox, B + 1, s);
     int nlx[2];
@@ -1035,9 +1125,8 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         P->tmp_a.ensure(size_t(nl + 1) * 8 + 64);
         int* icnt = P->tmp_a.as<int>();
         int* ioff = icnt + (nl + 1);
-        hipLaunchKernelGGL(k_item_count, dim3(nblocks(nl)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
+        hipLaunchKernelGGL(k_item_count, dim3(nblocks(nl + 1)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
                            P->bx_range.as<int2>(), icnt);
-        KIFMM_HIP(hipMemsetAsync(icnt + nl, 0, 4, s));
         exclusive_scan<int>(P, icnt, ioff, nl + 1, s);
         int ni = read_int(P, ioff + nl, s);
         P->n_items = ni;
