@@ -65,16 +65,17 @@ class Plan:
 
 
 def plan(x, kernel="laplace", p=6, leaf_size=128, adaptive=True, max_depth=21, root=None,
-         tau=TAU, periodic=False) -> Plan:
+         tau=TAU, periodic=False, m2l_rtol=0.0) -> Plan:
     """``periodic``: the explicit root cube ``root`` = (lo, side) is the unit
-    cell of a periodic system (Laplace only; every point inside the cell)."""
+    cell of a periodic system (Laplace only; every point inside the cell).
+    ``m2l_rtol`` > 0: M2L in the truncated common basis (``Operators``)."""
     x = np.asarray(x, dtype=np.float64)
     if periodic and (root is None or kernel != "laplace"):
         raise ValueError("periodic sums need the Laplace kernel and the cell as an explicit root")
     t = build_tree(x, leaf_size, adaptive, max_depth, root)
     L = build_lists(t, periodic)
     c = KERNELS[kernel]
-    return Plan(t, L, kernel, c, p, tau, Operators(p, c, t.s, tau), x[t.perm], periodic)
+    return Plan(t, L, kernel, c, p, tau, Operators(p, c, t.s, tau, m2l_rtol), x[t.perm], periodic)
 
 
 def _lowest(P: Plan) -> int:

@@ -96,10 +96,21 @@ def pinv_truncated(A: np.ndarray, tau: float = TAU):
 
 
 class Operators:
-    """Per-level FP64 operators for a root cube of side s (built lazily)."""
+    """Per-level FP64 operators for a root cube of side s (built lazily).
 
-    def __init__(self, p: int, c: float, s: float, tau: float = TAU):
+    ``m2l_rtol`` > 0 applies every M2L operator in a truncated common basis
+    (a reading; the paper does not say how its M2L is applied).  Because
+    M2L(-d) = M2L(d)^T, the left singular vectors of H = [M2L(d_1) ... M2L(d_316)]
+    also span the right ones of the stacked operators, so one basis Q (the left
+    singular vectors with sigma >= m2l_rtol * sigma_1) serves both sides:
+        M2L_c(d) = Q (Q^T M2L(d) Q) Q^T,
+    which keeps M2L_c(-d) = M2L_c(d)^T (the adjoint stays exact) and differs
+    from M2L(d) by at most 2 m2l_rtol sigma_1(H) in the spectral norm.
+    """
+
+    def __init__(self, p: int, c: float, s: float, tau: float = TAU, m2l_rtol: float = 0.0):
         self.p, self.c, self.s, self.tau = p, c, s, tau
+        self.m2l_rtol = float(m2l_rtol)
         self.n = n_surface(p)
         self._cache = {}
 
@@ -147,9 +158,33 @@ class Operators:
             self._cache[key] = kernel_matrix(trg, src, self.c)
         return self._cache[key]
 
-    def m2l(self, l, d):
+    def m2l_exact(self, l, d):
         """K(dc of a target box at level l, ue of the source box at offset d)."""
         w = self.w(l)
         trg = surface(self.p, RHO_DC, 0, w)
         src = surface(self.p, RHO_UE, np.asarray(d, dtype=np.float64) * w, w)
         return kernel_matrix(trg, src, self.c)
+
+    def m2l_basis(self, l):
+        """(Q, singular values of H) of the truncated common M2L basis at level l."""
+        key = ("m2l_basis", l)
+        if key not in self._cache:
+            H = np.hstack([self.m2l_exact(l, d) for d in far_offsets()])
+            U, S, _ = np.linalg.svd(H, full_matrices=False)
+            k = int(np.sum(S >= self.m2l_rtol * S[0]))
+            self._cache[key] = (U[:, :k], S)
+        return self._cache[key]
+
+    def m2l(self, l, d):
+        """The M2L operator as the sweep applies it (compressed when m2l_rtol > 0)."""
+        M = self.m2l_exact(l, d)
+        if self.m2l_rtol <= 0.0:
+            return M
+        Q, _ = self.m2l_basis(l)
+        return Q @ (Q.T @ M @ Q) @ Q.T
+
+
+def far_offsets():
+    """The 316 offsets of [-3,3]^3 outside [-1,1]^3, lexicographic (dx, dy, dz)."""
+    return [(dx, dy, dz) for dx in range(-3, 4) for dy in range(-3, 4) for dz in range(-3, 4)
+            if max(abs(dx), abs(dy), abs(dz)) > 1]

@@ -186,3 +186,48 @@ def test_field_gradient_accuracy_with_dipoles():
     u0, E0, G0 = kifmm.forward_dipoles(P, w.charges, None, grad=True)
     uf, Ef = kifmm.forward(P, w.charges)
     np.testing.assert_allclose(u0, uf, rtol=0, atol=1e-12 * np.abs(uf).max())
+
+
+def test_compressed_m2l_bound_and_symmetry():
+    # M2L in the truncated common basis Q: within 2 tau sigma_1(H) of the exact
+    # operator in the spectral norm (one-sided truncation error on each side),
+    # and M2L_c(-d) = M2L_c(d)^T, which the adjoint needs
+    from oracle import operators as O
+    tau = 1e-6
+    ops = O.Operators(6, 1.0, 1.0, m2l_rtol=tau)
+    Q, S = ops.m2l_basis(2)
+    assert Q.shape == (152, int(np.sum(S >= tau * S[0])))
+    np.testing.assert_allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=1e-12)
+    for d in [(2, 0, 0), (-3, 1, 2), (3, 3, 3), (0, -2, 1)]:
+        M, Mc = ops.m2l_exact(2, d), ops.m2l(2, d)
+        assert np.linalg.norm(M - Mc, 2) <= 2 * tau * S[0] * (1 + 1e-9)
+        Mm = ops.m2l(2, tuple(-v for v in d))
+        np.testing.assert_allclose(Mm, Mc.T, rtol=0, atol=1e-12 * np.abs(Mc).max())
+    exact = O.Operators(6, 1.0, 1.0)
+    np.testing.assert_array_equal(exact.m2l(2, (2, 1, 0)), exact.m2l_exact(2, (2, 1, 0)))
+
+
+def test_compressed_m2l_forward_and_adjoint():
+    # the compressed sweep stays within about 1e-6 of the exact one on the
+    # clustered shape, and its adjoint is still exact (unit steps in q)
+    w = workloads.make(2, n=6000)
+    P0 = kifmm.plan(w.positions, "laplace", 6, 48, True, 21, w.root)
+    P1 = kifmm.plan(w.positions, "laplace", 6, 48, True, 21, w.root, m2l_rtol=1e-6)
+    u0, E0 = kifmm.forward(P0, w.charges)
+    u1, E1 = kifmm.forward(P1, w.charges)
+    assert np.linalg.norm(u1 - u0) / np.linalg.norm(u0) < 2e-6
+    assert np.linalg.norm(E1 - E0) / np.linalg.norm(E0) < 2e-6
+    rng = np.random.default_rng(45)
+    ub = rng.standard_normal(w.n)
+    Eb = rng.standard_normal((w.n, 3))
+    qb, _ = kifmm.vjp(P1, w.charges, ub, Eb)
+
+    def loss(q):
+        u, E = kifmm.forward(P1, q)
+        return float(ub @ u + np.sum(Eb * E))
+
+    for k in (3, 2999):
+        dq = np.zeros(w.n)
+        dq[k] = 1.0
+        fd = (loss(w.charges + dq) - loss(w.charges - dq)) / 2.0
+        assert abs(fd - qb[k]) <= 1e-8 * max(1.0, abs(qb[k]))
