@@ -54,10 +54,10 @@ WORKLOADS = {
 CPU_SAMPLE = {1: 4096, 2: 131072, 3: 131072, 4: 131072, 5: 65536, 6: 8752}
 
 
-def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0):
+def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rtol=0.0):
     import torch
     plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root,
-                profile=True, periodic=w.periodic)
+                profile=True, periodic=w.periodic, m2l_rtol=m2l_rtol)
     lo, hi = None, None
     if move > 0:
         # particles drift between long-range calls (the DEM loop): each step
@@ -164,8 +164,9 @@ def roofline(res, n, precision, workload, npts):
                 work=f"20 x {c['p2p_pairs']} pairs")
 
 
-def cpu_baseline(k):
-    """FP64 oracle forward + adjoint on a bounded sample of the same workload."""
+def cpu_baseline(k, m2l_rtol):
+    """FP64 oracle forward + adjoint on a bounded sample of the same workload
+    (with the same M2L basis cut-off as the timed GPU path)."""
     import workloads
     from oracle import kifmm
     w = workloads.make(k, n=CPU_SAMPLE[k])
@@ -175,7 +176,7 @@ def cpu_baseline(k):
     Eb = rng.standard_normal((n, 3))
     t0 = time.perf_counter()
     P = kifmm.plan(w.positions, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, w.root,
-                   periodic=w.periodic)
+                   periodic=w.periodic, m2l_rtol=m2l_rtol)
     kifmm.forward(P, w.charges)
     kifmm.vjp(P, w.charges, ub, Eb)
     t = time.perf_counter() - t0
@@ -188,6 +189,10 @@ def cpu_baseline(k):
 
 # the workload --counter-run evaluates (its name and size, as recorded with the counters)
 COUNTER_WORKLOAD = ("clustered_1M_p6", 1_048_576)
+# M2L basis cut-off of the timed configuration (singular values below 1e-6
+# sigma_1 of the stacked offset operators dropped; the full-size parity tests
+# use the same)
+M2L_RTOL = 1e-6
 
 
 def counter_run(precision):
@@ -200,7 +205,8 @@ def counter_run(precision):
     w = workloads.make(2)
     pos = torch.tensor(w.positions, dtype=torch.float64, device="cuda")
     q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
-    plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root)
+    plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root,
+                m2l_rtol=M2L_RTOL)
     for _ in range(2):
         plan.evaluate(q)
     torch.cuda.synchronize()
@@ -376,6 +382,8 @@ def main():
     ap.add_argument("--move", type=float, default=0.0,
                     help="per-step random displacement (std per axis) of every particle before the re-tree")
     ap.add_argument("--paths", default="split_bf16,fp32")
+    ap.add_argument("--m2l-rtol", type=float, default=M2L_RTOL,
+                    help="M2L in the truncated common basis of the offset operators (0: exact operators)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counter-run", metavar="PRECISION", help="short run for rocprofv3 counter passes")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT", "CMD"))
@@ -411,7 +419,7 @@ def main():
     paths = {}
     for prec in args.paths.split(","):
         log(f"[bench] {prec}: N={n} steps={args.steps} warmup={args.warmup}")
-        paths[prec] = run_path(Plan, w, pos, q, gu, gE, prec, args.steps, args.warmup, args.move)
+        paths[prec] = run_path(Plan, w, pos, q, gu, gE, prec, args.steps, args.warmup, args.move, args.m2l_rtol)
         r = paths[prec]
         log(f"[bench] {prec}: {r['ms_per_step']:.3f} ms/step  tree {r['t_tree_ms']:.2f} fwd {r['t_fwd_ms']:.2f} "
             f"adj {r['t_adj_ms']:.2f}  phases {json.dumps({k: round(v, 3) for k, v in r['phases_fwd_ms'].items()})}"
@@ -442,7 +450,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload] + "; step = re-tree + forward + adjoint"
                                + (f"; particles move by N(0, {args.move}^2) per axis each step" if args.move else ""),
-                   "name": w.name, "n": n, "p": w.p, "leaf_size": w.leaf_size, "path": head},
+                   "name": w.name, "n": n, "p": w.p, "leaf_size": w.leaf_size, "path": head,
+                   "m2l_rtol": args.m2l_rtol},
         "roofline": roofline(H, ops_n, head, wkey, n),
         "paths": {k: {"particles_per_s": n / (v["ms_per_step"] * 1e-3), "ms_per_step": v["ms_per_step"],
                       "particles_per_s_without_tree": n / ((v["t_fwd_ms"] + v["t_adj_ms"]) * 1e-3),
@@ -457,7 +466,7 @@ def main():
     }
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.workload)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.m2l_rtol)
     for v in paths.values():
         v.pop("outputs", None)
     print(json.dumps(out), flush=True)

@@ -99,6 +99,15 @@ typedef struct {
                               non-harmonic part of the periodic kernel from the
                               sources' moments in closed form.  0 (default): free
                               space. */
+    double m2l_rtol;       /* > 0: apply M2L in the truncated common basis of the 316
+                              offset operators (left singular vectors of
+                              [M2L(d_1) ... M2L(d_316)] with sigma >= m2l_rtol
+                              sigma_1; the same basis on the source side since
+                              M2L(-d) = M2L(d)^T, so kifmm_backward stays the exact
+                              adjoint).  Used when its padded rank is a smaller M2L
+                              tile than the surface (p = 6, 1e-6: 116 of 152 -> 128;
+                              p = 8: 124 of 296 -> 128).  0 (default): the exact
+                              operators. */
 } kifmm_options;
 
 /* Fill *opts with the defaults listed above. */

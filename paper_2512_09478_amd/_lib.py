@@ -27,7 +27,7 @@ class Options(ctypes.Structure):
     _fields_ = [("adaptive", ctypes.c_int), ("max_depth", ctypes.c_int), ("precision", ctypes.c_int),
                 ("pinv_rtol", ctypes.c_double), ("explicit_root", ctypes.c_int),
                 ("root_lo", ctypes.c_double * 3), ("root_side", ctypes.c_double), ("profile", ctypes.c_int),
-                ("periodic", ctypes.c_int)]
+                ("periodic", ctypes.c_int), ("m2l_rtol", ctypes.c_double)]
 
 
 _lock = threading.Lock()

@@ -39,6 +39,7 @@ void check_options(const kifmm_options& o) {
     if (o.precision != KIFMM_FP32 && o.precision != KIFMM_SPLIT_BF16) throw Error(KIFMM_ERR_ARG, "unknown precision");
     if (!(o.pinv_rtol > 0.0 && o.pinv_rtol < 1.0)) throw Error(KIFMM_ERR_ARG, "pinv_rtol must be in (0, 1)");
     if (o.periodic && !o.explicit_root) throw Error(KIFMM_ERR_ARG, "a periodic plan needs the cell as an explicit root");
+    if (!(o.m2l_rtol >= 0.0 && o.m2l_rtol < 1.0)) throw Error(KIFMM_ERR_ARG, "m2l_rtol must be in [0, 1)");
     if (o.explicit_root) {
         int e = 0;
         double m = frexp(o.root_side, &e);
@@ -60,6 +61,7 @@ void alloc_densities(kifmm_plan* P, hipStream_t s) {
     // small trees get more M2L partial buffers (see launch_m2l)
     P->m2l_split_cap = bytes <= (size_t(64) << 20) ? kM2LSplitMax : kM2LSplit;
     P->psi_m.ensure(size_t(P->m2l_split_cap) * bytes);
+    if (P->cm) P->phi_k.ensure(size_t(2) * size_t(P->B) * P->cm->kp * 4);
     P->nearv.ensure(size_t(P->N) * 16);
     if (P->periodic) {
         P->mom.ensure(2 * 16 * sizeof(double));
@@ -159,6 +161,10 @@ int kifmm_setup_ex(const double* positions, int64_t N, int kernel, int p, int le
         P->N = N;
         P->periodic = o.periodic != 0;
         P->ops = &get_operators(p, o.pinv_rtol);
+        if (o.m2l_rtol > 0.0) {
+            const M2LBasis& cm = get_m2l_basis(p, o.pinv_rtol, o.m2l_rtol);
+            if (cm.kp > 0) P->cm = &cm;
+        }
         if (P->periodic) (void)get_lattice_operator(p, o.pinv_rtol);
         P->n = P->ops->n;
         P->npad = P->ops->npad;

@@ -139,6 +139,21 @@ struct Operators {
     std::vector<double> svd_u, svd_v;   // its singular vectors (n x n row-major, FP64)
 };
 
+// M2L in a truncated common basis Q (n x k, the left singular vectors of
+// [M2L(d_1) ... M2L(d_316)] with sigma >= rtol * sigma_1; since M2L(-d) =
+// M2L(d)^T the same basis serves the source side): the sweep projects the
+// upward densities, phi_k = Q^T phi_u, applies the k x k cores Q^T M2L(d) Q
+// and expands the result, psi += Q psi_k.  kp is the padded rank, one of the
+// tile sizes the M2L kernel is built for; kp = 0 means the basis does not pay.
+struct M2LBasis {
+    int k = 0, kp = 0;
+    DBuf proj;        // float [NP][kp]: Q, padded (phi_k[r] = sum_c proj[c][r] phi_u[c])
+    DBuf expd;        // float [kp][NP]: Q^T, padded (psi[r] += sum_j expd[j][r] psi_k[j])
+    DBuf core_f32;    // [316] cores in gather-fragment order at kp (FP32)
+    DBuf core_bf16;   // the same, bf16 hi/lo
+};
+const M2LBasis& get_m2l_basis(int p, double tau, double rtol);
+
 // Periodic root operator (unit cell, FP64 [n][n] row-major on the device):
 // the root downward equivalent density from the root upward density for
 // every image at cube distance two or more, DC2E F(dc - ue).
@@ -210,6 +225,7 @@ struct kifmm_plan {
     int64_t counts[10] = {};
     hipStream_t last_stream = nullptr;
     const kifmm::Operators* ops = nullptr;
+    const kifmm::M2LBasis* cm = nullptr;   // compressed M2L in use (null: the exact operators)
     kifmm::HostWords host;   // pinned words for small read-backs
 
     // points
@@ -238,6 +254,7 @@ struct kifmm_plan {
     int64_t n_xboxes = 0;
     // densities: [rhs][B][npad]
     kifmm::DBuf psi_u, phi_u, psi_d, phi_d;
+    kifmm::DBuf phi_k;      // compressed M2L: projected upward densities [rhs][B][kp]
     kifmm::DBuf psi_m;      // M2L partial check potentials [split][rhs][B][npad]
     int m2l_split_used = kifmm::kM2LSplit;
     int m2l_split_cap = kifmm::kM2LSplit;   // partial buffers allocated

@@ -431,8 +431,9 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
         load_acc<NP>(acc[cb],
-                     (split == 0 && tgt[cb] >= 0) ? psi_d + size_t(cb % nrhs) * rhs_stride + size_t(tgt[cb]) * NP
-                                                  : nullptr,
+                     (split == 0 && tgt[cb] >= 0 && psi_d)
+                         ? psi_d + size_t(cb % nrhs) * rhs_stride + size_t(tgt[cb]) * NP
+                         : nullptr,
                      lane);
     if (j < kVPerOct) {
         const int g8 = 8 * (lane >> 4);
@@ -1111,6 +1112,71 @@ __global__ __launch_bounds__(256) void k_far_grad(const int2* __restrict__ items
 #undef KIFMM_FARG_ITEM
 }
 
+// Compressed M2L, projection of the upward densities: phi_k = Q^T phi_u for
+// the boxes [b0, b0 + nb).  A block takes 16 boxes staged in LDS; thread t
+// computes row t % KP of 256 / KP of those boxes' outputs, reading column c of
+// Q^T (a contiguous row of `proj`) once for all of its boxes.
+template <int NP, int KP>
+__global__ __launch_bounds__(256) void k_project(int b0, int nb, const float* __restrict__ proj,
+                                                 const float* __restrict__ phi_u, float* __restrict__ phi_k) {
+    constexpr int G = 16, TPR = 256 / KP, BPT = G / TPR;   // threads per row, boxes per thread
+    static_assert(TPR >= 1 && G % TPR == 0, "tile");
+    __shared__ float in[G][NP];
+    const int first = b0 + blockIdx.x * G;
+    for (int t = threadIdx.x; t < G * NP; t += 256) {
+        const int g = t / NP, c = t % NP;
+        in[g][c] = first + g < b0 + nb ? phi_u[size_t(first + g) * NP + c] : 0.f;
+    }
+    __syncthreads();
+    if (threadIdx.x >= TPR * KP) return;   // (no barrier follows)
+    const int r = threadIdx.x % KP, h = threadIdx.x / KP;
+    float acc[BPT];
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) acc[q] = 0.f;
+    for (int c = 0; c < NP; ++c) {
+        const float a = proj[size_t(c) * KP + r];
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) acc[q] += a * in[h * BPT + q][c];
+    }
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+        const int b = first + h * BPT + q;
+        if (b < b0 + nb) phi_k[size_t(b) * KP + r] = acc[q];
+    }
+}
+
+// Compressed M2L, expansion: psi_d += Q (sum of the nsplit partial psi_k) for
+// the boxes [b0, b0 + nb); psi_d already holds the X-list part.
+template <int NP, int KP>
+__global__ __launch_bounds__(256) void k_expand(int b0, int nb, const float* __restrict__ expd,
+                                                const float* __restrict__ psi_k, int nsplit, size_t split_stride,
+                                                float* __restrict__ psi_d) {
+    constexpr int G = 16;
+    __shared__ float in[G][KP];
+    const int first = b0 + blockIdx.x * G;
+    for (int t = threadIdx.x; t < G * KP; t += 256) {
+        const int g = t / KP, j = t % KP;
+        float v = 0.f;
+        if (first + g < b0 + nb)
+            for (int sp = 0; sp < nsplit; ++sp) v += psi_k[sp * split_stride + size_t(first + g) * KP + j];
+        in[g][j] = v;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < NP; r += 256) {
+        float acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = 0.f;
+        for (int j = 0; j < KP; ++j) {
+            const float a = expd[size_t(j) * NP + r];
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] += a * in[g][j];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (first + g < b0 + nb) psi_d[size_t(first + g) * NP + r] += acc[g];
+    }
+}
+
 __global__ void k_fill0(float* __restrict__ p, size_t n) {
     size_t i = blockIdx.x * size_t(256) + threadIdx.x;
     if (i < n) p[i] = 0.f;
@@ -1168,9 +1234,12 @@ int first_down_level(const kifmm_plan* P) { return P->periodic ? 0 : 2; }
 // M2L for all levels; nrhs = 2 treats densities rhs 0 and 1 together (the
 // two columns share the target, the source and the operator), otherwise the
 // densities of right-hand side `rhs`.
+// M2L at tile size NP (the surface size, or the padded rank of the compressed
+// basis): sources src [rhs][B][NP], optional start values init (the X-list
+// check potentials; null for zero), partials out [split][rhs][B][NP].
 template <int NP>
-void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
-    const Operators& op = *P->ops;
+void launch_m2l_tile(kifmm_plan* P, int nrhs, int rhs, hipStream_t s, const float* src, const float* init,
+                     float* out, const uint4* ops_f32, const uint4* ops_bf16) {
     const int depth = P->depth;
     const int lv = first_v_level(P);
     if (depth < lv) return;
@@ -1199,18 +1268,72 @@ void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
     P->m2l_split_used = nsplit;
     const size_t stride = size_t(P->B) * NP;
     const size_t sstride = 2 * stride;
-    const float* phi_u = P->phi_u.as<float>() + size_t(rhs) * stride;
-    const float* psi_d = P->psi_d.as<float>() + size_t(rhs) * stride;
-    float* psi_m = P->psi_m.as<float>() + size_t(rhs) * stride;
+    const float* phi_u = src + size_t(rhs) * stride;
+    const float* psi_d = init ? init + size_t(rhs) * stride : nullptr;
+    float* psi_m = out + size_t(rhs) * stride;
     const int total = blocks * nsplit;
 #define KIFMM_M2L_LAUNCH(SPL, CBV, OPS)                                                                          \
     hipLaunchKernelGGL((k_m2l<NP, SPL, CBV>), dim3(total), dim3(WAVES * 64), 0, s, tt, total, blocks, nsplit,  \
                        nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2, vops_device(), \
                        phi_u, psi_d, psi_m, stride, sstride, OPS)
     const bool split = P->opt.precision == KIFMM_SPLIT_BF16;
-    if (split) KIFMM_M2L_LAUNCH(true, M2L_CB, op.m2l_bf16.as<uint4>());
-    else KIFMM_M2L_LAUNCH(false, M2L_CB, op.m2l_f32.as<uint4>());
+    if (split) KIFMM_M2L_LAUNCH(true, M2L_CB, ops_bf16);
+    else KIFMM_M2L_LAUNCH(false, M2L_CB, ops_f32);
 #undef KIFMM_M2L_LAUNCH
+}
+
+template <int NP>
+void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
+    if (!P->cm) {
+        const Operators& op = *P->ops;
+        launch_m2l_tile<NP>(P, nrhs, rhs, s, P->phi_u.as<float>(), P->psi_d.as<float>(), P->psi_m.as<float>(),
+                            op.m2l_f32.as<uint4>(), op.m2l_bf16.as<uint4>());
+        return;
+    }
+    const M2LBasis& cm = *P->cm;
+#define KIFMM_M2L_TILE(KP)                                                                                     \
+    launch_m2l_tile<KP>(P, nrhs, rhs, s, P->phi_k.as<float>(), nullptr, P->psi_m.as<float>(),               \
+                        cm.core_f32.as<uint4>(), cm.core_bf16.as<uint4>())
+    switch (cm.kp) {
+        case 32: KIFMM_M2L_TILE(32); break;
+        case 64: KIFMM_M2L_TILE(64); break;
+        case 128: KIFMM_M2L_TILE(128); break;
+        case 160: KIFMM_M2L_TILE(160); break;
+        case 224: KIFMM_M2L_TILE(224); break;
+        default: throw Error(KIFMM_ERR_STATE, "unsupported compressed M2L size");
+    }
+#undef KIFMM_M2L_TILE
+}
+
+// Compressed M2L: project (phi_k = Q^T phi_u) or expand (psi_d += Q psi_k)
+// the boxes from the first V level on, for right-hand side r.
+template <int NP, int KP>
+void project_expand_kp(kifmm_plan* P, bool project, int r, hipStream_t s) {
+    const int lv = first_v_level(P);
+    if (P->depth < lv) return;
+    const int b0 = int(P->lev[lv].start), nb = int(P->B) - b0;
+    if (nb <= 0) return;
+    const M2LBasis& cm = *P->cm;
+    const size_t sn = size_t(P->B) * NP, sk = size_t(P->B) * KP;
+    if (project)
+        hipLaunchKernelGGL((k_project<NP, KP>), dim3(unsigned(nblk(nb, 16))), dim3(256), 0, s, b0, nb,
+                           cm.proj.as<float>(), P->phi_u.as<float>() + r * sn, P->phi_k.as<float>() + r * sk);
+    else
+        hipLaunchKernelGGL((k_expand<NP, KP>), dim3(unsigned(nblk(nb, 16))), dim3(256), 0, s, b0, nb,
+                           cm.expd.as<float>(), P->psi_m.as<float>() + r * sk, P->m2l_split_used, 2 * sk,
+                           P->psi_d.as<float>() + r * sn);
+}
+
+template <int NP>
+void project_expand(kifmm_plan* P, bool project, int r, hipStream_t s) {
+    // the basis is only used when its tile is smaller than the surface's
+    const int kp = P->cm->kp;
+    if constexpr (NP > 32) if (kp == 32) return project_expand_kp<NP, 32>(P, project, r, s);
+    if constexpr (NP > 64) if (kp == 64) return project_expand_kp<NP, 64>(P, project, r, s);
+    if constexpr (NP > 128) if (kp == 128) return project_expand_kp<NP, 128>(P, project, r, s);
+    if constexpr (NP > 160) if (kp == 160) return project_expand_kp<NP, 160>(P, project, r, s);
+    if constexpr (NP > 224) if (kp == 224) return project_expand_kp<NP, 224>(P, project, r, s);
+    throw Error(KIFMM_ERR_STATE, "unsupported compressed M2L size");
 }
 
 // One sweep over the tree for the right-hand sides r0 .. r1-1: 0 = the
@@ -1270,6 +1393,9 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
             hipLaunchKernelGGL(k_lattice, dim3(1), dim3(NP), 0, s, R.as<double>(), op.n, NP,
                                P->phi_u.as<float>() + r * stride, P->phi_d.as<float>() + r * stride);
     }
+    // compressed M2L: its sources in the common basis
+    if (P->cm)
+        for (int r = r0; r < r1; ++r) project_expand<NP>(P, true, r, s);
     if (rec) record_phase(P, 1, s);
     // downward check potentials: zero, X list
     for (int r = r0; r < r1; ++r) {
@@ -1289,6 +1415,9 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
     } else {
         for (int r = r0; r < r1; ++r) launch_m2l<NP>(P, 1, r, s);
     }
+    // compressed M2L: its results back on the check surfaces, added to the X list
+    if (P->cm)
+        for (int r = r0; r < r1; ++r) project_expand<NP>(P, false, r, s);
     if (rec) record_phase(P, 3, s);
     // L2L + DC2E, coarse to fine
     for (int r = r0; r < r1; ++r)
@@ -1298,8 +1427,11 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
             if (blocks == 0) continue;
             hipLaunchKernelGGL((k_updown<NP, false>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, 0, 0,
                                int(pl.nl_start), int(pl.nl_count), l > ld ? 1 : 0, P->nonleaf.as<int>(),
-                               P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->psi_m.as<float>() + r * stride,
-                               P->m2l_split_used, 2 * stride, P->phi_d.as<float>() + r * stride,
+                               P->bx_child.as<int2>(), P->bx_leaf.as<int>(),
+                               // the check potentials: M2L partials (with the X list in the first), or,
+                               // compressed, the expanded sum already in psi_d
+                               P->cm ? P->psi_d.as<float>() + r * stride : P->psi_m.as<float>() + r * stride,
+                               P->cm ? 1 : P->m2l_split_used, 2 * stride, P->phi_d.as<float>() + r * stride,
                                P->phi_d.as<float>() + r * stride, op.l2l.as<uint4>(), op.dc2e_w1.as<uint4>(),
                                op.dc2e_v.as<uint4>());
         }

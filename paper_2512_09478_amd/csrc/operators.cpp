@@ -349,6 +349,111 @@ std::vector<double> lattice_kernel(const std::vector<double>& xs, const std::vec
 
 }  // namespace
 
+namespace {
+
+// Tile sizes the M2L kernel is instantiated for.
+int m2l_tile(int k) {
+    for (int t : {32, 64, 128, 160, 224, 320})
+        if (t >= k) return t;
+    return 0;
+}
+
+std::unique_ptr<M2LBasis> build_m2l_basis(int p, double rtol) {
+    auto b = std::make_unique<M2LBasis>();
+    const int n = 6 * (p - 1) * (p - 1) + 2;
+    const int np = (n + 31) / 32 * 32;
+    std::vector<double> sin = unit_surface(p, 1.05);
+    // the 316 unit M2L operators (dc <- ue at offset d) and G = sum_d M M^T,
+    // whose eigenvectors are the left singular vectors of [M(d_1) ... M(d_316)]
+    std::vector<std::vector<double>> M;
+    std::vector<double> G(size_t(n) * n, 0.0);
+    for (int dx = -3; dx <= 3; ++dx)
+        for (int dy = -3; dy <= 3; ++dy)
+            for (int dz = -3; dz <= 3; ++dz) {
+                if (std::max(abs(dx), std::max(abs(dy), abs(dz))) <= 1) continue;
+                std::vector<double> A(size_t(n) * n);
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        double src[3] = {dx + sin[3 * j], dy + sin[3 * j + 1], dz + sin[3 * j + 2]};
+                        A[size_t(i) * n + j] = inv_dist(&sin[3 * i], src);
+                    }
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j <= i; ++j) {
+                        double acc = 0.0;
+                        for (int c = 0; c < n; ++c) acc += A[size_t(i) * n + c] * A[size_t(j) * n + c];
+                        G[size_t(i) * n + j] += acc;
+                    }
+                M.push_back(std::move(A));
+            }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) G[size_t(i) * n + j] = G[size_t(j) * n + i];
+    std::vector<double> U(size_t(n) * n), S(n), V(size_t(n) * n);
+    jacobi_svd(n, G.data(), U.data(), S.data(), V.data());
+    // sigma_i(H) = sqrt(S_i): keep sigma_i >= rtol sigma_1
+    int k = 0;
+    while (k < n && S[k] >= rtol * rtol * S[0]) ++k;
+    b->k = k;
+    const int kp = m2l_tile(k);
+    if (kp == 0 || kp >= np) return b;   // no smaller tile: the exact operators are used
+    b->kp = kp;
+    std::vector<float> proj(size_t(np) * kp, 0.f), expd(size_t(kp) * np, 0.f);
+    for (int c = 0; c < n; ++c)
+        for (int r = 0; r < k; ++r) {
+            proj[size_t(c) * kp + r] = float(U[size_t(c) * n + r]);
+            expd[size_t(r) * np + c] = float(U[size_t(c) * n + r]);
+        }
+    upload(b->proj, proj.data(), proj.size() * 4);
+    upload(b->expd, expd.data(), expd.size() * 4);
+    // cores Q^T M(d) Q in the M2L kernel's gather-fragment order at kp
+    const size_t per = size_t(kp) * kp;
+    std::vector<float> core(size_t(kNumV) * per, 0.f);
+    std::vector<uint16_t> hi(size_t(kNumV) * per, 0), lo(size_t(kNumV) * per, 0);
+    std::vector<double> T(size_t(n) * k);
+    for (int m = 0; m < kNumV; ++m) {
+        const std::vector<double>& A = M[m];
+        for (int i = 0; i < n; ++i)   // T = M Q
+            for (int r = 0; r < k; ++r) {
+                double acc = 0.0;
+                for (int c = 0; c < n; ++c) acc += A[size_t(i) * n + c] * U[size_t(c) * n + r];
+                T[size_t(i) * k + r] = acc;
+            }
+        for (int a = 0; a < k; ++a)   // Q^T T
+            for (int r = 0; r < k; ++r) {
+                double acc = 0.0;
+                for (int i = 0; i < n; ++i) acc += U[size_t(i) * n + a] * T[size_t(i) * k + r];
+                const size_t at = size_t(m) * per + size_t(a) * kp + r;
+                core[at] = float(acc);
+                const uint16_t h = bf16_rne(float(acc));
+                hi[at] = h;
+                lo[at] = bf16_rne(float(acc - double(bf16_to_float(h))));
+            }
+    }
+    std::vector<uint32_t> f32(size_t(kNumV) * per);
+    std::vector<uint16_t> f16(size_t(kNumV) * per * 2);
+    for (int m = 0; m < kNumV; ++m) {
+        frag_f32(&core[m * per], kp, &f32[m * per]);
+        frag_bf16(&hi[m * per], &lo[m * per], kp, &f16[m * per * 2]);
+    }
+    upload(b->core_f32, f32.data(), f32.size() * 4);
+    upload(b->core_bf16, f16.data(), f16.size() * 2);
+    return b;
+}
+
+}  // namespace
+
+const M2LBasis& get_m2l_basis(int p, double tau, double rtol) {
+    static std::mutex mu;
+    static auto* cache = new std::map<std::tuple<int, int, double>, std::unique_ptr<M2LBasis>>();
+    (void)tau;   // the basis depends on the M2L operators only
+    int dev = 0;
+    KIFMM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_tuple(dev, p, rtol);
+    auto it = cache->find(key);
+    if (it == cache->end()) it = cache->emplace(key, build_m2l_basis(p, rtol)).first;
+    return *it->second;
+}
+
 const DBuf& get_lattice_operator(int p, double tau) {
     static std::mutex mu;
     static auto* cache = new std::map<std::tuple<int, int, double>, std::unique_ptr<DBuf>>();

@@ -43,7 +43,7 @@ class Plan:
     def __init__(self, positions: torch.Tensor, kernel: str = "laplace", p: int = 6, leaf_size: int = 128,
                  adaptive: bool = True, max_depth: int = 21, precision: str = "fp32",
                  pinv_rtol: float = 1e-7, root=None, profile: bool = False, stream=None,
-                 periodic: bool = False):
+                 periodic: bool = False, m2l_rtol: float = 0.0):
         L = _lib.lib()
         self.n = int(positions.shape[0])
         self.positions = _need(positions, torch.float64, (self.n, 3), "positions")
@@ -58,6 +58,7 @@ class Plan:
         opt.pinv_rtol = float(pinv_rtol)
         opt.profile = int(bool(profile))
         opt.periodic = int(bool(periodic))
+        opt.m2l_rtol = float(m2l_rtol)
         self.periodic = bool(periodic)
         if root is not None:
             opt.explicit_root = 1

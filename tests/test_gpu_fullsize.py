@@ -20,6 +20,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 NSAMPLE = 256
+# the benchmark's configuration: M2L in the truncated common basis (cut-off 1e-6)
+M2L_RTOL = 1e-6
 
 
 def rel(a, b):
@@ -35,13 +37,13 @@ def gpu_plan(w, precision):
     from paper_2512_09478_amd import Plan
     pos = torch.tensor(w.positions, dtype=torch.float64, device="cuda")
     return Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root,
-                periodic=w.periodic)
+                periodic=w.periodic, m2l_rtol=M2L_RTOL)
 
 
 def oracle_plan(w):
     t = time.time()
     P = kifmm.plan(w.positions, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, w.root,
-                   periodic=w.periodic)
+                   periodic=w.periodic, m2l_rtol=M2L_RTOL)
     say(f"  oracle tree + lists: {P.tree.nboxes} boxes, {time.time() - t:.1f} s")
     return P
 

@@ -42,8 +42,9 @@ def gpu_plan(w, leaf=None, precision="fp32", p=None, **kw):
                 root=w.root, **kw)
 
 
-def oracle_plan(w, leaf=None, p=None):
-    return kifmm.plan(w.positions, w.kernel, p or w.p, leaf or w.leaf_size, w.adaptive, w.max_depth, w.root)
+def oracle_plan(w, leaf=None, p=None, m2l_rtol=0.0):
+    return kifmm.plan(w.positions, w.kernel, p or w.p, leaf or w.leaf_size, w.adaptive, w.max_depth, w.root,
+                      m2l_rtol=m2l_rtol)
 
 
 # (k, n, leaf, p): shapes of the five workloads at sizes the oracle runs in seconds;
@@ -105,6 +106,41 @@ def test_forward_parity(built, k, n, leaf, p, precision):
     eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
     say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
     assert eu <= tol(k, precision) and eE <= tol(k, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("k,n,leaf,p", [(2, 12000, 48, 6), (4, 9000, 32, 6), (5, 12000, 64, 8)])
+def test_compressed_m2l_forward_parity(built, k, n, leaf, p, precision):
+    # M2L in the truncated common basis (rank 116 of 152 at p = 6, 124 of 296
+    # at p = 8, both run as 128-wide tiles) against the oracle's compressed sweep
+    say(f"compressed M2L forward workload {k} n={n} p={p} {precision}")
+    w = workloads.make(k, n=n)
+    G = gpu_plan(w, leaf, precision, p=p, m2l_rtol=1e-6)
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    u, E = G.evaluate(q)
+    O = oracle_plan(w, leaf, p, m2l_rtol=1e-6)
+    uo, Eo = kifmm.forward(O, w.charges)
+    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
+    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
+    assert eu <= tol(k, precision) and eE <= tol(k, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_compressed_m2l_backward_parity(built, precision):
+    say(f"compressed M2L backward {precision}")
+    w = workloads.make(4, n=6000)
+    G = gpu_plan(w, 32, precision, p=6, m2l_rtol=1e-6)
+    rng = np.random.default_rng(12)
+    ub = workloads.round_f32(rng.standard_normal(w.n))
+    Eb = workloads.round_f32(rng.standard_normal((w.n, 3)))
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    gq, gx = G.backward(q, torch.tensor(ub, dtype=torch.float32, device="cuda"),
+                        torch.tensor(Eb, dtype=torch.float32, device="cuda"))
+    O = oracle_plan(w, 32, 6, m2l_rtol=1e-6)
+    qo, xo = kifmm.vjp(O, w.charges, ub, Eb)
+    eq, ex = rel(gq.cpu().numpy(), qo), rel(gx.cpu().numpy(), xo)
+    say(f"  rel-L2 qbar {eq:.3e}  xbar {ex:.3e}")
+    assert eq <= TOL[precision] and ex <= TOL[precision]
 
 
 def test_single_leaf_is_direct_sum(built):

@@ -100,6 +100,21 @@ def test_periodic_forward_parity(built, name, precision):
     assert eu <= TOL[precision] and eE <= TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_periodic_compressed_m2l_parity(built, precision):
+    say(f"periodic compressed M2L {precision}")
+    from paper_2512_09478_amd import Plan
+    x, q, leaf = CASES["platelets"]
+    G = Plan(torch.tensor(x, dtype=torch.float64, device="cuda"), "laplace", 6, leaf, True, 21,
+             precision=precision, root=CELL, periodic=True, m2l_rtol=1e-6)
+    O = kifmm.plan(x, "laplace", 6, leaf, True, 21, CELL, periodic=True, m2l_rtol=1e-6)
+    u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
+    uo, Eo = kifmm.forward(O, q)
+    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
+    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
+    assert eu <= TOL[precision] and eE <= TOL[precision]
+
+
 def test_periodic_matches_ewald_sum(built):
     # the same run against the definition itself, at the method's accuracy
     say("periodic vs Ewald")
