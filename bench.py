@@ -68,6 +68,7 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rt
         gen = torch.Generator(device="cuda")
         gen.manual_seed(2512)
     counts = plan.counts()
+    counts["m2l_rank"], counts["m2l_tile"] = plan.m2l_rank()
     phases, phases_adj = [], []
     clumps = None
     if w.clump_offsets is not None:
@@ -150,12 +151,15 @@ def roofline(res, n, precision, workload, npts):
     cand = {"m2l": ph["m2l"], "p2p": ph["p2p"]}
     dom = max(cand, key=cand.get)
     if dom == "m2l":
-        flops = 2.0 * n * n * c["v_pairs"]
+        # the M2L as computed: 2 k^2 per V pair, k the rank of the operators
+        # in use (the surface size n for the exact operators)
+        k = c.get("m2l_rank", n)
+        flops = 2.0 * k * k * c["v_pairs"]
         peak = PEAK["bf16"] if precision == "split_bf16" else PEAK["fp32"]
         ach = flops / (ph["m2l"] * 1e-3) / 1e12
         return dict(kernel="k_m2l", bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
                     traffic=stored_traffic("k_m2l", precision, workload, npts), per_launch_ms=ph["m2l"],
-                    work=f"2 n^2 x {c['v_pairs']} V pairs")
+                    work=f"2 k^2 x {c['v_pairs']} V pairs, k = {k} (surface size {n})")
     flops = P2P_FLOP_PER_PAIR * c["p2p_pairs"]
     ach = flops / (ph["p2p"] * 1e-3) / 1e12
     return dict(kernel="k_p2p", bound="alu", achieved=ach, peak=PEAK["fp32"], unit="TFLOP/s",
@@ -215,7 +219,9 @@ def counter_run(precision):
     torch.neg(a, out=b)
     torch.cuda.synchronize()
     log(f"[bench] counter run done: {plan.counts()}")
-    print(json.dumps({"counts": plan.counts(), "precision": precision}), flush=True)
+    counts = plan.counts()
+    counts["m2l_rank"], counts["m2l_tile"] = plan.m2l_rank()
+    print(json.dumps({"counts": counts, "precision": precision}), flush=True)
     plan.close()
 
 
@@ -302,14 +308,16 @@ def summarize_counters(csv_a, counts_json, out, cmd_a):
         f.write(nl + "Achieved rates in this run (algorithmic work over the dispatch's own duration):" + nl + nl)
         if m2l:
             t = m2l[0][1]
-            fl = 2.0 * n * n * c["v_pairs"]
+            kr, tile = c.get("m2l_rank", n), c.get("m2l_tile", ((n + 31) // 32) * 32)
+            fl = 2.0 * kr * kr * c["v_pairs"]
             ex = m2l[0][4] * 2 * 16 * 16 * 32   # every M2L MFMA of the split path is a 16x16x32 bf16 product
-            f.write(f"* `k_m2l`: {c['v_pairs']:,} V pairs x 2 x {n}^2 = {fl / 1e9:.1f} GFLOP in {t * 1e3:.3f} ms "
+            f.write(f"* `k_m2l`: {c['v_pairs']:,} V pairs x 2 x {kr}^2 = {fl / 1e9:.1f} GFLOP in {t * 1e3:.3f} ms "
                     f"= {fl / t / 1e12:.1f} TFLOP/s useful ({fl / t / 2.5e15 * 100:.1f} % of the bf16 dense "
                     f"peak); executed {m2l[0][4]:.4g} bf16 16x16x32 MFMAs = {ex / 1e12:.2f} TFLOP, "
                     f"{ex / t / 1e15:.2f} PFLOP/s ({ex / t / 2.5e15 * 100:.1f} % of 2.5 PFLOP/s: three products "
-                    f"per split product, padding to {((n + 31) // 32) * 32} rows, slots walked for a block's "
-                    f"union of targets); MFMA busy {m2l[0][2] * 100:.1f} %." + nl)
+                    f"per split product, padding to {tile} rows, slots walked for a block's "
+                    f"union of targets); MFMA busy {m2l[0][2] * 100:.1f} %.  (Rank {kr} of the operators in use: the "
+                    f"truncated common basis of the {n}-point surface when it is smaller than {n}.)" + nl)
         if p2p:
             t = p2p[0][1]
             fl = 20.0 * c["p2p_pairs"]

@@ -250,6 +250,13 @@ int kifmm_clump_backward(kifmm_handle h, const float* charges, const float* fiel
 int kifmm_get_counts(kifmm_handle h, int64_t out[10]);
 
 /*
+ * The M2L operators in use (host out[2]): out[0] = their rank (the number of
+ * basis vectors kept with opts.m2l_rtol > 0, else the surface size n),
+ * out[1] = the tile the M2L kernel runs at (the padded rank, or n padded).
+ */
+int kifmm_get_m2l_rank(kifmm_handle h, int64_t out[2]);
+
+/*
  * Copy the tree to HOST buffers (each may be NULL), sized by kifmm_get_counts:
  *   keys [N] uint64 sorted Morton keys, perm [N] int64 (sorted position ->
  *   caller index), level/anchor/begin/end/parent/is_leaf per box (anchor is
@@ -273,7 +280,9 @@ int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indic
 
 /*
  * Per-phase device times in ms of the last evaluate/backward (host out[n]):
- * 0 P2M, 1 upward M2M+UC2E, 2 P2L, 3 M2L, 4 L2L+DC2E, 5 L2P+M2P (with the
+ * 0 P2M, 1 upward M2M+UC2E (and, with opts.m2l_rtol, the projection onto
+ * the M2L basis), 2 P2L, 3 M2L, 4 L2L+DC2E (and the expansion out of the M2L
+ * basis), 5 L2P+M2P (with the
  * final combination), 6 P2P (on the near-field stream, concurrent with 0-4),
  * 7 whole call.  Needs opts.profile = 1; returns the number written.
  */

@@ -35,7 +35,7 @@ _lib = None
 
 EXPORTS = ["kifmm_default_options", "kifmm_setup", "kifmm_setup_ex", "kifmm_rebuild", "kifmm_set_precision",
            "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient", "kifmm_backward",
-           "kifmm_clump_reduce", "kifmm_clump_backward", "kifmm_get_counts",
+           "kifmm_clump_reduce", "kifmm_clump_backward", "kifmm_get_counts", "kifmm_get_m2l_rank",
            "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times", "kifmm_destroy", "kifmm_status_string"]
 
 
@@ -63,6 +63,7 @@ def lib():
             L.kifmm_clump_reduce.argtypes = [H, P, P, P, I64, P, P, P, P]
             L.kifmm_clump_backward.argtypes = [H, P, P, P, I64, P, P, P, P, P, P, P, P]
             L.kifmm_get_counts.argtypes = [H, ctypes.POINTER(I64)]
+            L.kifmm_get_m2l_rank.argtypes = [H, ctypes.POINTER(I64)]
             L.kifmm_copy_tree.argtypes = [H, P, P, P, P, P, P, P, P, P]
             L.kifmm_copy_list.argtypes = [H, ctypes.c_char, P, P]
             L.kifmm_get_phase_times.argtypes = [H, ctypes.POINTER(ctypes.c_float), I]
@@ -74,7 +75,7 @@ def lib():
                          "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient", "kifmm_backward",
                          "kifmm_clump_reduce",
                          "kifmm_clump_backward",
-                         "kifmm_get_counts",
+                         "kifmm_get_counts", "kifmm_get_m2l_rank",
                          "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times"):
                 getattr(L, name).restype = I
             _lib = L

@@ -355,6 +355,15 @@ int kifmm_get_counts(kifmm_handle h, int64_t out[10]) {
     });
 }
 
+int kifmm_get_m2l_rank(kifmm_handle h, int64_t out[2]) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!out) throw Error(KIFMM_ERR_ARG, "null output");
+        out[0] = P->cm ? P->cm->k : P->n;
+        out[1] = P->cm ? P->cm->kp : P->npad;
+    });
+}
+
 int kifmm_copy_tree(kifmm_handle h, uint64_t* keys, int64_t* perm, int32_t* level, int32_t* anchor, int64_t* begin,
                     int64_t* end, int64_t* parent, int8_t* is_leaf, double* root) {
     return guarded([&] {

@@ -1415,10 +1415,11 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
     } else {
         for (int r = r0; r < r1; ++r) launch_m2l<NP>(P, 1, r, s);
     }
-    // compressed M2L: its results back on the check surfaces, added to the X list
+    if (rec) record_phase(P, 3, s);
+    // compressed M2L: its results back on the check surfaces, added to the X
+    // list (timed with the downward pass)
     if (P->cm)
         for (int r = r0; r < r1; ++r) project_expand<NP>(P, false, r, s);
-    if (rec) record_phase(P, 3, s);
     // L2L + DC2E, coarse to fine
     for (int r = r0; r < r1; ++r)
         for (int l = first_v_level(P); l <= depth; ++l) {

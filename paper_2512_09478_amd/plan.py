@@ -194,6 +194,12 @@ class Plan:
                 "surface_points"]
         return dict(zip(keys, [int(v) for v in out]))
 
+    def m2l_rank(self) -> tuple:
+        """(rank of the M2L operators in use, tile the M2L kernel runs at)."""
+        out = (ctypes.c_int64 * 2)()
+        check(_lib.lib().kifmm_get_m2l_rank(self.handle, out))
+        return int(out[0]), int(out[1])
+
     def tree(self) -> dict:
         c = self.counts()
         N, B = c["n"], c["boxes"]

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "kifmm.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(kifmm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(kifmm_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -70,4 +70,5 @@ def test_argument_errors_without_gpu(L):
                                   None) == -5
     out = (ctypes.c_int64 * 10)()
     assert L.kifmm_get_counts(None, out) == -5
+    assert L.kifmm_get_m2l_rank(None, out) == -5
     L.kifmm_destroy(None)
