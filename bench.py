@@ -412,7 +412,7 @@ def main():
         counter_run(args.counter_run)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on a single GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     import workloads

@@ -184,7 +184,7 @@ def _rsa_pack(rng: np.random.Generator, radii: np.ndarray, batch: int = 1024,
             slots = grid[cid][:, :, :m].reshape(todo.size, -1)           # [K, 27*m]
             d2 = np.sum((pc[slots] - c[:, None, :]) ** 2, axis=2)
             ok = ~np.any(d2 < (pr[slots] + r[:, None]) ** 2, axis=1)
-            # proposals of this round against the earlier accepted ones (in order)
+            # proposals of this batch against the earlier accepted ones (in order)
             acc = []
             for t in np.nonzero(ok)[0]:
                 if acc:
