@@ -147,8 +147,8 @@ struct Operators {
 // tile sizes the M2L kernel is built for; kp = 0 means the basis does not pay.
 struct M2LBasis {
     int k = 0, kp = 0;
-    DBuf proj;        // float [NP][kp]: Q, padded (phi_k[r] = sum_c proj[c][r] phi_u[c])
-    DBuf expd;        // float [kp][NP]: Q^T, padded (psi[r] += sum_j expd[j][r] psi_k[j])
+    DBuf q;           // float [NP][kp]: Q row-major, zero-padded (operand of the expansion psi += Q psi_k)
+    DBuf qt;          // float [kp][NP]: Q^T row-major, zero-padded (operand of the projection phi_k = Q^T phi)
     DBuf core_f32;    // [316] cores in gather-fragment order at kp (FP32)
     DBuf core_bf16;   // the same, bf16 hi/lo
 };

@@ -1112,68 +1112,68 @@ __global__ __launch_bounds__(256) void k_far_grad(const int2* __restrict__ items
 #undef KIFMM_FARG_ITEM
 }
 
-// Compressed M2L, projection of the upward densities: phi_k = Q^T phi_u for
-// the boxes [b0, b0 + nb).  A block takes 16 boxes staged in LDS; thread t
-// computes row t % KP of 256 / KP of those boxes' outputs, reading column c of
-// Q^T (a contiguous row of `proj`) once for all of its boxes.
-template <int NP, int KP>
-__global__ __launch_bounds__(256) void k_project(int b0, int nb, const float* __restrict__ proj,
-                                                 const float* __restrict__ phi_u, float* __restrict__ phi_k) {
-    constexpr int G = 16, TPR = 256 / KP, BPT = G / TPR;   // threads per row, boxes per thread
-    static_assert(TPR >= 1 && G % TPR == 0, "tile");
-    __shared__ float in[G][NP];
-    const int first = b0 + blockIdx.x * G;
-    for (int t = threadIdx.x; t < G * NP; t += 256) {
-        const int g = t / NP, c = t % NP;
-        in[g][c] = first + g < b0 + nb ? phi_u[size_t(first + g) * NP + c] : 0.f;
-    }
-    __syncthreads();
-    if (threadIdx.x >= TPR * KP) return;   // (no barrier follows)
-    const int r = threadIdx.x % KP, h = threadIdx.x / KP;
-    float acc[BPT];
+// Compressed M2L change of basis on MFMA, for the boxes [b0, b0 + nb):
+//   out[b][j] = sum_k in[b][k] W[j][k]        (ACCUM: out[b][j] += ...)
+// with W row-major [NOUT][NIN] and `in` the sum of nsplit arrays split_stride
+// apart.  The projection phi_k = Q^T phi_u takes W = Q^T ([kp][NP]); the
+// expansion psi_d += Q (sum of the partial psi_k) takes W = Q ([NP][kp]).
+// A wave owns 16 boxes and CPW of the NOUT/16 column tiles (v_mfma_f32_16x16x4_f32,
+// operand layout as in the file header).  In a 16-wide k chunk the lane in
+// group kk = lane/16 loads the float4 k0 + 4 kk .. k0 + 4 kk + 3 of its box row
+// and of the W row of its column, and step s of the four MFMAs takes component
+// s: k = k0 + 4 kk + s, the same permutation on both operands.
+template <int NIN, int NOUT, bool ACCUM>
+__global__ __launch_bounds__(256) void k_basis(int b0, int nb, const float* __restrict__ W,
+                                               const float* __restrict__ in, int nsplit, size_t split_stride,
+                                               float* __restrict__ out) {
+    constexpr int T = NOUT / 16, NCP = T % 2 == 0 ? 2 : 1, CPW = T / NCP;   // column parts, tiles per wave
+    static_assert(NIN % 32 == 0 && NOUT % 16 == 0, "tile");
+    const int item = blockIdx.x * 4 + int(threadIdx.x >> 6);
+    const int g = item / NCP, cp = item % NCP;
+    const int row0 = b0 + 16 * g, end = b0 + nb;
+    if (row0 >= end) return;   // whole wave (no barrier in this kernel)
+    const int lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
+    const bool live = row0 + i < end;
+    const float* arow = in + size_t(row0 + i) * NIN + 4 * kk;
+    const float* wrow = W + size_t(16 * cp * CPW + i) * NIN + 4 * kk;
+    v4f c[CPW];
 #pragma unroll
-    for (int q = 0; q < BPT; ++q) acc[q] = 0.f;
-    for (int c = 0; c < NP; ++c) {
-        const float a = proj[size_t(c) * KP + r];
+    for (int t = 0; t < CPW; ++t) c[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < NIN; k0 += 32) {
+        // two chunks per step: a box row's 128 contiguous bytes in one go
+        float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+        if (live)
+            for (int sp = 0; sp < nsplit; ++sp) {
+                const float4 x0 = *reinterpret_cast<const float4*>(arow + sp * split_stride + k0);
+                const float4 x1 = *reinterpret_cast<const float4*>(arow + sp * split_stride + k0 + 16);
+                a0.x += x0.x; a0.y += x0.y; a0.z += x0.z; a0.w += x0.w;
+                a1.x += x1.x; a1.y += x1.y; a1.z += x1.z; a1.w += x1.w;
+            }
 #pragma unroll
-        for (int q = 0; q < BPT; ++q) acc[q] += a * in[h * BPT + q][c];
-    }
-#pragma unroll
-    for (int q = 0; q < BPT; ++q) {
-        const int b = first + h * BPT + q;
-        if (b < b0 + nb) phi_k[size_t(b) * KP + r] = acc[q];
-    }
-}
-
-// Compressed M2L, expansion: psi_d += Q (sum of the nsplit partial psi_k) for
-// the boxes [b0, b0 + nb); psi_d already holds the X-list part.
-template <int NP, int KP>
-__global__ __launch_bounds__(256) void k_expand(int b0, int nb, const float* __restrict__ expd,
-                                                const float* __restrict__ psi_k, int nsplit, size_t split_stride,
-                                                float* __restrict__ psi_d) {
-    constexpr int G = 16;
-    __shared__ float in[G][KP];
-    const int first = b0 + blockIdx.x * G;
-    for (int t = threadIdx.x; t < G * KP; t += 256) {
-        const int g = t / KP, j = t % KP;
-        float v = 0.f;
-        if (first + g < b0 + nb)
-            for (int sp = 0; sp < nsplit; ++sp) v += psi_k[sp * split_stride + size_t(first + g) * KP + j];
-        in[g][j] = v;
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < NP; r += 256) {
-        float acc[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = 0.f;
-        for (int j = 0; j < KP; ++j) {
-            const float a = expd[size_t(j) * NP + r];
-#pragma unroll
-            for (int g = 0; g < G; ++g) acc[g] += a * in[g][j];
+        for (int t = 0; t < CPW; ++t) {
+            const float4 w0 = *reinterpret_cast<const float4*>(wrow + size_t(16 * t) * NIN + k0);
+            const float4 w1 = *reinterpret_cast<const float4*>(wrow + size_t(16 * t) * NIN + k0 + 16);
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, w0.x, c[t], 0, 0, 0);
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, w0.y, c[t], 0, 0, 0);
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.z, w0.z, c[t], 0, 0, 0);
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.w, w0.w, c[t], 0, 0, 0);
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, w1.x, c[t], 0, 0, 0);
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, w1.y, c[t], 0, 0, 0);
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.z, w1.z, c[t], 0, 0, 0);
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.w, w1.w, c[t], 0, 0, 0);
         }
+    }
+    // D[4 kk + v][i] of tile t: box row0 + 4 kk + v, column 16 (cp CPW + t) + i
 #pragma unroll
-        for (int g = 0; g < G; ++g)
-            if (first + g < b0 + nb) psi_d[size_t(first + g) * NP + r] += acc[g];
+    for (int v = 0; v < 4; ++v) {
+        const int b = row0 + 4 * kk + v;
+        if (b >= end) continue;
+        float* o = out + size_t(b) * NOUT + 16 * cp * CPW + i;
+#pragma unroll
+        for (int t = 0; t < CPW; ++t) {
+            if constexpr (ACCUM) o[16 * t] += c[t][v];
+            else o[16 * t] = c[t][v];
+        }
     }
 }
 
@@ -1315,13 +1315,17 @@ void project_expand_kp(kifmm_plan* P, bool project, int r, hipStream_t s) {
     if (nb <= 0) return;
     const M2LBasis& cm = *P->cm;
     const size_t sn = size_t(P->B) * NP, sk = size_t(P->B) * KP;
+    // work items: 16 boxes by one of the (one or two) column parts, four per block
+    const auto blocks = [&](int nout) {
+        const int parts = (nout / 16) % 2 == 0 ? 2 : 1;
+        return dim3(unsigned(nblk(int64_t(nblk(nb, 16)) * parts, 4)));
+    };
     if (project)
-        hipLaunchKernelGGL((k_project<NP, KP>), dim3(unsigned(nblk(nb, 16))), dim3(256), 0, s, b0, nb,
-                           cm.proj.as<float>(), P->phi_u.as<float>() + r * sn, P->phi_k.as<float>() + r * sk);
+        hipLaunchKernelGGL((k_basis<NP, KP, false>), blocks(KP), dim3(256), 0, s, b0, nb, cm.qt.as<float>(),
+                           P->phi_u.as<float>() + r * sn, 1, size_t(0), P->phi_k.as<float>() + r * sk);
     else
-        hipLaunchKernelGGL((k_expand<NP, KP>), dim3(unsigned(nblk(nb, 16))), dim3(256), 0, s, b0, nb,
-                           cm.expd.as<float>(), P->psi_m.as<float>() + r * sk, P->m2l_split_used, 2 * sk,
-                           P->psi_d.as<float>() + r * sn);
+        hipLaunchKernelGGL((k_basis<KP, NP, true>), blocks(NP), dim3(256), 0, s, b0, nb, cm.q.as<float>(),
+                           P->psi_m.as<float>() + r * sk, P->m2l_split_used, 2 * sk, P->psi_d.as<float>() + r * sn);
 }
 
 template <int NP>

@@ -396,14 +396,14 @@ std::unique_ptr<M2LBasis> build_m2l_basis(int p, double rtol) {
     const int kp = m2l_tile(k);
     if (kp == 0 || kp >= np) return b;   // no smaller tile: the exact operators are used
     b->kp = kp;
-    std::vector<float> proj(size_t(np) * kp, 0.f), expd(size_t(kp) * np, 0.f);
+    std::vector<float> q(size_t(np) * kp, 0.f), qt(size_t(kp) * np, 0.f);
     for (int c = 0; c < n; ++c)
         for (int r = 0; r < k; ++r) {
-            proj[size_t(c) * kp + r] = float(U[size_t(c) * n + r]);
-            expd[size_t(r) * np + c] = float(U[size_t(c) * n + r]);
+            q[size_t(c) * kp + r] = float(U[size_t(c) * n + r]);
+            qt[size_t(r) * np + c] = float(U[size_t(c) * n + r]);
         }
-    upload(b->proj, proj.data(), proj.size() * 4);
-    upload(b->expd, expd.data(), expd.size() * 4);
+    upload(b->q, q.data(), q.size() * 4);
+    upload(b->qt, qt.data(), qt.size() * 4);
     // cores Q^T M(d) Q in the M2L kernel's gather-fragment order at kp
     const size_t per = size_t(kp) * kp;
     std::vector<float> core(size_t(kNumV) * per, 0.f);
