@@ -245,7 +245,9 @@ int kifmm_clump_backward(kifmm_handle h, const float* charges, const float* fiel
 /*
  * Sizes of the plan (host out[10]): boxes, leaves, depth, V-list pairs,
  * near-field point pairs (P2P, self pairs included), W-list pairs, X-list
- * pairs, U-list leaf pairs, N, surface points n.
+ * pairs, U-list leaf pairs, N, surface points n.  The two pair counts are
+ * taken on the first call after a build (two small kernels on the handle's
+ * last stream, which the call then synchronises), not by the build itself.
  */
 int kifmm_get_counts(kifmm_handle h, int64_t out[10]);
 

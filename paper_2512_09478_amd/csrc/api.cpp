@@ -351,6 +351,7 @@ int kifmm_get_counts(kifmm_handle h, int64_t out[10]) {
     return guarded([&] {
         kifmm_plan* P = checked(h);
         if (!out) throw Error(KIFMM_ERR_ARG, "null output");
+        if (!P->pairs_counted) count_pairs(P, P->last_stream);
         for (int k = 0; k < 10; ++k) out[k] = P->counts[k];
     });
 }

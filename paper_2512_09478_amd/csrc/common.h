@@ -223,6 +223,7 @@ struct kifmm_plan {
     int64_t bfar = 0;       // first box with a downward density (level 2, or the root when periodic)
     std::vector<kifmm::LevelInfo> lev;
     int64_t counts[10] = {};
+    bool pairs_counted = false;   // counts[3] and counts[4] (V pairs, P2P pairs) are taken on request
     hipStream_t last_stream = nullptr;
     const kifmm::Operators* ops = nullptr;
     const kifmm::M2LBasis* cm = nullptr;   // compressed M2L in use (null: the exact operators)
@@ -266,7 +267,7 @@ struct kifmm_plan {
     kifmm::DBuf mom;        // periodic: double [rhs][16] source moments about the cell centre
     kifmm::DBuf mom_part;   // their per-block partial sums
     // scratch
-    kifmm::DBuf tmp_a, tmp_b, tmp_c, tmp_d, tmp_e, tmp_f, scan_tmp, flag;
+    kifmm::DBuf tmp_a, tmp_b, tmp_c, tmp_d, tmp_e, tmp_f, scan_tmp, flag, pair_cnt;
     kifmm::PhaseEvents events;
     kifmm::SideStream nearq;   // near-field stream
     float phase_ms[8] = {};
@@ -278,6 +279,9 @@ namespace kifmm {
 
 // ---- tree.hip
 void build_tree(kifmm_plan* P, const double* positions, hipStream_t s);
+// V-list pairs and near-field point pairs of the current lists into
+// counts[3], counts[4] (synchronises s)
+void count_pairs(kifmm_plan* P, hipStream_t s);
 // offset (in box widths) from a box at octant o to the source of its V slot j
 void v_slot_offset(int o, int j, int d[3]);
 // ---- farfield.hip

@@ -570,95 +570,92 @@ __global__ void k_vdense(int b0, int nb, const int4* __restrict__ anchor, const 
     }
 }
 
+// The next three kernels take one wave per box.  Its candidates are the 27
+// colleagues of a box P (lanes 0..26) and, when P has them, P's coarse
+// adjacent leaves (lanes 27..52, a row that ends at its first -1); each lane
+// tests its own candidate and the kept ones are compacted in lane order by a
+// ballot, which is the order of a serial walk over the two rows.
+__device__ inline int wave_candidate(int lane, int P, bool with_cal, const int* __restrict__ coll,
+                                     const int* __restrict__ cal) {
+    if (lane < 27) return coll[27 * int64_t(P) + lane];
+    if (with_cal && lane < 53) return cal[26 * int64_t(P) + (lane - 27)];
+    return -1;
+}
+
 // Coarse adjacent leaves: leaves of a coarser level adjacent to b; at most 26.
-__global__ void k_cal(int b0, int nb, const int4* __restrict__ anchor, const int* __restrict__ parent,
-                      const int* __restrict__ leafflag, const int* __restrict__ coll, int* __restrict__ cal,
-                      int* __restrict__ bad) {
-    int i = blockIdx.x * TB + threadIdx.x;
-    if (i >= nb) return;
-    int b = b0 + i;
-    int4 ab = anchor[b];
-    int P = parent[b];
-    int cnt = 0;
-    int* out = cal + 26 * int64_t(b);
-    for (int d = 0; d < 27; ++d) {
-        int Q = coll[27 * int64_t(P) + d];
-        if (Q >= 0 && leafflag[img_box(Q)] && adjacent_image(anchor[img_box(Q)], Q, ab)) {
-            if (cnt < 26) out[cnt] = Q;
-            ++cnt;
-        }
-    }
+// They are the leaf colleagues of parent(b) and the coarse adjacent leaves of
+// parent(b) that touch b.
+__global__ __launch_bounds__(256) void k_cal(int b0, int nb, const int4* __restrict__ anchor,
+                                             const int* __restrict__ parent, const int* __restrict__ leafflag,
+                                             const int* __restrict__ coll, int* __restrict__ cal,
+                                             int* __restrict__ bad) {
+    const int lane = threadIdx.x & 63, i = blockIdx.x * 4 + int(threadIdx.x >> 6);
+    if (i >= nb) return;   // whole wave
+    const int b = b0 + i;
+    const int4 ab = anchor[b];
+    const int P = parent[b];
     // (the root has no coarse adjacent leaves; its row is never written)
-    for (int k = 0; P > 0 && k < 26; ++k) {
-        int Q = cal[26 * int64_t(P) + k];
-        if (Q < 0) break;
-        if (adjacent_image(anchor[img_box(Q)], Q, ab)) {
-            if (cnt < 26) out[cnt] = Q;
-            ++cnt;
-        }
+    const int Q = wave_candidate(lane, P, P > 0, coll, cal);
+    bool keep = false;
+    if (Q >= 0) {
+        const int A = img_box(Q);
+        keep = (lane >= 27 || leafflag[A]) && adjacent_image(anchor[A], Q, ab);
     }
-    if (cnt > 26) atomicOr(bad, 2);
-    for (int k = cnt; k < 26; ++k) out[k] = -1;
+    const uint64_t m = __ballot(keep);
+    const int cnt = __popcll(m), pos = __popcll(m & lane_lt_mask());
+    int* out = cal + 26 * int64_t(b);
+    if (keep && pos < 26) out[pos] = Q;
+    if (lane >= cnt && lane < 26) out[lane] = -1;
+    if (lane == 0 && cnt > 26) atomicOr(bad, 2);
 }
 
 // X(b), level >= 2: leaves adjacent to parent(b) of its level or coarser that
 // are not adjacent to b.  mode 0 counts, mode 1 fills.
-__global__ void k_xlist(int b0, int nb, const int4* __restrict__ anchor, const int* __restrict__ parent,
-                        const int* __restrict__ leafflag, const int* __restrict__ coll,
-                        const int* __restrict__ cal, int* __restrict__ cnt_or_off, int* __restrict__ idx,
-                        int mode) {
-    int i = blockIdx.x * TB + threadIdx.x;
-    if (i >= nb) return;
-    int b = b0 + i;
-    int4 ab = anchor[b];
-    int P = parent[b];
-    int c = 0;
-    int at = mode ? cnt_or_off[b] : 0;
+__global__ __launch_bounds__(256) void k_xlist(int b0, int nb, const int4* __restrict__ anchor,
+                                               const int* __restrict__ parent, const int* __restrict__ leafflag,
+                                               const int* __restrict__ coll, const int* __restrict__ cal,
+                                               int* __restrict__ cnt_or_off, int* __restrict__ idx, int mode) {
+    const int lane = threadIdx.x & 63, i = blockIdx.x * 4 + int(threadIdx.x >> 6);
+    if (i >= nb) return;   // whole wave
+    const int b = b0 + i;
+    const int P = parent[b];
     if (P < 0) {   // the (periodic) root
-        if (!mode) cnt_or_off[b] = 0;
+        if (!mode && lane == 0) cnt_or_off[b] = 0;
         return;
     }
-    for (int d = 0; d < 27; ++d) {
-        int Q = coll[27 * int64_t(P) + d];
-        if (Q >= 0 && leafflag[img_box(Q)] && !adjacent_image(anchor[img_box(Q)], Q, ab)) {
-            if (mode) idx[at + c] = Q;
-            ++c;
-        }
+    const int4 ab = anchor[b];
+    const int Q = wave_candidate(lane, P, P > 0, coll, cal);
+    bool keep = false;
+    if (Q >= 0) {
+        const int A = img_box(Q);
+        keep = (lane >= 27 || leafflag[A]) && !adjacent_image(anchor[A], Q, ab);
     }
-    for (int k = 0; P > 0 && k < 26; ++k) {
-        int Q = cal[26 * int64_t(P) + k];
-        if (Q < 0) break;
-        if (!adjacent_image(anchor[img_box(Q)], Q, ab)) {
-            if (mode) idx[at + c] = Q;
-            ++c;
-        }
+    const uint64_t m = __ballot(keep);
+    if (mode) {
+        if (keep) idx[cnt_or_off[b] + __popcll(m & lane_lt_mask())] = Q;
+    } else if (lane == 0) {
+        cnt_or_off[b] = __popcll(m);
     }
-    if (!mode) cnt_or_off[b] = c;
 }
 
 // U(b) own part: leaf colleagues (b included) and coarse adjacent leaves.
-__global__ void k_ulist_own(int B, const int* __restrict__ leafflag, const int* __restrict__ coll,
-                            const int* __restrict__ cal, int* __restrict__ cnt_or_off, int* __restrict__ idx,
-                            int* __restrict__ cursor, int mode) {
-    int b = blockIdx.x * TB + threadIdx.x;
-    if (b >= B || !leafflag[b]) return;
-    int c = 0;
-    int at = mode ? cnt_or_off[b] : 0;
-    for (int d = 0; d < 27; ++d) {
-        int Q = coll[27 * int64_t(b) + d];
-        if (Q >= 0 && leafflag[img_box(Q)]) {
-            if (mode) idx[at + c] = Q;
-            ++c;
-        }
+__global__ __launch_bounds__(256) void k_ulist_own(int B, const int* __restrict__ leafflag,
+                                                   const int* __restrict__ coll, const int* __restrict__ cal,
+                                                   int* __restrict__ cnt_or_off, int* __restrict__ idx,
+                                                   int* __restrict__ cursor, int mode) {
+    const int lane = threadIdx.x & 63, b = blockIdx.x * 4 + int(threadIdx.x >> 6);
+    if (b >= B || !leafflag[b]) return;   // whole wave
+    const int Q = wave_candidate(lane, b, b > 0, coll, cal);
+    const bool keep = Q >= 0 && (lane >= 27 || leafflag[img_box(Q)]);
+    const uint64_t m = __ballot(keep);
+    const int c = __popcll(m);
+    if (mode) {
+        const int at = cnt_or_off[b];
+        if (keep) idx[at + __popcll(m & lane_lt_mask())] = Q;
+        if (lane == 0) cursor[b] = at + c;
+    } else if (lane == 0) {
+        cnt_or_off[b] = c;
     }
-    for (int k = 0; b > 0 && k < 26; ++k) {
-        int Q = cal[26 * int64_t(b) + k];
-        if (Q < 0) break;
-        if (mode) idx[at + c] = Q;
-        ++c;
-    }
-    if (mode) cursor[b] = at + c;
-    else cnt_or_off[b] = c;
 }
 
 // U(b) finer part: every leaf A lists b in cal[A]  ->  A in U(b) (an image
@@ -806,9 +803,10 @@ __global__ void k_item_fill(int nl, const int* __restrict__ leaves, const int2* 
         const unsigned long long nt = min(64, r.y - t0);
         items[at] = make_int2(b, t0);
         const unsigned long long cn = nt * src, cf = nt * nfar * 64;
-        // heaviest first: 16-bit keys, descending in log2(cost) (2^-11 steps)
-        key_near[at] = 0xffffull - min(0xffffull, (unsigned long long)(log2(double(cn) + 1.0) * 2048.0));
-        key_far[at] = 0xffffull - min(0xffffull, (unsigned long long)(log2(double(cf) + 1.0) * 2048.0));
+        // heaviest first: 8-bit keys (one radix pass), descending in log2(cost)
+        // in steps of 1/8 (costs within 9 % share a key and keep their order)
+        key_near[at] = 0xffull - min(0xffull, (unsigned long long)(log2(double(cn) + 1.0) * 8.0));
+        key_far[at] = 0xffull - min(0xffull, (unsigned long long)(log2(double(cf) + 1.0) * 8.0));
         id_near[at] = uint32_t(at);
         id_far[at] = uint32_t(at);
     }
@@ -1043,7 +1041,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     // coarse adjacent leaves, top-down
     P->cal.ensure(size_t(B) * 26 * 4);   // every row below the root is written by k_cal
     for (int l = 1; l <= P->depth; ++l)
-        hipLaunchKernelGGL(k_cal, dim3(nblocks(P->lev[l].count)), dim3(TB), 0, s, int(P->lev[l].start),
+        hipLaunchKernelGGL(k_cal, dim3(nblocks(P->lev[l].count, 4)), dim3(TB), 0, s, int(P->lev[l].start),
                            int(P->lev[l].count), P->bx_anchor.as<int4>(), P->bx_parent.as<int>(),
                            P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), bad);
     // X lists (rows over all boxes; non-empty from the first far-field level)
@@ -1051,7 +1049,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     int* xoff = P->x_off.as<int>();
     KIFMM_HIP(hipMemsetAsync(xoff, 0, size_t(B + 1) * 4, s));
     if (nvb > 0)
-        hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
+        hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
                            P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
                            (int*)nullptr, 0);
     exclusive_scan<int>(P, xoff, xoff, B + 1, s);
@@ -1063,7 +1061,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     const size_t xcap = size_t(std::max(nvb, 1)) * 52, ucap = size_t(B) * (53 + 26);
     P->x_idx.ensure(xcap * 4);
     if (nvb > 0) {
-        hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
+        hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
                            P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
                            P->x_idx.as<int>(), 1);
         hipLaunchKernelGGL(k_sort_rows, dim3(B), dim3(64), 0, s, B, xoff, P->x_idx.as<int>());
@@ -1076,13 +1074,13 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     int* fcnt = cursor + (B + 1);
     KIFMM_HIP(hipMemsetAsync(uoff, 0, size_t(B + 1) * 4, s));
     KIFMM_HIP(hipMemsetAsync(fcnt, 0, size_t(B + 1) * 4, s));
-    hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
+    hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
                        P->cal.as<int>(), uoff, (int*)nullptr, (int*)nullptr, 0);
     hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
                        uoff, (int*)nullptr, (int*)nullptr, 0);
     exclusive_scan<int>(P, uoff, uoff, B + 1, s);
     P->u_idx.ensure(ucap * 4);
-    hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
+    hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
                        P->cal.as<int>(), uoff, P->u_idx.as<int>(), cursor, 1);
     hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
                        (int*)nullptr, P->u_idx.as<int>(), cursor, 1);
@@ -1141,31 +1139,21 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         P->tmp_c.ensure(size_t(ni) * 8);
         hipLaunchKernelGGL(k_item_fill, dim3(nblocks(nl)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
                            P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), woff, b2, ioff, items, kn, kf, idn, idf);
-        radix_sort(P, kn, idn, P->tmp_c.as<uint64_t>(), vtmp, ni, 16, s);
-        radix_sort(P, kf, idf, P->tmp_c.as<uint64_t>(), vtmp, ni, 16, s);
+        radix_sort(P, kn, idn, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
+        radix_sort(P, kf, idf, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
         P->items_near.ensure(size_t(ni) * 8);
         P->items_far.ensure(size_t(ni) * 8);
         hipLaunchKernelGGL(k_item_gather, dim3(nblocks(ni)), dim3(TB), 0, s, ni, items, idn, idf,
                            P->items_near.as<int2>(), P->items_far.as<int2>());
     }
-    // counts
-    P->tmp_a.ensure(64);
-    unsigned long long* dc = P->tmp_a.as<unsigned long long>();
-    KIFMM_HIP(hipMemsetAsync(dc, 0, 16, s));
-    if (nvb > 0)
-        hipLaunchKernelGGL(k_count_v, dim3(std::min(1024, nblocks(int64_t(nvb) * kVPerOct))), dim3(TB), 0, s,
-                           int64_t(nvb) * kVPerOct, P->vdense.as<int>(), dc);
-    hipLaunchKernelGGL(k_counts, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->bx_range.as<int2>(),
-                       uoff, P->u_idx.as<int>(), dc);
+    // counts (the pair counts are taken on request: count_pairs)
     unsigned long long* hw = P->host.get();
-    KIFMM_HIP(hipMemcpyAsync(hw, dc, 16, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipMemcpyAsync(hw + 2, bad, 4, hipMemcpyDeviceToHost, s));
     int* hl = reinterpret_cast<int*>(hw + 3);   // list sizes: X, U, W
     KIFMM_HIP(hipMemcpyAsync(hl, xoff + B, 4, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipMemcpyAsync(hl + 1, uoff + B, 4, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipMemcpyAsync(hl + 2, woff + B, 4, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipStreamSynchronize(s));
-    const unsigned long long hc[2] = {hw[0], hw[1]};
     const int hbad = int(hw[2] & 0xffffffffull);
     const int nx = hl[0], nu = hl[1], nw = hl[2];
     if (hbad & 1)
@@ -1175,13 +1163,33 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     P->counts[0] = B;
     P->counts[1] = nl;
     P->counts[2] = P->depth;
-    P->counts[3] = int64_t(hc[0]);
-    P->counts[4] = int64_t(hc[1]);
+    P->counts[3] = 0;
+    P->counts[4] = 0;
+    P->pairs_counted = false;
     P->counts[5] = nw;
     P->counts[6] = nx;
     P->counts[7] = nu;
     P->counts[8] = N;
     P->counts[9] = P->n;
+}
+
+void count_pairs(kifmm_plan* P, hipStream_t s) {
+    const int B = int(P->B), nvb = B - int(P->bfar);
+    P->pair_cnt.ensure(64);
+    unsigned long long* dc = P->pair_cnt.as<unsigned long long>();
+    KIFMM_HIP(hipMemsetAsync(dc, 0, 16, s));
+    if (nvb > 0)
+        hipLaunchKernelGGL(k_count_v, dim3(std::min(1024, nblocks(int64_t(nvb) * kVPerOct))), dim3(TB), 0, s,
+                           int64_t(nvb) * kVPerOct, P->vdense.as<int>(), dc);
+    if (B > 0)
+        hipLaunchKernelGGL(k_counts, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(),
+                           P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), dc);
+    unsigned long long* hw = P->host.get();
+    KIFMM_HIP(hipMemcpyAsync(hw, dc, 16, hipMemcpyDeviceToHost, s));
+    KIFMM_HIP(hipStreamSynchronize(s));
+    P->counts[3] = int64_t(hw[0]);
+    P->counts[4] = int64_t(hw[1]);
+    P->pairs_counted = true;
 }
 
 }  // namespace kifmm
