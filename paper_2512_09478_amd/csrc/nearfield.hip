@@ -2,10 +2,14 @@
 // zone), written sorted as a float4 per point; the leaf-evaluation kernel adds
 // it to the far field and writes the caller-order outputs.
 //
-// Work items of at most 64 targets of one leaf, launched heaviest first; four
-// waves per item split the sources.  An item with nt <= 32 targets gives each
-// target S = 64/round_up_pow2(nt) lanes (at most 8) per wave; partial sums are
-// combined with cross-lane shuffles and then over the waves in a fixed order.
+// Work items of at most 64 targets of one leaf, launched heaviest first.  An
+// item with 16 or more targets gives each of its four waves a quarter of the
+// targets and all of the sources; a smaller item gives every wave all of its
+// targets and every fourth group of sources.  Inside a wave a target has
+// S = floor(64 / targets of the wave) consecutive lanes that split the
+// sources, so at least 60 of the 64 lanes work; the lane partial sums are
+// combined by a shuffle tree inside the group of S lanes and, for a small
+// item, over the waves, both in a fixed order.
 // The points of the U-list source leaves are streamed through LDS as float4
 // (x, y, z, q) in global FP32 coordinates, many leaves per batch, so every
 // pair difference is a correctly rounded FP32
@@ -41,7 +45,42 @@ __global__ void k_gather_adj(int64_t N, const int* __restrict__ perm, const floa
 
 __device__ inline float rsq(float r2) { return r2 > 0.f ? __frsqrt_rn(r2) : 0.f; }
 
-__device__ inline int lanes_per_target(int nt) { return nt <= 8 ? 8 : nt <= 16 ? 4 : nt <= 32 ? 2 : 1; }
+// Lane map of a work item (first target `first`, nt targets, 1 <= nt <= 64).
+struct NearMap {
+    int S;         // lanes per target in this wave (4 .. 64)
+    int slice;     // this lane's place among them
+    int i;         // target (sorted index)
+    int j0, dj;    // staged sources j0, j0 + dj, ...
+    bool act;      // the lane serves a target
+    bool split;    // the waves split the sources (small item): sum over waves
+};
+
+__device__ inline NearMap near_map(int first, int nt) {
+    NearMap m;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    m.split = nt < 16;
+    const int per = m.split ? nt : (nt + 3) / 4;   // targets per wave
+    const int t0 = m.split ? 0 : w * per;
+    const int ntw = min(per, nt - t0);              // >= 1: nt - 3 ceil(nt/4) > 0 for nt >= 16
+    m.S = 64 / ntw;
+    m.slice = lane % m.S;
+    const int tl = lane / m.S;
+    m.act = tl < ntw;
+    m.i = first + t0 + tl;
+    m.j0 = m.split ? w * m.S + m.slice : m.slice;
+    m.dj = m.split ? 4 * m.S : m.S;
+    return m;
+}
+
+// Sum over the S lanes of a target (lanes [g S, g S + S) of the wave); the
+// first lane of the group ends with the total.
+__device__ inline float group_sum(float v, int slice, int S) {
+    for (int off = 1; off < S; off <<= 1) {
+        const float t = __shfl_down(v, off, 64);
+        if (slice + off < S) v += t;
+    }
+    return v;
+}
 
 // Stream the points of U(b) through LDS, all four waves staging together;
 // calls body(m) after each batch of m staged points.  Block-uniform control.
@@ -81,11 +120,6 @@ __device__ inline void stream_sources(const int* __restrict__ uoff, const int* _
     }
 }
 
-__device__ inline float lane_sum(float v, int S) {
-    for (int off = 1; off < S; off <<= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // Sum NV per-lane values over the four waves in a fixed order (wave 0 ends
 // with the totals).
 template <int NV>
@@ -100,9 +134,18 @@ __device__ inline void wave_reduce(float (&v)[NV], float (*red)[NV][64]) {
         for (int q = 0; q < NV; ++q) v[q] = ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane];
 }
 
-// Work item = (leaf, first target): up to 64 targets.  The four waves of the
-// block take interleaved groups of the staged sources; within a wave each
-// target has S lanes.
+// Totals of an item's lane partials; true on the lane that writes them.
+// Block-uniform (m.split depends on the item only).
+template <int NV>
+__device__ inline bool near_finish(float (&v)[NV], const NearMap& m, float (*red)[NV][64]) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = group_sum(v[q], m.slice, m.S);
+    if (!m.split) return m.act && m.slice == 0;
+    wave_reduce<NV>(v, red);
+    return (threadIdx.x >> 6) == 0 && m.act && m.slice == 0;
+}
+
+// Work item = (leaf, first target): up to 64 targets, lanes as in near_map.
 __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int n_items, const int2* __restrict__ range,
                                              const int* __restrict__ uoff, const int* __restrict__ uidx,
                                              const float4* __restrict__ pts, float cst, float cell,
@@ -114,16 +157,14 @@ __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int
         const int2 it = items[item];
         const int b = it.x;
         const int nt = min(64, range[b].y - it.y);
-        const int S = lanes_per_target(nt);
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int slice = lane & (S - 1);
-        const int i = it.y + lane / S;
-        const bool act = lane / S < nt;
+        const NearMap nm = near_map(it.y, nt);
+        const int i = nm.i;
+        const bool act = nm.act;
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
         stream_sources(uoff, uidx, range, b, pts, nullptr, cell, sh, nullptr, [&](int m) {
 #pragma unroll 4
-            for (int j = w * S + slice; j < m; j += 4 * S) {
+            for (int j = nm.j0; j < m; j += nm.dj) {
                 const float4 y = sh[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
                 const float ri = rsq(dx * dx + dy * dy + dz * dz);
@@ -135,10 +176,7 @@ __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int
                 v[3] += qr3 * dz;
             }
         });
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = lane_sum(v[q], S);
-        wave_reduce<4>(v, red);
-        if (w == 0 && act && slice == 0) nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
+        if (near_finish<4>(v, nm, red)) nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
     }
 }
 
@@ -156,15 +194,13 @@ __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items,
         const int2 it = items[item];
         const int b = it.x;
         const int nt = min(64, range[b].y - it.y);
-        const int S = lanes_per_target(nt);
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int slice = lane & (S - 1);
-        const int i = it.y + lane / S;
-        const bool act = lane / S < nt;
+        const NearMap nm = near_map(it.y, nt);
+        const int i = nm.i;
+        const bool act = nm.act;
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
         stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
-            for (int j = w * S + slice; j < m; j += 4 * S) {
+            for (int j = nm.j0; j < m; j += nm.dj) {
                 const float4 y = sh[j];
                 const float4 bj = sh2[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
@@ -179,10 +215,7 @@ __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items,
                 v[3] += gh * dz + bj.w * ri3;
             }
         });
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = lane_sum(v[q], S);
-        wave_reduce<4>(v, red);
-        if (w == 0 && act && slice == 0) nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
+        if (near_finish<4>(v, nm, red)) nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
     }
 }
 
@@ -203,15 +236,13 @@ __global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items
         const int2 it = items[item];
         const int b = it.x;
         const int nt = min(64, range[b].y - it.y);
-        const int S = lanes_per_target(nt);
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int slice = lane & (S - 1);
-        const int i = it.y + lane / S;
-        const bool act = lane / S < nt;
+        const NearMap nm = near_map(it.y, nt);
+        const int i = nm.i;
+        const bool act = nm.act;
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // u, E xyz, dE/dx xx yy zz xy xz yz
         stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
-            for (int j = w * S + slice; j < m; j += 4 * S) {
+            for (int j = nm.j0; j < m; j += nm.dj) {
                 const float4 y = sh[j];
                 const float4 bj = src2 ? sh2[j] : make_float4(y.w, 0.f, 0.f, 0.f);
                 const float d[3] = {x.x - y.x, x.y - y.y, x.z - y.z};
@@ -237,10 +268,7 @@ __global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items
                 }
             }
         });
-#pragma unroll
-        for (int q = 0; q < 10; ++q) v[q] = lane_sum(v[q], S);
-        wave_reduce<10>(v, red);
-        if (w == 0 && act && slice == 0) {
+        if (near_finish<10>(v, nm, red)) {
             nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
 #pragma unroll
             for (int k = 0; k < 6; ++k) nearg[6 * size_t(i) + k] = cst * v[4 + k];
@@ -264,11 +292,9 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
         const int2 it = items[item];
         const int b = it.x;
         const int nt = min(64, range[b].y - it.y);
-        const int S = lanes_per_target(nt);
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int slice = lane & (S - 1);
-        const int i = it.y + lane / S;
-        const bool act = lane / S < nt;
+        const NearMap nm = near_map(it.y, nt);
+        const int i = nm.i;
+        const bool act = nm.act;
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         const float4 a = act ? src2[i] : make_float4(0, 0, 0, 0);
         // The adjoint combination xbar_k = -ubar_k E_k - H_k Ebar_k - q_k E_psi,k
@@ -280,7 +306,7 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
         float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         const float uk = a.x, qk = x.w;
         stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
-            for (int j = w * S + slice; j < m; j += 4 * S) {
+            for (int j = nm.j0; j < m; j += nm.dj) {
                 const float4 y = sh[j];
                 const float4 bj = sh2[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
@@ -303,10 +329,7 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
                 v[7] += bj.x * ri - rj * ri3;
             }
         });
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = lane_sum(v[q], S);
-        wave_reduce<8>(v, red);
-        if (w == 0 && act && slice == 0)
+        if (near_finish<8>(v, nm, red))
             nearv[i] = make_float4(cst * (v[0] + v[3] * a.y - qk * v[4]), cst * (v[1] + v[3] * a.z - qk * v[5]),
                                    cst * (v[2] + v[3] * a.w - qk * v[6]), cst * v[7]);
     }
