@@ -278,6 +278,7 @@ __global__ __launch_bounds__(2 * NP) void k_p2l(const int* __restrict__ xboxes, 
     __shared__ float4 sh[256];
     __shared__ float4 sh2[256];
     __shared__ float red[NP];
+    __builtin_amdgcn_s_setprio(2);   // issue ahead of the near-field waves sharing the SIMD
     const int b = xboxes[blockIdx.x];
     const int4 a = anchor[b];
     const int i = threadIdx.x % NP, slice = threadIdx.x / NP;
@@ -383,6 +384,7 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
     __shared__ uint4 lds1[WORDS];
     __shared__ unsigned vmask[6];
     __shared__ short sop[kVPerOct];   // operator index of each V slot of octant o
+    __builtin_amdgcn_s_setprio(2);   // issue ahead of the near-field waves sharing the SIMD
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
     // logical tile order (split, octant, level, parent group): the blocks an XCD
     // runs together share one window of operators and neighbouring sources
@@ -559,6 +561,7 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
                                                 const uint4* __restrict__ w1c, const uint4* __restrict__ vc) {
     constexpr int RB = NP / 16, KC = NP / 32, NR = (RB + 3) / 4;
     __shared__ v4f xa[RB][64];
+    __builtin_amdgcn_s_setprio(2);   // issue ahead of the near-field waves sharing the SIMD
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int bid = xcd_remap(blockIdx.x, nblk);
     const int g4 = 4 * (lane >> 4), g8 = 8 * (lane >> 4);
@@ -1128,6 +1131,7 @@ __global__ __launch_bounds__(256) void k_basis(int b0, int nb, const float* __re
                                                float* __restrict__ out) {
     constexpr int T = NOUT / 16, NCP = T % 2 == 0 ? 2 : 1, CPW = T / NCP;   // column parts, tiles per wave
     static_assert(NIN % 32 == 0 && NOUT % 16 == 0, "tile");
+    __builtin_amdgcn_s_setprio(2);   // issue ahead of the near-field waves sharing the SIMD
     const int item = blockIdx.x * 4 + int(threadIdx.x >> 6);
     const int g = item / NCP, cp = item % NCP;
     const int row0 = b0 + 16 * g, end = b0 + nb;
