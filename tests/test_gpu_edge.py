@@ -202,3 +202,29 @@ def test_input_errors_leave_destroyable_handles():
     G.close()
     with pytest.raises(KifmmError):
         G.evaluate(q)
+
+
+
+def test_pair_counts_follow_rebuild():
+    """The V-pair and near-field pair counts are taken on request after each
+    build: after a rebuild on other positions they are those of the new tree,
+    checked against the oracle's lists of the same positions."""
+    from paper_2512_09478_amd import Plan
+    say("pair counts after a rebuild")
+    rng = np.random.default_rng(31)
+    xa = workloads.uniform_cube(rng, 3000)
+    xb = workloads.round_f32(np.clip(workloads.clustered(rng, 3000), 0.0, np.nextafter(1.0, 0.0)))
+    root = ((0.0, 0.0, 0.0), 1.0)
+    G = Plan(torch.tensor(xa, dtype=torch.float64, device="cuda"), "laplace", 4, 16, root=root)
+    ca = G.counts()
+    G.rebuild(torch.tensor(xb, dtype=torch.float64, device="cuda"))
+    cb = G.counts()
+    O = kifmm.plan(xb, "laplace", 4, 16, True, 21, root)
+    voff, _ = O.lists.csr("V")
+    uoff, uidx = O.lists.csr("U")
+    npts = O.tree.end - O.tree.begin
+    tgt = np.repeat(np.arange(len(uoff) - 1), np.diff(uoff))
+    assert cb["v_pairs"] == int(voff[-1])
+    assert cb["p2p_pairs"] == int((npts[tgt] * npts[uidx]).sum())
+    assert cb["boxes"] == O.tree.nboxes and ca["n"] == cb["n"] == 3000
+    G.close()
