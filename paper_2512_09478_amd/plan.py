@@ -188,6 +188,9 @@ class Plan:
 
     # -- introspection
     def counts(self) -> dict:
+        """Sizes of the tree and lists.  The V-pair and near-field pair counts
+        are taken on the first call after a build (two small kernels on the
+        plan's last stream, which is then synchronised)."""
         out = (ctypes.c_int64 * 10)()
         check(_lib.lib().kifmm_get_counts(self.handle, out))
         keys = ["boxes", "leaves", "depth", "v_pairs", "p2p_pairs", "w_pairs", "x_pairs", "u_pairs", "n",
