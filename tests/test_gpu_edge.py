@@ -228,3 +228,38 @@ def test_pair_counts_follow_rebuild():
     assert cb["p2p_pairs"] == int((npts[tgt] * npts[uidx]).sum())
     assert cb["boxes"] == O.tree.nboxes and ca["n"] == cb["n"] == 3000
     G.close()
+
+
+def test_box_storage_grows_mid_build():
+    """100 pairs of points 2^-19 apart with leaf size 1: each pair is a chain of
+    single-child boxes down to the level that separates it, about 1,700 boxes
+    in all, more than the 1,024 the build first allocates.  The level that
+    overflows is redone after the storage grows; tree, lists and fields match
+    the oracle."""
+    from paper_2512_09478_amd import Plan
+    say("box storage growth during the build")
+    rng = np.random.default_rng(77)
+    a = workloads.round_f32(0.1 + 0.8 * rng.random((100, 3)))
+    b = workloads.round_f32(a + np.array([2.0 ** -19, 0.0, 0.0]))
+    x = np.concatenate([a, b])
+    q = workloads.round_f32(rng.standard_normal(200))
+    root = ((0.0, 0.0, 0.0), 1.0)
+    G = Plan(torch.tensor(x, dtype=torch.float64, device="cuda"), "laplace", 4, 1, root=root)
+    t = G.tree()
+    O = kifmm.plan(x, "laplace", 4, 1, True, 21, root)
+    assert O.tree.nboxes > 1024
+    np.testing.assert_array_equal(t["level"], O.tree.level)
+    np.testing.assert_array_equal(t["anchor"], O.tree.anchor)
+    np.testing.assert_array_equal(t["begin"], O.tree.begin)
+    np.testing.assert_array_equal(t["parent"], O.tree.parent)
+    for which in "UVWX":
+        off, idx = G.list_csr(which)
+        ooff, oidx = O.lists.csr(which)
+        np.testing.assert_array_equal(off, ooff, err_msg=which)
+        np.testing.assert_array_equal(idx, oidx, err_msg=which)
+    u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
+    uo, Eo = kifmm.forward(O, q)
+    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
+    say(f"  boxes {O.tree.nboxes}, depth {G.counts()['depth']}, rel-L2 u {eu:.3e} E {eE:.3e}")
+    assert eu <= 1e-5 and eE <= 1e-5
+    G.close()
