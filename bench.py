@@ -231,7 +231,11 @@ def short_name(name):
     return name.split("(")[0]
 
 
-def summarize_trace(db, out, cmd):
+TRACE_TITLE = ("clustered 1,048,576 charges, p = 6, leaf 128, M2L in the truncated basis (rank 116, cut-off 1e-6) "
+               "(bench step: re-tree + forward + adjoint, split-bf16 and FP32 paths)")
+
+
+def summarize_trace(db, out, cmd, title=TRACE_TITLE):
     """Per-kernel (and per grid size) duration table from a rocprofv3 database."""
     import sqlite3
     c = sqlite3.connect(db)
@@ -240,8 +244,7 @@ def summarize_trace(db, out, cmd):
                      "group by name, grid_x order by sum(duration) desc limit 40").fetchall()
     tot = c.execute("select sum(duration)/1e6 from kernels").fetchone()[0]
     with open(out, "w") as f:
-        f.write("# Kernel trace: clustered 1,048,576 charges, p = 6, leaf 128 (bench step: re-tree + forward "
-                "+ adjoint, split-bf16 and FP32 paths)\n\n")
+        f.write(f"# Kernel trace: {title}\n\n")
         f.write(f"Command (repository root on an MI355X):\n\n```\n{cmd}\n```\n\n")
         f.write(f"Total kernel time {tot:.1f} ms. Rows are per kernel and grid size (the forward and adjoint "
                 "M2L differ in grid).\n\n")
@@ -394,12 +397,14 @@ def main():
                     help="M2L in the truncated common basis of the offset operators (0: exact operators)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counter-run", metavar="PRECISION", help="short run for rocprofv3 counter passes")
-    ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT", "CMD"))
+    ap.add_argument("--summarize-trace", nargs="+", metavar="DB OUT CMD [TITLE]")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("CSV", "COUNTS_LOG", "OUT", "CMD"))
     ap.add_argument("--summarize-traffic", nargs=6,
                     metavar=("FETCH_CSV", "WRITE_CSV", "OUT", "CMD_FETCH", "CMD_WRITE", "PRECISION"))
     args = ap.parse_args()
     if args.summarize_trace:
+        if len(args.summarize_trace) not in (3, 4):
+            raise SystemExit("--summarize-trace takes DB OUT CMD [TITLE]")
         summarize_trace(*args.summarize_trace)
         return
     if args.summarize_counters:
