@@ -14,6 +14,14 @@ Follows the four steps of Section 2.2 in order:
    level 2), the upward densities of the W-list boxes and the points of the
    U-list leaves (pairs at distance zero skipped).
 
+A W/X pair links a box A and a finer box F (F in W(A), A in X(F)).  The paper
+leaves open how such a pair is evaluated; the reading used here (see
+``direct_xw``): when F is a leaf holding at most n points (n the surface
+size) the pair is summed point to point in both directions, which costs
+fewer kernel evaluations than n per point of the other box, and is exact;
+otherwise A's points go onto F's downward check surface (X) and F's upward
+density is evaluated at A's points (W).
+
 Sources carry a monopole s_j and optionally a dipole m_j (the dipole sources
 are what the adjoint needs); targets receive the potential, E = -grad and, on
 request, the Hessian of the potential.
@@ -82,6 +90,29 @@ def _lowest(P: Plan) -> int:
     """Coarsest level with far-field interactions: 2 in free space; 0 when
     periodic (the root receives the images beyond its neighbours)."""
     return 0 if P.periodic else 2
+
+
+def direct_xw(P: Plan, f: int) -> bool:
+    """Whether the W/X pairs whose finer box is ``f`` are summed point to point:
+    ``f`` is a leaf holding at most n points (the rule is symmetric, so the
+    discrete operator stays symmetric)."""
+    t = P.tree
+    return bool(t.is_leaf[f]) and int(t.end[f] - t.begin[f]) <= P.ops.n
+
+
+def near_lists(P: Plan):
+    """Point-to-point source boxes of every box: the U list, the X list when the
+    box itself is a direct finer box, and the W-list boxes that are.  Entries
+    keep their image shift.  Returns a list of lists."""
+    L = P.lists
+    near = []
+    for b in range(P.tree.nboxes):
+        row = list(L.U[b])
+        if L.X[b] and direct_xw(P, b):
+            row.extend(L.X[b])
+        row.extend(e for e in L.W[b] if direct_xw(P, decode(e)[0]))
+        near.append(row)
+    return near
 
 
 def _image(P: Plan, e):
@@ -158,8 +189,9 @@ def downward(P: Plan, s, m, phi_u, needed: np.ndarray) -> np.ndarray:
         for d, (rows, srcs) in groups.items():
             np.add.at(psi, np.array(rows), phi_u[np.array(srcs)] @ ops.m2l(l, d).T)
         # X list: source points straight onto the downward check surface
+        # (unless the pairs are summed point to point)
         for r, b in enumerate(boxes):
-            if not L.X[b]:
+            if not L.X[b] or direct_xw(P, b):
                 continue
             dc = surface(P.p, RHO_DC, t.center(b), w)
             for e in L.X[b]:
@@ -226,6 +258,8 @@ def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
             dens.append(phi_d[b])
         for e in L.W[b]:
             a, disp = _image(P, e)
+            if direct_xw(P, a):
+                continue   # summed point to point with the near field
             surf.append(surface(P.p, RHO_UE, t.center(a) + disp, ops.w(int(t.level[a]))))
             dens.append(phi_u[a])
         if not surf:
@@ -238,7 +272,10 @@ def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
         E[grp] += El
         if hess:
             H[grp] += Hl
-    uoff, uenc = L.csr("U")
+    near = near_lists(P)
+    uoff = np.zeros(len(near) + 1, dtype=np.int64)
+    uoff[1:] = np.cumsum([len(r) for r in near])
+    uenc = np.array([e for r in near for e in r], dtype=np.int64)
     uidx = np.array([decode(e)[0] for e in uenc], dtype=np.int64)
     ushift = None
     if P.periodic:

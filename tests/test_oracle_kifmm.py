@@ -231,3 +231,31 @@ def test_compressed_m2l_forward_and_adjoint():
         dq[k] = 1.0
         fd = (loss(w.charges + dq) - loss(w.charges - dq)) / 2.0
         assert abs(fd - qb[k]) <= 1e-8 * max(1.0, abs(qb[k]))
+
+
+def test_small_leaf_w_x_pairs_are_direct():
+    """A W/X pair whose finer box F is a leaf of at most n points is summed point
+    to point in both directions (the reading of the oracle's header): with
+    charges only in one X-list source A of such a leaf, the potential and field
+    at F's points are the direct sum over A's points to rounding, and with
+    charges only in F, those at A's points are (the W direction).  An expansion
+    would leave an error of order 1e-6 here."""
+    from oracle.tree import decode
+    w = workloads.make(2, n=3000)
+    P = kifmm.plan(w.positions, "laplace", 4, 16, True, 21, w.root)
+    t, L = P.tree, P.lists
+    n = P.ops.n
+    cases = [(f, decode(e)[0]) for f in range(t.nboxes) if L.X[f] and kifmm.direct_xw(P, f)
+             for e in L.X[f][:1]]
+    assert len(cases) >= 3
+    rng = np.random.default_rng(4)
+    for f, a in cases[:3]:
+        assert t.is_leaf[f] and t.end[f] - t.begin[f] <= n
+        for src, dst in ((a, f), (f, a)):
+            q = np.zeros(w.n)
+            ids = t.perm[t.begin[src]:t.end[src]]
+            q[ids] = rng.standard_normal(ids.shape[0])
+            u, E = kifmm.forward(P, q)
+            ud, Ed, _ = direct.potential_field(w.positions, q)
+            tid = t.perm[t.begin[dst]:t.end[dst]]
+            assert rel(u[tid], ud[tid]) < 1e-12 and rel(E[tid], Ed[tid]) < 1e-12
