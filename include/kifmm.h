@@ -244,7 +244,7 @@ int kifmm_clump_backward(kifmm_handle h, const float* charges, const float* fiel
 
 /*
  * Sizes of the plan (host out[10]): boxes, leaves, depth, V-list pairs,
- * near-field point pairs (P2P, self pairs included), W-list pairs, X-list
+ * near-field point pairs (over the near lists, self pairs included), W-list pairs, X-list
  * pairs, U-list leaf pairs, N, surface points n.  The two pair counts are
  * taken on the first call after a build (two small kernels on the handle's
  * last stream, which the call then synchronises), not by the build itself.
@@ -270,9 +270,15 @@ int kifmm_copy_tree(kifmm_handle h, uint64_t* keys, int64_t* perm, int32_t* leve
                     int8_t* is_leaf, double* root);
 
 /*
- * Copy one interaction list (which = 'U', 'V', 'W' or 'X') as host CSR over
- * boxes: offsets [B+1] int64, indices [pairs] int64 (source boxes, ascending
- * within a row).  Pass offsets only (indices NULL) to size the second call.
+ * Copy one interaction list (which = 'U', 'V', 'W' or 'X', or 'N' for the
+ * near list that the point-to-point pass walks) as host CSR over boxes:
+ * offsets [B+1] int64, indices [pairs] int64 (source boxes, ascending within a
+ * row of U, V, W, X; a near row is U, then X, then W entries).  A W/X pair
+ * (box A, finer box F: F in W(A), A in X(F)) is summed point to point in both
+ * directions, and so sits in the near lists of the leaves F and A, when F is
+ * a leaf holding at most n points (n the surface size); the other W/X pairs
+ * go through the expansions.  Pass offsets only (indices NULL) to size the
+ * second call.
  * Periodic plans: an entry names box (entry & (2^26 - 1)) shifted by s root
  * widths, s in {-1,0,1}^3 coded in entry >> 26 as (9 (sx+1) + 3 (sy+1) +
  * (sz+1) + 14) mod 27 (0 = unshifted, so free-space entries are plain box

@@ -424,9 +424,9 @@ int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indic
         KIFMM_HIP(hipStreamSynchronize(P->last_stream));
         const int64_t B = P->B;
         std::vector<int> off(size_t(B) + 1), idx;
-        if (which == 'U' || which == 'W' || which == 'X') {
-            const DBuf& o = which == 'U' ? P->u_off : which == 'W' ? P->w_off : P->x_off;
-            const DBuf& ix = which == 'U' ? P->u_idx : which == 'W' ? P->w_idx : P->x_idx;
+        if (which == 'U' || which == 'W' || which == 'X' || which == 'N') {
+            const DBuf& o = which == 'U' ? P->u_off : which == 'W' ? P->w_off : which == 'X' ? P->x_off : P->n_off;
+            const DBuf& ix = which == 'U' ? P->u_idx : which == 'W' ? P->w_idx : which == 'X' ? P->x_idx : P->n_idx;
             KIFMM_HIP(hipMemcpy(off.data(), o.p, off.size() * 4, hipMemcpyDeviceToHost));
             idx.resize(size_t(off[size_t(B)]));
             if (!idx.empty()) KIFMM_HIP(hipMemcpy(idx.data(), ix.p, idx.size() * 4, hipMemcpyDeviceToHost));
@@ -465,7 +465,7 @@ int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indic
                 off[size_t(b) + 1] = int(idx.size());
             }
         } else {
-            throw Error(KIFMM_ERR_ARG, "list must be one of U, V, W, X");
+            throw Error(KIFMM_ERR_ARG, "list must be one of U, V, W, X, N");
         }
         for (int64_t b = 0; b <= B; ++b) offsets[b] = off[size_t(b)];
         if (indices)

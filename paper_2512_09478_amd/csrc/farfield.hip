@@ -1461,12 +1461,12 @@ void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s
     size_t stride = size_t(P->B) * NP;
     if (bwd)
         hipLaunchKernelGGL((k_far<NP, true>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(), b2,
-                           P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->w_off.as<int>(), P->w_idx.as<int>(),
+                           P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->wf_off.as<int>(), P->wf_idx.as<int>(),
                            P->pts.as<float4>(), P->src2.as<float4>(), P->phi_d.as<float>(), P->phi_u.as<float>(),
                            stride, op.surf.as<float4>(), op.n, geo, float(P->c), P->N, fo);
     else
         hipLaunchKernelGGL((k_far<NP, false>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(), b2,
-                           P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->w_off.as<int>(), P->w_idx.as<int>(),
+                           P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->wf_off.as<int>(), P->wf_idx.as<int>(),
                            P->pts.as<float4>(), (const float4*)nullptr, P->phi_d.as<float>() + rhs * stride,
                            P->phi_u.as<float>() + rhs * stride, stride, op.surf.as<float4>(), op.n, geo, float(P->c),
                            P->N, fo);
@@ -1484,8 +1484,8 @@ void far_grad_impl(kifmm_plan* P, float* pot, float* field, float* grad, hipStre
     }
     const size_t stride = size_t(P->B) * NP;
     hipLaunchKernelGGL((k_far_grad<NP>), dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_far.as<int2>(),
-                       int(P->bfar), P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->w_off.as<int>(),
-                       P->w_idx.as<int>(), P->pts.as<float4>(), P->phi_d.as<float>() + rhs * stride,
+                       int(P->bfar), P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->wf_off.as<int>(),
+                       P->wf_idx.as<int>(), P->pts.as<float4>(), P->phi_d.as<float>() + rhs * stride,
                        P->phi_u.as<float>() + rhs * stride, op.surf.as<float4>(), op.n, geo, float(P->c), fo,
                        P->nearg.as<float>(), grad);
 }

@@ -354,27 +354,27 @@ void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const
 
 void launch_p2p_forward(kifmm_plan* P, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(), int(P->n_items),
-                       P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), P->pts.as<float4>(),
+                       P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(), P->pts.as<float4>(),
                        float(P->c), float(P->side), P->nearv.as<float4>());
 }
 
 void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p_dip, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
-                       int(P->n_items), P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(),
+                       int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
                        P->pts.as<float4>(), P->src2.as<float4>(), float(P->c), float(P->side), P->nearv.as<float4>());
 }
 
 void launch_p2p_gradient(kifmm_plan* P, bool dipoles, hipStream_t s) {
     P->nearg.ensure(size_t(P->N) * 24);
     hipLaunchKernelGGL(k_p2p_grad, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
-                       int(P->n_items), P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(),
+                       int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
                        P->pts.as<float4>(), dipoles ? P->src2.as<float4>() : nullptr, float(P->c), float(P->side),
                        P->nearv.as<float4>(), P->nearg.as<float>());
 }
 
 void launch_p2p_backward(kifmm_plan* P, hipStream_t s) {
     hipLaunchKernelGGL(k_p2p_bwd, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
-                       int(P->n_items), P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), P->pts.as<float4>(),
+                       int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(), P->pts.as<float4>(),
                        P->src2.as<float4>(), float(P->c), float(P->side), P->nearv.as<float4>());
 }
 

@@ -719,18 +719,74 @@ __global__ __launch_bounds__(64) void k_sort_rows(int B, const int* __restrict__
     }
 }
 
+// A W/X pair (box A, finer box F: F in W(A), A in X(F)) is summed point to
+// point in both directions when F is a leaf with at most n points; those
+// pairs join the U list in the near list of each leaf.
+__device__ inline bool direct_xw(int f, const int* __restrict__ leafflag, const int2* __restrict__ range, int n) {
+    const int2 r = range[f];
+    return leafflag[f] && r.y - r.x <= n;
+}
+
+// Near list of leaf b: U(b), then X(b) when b is itself such an F, then the
+// W(b) boxes that are; and the far W list: the other W(b) boxes.  One wave per
+// box, entries copied 64 at a time, the W split kept in order by ballots.
+// mode 0 counts (entry B of both count arrays is the scans' last), mode 1 fills.
+__global__ __launch_bounds__(256) void k_near(int B, int n, const int* __restrict__ leafflag,
+                                              const int2* __restrict__ range, const int* __restrict__ uoff,
+                                              const int* __restrict__ uidx, const int* __restrict__ xoff,
+                                              const int* __restrict__ xidx, const int* __restrict__ woff,
+                                              const int* __restrict__ widx, int* __restrict__ noff,
+                                              int* __restrict__ nidx, int* __restrict__ wfoff,
+                                              int* __restrict__ wfidx, int mode) {
+    const int lane = threadIdx.x & 63, b = blockIdx.x * 4 + int(threadIdx.x >> 6);
+    if (b == B && !mode && lane == 0) noff[B] = wfoff[B] = 0;
+    if (b >= B) return;   // whole wave
+    if (!leafflag[b]) {
+        if (!mode && lane == 0) noff[b] = wfoff[b] = 0;
+        return;
+    }
+    const int u0 = uoff[b], nu = uoff[b + 1] - u0;
+    const int x0 = xoff[b], nx = direct_xw(b, leafflag, range, n) ? xoff[b + 1] - x0 : 0;
+    const int w0 = woff[b], nw = woff[b + 1] - w0;
+    const uint64_t lt = lane_lt_mask();
+    int at = mode ? noff[b] : 0, atf = mode ? wfoff[b] : 0;
+    if (mode) {
+        for (int k = lane; k < nu; k += 64) nidx[at + k] = uidx[u0 + k];
+        for (int k = lane; k < nx; k += 64) nidx[at + nu + k] = xidx[x0 + k];
+    }
+    at += nu + nx;
+    for (int k0 = 0; k0 < nw; k0 += 64) {
+        const int k = k0 + lane;
+        const int e = k < nw ? widx[w0 + k] : 0;
+        const bool dir = k < nw && direct_xw(img_box(e), leafflag, range, n);
+        const bool far = k < nw && !dir;
+        const uint64_t md = __ballot(dir), mf = __ballot(far);
+        if (mode) {
+            if (dir) nidx[at + __popcll(md & lt)] = e;
+            if (far) wfidx[atf + __popcll(mf & lt)] = e;
+        }
+        at += __popcll(md);
+        atf += __popcll(mf);
+    }
+    if (!mode && lane == 0) {
+        noff[b] = at;
+        wfoff[b] = atf;
+    }
+}
+
 __global__ void k_copy_int(const int* __restrict__ a, int* __restrict__ b, int n) {
     int i = blockIdx.x * TB + threadIdx.x;
     if (i < n) b[i] = a[i];
 }
 
-__global__ void k_flags(int B, const int* __restrict__ leafflag, const int* __restrict__ xcnt, int b2,
-                        int* __restrict__ fl, int* __restrict__ fx) {
+// Leaves, and boxes that take P2L (an X list, and not summed point to point).
+__global__ void k_flags(int B, const int* __restrict__ leafflag, const int2* __restrict__ range, int n,
+                        const int* __restrict__ xcnt, int b2, int* __restrict__ fl, int* __restrict__ fx) {
     int b = blockIdx.x * TB + threadIdx.x;
     if (b == B) fl[B] = fx[B] = 0;   // the scans' last entries
     if (b >= B) return;
     fl[b] = leafflag[b];
-    fx[b] = (b >= b2 && xcnt[b + 1] > xcnt[b]) ? 1 : 0;
+    fx[b] = (b >= b2 && xcnt[b + 1] > xcnt[b] && !direct_xw(b, leafflag, range, n)) ? 1 : 0;
 }
 
 __global__ void k_compact(int B, const int* __restrict__ flag, const int* __restrict__ off, int* __restrict__ out) {
@@ -1100,13 +1156,30 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                            (int*)nullptr, P->w_idx.as<int>(), cursor, 1);
         hipLaunchKernelGGL(k_sort_rows, dim3(B), dim3(64), 0, s, B, woff, P->w_idx.as<int>());
     }
+    // near lists (U plus the W/X pairs summed point to point) and the W lists
+    // of the leaf evaluation (the other W pairs)
+    P->n_off.ensure(size_t(B + 1) * 4);
+    P->wf_off.ensure(size_t(B + 1) * 4);
+    int* noff = P->n_off.as<int>();
+    int* wfoff = P->wf_off.as<int>();
+    hipLaunchKernelGGL(k_near, dim3(nblocks(B + 1, 4)), dim3(TB), 0, s, B, P->n, P->bx_leaf.as<int>(),
+                       P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), xoff, P->x_idx.as<int>(), woff,
+                       P->w_idx.as<int>(), noff, (int*)nullptr, wfoff, (int*)nullptr, 0);
+    exclusive_scan<int>(P, noff, noff, B + 1, s);
+    exclusive_scan<int>(P, wfoff, wfoff, B + 1, s);
+    P->n_idx.ensure((ucap + 2 * xcap) * 4);
+    P->wf_idx.ensure(xcap * 4);
+    hipLaunchKernelGGL(k_near, dim3(nblocks(B + 1, 4)), dim3(TB), 0, s, B, P->n, P->bx_leaf.as<int>(),
+                       P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), xoff, P->x_idx.as<int>(), woff,
+                       P->w_idx.as<int>(), noff, P->n_idx.as<int>(), wfoff, P->wf_idx.as<int>(), 1);
     // leaf list and X-box list
     P->tmp_f.ensure(size_t(B + 1) * 4 * 4);
     int* fl = P->tmp_f.as<int>();
     int* fx = fl + (B + 1);
     int* ol = fx + (B + 1);
     int* ox = ol + (B + 1);
-    hipLaunchKernelGGL(k_flags, dim3(nblocks(B + 1)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), xoff, b2, fl, fx);
+    hipLaunchKernelGGL(k_flags, dim3(nblocks(B + 1)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->bx_range.as<int2>(),
+                       P->n, xoff, b2, fl, fx);
     exclusive_scan<int>(P, fl, ol, B + 1, s);
     exclusive_scan<int>(P, fx, ox, B + 1, s);
     int nlx[2];
@@ -1138,7 +1211,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         uint32_t* vtmp = idf + ni;
         P->tmp_c.ensure(size_t(ni) * 8);
         hipLaunchKernelGGL(k_item_fill, dim3(nblocks(nl)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
-                           P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), woff, b2, ioff, items, kn, kf, idn, idf);
+                           P->bx_range.as<int2>(), noff, P->n_idx.as<int>(), wfoff, b2, ioff, items, kn, kf, idn, idf);
         radix_sort(P, kn, idn, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
         radix_sort(P, kf, idf, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
         P->items_near.ensure(size_t(ni) * 8);
@@ -1183,7 +1256,7 @@ void count_pairs(kifmm_plan* P, hipStream_t s) {
                            int64_t(nvb) * kVPerOct, P->vdense.as<int>(), dc);
     if (B > 0)
         hipLaunchKernelGGL(k_counts, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(),
-                           P->bx_range.as<int2>(), P->u_off.as<int>(), P->u_idx.as<int>(), dc);
+                           P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(), dc);
     unsigned long long* hw = P->host.get();
     KIFMM_HIP(hipMemcpyAsync(hw, dc, 16, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipStreamSynchronize(s));

@@ -87,6 +87,10 @@ def test_tree_and_lists_bit_exact(built, k, n, leaf, p):
         ooff, oidx = O.lists.csr(which)
         np.testing.assert_array_equal(off, ooff, err_msg=which)
         np.testing.assert_array_equal(idx, oidx, err_msg=which)
+    near = kifmm.near_lists(O)
+    off, idx = G.list_csr("N")
+    np.testing.assert_array_equal(off[1:] - off[:-1], [len(r) for r in near])
+    np.testing.assert_array_equal(idx, [e for r in near for e in r])
     c = G.counts()
     assert c["v_pairs"] == len(O.lists.csr("V")[1])
     assert c["leaves"] == int(ot.is_leaf.sum()) and c["boxes"] == ot.nboxes

@@ -86,6 +86,11 @@ def test_periodic_tree_and_lists_bit_exact(built, name):
         np.testing.assert_array_equal(idx, oidx, err_msg=which)
         shifted += int(np.sum(np.asarray(idx) >= (1 << 26)))
     assert shifted > 0   # the cell's faces are crossed
+    # near lists: U plus the W/X pairs summed point to point
+    near = kifmm.near_lists(O)
+    off, idx = G.list_csr("N")
+    np.testing.assert_array_equal(off[1:] - off[:-1], [len(r) for r in near])
+    np.testing.assert_array_equal(idx, [e for r in near for e in r])
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
