@@ -839,23 +839,28 @@ __global__ void k_item_count(int nl, const int* __restrict__ leaves, const int2*
     cnt[i] = (r.y - r.x + 63) / 64;
 }
 
-__global__ void k_item_fill(int nl, const int* __restrict__ leaves, const int2* __restrict__ range,
-                            const int* __restrict__ uoff, const int* __restrict__ uidx, const int* __restrict__ woff,
-                            int b2, const int* __restrict__ off, int2* __restrict__ items,
-                            uint64_t* __restrict__ key_near, uint64_t* __restrict__ key_far,
-                            uint32_t* __restrict__ id_near, uint32_t* __restrict__ id_far) {
-    int i = blockIdx.x * TB + threadIdx.x;
-    if (i >= nl) return;
+// One wave per leaf: the lanes sum the near-list source points, then take the
+// leaf's items (up to 64 targets each) one per lane.
+__global__ __launch_bounds__(256) void k_item_fill(int nl, const int* __restrict__ leaves,
+                                                   const int2* __restrict__ range, const int* __restrict__ uoff,
+                                                   const int* __restrict__ uidx, const int* __restrict__ woff, int b2,
+                                                   const int* __restrict__ off, int2* __restrict__ items,
+                                                   uint64_t* __restrict__ key_near, uint64_t* __restrict__ key_far,
+                                                   uint32_t* __restrict__ id_near, uint32_t* __restrict__ id_far) {
+    const int lane = threadIdx.x & 63, i = blockIdx.x * 4 + int(threadIdx.x >> 6);
+    if (i >= nl) return;   // whole wave
     const int b = leaves[i];
     const int2 r = range[b];
     unsigned long long src = 0;
-    for (int k = uoff[b]; k < uoff[b + 1]; ++k) {
-        int2 ra = range[img_box(uidx[k])];
+    for (int k = uoff[b] + lane; k < uoff[b + 1]; k += 64) {
+        const int2 ra = range[img_box(uidx[k])];
         src += ra.y - ra.x;
     }
+    for (int o = 32; o >= 1; o >>= 1) src += __shfl_xor(src, o, 64);
     const unsigned long long nfar = (b >= b2 ? 1 : 0) + (woff[b + 1] - woff[b]);
-    for (int c = 0, at = off[i]; r.x + 64 * c < r.y; ++c, ++at) {
-        const int t0 = r.x + 64 * c;
+    const int nitem = (r.y - r.x + 63) / 64;
+    for (int c = lane; c < nitem; c += 64) {
+        const int at = off[i] + c, t0 = r.x + 64 * c;
         const unsigned long long nt = min(64, r.y - t0);
         items[at] = make_int2(b, t0);
         const unsigned long long cn = nt * src, cf = nt * nfar * 64;
@@ -1210,7 +1215,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         uint32_t* idf = idn + ni;
         uint32_t* vtmp = idf + ni;
         P->tmp_c.ensure(size_t(ni) * 8);
-        hipLaunchKernelGGL(k_item_fill, dim3(nblocks(nl)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
+        hipLaunchKernelGGL(k_item_fill, dim3(nblocks(nl, 4)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
                            P->bx_range.as<int2>(), noff, P->n_idx.as<int>(), wfoff, b2, ioff, items, kn, kf, idn, idf);
         radix_sort(P, kn, idn, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
         radix_sort(P, kf, idf, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
