@@ -55,6 +55,9 @@ CASES = [
     (2, 12000, 48, 6),
     (4, 9000, 32, 6),
     (5, 12000, 64, 8),
+    # leaves of up to 64 points against 56 surface points: W/X pairs of both
+    # kinds (point to point for leaves of at most 56 points, expansions above)
+    (2, 8000, 64, 4),
 ]
 
 
