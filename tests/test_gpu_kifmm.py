@@ -153,6 +153,25 @@ def test_compressed_m2l_backward_parity(built, precision):
     assert eq <= TOL[precision] and ex <= TOL[precision]
 
 
+def test_backward_parity_mixed_w_x(built):
+    """The adjoint on a tree whose W/X pairs take both paths (p = 4, leaves of
+    up to 64 points against 56 surface points)."""
+    say("backward parity, W/X pairs of both kinds")
+    w = workloads.make(2, n=8000)
+    G = gpu_plan(w, 64, "fp32", p=4)
+    rng = np.random.default_rng(21)
+    ub = workloads.round_f32(rng.standard_normal(w.n))
+    Eb = workloads.round_f32(rng.standard_normal((w.n, 3)))
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    gq, gx = G.backward(q, torch.tensor(ub, dtype=torch.float32, device="cuda"),
+                        torch.tensor(Eb, dtype=torch.float32, device="cuda"))
+    O = oracle_plan(w, 64, 4)
+    qo, xo = kifmm.vjp(O, w.charges, ub, Eb)
+    eq, ex = rel(gq.cpu().numpy(), qo), rel(gx.cpu().numpy(), xo)
+    say(f"  rel-L2 qbar {eq:.3e}  xbar {ex:.3e}")
+    assert eq <= TOL["fp32"] and ex <= TOL["fp32"]
+
+
 def test_single_leaf_is_direct_sum(built):
     say("single leaf")
     w = workloads.make(4, n=300)
