@@ -692,9 +692,14 @@ __global__ void k_wlist(int b0, int nb, const int* __restrict__ xoff, const int*
 // smaller entries) through LDS; longer rows fall back to one lane.
 constexpr int SORT_CAP = 1024;
 
-__global__ __launch_bounds__(64) void k_sort_rows(int B, const int* __restrict__ off, int* __restrict__ idx) {
+// blockIdx.y picks one of up to three lists (offsets, entries), sorted in one launch.
+__global__ __launch_bounds__(64) void k_sort_rows(int B, const int* __restrict__ off0, int* __restrict__ idx0,
+                                                  const int* __restrict__ off1, int* __restrict__ idx1,
+                                                  const int* __restrict__ off2, int* __restrict__ idx2) {
     __shared__ int v[SORT_CAP];
     const int b = blockIdx.x;
+    const int* off = blockIdx.y == 0 ? off0 : blockIdx.y == 1 ? off1 : off2;
+    int* idx = blockIdx.y == 0 ? idx0 : blockIdx.y == 1 ? idx1 : idx2;
     const int s = off[b], e = off[b + 1], len = e - s;
     if (len <= 1) return;
     if (len <= SORT_CAP) {
@@ -1125,7 +1130,6 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
                            P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
                            P->x_idx.as<int>(), 1);
-        hipLaunchKernelGGL(k_sort_rows, dim3(B), dim3(64), 0, s, B, xoff, P->x_idx.as<int>());
     }
     // U lists
     P->u_off.ensure(size_t(B + 1) * 4);
@@ -1145,7 +1149,6 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                        P->cal.as<int>(), uoff, P->u_idx.as<int>(), cursor, 1);
     hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
                        (int*)nullptr, P->u_idx.as<int>(), cursor, 1);
-    hipLaunchKernelGGL(k_sort_rows, dim3(B), dim3(64), 0, s, B, uoff, P->u_idx.as<int>());
     // W lists = transpose of X
     P->w_off.ensure(size_t(B + 1) * 4);
     int* woff = P->w_off.as<int>();
@@ -1159,8 +1162,10 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         hipLaunchKernelGGL(k_copy_int, dim3(nblocks(B + 1)), dim3(TB), 0, s, woff, cursor, B + 1);
         hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(),
                            (int*)nullptr, P->w_idx.as<int>(), cursor, 1);
-        hipLaunchKernelGGL(k_sort_rows, dim3(B), dim3(64), 0, s, B, woff, P->w_idx.as<int>());
     }
+    // every row of X, U and W ascending (U and W were filled through atomics)
+    hipLaunchKernelGGL(k_sort_rows, dim3(B, 3), dim3(64), 0, s, B, xoff, P->x_idx.as<int>(), uoff,
+                       P->u_idx.as<int>(), woff, P->w_idx.as<int>());
     // near lists (U plus the W/X pairs summed point to point) and the W lists
     // of the leaf evaluation (the other W pairs)
     P->n_off.ensure(size_t(B + 1) * 4);
