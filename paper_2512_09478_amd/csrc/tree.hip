@@ -426,37 +426,48 @@ __global__ void k_split(const int* __restrict__ front, int nf, int l, const uint
     }
 }
 
+// Eight lanes per front box, lane o writing child octant o: a child's index
+// and its place in the non-leaf list are the counts of the non-empty (and
+// non-leaf) octants below it, so the children keep the octant order.
 __global__ void k_emit(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
                        const int* __restrict__ bounds, const unsigned long long* __restrict__ off,
                        int child_start, int nl_base,
                        int4* __restrict__ anchor, int2* __restrict__ range, int* __restrict__ parent,
                        int2* __restrict__ child, int* __restrict__ leafflag, uint64_t* __restrict__ mkey,
                        int* __restrict__ nonleaf, int leaf_size, int adaptive, int max_depth, int Lu) {
-    int f = blockIdx.x * TB + threadIdx.x;
-    if (f >= nf) return;
-    int P = front[f];
-    int4 a = anchor[P];
-    const int* bd = bounds + 9 * f;
+    const int64_t gid = int64_t(blockIdx.x) * TB + threadIdx.x;
+    const int f = int(gid >> 3), o = int(gid & 7);
+    const bool act = f < nf;
+    int cnt = 0, b0 = 0, b1 = 0;
+    if (act) {
+        const int* bd = bounds + 9 * f;
+        b0 = bd[o];
+        b1 = bd[o + 1];
+        cnt = b1 - b0;
+    }
+    const bool has = act && cnt > 0;
+    const bool leaf = adaptive ? (cnt <= leaf_size || l + 1 == max_depth) : (l + 1 == Lu);
+    const bool inner = has && !leaf;
+    const int sh8 = (threadIdx.x & 63) & ~7;   // this box's 8 lanes within the wave
+    const unsigned mh = unsigned(__ballot(has) >> sh8) & 0xffu;
+    const unsigned mn = unsigned(__ballot(inner) >> sh8) & 0xffu;
+    if (!act) return;
+    const int P = front[f];
     const unsigned long long of = off[f];   // child offset | non-leaf offset << 32
-    int c = child_start + int(of & 0xffffffffull);
-    int first = c, mask = 0;
-    int nl = nl_base + int(of >> 32);
-    int shift = 3 * (kBits - (l + 1));
-    for (int o = 0; o < 8; ++o) {
-        int cnt = bd[o + 1] - bd[o];
-        if (cnt <= 0) continue;
-        mask |= 1 << o;
-        bool leaf = adaptive ? (cnt <= leaf_size || l + 1 == max_depth) : (l + 1 == Lu);
+    const int first = child_start + int(of & 0xffffffffull);
+    const unsigned below = (1u << o) - 1u;
+    if (has) {
+        const int c = first + __popc(mh & below);
+        const int4 a = anchor[P];
         anchor[c] = make_int4(2 * a.x + ((o >> 2) & 1), 2 * a.y + ((o >> 1) & 1), 2 * a.z + (o & 1), l + 1);
-        range[c] = make_int2(bd[o], bd[o + 1]);
+        range[c] = make_int2(b0, b1);
         parent[c] = P;
         child[c] = make_int2(-1, 0);
         leafflag[c] = leaf ? 1 : 0;
-        mkey[c] = keys[bd[o]] >> shift;
-        if (!leaf) nonleaf[nl++] = c;
-        ++c;
+        mkey[c] = keys[b0] >> (3 * (kBits - (l + 1)));
+        if (inner) nonleaf[nl_base + int(of >> 32) + __popc(mn & below)] = c;
     }
-    child[P] = make_int2(first, mask);
+    if (o == 0) child[P] = make_int2(first, int(mh));
 }
 
 __global__ void k_root(int N, int leaf, int4* anchor, int2* range, int* parent, int2* child, int* leafflag,
@@ -1065,7 +1076,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
             cap = ncap;
             front = P->nonleaf.as<int>() + cur.nl_start;
         }
-        hipLaunchKernelGGL(k_emit, dim3(nblocks(nf)), dim3(TB), 0, s, front, nf, l, keys, bounds, off,
+        hipLaunchKernelGGL(k_emit, dim3(nblocks(int64_t(nf) * 8)), dim3(TB), 0, s, front, nf, l, keys, bounds, off,
                            int(nx.start), int(nx.nl_start), P->bx_anchor.as<int4>(), P->bx_range.as<int2>(),
                            P->bx_parent.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(),
                            P->bx_mkey.as<uint64_t>(), P->nonleaf.as<int>(), P->leaf, o.adaptive, o.max_depth, Lu);
