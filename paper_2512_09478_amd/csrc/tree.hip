@@ -670,27 +670,29 @@ __global__ __launch_bounds__(256) void k_ulist_own(int B, const int* __restrict_
 }
 
 // U(b) finer part: every leaf A lists b in cal[A]  ->  A in U(b) (an image
-// of b seen from A is A seen from b with the shift negated).
-__global__ void k_ulist_fine(int B, const int* __restrict__ leafflag, const int* __restrict__ cal,
-                             int* __restrict__ cnt, int* __restrict__ idx, int* __restrict__ cursor, int mode) {
-    int a = blockIdx.x * TB + threadIdx.x;
-    if (a >= B || a == 0 || !leafflag[a]) return;   // a root leaf has no coarse adjacent leaves
-    for (int k = 0; k < 26; ++k) {
-        int e = cal[26 * int64_t(a) + k];
-        if (e < 0) break;
-        const int b = img_box(e);
-        if (mode) idx[atomicAdd(&cursor[b], 1)] = img_flip((e & ~kBoxMask) | a);
-        else atomicAdd(&cnt[b], 1);
-    }
+// of b seen from A is A seen from b with the shift negated).  One wave per
+// leaf A, one lane per cal entry (the row sort undoes the atomics' order).
+__global__ __launch_bounds__(256) void k_ulist_fine(int B, const int* __restrict__ leafflag,
+                                                    const int* __restrict__ cal, int* __restrict__ cnt,
+                                                    int* __restrict__ idx, int* __restrict__ cursor, int mode) {
+    const int lane = threadIdx.x & 63, a = blockIdx.x * 4 + int(threadIdx.x >> 6);
+    if (a >= B || a == 0 || !leafflag[a] || lane >= 26) return;   // a root leaf has no coarse adjacent leaves
+    const int e = cal[26 * int64_t(a) + lane];
+    if (e < 0) return;   // the row ends at its first -1
+    const int b = img_box(e);
+    if (mode) idx[atomicAdd(&cursor[b], 1)] = img_flip((e & ~kBoxMask) | a);
+    else atomicAdd(&cnt[b], 1);
 }
 
-// W(b) = {A : b in X(A)}.
-__global__ void k_wlist(int b0, int nb, const int* __restrict__ xoff, const int* __restrict__ xidx,
-                        int* __restrict__ cnt, int* __restrict__ idx, int* __restrict__ cursor, int mode) {
-    int i = blockIdx.x * TB + threadIdx.x;
+// W(b) = {A : b in X(A)}.  One wave per box A, one lane per X(A) entry (the
+// order the atomics give is undone by the row sort).
+__global__ __launch_bounds__(256) void k_wlist(int b0, int nb, const int* __restrict__ xoff,
+                                               const int* __restrict__ xidx, int* __restrict__ cnt,
+                                               int* __restrict__ idx, int* __restrict__ cursor, int mode) {
+    const int lane = threadIdx.x & 63, i = blockIdx.x * 4 + int(threadIdx.x >> 6);
     if (i >= nb) return;
-    int A = b0 + i;
-    for (int k = xoff[A]; k < xoff[A + 1]; ++k) {
+    const int A = b0 + i;
+    for (int k = xoff[A] + lane; k < xoff[A + 1]; k += 64) {
         const int e = xidx[k];
         const int b = img_box(e);
         if (mode) idx[atomicAdd(&cursor[b], 1)] = img_flip((e & ~kBoxMask) | A);
@@ -1152,26 +1154,26 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     KIFMM_HIP(hipMemsetAsync(fcnt, 0, size_t(B + 1) * 4, s));
     hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
                        P->cal.as<int>(), uoff, (int*)nullptr, (int*)nullptr, 0);
-    hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
+    hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
                        uoff, (int*)nullptr, (int*)nullptr, 0);
     exclusive_scan<int>(P, uoff, uoff, B + 1, s);
     P->u_idx.ensure(ucap * 4);
     hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
                        P->cal.as<int>(), uoff, P->u_idx.as<int>(), cursor, 1);
-    hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
+    hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
                        (int*)nullptr, P->u_idx.as<int>(), cursor, 1);
     // W lists = transpose of X
     P->w_off.ensure(size_t(B + 1) * 4);
     int* woff = P->w_off.as<int>();
     KIFMM_HIP(hipMemsetAsync(woff, 0, size_t(B + 1) * 4, s));
     if (nvb > 0)
-        hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(), woff,
+        hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(), woff,
                            (int*)nullptr, (int*)nullptr, 0);
     exclusive_scan<int>(P, woff, woff, B + 1, s);
     P->w_idx.ensure(xcap * 4);
     if (nvb > 0) {
         hipLaunchKernelGGL(k_copy_int, dim3(nblocks(B + 1)), dim3(TB), 0, s, woff, cursor, B + 1);
-        hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(),
+        hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(),
                            (int*)nullptr, P->w_idx.as<int>(), cursor, 1);
     }
     // every row of X, U and W ascending (U and W were filled through atomics)
