@@ -290,8 +290,7 @@ int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indic
  * Per-phase device times in ms of the last evaluate/backward (host out[n]):
  * 0 P2M, 1 upward M2M+UC2E (and, with opts.m2l_rtol, the projection onto
  * the M2L basis), 2 P2L, 3 M2L, 4 L2L+DC2E (and the expansion out of the M2L
- * basis; with opts.m2l_rtol P2L runs after the M2L and is counted here, phase
- * 2 being empty), 5 L2P+M2P (with the
+ * basis), 5 L2P+M2P (with the
  * final combination), 6 P2P (on the near-field stream, concurrent with 0-4),
  * 7 whole call.  Needs opts.profile = 1; returns the number written.
  */

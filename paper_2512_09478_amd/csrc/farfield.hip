@@ -1405,41 +1405,25 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
     if (P->cm)
         for (int r = r0; r < r1; ++r) project_expand<NP>(P, true, r, s);
     if (rec) record_phase(P, 1, s);
-    // downward check potentials: zero, X list.  The exact M2L starts from the
-    // X-list part, so P2L goes first; the compressed M2L writes k-space
-    // partials only, so P2L follows it (and no longer shares the GPU with the
-    // near field, which by then has mostly finished).
-    auto zero_and_p2l = [&]() {
-        for (int r = r0; r < r1; ++r) {
-            float* psi_d = P->psi_d.as<float>() + r * stride;
-            size_t nz = size_t(B - b2) * NP;
-            hipLaunchKernelGGL(k_fill0, dim3(unsigned((nz + 255) / 256)), dim3(256), 0, s, psi_d + size_t(b2) * NP,
-                               nz);
-            if (P->n_xboxes > 0)
-                hipLaunchKernelGGL(k_p2l<NP>, dim3(unsigned(P->n_xboxes)), dim3(tpb), 0, s, P->xboxes.as<int>(),
-                                   P->x_off.as<int>(), P->x_idx.as<int>(), P->bx_anchor.as<int4>(),
-                                   P->bx_range.as<int2>(), pts, r ? P->src2.as<float4>() : nullptr, surf, op.n,
-                                   geo, psi_d);
-        }
-    };
-    auto m2l = [&]() {
-        if (r1 - r0 == 2) {
-            launch_m2l<NP>(P, 2, 0, s);
-        } else {
-            for (int r = r0; r < r1; ++r) launch_m2l<NP>(P, 1, r, s);
-        }
-    };
-    if (!P->cm) {
-        zero_and_p2l();
-        if (rec) record_phase(P, 2, s);
-        m2l();
-        if (rec) record_phase(P, 3, s);
-    } else {
-        if (rec) record_phase(P, 2, s);
-        m2l();
-        if (rec) record_phase(P, 3, s);
-        zero_and_p2l();
+    // downward check potentials: zero, X list
+    for (int r = r0; r < r1; ++r) {
+        float* psi_d = P->psi_d.as<float>() + r * stride;
+        size_t nz = size_t(B - b2) * NP;
+        hipLaunchKernelGGL(k_fill0, dim3(unsigned((nz + 255) / 256)), dim3(256), 0, s, psi_d + size_t(b2) * NP, nz);
+        if (P->n_xboxes > 0)
+            hipLaunchKernelGGL(k_p2l<NP>, dim3(unsigned(P->n_xboxes)), dim3(tpb), 0, s, P->xboxes.as<int>(),
+                               P->x_off.as<int>(), P->x_idx.as<int>(), P->bx_anchor.as<int4>(),
+                               P->bx_range.as<int2>(), pts, r ? P->src2.as<float4>() : nullptr, surf, op.n, geo,
+                               psi_d);
     }
+    if (rec) record_phase(P, 2, s);
+    // V list
+    if (r1 - r0 == 2) {
+        launch_m2l<NP>(P, 2, 0, s);
+    } else {
+        for (int r = r0; r < r1; ++r) launch_m2l<NP>(P, 1, r, s);
+    }
+    if (rec) record_phase(P, 3, s);
     // compressed M2L: its results back on the check surfaces, added to the X
     // list (timed with the downward pass)
     if (P->cm)
