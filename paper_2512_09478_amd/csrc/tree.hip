@@ -848,12 +848,16 @@ __global__ void k_counts(int B, const int* __restrict__ leafflag, const int2* __
 
 // Leaf work items of at most 64 targets, with cost estimates for ordering
 // the near-field and leaf-evaluation launches heaviest first.
-__global__ void k_item_count(int nl, const int* __restrict__ leaves, const int2* __restrict__ range,
-                             int* __restrict__ cnt) {
-    int i = blockIdx.x * TB + threadIdx.x;
-    if (i == nl) cnt[nl] = 0;   // the scan's last entry
-    if (i >= nl) return;
-    int2 r = range[leaves[i]];
+__global__ void k_item_count(int B, const int* __restrict__ nl_dev, const int* __restrict__ leaves,
+                             const int2* __restrict__ range, int* __restrict__ cnt) {
+    // entries nl .. B are zero, so that a scan of B + 1 entries ends with the total
+    const int i = blockIdx.x * TB + threadIdx.x;
+    if (i > B) return;
+    if (i >= *nl_dev) {
+        cnt[i] = 0;
+        return;
+    }
+    const int2 r = range[leaves[i]];
     cnt[i] = (r.y - r.x + 63) / 64;
 }
 
@@ -1205,25 +1209,32 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                        P->n, xoff, b2, fl, fx);
     exclusive_scan<int>(P, fl, ol, B + 1, s);
     exclusive_scan<int>(P, fx, ox, B + 1, s);
-    int nlx[2];
-    read_ints(P, s, {ol + B, ox + B}, nlx);
-    const int nl = nlx[0], nxb = nlx[1];
-    P->nleaves = nl;
-    P->n_xboxes = nxb;
-    P->leaves.ensure(size_t(std::max(nl, 1)) * 4);
-    P->xboxes.ensure(size_t(std::max(nxb, 1)) * 4);
+    // the leaf and X-box lists are sized by B, so that every size of the build
+    // is read back once, below
+    P->leaves.ensure(size_t(B) * 4);
+    P->xboxes.ensure(size_t(B) * 4);
     hipLaunchKernelGGL(k_compact, dim3(nblocks(B)), dim3(TB), 0, s, B, fl, ol, P->leaves.as<int>());
     hipLaunchKernelGGL(k_compact, dim3(nblocks(B)), dim3(TB), 0, s, B, fx, ox, P->xboxes.as<int>());
+    // work items per leaf (at most 64 targets each)
+    P->tmp_a.ensure(size_t(B + 1) * 8 + 64);
+    int* icnt = P->tmp_a.as<int>();
+    int* ioff = icnt + (B + 1);
+    hipLaunchKernelGGL(k_item_count, dim3(nblocks(B + 1)), dim3(TB), 0, s, B, ol + B, P->leaves.as<int>(),
+                       P->bx_range.as<int2>(), icnt);
+    exclusive_scan<int>(P, icnt, ioff, B + 1, s);
+    // sizes: leaves, X boxes, items, the input flags, list lengths X, U, W
+    int hs[7];
+    read_ints(P, s, {ol + B, ox + B, ioff + B, bad, xoff + B, uoff + B, woff + B}, hs);
+    const int nl = hs[0], nxb = hs[1], ni = hs[2], hbad = hs[3], nx = hs[4], nu = hs[5], nw = hs[6];
+    if (hbad & 1)
+        throw Error(KIFMM_ERR_INPUT, o.explicit_root ? "non-finite position or point outside the explicit root"
+                                                     : "non-finite position");
+    if (hbad & 2) throw Error(KIFMM_ERR_STATE, "more than 26 coarse adjacent leaves");
+    P->nleaves = nl;
+    P->n_xboxes = nxb;
+    P->n_items = ni;
     // leaf work items, heaviest first
     {
-        P->tmp_a.ensure(size_t(nl + 1) * 8 + 64);
-        int* icnt = P->tmp_a.as<int>();
-        int* ioff = icnt + (nl + 1);
-        hipLaunchKernelGGL(k_item_count, dim3(nblocks(nl + 1)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
-                           P->bx_range.as<int2>(), icnt);
-        exclusive_scan<int>(P, icnt, ioff, nl + 1, s);
-        int ni = read_int(P, ioff + nl, s);
-        P->n_items = ni;
         P->item_tmp.ensure(size_t(ni) * (8 + 8 + 8 + 4 + 4 + 4 + 4) + 1024);
         char* base = P->item_tmp.as<char>();
         int2* items = reinterpret_cast<int2*>(base);
@@ -1243,19 +1254,6 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                            P->items_near.as<int2>(), P->items_far.as<int2>());
     }
     // counts (the pair counts are taken on request: count_pairs)
-    unsigned long long* hw = P->host.get();
-    KIFMM_HIP(hipMemcpyAsync(hw + 2, bad, 4, hipMemcpyDeviceToHost, s));
-    int* hl = reinterpret_cast<int*>(hw + 3);   // list sizes: X, U, W
-    KIFMM_HIP(hipMemcpyAsync(hl, xoff + B, 4, hipMemcpyDeviceToHost, s));
-    KIFMM_HIP(hipMemcpyAsync(hl + 1, uoff + B, 4, hipMemcpyDeviceToHost, s));
-    KIFMM_HIP(hipMemcpyAsync(hl + 2, woff + B, 4, hipMemcpyDeviceToHost, s));
-    KIFMM_HIP(hipStreamSynchronize(s));
-    const int hbad = int(hw[2] & 0xffffffffull);
-    const int nx = hl[0], nu = hl[1], nw = hl[2];
-    if (hbad & 1)
-        throw Error(KIFMM_ERR_INPUT, o.explicit_root ? "non-finite position or point outside the explicit root"
-                                                     : "non-finite position");
-    if (hbad & 2) throw Error(KIFMM_ERR_STATE, "more than 26 coarse adjacent leaves");
     P->counts[0] = B;
     P->counts[1] = nl;
     P->counts[2] = P->depth;
