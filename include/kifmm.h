@@ -21,8 +21,10 @@
  *    comment says "host".  Arrays are dense, row-major, in the caller's point
  *    order: positions [N][3] double, charges [N] float, field [N][3] float.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *    kifmm_setup* synchronises that stream (tree sizes are read back); all
- *    other calls are asynchronous on it.  kifmm_evaluate and kifmm_backward
+ *    kifmm_setup*, kifmm_rebuild and kifmm_set_clumps synchronise that
+ *    stream (sizes and offsets are read back), as do the query and copy
+ *    calls and kifmm_synchronize; the evaluation, adjoint and clump calls
+ *    are asynchronous on it.  kifmm_evaluate and kifmm_backward
  *    run the near field on a second stream owned by the handle, forked from
  *    and joined back to `stream` with events, so their results are ordered
  *    on `stream` as if everything ran there.  One handle must not be used
@@ -209,15 +211,18 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
 /*
  * Clump aggregation (Section 2.4): pebble forces F_k = q_k E_k are summed
  * per clump, F_c = sum F_k and T_c = sum (x_k - X_c) x F_k, in FP64, over the
- * pebbles of each clump in caller order (deterministic).
+ * pebbles of each clump (a segmented reduction in a fixed order: a
+ * deterministic result equal to the caller-order sum up to FP64 rounding).
  *   charges        device [N] float, field device [N][3] float (from
  *                  kifmm_evaluate), both caller order.
  *   clump_offsets  device [C+1] int64, CSR over caller order, offsets[0] = 0,
- *                  non-decreasing, offsets[C] <= N (else KIFMM_ERR_INPUT,
- *                  detected on the host after a copy of the offsets).
+ *                  non-decreasing, offsets[C] <= N.  Checked on the device:
+ *                  a clump whose row is not valid gets NaN force and torque,
+ *                  and the next kifmm_synchronize returns KIFMM_ERR_INPUT.
  *   centers        device [C][3] double, the reference point X_c of each clump.
  *   force, torque  device [C][3] double.
- * The pebble positions are the plan's.
+ * The pebble positions are the plan's.  Asynchronous; the first call on a
+ * plan allocates its partial-sum buffer (16 bytes per pebble or less).
  */
 int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field,
                        const int64_t* clump_offsets, int64_t C, const double* centers,
@@ -230,17 +235,69 @@ int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field,
  *   grad_field[k]     = q_k (dL/dF_c + dL/dT_c x r_k)
  *   grad_positions[k] = q_k (E_k x dL/dT_c)
  *   grad_centers[c]   = - sum_{k in c} grad_positions[k]
- * Arguments as for kifmm_clump_reduce; grad_force, grad_torque: device [C][3]
- * double (either may be NULL = 0); grad_charges [N] float, grad_field [N][3]
- * float, grad_positions [N][3] float, grad_centers [C][3] double (each may be
- * NULL).  These are the direct parts: the charge and position gradients of
- * the whole map (q, x) -> (F_c, T_c) add kifmm_backward with grad_field as its
- * dL/dE.  Pebbles after offsets[C] get zeros.  FP64 arithmetic, caller order.
+ * Arguments as for kifmm_clump_reduce (offsets checked the same way);
+ * grad_force, grad_torque: device [C][3] double (either may be NULL = 0);
+ * grad_charges [N] float, grad_field [N][3] float, grad_positions [N][3]
+ * float, grad_centers [C][3] double (each may be NULL).  These are the direct
+ * parts: the charge and position gradients of the whole map (q, x) ->
+ * (F_c, T_c) add kifmm_backward with grad_field as its dL/dE.  Pebbles outside
+ * every clump get zeros.  FP64 arithmetic; asynchronous.
  */
 int kifmm_clump_backward(kifmm_handle h, const float* charges, const float* field,
                          const int64_t* clump_offsets, int64_t C, const double* centers,
                          const double* grad_force, const double* grad_torque, float* grad_charges,
                          float* grad_field, float* grad_positions, double* grad_centers, void* stream);
+
+/*
+ * Register the rigid clumps of Section 2.4 with the plan: clump c is the
+ * caller-order points [clump_offsets[c], clump_offsets[c+1]) (device [C+1]
+ * int64, offsets[0] = 0, non-decreasing, offsets[C] <= N; points after
+ * offsets[C] belong to no clump).  The offsets are copied and checked here
+ * (KIFMM_ERR_INPUT), so the clump calls below neither copy nor check them.
+ * The membership stays with the plan through kifmm_rebuild; C = 0 removes it.
+ * Synchronises `stream`.
+ */
+int kifmm_set_clumps(kifmm_handle h, const int64_t* clump_offsets, int64_t C, void* stream);
+
+/*
+ * Force and torque on every registered clump (Section 2.4): one evaluation of
+ * the charges, then the FP64 aggregation of kifmm_clump_reduce.  The
+ * evaluation leaves out the point-to-point pairs of two pebbles of one clump:
+ * such a pair's forces are equal and opposite along the line joining the two
+ * pebbles, so they add nothing to F_c or T_c, and leaving them out keeps
+ * their (large, cancelling) rounding out of the sums.
+ *   charges        device [N] float, caller order.
+ *   centers        device [C][3] double (X_c).
+ *   force, torque  device [C][3] double.
+ *   field          device [N][3] float or NULL: receives the pebble fields
+ *                  the sums used (the field at each pebble without the
+ *                  point-to-point part of its own clump).
+ * Asynchronous.  Keeps the forward state for kifmm_clump_forces_backward.
+ */
+int kifmm_clump_forces(kifmm_handle h, const float* charges, const double* centers, double* force,
+                       double* torque, float* field, void* stream);
+
+/*
+ * Vector-Jacobian product of kifmm_clump_forces (tree frozen), for dL/dF_c and
+ * dL/dT_c (device [C][3] double, either may be NULL = 0), at the charges of
+ * the last kifmm_clump_forces on this handle (passed again: `charges`, the
+ * same [N] float buffer contents):
+ *   grad_charges [N] float, grad_positions [N][3] float, grad_centers [C][3]
+ *   double (each may be NULL)
+ * hold the whole gradient: the aggregation's direct parts plus the adjoint
+ * sweep of its dL/dE (the same pairs left out).  KIFMM_ERR_STATE when the last
+ * evaluation on the handle was not kifmm_clump_forces.  Asynchronous.
+ */
+int kifmm_clump_forces_backward(kifmm_handle h, const float* charges, const double* centers,
+                                const double* grad_force, const double* grad_torque, float* grad_charges,
+                                float* grad_positions, double* grad_centers, void* stream);
+
+/*
+ * Wait for the handle's work on `stream` and report input errors that
+ * asynchronous calls found on the device since the last kifmm_synchronize
+ * (invalid clump offsets: KIFMM_ERR_INPUT); clears them.
+ */
+int kifmm_synchronize(kifmm_handle h, void* stream);
 
 /*
  * Sizes of the plan (host out[10]): boxes, leaves, depth, V-list pairs,

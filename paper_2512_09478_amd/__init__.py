@@ -6,4 +6,5 @@ HIP kernels behind the C ABI in include/kifmm.h; this package is the thin
 Python binding (torch supplies device memory and streams).
 """
 from ._lib import KifmmError, lib  # noqa: F401
-from .plan import ClumpFunction, KifmmFunction, Plan, clump_reduce, kifmm  # noqa: F401
+from .plan import (ClumpForcesFunction, ClumpFunction, KifmmFunction, Plan, clump_forces,  # noqa: F401
+                   clump_reduce, kifmm)

@@ -85,7 +85,8 @@ void begin_phases(kifmm_plan* P, hipStream_t s) {
     KIFMM_HIP(hipEventRecord(P->events.ev[0], s));
 }
 
-enum NearKind { NEAR_FORWARD, NEAR_BACKWARD, NEAR_DIPOLES, NEAR_GRAD, NEAR_GRAD_DIPOLES };
+enum NearKind { NEAR_FORWARD, NEAR_BACKWARD, NEAR_DIPOLES, NEAR_GRAD, NEAR_GRAD_DIPOLES, NEAR_FORWARD_EXCL,
+                NEAR_BACKWARD_EXCL };
 
 // The near field does not depend on the far-field sweep: it runs on the side
 // stream, forked from `s` after P2M (so that the sweep's first kernel is not
@@ -98,10 +99,10 @@ void fork_near(kifmm_plan* P, NearKind kind, hipStream_t s) {
     KIFMM_HIP(hipStreamWaitEvent(t, P->nearq.fork, 0));
     const bool prof = P->opt.profile && P->events.made;
     if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[0], t));
-    if (kind == NEAR_BACKWARD) launch_p2p_backward(P, t);
+    if (kind == NEAR_BACKWARD || kind == NEAR_BACKWARD_EXCL) launch_p2p_backward(P, t, kind == NEAR_BACKWARD_EXCL);
     else if (kind == NEAR_DIPOLES) launch_p2p_dipoles(P, t);
     else if (kind == NEAR_GRAD || kind == NEAR_GRAD_DIPOLES) launch_p2p_gradient(P, kind == NEAR_GRAD_DIPOLES, t);
-    else launch_p2p_forward(P, t);
+    else launch_p2p_forward(P, t, kind == NEAR_FORWARD_EXCL);
     if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[1], t));
     KIFMM_HIP(hipEventRecord(P->nearq.join, t));
 }
@@ -169,6 +170,8 @@ int kifmm_setup_ex(const double* positions, int64_t N, int kernel, int p, int le
         P->n = P->ops->n;
         P->npad = P->ops->npad;
         P->last_stream = s;
+        P->status.ensure(sizeof(int));
+        KIFMM_HIP(hipMemsetAsync(P->status.p, 0, sizeof(int), s));
         build_tree(P, positions, s);
         alloc_densities(P, s);
         KIFMM_HIP(hipStreamSynchronize(s));
@@ -193,8 +196,10 @@ int kifmm_rebuild(kifmm_handle h, const double* positions, void* stream) {
         h->last_stream = s;
         h->B = 0;
         h->fwd_valid = false;
+        h->fwd_excl = false;
         build_tree(h, positions, s);
         alloc_densities(h, s);
+        launch_clump_ids(h, s);
         KIFMM_HIP(hipStreamSynchronize(s));
     });
 }
@@ -205,6 +210,7 @@ int kifmm_set_precision(kifmm_handle h, int precision) {
         if (precision != KIFMM_FP32 && precision != KIFMM_SPLIT_BF16) throw Error(KIFMM_ERR_ARG, "unknown precision");
         h->opt.precision = precision;
         h->fwd_valid = false;
+        h->fwd_excl = false;
     });
 }
 
@@ -216,6 +222,7 @@ int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float
         P->last_stream = s;
         begin_phases(P, s);
         P->fwd_valid = false;
+        P->fwd_excl = false;
         launch_gather(P, charges, nullptr, nullptr, false, s);
         run_sweep(P, 0, 1, s, true, [&] { fork_near(P, NEAR_FORWARD, s); });
         join_near(P, s);
@@ -239,6 +246,7 @@ int kifmm_evaluate_dipoles(kifmm_handle h, const float* charges, const float* di
         // dipoles; the sorted points' charges are overwritten, so a later
         // kifmm_backward must pass its charges
         P->fwd_valid = false;
+        P->fwd_excl = false;
         launch_gather(P, charges, charges, dipoles, true, s, true);
         run_sweep(P, 1, 2, s, true, [&] { fork_near(P, NEAR_DIPOLES, s); });
         join_near(P, s);
@@ -258,6 +266,7 @@ int kifmm_evaluate_gradient(kifmm_handle h, const float* charges, const float* d
         P->last_stream = s;
         begin_phases(P, s);
         P->fwd_valid = false;
+        P->fwd_excl = false;
         // with dipoles the sources go through right-hand side 1 (as in
         // kifmm_evaluate_dipoles), otherwise through 0
         const int rhs = dipoles ? 1 : 0;
@@ -284,7 +293,10 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
         begin_phases(P, s);
         // null charges: the charges, sorted points and densities of the last
         // forward pass are still in place and only the adjoint sources are swept
-        if (charges) P->fwd_valid = false;
+        if (charges) {
+            P->fwd_valid = false;
+            P->fwd_excl = false;
+        }
         launch_gather(P, charges, grad_potential, grad_field, true, s);
         run_sweep(P, charges ? 0 : 1, 2, s, true, [&] { fork_near(P, NEAR_BACKWARD, s); });
         P->fwd_valid = true;
@@ -298,33 +310,21 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
 
 }  // extern "C"
 
-namespace {
-// Copies the CSR offsets to the host and checks them; returns offsets[C].
-int64_t check_offsets(kifmm_plan* P, const int64_t* clump_offsets, int64_t C, hipStream_t s) {
-    std::vector<int64_t> off(size_t(C) + 1);
-    KIFMM_HIP(hipMemcpyAsync(off.data(), clump_offsets, off.size() * 8, hipMemcpyDeviceToHost, s));
-    KIFMM_HIP(hipStreamSynchronize(s));
-    if (off[0] != 0 || off[size_t(C)] > P->N) throw Error(KIFMM_ERR_INPUT, "clump offsets out of range");
-    for (int64_t c = 0; c < C; ++c)
-        if (off[size_t(c) + 1] < off[size_t(c)]) throw Error(KIFMM_ERR_INPUT, "clump offsets not monotone");
-    return off[size_t(C)];
-}
-}  // namespace
-
 extern "C" {
 
 int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field, const int64_t* clump_offsets,
                        int64_t C, const double* centers, double* force, double* torque, void* stream) {
     return guarded([&] {
         kifmm_plan* P = checked(h);
-        if (C < 0) throw Error(KIFMM_ERR_ARG, "negative clump count");
+        if (C < 0 || C >= (int64_t(1) << 31)) throw Error(KIFMM_ERR_ARG, "clump count out of range");
         if (C == 0) return;
         if (!charges || !field || !clump_offsets || !centers || !force || !torque)
             throw Error(KIFMM_ERR_ARG, "null pointer argument");
         hipStream_t s = static_cast<hipStream_t>(stream);
         P->last_stream = s;
-        check_offsets(P, clump_offsets, C, s);
-        launch_clump_reduce(P, charges, field, clump_offsets, C, centers, force, torque, s);
+        P->clump_part.ensure(clump_scratch_bytes(P->N, 6));
+        launch_clump_reduce(P, charges, field, clump_offsets, nullptr, C, centers, force, torque,
+                            P->clump_part.as<double>(), s);
         KIFMM_HIP(hipGetLastError());
     });
 }
@@ -335,15 +335,112 @@ int kifmm_clump_backward(kifmm_handle h, const float* charges, const float* fiel
                          void* stream) {
     return guarded([&] {
         kifmm_plan* P = checked(h);
-        if (C < 0) throw Error(KIFMM_ERR_ARG, "negative clump count");
+        if (C < 0 || C >= (int64_t(1) << 31)) throw Error(KIFMM_ERR_ARG, "clump count out of range");
         if (!charges || !field || (C > 0 && (!clump_offsets || !centers)))
             throw Error(KIFMM_ERR_ARG, "null pointer argument");
         hipStream_t s = static_cast<hipStream_t>(stream);
         P->last_stream = s;
-        const int64_t covered = C > 0 ? check_offsets(P, clump_offsets, C, s) : 0;
-        launch_clump_backward(P, charges, field, clump_offsets, C, covered, centers, grad_force, grad_torque,
-                              grad_charges, grad_field, grad_positions, grad_centers, s);
+        P->clump_part.ensure(clump_scratch_bytes(P->N, 6));
+        launch_clump_backward(P, charges, field, clump_offsets, nullptr, C, centers, grad_force, grad_torque,
+                              grad_charges, grad_field, grad_positions, false, C > 0 ? grad_centers : nullptr,
+                              P->clump_part.as<double>(), s);
         KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_set_clumps(kifmm_handle h, const int64_t* clump_offsets, int64_t C, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (C < 0 || C >= (int64_t(1) << 31)) throw Error(KIFMM_ERR_ARG, "clump count out of range");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        if (P->fwd_excl) P->fwd_valid = false;
+        P->fwd_excl = false;
+        P->clumps = 0;
+        if (C == 0) return;
+        if (!clump_offsets) throw Error(KIFMM_ERR_ARG, "null clump offsets");
+        std::vector<int64_t> off(size_t(C) + 1);
+        KIFMM_HIP(hipMemcpyAsync(off.data(), clump_offsets, off.size() * 8, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipStreamSynchronize(s));
+        if (off[0] != 0 || off[size_t(C)] > P->N) throw Error(KIFMM_ERR_INPUT, "clump offsets out of range");
+        for (int64_t c = 0; c < C; ++c)
+            if (off[size_t(c) + 1] < off[size_t(c)]) throw Error(KIFMM_ERR_INPUT, "clump offsets not monotone");
+        P->clump_off.ensure(off.size() * 8);
+        KIFMM_HIP(hipMemcpyAsync(P->clump_off.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
+        set_clump_ids(P, P->clump_off.as<int64_t>(), C, s);
+        P->clumps = C;
+        launch_clump_ids(P, s);
+        P->clump_part.ensure(clump_scratch_bytes(P->N, 6));
+        KIFMM_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int kifmm_clump_forces(kifmm_handle h, const float* charges, const double* centers, double* force, double* torque,
+                       float* field, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (P->clumps <= 0) throw Error(KIFMM_ERR_STATE, "no clumps registered (kifmm_set_clumps)");
+        if (!charges || !centers || !force || !torque) throw Error(KIFMM_ERR_ARG, "null pointer argument");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        begin_phases(P, s);
+        P->fwd_valid = false;
+        P->fwd_excl = false;
+        launch_gather(P, charges, nullptr, nullptr, false, s);
+        run_sweep(P, 0, 1, s, true, [&] { fork_near(P, NEAR_FORWARD_EXCL, s); });
+        join_near(P, s);
+        float* E = P->clump_E.ensure(size_t(P->N) * 12) ? P->clump_E.as<float>() : nullptr;
+        run_far_eval(P, false, nullptr, E, s);
+        record_phase(P, 6, s);
+        launch_clump_reduce(P, charges, E, P->clump_off.as<int64_t>(), P->cid.as<int>(), P->clumps, centers, force,
+                            torque, P->clump_part.as<double>(), s);
+        if (field) KIFMM_HIP(hipMemcpyAsync(field, E, size_t(P->N) * 12, hipMemcpyDeviceToDevice, s));
+        P->has_phase = P->opt.profile ? 1 : 0;
+        P->fwd_valid = true;
+        P->fwd_excl = true;
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_clump_forces_backward(kifmm_handle h, const float* charges, const double* centers,
+                                const double* grad_force, const double* grad_torque, float* grad_charges,
+                                float* grad_positions, double* grad_centers, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!P->fwd_valid || !P->fwd_excl || P->clumps <= 0)
+            throw Error(KIFMM_ERR_STATE, "no kifmm_clump_forces evaluation to differentiate");
+        if (!charges || !centers) throw Error(KIFMM_ERR_ARG, "null pointer argument");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        begin_phases(P, s);
+        float* Eb = P->clump_Eb.ensure(size_t(P->N) * 12) ? P->clump_Eb.as<float>() : nullptr;
+        // the aggregation's direct parts into the outputs, its dL/dE into Eb
+        launch_clump_backward(P, charges, P->clump_E.as<float>(), P->clump_off.as<int64_t>(), P->cid.as<int>(),
+                              P->clumps, centers, grad_force, grad_torque, grad_charges, Eb, grad_positions, false,
+                              grad_centers, P->clump_part.as<double>(), s);
+        // the FMM part for the dipole sources dL/dE (forward densities reused),
+        // the same pairs left out, added to the outputs
+        launch_gather(P, nullptr, nullptr, Eb, true, s);
+        run_sweep(P, 1, 2, s, true, [&] { fork_near(P, NEAR_BACKWARD_EXCL, s); });
+        join_near(P, s);
+        run_far_eval(P, true, grad_charges, grad_positions, s, 0, true);
+        record_phase(P, 6, s);
+        P->has_phase = P->opt.profile ? 2 : 0;
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_synchronize(kifmm_handle h, void* stream) {
+    return guarded([&] {
+        if (!h) throw Error(KIFMM_ERR_STATE, "null handle");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        unsigned long long* w = h->host.get();
+        w[63] = 0;
+        KIFMM_HIP(hipMemcpyAsync(&w[63], h->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipMemsetAsync(h->status.p, 0, sizeof(int), s));
+        KIFMM_HIP(hipStreamSynchronize(s));
+        if (static_cast<int>(w[63] & 0xffffffffull))
+            throw Error(KIFMM_ERR_INPUT, "clump offsets of an earlier call were not a valid CSR (its clumps got NaN)");
     });
 }
 

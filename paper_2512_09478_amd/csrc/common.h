@@ -275,6 +275,17 @@ struct kifmm_plan {
     float phase_ms[8] = {};
     int has_phase = 0;
     bool fwd_valid = false;   // densities of right-hand side 0 and pts hold the last forward pass
+    bool fwd_excl = false;    // ... and that pass left out the pairs of pebbles of one clump
+    // input errors found on the device (clump offsets): int word, cleared by kifmm_synchronize
+    kifmm::DBuf status;
+    // registered clumps (kifmm_set_clumps)
+    int64_t clumps = 0;
+    kifmm::DBuf clump_off;    // int64 [C+1] CSR over caller order
+    kifmm::DBuf cid;          // int32 [N] clump of each caller-order point (-1: none)
+    kifmm::DBuf cid_s;        // int32 [N] sorted clump keys (unique negative values outside clumps)
+    kifmm::DBuf clump_part;   // segment partials of the clump reductions [blocks][2][6] double
+    kifmm::DBuf clump_E;      // float [N][3] pebble fields of the last kifmm_clump_forces
+    kifmm::DBuf clump_Eb;     // float [N][3] its adjoint field sources
 };
 
 namespace kifmm {
@@ -290,7 +301,8 @@ void v_slot_offset(int o, int j, int d[3]);
 void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between);
 // leaf evaluation; adds the near-field part and writes the caller-order
 // outputs (forward: potential, field; backward: grad_charges, grad_positions)
-void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs = 0);
+void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs = 0,
+                  bool accumulate = false);
 // leaf evaluation with the field gradient (densities of right-hand side rhs)
 void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs);
 // ---- nearfield.hip
@@ -298,17 +310,28 @@ void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStrea
 // for null charges), and for `adjoint` the sorted (gpot, gfield) sources
 void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const float* gfield,
                    bool adjoint, hipStream_t s, bool points = false);
-void launch_p2p_forward(kifmm_plan* P, hipStream_t s);
-void launch_p2p_backward(kifmm_plan* P, hipStream_t s);
+// excl: pairs of points with equal sorted clump keys (cid_s) are left out
+void launch_p2p_forward(kifmm_plan* P, hipStream_t s, bool excl = false);
+void launch_p2p_backward(kifmm_plan* P, hipStream_t s, bool excl = false);
 void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s);
 // u, E and dE/dx of monopoles (pts.w, or src2.x with `dipoles`) and dipoles (src2.yzw)
 void launch_p2p_gradient(kifmm_plan* P, bool dipoles, hipStream_t s);
 // ---- clump.hip
-void launch_clump_reduce(kifmm_plan* P, const float* q, const float* E, const int64_t* off, int64_t C,
-                         const double* centers, double* F, double* T, hipStream_t s);
-void launch_clump_backward(kifmm_plan* P, const float* q, const float* E, const int64_t* off, int64_t C,
-                           int64_t covered, const double* centers, const double* Fb, const double* Tb, float* qb,
-                           float* Eb, float* xb, double* Xb, hipStream_t s);
+// Per-clump sums over the CSR offsets `off` (caller order); with `cid` (the
+// registered caller-order clump ids) the offsets are trusted, without it
+// they are checked on the device (errors into P->status).  `part` holds
+// clump_scratch_bytes(N, 6) bytes.
+void launch_clump_reduce(kifmm_plan* P, const float* q, const float* E, const int64_t* off, const int* cid, int64_t C,
+                         const double* centers, double* F, double* T, double* part, hipStream_t s);
+// `acc`: grad_charges and grad_positions are added to, not overwritten
+void launch_clump_backward(kifmm_plan* P, const float* q, const float* E, const int64_t* off, const int* cid,
+                           int64_t C, const double* centers, const double* Fb, const double* Tb, float* qb,
+                           float* Eb, float* xb, bool acc, double* Xb, double* part, hipStream_t s);
+size_t clump_scratch_bytes(int64_t N, int nv);
+// caller-order clump ids from checked device offsets
+void set_clump_ids(kifmm_plan* P, const int64_t* off_dev, int64_t C, hipStream_t s);
+// sorted clump keys for the current tree (after a build)
+void launch_clump_ids(kifmm_plan* P, hipStream_t s);
 // ---- api.cpp
 void record_phase(kifmm_plan* P, int idx, hipStream_t s);
 

@@ -732,6 +732,7 @@ struct FarOut {
     const double* mom;
     double o[3];
     double k1;
+    int acc;               // 1: outputs are added to instead of overwritten
 };
 
 // The non-harmonic part k1 |x - y|^2 of the periodic kernel summed over the
@@ -883,21 +884,22 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
         // far + near, written in caller order
         const float4 nr = out.nearv[i];
         const size_t j = size_t(out.perm[i]);
+        float oa, ob[3];
         if (!BWD) {
-            if (out.a) out.a[j] = v[0] + nr.x;
-            if (out.b) {
-                out.b[3 * j] = v[1] + nr.y;
-                out.b[3 * j + 1] = v[2] + nr.z;
-                out.b[3 * j + 2] = v[3] + nr.w;
-            }
+            oa = v[0] + nr.x;
+            ob[0] = v[1] + nr.y;
+            ob[1] = v[2] + nr.z;
+            ob[2] = v[3] + nr.w;
         } else {
-            if (out.a) out.a[j] = v[3] + nr.w;
-            if (out.b) {
-                out.b[3 * j] = v[0] + nr.x;
-                out.b[3 * j + 1] = v[1] + nr.y;
-                out.b[3 * j + 2] = v[2] + nr.z;
-            }
+            oa = v[3] + nr.w;
+            ob[0] = v[0] + nr.x;
+            ob[1] = v[1] + nr.y;
+            ob[2] = v[2] + nr.z;
         }
+        if (out.a) out.a[j] = out.acc ? out.a[j] + oa : oa;
+        if (out.b)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) out.b[3 * j + d] = out.acc ? out.b[3 * j + d] + ob[d] : ob[d];
     }
 }
 
@@ -1448,11 +1450,11 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
 }
 
 template <int NP>
-void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s, int rhs) {
+void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
     const int b2 = int(P->bfar);
-    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), out_a, out_b, nullptr, {0, 0, 0}, 0.0};
+    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), out_a, out_b, nullptr, {0, 0, 0}, 0.0, acc ? 1 : 0};
     if (P->periodic) {
         fo.mom = P->mom.as<double>() + (bwd ? 0 : 16 * rhs);
         for (int d = 0; d < 3; ++d) fo.o[d] = P->lo[d] + 0.5 * P->side;
@@ -1476,7 +1478,7 @@ template <int NP>
 void far_grad_impl(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
-    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), pot, field, nullptr, {0, 0, 0}, 0.0};
+    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), pot, field, nullptr, {0, 0, 0}, 0.0, 0};
     if (P->periodic) {
         fo.mom = P->mom.as<double>() + 16 * rhs;
         for (int d = 0; d < 3; ++d) fo.o[d] = P->lo[d] + 0.5 * P->side;
@@ -1516,14 +1518,14 @@ void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const 
     }
 }
 
-void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs) {
+void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc) {
     switch (P->npad) {
-        case 32: far_impl<32>(P, backward, out_a, out_b, s, rhs); break;
-        case 64: far_impl<64>(P, backward, out_a, out_b, s, rhs); break;
-        case 128: far_impl<128>(P, backward, out_a, out_b, s, rhs); break;
-        case 160: far_impl<160>(P, backward, out_a, out_b, s, rhs); break;
-        case 224: far_impl<224>(P, backward, out_a, out_b, s, rhs); break;
-        case 320: far_impl<320>(P, backward, out_a, out_b, s, rhs); break;
+        case 32: far_impl<32>(P, backward, out_a, out_b, s, rhs, acc); break;
+        case 64: far_impl<64>(P, backward, out_a, out_b, s, rhs, acc); break;
+        case 128: far_impl<128>(P, backward, out_a, out_b, s, rhs, acc); break;
+        case 160: far_impl<160>(P, backward, out_a, out_b, s, rhs, acc); break;
+        case 224: far_impl<224>(P, backward, out_a, out_b, s, rhs, acc); break;
+        case 320: far_impl<320>(P, backward, out_a, out_b, s, rhs, acc); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }

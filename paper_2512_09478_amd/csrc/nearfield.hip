@@ -85,11 +85,12 @@ __device__ inline float group_sum(float v, int slice, int S) {
 // Stream the points of U(b) through LDS, all four waves staging together;
 // calls body(m) after each batch of m staged points.  Block-uniform control.
 // A periodic image of a leaf is staged moved by its shift times the cell side.
+// With `ckey` the sources' clump keys are staged into shk as well.
 template <class Body>
 __device__ inline void stream_sources(const int* __restrict__ uoff, const int* __restrict__ uidx,
                                       const int2* __restrict__ range, int b, const float4* __restrict__ pts,
                                       const float4* __restrict__ src2, float cell, float4* sh, float4* sh2,
-                                      Body body) {
+                                      Body body, const int* __restrict__ ckey = nullptr, int* shk = nullptr) {
     int k = uoff[b];
     const int kend = uoff[b + 1];
     int pos = 0;
@@ -107,6 +108,7 @@ __device__ inline void stream_sources(const int* __restrict__ uoff, const int* _
                 const float4 p = pts[ra.x + pos + q];
                 sh[m + q] = make_float4(p.x + ox, p.y + oy, p.z + oz, p.w);
                 if (src2) sh2[m + q] = src2[ra.x + pos + q];
+                if (ckey) shk[m + q] = ckey[ra.x + pos + q];
             }
             m += take;
             pos += take;
@@ -146,11 +148,15 @@ __device__ inline bool near_finish(float (&v)[NV], const NearMap& m, float (*red
 }
 
 // Work item = (leaf, first target): up to 64 targets, lanes as in near_map.
+// EXCL: pairs whose clump keys (ckey, sorted) are equal are left out, which
+// drops the pairs of pebbles of one clump and the self pair.
+template <bool EXCL>
 __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int n_items, const int2* __restrict__ range,
                                              const int* __restrict__ uoff, const int* __restrict__ uidx,
                                              const float4* __restrict__ pts, float cst, float cell,
-                                             float4* __restrict__ nearv) {
+                                             float4* __restrict__ nearv, const int* __restrict__ ckey) {
     __shared__ float4 sh[NF_STAGE];
+    __shared__ int shk[EXCL ? NF_STAGE : 1];
     __shared__ float red[4][4][64];
     // the grid strides over the items (launched with one block per item)
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -161,13 +167,15 @@ __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int
         const int i = nm.i;
         const bool act = nm.act;
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
+        const int ck = (EXCL && act) ? ckey[i] : 0;
         float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
         stream_sources(uoff, uidx, range, b, pts, nullptr, cell, sh, nullptr, [&](int m) {
 #pragma unroll 4
             for (int j = nm.j0; j < m; j += nm.dj) {
                 const float4 y = sh[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
-                const float ri = rsq(dx * dx + dy * dy + dz * dz);
+                float ri = rsq(dx * dx + dy * dy + dz * dz);
+                if (EXCL) ri = shk[j] != ck ? ri : 0.f;
                 const float qr = y.w * ri;
                 const float qr3 = qr * ri * ri;
                 v[0] += qr;
@@ -175,7 +183,7 @@ __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int
                 v[2] += qr3 * dy;
                 v[3] += qr3 * dz;
             }
-        });
+        }, EXCL ? ckey : nullptr, shk);
         if (near_finish<4>(v, nm, red)) nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
     }
 }
@@ -280,12 +288,15 @@ __global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items
 //   qbar_k = psi_k,  xbar_k = -ubar_k E_k - H_k Ebar_k - q_k E_psi,k
 // where E, H come from the charges q and psi, E_psi from monopoles ubar and
 // dipoles Ebar (psi = sum ubar K - Ebar . G).
+template <bool EXCL>
 __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items, int n_items, const int2* __restrict__ range,
                                                  const int* __restrict__ uoff, const int* __restrict__ uidx,
                                                  const float4* __restrict__ pts, const float4* __restrict__ src2,
-                                                 float cst, float cell, float4* __restrict__ nearv) {
+                                                 float cst, float cell, float4* __restrict__ nearv,
+                                                 const int* __restrict__ ckey) {
     __shared__ float4 sh[NF_STAGE];
     __shared__ float4 sh2[NF_STAGE];
+    __shared__ int shk[EXCL ? NF_STAGE : 1];
     __shared__ float red[4][8][64];
     // the grid strides over the items (launched with one block per item)
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -305,12 +316,14 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
         // and xbar = X + S Ebar_k - q_k T;  qbar = psi = sum ubar_j/r - r.Ebar_j/r^3.
         float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         const float uk = a.x, qk = x.w;
+        const int ck = (EXCL && act) ? ckey[i] : 0;
         stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
             for (int j = nm.j0; j < m; j += nm.dj) {
                 const float4 y = sh[j];
                 const float4 bj = sh2[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
-                const float ri = rsq(dx * dx + dy * dy + dz * dz);
+                float ri = rsq(dx * dx + dy * dy + dz * dz);
+                if (EXCL) ri = shk[j] != ck ? ri : 0.f;
                 const float ri2 = ri * ri;
                 const float ri3 = ri2 * ri;
                 const float ri5 = ri3 * ri2;
@@ -328,7 +341,7 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
                 v[6] += bj.w * ri3;
                 v[7] += bj.x * ri - rj * ri3;
             }
-        });
+        }, EXCL ? ckey : nullptr, shk);
         if (near_finish<8>(v, nm, red))
             nearv[i] = make_float4(cst * (v[0] + v[3] * a.y - qk * v[4]), cst * (v[1] + v[3] * a.z - qk * v[5]),
                                    cst * (v[2] + v[3] * a.w - qk * v[6]), cst * v[7]);
@@ -352,10 +365,17 @@ void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const
     }
 }
 
-void launch_p2p_forward(kifmm_plan* P, hipStream_t s) {
-    hipLaunchKernelGGL(k_p2p, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(), int(P->n_items),
-                       P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(), P->pts.as<float4>(),
-                       float(P->c), float(P->side), P->nearv.as<float4>());
+void launch_p2p_forward(kifmm_plan* P, hipStream_t s, bool excl) {
+    if (excl)
+        hipLaunchKernelGGL(k_p2p<true>, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
+                           int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
+                           P->pts.as<float4>(), float(P->c), float(P->side), P->nearv.as<float4>(),
+                           (const int*)P->cid_s.as<int>());
+    else
+        hipLaunchKernelGGL(k_p2p<false>, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
+                           int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
+                           P->pts.as<float4>(), float(P->c), float(P->side), P->nearv.as<float4>(),
+                           (const int*)nullptr);
 }
 
 void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s) {
@@ -372,10 +392,17 @@ void launch_p2p_gradient(kifmm_plan* P, bool dipoles, hipStream_t s) {
                        P->nearv.as<float4>(), P->nearg.as<float>());
 }
 
-void launch_p2p_backward(kifmm_plan* P, hipStream_t s) {
-    hipLaunchKernelGGL(k_p2p_bwd, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
-                       int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(), P->pts.as<float4>(),
-                       P->src2.as<float4>(), float(P->c), float(P->side), P->nearv.as<float4>());
+void launch_p2p_backward(kifmm_plan* P, hipStream_t s, bool excl) {
+    if (excl)
+        hipLaunchKernelGGL(k_p2p_bwd<true>, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
+                           int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
+                           P->pts.as<float4>(), P->src2.as<float4>(), float(P->c), float(P->side),
+                           P->nearv.as<float4>(), (const int*)P->cid_s.as<int>());
+    else
+        hipLaunchKernelGGL(k_p2p_bwd<false>, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
+                           int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
+                           P->pts.as<float4>(), P->src2.as<float4>(), float(P->c), float(P->side),
+                           P->nearv.as<float4>(), (const int*)nullptr);
 }
 
 }  // namespace kifmm

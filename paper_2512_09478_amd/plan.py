@@ -186,6 +186,50 @@ class Plan:
                                               _ptr(Tb), _ptr(qb), _ptr(Eb), _ptr(xb), _ptr(Xb), _stream(stream)))
         return qb, Eb, xb, Xb
 
+    def set_clumps(self, offsets, stream=None):
+        """Register clumps (CSR offsets [C+1] int64 over caller order, checked
+        here) for clump_forces; they stay through rebuild."""
+        C = int(offsets.shape[0]) - 1
+        off = _need(offsets, torch.int64, (C + 1,), "offsets")
+        check(_lib.lib().kifmm_set_clumps(self.handle, _ptr(off), C, _stream(stream)))
+        self.clumps = C
+        self._fwd_token = None
+
+    def clump_forces(self, charges, centers, field=False, stream=None):
+        """Per-clump force and torque of the registered clumps, from an
+        evaluation without the point-to-point pairs inside a clump (they add
+        nothing to either); with field=True also the pebble fields used."""
+        C = getattr(self, "clumps", 0)
+        q = _need(charges, torch.float32, (self.n,), "charges")
+        cen = _need(centers, torch.float64, (C, 3), "centers")
+        F = torch.empty((C, 3), dtype=torch.float64, device=q.device)
+        T = torch.empty((C, 3), dtype=torch.float64, device=q.device)
+        E = torch.empty((self.n, 3), dtype=torch.float32, device=q.device) if field else None
+        self._fwd_token = None
+        check(_lib.lib().kifmm_clump_forces(self.handle, _ptr(q), _ptr(cen), _ptr(F), _ptr(T), _ptr(E),
+                                            _stream(stream)))
+        self._new_forward_state()
+        return (F, T, E) if field else (F, T)
+
+    def clump_forces_backward(self, charges, centers, grad_force=None, grad_torque=None, stream=None):
+        """dL/dq, dL/dx, dL/dX_c of the last clump_forces (whole gradient)."""
+        C = getattr(self, "clumps", 0)
+        q = _need(charges, torch.float32, (self.n,), "charges")
+        cen = _need(centers, torch.float64, (C, 3), "centers")
+        Fb = None if grad_force is None else _need(grad_force, torch.float64, (C, 3), "grad_force")
+        Tb = None if grad_torque is None else _need(grad_torque, torch.float64, (C, 3), "grad_torque")
+        dev = q.device
+        gq = torch.empty(self.n, dtype=torch.float32, device=dev)
+        gx = torch.empty((self.n, 3), dtype=torch.float32, device=dev)
+        gX = torch.empty((C, 3), dtype=torch.float64, device=dev)
+        check(_lib.lib().kifmm_clump_forces_backward(self.handle, _ptr(q), _ptr(cen), _ptr(Fb), _ptr(Tb), _ptr(gq),
+                                                     _ptr(gx), _ptr(gX), _stream(stream)))
+        return gq, gx, gX
+
+    def synchronize(self, stream=None):
+        """Wait for the plan's work and raise input errors found on the device."""
+        check(_lib.lib().kifmm_synchronize(self.handle, _stream(stream)))
+
     # -- introspection
     def counts(self) -> dict:
         """Sizes of the tree and lists.  The V-pair and near-field pair counts
@@ -297,3 +341,33 @@ class ClumpFunction(torch.autograd.Function):
 
 def clump_reduce(charges, field, positions, centers, plan: Plan, offsets):
     return ClumpFunction.apply(charges, field, positions, centers, plan, offsets)
+
+
+class ClumpForcesFunction(torch.autograd.Function):
+    """(charges, positions, centers) -> per-clump (force, torque) of the
+    plan's registered clumps, with the library's whole gradient as backward."""
+
+    @staticmethod
+    def forward(ctx, charges, positions, centers, plan: Plan):
+        if positions.data_ptr() != plan.positions.data_ptr():
+            raise ValueError("positions must be the tensor the plan was built from")
+        F, T = plan.clump_forces(charges, centers)
+        ctx.plan = plan
+        ctx.token = plan._fwd_token
+        ctx.save_for_backward(charges, centers)
+        return F, T
+
+    @staticmethod
+    def backward(ctx, gF, gT):
+        charges, centers = ctx.saved_tensors
+        if ctx.token is None or ctx.plan._fwd_token != ctx.token:
+            # the plan has been used since: redo the forward pass
+            ctx.plan.clump_forces(charges, centers)
+        gF = None if gF is None else gF.contiguous().double()
+        gT = None if gT is None else gT.contiguous().double()
+        gq, gx, gX = ctx.plan.clump_forces_backward(charges, centers, gF, gT)
+        return gq, gx.to(torch.float64), gX, None
+
+
+def clump_forces(charges, positions, centers, plan: Plan):
+    return ClumpForcesFunction.apply(charges, positions, centers, plan)

@@ -37,8 +37,14 @@ def test_roofline_takes_the_kernel_with_most_time_per_step():
     assert r["traffic"] is None   # nothing stored for this workload
 
 
-def test_stored_traffic_matches_current_sources():
-    # the committed profile was taken with the current M2L and P2P sources
-    for kern in ("k_m2l", "k_p2p"):
-        t = bench.stored_traffic(kern, "split_bf16", "clustered_1M_p6", 1048576)
-        assert t is not None and t > 0
+def test_stored_traffic_follows_the_sources():
+    # a stored traffic figure is reported only while the kernel's source file
+    # is the one the counters were taken with, else null
+    recs = [json.loads(l[len("traffic_json: "):]) for l in open(bench.TRAFFIC_FILE) if l.startswith("traffic_json: ")]
+    assert recs
+    for r in recs:
+        t = bench.stored_traffic(r["kernel"], r["precision"], r["workload"], r["n"])
+        if r["source_sha256_16"] == bench.source_digest(r["kernel"]):
+            assert t == r["bytes_per_launch"] and t > 0
+        else:
+            assert t is None

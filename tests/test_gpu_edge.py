@@ -7,6 +7,7 @@ import pytest
 
 import workloads
 from oracle import direct, kifmm
+from _parity import check
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -64,8 +65,8 @@ def test_coincident_points_reach_max_depth(max_depth):
     assert c["depth"] == max_depth
     P = kifmm.plan(x, "laplace", 4, 16, True, max_depth, ((0, 0, 0), 1.0))
     uo, Eo = kifmm.forward(P, q)
-    assert rel(u, uo) < 1e-5
-    assert rel(E[nc:], Eo[nc:]) < 1e-5
+    check("u", u, uo, 1e-5)
+    check("E (other points)", E[nc:], Eo[nc:], 1e-5)
     eps32 = float(np.finfo(np.float32).eps) / 2
     bound = 64 * eps32 * np.abs(uo[:nc]).max() / 2.0 ** -max_depth
     err = np.abs(E[:nc] - Eo[:nc]).max()
@@ -86,7 +87,8 @@ def test_upper_face_and_explicit_root():
     P = kifmm.plan(x, "laplace", 5, 24, True, 21, ((0, 0, 0), 1.0))
     np.testing.assert_array_equal(t["keys"], P.tree.keys)
     uo, Eo = kifmm.forward(P, q)
-    assert rel(u, uo) < 1e-5 and rel(E, Eo) < 1e-5
+    check("u", u, uo, 1e-5)
+    check("E", E, Eo, 1e-5)
 
 
 @pytest.mark.parametrize("leaf,max_depth,adaptive", [(1, 21, True), (8, 2, True), (50, 21, False), (4, 3, False)])
@@ -99,7 +101,8 @@ def test_leaf_and_depth_limits(leaf, max_depth, adaptive):
     np.testing.assert_array_equal(t["begin"], P.tree.begin)
     np.testing.assert_array_equal(t["is_leaf"], P.tree.is_leaf)
     uo, Eo = kifmm.forward(P, w.charges)
-    assert rel(u, uo) < 1e-5 and rel(E, Eo) < 1e-5
+    check("u", u, uo, 1e-5)
+    check("E", E, Eo, 1e-5)
 
 
 @pytest.mark.parametrize("p", [2, 3, 5, 7])
@@ -110,7 +113,8 @@ def test_other_orders(p):
     P = kifmm.plan(w.positions, "gravity", p, 32, True, 12, w.root)
     uo, Eo = kifmm.forward(P, w.charges)
     tol = 1e-4 if p >= 7 else 1e-5
-    assert rel(u, uo) < tol and rel(E, Eo) < tol
+    check("u", u, uo, tol)
+    check("E", E, Eo, tol)
 
 
 def test_automatic_root_and_negative_coordinates():
@@ -123,7 +127,8 @@ def test_automatic_root_and_negative_coordinates():
     t = G.tree()
     assert t["side"] == P.tree.s and np.array_equal(t["lo"], P.tree.lo)
     uo, Eo = kifmm.forward(P, q)
-    assert rel(u, uo) < 1e-5 and rel(E, Eo) < 1e-5
+    check("u", u, uo, 1e-5)
+    check("E", E, Eo, 1e-5)
 
 
 def test_rebuild_matches_fresh_setup_and_precision_switch():
@@ -145,7 +150,8 @@ def test_rebuild_matches_fresh_setup_and_precision_switch():
     u3, E3 = G.evaluate(q)
     P = kifmm.plan(x2, "laplace", 5, 32, True, 21, w.root)
     uo, Eo = kifmm.forward(P, w.charges)
-    assert rel(u3.cpu().numpy(), uo) < 1e-4 and rel(E3.cpu().numpy(), Eo) < 1e-4
+    check("u", u3, uo, 1e-4)
+    check("E", E3, Eo, 1e-4)
 
 
 def test_side_stream_and_phase_times():
@@ -163,7 +169,8 @@ def test_side_stream_and_phase_times():
     assert set(ph) >= {"m2l", "p2p", "total"} and ph["total"] > 0
     P = kifmm.plan(w.positions, "laplace", 4, 48, True, 21, w.root)
     uo, Eo = kifmm.forward(P, w.charges)
-    assert rel(u.cpu().numpy(), uo) < 1e-5 and rel(E.cpu().numpy(), Eo) < 1e-5
+    check("u", u, uo, 1e-5)
+    check("E", E, Eo, 1e-5)
 
 
 def test_input_errors_leave_destroyable_handles():
@@ -183,12 +190,31 @@ def test_input_errors_leave_destroyable_handles():
     u, E = G.evaluate(q)
     off = torch.tensor([0, 50, 40, 100], dtype=torch.int64, device="cuda")   # not monotone
     cen = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    # the clump calls check their offsets on the device: NaN for the bad
+    # clumps, the error at the next synchronisation
+    F, T = G.clump_reduce(q, E, off, cen)
     with pytest.raises(KifmmError) as ei:
-        G.clump_reduce(q, E, off, cen)
+        G.synchronize()
     assert ei.value.code == -2
+    assert torch.isnan(F[1]).all() and torch.isfinite(F[0]).all()
+    G.synchronize()   # cleared
     off = torch.tensor([0, 50, 120], dtype=torch.int64, device="cuda")      # beyond N
-    with pytest.raises(KifmmError):
-        G.clump_reduce(q, E, off, cen[:2])
+    G.clump_reduce(q, E, off, cen[:2])
+    with pytest.raises(KifmmError) as ei:
+        G.synchronize()
+    assert ei.value.code == -2
+    G.clump_backward(q, E, torch.tensor([0, 50, 40, 100], dtype=torch.int64, device="cuda"), cen,
+                     torch.ones((3, 3), dtype=torch.float64, device="cuda"))
+    with pytest.raises(KifmmError) as ei:
+        G.synchronize()
+    assert ei.value.code == -2
+    # registration checks them at once
+    with pytest.raises(KifmmError) as ei:
+        G.set_clumps(off)
+    assert ei.value.code == -2
+    with pytest.raises(KifmmError) as ei:
+        G.clump_forces(q, cen[:0])     # nothing registered
+    assert ei.value.code == -5
     # the handle still works and is destroyable
     u2, E2 = G.evaluate(q)
     assert torch.equal(u, u2)
@@ -259,7 +285,7 @@ def test_box_storage_grows_mid_build():
         np.testing.assert_array_equal(idx, oidx, err_msg=which)
     u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
     uo, Eo = kifmm.forward(O, q)
-    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
-    say(f"  boxes {O.tree.nboxes}, depth {G.counts()['depth']}, rel-L2 u {eu:.3e} E {eE:.3e}")
-    assert eu <= 1e-5 and eE <= 1e-5
+    say(f"  boxes {O.tree.nboxes}, depth {G.counts()['depth']}")
+    check("u", u, uo, 1e-5)
+    check("E", E, Eo, 1e-5)
     G.close()

@@ -13,6 +13,7 @@ import pytest
 import workloads
 from oracle import direct, kifmm
 from oracle import tree as OT
+from _parity import check, rel
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -24,10 +25,6 @@ TOL_WORKLOAD = {5: {"fp32": 1e-4, "split_bf16": 1e-4}}
 
 def tol(k, precision):
     return TOL_WORKLOAD.get(k, TOL)[precision]
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
 def say(msg):
@@ -110,9 +107,8 @@ def test_forward_parity(built, k, n, leaf, p, precision):
     torch.cuda.synchronize()
     O = oracle_plan(w, leaf, p)
     uo, Eo = kifmm.forward(O, w.charges)
-    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
-    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
-    assert eu <= tol(k, precision) and eE <= tol(k, precision)
+    check("u", u, uo, tol(k, precision))
+    check("E", E, Eo, tol(k, precision))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
@@ -130,9 +126,8 @@ def test_compressed_m2l_forward_parity(built, k, n, leaf, p, precision):
     u, E = G.evaluate(q)
     O = oracle_plan(w, leaf, p, m2l_rtol=1e-6)
     uo, Eo = kifmm.forward(O, w.charges)
-    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
-    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
-    assert eu <= tol(k, precision) and eE <= tol(k, precision)
+    check("u", u, uo, tol(k, precision))
+    check("E", E, Eo, tol(k, precision))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
@@ -148,9 +143,8 @@ def test_compressed_m2l_backward_parity(built, precision):
                         torch.tensor(Eb, dtype=torch.float32, device="cuda"))
     O = oracle_plan(w, 32, 6, m2l_rtol=1e-6)
     qo, xo = kifmm.vjp(O, w.charges, ub, Eb)
-    eq, ex = rel(gq.cpu().numpy(), qo), rel(gx.cpu().numpy(), xo)
-    say(f"  rel-L2 qbar {eq:.3e}  xbar {ex:.3e}")
-    assert eq <= TOL[precision] and ex <= TOL[precision]
+    check("qbar", gq, qo, TOL[precision])
+    check("xbar", gx, xo, TOL[precision])
 
 
 def test_backward_parity_mixed_w_x(built):
@@ -167,9 +161,8 @@ def test_backward_parity_mixed_w_x(built):
                         torch.tensor(Eb, dtype=torch.float32, device="cuda"))
     O = oracle_plan(w, 64, 4)
     qo, xo = kifmm.vjp(O, w.charges, ub, Eb)
-    eq, ex = rel(gq.cpu().numpy(), qo), rel(gx.cpu().numpy(), xo)
-    say(f"  rel-L2 qbar {eq:.3e}  xbar {ex:.3e}")
-    assert eq <= TOL["fp32"] and ex <= TOL["fp32"]
+    check("qbar", gq, qo, TOL["fp32"])
+    check("xbar", gx, xo, TOL["fp32"])
 
 
 def test_single_leaf_is_direct_sum(built):
@@ -179,7 +172,8 @@ def test_single_leaf_is_direct_sum(built):
     q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
     u, E = G.evaluate(q)
     ud, Ed, _ = direct.potential_field(w.positions, w.charges)
-    assert rel(u.cpu().numpy(), ud) < 1e-6 and rel(E.cpu().numpy(), Ed) < 1e-6
+    check("u", u, ud, 1e-6)
+    check("E", E, Ed, 1e-6)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
@@ -195,10 +189,10 @@ def test_identical_charges_far_field_dominated(built, precision):
     u, E = G.evaluate(torch.ones(w.n, dtype=torch.float32, device="cuda"))
     u, E = u.cpu().numpy(), E.cpu().numpy()
     uo, Eo = kifmm.forward(oracle_plan(w), q1)
-    eu, eE = rel(u, uo), rel(E, Eo)
+    check("u", u, uo, TOL[precision])
+    check("E", E, Eo, TOL[precision])
     ud, Ed, _ = direct.potential_field(w.positions, q1)
-    say(f"  vs oracle: u {eu:.2e} E {eE:.2e}; vs direct sum: u {rel(u, ud):.2e} E {rel(E, Ed):.2e}")
-    assert eu <= TOL[precision] and eE <= TOL[precision]
+    say(f"  vs direct sum: u {rel(u, ud):.2e} E {rel(E, Ed):.2e}")
     assert rel(u, ud) < 1e-3 and rel(E, Ed) < 1e-2
 
 
@@ -217,9 +211,9 @@ def test_dipole_forward_parity(built, precision):
     for charges, qo in ((q, w.charges), (None, None)):
         u, E = G.evaluate_dipoles(charges, md)
         uo, Eo = kifmm.forward_dipoles(O, qo, m)
-        eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
-        say(f"  charges={'yes' if charges is not None else 'no'}  rel-L2 u {eu:.3e}  E {eE:.3e}")
-        assert eu <= TOL[precision] and eE <= TOL[precision]
+        say(f"  charges={'yes' if charges is not None else 'no'}")
+        check("u", u, uo, TOL[precision])
+        check("E", E, Eo, TOL[precision])
     # the dipole pass overwrote the stored forward state: backward needs charges
     from paper_2512_09478_amd import KifmmError
     with pytest.raises(KifmmError):
@@ -227,7 +221,8 @@ def test_dipole_forward_parity(built, precision):
     # and an ordinary evaluation afterwards is unaffected
     u2, E2 = G.evaluate(q)
     uo2, Eo2 = kifmm.forward(O, w.charges)
-    assert rel(u2.cpu().numpy(), uo2) <= TOL[precision] and rel(E2.cpu().numpy(), Eo2) <= TOL[precision]
+    check("u", u2, uo2, TOL[precision])
+    check("E", E2, Eo2, TOL[precision])
 
 
 @pytest.mark.parametrize("with_charges,with_dipoles", [(True, False), (True, True), (False, True)])
@@ -244,9 +239,9 @@ def test_field_gradient_parity(built, with_charges, with_dipoles):
     u, E, Gr = G.evaluate_gradient(q, md)
     uo, Eo, Go = kifmm.forward_dipoles(O, w.charges if with_charges else None, m if with_dipoles else None,
                                        grad=True)
-    eu, eE, eG = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo), rel(Gr.cpu().numpy(), Go)
-    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}  dE/dx {eG:.3e}")
-    assert eu <= TOL["split_bf16"] and eE <= TOL["split_bf16"] and eG <= TOL["split_bf16"]
+    check("u", u, uo, TOL["split_bf16"])
+    check("E", E, Eo, TOL["split_bf16"])
+    check("dE/dx", Gr, Go, TOL["split_bf16"])
     # the potential and field equal those of the plain calls
     if with_dipoles:
         u2, E2 = G.evaluate_dipoles(q, md)
@@ -263,10 +258,9 @@ def test_field_gradient_fp32_parity(built):
     O = oracle_plan(w, 32, 6)
     u, E, Gr = G.evaluate_gradient(torch.tensor(w.charges, dtype=torch.float32, device="cuda"))
     uo, Eo, Go = kifmm.forward_dipoles(O, w.charges, None, grad=True)
-    eG = rel(Gr.cpu().numpy(), Go)
-    say(f"  rel-L2 dE/dx {eG:.3e}")
-    assert rel(u.cpu().numpy(), uo) <= TOL["fp32"] and rel(E.cpu().numpy(), Eo) <= TOL["fp32"]
-    assert eG <= TOL["fp32"]
+    check("u", u, uo, TOL["fp32"])
+    check("E", E, Eo, TOL["fp32"])
+    check("dE/dx", Gr, Go, TOL["fp32"])
 
 
 def test_deterministic_repeat(built):
@@ -292,9 +286,8 @@ def test_backward_parity(built, precision):
                         torch.tensor(Eb, dtype=torch.float32, device="cuda"))
     O = oracle_plan(w, 32, 6)
     qo, xo = kifmm.vjp(O, w.charges, ub, Eb)
-    eq, ex = rel(gq.cpu().numpy(), qo), rel(gx.cpu().numpy(), xo)
-    say(f"  rel-L2 qbar {eq:.3e}  xbar {ex:.3e}")
-    assert eq <= TOL[precision] and ex <= TOL[precision]
+    check("qbar", gq, qo, TOL[precision])
+    check("xbar", gx, xo, TOL[precision])
     # reusing the forward pass of evaluate (null charges) gives the same product
     G.evaluate(q)
     gq2, gx2 = G.backward(None, torch.tensor(ub, dtype=torch.float32, device="cuda"),
@@ -373,8 +366,157 @@ def test_clump_loss_gradient_through_fmm(built, precision):
     _, Eo = kifmm.forward(O, w.charges)
     qd, Ed, xd, Xd = clump.clump_vjp(w.positions, w.charges, Eo, w.clump_offsets, w.clump_centers, a, b)
     qf, xf = kifmm.vjp(O, w.charges, np.zeros(w.n), Ed)
-    eq = rel(q.grad.cpu().numpy(), qd + qf)
-    ex = rel(pos.grad.cpu().numpy(), xd + xf)
-    eX = rel(cen.grad.cpu().numpy(), Xd)
-    say(f"  rel-L2 dL/dq {eq:.3e} dL/dx {ex:.3e} dL/dX {eX:.3e}")
-    assert eq <= TOL[precision] and ex <= TOL[precision] and eX <= TOL[precision]
+    check("dL/dq", q.grad, qd + qf, TOL[precision])
+    check("dL/dx", pos.grad, xd + xf, TOL[precision])
+    check("dL/dX", cen.grad, Xd, TOL[precision])
+
+
+def ragged_clumps(n, seed):
+    """CSR offsets of clumps of 0 to 700 pebbles (several cross the 256-pebble
+    blocks of the reduction, a few are empty), the last pebbles in no clump."""
+    rng = np.random.default_rng(seed)
+    sizes = []
+    while sum(sizes) < n - 800:
+        sizes.append(int(rng.choice([0, 1, 3, 8, 40, 255, 256, 257, 700])))
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return off
+
+
+def test_clump_reduce_ragged_clumps(built):
+    """Clumps of every size against the oracle's caller-order FP64 sums on the
+    same GPU field: empty clumps, clumps inside one block, clumps across
+    several blocks, pebbles after the last clump."""
+    say("clump reduce, ragged clump sizes")
+    from oracle import clump
+    w = workloads.make(4, n=6000)
+    G = gpu_plan(w, 32, p=4)
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    u, E = G.evaluate(q)
+    off = ragged_clumps(w.n, 8)
+    C = len(off) - 1
+    cen = np.random.default_rng(9).random((C, 3))
+    F, T = G.clump_reduce(q, E, torch.tensor(off, device="cuda"), torch.tensor(cen, device="cuda"))
+    Eh = E.cpu().numpy().astype(np.float64)
+    qh = np.asarray(w.charges, np.float32).astype(np.float64)
+    Fo, To = clump.clump_reduce(w.positions, qh, Eh, off, cen)
+    np.testing.assert_allclose(F.cpu().numpy(), Fo, rtol=1e-12, atol=1e-12 * np.abs(Fo).max())
+    np.testing.assert_allclose(T.cpu().numpy(), To, rtol=1e-12, atol=1e-12 * np.abs(To).max())
+    rng = np.random.default_rng(10)
+    Fb, Tb = rng.standard_normal((C, 3)), rng.standard_normal((C, 3))
+    qb, Eb, xb, Xb = G.clump_backward(q, E, torch.tensor(off, device="cuda"), torch.tensor(cen, device="cuda"),
+                                      torch.tensor(Fb, device="cuda"), torch.tensor(Tb, device="cuda"))
+    qo, Eo, xo, Xo = clump.clump_vjp(w.positions, qh, Eh, off, cen, Fb, Tb)
+    for got, ref in ((qb, qo), (Eb, Eo), (xb, xo)):
+        assert rel(got.cpu().numpy(), ref) < 1e-6
+    np.testing.assert_allclose(Xb.cpu().numpy(), Xo, rtol=1e-12, atol=1e-12 * np.abs(Xo).max())
+    G.synchronize()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_clump_forces_parity(built, precision):
+    """Registered clumps: the clump forces and torques (same-clump pairs left
+    out of the near field, where they cancel) against the oracle's, which sums
+    every pebble's whole field."""
+    say(f"clump forces {precision}")
+    from oracle import clump
+    w = workloads.make(3, n=8000)
+    G = gpu_plan(w, 32, precision, p=6)
+    off = torch.tensor(w.clump_offsets, device="cuda")
+    cen = torch.tensor(w.clump_centers, device="cuda")
+    G.set_clumps(off)
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    F, T = G.clump_forces(q, cen)
+    O = oracle_plan(w, 32, 6)
+    _, Eo = kifmm.forward(O, w.charges)
+    Fo, To = clump.clump_reduce(w.positions, w.charges, Eo, w.clump_offsets, w.clump_centers)
+    check("F_c", F, Fo, TOL[precision])
+    check("T_c", T, To, TOL[precision])
+    G.synchronize()
+
+
+def same_clump_pairs_are_near(O, offsets):
+    """Whether every pair of pebbles of one clump lies in a pair of leaves of
+    the near lists (then leaving such pairs out of the near field drops every
+    same-clump pair)."""
+    t = O.tree
+    leaf_of = np.empty(O.n, dtype=np.int64)
+    for b in t.leaves():
+        leaf_of[t.begin[b]:t.end[b]] = b
+    inv = np.empty_like(t.perm)
+    inv[t.perm] = np.arange(O.n)
+    near = [set(r) for r in kifmm.near_lists(O)]
+    for c in range(len(offsets) - 1):
+        leaves = {int(leaf_of[inv[k]]) for k in range(offsets[c], offsets[c + 1])}
+        if any(a not in near[b] for a in leaves for b in leaves):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_clump_forces_gradient(built, precision):
+    """Autograd of a linear loss on the registered clumps' forces and torques
+    through clump_forces, against the oracle's clump VJP plus KIFMM VJP.  The
+    leaves (128 points) are wider than the clumps, as in the clump workload,
+    so every same-clump pair is a near-field pair, which clump_forces leaves
+    out; the same loss through evaluate + clump_reduce keeps those pairs,
+    whose adjoint terms cancel only in the sum (its error is printed)."""
+    say(f"clump forces gradient {precision}")
+    from oracle import clump
+    from paper_2512_09478_amd import clump_forces
+    w = workloads.make(3, n=8000)
+    O = oracle_plan(w, 128, 6)
+    assert same_clump_pairs_are_near(O, w.clump_offsets)
+    G = gpu_plan(w, 128, precision, p=6)
+    G.set_clumps(torch.tensor(w.clump_offsets, device="cuda"))
+    C = len(w.clump_offsets) - 1
+    rng = np.random.default_rng(34)
+    a = rng.standard_normal((C, 3))
+    b = rng.standard_normal((C, 3))
+    pos = G.positions.requires_grad_(True)
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda", requires_grad=True)
+    cen = torch.tensor(w.clump_centers, device="cuda", requires_grad=True)
+    F, T = clump_forces(q, pos, cen, G)
+    loss = (F * torch.tensor(a, device="cuda")).sum() + (T * torch.tensor(b, device="cuda")).sum()
+    loss.backward()
+    _, Eo = kifmm.forward(O, w.charges)
+    qd, Ed, xd, Xd = clump.clump_vjp(w.positions, w.charges, Eo, w.clump_offsets, w.clump_centers, a, b)
+    qf, xf = kifmm.vjp(O, w.charges, np.zeros(w.n), Ed)
+    check("dL/dq", q.grad, qd + qf, TOL[precision])
+    check("dL/dx", pos.grad, xd + xf, TOL[precision])
+    check("dL/dX", cen.grad, Xd, TOL[precision])
+    gx = pos.grad.detach().cpu().numpy()
+    # the same loss through evaluate + clump_reduce (every pair kept)
+    pos.grad = None
+    q.grad = None
+    from paper_2512_09478_amd import clump_reduce as creduce
+    from paper_2512_09478_amd import kifmm as kop
+    u, E = kop(q, pos, G)
+    F2, T2 = creduce(q, E, pos, cen.detach(), G, torch.tensor(w.clump_offsets, device="cuda"))
+    loss2 = (F2 * torch.tensor(a, device="cuda")).sum() + (T2 * torch.tensor(b, device="cuda")).sum()
+    loss2.backward()
+    say(f"  evaluate + clump_reduce: rel-L2 dL/dx {rel(pos.grad.cpu().numpy(), xd + xf):.3e} "
+        f"(clump_forces {rel(gx, xd + xf):.3e})")
+
+
+def test_clump_forces_field_leaves_out_same_clump_pairs(built):
+    """The pebble field that clump_forces sums is the plain field minus the
+    direct field of the pebble's own clump (every same-clump pair is a
+    near-field pair here)."""
+    say("clump forces field without same-clump pairs")
+    from oracle import direct
+    w = workloads.make(3, n=4000)
+    O = oracle_plan(w, 64, 4)
+    assert same_clump_pairs_are_near(O, w.clump_offsets)
+    G = gpu_plan(w, 64, "fp32", p=4)
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    _, E = G.evaluate(q)
+    G.set_clumps(torch.tensor(w.clump_offsets, device="cuda"))
+    F, T, Ex = G.clump_forces(q, torch.tensor(w.clump_centers, device="cuda"), field=True)
+    Ein = np.zeros((w.n, 3))
+    off = w.clump_offsets
+    for c in range(len(off) - 1):
+        sl = slice(off[c], off[c + 1])
+        Ein[sl] = direct.potential_field(w.positions[sl], w.charges[sl])[1]
+    _, Eo = kifmm.forward(O, w.charges)
+    check("E without own clump", Ex, Eo - Ein, TOL["fp32"])
+    check("E", E, Eo, TOL["fp32"])

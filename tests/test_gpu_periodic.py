@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workloads
+from _parity import check
 from oracle import kifmm
 from oracle import periodic as per
 
@@ -100,9 +101,8 @@ def test_periodic_forward_parity(built, name, precision):
     x, q, G, O = plans(name, precision)
     u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
     uo, Eo = kifmm.forward(O, q)
-    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
-    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
-    assert eu <= TOL[precision] and eE <= TOL[precision]
+    check("u", u.cpu().numpy(), uo, TOL[precision])
+    check("E", E.cpu().numpy(), Eo, TOL[precision])
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
@@ -115,9 +115,8 @@ def test_periodic_compressed_m2l_parity(built, precision):
     O = kifmm.plan(x, "laplace", 6, leaf, True, 21, CELL, periodic=True, m2l_rtol=1e-6)
     u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
     uo, Eo = kifmm.forward(O, q)
-    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
-    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
-    assert eu <= TOL[precision] and eE <= TOL[precision]
+    check("u", u.cpu().numpy(), uo, TOL[precision])
+    check("E", E.cpu().numpy(), Eo, TOL[precision])
 
 
 def test_periodic_matches_ewald_sum(built):
@@ -127,6 +126,7 @@ def test_periodic_matches_ewald_sum(built):
     u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
     t = np.arange(0, x.shape[0], 11)
     ue, Ee = per.ewald(x, q, 1.0, targets=t)
+    # the method's own accuracy (not parity): rel-L2 only
     eu, eE = rel(u.cpu().numpy()[t], ue), rel(E.cpu().numpy()[t], Ee)
     say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
     assert eu <= 5e-5 and eE <= 5e-5
@@ -143,9 +143,8 @@ def test_periodic_backward_parity(built, precision):
     gq, gx = G.backward(qt, torch.tensor(ub, dtype=torch.float32, device="cuda"),
                         torch.tensor(Eb, dtype=torch.float32, device="cuda"))
     qo, xo = kifmm.vjp(O, q, ub, Eb)
-    eq, ex = rel(gq.cpu().numpy(), qo), rel(gx.cpu().numpy(), xo)
-    say(f"  rel-L2 qbar {eq:.3e}  xbar {ex:.3e}")
-    assert eq <= TOL[precision] and ex <= TOL[precision]
+    check("qbar", gq, qo, TOL[precision])
+    check("xbar", gx, xo, TOL[precision])
     # reusing the forward pass gives the same product
     G.evaluate(qt)
     gq2, gx2 = G.backward(None, torch.tensor(ub, dtype=torch.float32, device="cuda"),
@@ -161,9 +160,8 @@ def test_periodic_dipoles_parity(built):
     m = workloads.round_f32(rng.standard_normal((x.shape[0], 3)) * 3e-3)
     u, E = G.evaluate_dipoles(None, torch.tensor(m, dtype=torch.float32, device="cuda"))
     uo, Eo = kifmm.forward_dipoles(O, None, m)
-    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
-    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
-    assert eu <= TOL["fp32"] and eE <= TOL["fp32"]
+    check("u", u.cpu().numpy(), uo, TOL["fp32"])
+    check("E", E.cpu().numpy(), Eo, TOL["fp32"])
 
 
 def test_periodic_field_gradient_parity(built):
@@ -174,9 +172,9 @@ def test_periodic_field_gradient_parity(built):
     u, E, Gr = G.evaluate_gradient(torch.tensor(q, dtype=torch.float32, device="cuda"),
                                    torch.tensor(m, dtype=torch.float32, device="cuda"))
     uo, Eo, Go = kifmm.forward_dipoles(O, q, m, grad=True)
-    eu, eE, eG = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo), rel(Gr.cpu().numpy(), Go)
-    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}  dE/dx {eG:.3e}")
-    assert eu <= TOL["fp32"] and eE <= TOL["fp32"] and eG <= TOL["fp32"]
+    check("u", u, uo, TOL["fp32"])
+    check("E", E, Eo, TOL["fp32"])
+    check("dE/dx", Gr, Go, TOL["fp32"])
 
 
 @pytest.mark.parametrize("n,leaf", [(20, 64), (300, 64)])
@@ -190,9 +188,9 @@ def test_periodic_shallow_trees(built, n, leaf):
     O = kifmm.plan(x, "laplace", 6, leaf, True, 21, CELL, periodic=True)
     u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
     uo, Eo = kifmm.forward(O, q)
-    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
-    say(f"  depth {G.counts()['depth']}  rel-L2 u {eu:.3e}  E {eE:.3e}")
-    assert eu <= 1e-5 and eE <= 1e-5
+    say(f"  depth {G.counts()['depth']}")
+    check("u", u.cpu().numpy(), uo, 1e-5)
+    check("E", E.cpu().numpy(), Eo, 1e-5)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
@@ -211,9 +209,8 @@ def test_periodic_uniform_tree(built, precision):
         np.testing.assert_array_equal(idx, oidx, err_msg=which)
     u, E = G.evaluate(torch.tensor(q, dtype=torch.float32, device="cuda"))
     uo, Eo = kifmm.forward(O, q)
-    eu, eE = rel(u.cpu().numpy(), uo), rel(E.cpu().numpy(), Eo)
-    say(f"  rel-L2 u {eu:.3e}  E {eE:.3e}")
-    assert eu <= TOL[precision] and eE <= TOL[precision]
+    check("u", u.cpu().numpy(), uo, TOL[precision])
+    check("E", E.cpu().numpy(), Eo, TOL[precision])
 
 
 def test_periodic_argument_errors(built):
