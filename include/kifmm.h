@@ -229,6 +229,20 @@ int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field,
                        double* force, double* torque, void* stream);
 
 /*
+ * kifmm_clump_reduce for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * the same arguments, kernels and results, but the reduction's partial sums
+ * live in a fixed device array of the library (4 MiB per device, held until
+ * the process ends) instead of a buffer of the plan, and the call allocates
+ * nothing.  Its limit is N <= 11,184,640 points (KIFMM_ERR_ARG beyond).  All
+ * calls on one device share that array: calls that overlap on one device
+ * (other streams, other handles) race and must be ordered by the caller.
+ */
+int kifmm_clump_reduce_noalloc(kifmm_handle h, const float* charges, const float* field,
+                               const int64_t* clump_offsets, int64_t C, const double* centers,
+                               double* force, double* torque, void* stream);
+
+/*
  * Backward of kifmm_clump_reduce (the vector-Jacobian product of the Section
  * 2.4 aggregation) for given dL/dF_c and dL/dT_c, with r_k = x_k - X_c:
  *   grad_charges[k]   = dL/dF_c . E_k + dL/dT_c . (r_k x E_k)

@@ -35,7 +35,7 @@ _lib = None
 
 EXPORTS = ["kifmm_default_options", "kifmm_setup", "kifmm_setup_ex", "kifmm_rebuild", "kifmm_set_precision",
            "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient", "kifmm_backward",
-           "kifmm_clump_reduce", "kifmm_clump_backward", "kifmm_set_clumps", "kifmm_clump_forces",
+           "kifmm_clump_reduce", "kifmm_clump_reduce_noalloc", "kifmm_clump_backward", "kifmm_set_clumps", "kifmm_clump_forces",
            "kifmm_clump_forces_backward", "kifmm_synchronize", "kifmm_get_counts", "kifmm_get_m2l_rank",
            "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times", "kifmm_destroy", "kifmm_status_string"]
 
@@ -62,6 +62,7 @@ def lib():
             L.kifmm_evaluate_gradient.argtypes = [H, P, P, P, P, P, P]
             L.kifmm_backward.argtypes = [H, P, P, P, P, P, P]
             L.kifmm_clump_reduce.argtypes = [H, P, P, P, I64, P, P, P, P]
+            L.kifmm_clump_reduce_noalloc.argtypes = [H, P, P, P, I64, P, P, P, P]
             L.kifmm_clump_backward.argtypes = [H, P, P, P, I64, P, P, P, P, P, P, P, P]
             L.kifmm_set_clumps.argtypes = [H, P, I64, P]
             L.kifmm_clump_forces.argtypes = [H, P, P, P, P, P, P]
@@ -78,7 +79,7 @@ def lib():
             L.kifmm_status_string.restype = ctypes.c_char_p
             for name in ("kifmm_setup", "kifmm_setup_ex", "kifmm_rebuild", "kifmm_set_precision",
                          "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient", "kifmm_backward",
-                         "kifmm_clump_reduce", "kifmm_clump_backward", "kifmm_set_clumps", "kifmm_clump_forces",
+                         "kifmm_clump_reduce", "kifmm_clump_reduce_noalloc", "kifmm_clump_backward", "kifmm_set_clumps", "kifmm_clump_forces",
                          "kifmm_clump_forces_backward", "kifmm_synchronize",
                          "kifmm_get_counts", "kifmm_get_m2l_rank",
                          "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times"):

@@ -172,6 +172,7 @@ int kifmm_setup_ex(const double* positions, int64_t N, int kernel, int p, int le
         P->last_stream = s;
         P->status.ensure(sizeof(int));
         KIFMM_HIP(hipMemsetAsync(P->status.p, 0, sizeof(int), s));
+        (void)noalloc_scratch();   // the fixed scratch's address on this device
         build_tree(P, positions, s);
         alloc_densities(P, s);
         KIFMM_HIP(hipStreamSynchronize(s));
@@ -325,6 +326,25 @@ int kifmm_clump_reduce(kifmm_handle h, const float* charges, const float* field,
         P->clump_part.ensure(clump_scratch_bytes(P->N, 6));
         launch_clump_reduce(P, charges, field, clump_offsets, nullptr, C, centers, force, torque,
                             P->clump_part.as<double>(), s);
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_clump_reduce_noalloc(kifmm_handle h, const float* charges, const float* field,
+                               const int64_t* clump_offsets, int64_t C, const double* centers, double* force,
+                               double* torque, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (C < 0 || C >= (int64_t(1) << 31)) throw Error(KIFMM_ERR_ARG, "clump count out of range");
+        if (clump_scratch_bytes(P->N, 6) > kNoAllocScratchBytes)
+            throw Error(KIFMM_ERR_ARG, "N beyond the fixed scratch of kifmm_clump_reduce_noalloc (11,184,640 points)");
+        if (C == 0) return;
+        if (!charges || !field || !clump_offsets || !centers || !force || !torque)
+            throw Error(KIFMM_ERR_ARG, "null pointer argument");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        launch_clump_reduce(P, charges, field, clump_offsets, nullptr, C, centers, force, torque,
+                            static_cast<double*>(noalloc_scratch()), s);
         KIFMM_HIP(hipGetLastError());
     });
 }

@@ -18,6 +18,8 @@
 // kifmm_synchronize reports; reads stay inside the buffers in every case.
 #include <math.h>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace kifmm {
@@ -233,9 +235,33 @@ __global__ void k_clump_sorted(int64_t N, const int* __restrict__ perm, const in
 
 unsigned nblocks(int64_t n) { return unsigned((n + CB - 1) / CB); }
 
+// The fixed scratch of kifmm_clump_reduce_noalloc: the segment partials of
+// the reduction.  Every slot a call reads is written earlier by the same
+// call, so nothing needs clearing; calls that overlap on one device share it
+// and race.
+__device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
 
 size_t clump_scratch_bytes(int64_t N, int nv) { return size_t(nblocks(N)) * 2 * nv * sizeof(double); }
+
+void* noalloc_scratch() {
+    int dev = 0;
+    KIFMM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Error(KIFMM_ERR_STATE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        // the host-side name of the array is not a device address: look the
+        // device copy up once, with this device current
+        void* p = nullptr;
+        KIFMM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
 
 void launch_clump_reduce(kifmm_plan* P, const float* q, const float* E, const int64_t* off, const int* cid, int64_t C,
                          const double* centers, double* F, double* T, double* part, hipStream_t s) {

@@ -21,6 +21,11 @@ constexpr int kM2LSplit = 4;          // M2L V slots split over this many blocks
 constexpr int kM2LSplitMax = 16;      // ... and up to this many for small trees
 constexpr int kM2LFill = 2048;        // M2L blocks wanted before the split stops growing
 constexpr int kMomentBlocks = 256;    // blocks of the periodic moment reduction
+// fixed device scratch of kifmm_clump_reduce_noalloc (per device, for the
+// process lifetime): the clump reduction's segment partials, 96 bytes per
+// block of 256 pebbles, so at most 11,184,640 pebbles
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
 
 // Error carrying a status code; caught at the ABI.
 struct Error : std::runtime_error {
@@ -328,6 +333,8 @@ void launch_clump_backward(kifmm_plan* P, const float* q, const float* E, const 
                            int64_t C, const double* centers, const double* Fb, const double* Tb, float* qb,
                            float* Eb, float* xb, bool acc, double* Xb, double* part, hipStream_t s);
 size_t clump_scratch_bytes(int64_t N, int nv);
+// device address of the fixed scratch on the current device (looked up once per device)
+void* noalloc_scratch();
 // caller-order clump ids from checked device offsets
 void set_clump_ids(kifmm_plan* P, const int64_t* off_dev, int64_t C, hipStream_t s);
 // sorted clump keys for the current tree (after a build)

@@ -168,6 +168,22 @@ class Plan:
                                             _ptr(T), _stream(stream)))
         return F, T
 
+    def clump_reduce_noalloc(self, charges, field, offsets, centers, force, torque, stream=None):
+        """clump_reduce into caller-given force and torque [C, 3] float64,
+        through the entry point that allocates nothing (fixed device scratch)."""
+        C = int(offsets.shape[0]) - 1
+        q = _need(charges, torch.float32, (self.n,), "charges")
+        E = _need(field, torch.float32, (self.n, 3), "field")
+        off = _need(offsets, torch.int64, (C + 1,), "offsets")
+        cen = _need(centers, torch.float64, (C, 3), "centers")
+        F = _need(force, torch.float64, (C, 3), "force")
+        T = _need(torque, torch.float64, (C, 3), "torque")
+        if F.data_ptr() != force.data_ptr() or T.data_ptr() != torque.data_ptr():
+            raise ValueError("force and torque must be contiguous")
+        check(_lib.lib().kifmm_clump_reduce_noalloc(self.handle, _ptr(q), _ptr(E), _ptr(off), C, _ptr(cen),
+                                                    _ptr(F), _ptr(T), _stream(stream)))
+        return F, T
+
     def clump_backward(self, charges, field, offsets, centers, grad_force=None, grad_torque=None, stream=None):
         """Direct parts of the clump VJP: (dL/dq, dL/dE, dL/dx, dL/dX_c)."""
         C = int(offsets.shape[0]) - 1
