@@ -330,6 +330,22 @@ int kifmm_get_counts(kifmm_handle h, int64_t out[10]);
 int kifmm_get_m2l_rank(kifmm_handle h, int64_t out[2]);
 
 /*
+ * The FP64 operators behind the plan (Section 2.2: the translation and
+ * check-to-equivalent matrices computed from the kernel), for checks against
+ * an independent computation.  Unit box, kernel 1/r; HOST buffers.
+ *   which 0: singular values of K(uc, ue) (n values, descending); out[1] =
+ *            the rank the pseudoinverses keep (sigma >= pinv_rtol sigma_1).
+ *   which 1: singular values of [M2L(d_1) ... M2L(d_316)] (n values,
+ *            descending, from the eigenvalues of the sum of M2L(d) M2L(d)^T);
+ *            out[1] = the rank kept with opts.m2l_rtol (KIFMM_ERR_STATE when
+ *            the plan has m2l_rtol = 0).
+ *   which 2: the pseudoinverse UC2E of K(uc, ue), n x n row-major.
+ *   values   host, cap doubles, or NULL to ask for the size; out[0] = the
+ *            number of values (KIFMM_ERR_ARG when cap is smaller).
+ */
+int kifmm_get_operator(kifmm_handle h, int which, double* values, int64_t cap, int64_t out[2]);
+
+/*
  * Copy the tree to HOST buffers (each may be NULL), sized by kifmm_get_counts:
  *   keys [N] uint64 sorted Morton keys, perm [N] int64 (sorted position ->
  *   caller index), level/anchor/begin/end/parent/is_leaf per box (anchor is

@@ -482,6 +482,43 @@ int kifmm_get_m2l_rank(kifmm_handle h, int64_t out[2]) {
     });
 }
 
+int kifmm_get_operator(kifmm_handle h, int which, double* values, int64_t cap, int64_t out[2]) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!out) throw Error(KIFMM_ERR_ARG, "null output");
+        const Operators& op = *P->ops;
+        const int n = op.n;
+        std::vector<double> v;
+        if (which == 0) {
+            v = op.sigma;
+            out[1] = op.rank;
+        } else if (which == 1) {
+            if (!(P->opt.m2l_rtol > 0.0)) throw Error(KIFMM_ERR_STATE, "the plan has no M2L basis (m2l_rtol = 0)");
+            const M2LBasis& cm = get_m2l_basis(P->p, P->opt.pinv_rtol, P->opt.m2l_rtol);
+            v = cm.sigma;
+            out[1] = cm.k;
+        } else if (which == 2) {
+            // UC2E = V_k diag(1 / sigma_k) U_k^T, unit box, kernel 1/r
+            v.assign(size_t(n) * n, 0.0);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    double acc = 0.0;
+                    for (int r = 0; r < op.rank; ++r)
+                        acc += op.svd_v[size_t(i) * n + r] / op.sigma[r] * op.svd_u[size_t(j) * n + r];
+                    v[size_t(i) * n + j] = acc;
+                }
+            out[1] = op.rank;
+        } else {
+            throw Error(KIFMM_ERR_ARG, "which must be 0, 1 or 2");
+        }
+        out[0] = int64_t(v.size());
+        if (values) {
+            if (cap < int64_t(v.size())) throw Error(KIFMM_ERR_ARG, "values buffer too small");
+            std::copy(v.begin(), v.end(), values);
+        }
+    });
+}
+
 int kifmm_copy_tree(kifmm_handle h, uint64_t* keys, int64_t* perm, int32_t* level, int32_t* anchor, int64_t* begin,
                     int64_t* end, int64_t* parent, int8_t* is_leaf, double* root) {
     return guarded([&] {

@@ -152,6 +152,7 @@ struct Operators {
 // tile sizes the M2L kernel is built for; kp = 0 means the basis does not pay.
 struct M2LBasis {
     int k = 0, kp = 0;
+    std::vector<double> sigma;   // singular values of [M2L(d_1) ... M2L(d_316)] (unit operators), descending
     DBuf q;           // float [NP][kp]: Q row-major, zero-padded (operand of the expansion psi += Q psi_k)
     DBuf qt;          // float [kp][NP]: Q^T row-major, zero-padded (operand of the projection phi_k = Q^T phi)
     DBuf core_f32;    // [316] cores in gather-fragment order at kp (FP32)

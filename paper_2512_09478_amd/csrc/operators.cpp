@@ -393,6 +393,8 @@ std::unique_ptr<M2LBasis> build_m2l_basis(int p, double rtol) {
     int k = 0;
     while (k < n && S[k] >= rtol * rtol * S[0]) ++k;
     b->k = k;
+    b->sigma.resize(n);
+    for (int i = 0; i < n; ++i) b->sigma[i] = std::sqrt(std::max(S[i], 0.0));
     const int kp = m2l_tile(k);
     if (kp == 0 || kp >= np) return b;   // no smaller tile: the exact operators are used
     b->kp = kp;

@@ -263,6 +263,19 @@ class Plan:
         check(_lib.lib().kifmm_get_m2l_rank(self.handle, out))
         return int(out[0]), int(out[1])
 
+    def operator(self, which: int):
+        """(values, rank) of the plan's FP64 operators: 0 singular values of
+        K(uc, ue), 1 singular values of the stacked M2L operators, 2 UC2E [n, n]."""
+        L = _lib.lib()
+        out = (ctypes.c_int64 * 2)()
+        check(L.kifmm_get_operator(self.handle, int(which), None, 0, out))
+        v = np.empty(int(out[0]), dtype=np.float64)
+        check(L.kifmm_get_operator(self.handle, int(which), v.ctypes.data_as(ctypes.c_void_p), v.size, out))
+        if which == 2:
+            n = int(round(np.sqrt(v.size)))
+            v = v.reshape(n, n)
+        return v, int(out[1])
+
     def tree(self) -> dict:
         c = self.counts()
         N, B = c["n"], c["boxes"]

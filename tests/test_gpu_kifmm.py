@@ -520,3 +520,37 @@ def test_clump_forces_field_leaves_out_same_clump_pairs(built):
     _, Eo = kifmm.forward(O, w.charges)
     check("E without own clump", Ex, Eo - Ein, TOL["fp32"])
     check("E", E, Eo, TOL["fp32"])
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6, 7, 8])
+def test_operators_and_ranks_match_oracle(built, p):
+    """The library's FP64 operator precompute against the oracle's: singular
+    values of K(uc, ue) and the pseudoinverse's kept rank, the UC2E matrix,
+    and (p >= 4) the singular values of the stacked M2L operators with the
+    rank the compressed M2L keeps at 1e-6 (the library takes them from the
+    eigenvalues of the Gram matrix, the oracle from an SVD)."""
+    from oracle.operators import RHO_UC, RHO_UE, TAU, Operators, kernel_matrix, pinv_truncated, surface
+    say(f"operators p={p}")
+    w = workloads.make(4, n=500)
+    G = gpu_plan(w, 16, p=p, m2l_rtol=1e-6)
+    A = kernel_matrix(surface(p, RHO_UC, 0, 1.0), surface(p, RHO_UE, 0, 1.0), 1.0)
+    Po, rank_o, So = pinv_truncated(A, TAU)
+    S, rank = G.operator(0)
+    assert rank == rank_o
+    keep = So >= 1e-3 * TAU * So[0]
+    np.testing.assert_allclose(S[keep], So[keep], rtol=1e-8)
+    Pl, _ = G.operator(2)
+    e = np.linalg.norm(Pl - Po) / np.linalg.norm(Po)
+    say(f"  pinv rank {rank}; UC2E rel difference {e:.2e}")
+    assert e <= 1e-7
+    if p >= 4:
+        Q, Sm_o = Operators(p, 1.0, 1.0, TAU, 1e-6).m2l_basis(0)
+        Sm, krank = G.operator(1)
+        assert krank == Q.shape[1]
+        keep = Sm_o >= 1e-2 * 1e-6 * Sm_o[0]
+        np.testing.assert_allclose(Sm[keep], Sm_o[keep], rtol=1e-3)
+        kr, tile = G.m2l_rank()
+        n = len(S)
+        say(f"  M2L rank {krank} (tile {tile})")
+        # the basis is used when its padded rank is a smaller tile than the surface's
+        assert kr == (krank if tile < (n + 31) // 32 * 32 else n)
