@@ -5,14 +5,19 @@ Laplace workload (60 % uniform + 40 % in 20 Gaussian clusters, p = 6, leaf 128,
 adaptive octree): re-tree at the positions (keys, sort, octree, lists), the
 forward evaluation (u, E) and the adjoint (dL/dq, dL/dx for given dL/du,
 dL/dE).  Inputs are resident in HBM before the timed region starts.
-``--workload k`` measures the other generators the same way (the clump
-workload adds the per-clump force and torque to the step).
+``--workload k`` measures the other generators the same way (for the clump
+workload the forward pass is the force and torque of the registered clumps
+and the adjoint the gradient of a linear loss on them).
 
 Prints one JSON line.  The headline path is the split-bf16 M2L (all else
 FP32); the plain FP32 path is measured beside it.  The roofline object is for
-the kernel with the largest share of a forward evaluation, timed with HIP
-events on the stream it is launched on.  The CPU baseline is the FP64 oracle
-(test infrastructure) timed on a bounded sample of the same workload.
+the kernel with the most time per step, timed with HIP events that the
+library records on the stream the kernel is launched on (read after the
+timed region).  The line also carries the largest single-GPU workload (8.4M
+Plummer masses, p = 8) on the headline path, the oracle's check of the timed
+outputs on 256 sampled targets (rel-L2 and worst element per output and
+path), and the CPU baseline: the FP64 oracle (test infrastructure) timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -55,6 +60,10 @@ CPU_SAMPLE = {1: 4096, 2: 131072, 3: 131072, 4: 131072, 5: 65536, 6: 8752}
 
 
 def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rtol=0.0):
+    """Time `steps` steps (re-tree + forward + adjoint) after `warmup` ones.
+    The library records HIP events around every phase of every call on the
+    streams the kernels run on; they are read after the timed region, so the
+    timed steps never wait on the host."""
     import torch
     plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=precision, root=w.root,
                 profile=True, periodic=w.periodic, m2l_rtol=m2l_rtol)
@@ -69,12 +78,19 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rt
         gen.manual_seed(2512)
     counts = plan.counts()
     counts["m2l_rank"], counts["m2l_tile"] = plan.m2l_rank()
-    phases, phases_adj = [], []
     clumps = None
     if w.clump_offsets is not None:
-        clumps = (torch.tensor(w.clump_offsets, device="cuda"), torch.tensor(w.clump_centers, device="cuda"))
+        # the clump workload: registered clumps, per-clump force and torque as
+        # the forward pass, the gradient of a linear loss on them as the adjoint
+        C = len(w.clump_offsets) - 1
+        plan.set_clumps(torch.tensor(w.clump_offsets, device="cuda"))
+        rng = np.random.default_rng(78)
+        cen = torch.tensor(w.clump_centers, device="cuda")
+        gF = torch.tensor(rng.standard_normal((C, 3)), device="cuda")
+        gT = torch.tensor(rng.standard_normal((C, 3)), device="cuda")
+        clumps = (cen, gF, gT)
 
-    def step(record):
+    def step():
         if move > 0:
             pos.add_(torch.randn(pos.shape, generator=gen, dtype=pos.dtype, device=pos.device), alpha=move)
             if w.periodic:
@@ -83,40 +99,50 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rt
             torch.maximum(pos, lo, out=pos)
             torch.minimum(pos, hi, out=pos)
         plan.rebuild(pos)
-        u, E = plan.evaluate(q)
         if clumps is not None:
-            plan.clump_reduce(q, E, *clumps)
-        if record:
-            phases.append(plan.phase_times())
+            cen, gF, gT = clumps
+            F, T = plan.clump_forces(q, cen)
+            gq, gx, gX = plan.clump_forces_backward(q, cen, gF, gT)
+            return F, T, gq, gx
+        u, E = plan.evaluate(q)
         gq, gx = plan.backward(None, gu, gE)   # adjoint of the evaluation just made
-        if record:
-            phases_adj.append(plan.phase_times())
         return u, E, gq, gx
 
     for _ in range(warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        out = step(True)
+        out = step()
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / steps
+    # the phases of the timed calls (two per step: forward, then adjoint)
+    ncalls = min(2 * steps, 64)
+    calls = [plan.phase_times(back) for back in range(ncalls - 1, -1, -1)]
+    phases, phases_adj = calls[0::2], calls[1::2]
     # split of one step (untimed repetitions)
     torch.cuda.synchronize()
     a = time.perf_counter()
     plan.rebuild(pos)
     torch.cuda.synchronize()
     b = time.perf_counter()
-    plan.evaluate(q)
+    if clumps is not None:
+        plan.clump_forces(q, clumps[0])
+    else:
+        plan.evaluate(q)
     torch.cuda.synchronize()
     c = time.perf_counter()
-    plan.backward(None, gu, gE)
+    if clumps is not None:
+        plan.clump_forces_backward(q, clumps[0], clumps[1], clumps[2])
+    else:
+        plan.backward(None, gu, gE)
     torch.cuda.synchronize()
     d = time.perf_counter()
     ph = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
     pha = {k: float(np.mean([p[k] for p in phases_adj])) for k in phases_adj[0]}
     res = dict(ms_per_step=1e3 * t, t_tree_ms=1e3 * (b - a), t_fwd_ms=1e3 * (c - b), t_adj_ms=1e3 * (d - c),
-               phases_fwd_ms=ph, phases_adj_ms=pha, counts=counts, outputs=[o.detach() for o in out])
+               phases_fwd_ms=ph, phases_adj_ms=pha, counts=counts, outputs=[o.detach() for o in out],
+               timed_launches=len(calls))
     plan.close()
     return res
 
@@ -194,6 +220,70 @@ def cpu_baseline(k, m2l_rtol):
     return dict(value=n / t, unit="particles/s", cores=cores, kind="oracle",
                 sample=f"the same workload generator at N={n} (same p, leaf, tree rules): "
                        f"tree+lists+forward+adjoint in FP64, {t:.1f} s")
+
+
+def oracle_check(w, paths, gu, gE, m2l_rtol, nsample=256):
+    """The oracle as the checker of the timed outputs: the same plan (tree,
+    lists, operators) in FP64, evaluated at `nsample` sampled targets, forward
+    and adjoint; with the truncated M2L basis also the forward with the exact
+    operators.  Per path and output: rel-L2 and the worst element
+    (max |y - y_ref| / max |y_ref|) over the sample."""
+    import dataclasses
+
+    from oracle import kifmm
+    from oracle.operators import Operators
+    t0 = time.perf_counter()
+    P = kifmm.plan(w.positions, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, w.root,
+                   periodic=w.periodic, m2l_rtol=m2l_rtol)
+    idx = np.sort(np.random.default_rng(21).choice(w.n, nsample, replace=False))
+    ub = gu.double().cpu().numpy()
+    Eb = gE.double().cpu().numpy()
+    ref = {}
+    ref["u"], ref["E"] = kifmm.forward(P, w.charges, targets=idx)
+    ref["qbar"], ref["xbar"] = kifmm.vjp(P, w.charges, ub, Eb, targets=idx)
+    if m2l_rtol > 0:
+        PX = dataclasses.replace(P, ops=Operators(P.p, P.c, P.tree.s, P.tau, 0.0))
+        ref["u_exact_m2l"], ref["E_exact_m2l"] = kifmm.forward(PX, w.charges, targets=idx)
+    t = time.perf_counter() - t0
+
+    def err(a, b):
+        return {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                "worst": float(np.max(np.abs(a - b)) / np.max(np.abs(b)))}
+
+    out = {"sample": f"{nsample} sampled targets of the timed plan; oracle {t:.1f} s",
+           "tolerance": {"fp32": 1e-5, "split_bf16": 1e-4}}
+    for prec, r in paths.items():
+        got = dict(zip(("u", "E", "qbar", "xbar"), (o.double().cpu().numpy()[idx] for o in r["outputs"])))
+        res = {k: err(got[k], ref[k]) for k in ("u", "E", "qbar", "xbar")}
+        if m2l_rtol > 0:
+            res["u_vs_exact_m2l"] = err(got["u"], ref["u_exact_m2l"])
+            res["E_vs_exact_m2l"] = err(got["E"], ref["E_exact_m2l"])
+        out[prec] = res
+    return out
+
+
+# the largest single-GPU workload, measured beside the headline
+LARGEST = 5
+
+
+def run_largest(Plan, steps, warmup, m2l_rtol):
+    """The Plummer workload (8,388,608 unit masses, p = 8) on the headline path:
+    ms per step (re-tree + forward + adjoint) and its dominant kernel."""
+    import torch
+    import workloads
+    w = workloads.make(LARGEST)
+    pos = torch.tensor(w.positions, dtype=torch.float64, device="cuda")
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(77)
+    gu = torch.tensor(workloads.round_f32(rng.standard_normal(w.n)), dtype=torch.float32, device="cuda")
+    gE = torch.tensor(workloads.round_f32(rng.standard_normal((w.n, 3))), dtype=torch.float32, device="cuda")
+    r = run_path(Plan, w, pos, q, gu, gE, "split_bf16", steps, warmup, 0.0, m2l_rtol)
+    r.pop("outputs", None)
+    return {"workload": WORKLOADS[LARGEST], "name": w.name, "n": w.n, "path": "split_bf16", "steps": steps,
+            "warmup": warmup, "ms_per_step": r["ms_per_step"], "particles_per_s": w.n / (r["ms_per_step"] * 1e-3),
+            "t_tree_ms": r["t_tree_ms"], "t_fwd_ms": r["t_fwd_ms"], "t_adj_ms": r["t_adj_ms"],
+            "phases_fwd_ms": r["phases_fwd_ms"], "phases_adj_ms": r["phases_adj_ms"], "counts": r["counts"],
+            "roofline": roofline(r, r["counts"]["surface_points"], "split_bf16", w.name, w.n)}
 
 
 # the workload --counter-run evaluates (its name and size, as recorded with the counters)
@@ -400,7 +490,8 @@ def main():
     ap.add_argument("--paths", default="split_bf16,fp32")
     ap.add_argument("--m2l-rtol", type=float, default=M2L_RTOL,
                     help="M2L in the truncated common basis of the offset operators (0: exact operators)")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (CPU baseline and accuracy check)")
+    ap.add_argument("--no-largest", action="store_true", help="skip the largest workload beside the headline")
     ap.add_argument("--counter-run", metavar="PRECISION", help="short run for rocprofv3 counter passes")
     ap.add_argument("--summarize-trace", nargs="+", metavar="DB OUT CMD [TITLE]")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("CSV", "COUNTS_LOG", "OUT", "CMD"))
@@ -449,7 +540,8 @@ def main():
     wkey = w.name + ("+move" if args.move else "")
     agree = {}
     if "fp32" in paths and "split_bf16" in paths:
-        for name, i in (("u", 0), ("E", 1), ("qbar", 2), ("xbar", 3)):
+        names = ("F_c", "T_c") if w.clump_offsets is not None else ("u", "E")
+        for name, i in ((names[0], 0), (names[1], 1), ("qbar", 2), ("xbar", 3)):
             a = paths["split_bf16"]["outputs"][i].double()
             b = paths["fp32"]["outputs"][i].double()
             agree[name] = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
@@ -480,9 +572,17 @@ def main():
                       "roofline": roofline(v, ops_n, k, wkey, n)}
                   for k, v in paths.items()},
         "counts": H["counts"],
+        "timed_launches_per_path": H["timed_launches"],
         "split_vs_fp32_rel_l2": agree,
     }
+    if args.workload == 2 and args.n is None and not args.move and not args.no_largest:
+        log("[bench] largest workload (Plummer, 8,388,608 points, p = 8), split-bf16 path")
+        out["largest_config"] = run_largest(Plan, 5, 2, args.m2l_rtol)
+        log(f"[bench] largest: {out['largest_config']['ms_per_step']:.2f} ms/step")
     if not args.no_cpu:
+        if w.clump_offsets is None and not args.move:
+            log("[bench] oracle check of the timed outputs (256 sampled targets)")
+            out["accuracy_vs_oracle"] = oracle_check(w, paths, gu, gE, args.m2l_rtol)
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.m2l_rtol)
     for v in paths.values():

@@ -379,9 +379,18 @@ int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indic
  * the M2L basis), 2 P2L, 3 M2L, 4 L2L+DC2E (and the expansion out of the M2L
  * basis), 5 L2P+M2P (with the
  * final combination), 6 P2P (on the near-field stream, concurrent with 0-4),
- * 7 whole call.  Needs opts.profile = 1; returns the number written.
+ * 7 whole call.  Needs opts.profile = 1; returns the number written (0 when
+ * the call recorded nothing).  Waits for that call's events.
  */
 int kifmm_get_phase_times(kifmm_handle h, float* out, int n);
+
+/*
+ * The same for the profiled call `back` calls before the last (0 = the last,
+ * up to 63: the plan keeps the events of its last 64 profiled evaluation,
+ * adjoint and clump-force calls), so that a run of calls can be timed
+ * without waiting between them.  KIFMM_ERR_ARG when that call is not kept.
+ */
+int kifmm_get_phase_times_at(kifmm_handle h, int back, float* out, int n);
 
 /* Release the handle and everything it owns (NULL is accepted). */
 void kifmm_destroy(kifmm_handle h);

@@ -77,12 +77,23 @@ kifmm_plan* checked(kifmm_handle h) {
 
 void begin_phases(kifmm_plan* P, hipStream_t s) {
     if (!P->opt.profile) return;
-    if (!P->events.made) {
-        for (auto& e : P->events.ev) KIFMM_HIP(hipEventCreate(&e));
-        for (auto& e : P->events.p2p) KIFMM_HIP(hipEventCreate(&e));
-        P->events.made = true;
+    PhaseEvents& pe = P->events;
+    if (!pe.made) {
+        for (auto& row : pe.ev)
+            for (auto& e : row) KIFMM_HIP(hipEventCreate(&e));
+        for (auto& row : pe.p2p)
+            for (auto& e : row) KIFMM_HIP(hipEventCreate(&e));
+        pe.made = true;
     }
-    KIFMM_HIP(hipEventRecord(P->events.ev[0], s));
+    pe.cur = (pe.cur + 1) % PhaseEvents::kRing;
+    pe.valid[pe.cur] = false;
+    ++pe.calls;
+    KIFMM_HIP(hipEventRecord(pe.ev[pe.cur][0], s));
+}
+
+// the profiled call has recorded all its events
+void end_phases(kifmm_plan* P) {
+    if (P->opt.profile && P->events.made) P->events.valid[P->events.cur] = true;
 }
 
 enum NearKind { NEAR_FORWARD, NEAR_BACKWARD, NEAR_DIPOLES, NEAR_GRAD, NEAR_GRAD_DIPOLES, NEAR_FORWARD_EXCL,
@@ -98,12 +109,12 @@ void fork_near(kifmm_plan* P, NearKind kind, hipStream_t s) {
     KIFMM_HIP(hipEventRecord(P->nearq.fork, s));
     KIFMM_HIP(hipStreamWaitEvent(t, P->nearq.fork, 0));
     const bool prof = P->opt.profile && P->events.made;
-    if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[0], t));
+    if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[P->events.cur][0], t));
     if (kind == NEAR_BACKWARD || kind == NEAR_BACKWARD_EXCL) launch_p2p_backward(P, t, kind == NEAR_BACKWARD_EXCL);
     else if (kind == NEAR_DIPOLES) launch_p2p_dipoles(P, t);
     else if (kind == NEAR_GRAD || kind == NEAR_GRAD_DIPOLES) launch_p2p_gradient(P, kind == NEAR_GRAD_DIPOLES, t);
     else launch_p2p_forward(P, t, kind == NEAR_FORWARD_EXCL);
-    if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[1], t));
+    if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[P->events.cur][1], t));
     KIFMM_HIP(hipEventRecord(P->nearq.join, t));
 }
 
@@ -117,7 +128,7 @@ void join_near(kifmm_plan* P, hipStream_t s) {
 namespace kifmm {
 void record_phase(kifmm_plan* P, int idx, hipStream_t s) {
     if (!P->opt.profile || !P->events.made) return;
-    KIFMM_HIP(hipEventRecord(P->events.ev[idx + 1], s));
+    KIFMM_HIP(hipEventRecord(P->events.ev[P->events.cur][idx + 1], s));
 }
 }  // namespace kifmm
 
@@ -229,7 +240,7 @@ int kifmm_evaluate(kifmm_handle h, const float* charges, float* potential, float
         join_near(P, s);
         run_far_eval(P, false, potential, field, s);
         record_phase(P, 6, s);
-        P->has_phase = P->opt.profile ? 1 : 0;
+        end_phases(P);
         P->fwd_valid = true;
         KIFMM_HIP(hipGetLastError());
     });
@@ -253,7 +264,7 @@ int kifmm_evaluate_dipoles(kifmm_handle h, const float* charges, const float* di
         join_near(P, s);
         run_far_eval(P, false, potential, field, s, 1);
         record_phase(P, 6, s);
-        P->has_phase = P->opt.profile ? 3 : 0;
+        end_phases(P);
         KIFMM_HIP(hipGetLastError());
     });
 }
@@ -277,7 +288,7 @@ int kifmm_evaluate_gradient(kifmm_handle h, const float* charges, const float* d
         join_near(P, s);
         run_far_grad(P, potential, field, field_grad, s, rhs);
         record_phase(P, 6, s);
-        P->has_phase = P->opt.profile ? 3 : 0;
+        end_phases(P);
         KIFMM_HIP(hipGetLastError());
     });
 }
@@ -304,7 +315,7 @@ int kifmm_backward(kifmm_handle h, const float* charges, const float* grad_poten
         join_near(P, s);
         run_far_eval(P, true, grad_charges, grad_positions, s);
         record_phase(P, 6, s);
-        P->has_phase = P->opt.profile ? 2 : 0;
+        end_phases(P);
         KIFMM_HIP(hipGetLastError());
     });
 }
@@ -415,7 +426,7 @@ int kifmm_clump_forces(kifmm_handle h, const float* charges, const double* cente
         launch_clump_reduce(P, charges, E, P->clump_off.as<int64_t>(), P->cid.as<int>(), P->clumps, centers, force,
                             torque, P->clump_part.as<double>(), s);
         if (field) KIFMM_HIP(hipMemcpyAsync(field, E, size_t(P->N) * 12, hipMemcpyDeviceToDevice, s));
-        P->has_phase = P->opt.profile ? 1 : 0;
+        end_phases(P);
         P->fwd_valid = true;
         P->fwd_excl = true;
         KIFMM_HIP(hipGetLastError());
@@ -445,7 +456,7 @@ int kifmm_clump_forces_backward(kifmm_handle h, const float* charges, const doub
         join_near(P, s);
         run_far_eval(P, true, grad_charges, grad_positions, s, 0, true);
         record_phase(P, 6, s);
-        P->has_phase = P->opt.profile ? 2 : 0;
+        end_phases(P);
         KIFMM_HIP(hipGetLastError());
     });
 }
@@ -627,31 +638,41 @@ int kifmm_copy_list(kifmm_handle h, char which, int64_t* offsets, int64_t* indic
     });
 }
 
-int kifmm_get_phase_times(kifmm_handle h, float* out, int n) {
+int kifmm_get_phase_times_at(kifmm_handle h, int back, float* out, int n) {
     int written = 0;
     int rc = guarded([&] {
         kifmm_plan* P = checked(h);
         if (!out) throw Error(KIFMM_ERR_ARG, "null output");
-        if (!P->has_phase || !P->events.made) return;
-        KIFMM_HIP(hipEventSynchronize(P->events.ev[7]));
-        KIFMM_HIP(hipEventSynchronize(P->events.p2p[1]));
+        const PhaseEvents& pe = P->events;
+        if (!pe.made) return;
+        if (back < 0 || back >= PhaseEvents::kRing || back >= pe.calls)
+            throw Error(KIFMM_ERR_ARG, "no profiled call that far back");
+        const int k = ((pe.cur - back) % PhaseEvents::kRing + PhaseEvents::kRing) % PhaseEvents::kRing;
+        if (!pe.valid[k]) return;
+        const hipEvent_t* ev = pe.ev[k];
+        KIFMM_HIP(hipEventSynchronize(ev[7]));
+        KIFMM_HIP(hipEventSynchronize(pe.p2p[k][1]));
         float ms[8] = {};
-        for (int k = 0; k < 5; ++k) KIFMM_HIP(hipEventElapsedTime(&ms[k], P->events.ev[k], P->events.ev[k + 1]));
-        KIFMM_HIP(hipEventElapsedTime(&ms[5], P->events.ev[6], P->events.ev[7]));
-        KIFMM_HIP(hipEventElapsedTime(&ms[6], P->events.p2p[0], P->events.p2p[1]));
-        KIFMM_HIP(hipEventElapsedTime(&ms[7], P->events.ev[0], P->events.ev[7]));
-        for (int k = 0; k < std::min(n, 8); ++k) out[k] = ms[k];
+        for (int i = 0; i < 5; ++i) KIFMM_HIP(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+        KIFMM_HIP(hipEventElapsedTime(&ms[5], ev[6], ev[7]));
+        KIFMM_HIP(hipEventElapsedTime(&ms[6], pe.p2p[k][0], pe.p2p[k][1]));
+        KIFMM_HIP(hipEventElapsedTime(&ms[7], ev[0], ev[7]));
+        for (int i = 0; i < std::min(n, 8); ++i) out[i] = ms[i];
         written = std::min(n, 8);
     });
     return rc == KIFMM_OK ? written : rc;
 }
 
+int kifmm_get_phase_times(kifmm_handle h, float* out, int n) { return kifmm_get_phase_times_at(h, 0, out, n); }
+
 void kifmm_destroy(kifmm_handle h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->last_stream);
     if (h->events.made) {
-        for (auto& e : h->events.ev) (void)hipEventDestroy(e);
-        for (auto& e : h->events.p2p) (void)hipEventDestroy(e);
+        for (auto& row : h->events.ev)
+            for (auto& e : row) (void)hipEventDestroy(e);
+        for (auto& row : h->events.p2p)
+            for (auto& e : row) (void)hipEventDestroy(e);
     }
     delete h;
 }

@@ -181,13 +181,18 @@ struct LevelInfo {
     int64_t nl_start = 0, nl_count = 0;  // non-leaf boxes of this level in nonleaf[]
 };
 
-// Phase events: ev[0] start, ev[1..5] after P2M, upward, P2L, M2L, downward
-// on the caller's stream, ev[6] after it has joined the near-field stream,
-// ev[7] after the leaf evaluation; p2p[0..1] around the near field on the
-// side stream.
+// Phase events of the last kRing profiled calls (a ring, so that a caller
+// can read them after a run of calls without synchronising in between): per
+// call ev[0] start, ev[1..5] after P2M, upward, P2L, M2L, downward on the
+// caller's stream, ev[6] after it has joined the near-field stream, ev[7]
+// after the leaf evaluation; p2p[0..1] around the near field on the side stream.
 struct PhaseEvents {
-    hipEvent_t ev[8] = {};
-    hipEvent_t p2p[2] = {};
+    static constexpr int kRing = 64;
+    hipEvent_t ev[kRing][8] = {};
+    hipEvent_t p2p[kRing][2] = {};
+    bool valid[kRing] = {};   // the slot holds a finished call's events
+    int cur = kRing - 1;      // slot of the last (or running) call
+    int64_t calls = 0;
     bool made = false;
 };
 
@@ -278,8 +283,6 @@ struct kifmm_plan {
     kifmm::DBuf tmp_a, tmp_b, tmp_c, tmp_d, tmp_e, tmp_f, scan_tmp, flag, pair_cnt;
     kifmm::PhaseEvents events;
     kifmm::SideStream nearq;   // near-field stream
-    float phase_ms[8] = {};
-    int has_phase = 0;
     bool fwd_valid = false;   // densities of right-hand side 0 and pts hold the last forward pass
     bool fwd_excl = false;    // ... and that pass left out the pairs of pebbles of one clump
     // input errors found on the device (clump offsets): int word, cleared by kifmm_synchronize

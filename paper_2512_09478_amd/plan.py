@@ -304,9 +304,10 @@ class Plan:
                                 idx.ctypes.data_as(ctypes.c_void_p) if idx.size else None))
         return off, idx
 
-    def phase_times(self) -> dict:
+    def phase_times(self, back: int = 0) -> dict:
+        """Phase times (ms) of the profiled call ``back`` calls before the last."""
         out = (ctypes.c_float * 8)()
-        n = check(_lib.lib().kifmm_get_phase_times(self.handle, out, 8))
+        n = check(_lib.lib().kifmm_get_phase_times_at(self.handle, int(back), out, 8))
         return {PHASES[k]: float(out[k]) for k in range(n)}
 
 
