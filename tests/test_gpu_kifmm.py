@@ -537,8 +537,10 @@ def test_operators_and_ranks_match_oracle(built, p):
     Po, rank_o, So = pinv_truncated(A, TAU)
     S, rank = G.operator(0)
     assert rank == rank_o
-    keep = So >= 1e-3 * TAU * So[0]
-    np.testing.assert_allclose(S[keep], So[keep], rtol=1e-8)
+    # both SVDs are accurate to about eps sigma_1 in absolute terms; compare
+    # the values down to half the cut-off
+    keep = So >= 0.5 * TAU * So[0]
+    np.testing.assert_allclose(S[keep], So[keep], rtol=1e-8, atol=1e-13 * So[0])
     Pl, _ = G.operator(2)
     e = np.linalg.norm(Pl - Po) / np.linalg.norm(Po)
     say(f"  pinv rank {rank}; UC2E rel difference {e:.2e}")
@@ -547,7 +549,9 @@ def test_operators_and_ranks_match_oracle(built, p):
         Q, Sm_o = Operators(p, 1.0, 1.0, TAU, 1e-6).m2l_basis(0)
         Sm, krank = G.operator(1)
         assert krank == Q.shape[1]
-        keep = Sm_o >= 1e-2 * 1e-6 * Sm_o[0]
+        # the Gram route loses relative accuracy as eps (sigma_1/sigma)^2: compare
+        # the values down to half the cut-off (2e-4 there), which covers the cut
+        keep = Sm_o >= 0.5 * 1e-6 * Sm_o[0]
         np.testing.assert_allclose(Sm[keep], Sm_o[keep], rtol=1e-3)
         kr, tile = G.m2l_rank()
         n = len(S)
