@@ -142,7 +142,7 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rt
     pha = {k: float(np.mean([p[k] for p in phases_adj])) for k in phases_adj[0]}
     res = dict(ms_per_step=1e3 * t, t_tree_ms=1e3 * (b - a), t_fwd_ms=1e3 * (c - b), t_adj_ms=1e3 * (d - c),
                phases_fwd_ms=ph, phases_adj_ms=pha, counts=counts, outputs=[o.detach() for o in out],
-               timed_launches=len(calls))
+               timed_launches=len(calls), builds=plan.build_stats())
     plan.close()
     return res
 
@@ -569,6 +569,7 @@ def main():
                       "particles_per_s_adjoint": n / (v["t_adj_ms"] * 1e-3),
                       "t_tree_ms": v["t_tree_ms"], "t_fwd_ms": v["t_fwd_ms"], "t_adj_ms": v["t_adj_ms"],
                       "phases_fwd_ms": v["phases_fwd_ms"], "phases_adj_ms": v["phases_adj_ms"],
+                      "tree_builds": v["builds"],
                       "roofline": roofline(v, ops_n, k, wkey, n)}
                   for k, v in paths.items()},
         "counts": H["counts"],

@@ -138,7 +138,12 @@ int kifmm_setup_ex(const double* positions, int64_t N, int kernel, int p, int le
  * Rebuild the tree and lists of an existing plan for new positions (same N,
  * kernel, p, leaf size and options); work space is reused where it fits.
  * This is the per-call re-tree of particles that move between long-range
- * evaluations (Section 2.4).  Synchronises `stream`.
+ * evaluations (Section 2.4).  The sort starts from the previous build's
+ * order: the keys are formed in that order, the points out of order with a
+ * neighbour are sorted on their own and merged back into the rest (when the
+ * rest is in order and they are at most a quarter of the points; otherwise
+ * the full radix sort runs).  The result is the same order as a fresh
+ * set-up's.  Synchronises `stream`.
  */
 int kifmm_rebuild(kifmm_handle h, const double* positions, void* stream);
 
@@ -321,6 +326,16 @@ int kifmm_synchronize(kifmm_handle h, void* stream);
  * last stream, which the call then synchronises), not by the build itself.
  */
 int kifmm_get_counts(kifmm_handle h, int64_t out[10]);
+
+/*
+ * Build statistics (host out[3]): out[0] tree builds of the plan (set-up and
+ * rebuilds), out[1] builds that started from the previous build's order (a
+ * rebuild with that order at hand), out[2] of those, the ones whose sort was
+ * finished that way (the points out of order with a neighbour sorted on their
+ * own and merged back into the rest); the others ran the full radix sort.
+ * Either way the order is the same: by key, ties by caller index.
+ */
+int kifmm_get_build_stats(kifmm_handle h, int64_t out[3]);
 
 /*
  * The M2L operators in use (host out[2]): out[0] = their rank (the number of

@@ -37,7 +37,7 @@ EXPORTS = ["kifmm_default_options", "kifmm_setup", "kifmm_setup_ex", "kifmm_rebu
            "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient", "kifmm_backward",
            "kifmm_clump_reduce", "kifmm_clump_reduce_noalloc", "kifmm_clump_backward", "kifmm_set_clumps", "kifmm_clump_forces",
            "kifmm_clump_forces_backward", "kifmm_synchronize", "kifmm_get_counts", "kifmm_get_m2l_rank",
-           "kifmm_get_operator", "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times",
+           "kifmm_get_build_stats", "kifmm_get_operator", "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times",
            "kifmm_get_phase_times_at", "kifmm_destroy", "kifmm_status_string"]
 
 
@@ -72,6 +72,7 @@ def lib():
             L.kifmm_get_counts.argtypes = [H, ctypes.POINTER(I64)]
             L.kifmm_get_m2l_rank.argtypes = [H, ctypes.POINTER(I64)]
             L.kifmm_get_operator.argtypes = [H, I, P, I64, ctypes.POINTER(I64)]
+            L.kifmm_get_build_stats.argtypes = [H, ctypes.POINTER(I64)]
             L.kifmm_copy_tree.argtypes = [H, P, P, P, P, P, P, P, P, P]
             L.kifmm_copy_list.argtypes = [H, ctypes.c_char, P, P]
             L.kifmm_get_phase_times.argtypes = [H, ctypes.POINTER(ctypes.c_float), I]
@@ -84,7 +85,7 @@ def lib():
                          "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient", "kifmm_backward",
                          "kifmm_clump_reduce", "kifmm_clump_reduce_noalloc", "kifmm_clump_backward", "kifmm_set_clumps", "kifmm_clump_forces",
                          "kifmm_clump_forces_backward", "kifmm_synchronize",
-                         "kifmm_get_counts", "kifmm_get_m2l_rank", "kifmm_get_operator",
+                         "kifmm_get_counts", "kifmm_get_m2l_rank", "kifmm_get_operator", "kifmm_get_build_stats",
                          "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times",
                          "kifmm_get_phase_times_at"):
                 getattr(L, name).restype = I

@@ -484,6 +484,16 @@ int kifmm_get_counts(kifmm_handle h, int64_t out[10]) {
     });
 }
 
+int kifmm_get_build_stats(kifmm_handle h, int64_t out[3]) {
+    return guarded([&] {
+        if (!h) throw Error(KIFMM_ERR_STATE, "null handle");
+        if (!out) throw Error(KIFMM_ERR_ARG, "null output");
+        out[0] = h->builds;
+        out[1] = h->resort_steps;
+        out[2] = h->resort_hits;
+    });
+}
+
 int kifmm_get_m2l_rank(kifmm_handle h, int64_t out[2]) {
     return guarded([&] {
         kifmm_plan* P = checked(h);

@@ -281,6 +281,9 @@ struct kifmm_plan {
     kifmm::DBuf mom_part;   // their per-block partial sums
     // scratch
     kifmm::DBuf tmp_a, tmp_b, tmp_c, tmp_d, tmp_e, tmp_f, scan_tmp, flag, pair_cnt;
+    kifmm::DBuf resort;     // re-sort from the previous order: flags, offsets, the two subsequences
+    bool sorted_valid = false;   // perm holds the order of the last build (same N)
+    int64_t builds = 0, resort_steps = 0, resort_hits = 0;   // builds; those that tried / completed the re-sort
     kifmm::PhaseEvents events;
     kifmm::SideStream nearq;   // near-field stream
     bool fwd_valid = false;   // densities of right-hand side 0 and pts hold the last forward pass

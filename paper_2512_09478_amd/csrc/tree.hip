@@ -17,6 +17,7 @@ namespace kifmm {
 namespace {
 
 constexpr int TB = 256;
+constexpr int64_t kSmallTreeN = 131072;   // trees of at most this many points: levels in one block
 inline int nblocks(int64_t n, int per = TB) { return int((n + per - 1) / per); }
 
 struct LevelTable {
@@ -97,6 +98,128 @@ __global__ void k_keys(const double* __restrict__ x, int64_t N, double lo0, doub
     if (b) atomicOr(bad, 1);
     keys[i] = morton3(k[0], k[1], k[2]);
     idx[i] = uint32_t(i);
+}
+
+// ----------------------------------------------------------------- re-sort from the previous order
+// Points that move between builds keep most of their order.  The order is by
+// (key, caller index), a total order, so the sorted result does not depend on
+// how it is reached: the keys are formed in the previous sorted order, the
+// points out of order with a near neighbour in that sequence (D) are taken
+// out, the rest (R) is checked to be sorted, D is sorted, and the two are
+// merged.
+
+// (key, index) strictly before (key2, index2)
+__device__ inline bool kv_less(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib) {
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+__global__ void k_keys_prev(const double* __restrict__ x, int64_t N, double lo0, double lo1, double lo2,
+                            double scale, double side, int check_root, const int* __restrict__ prev,
+                            uint64_t* __restrict__ keys, uint32_t* __restrict__ idx, int* __restrict__ bad) {
+    int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x;
+    if (i >= N) return;
+    const int64_t j = prev[i];
+    const double lo[3] = {lo0, lo1, lo2};
+    uint64_t k[3];
+    int b = 0;
+    for (int d = 0; d < 3; ++d) {
+        double v = x[3 * j + d];
+        if (!isfinite(v)) b = 1;
+        if (check_root && (v < lo[d] || v > lo[d] + side)) b = 1;
+        double f = floor(__dmul_rn(__dsub_rn(v, lo[d]), scale));
+        f = fmin(fmax(f, 0.0), double((1 << kBits) - 1));
+        k[d] = b ? 0 : uint64_t(f);
+    }
+    if (b) atomicOr(bad, 1);
+    keys[i] = morton3(k[0], k[1], k[2]);
+    idx[i] = uint32_t(j);
+}
+
+// flag[i] = 1 when element i is out of order with any element at most
+// kResortWindow places away (so that a group of up to that many points that
+// moved together past others is taken out whole); flag[N] = 0
+constexpr int kResortWindow = 8;
+__global__ void k_displaced(const uint64_t* __restrict__ k, const uint32_t* __restrict__ v, int64_t N,
+                            int* __restrict__ flag) {
+    int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x;
+    if (i > N) return;
+    if (i == N) {
+        flag[N] = 0;
+        return;
+    }
+    const uint64_t ki = k[i];
+    const uint32_t vi = v[i];
+    bool d = false;
+    for (int w = 1; w <= kResortWindow; ++w) {
+        if (i - w >= 0 && !kv_less(k[i - w], v[i - w], ki, vi)) d = true;
+        if (i + w < N && !kv_less(ki, vi, k[i + w], v[i + w])) d = true;
+    }
+    flag[i] = d ? 1 : 0;
+}
+
+// split into D (flagged, in order) and R (the rest, in order)
+__global__ void k_split_dr(const uint64_t* __restrict__ k, const uint32_t* __restrict__ v, int64_t N,
+                           const int* __restrict__ flag, const int* __restrict__ dpos, uint64_t* __restrict__ dk,
+                           uint32_t* __restrict__ dv, uint64_t* __restrict__ rk, uint32_t* __restrict__ rv) {
+    int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x;
+    if (i >= N) return;
+    if (flag[i]) {
+        dk[dpos[i]] = k[i];
+        dv[dpos[i]] = v[i];
+    } else {
+        const int64_t r = i - dpos[i];
+        rk[r] = k[i];
+        rv[r] = v[i];
+    }
+}
+
+// err |= 1 when R (size N - dpos[N]) is not sorted
+__global__ void k_check_sorted(const uint64_t* __restrict__ rk, const uint32_t* __restrict__ rv, int64_t N,
+                               const int* __restrict__ dpos, int* __restrict__ err) {
+    int64_t r = blockIdx.x * int64_t(TB) + threadIdx.x;
+    const int64_t nr = N - dpos[N];
+    if (r + 1 >= nr) return;
+    if (!kv_less(rk[r], rv[r], rk[r + 1], rv[r + 1])) atomicOr(err, 1);
+}
+
+// after a stable sort of D by key: runs of equal keys put in index order
+__global__ void k_fix_ties(const uint64_t* __restrict__ dk, uint32_t* __restrict__ dv, int64_t n) {
+    int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x;
+    if (i >= n || (i > 0 && dk[i - 1] == dk[i])) return;
+    int64_t e = i + 1;
+    while (e < n && dk[e] == dk[i]) ++e;
+    for (int64_t a = i + 1; a < e; ++a) {   // insertion sort of the (short) run
+        const uint32_t t = dv[a];
+        int64_t b = a;
+        while (b > i && dv[b - 1] > t) {
+            dv[b] = dv[b - 1];
+            --b;
+        }
+        dv[b] = t;
+    }
+}
+
+// number of elements of the sorted (k, v)[0, n) before (key, val)
+__device__ inline int64_t rank_in(const uint64_t* __restrict__ k, const uint32_t* __restrict__ v, int64_t n,
+                                  uint64_t key, uint32_t val) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (kv_less(k[mid], v[mid], key, val)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// merge: every element of A goes to its index plus its rank in B
+__global__ void k_merge_into(const uint64_t* __restrict__ ak, const uint32_t* __restrict__ av, int64_t na,
+                             const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bv, int64_t nb,
+                             uint64_t* __restrict__ ok, uint32_t* __restrict__ ov) {
+    int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x;
+    if (i >= na) return;
+    const int64_t p = i + rank_in(bk, bv, nb, ak[i], av[i]);
+    ok[p] = ak[i];
+    ov[p] = av[i];
 }
 
 // ----------------------------------------------------------------- scan
@@ -369,14 +492,11 @@ void radix_sort(kifmm_plan* P, uint64_t* keys, uint32_t* vals, uint64_t* ktmp, u
 // Writes per front box its child count c and non-leaf child count n packed
 // as c | n << 32 (and a zero at index nf, so that one exclusive scan of nf + 1
 // values gives both offsets).
-__global__ void k_split(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
-                        const int2* __restrict__ range, int* __restrict__ bounds /*[nf][9]*/,
-                        unsigned long long* __restrict__ cnt, int leaf_size, int adaptive, int max_depth, int Lu) {
-    const int64_t gid = int64_t(blockIdx.x) * TB + threadIdx.x;
-    const int f = int(gid >> 6), lane = int(gid & 63);
-    if (gid == 0) cnt[nf] = 0;
-    if (f >= nf) return;   // uniform over the wave
-    const int2 r = range[front[f]];
+// One wave: child boundaries of front box f (key run r) at level l; lane 0
+// writes the 9 bounds to out and returns the packed counts (others return 0).
+__device__ inline unsigned long long split_box(int2 r, int l, const uint64_t* __restrict__ keys, int lane,
+                                               int* __restrict__ out, int leaf_size, int adaptive, int max_depth,
+                                               int Lu) {
     const int shift = 3 * (kBits - (l + 1));
     const int grp = lane / 9, k = lane % 9;
     const int o = grp + 1;
@@ -410,34 +530,43 @@ __global__ void k_split(const int* __restrict__ front, int nf, int l, const uint
     bd[8] = r.y;
 #pragma unroll
     for (int q = 1; q < 8; ++q) bd[q] = __shfl(lo, 9 * (q - 1), 64);
-    if (lane == 0) {
-        int* out = bounds + 9 * f;
-        int c = 0, nl = 0;
-        for (int q = 0; q < 9; ++q) out[q] = bd[q];
-        for (int q = 0; q < 8; ++q) {
-            const int cnt = bd[q + 1] - bd[q];
-            if (cnt > 0) {
-                ++c;
-                const bool leaf = adaptive ? (cnt <= leaf_size || l + 1 == max_depth) : (l + 1 == Lu);
-                if (!leaf) ++nl;
-            }
+    if (lane != 0) return 0;
+    int c = 0, nl = 0;
+    for (int q = 0; q < 9; ++q) out[q] = bd[q];
+    for (int q = 0; q < 8; ++q) {
+        const int cnt = bd[q + 1] - bd[q];
+        if (cnt > 0) {
+            ++c;
+            const bool leaf = adaptive ? (cnt <= leaf_size || l + 1 == max_depth) : (l + 1 == Lu);
+            if (!leaf) ++nl;
         }
-        cnt[f] = (unsigned long long)c | ((unsigned long long)nl << 32);
     }
+    return (unsigned long long)c | ((unsigned long long)nl << 32);
+}
+
+__global__ void k_split(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
+                        const int2* __restrict__ range, int* __restrict__ bounds /*[nf][9]*/,
+                        unsigned long long* __restrict__ cnt, int leaf_size, int adaptive, int max_depth, int Lu) {
+    const int64_t gid = int64_t(blockIdx.x) * TB + threadIdx.x;
+    const int f = int(gid >> 6), lane = int(gid & 63);
+    if (gid == 0) cnt[nf] = 0;
+    if (f >= nf) return;   // uniform over the wave
+    const unsigned long long c =
+        split_box(range[front[f]], l, keys, lane, bounds + 9 * f, leaf_size, adaptive, max_depth, Lu);
+    if (lane == 0) cnt[f] = c;
 }
 
 // Eight lanes per front box, lane o writing child octant o: a child's index
 // and its place in the non-leaf list are the counts of the non-empty (and
-// non-leaf) octants below it, so the children keep the octant order.
-__global__ void k_emit(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
-                       const int* __restrict__ bounds, const unsigned long long* __restrict__ off,
-                       int child_start, int nl_base,
-                       int4* __restrict__ anchor, int2* __restrict__ range, int* __restrict__ parent,
-                       int2* __restrict__ child, int* __restrict__ leafflag, uint64_t* __restrict__ mkey,
-                       int* __restrict__ nonleaf, int leaf_size, int adaptive, int max_depth, int Lu) {
-    const int64_t gid = int64_t(blockIdx.x) * TB + threadIdx.x;
-    const int f = int(gid >> 3), o = int(gid & 7);
-    const bool act = f < nf;
+// non-leaf) octants below it, so the children keep the octant order.  The
+// eight lanes of a box are lanes 8k .. 8k+7 of one wave; every lane of the
+// wave calls this (act = false for lanes without a box).
+__device__ inline void emit_box(bool act, int f, int o, int l, const int* __restrict__ front,
+                                const uint64_t* __restrict__ keys, const int* __restrict__ bounds,
+                                const unsigned long long* __restrict__ off, int child_start, int nl_base,
+                                int4* __restrict__ anchor, int2* __restrict__ range, int* __restrict__ parent,
+                                int2* __restrict__ child, int* __restrict__ leafflag, uint64_t* __restrict__ mkey,
+                                int* __restrict__ nonleaf, int leaf_size, int adaptive, int max_depth, int Lu) {
     int cnt = 0, b0 = 0, b1 = 0;
     if (act) {
         const int* bd = bounds + 9 * f;
@@ -468,6 +597,107 @@ __global__ void k_emit(const int* __restrict__ front, int nf, int l, const uint6
         if (inner) nonleaf[nl_base + int(of >> 32) + __popc(mn & below)] = c;
     }
     if (o == 0) child[P] = make_int2(first, int(mh));
+}
+
+__global__ void k_emit(const int* __restrict__ front, int nf, int l, const uint64_t* __restrict__ keys,
+                       const int* __restrict__ bounds, const unsigned long long* __restrict__ off,
+                       int child_start, int nl_base,
+                       int4* __restrict__ anchor, int2* __restrict__ range, int* __restrict__ parent,
+                       int2* __restrict__ child, int* __restrict__ leafflag, uint64_t* __restrict__ mkey,
+                       int* __restrict__ nonleaf, int leaf_size, int adaptive, int max_depth, int Lu) {
+    const int64_t gid = int64_t(blockIdx.x) * TB + threadIdx.x;
+    const int f = int(gid >> 3), o = int(gid & 7);
+    emit_box(f < nf, f, o, l, front, keys, bounds, off, child_start, nl_base, anchor, range, parent, child, leafflag,
+             mkey, nonleaf, leaf_size, adaptive, max_depth, Lu);
+}
+
+// Every level of a small tree in one block (one launch, no read-back per
+// level): per level, split the front boxes (one wave each), scan their child
+// counts, emit the children.  lev[l] = (start, count, nl_start, nl_count);
+// lev_n[0] = number of levels, lev_n[1] = 1 when the box storage `cap` or the
+// scratch (nf_cap front boxes) would overflow, then the caller builds the
+// levels the general way.
+constexpr int LB_THREADS = 1024;
+__global__ __launch_bounds__(LB_THREADS) void k_levels_block(
+    const uint64_t* __restrict__ keys, int cap, int nf_cap, int* __restrict__ bounds,
+    unsigned long long* __restrict__ cnt, unsigned long long* __restrict__ off, int4* __restrict__ anchor,
+    int2* __restrict__ range, int* __restrict__ parent, int2* __restrict__ child, int* __restrict__ leafflag,
+    uint64_t* __restrict__ mkey, int* __restrict__ nonleaf, int4* __restrict__ lev, int* __restrict__ lev_n,
+    int leaf_size, int adaptive, int max_depth, int Lu, int root_nl) {
+    __shared__ unsigned long long wsum[LB_THREADS / 64];
+    __shared__ unsigned long long carry;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = LB_THREADS / 64;
+    int start = 0, count = 1, nl_start = 0, nl_count = root_nl;
+    int total = 1, nl_total = root_nl;
+    if (t == 0) {
+        lev[0] = make_int4(0, 1, 0, root_nl);
+        lev_n[1] = 0;
+    }
+    int l = 0;
+    for (; nl_count > 0; ++l) {
+        if (l + 1 >= kMaxLevels || nl_count > nf_cap) {
+            if (t == 0) lev_n[1] = 1;
+            break;
+        }
+        const int nf = nl_count;
+        const int* front = nonleaf + nl_start;
+        // split: one wave per front box
+        for (int f = wave; f < nf; f += nw) {
+            const unsigned long long c =
+                split_box(range[front[f]], l, keys, lane, bounds + 9 * f, leaf_size, adaptive, max_depth, Lu);
+            if (lane == 0) cnt[f] = c;
+        }
+        __syncthreads();
+        // exclusive scan of the packed counts (chunks of LB_THREADS, in order)
+        if (t == 0) carry = 0;
+        __syncthreads();
+        for (int c0 = 0; c0 < nf; c0 += LB_THREADS) {
+            const int i = c0 + t;
+            const unsigned long long v = i < nf ? cnt[i] : 0ull;
+            unsigned long long x = v;   // inclusive scan within the wave
+            for (int d = 1; d < 64; d <<= 1) {
+                const unsigned long long y = __shfl_up(x, d, 64);
+                if (lane >= d) x += y;
+            }
+            if (lane == 63) wsum[wave] = x;
+            __syncthreads();
+            if (t == 0) {
+                unsigned long long a = carry;
+                for (int w = 0; w < nw; ++w) {
+                    const unsigned long long b = wsum[w];
+                    wsum[w] = a;
+                    a += b;
+                }
+                carry = a;
+            }
+            __syncthreads();
+            if (i < nf) off[i] = wsum[wave] + x - v;
+            __syncthreads();
+        }
+        const unsigned long long tot = carry;
+        const int ncount = int(tot & 0xffffffffull), nnl = int(tot >> 32);
+        if (total + ncount > cap) {
+            if (t == 0) lev_n[1] = 1;
+            break;
+        }
+        __syncthreads();
+        // emit: eight lanes per front box
+        for (int g0 = 0; g0 < nf * 8; g0 += LB_THREADS) {
+            const int gid = g0 + t;
+            const int f = gid >> 3, o = gid & 7;
+            emit_box(f < nf, f, o, l, front, keys, bounds, off, total, nl_total, anchor, range, parent, child,
+                     leafflag, mkey, nonleaf, leaf_size, adaptive, max_depth, Lu);
+        }
+        __syncthreads();
+        start = total;
+        count = ncount;
+        nl_start = nl_total;
+        nl_count = nnl;
+        total += ncount;
+        nl_total += nnl;
+        if (t == 0) lev[l + 1] = make_int4(start, count, nl_start, nl_count);
+    }
+    if (t == 0) lev_n[0] = l + 1;
 }
 
 __global__ void k_root(int N, int leaf, int4* anchor, int2* range, int* parent, int2* child, int* leafflag,
@@ -968,6 +1198,57 @@ static int read_int(kifmm_plan* P, const int* dptr, hipStream_t s) {
     return v;
 }
 
+// Re-sort from the order of the previous build (same N): keys in that order,
+// the displaced subsequence D sorted and merged back into the rest R.  Writes
+// the sorted keys and indices (P->keys, P->tmp_b) and returns true; returns
+// false (nothing written that the full sort needs) when R is not in order or
+// D is more than a quarter of the points, for the caller's full sort.
+static bool resort(kifmm_plan* P, double scale, hipStream_t s) {
+    const int64_t N = P->N;
+    const kifmm_options& o = P->opt;
+    ++P->resort_steps;
+    const size_t n1 = size_t(N) + 1;
+    // flags, offsets, error word, D and R (keys and indices)
+    const size_t need = n1 * 4 * 2 + 64 + size_t(N) * 12 * 2 + 256;
+    P->resort.ensure(need);
+    char* base = P->resort.as<char>();
+    int* flag = reinterpret_cast<int*>(base);
+    int* dpos = flag + n1;
+    int* err = dpos + n1;
+    uint64_t* dk = reinterpret_cast<uint64_t*>(base + ((n1 * 8 + 64 + 255) & ~size_t(255)));
+    uint64_t* rk = dk + N;
+    uint32_t* dv = reinterpret_cast<uint32_t*>(rk + N);
+    uint32_t* rv = dv + N;
+    uint64_t* ka = P->tmp_c.as<uint64_t>();
+    uint32_t* va = P->tmp_d.as<uint32_t>();
+    int* bad = P->flag.as<int>();
+    KIFMM_HIP(hipMemsetAsync(err, 0, 4, s));
+    hipLaunchKernelGGL(k_keys_prev, dim3(nblocks(N)), dim3(TB), 0, s, P->x64.as<double>(), N, P->lo[0], P->lo[1],
+                       P->lo[2], scale, P->side, o.explicit_root, P->perm.as<int>(), ka, va, bad);
+    hipLaunchKernelGGL(k_displaced, dim3(nblocks(N + 1)), dim3(TB), 0, s, ka, va, N, flag);
+    exclusive_scan<int>(P, flag, dpos, N + 1, s);
+    hipLaunchKernelGGL(k_split_dr, dim3(nblocks(N)), dim3(TB), 0, s, ka, va, N, flag, dpos, dk, dv, rk, rv);
+    hipLaunchKernelGGL(k_check_sorted, dim3(nblocks(N)), dim3(TB), 0, s, rk, rv, N, dpos, err);
+    int h[2];
+    read_ints(P, s, {dpos + N, err}, h);
+    const int64_t nd = h[0], nr = N - nd;
+    if (h[1] || nd > N / 4) return false;
+    if (nd > 0) {
+        // D by key (stable, so equal keys stay in their previous order), then
+        // equal keys by index; the scratch of the full sort is free here
+        radix_sort(P, dk, dv, ka, va, nd, 63, s);
+        hipLaunchKernelGGL(k_fix_ties, dim3(nblocks(nd)), dim3(TB), 0, s, dk, dv, nd);
+    }
+    uint64_t* keys = P->keys.as<uint64_t>();
+    uint32_t* idx = P->tmp_b.as<uint32_t>();
+    if (nr > 0)
+        hipLaunchKernelGGL(k_merge_into, dim3(nblocks(nr)), dim3(TB), 0, s, rk, rv, nr, dk, dv, nd, keys, idx);
+    if (nd > 0)
+        hipLaunchKernelGGL(k_merge_into, dim3(nblocks(nd)), dim3(TB), 0, s, dk, dv, nd, rk, rv, nr, keys, idx);
+    ++P->resort_hits;
+    return true;
+}
+
 void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     const int64_t N = P->N;
     const kifmm_options& o = P->opt;
@@ -1017,11 +1298,16 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     uint64_t* keys = P->keys.as<uint64_t>();
     uint32_t* idx = P->tmp_b.as<uint32_t>();
     double scale = ldexp(1.0, kBits) / P->side;
-    hipLaunchKernelGGL(k_keys, dim3(nblocks(N)), dim3(TB), 0, s, P->x64.as<double>(), N, P->lo[0], P->lo[1],
-                       P->lo[2], scale, P->side, o.explicit_root, keys, idx, bad);
     // a flagged point gets key 0, so the build below stays in bounds; the flag
     // is read with the final counts
-    radix_sort(P, keys, idx, P->tmp_c.as<uint64_t>(), P->tmp_d.as<uint32_t>(), N, 63, s);
+    const bool prev_order = P->sorted_valid;
+    P->sorted_valid = false;
+    ++P->builds;
+    if (!(prev_order && resort(P, scale, s))) {
+        hipLaunchKernelGGL(k_keys, dim3(nblocks(N)), dim3(TB), 0, s, P->x64.as<double>(), N, P->lo[0], P->lo[1],
+                           P->lo[2], scale, P->side, o.explicit_root, keys, idx, bad);
+        radix_sort(P, keys, idx, P->tmp_c.as<uint64_t>(), P->tmp_d.as<uint32_t>(), N, 63, s);
+    }
     P->xs.ensure(size_t(N) * 16);
     P->perm.ensure(size_t(N) * 4);
     hipLaunchKernelGGL(k_gather_pos, dim3(nblocks(N)), dim3(TB), 0, s, P->x64.as<double>(), idx, N,
@@ -1053,7 +1339,42 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     L0.nl_count = root_leaf ? 0 : 1;
     P->lev.push_back(L0);
     int64_t total = 1, nl_total = L0.nl_count;
-    for (int l = 0;; ++l) {
+    // a small tree: every level in one block, one read-back of the level table
+    bool levels_done = false;
+    if (N <= kSmallTreeN && !root_leaf) {
+        const int ncap = int(cap);
+        P->tmp_a.ensure(size_t(ncap) * 9 * 4 + size_t(ncap + 1) * 16 + size_t(kMaxLevels + 1) * 16 + 256);
+        char* base = P->tmp_a.as<char>();
+        int* bounds = reinterpret_cast<int*>(base);
+        unsigned long long* cnt = reinterpret_cast<unsigned long long*>(base + ((size_t(ncap) * 9 * 4 + 15) & ~size_t(15)));
+        unsigned long long* offs = cnt + (ncap + 1);
+        int4* levt = reinterpret_cast<int4*>(offs + (ncap + 1));
+        int* levn = reinterpret_cast<int*>(levt + (kMaxLevels + 1));
+        hipLaunchKernelGGL(k_levels_block, dim3(1), dim3(LB_THREADS), 0, s, keys, ncap, ncap, bounds, cnt, offs,
+                           P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->bx_parent.as<int>(),
+                           P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->bx_mkey.as<uint64_t>(),
+                           P->nonleaf.as<int>(), levt, levn, P->leaf, o.adaptive, o.max_depth, Lu, 1);
+        int* hw = reinterpret_cast<int*>(P->host.get());
+        KIFMM_HIP(hipMemcpyAsync(hw, levn, 8, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipMemcpyAsync(hw + 4, levt, size_t(kMaxLevels + 1) * 16, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipStreamSynchronize(s));
+        if (hw[1] == 0) {
+            const int nlev = hw[0];
+            P->lev.clear();
+            for (int l = 0; l < nlev; ++l) {
+                LevelInfo li;
+                li.start = hw[4 + 4 * l];
+                li.count = hw[5 + 4 * l];
+                li.nl_start = hw[6 + 4 * l];
+                li.nl_count = hw[7 + 4 * l];
+                P->lev.push_back(li);
+            }
+            total = P->lev.back().start + P->lev.back().count;
+            levels_done = true;
+        }
+        // else: storage or scratch would overflow; build the levels below
+    }
+    for (int l = 0; !levels_done; ++l) {
         const LevelInfo cur = P->lev[l];
         if (cur.nl_count == 0) break;
         int nf = int(cur.nl_count);
@@ -1265,6 +1586,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     P->counts[7] = nu;
     P->counts[8] = N;
     P->counts[9] = P->n;
+    P->sorted_valid = true;   // perm is this build's order: the next build may start from it
 }
 
 void count_pairs(kifmm_plan* P, hipStream_t s) {

@@ -263,6 +263,12 @@ class Plan:
         check(_lib.lib().kifmm_get_m2l_rank(self.handle, out))
         return int(out[0]), int(out[1])
 
+    def build_stats(self) -> dict:
+        """Tree builds of the plan, and how many re-sorted from the previous order."""
+        out = (ctypes.c_int64 * 3)()
+        check(_lib.lib().kifmm_get_build_stats(self.handle, out))
+        return dict(builds=int(out[0]), resort_tried=int(out[1]), resort_done=int(out[2]))
+
     def operator(self, which: int):
         """(values, rank) of the plan's FP64 operators: 0 singular values of
         K(uc, ue), 1 singular values of the stacked M2L operators, 2 UC2E [n, n]."""

@@ -289,3 +289,39 @@ def test_box_storage_grows_mid_build():
     check("u", u, uo, 1e-5)
     check("E", E, Eo, 1e-5)
     G.close()
+
+
+@pytest.mark.parametrize("n", [3000, 20000])
+def test_rebuild_resorts_from_previous_order(n):
+    """Particles that move a little between builds: the rebuild starts from the
+    previous order (points out of order with a neighbour sorted on their own
+    and merged back), and keys, permutation and boxes equal the oracle's for
+    the new positions, bit for bit; coincident pairs moved together keep
+    equal keys, whose order is by caller index.  A large move falls back to
+    the full sort with the same result."""
+    from paper_2512_09478_amd import Plan
+    say(f"rebuild from the previous order, n={n}")
+    rng = np.random.default_rng(71)
+    base = workloads.clustered(rng, n - 100)
+    x = np.concatenate([base, base[:50], base[:50]])           # 50 coincident pairs
+    x = workloads.round_f32(np.clip(x, 0.0, np.nextafter(1.0, 0.0)))
+    root = ((0.0, 0.0, 0.0), 1.0)
+    G = Plan(torch.tensor(x, dtype=torch.float64, device="cuda"), "laplace", 4, 32, root=root)
+    for step, sigma in enumerate((1e-4, 1e-4, 3e-2)):
+        dx = rng.standard_normal(x.shape) * sigma
+        dx[n - 50:] = dx[n - 100:n - 50]                        # the pairs move together
+        x = workloads.round_f32(np.clip(x + dx, 0.0, np.nextafter(1.0, 0.0)))
+        G.rebuild(torch.tensor(x, dtype=torch.float64, device="cuda"))
+        t = G.tree()
+        O = kifmm.plan(x, "laplace", 4, 32, True, 21, root)
+        np.testing.assert_array_equal(t["keys"], O.tree.keys)
+        np.testing.assert_array_equal(t["perm"], O.tree.perm)
+        np.testing.assert_array_equal(t["begin"], O.tree.begin)
+        np.testing.assert_array_equal(t["level"], O.tree.level)
+        st = G.build_stats()
+        say(f"  step {step} (sigma {sigma}): {st}")
+    st = G.build_stats()
+    assert st["builds"] == 4 and st["resort_tried"] == 3 and st["resort_done"] >= 2
+    u, E = G.evaluate(torch.tensor(workloads.round_f32(rng.standard_normal(n)), dtype=torch.float32, device="cuda"))
+    assert torch.isfinite(u).all()
+    G.close()
