@@ -120,27 +120,31 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rt
     ncalls = min(2 * steps, 64)
     calls = [plan.phase_times(back) for back in range(ncalls - 1, -1, -1)]
     phases, phases_adj = calls[0::2], calls[1::2]
-    # split of one step (untimed repetitions)
-    torch.cuda.synchronize()
-    a = time.perf_counter()
-    plan.rebuild(pos)
-    torch.cuda.synchronize()
-    b = time.perf_counter()
-    if clumps is not None:
-        plan.clump_forces(q, clumps[0])
-    else:
-        plan.evaluate(q)
-    torch.cuda.synchronize()
-    c = time.perf_counter()
-    if clumps is not None:
-        plan.clump_forces_backward(q, clumps[0], clumps[1], clumps[2])
-    else:
-        plan.backward(None, gu, gE)
-    torch.cuda.synchronize()
-    d = time.perf_counter()
+    # split of a step (untimed repetitions at the last positions, mean of five)
+    split = np.zeros(3)
+    for _ in range(5):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        plan.rebuild(pos)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        if clumps is not None:
+            plan.clump_forces(q, clumps[0])
+        else:
+            plan.evaluate(q)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        if clumps is not None:
+            plan.clump_forces_backward(q, clumps[0], clumps[1], clumps[2])
+        else:
+            plan.backward(None, gu, gE)
+        torch.cuda.synchronize()
+        d = time.perf_counter()
+        split += (b - a, c - b, d - c)
+    split /= 5
     ph = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
     pha = {k: float(np.mean([p[k] for p in phases_adj])) for k in phases_adj[0]}
-    res = dict(ms_per_step=1e3 * t, t_tree_ms=1e3 * (b - a), t_fwd_ms=1e3 * (c - b), t_adj_ms=1e3 * (d - c),
+    res = dict(ms_per_step=1e3 * t, t_tree_ms=1e3 * split[0], t_fwd_ms=1e3 * split[1], t_adj_ms=1e3 * split[2],
                phases_fwd_ms=ph, phases_adj_ms=pha, counts=counts, outputs=[o.detach() for o in out],
                timed_launches=len(calls), builds=plan.build_stats())
     plan.close()

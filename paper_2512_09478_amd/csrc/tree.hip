@@ -454,11 +454,107 @@ __global__ __launch_bounds__(256) void k_rs_block(uint64_t* __restrict__ keys, u
     }
 }
 
+// The whole sort of at most RS_SMALL keys in one block of RS_SMALL_WAVES
+// waves (one launch): wave w holds keys [1024 w, 1024 (w + 1)) in registers,
+// ranks them as k_rs_scatter does and scatters each pass into the other of two
+// global buffers (keys/vals and ktmp/vtmp), from which the next pass reloads
+// its share; an even number of passes ends in keys/vals.
+constexpr int RS_SMALL_WAVES = 16;
+constexpr int RS_SMALL = RS_SMALL_WAVES * RS_WAVE_ITEMS;   // 16384 keys
+__global__ __launch_bounds__(RS_SMALL_WAVES * 64) void k_rs_small(uint64_t* __restrict__ keys,
+                                                                  uint32_t* __restrict__ vals,
+                                                                  uint64_t* __restrict__ ktmp,
+                                                                  uint32_t* __restrict__ vtmp, int n, int passes) {
+    __shared__ uint32_t cnt[RS_SMALL_WAVES][256];
+    __shared__ uint32_t scan[256];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, t = threadIdx.x;
+    const int b0 = w * RS_WAVE_ITEMS;
+    uint64_t k[RS_ITEMS];
+    uint32_t v[RS_ITEMS];
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int i = b0 + r * 64 + lane;
+        k[r] = i < n ? keys[i] : 0;
+        v[r] = i < n ? vals[i] : 0;
+    }
+    const uint64_t lt = lane_lt_mask();
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = 8 * ps;
+        uint64_t* kout = (ps & 1) ? keys : ktmp;
+        uint32_t* vout = (ps & 1) ? vals : vtmp;
+        for (int d = t; d < RS_SMALL_WAVES * 256; d += RS_SMALL_WAVES * 64) (&cnt[0][0])[d] = 0;
+        __syncthreads();
+        for (int r = 0; r < RS_ITEMS; ++r) {
+            const bool valid = b0 + r * 64 + lane < n;
+            const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+            for (int bt = 0; bt < 8; ++bt) {
+                const uint64_t m = __ballot((dg >> bt) & 1u);
+                peers &= ((dg >> bt) & 1u) ? m : ~m;
+            }
+            if (valid && (peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
+        }
+        __syncthreads();
+        // exclusive scan over the digits of the totals, then per wave
+        uint32_t tot = 0;
+        if (t < 256)
+            for (int ww = 0; ww < RS_SMALL_WAVES; ++ww) tot += cnt[ww][t];
+        if (t < 256) scan[t] = tot;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const uint32_t a = (t < 256 && t >= off) ? scan[t - off] : 0u;
+            __syncthreads();
+            if (t < 256) scan[t] += a;
+            __syncthreads();
+        }
+        if (t < 256) {
+            uint32_t run = scan[t] - tot;
+            for (int ww = 0; ww < RS_SMALL_WAVES; ++ww) {
+                const uint32_t c = cnt[ww][t];
+                cnt[ww][t] = run;   // becomes the wave's base for digit t
+                run += c;
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < RS_ITEMS; ++r) {
+            const bool valid = b0 + r * 64 + lane < n;
+            const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+            for (int bt = 0; bt < 8; ++bt) {
+                const uint64_t m = __ballot((dg >> bt) & 1u);
+                peers &= ((dg >> bt) & 1u) ? m : ~m;
+            }
+            uint32_t pos = 0;
+            if (valid) pos = cnt[w][dg] + uint32_t(__popcll(peers & lt));
+            __builtin_amdgcn_wave_barrier();
+            if (valid) {
+                kout[pos] = k[r];
+                vout[pos] = v[r];
+                if ((peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();   // the pass's stores are visible to the whole block
+        for (int r = 0; r < RS_ITEMS; ++r) {
+            const int i = b0 + r * 64 + lane;
+            if (i < n) {
+                k[r] = kout[i];
+                v[r] = vout[i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 void radix_sort(kifmm_plan* P, uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n,
                 int bits, hipStream_t s) {
     if (n <= 0) return;
     if (n <= RS_TILE) {   // one block, one launch
         hipLaunchKernelGGL(k_rs_block, dim3(1), dim3(TB), 0, s, keys, vals, int(n), (bits + 7) / 8);
+        return;
+    }
+    if (n <= RS_SMALL && ((bits + 7) / 8) % 2 == 0) {   // one larger block, one launch
+        hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(RS_SMALL_WAVES * 64), 0, s, keys, vals, ktmp, vtmp, int(n),
+                           (bits + 7) / 8);
         return;
     }
     int nblk = int((n + RS_TILE - 1) / RS_TILE);
@@ -1202,7 +1298,8 @@ static int read_int(kifmm_plan* P, const int* dptr, hipStream_t s) {
 // the displaced subsequence D sorted and merged back into the rest R.  Writes
 // the sorted keys and indices (P->keys, P->tmp_b) and returns true; returns
 // false (nothing written that the full sort needs) when R is not in order or
-// D is more than a quarter of the points, for the caller's full sort.
+// D is more than a quarter of the points (and more than one block sorts at
+// once), for the caller's full sort.
 static bool resort(kifmm_plan* P, double scale, hipStream_t s) {
     const int64_t N = P->N;
     const kifmm_options& o = P->opt;
@@ -1232,7 +1329,7 @@ static bool resort(kifmm_plan* P, double scale, hipStream_t s) {
     int h[2];
     read_ints(P, s, {dpos + N, err}, h);
     const int64_t nd = h[0], nr = N - nd;
-    if (h[1] || nd > N / 4) return false;
+    if (h[1] || (nd > N / 4 && nd > RS_TILE)) return false;
     if (nd > 0) {
         // D by key (stable, so equal keys stay in their previous order), then
         // equal keys by index; the scratch of the full sort is free here
