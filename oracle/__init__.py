@@ -20,5 +20,6 @@ Modules
   operators  surfaces, kernel matrices, truncated-SVD pseudoinverses
   kifmm      FMM forward sweep and its discrete adjoint
   clump      per-clump force and torque
+  stokes     Stokeslet sums of point forces (direct, and through the Laplace KIFMM)
   closed_forms  analytic reference values used to pin the above
 """

@@ -1,0 +1,72 @@
+"""Stokes flow of point forces -- TEST INFRASTRUCTURE ONLY.
+
+The sum of eq. (1) in Section 2.2 with a tensor kernel: the paper names
+vector and tensor kernels (and periodic Stokes sums in Section 2.4) among what
+the kernel-independent method evaluates.  For point forces f_j at x_j in a
+fluid of viscosity mu, the velocity at each point is the Stokeslet sum
+
+    u(x_i) = 1/(8 pi mu) sum_{j : x_j != x_i} [ f_j / r + (r . f_j) r / r^3 ],
+    r = x_i - x_j,  r = |r|.
+
+``direct`` is that definition written out (O(N^2), FP64).
+
+``kifmm`` evaluates the same sum with the plan's Laplace KIFMM: the Stokeslet
+is a combination of harmonic potentials and their gradients (the harmonic
+decomposition of Tornberg and Greengard, J. Comput. Phys. 227 (2008)): with
+x' = x - o for a fixed origin o,
+
+    phi_k(x) = sum_j f_{j,k} / r  (k = 1, 2, 3),   phi_4(x) = sum_j (x'_j . f_j) / r,
+    sum_j S(r) f_j = phi - x'_k grad phi_k + grad phi_4,
+
+since -x'_k d_a(f_k/r) + d_a((x'_j . f)/r) = (r . f) r_a / r^3 for each pair.
+Each phi is one charge evaluation of the plan (charges f_x, f_y, f_z and
+x'.f); the origin is the root cube's centre.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def direct(x, f, mu=1.0, targets=None, chunk=512):
+    """Velocity [nt, 3] at the points ``targets`` (all by default)."""
+    x = np.asarray(x, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64).reshape(-1, 3)
+    t = np.arange(x.shape[0]) if targets is None else np.asarray(targets)
+    out = np.zeros((t.shape[0], 3))
+    for a in range(0, t.shape[0], chunk):
+        xt = x[t[a:a + chunk]]
+        r = xt[:, None, :] - x[None, :, :]
+        r2 = np.einsum("ijk,ijk->ij", r, r)
+        inv = np.zeros_like(r2)
+        nz = r2 > 0
+        inv[nz] = 1.0 / np.sqrt(r2[nz])
+        rf = np.einsum("ijk,jk->ij", r, f)
+        out[a:a + chunk] = np.einsum("ij,jk->ik", inv, f) + np.einsum("ij,ijk->ik", rf * inv ** 3, r)
+    return out / (8.0 * math.pi * mu)
+
+
+def origin(P):
+    """The fixed origin of the decomposition: the root cube's centre."""
+    return P.tree.lo + 0.5 * P.tree.s
+
+
+def kifmm(P, f, mu=1.0, targets=None):
+    """The Stokeslet sum through four Laplace evaluations of the oracle plan
+    ``P`` (its kernel constant c = P.c): u = (1/(8 pi mu c)) [psi_a +
+    x'_k E(k)_a - E(4)_a], psi_k and E(k) = -grad psi_k the plan's potential
+    and field of the charges f_k (k = 1, 2, 3) and x'.f (k = 4)."""
+    from . import kifmm as K
+    f = np.asarray(f, dtype=np.float64).reshape(-1, 3)
+    o = origin(P)
+    xs = P.x[np.argsort(P.tree.perm)]          # caller order
+    xp = xs - o
+    charges = [f[:, 0], f[:, 1], f[:, 2], np.einsum("ij,ij->i", xp, f)]
+    res = [K.forward(P, q, targets=targets) for q in charges]
+    xt = xp if targets is None else xp[np.asarray(targets)]
+    u = np.stack([res[a][0] for a in range(3)], axis=1)
+    for k in range(3):
+        u += xt[:, k:k + 1] * res[k][1]
+    u -= res[3][1]
+    return u / (8.0 * math.pi * mu * P.c)

@@ -1,0 +1,128 @@
+"""Pins of the Stokeslet oracle (CPU only): the direct sum against closed
+forms of Stokes flow, the divergence-free velocity, the kernel's symmetry,
+and the harmonic decomposition that the fast evaluation uses."""
+import math
+
+import numpy as np
+
+import workloads
+from oracle import direct, kifmm, stokes
+from oracle.closed_forms import fibonacci_sphere
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_single_force_is_the_stokeslet():
+    f = np.array([[0.3, -1.2, 0.7], [0.0, 0.0, 0.0]])
+    x = np.array([[0.1, 0.2, 0.3], [0.6, -0.1, 0.5]])
+    u = stokes.direct(x, f, mu=2.0)
+    r = x[1] - x[0]
+    d = np.linalg.norm(r)
+    ref = (f[0] / d + np.dot(r, f[0]) * r / d ** 3) / (8 * math.pi * 2.0)
+    np.testing.assert_allclose(u[1], ref, rtol=1e-14)
+    assert np.all(u[0] == 0.0)   # no force at point 1, no self term at point 0
+
+
+def test_sphere_with_uniform_traction():
+    """A sphere of radius a carrying the uniform traction 3 mu U / (2a) (the
+    surface force of a sphere translating with velocity U in Stokes flow)
+    moves its interior rigidly with U and makes outside the flow
+    (3a/4)(U/r + (U.r) r/r^3) + (a^3/4)(U/r^3 - 3 (U.r) r/r^5); here as point
+    forces on a 4,000-point Fibonacci sphere."""
+    mu, a, N = 1.3, 0.2, 4000
+    c = np.array([0.5, 0.5, 0.5])
+    U = np.array([0.3, -0.2, 0.5])
+    y = fibonacci_sphere(N, a, c)
+    f = np.tile(6 * math.pi * mu * a * U / N, (N, 1))
+    dirs = np.array([[1.0, 0, 0], [0.3, 0.4, 0.866], [0, -1.0, 0]])
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    inside = c + np.array([[0.0, 0, 0], [0.05, 0.02, -0.03], [0.0, 0.09, 0.0]])
+    outside = c + dirs * np.array([[2 * a], [3 * a], [1.5 * a]])
+    X = np.concatenate([y, inside, outside])
+    F = np.concatenate([f, np.zeros((6, 3))])
+    u = stokes.direct(X, F, mu, targets=np.arange(N, N + 6))
+
+    def flow(p):
+        r = p - c
+        d = np.linalg.norm(r)
+        return 0.75 * a * (U / d + np.dot(U, r) * r / d ** 3) + 0.25 * a ** 3 * (U / d ** 3 - 3 * np.dot(U, r) * r / d ** 5)
+
+    ref = np.concatenate([np.tile(U, (3, 1)), np.array([flow(p) for p in outside])])
+    assert np.abs(u - ref).max() <= 1e-5 * np.linalg.norm(U)
+
+
+def test_velocity_is_divergence_free():
+    rng = np.random.default_rng(4)
+    x = rng.random((200, 3))
+    f = rng.standard_normal((200, 3))
+    probes = rng.random((5, 3)) * 0.2 + 1.2          # away from every source
+    h = 1e-4
+    div = []
+    scale = []
+    for p in probes:
+        d = 0.0
+        g = 0.0
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            X = np.concatenate([x, [p + e], [p - e]])
+            F = np.concatenate([f, np.zeros((2, 3))])
+            up, um = stokes.direct(X, F, targets=[200, 201])
+            d += (up[k] - um[k]) / (2 * h)
+            g = max(g, np.abs(up - um).max() / (2 * h))
+        div.append(d)
+        scale.append(g)
+    assert np.max(np.abs(div)) <= 1e-7 * np.max(scale)
+
+
+def test_symmetry_of_the_kernel():
+    rng = np.random.default_rng(5)
+    x = rng.random((400, 3))
+    f = rng.standard_normal((400, 3))
+    g = rng.standard_normal((400, 3))
+    a = float(np.sum(g * stokes.direct(x, f)))
+    b = float(np.sum(f * stokes.direct(x, g)))
+    assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+
+
+def test_far_field_of_a_compact_cluster():
+    rng = np.random.default_rng(6)
+    c = np.array([0.1, 0.2, 0.3])
+    s = 0.01
+    y = c + s * (rng.random((50, 3)) - 0.5)
+    f = rng.standard_normal((50, 3))
+    p = c + np.array([0.8, -0.3, 0.5])
+    u = stokes.direct(np.concatenate([y, [p]]), np.concatenate([f, [[0, 0, 0]]]), targets=[50])[0]
+    F = f.sum(axis=0)
+    r = p - c
+    d = np.linalg.norm(r)
+    ref = (F / d + np.dot(r, F) * r / d ** 3) / (8 * math.pi)
+    # the first neglected (moment) term is of relative size s / d times the
+    # ratio of the force magnitudes to their sum
+    assert np.linalg.norm(u - ref) <= 3 * (s / d) * np.abs(f).sum(axis=0).max() / (8 * math.pi * d)
+
+
+def test_harmonic_decomposition_with_direct_laplace_sums():
+    rng = np.random.default_rng(7)
+    x = rng.random((300, 3))
+    f = rng.standard_normal((300, 3))
+    o = np.array([0.5, 0.5, 0.5])
+    xp = x - o
+    res = [direct.potential_field(x, q) for q in (f[:, 0], f[:, 1], f[:, 2], np.einsum("ij,ij->i", xp, f))]
+    u = np.stack([res[k][0] for k in range(3)], axis=1) + sum(xp[:, k:k + 1] * res[k][1] for k in range(3))
+    u = (u - res[3][1]) / (8 * math.pi / (4 * math.pi))
+    assert rel(u, stokes.direct(x, f)) <= 1e-13
+
+
+def test_kifmm_stokes_converges_to_the_direct_sum():
+    w = workloads.make(2, n=6000)
+    f = workloads.round_f32(np.random.default_rng(8).standard_normal((w.n, 3)))
+    ud = stokes.direct(w.positions, f)
+    err = []
+    for p in (4, 6, 8):
+        P = kifmm.plan(w.positions, "laplace", p, 64, True, 21, w.root)
+        err.append(rel(stokes.kifmm(P, f), ud))
+    assert err[0] > 10 * err[1] > 10 * err[2]
+    assert err[1] < 5e-5 and err[2] < 5e-6
