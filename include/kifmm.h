@@ -195,6 +195,24 @@ int kifmm_evaluate_gradient(kifmm_handle h, const float* charges, const float* d
                             float* field, float* field_grad, void* stream);
 
 /*
+ * Stokes flow of point forces (the tensor Stokeslet kernel that eq. (1)
+ * covers, Section 2.2): for forces f_j at the plan's points in a fluid of
+ * viscosity mu,
+ *   u_i = 1/(8 pi mu) sum_{j : x_j != x_i} [ f_j / r + (r . f_j) r / r^3 ],  r = x_i - x_j.
+ * The near lists are summed point to point with this kernel; the rest comes
+ * from four charge evaluations of the plan's Laplace method (the harmonic
+ * decomposition of the Stokeslet: with x' = x - o, o the root cube's centre,
+ * the charges f_x, f_y, f_z and x' . f give potentials psi_k and fields E(k),
+ * and sum S f = (psi_a + x'_k E(k)_a - E(4)_a) / c).
+ *   forces     device [N][3] float, caller order.
+ *   viscosity  mu > 0.
+ *   velocity   device [N][3] float, caller order.
+ * Needs a free-space Laplace plan (KIFMM_ERR_STATE otherwise).  Two sweeps of
+ * two right-hand sides each; afterwards kifmm_backward needs its charges.
+ */
+int kifmm_evaluate_stokes(kifmm_handle h, const float* forces, double viscosity, float* velocity, void* stream);
+
+/*
  * Vector-Jacobian product of the discrete map (q, x) -> (u, E) of
  * kifmm_evaluate at the plan's positions with the tree frozen: given
  * grad_potential = dL/du and grad_field = dL/dE (either may be NULL = 0),

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <string>
 
@@ -97,13 +98,13 @@ void end_phases(kifmm_plan* P) {
 }
 
 enum NearKind { NEAR_FORWARD, NEAR_BACKWARD, NEAR_DIPOLES, NEAR_GRAD, NEAR_GRAD_DIPOLES, NEAR_FORWARD_EXCL,
-                NEAR_BACKWARD_EXCL };
+                NEAR_BACKWARD_EXCL, NEAR_STOKES };
 
 // The near field does not depend on the far-field sweep: it runs on the side
 // stream, forked from `s` after P2M (so that the sweep's first kernel is not
 // queued behind it) and joined back before the leaf evaluation, which adds it
 // to the far field.
-void fork_near(kifmm_plan* P, NearKind kind, hipStream_t s) {
+void fork_near(kifmm_plan* P, NearKind kind, hipStream_t s, double viscosity = 1.0) {
     P->nearq.make();
     hipStream_t t = P->nearq.s;
     KIFMM_HIP(hipEventRecord(P->nearq.fork, s));
@@ -112,6 +113,7 @@ void fork_near(kifmm_plan* P, NearKind kind, hipStream_t s) {
     if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[P->events.cur][0], t));
     if (kind == NEAR_BACKWARD || kind == NEAR_BACKWARD_EXCL) launch_p2p_backward(P, t, kind == NEAR_BACKWARD_EXCL);
     else if (kind == NEAR_DIPOLES) launch_p2p_dipoles(P, t);
+    else if (kind == NEAR_STOKES) launch_p2p_stokes(P, viscosity, t);
     else if (kind == NEAR_GRAD || kind == NEAR_GRAD_DIPOLES) launch_p2p_gradient(P, kind == NEAR_GRAD_DIPOLES, t);
     else launch_p2p_forward(P, t, kind == NEAR_FORWARD_EXCL);
     if (prof) KIFMM_HIP(hipEventRecord(P->events.p2p[P->events.cur][1], t));
@@ -287,6 +289,39 @@ int kifmm_evaluate_gradient(kifmm_handle h, const float* charges, const float* d
                   [&] { fork_near(P, dipoles ? NEAR_GRAD_DIPOLES : NEAR_GRAD, s); });
         join_near(P, s);
         run_far_grad(P, potential, field, field_grad, s, rhs);
+        record_phase(P, 6, s);
+        end_phases(P);
+        KIFMM_HIP(hipGetLastError());
+    });
+}
+
+int kifmm_evaluate_stokes(kifmm_handle h, const float* forces, double viscosity, float* velocity, void* stream) {
+    return guarded([&] {
+        kifmm_plan* P = checked(h);
+        if (!forces || !velocity) throw Error(KIFMM_ERR_ARG, "null forces or velocity");
+        if (!(viscosity > 0.0) || !std::isfinite(viscosity)) throw Error(KIFMM_ERR_ARG, "viscosity must be positive");
+        if (P->kernel != KIFMM_LAPLACE) throw Error(KIFMM_ERR_STATE, "Stokes sums need a Laplace plan");
+        if (P->periodic) throw Error(KIFMM_ERR_STATE, "Stokes sums are free-space only");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->last_stream = s;
+        begin_phases(P, s);
+        P->fwd_valid = false;
+        P->fwd_excl = false;
+        const size_t N = size_t(P->N);
+        float* pot = static_cast<float*>(P->stk_far.ensure(N * 16 * sizeof(float)));
+        float* fld = pot + 4 * N;
+        // charges f_x, f_y: one sweep with two right-hand sides, the Stokeslet
+        // near field on the side stream beside it
+        launch_gather_stokes(P, forces, 0, s);
+        run_sweep(P, 0, 2, s, true, [&] { fork_near(P, NEAR_STOKES, s, viscosity); });
+        for (int r = 0; r < 2; ++r) run_far_eval(P, false, pot + r * N, fld + 3 * r * N, s, r, false, false);
+        // charges f_z and x'.f
+        launch_gather_stokes(P, forces, 1, s);
+        run_sweep(P, 0, 2, s, false, [] {});
+        for (int r = 0; r < 2; ++r)
+            run_far_eval(P, false, pot + (2 + r) * N, fld + 3 * (2 + r) * N, s, r, false, false);
+        join_near(P, s);
+        launch_stokes_combine(P, viscosity, velocity, s);
         record_phase(P, 6, s);
         end_phases(P);
         KIFMM_HIP(hipGetLastError());

@@ -298,6 +298,10 @@ struct kifmm_plan {
     kifmm::DBuf clump_part;   // segment partials of the clump reductions [blocks][2][6] double
     kifmm::DBuf clump_E;      // float [N][3] pebble fields of the last kifmm_clump_forces
     kifmm::DBuf clump_Eb;     // float [N][3] its adjoint field sources
+    // Stokeslet evaluation
+    kifmm::DBuf stk;          // float4 [N] sorted forces
+    kifmm::DBuf stk_near;     // float4 [N] sorted near-field velocity
+    kifmm::DBuf stk_far;      // float [4][N] potentials, [4][N][3] fields of the harmonic charges (caller order)
 };
 
 namespace kifmm {
@@ -313,8 +317,9 @@ void v_slot_offset(int o, int j, int d[3]);
 void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between);
 // leaf evaluation; adds the near-field part and writes the caller-order
 // outputs (forward: potential, field; backward: grad_charges, grad_positions)
+// (near = false: the near-field part is not added)
 void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs = 0,
-                  bool accumulate = false);
+                  bool accumulate = false, bool near = true);
 // leaf evaluation with the field gradient (densities of right-hand side rhs)
 void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs);
 // ---- nearfield.hip
@@ -326,6 +331,11 @@ void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const
 void launch_p2p_forward(kifmm_plan* P, hipStream_t s, bool excl = false);
 void launch_p2p_backward(kifmm_plan* P, hipStream_t s, bool excl = false);
 void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s);
+// Stokeslet sources (pass 0: f_x, f_y; pass 1: f_z, x'.f) and the Stokeslet near field
+void launch_gather_stokes(kifmm_plan* P, const float* forces, int pass, hipStream_t s);
+void launch_p2p_stokes(kifmm_plan* P, double viscosity, hipStream_t s);
+// velocity from the harmonic potentials and fields (caller order) and the near part
+void launch_stokes_combine(kifmm_plan* P, double viscosity, float* velocity, hipStream_t s);
 // u, E and dE/dx of monopoles (pts.w, or src2.x with `dipoles`) and dipoles (src2.yzw)
 void launch_p2p_gradient(kifmm_plan* P, bool dipoles, hipStream_t s);
 // ---- clump.hip

@@ -722,7 +722,7 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
 // Small items give each target S lanes of a wave (as in the near field) that
 // split the surface points and are summed by shuffles.
 struct FarOut {
-    const float4* nearv;   // sorted near-field part: forward (u, E), backward (xbar, psi)
+    const float4* nearv;   // sorted near-field part: forward (u, E), backward (xbar, psi); or null
     const int* perm;       // sorted position -> caller index
     float* a;              // forward: potential [N] | backward: grad_charges [N] (either may be null)
     float* b;              // forward: field [N][3]  | backward: grad_positions [N][3]
@@ -882,7 +882,7 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
             }
         }
         // far + near, written in caller order
-        const float4 nr = out.nearv[i];
+        const float4 nr = out.nearv ? out.nearv[i] : make_float4(0.f, 0.f, 0.f, 0.f);
         const size_t j = size_t(out.perm[i]);
         float oa, ob[3];
         if (!BWD) {
@@ -1450,11 +1450,12 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
 }
 
 template <int NP>
-void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc) {
+void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc, bool near) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
     const int b2 = int(P->bfar);
-    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), out_a, out_b, nullptr, {0, 0, 0}, 0.0, acc ? 1 : 0};
+    FarOut fo{near ? P->nearv.as<float4>() : nullptr, P->perm.as<int>(), out_a, out_b, nullptr, {0, 0, 0}, 0.0,
+              acc ? 1 : 0};
     if (P->periodic) {
         fo.mom = P->mom.as<double>() + (bwd ? 0 : 16 * rhs);
         for (int d = 0; d < 3; ++d) fo.o[d] = P->lo[d] + 0.5 * P->side;
@@ -1494,6 +1495,38 @@ void far_grad_impl(kifmm_plan* P, float* pot, float* field, float* grad, hipStre
 
 }  // namespace
 
+namespace {
+// Stokeslet velocity from the four harmonic charges' potentials psi_k and
+// fields E(k) (caller order) and the near part (sorted):
+//   u_a = cf (psi_a + x'_k E(k)_a - E(4)_a) + near_a,  x' = x - o.
+__global__ void k_stokes_combine(int64_t N, const int* __restrict__ perm, const double* __restrict__ x64, double o0,
+                                 double o1, double o2, const float* __restrict__ pot, const float* __restrict__ fld,
+                                 const float4* __restrict__ near, float cf, float* __restrict__ u) {
+    int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
+    if (i >= N) return;
+    const size_t j = size_t(perm[i]);
+    const float xp[3] = {float(x64[3 * j] - o0), float(x64[3 * j + 1] - o1), float(x64[3 * j + 2] - o2)};
+    const float4 nr = near[i];
+    const float na[3] = {nr.x, nr.y, nr.z};
+    const size_t sN = size_t(N);
+    for (int a = 0; a < 3; ++a) {
+        float v = pot[a * sN + j] - fld[(3 * sN + j) * 3 + a];
+        for (int k = 0; k < 3; ++k) v += xp[k] * fld[(k * sN + j) * 3 + a];
+        u[3 * j + a] = cf * v + na[a];
+    }
+}
+}  // namespace
+
+void launch_stokes_combine(kifmm_plan* P, double viscosity, float* velocity, hipStream_t s) {
+    const int64_t N = P->N;
+    const float* pot = P->stk_far.as<float>();
+    const float* fld = pot + 4 * size_t(N);
+    const double o[3] = {P->lo[0] + 0.5 * P->side, P->lo[1] + 0.5 * P->side, P->lo[2] + 0.5 * P->side};
+    hipLaunchKernelGGL(k_stokes_combine, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, N, P->perm.as<int>(),
+                       P->x64.as<double>(), o[0], o[1], o[2], pot, fld, P->stk_near.as<float4>(),
+                       float(1.0 / (8.0 * M_PI * viscosity * P->c)), velocity);
+}
+
 void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs) {
     switch (P->npad) {
         case 32: far_grad_impl<32>(P, pot, field, grad, s, rhs); break;
@@ -1518,14 +1551,15 @@ void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const 
     }
 }
 
-void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc) {
+void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc,
+                  bool near) {
     switch (P->npad) {
-        case 32: far_impl<32>(P, backward, out_a, out_b, s, rhs, acc); break;
-        case 64: far_impl<64>(P, backward, out_a, out_b, s, rhs, acc); break;
-        case 128: far_impl<128>(P, backward, out_a, out_b, s, rhs, acc); break;
-        case 160: far_impl<160>(P, backward, out_a, out_b, s, rhs, acc); break;
-        case 224: far_impl<224>(P, backward, out_a, out_b, s, rhs, acc); break;
-        case 320: far_impl<320>(P, backward, out_a, out_b, s, rhs, acc); break;
+        case 32: far_impl<32>(P, backward, out_a, out_b, s, rhs, acc, near); break;
+        case 64: far_impl<64>(P, backward, out_a, out_b, s, rhs, acc, near); break;
+        case 128: far_impl<128>(P, backward, out_a, out_b, s, rhs, acc, near); break;
+        case 160: far_impl<160>(P, backward, out_a, out_b, s, rhs, acc, near); break;
+        case 224: far_impl<224>(P, backward, out_a, out_b, s, rhs, acc, near); break;
+        case 320: far_impl<320>(P, backward, out_a, out_b, s, rhs, acc, near); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }

@@ -17,6 +17,8 @@
 // self pair, coincident points) are skipped.  The forward kernel counts
 // 20 FLOP per pair (3 sub, 5 for r^2, rsqrt, 4 for q/r and q/r^3, 7 for the
 // four sums).
+#include <math.h>
+
 #include "common.h"
 
 namespace kifmm {
@@ -348,6 +350,67 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
     }
 }
 
+// Stokeslet sources: pass 0 sets pts.w = f_x, src2 = (f_y, 0, 0, 0) and the
+// sorted forces stk = (f_x, f_y, f_z, 0); pass 1 sets pts.w = f_z and
+// src2 = (x' . f, 0, 0, 0), x' = x - o (FP64 positions), the charges of the
+// four harmonic potentials of the decomposition.
+__global__ void k_gather_stokes(int64_t N, const float4* __restrict__ xs, const double* __restrict__ x64,
+                                const int* __restrict__ perm, const float* __restrict__ f, double o0, double o1,
+                                double o2, int pass, float4* __restrict__ pts, float4* __restrict__ src2,
+                                float4* __restrict__ stk) {
+    int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
+    if (i >= N) return;
+    const size_t j = size_t(perm[i]);
+    const float fx = f[3 * j], fy = f[3 * j + 1], fz = f[3 * j + 2];
+    float4 x = xs[i];
+    if (pass == 0) {
+        x.w = fx;
+        src2[i] = make_float4(fy, 0.f, 0.f, 0.f);
+        stk[i] = make_float4(fx, fy, fz, 0.f);
+    } else {
+        x.w = fz;
+        const double m = (x64[3 * j] - o0) * double(fx) + (x64[3 * j + 1] - o1) * double(fy) +
+                         (x64[3 * j + 2] - o2) * double(fz);
+        src2[i] = make_float4(float(m), 0.f, 0.f, 0.f);
+    }
+    pts[i] = x;
+}
+
+// Near field of point forces (the Stokeslet): u += f/r + (r.f) r/r^3 over
+// the near lists, pairs at distance zero skipped; positions from xs, forces
+// from stk (sorted); written as cst * u to out (sorted).
+__global__ __launch_bounds__(256) void k_p2p_stokes(const int2* __restrict__ items, int n_items,
+                                                    const int2* __restrict__ range, const int* __restrict__ uoff,
+                                                    const int* __restrict__ uidx, const float4* __restrict__ xs,
+                                                    const float4* __restrict__ stk, float cst,
+                                                    float4* __restrict__ out) {
+    __shared__ float4 sh[NF_STAGE];
+    __shared__ float4 sh2[NF_STAGE];
+    __shared__ float red[4][3][64];
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int2 it = items[item];
+        const int b = it.x;
+        const int nt = min(64, range[b].y - it.y);
+        const NearMap nm = near_map(it.y, nt);
+        const int i = nm.i;
+        const float4 x = nm.act ? xs[i] : make_float4(0, 0, 0, 0);
+        float v[3] = {0.f, 0.f, 0.f};
+        stream_sources(uoff, uidx, range, b, xs, stk, 0.f, sh, sh2, [&](int m) {
+            for (int j = nm.j0; j < m; j += nm.dj) {
+                const float4 y = sh[j];
+                const float4 fj = sh2[j];
+                const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
+                const float ri = rsq(dx * dx + dy * dy + dz * dz);
+                const float t = (dx * fj.x + dy * fj.y + dz * fj.z) * ri * ri * ri;
+                v[0] += fj.x * ri + t * dx;
+                v[1] += fj.y * ri + t * dy;
+                v[2] += fj.z * ri + t * dz;
+            }
+        });
+        if (near_finish<3>(v, nm, red)) out[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], 0.f);
+    }
+}
+
 }  // namespace
 
 void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const float* gfield, bool adjoint,
@@ -376,6 +439,26 @@ void launch_p2p_forward(kifmm_plan* P, hipStream_t s, bool excl) {
                            int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
                            P->pts.as<float4>(), float(P->c), float(P->side), P->nearv.as<float4>(),
                            (const int*)nullptr);
+}
+
+void launch_gather_stokes(kifmm_plan* P, const float* forces, int pass, hipStream_t s) {
+    const int64_t N = P->N;
+    P->pts.ensure(size_t(N) * 16);
+    P->src2.ensure(size_t(N) * 16);
+    P->stk.ensure(size_t(N) * 16);
+    const double o[3] = {P->lo[0] + 0.5 * P->side, P->lo[1] + 0.5 * P->side, P->lo[2] + 0.5 * P->side};
+    hipLaunchKernelGGL(k_gather_stokes, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, N, P->xs.as<float4>(),
+                       P->x64.as<double>(), P->perm.as<int>(), forces, o[0], o[1], o[2], pass, P->pts.as<float4>(),
+                       P->src2.as<float4>(), P->stk.as<float4>());
+}
+
+void launch_p2p_stokes(kifmm_plan* P, double viscosity, hipStream_t s) {
+    P->stk_near.ensure(size_t(P->N) * 16);
+    // the Stokes cell is not periodic: no image shifts in the lists
+    hipLaunchKernelGGL(k_p2p_stokes, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
+                       int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
+                       P->xs.as<float4>(), P->stk.as<float4>(), float(1.0 / (8.0 * M_PI * viscosity)),
+                       P->stk_near.as<float4>());
 }
 
 void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s) {

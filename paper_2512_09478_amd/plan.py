@@ -139,6 +139,14 @@ class Plan:
                                                  _stream(stream)))
         return u, E, G
 
+    def evaluate_stokes(self, forces, viscosity=1.0, stream=None):
+        """Velocity [N, 3] of point forces [N, 3] (Stokeslet sum) at the plan's points."""
+        f = _need(forces, torch.float32, (self.n, 3), "forces")
+        u = torch.empty((self.n, 3), dtype=torch.float32, device=f.device)
+        self._fwd_token = None
+        check(_lib.lib().kifmm_evaluate_stokes(self.handle, _ptr(f), float(viscosity), _ptr(u), _stream(stream)))
+        return u
+
     def backward(self, charges, grad_potential=None, grad_field=None, stream=None):
         """dL/dq, dL/dx.  ``charges=None`` reuses the charges and forward
         densities of the last evaluate on this plan (no forward sweep)."""
