@@ -90,7 +90,7 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rt
         gT = torch.tensor(rng.standard_normal((C, 3)), device="cuda")
         clumps = (cen, gF, gT)
 
-    def step():
+    def drift():
         if move > 0:
             pos.add_(torch.randn(pos.shape, generator=gen, dtype=pos.dtype, device=pos.device), alpha=move)
             if w.periodic:
@@ -98,6 +98,9 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rt
                 pos.sub_(lo).remainder_(w.root[1]).add_(lo)
             torch.maximum(pos, lo, out=pos)
             torch.minimum(pos, hi, out=pos)
+
+    def step():
+        drift()
         plan.rebuild(pos)
         if clumps is not None:
             cen, gF, gT = clumps
@@ -120,9 +123,11 @@ def run_path(Plan, w, pos, q, gu, gE, precision, steps, warmup, move=0.0, m2l_rt
     ncalls = min(2 * steps, 64)
     calls = [plan.phase_times(back) for back in range(ncalls - 1, -1, -1)]
     phases, phases_adj = calls[0::2], calls[1::2]
-    # split of a step (untimed repetitions at the last positions, mean of five)
+    # split of a step (untimed repetitions, mean of five; moving particles
+    # drift before each, outside the timed part)
     split = np.zeros(3)
     for _ in range(5):
+        drift()
         torch.cuda.synchronize()
         a = time.perf_counter()
         plan.rebuild(pos)
