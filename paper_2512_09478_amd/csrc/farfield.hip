@@ -377,8 +377,8 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
                                              const int* __restrict__ nonleaf, const int2* __restrict__ child,
                                              const int* __restrict__ vdense, int b2, const VOps* __restrict__ vops,
                                              const float* __restrict__ phi_u, const float* __restrict__ psi_d,
-                                             float* __restrict__ psi_m, size_t rhs_stride, size_t split_stride,
-                                             const uint4* __restrict__ ops) {
+                                             const int* __restrict__ xflag, float* __restrict__ psi_m,
+                                             size_t rhs_stride, size_t split_stride, const uint4* __restrict__ ops) {
     constexpr int RB = NP / 16, KC = NP / 32, WORDS = RB * 128;
     __shared__ uint4 lds0[WORDS];
     __shared__ uint4 lds1[WORDS];
@@ -428,12 +428,14 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
     }
     __syncthreads();
     int j = next_slot(vmask, -1);   // block-uniform; kVPerOct when this slot range is empty
-    // split 0 starts from the X-list check potential, the others from zero
+    // split 0 of a target that the P2L kernel wrote starts from its X-list
+    // check potential (no other box's value is written before), the others
+    // from zero
     v4f acc[CB][RB];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
         load_acc<NP>(acc[cb],
-                     (split == 0 && tgt[cb] >= 0 && psi_d)
+                     (split == 0 && tgt[cb] >= 0 && psi_d && xflag[tgt[cb]])
                          ? psi_d + size_t(cb % nrhs) * rhs_stride + size_t(tgt[cb]) * NP
                          : nullptr,
                      lane);
@@ -1121,7 +1123,9 @@ __global__ __launch_bounds__(256) void k_far_grad(const int2* __restrict__ items
 //   out[b][j] = sum_k in[b][k] W[j][k]        (ACCUM: out[b][j] += ...)
 // with W row-major [NOUT][NIN] and `in` the sum of nsplit arrays split_stride
 // apart.  The projection phi_k = Q^T phi_u takes W = Q^T ([kp][NP]); the
-// expansion psi_d += Q (sum of the partial psi_k) takes W = Q ([NP][kp]).
+// expansion psi_d += Q (sum of the partial psi_k) takes W = Q ([NP][kp]),
+// adding only to the boxes whose check potentials the P2L kernel wrote
+// (xflag); the others are stored.
 // A wave owns 16 boxes and CPW of the NOUT/16 column tiles (v_mfma_f32_16x16x4_f32,
 // operand layout as in the file header).  In a 16-wide k chunk the lane in
 // group kk = lane/16 loads the float4 k0 + 4 kk .. k0 + 4 kk + 3 of its box row
@@ -1130,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_far_grad(const int2* __restrict__ items
 template <int NIN, int NOUT, bool ACCUM>
 __global__ __launch_bounds__(256) void k_basis(int b0, int nb, const float* __restrict__ W,
                                                const float* __restrict__ in, int nsplit, size_t split_stride,
-                                               float* __restrict__ out) {
+                                               float* __restrict__ out, const int* __restrict__ xflag) {
     constexpr int T = NOUT / 16, NCP = T % 2 == 0 ? 2 : 1, CPW = T / NCP;   // column parts, tiles per wave
     static_assert(NIN % 32 == 0 && NOUT % 16 == 0, "tile");
     __builtin_amdgcn_s_setprio(2);   // issue ahead of the near-field waves sharing the SIMD
@@ -1175,17 +1179,10 @@ __global__ __launch_bounds__(256) void k_basis(int b0, int nb, const float* __re
         const int b = row0 + 4 * kk + v;
         if (b >= end) continue;
         float* o = out + size_t(b) * NOUT + 16 * cp * CPW + i;
+        const bool add = ACCUM && xflag[b];
 #pragma unroll
-        for (int t = 0; t < CPW; ++t) {
-            if constexpr (ACCUM) o[16 * t] += c[t][v];
-            else o[16 * t] = c[t][v];
-        }
+        for (int t = 0; t < CPW; ++t) o[16 * t] = add ? o[16 * t] + c[t][v] : c[t][v];
     }
-}
-
-__global__ void k_fill0(float* __restrict__ p, size_t n) {
-    size_t i = blockIdx.x * size_t(256) + threadIdx.x;
-    if (i < n) p[i] = 0.f;
 }
 
 int nblk(int64_t n, int per) { return int((n + per - 1) / per); }
@@ -1281,7 +1278,7 @@ void launch_m2l_tile(kifmm_plan* P, int nrhs, int rhs, hipStream_t s, const floa
 #define KIFMM_M2L_LAUNCH(SPL, CBV, OPS)                                                                          \
     hipLaunchKernelGGL((k_m2l<NP, SPL, CBV>), dim3(total), dim3(WAVES * 64), 0, s, tt, total, blocks, nsplit,  \
                        nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2, vops_device(), \
-                       phi_u, psi_d, psi_m, stride, sstride, OPS)
+                       phi_u, psi_d, P->xflag.as<int>(), psi_m, stride, sstride, OPS)
     const bool split = P->opt.precision == KIFMM_SPLIT_BF16;
     if (split) KIFMM_M2L_LAUNCH(true, M2L_CB, ops_bf16);
     else KIFMM_M2L_LAUNCH(false, M2L_CB, ops_f32);
@@ -1328,10 +1325,11 @@ void project_expand_kp(kifmm_plan* P, bool project, int r, hipStream_t s) {
     };
     if (project)
         hipLaunchKernelGGL((k_basis<NP, KP, false>), blocks(KP), dim3(256), 0, s, b0, nb, cm.qt.as<float>(),
-                           P->phi_u.as<float>() + r * sn, 1, size_t(0), P->phi_k.as<float>() + r * sk);
+                           P->phi_u.as<float>() + r * sn, 1, size_t(0), P->phi_k.as<float>() + r * sk, nullptr);
     else
         hipLaunchKernelGGL((k_basis<KP, NP, true>), blocks(NP), dim3(256), 0, s, b0, nb, cm.q.as<float>(),
-                           P->psi_m.as<float>() + r * sk, P->m2l_split_used, 2 * sk, P->psi_d.as<float>() + r * sn);
+                           P->psi_m.as<float>() + r * sk, P->m2l_split_used, 2 * sk, P->psi_d.as<float>() + r * sn,
+                           P->xflag.as<int>());
 }
 
 template <int NP>
@@ -1407,11 +1405,11 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
     if (P->cm)
         for (int r = r0; r < r1; ++r) project_expand<NP>(P, true, r, s);
     if (rec) record_phase(P, 1, s);
-    // downward check potentials: zero, X list
+    // downward check potentials of the boxes the P2L kernel sums (flagged in
+    // xflag; the M2L and the compressed expansion read no other box's value
+    // before writing it)
     for (int r = r0; r < r1; ++r) {
         float* psi_d = P->psi_d.as<float>() + r * stride;
-        size_t nz = size_t(B - b2) * NP;
-        hipLaunchKernelGGL(k_fill0, dim3(unsigned((nz + 255) / 256)), dim3(256), 0, s, psi_d + size_t(b2) * NP, nz);
         if (P->n_xboxes > 0)
             hipLaunchKernelGGL(k_p2l<NP>, dim3(unsigned(P->n_xboxes)), dim3(tpb), 0, s, P->xboxes.as<int>(),
                                P->x_off.as<int>(), P->x_idx.as<int>(), P->bx_anchor.as<int4>(),

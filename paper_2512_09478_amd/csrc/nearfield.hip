@@ -74,6 +74,19 @@ __device__ inline NearMap near_map(int first, int nt) {
     return m;
 }
 
+// Calls f(j) for this lane's staged sources j = j0, j0 + dj, ... below m.
+// Every lane of the wave has T = ceil(m / dj) or T - 1 of them (j0 < dj), and
+// its first T - 1 are below m: those steps run without a bounds check and
+// with a wave-uniform trip count, only the last one is checked.
+template <int UNROLL, class F>
+__device__ inline void for_sources(const NearMap& nm, int m, F f) {
+    const int T = __builtin_amdgcn_readfirstlane((m + nm.dj - 1) / nm.dj);
+    int j = nm.j0;
+#pragma unroll UNROLL
+    for (int st = 0; st < T - 1; ++st, j += nm.dj) f(j);
+    if (T > 0 && j < m) f(j);
+}
+
 // Sum over the S lanes of a target (lanes [g S, g S + S) of the wave); the
 // first lane of the group ends with the total.
 __device__ inline float group_sum(float v, int slice, int S) {
@@ -172,8 +185,7 @@ __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int
         const int ck = (EXCL && act) ? ckey[i] : 0;
         float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
         stream_sources(uoff, uidx, range, b, pts, nullptr, cell, sh, nullptr, [&](int m) {
-#pragma unroll 4
-            for (int j = nm.j0; j < m; j += nm.dj) {
+            for_sources<4>(nm, m, [&](int j) {
                 const float4 y = sh[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
                 float ri = rsq(dx * dx + dy * dy + dz * dz);
@@ -184,7 +196,7 @@ __global__ __launch_bounds__(256) void k_p2p(const int2* __restrict__ items, int
                 v[1] += qr3 * dx;
                 v[2] += qr3 * dy;
                 v[3] += qr3 * dz;
-            }
+            });
         }, EXCL ? ckey : nullptr, shk);
         if (near_finish<4>(v, nm, red)) nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
     }
@@ -210,7 +222,7 @@ __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items,
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
         stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
-            for (int j = nm.j0; j < m; j += nm.dj) {
+            for_sources<1>(nm, m, [&](int j) {
                 const float4 y = sh[j];
                 const float4 bj = sh2[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
@@ -223,7 +235,7 @@ __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items,
                 v[1] += gh * dx + bj.y * ri3;
                 v[2] += gh * dy + bj.z * ri3;
                 v[3] += gh * dz + bj.w * ri3;
-            }
+            });
         });
         if (near_finish<4>(v, nm, red)) nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
     }
@@ -252,7 +264,7 @@ __global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // u, E xyz, dE/dx xx yy zz xy xz yz
         stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
-            for (int j = nm.j0; j < m; j += nm.dj) {
+            for_sources<1>(nm, m, [&](int j) {
                 const float4 y = sh[j];
                 const float4 bj = src2 ? sh2[j] : make_float4(y.w, 0.f, 0.f, 0.f);
                 const float d[3] = {x.x - y.x, x.y - y.y, x.z - y.z};
@@ -276,7 +288,7 @@ __global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items
                     if (a == c) t += bj.x * ri3 - 3.f * mr * ri5;
                     v[4 + k] += t;
                 }
-            }
+            });
         });
         if (near_finish<10>(v, nm, red)) {
             nearv[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], cst * v[3]);
@@ -299,7 +311,7 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
     __shared__ float4 sh[NF_STAGE];
     __shared__ float4 sh2[NF_STAGE];
     __shared__ int shk[EXCL ? NF_STAGE : 1];
-    __shared__ float red[4][8][64];
+    __shared__ float red[4][9][64];
     // the grid strides over the items (launched with one block per item)
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int2 it = items[item];
@@ -316,11 +328,12 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
         //           + (q_j Ebar_k - q_k Ebar_j)/r^3,
         // with the target's Ebar_k taken out of the sum: v = (X xyz, S, T xyz, psi)
         // and xbar = X + S Ebar_k - q_k T;  qbar = psi = sum ubar_j/r - r.Ebar_j/r^3.
-        float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        // psi is kept as its two sums (v[7] ubar_j / r, v[8] r.Ebar_j / r^3)
+        float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         const float uk = a.x, qk = x.w;
         const int ck = (EXCL && act) ? ckey[i] : 0;
         stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
-            for (int j = nm.j0; j < m; j += nm.dj) {
+            for_sources<1>(nm, m, [&](int j) {
                 const float4 y = sh[j];
                 const float4 bj = sh2[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
@@ -328,12 +341,12 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
                 if (EXCL) ri = shk[j] != ck ? ri : 0.f;
                 const float ri2 = ri * ri;
                 const float ri3 = ri2 * ri;
-                const float ri5 = ri3 * ri2;
                 const float rk = dx * a.y + dy * a.z + dz * a.w;
                 const float rj = dx * bj.y + dy * bj.z + dz * bj.w;
                 const float t1 = uk * y.w + qk * bj.x;
                 const float t2 = y.w * rk - qk * rj;
-                const float coef = -ri3 * t1 - 3.f * ri5 * t2;
+                // -(t1 / r^3 + 3 t2 / r^5)
+                const float coef = -ri3 * (t1 + 3.f * (ri2 * t2));
                 v[0] += coef * dx;
                 v[1] += coef * dy;
                 v[2] += coef * dz;
@@ -341,12 +354,13 @@ __global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items,
                 v[4] += bj.y * ri3;
                 v[5] += bj.z * ri3;
                 v[6] += bj.w * ri3;
-                v[7] += bj.x * ri - rj * ri3;
-            }
+                v[7] += bj.x * ri;
+                v[8] += rj * ri3;
+            });
         }, EXCL ? ckey : nullptr, shk);
-        if (near_finish<8>(v, nm, red))
+        if (near_finish<9>(v, nm, red))
             nearv[i] = make_float4(cst * (v[0] + v[3] * a.y - qk * v[4]), cst * (v[1] + v[3] * a.z - qk * v[5]),
-                                   cst * (v[2] + v[3] * a.w - qk * v[6]), cst * v[7]);
+                                   cst * (v[2] + v[3] * a.w - qk * v[6]), cst * (v[7] - v[8]));
     }
 }
 
@@ -396,7 +410,7 @@ __global__ __launch_bounds__(256) void k_p2p_stokes(const int2* __restrict__ ite
         const float4 x = nm.act ? xs[i] : make_float4(0, 0, 0, 0);
         float v[3] = {0.f, 0.f, 0.f};
         stream_sources(uoff, uidx, range, b, xs, stk, 0.f, sh, sh2, [&](int m) {
-            for (int j = nm.j0; j < m; j += nm.dj) {
+            for_sources<1>(nm, m, [&](int j) {
                 const float4 y = sh[j];
                 const float4 fj = sh2[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
@@ -405,7 +419,7 @@ __global__ __launch_bounds__(256) void k_p2p_stokes(const int2* __restrict__ ite
                 v[0] += fj.x * ri + t * dx;
                 v[1] += fj.y * ri + t * dy;
                 v[2] += fj.z * ri + t * dz;
-            }
+            });
         });
         if (near_finish<3>(v, nm, red)) out[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], 0.f);
     }

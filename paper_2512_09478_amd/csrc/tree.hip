@@ -1618,11 +1618,14 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                        P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), xoff, P->x_idx.as<int>(), woff,
                        P->w_idx.as<int>(), noff, P->n_idx.as<int>(), wfoff, P->wf_idx.as<int>(), 1);
     // leaf list and X-box list
-    P->tmp_f.ensure(size_t(B + 1) * 4 * 4);
+    P->tmp_f.ensure(size_t(B + 1) * 4 * 3);
     int* fl = P->tmp_f.as<int>();
-    int* fx = fl + (B + 1);
-    int* ol = fx + (B + 1);
+    int* ol = fl + (B + 1);
     int* ox = ol + (B + 1);
+    // the X-box flags are kept: a box's downward check potential is written by
+    // the P2L kernel exactly when its flag is set
+    P->xflag.ensure(size_t(B + 1) * 4);
+    int* fx = P->xflag.as<int>();
     hipLaunchKernelGGL(k_flags, dim3(nblocks(B + 1)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->bx_range.as<int2>(),
                        P->n, xoff, b2, fl, fx);
     exclusive_scan<int>(P, fl, ol, B + 1, s);

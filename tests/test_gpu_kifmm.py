@@ -273,6 +273,33 @@ def test_deterministic_repeat(built):
     assert torch.equal(u1, u2) and torch.equal(E1, E2)
 
 
+@pytest.mark.parametrize("m2l_rtol", [0.0, 1e-6])
+def test_results_do_not_depend_on_earlier_calls(built, m2l_rtol):
+    """A forward and an adjoint give the same bits on a fresh plan and on one
+    that has evaluated other charges and adjoint sources before: no buffer
+    keeps a value from an earlier call that a later one reads (the X-list
+    check potentials of a tree with X pairs of both kinds, the M2L partials)."""
+    say(f"no state carried between calls (m2l_rtol {m2l_rtol:g})")
+    w = workloads.make(4, n=20000)
+    rng = np.random.default_rng(91)
+    f32 = lambda a: torch.tensor(workloads.round_f32(a), dtype=torch.float32, device="cuda")
+    q, q2 = f32(w.charges), f32(rng.standard_normal(w.n))
+    gu, gu2 = f32(rng.standard_normal(w.n)), f32(rng.standard_normal(w.n))
+    gE, gE2 = f32(rng.standard_normal((w.n, 3))), f32(rng.standard_normal((w.n, 3)))
+    G1 = gpu_plan(w, 32, p=6, m2l_rtol=m2l_rtol)
+    c = G1.counts()
+    assert c["x_pairs"] > 0
+    u1, E1 = G1.evaluate(q)
+    a1 = G1.backward(None, gu, gE)
+    G2 = gpu_plan(w, 32, p=6, m2l_rtol=m2l_rtol)
+    G2.evaluate(q2)
+    G2.backward(None, gu2, gE2)
+    u2, E2 = G2.evaluate(q)
+    a2 = G2.backward(None, gu, gE)
+    for name, x, y in (("u", u1, u2), ("E", E1, E2), ("qbar", a1[0], a2[0]), ("xbar", a1[1], a2[1])):
+        assert torch.equal(x, y), name
+
+
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
 def test_backward_parity(built, precision):
     say(f"backward parity {precision}")
