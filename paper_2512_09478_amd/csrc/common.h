@@ -259,6 +259,7 @@ struct kifmm_plan {
     kifmm::DBuf cal;        // int32 [B][26] coarse adjacent leaves (-1 padded)
     kifmm::DBuf vdense;     // int32 [B - start(2)][189] V sources by octant-local offset slot
     kifmm::DBuf u_off, u_idx, w_off, w_idx, x_off, x_idx;   // CSR over boxes, int32
+    kifmm::DBuf readback;   // staging words of the tree build's read-backs
     kifmm::DBuf xflag;   // [B + 1] int32: 1 for the boxes the P2L kernel writes (X lists not summed directly)
     kifmm::DBuf n_off, n_idx;   // near lists: U plus the W/X pairs summed point to point
     kifmm::DBuf wf_off, wf_idx; // W lists of the leaf evaluation (the other W pairs)

@@ -459,6 +459,7 @@ __global__ __launch_bounds__(256) void k_rs_block(uint64_t* __restrict__ keys, u
 // ranks them as k_rs_scatter does and scatters each pass into the other of two
 // global buffers (keys/vals and ktmp/vtmp), from which the next pass reloads
 // its share; an even number of passes ends in keys/vals.
+constexpr int kItemOrderMin = 1024;   // leaf work items sorted by cost only above this count
 constexpr int RS_SMALL_WAVES = 16;
 constexpr int RS_SMALL = RS_SMALL_WAVES * RS_WAVE_ITEMS;   // 16384 keys
 __global__ __launch_bounds__(RS_SMALL_WAVES * 64) void k_rs_small(uint64_t* __restrict__ keys,
@@ -1133,6 +1134,11 @@ __global__ void k_flags(int B, const int* __restrict__ leafflag, const int2* __r
     fx[b] = (b >= b2 && xcnt[b + 1] > xcnt[b] && !direct_xw(b, leafflag, range, n)) ? 1 : 0;
 }
 
+__global__ void k_zero4(int n, int* __restrict__ a, int* __restrict__ b, int* __restrict__ c, int* __restrict__ d) {
+    const int i = blockIdx.x * TB + threadIdx.x;
+    if (i < n) a[i] = b[i] = c[i] = d[i] = 0;
+}
+
 __global__ void k_compact(int B, const int* __restrict__ flag, const int* __restrict__ off, int* __restrict__ out) {
     int b = blockIdx.x * TB + threadIdx.x;
     if (b >= B) return;
@@ -1280,12 +1286,33 @@ void v_slot_offset(int o, int j, int d[3]) {
 }
 
 // Read device ints through the plan's pinned words (one copy each, one wait).
+struct IntPicks {
+    const int* p[8];
+    int n;
+};
+
+__global__ void k_pick_ints(IntPicks a, int* __restrict__ out) {
+    if (int(threadIdx.x) < a.n) out[threadIdx.x] = *a.p[threadIdx.x];
+}
+
+// Read up to eight device ints: gathered into one staging word array by a
+// one-wave kernel, then one copy and one synchronisation.
 static void read_ints(kifmm_plan* P, hipStream_t s, std::initializer_list<const int*> src, int* dst) {
     int* h = reinterpret_cast<int*>(P->host.get());
-    int k = 0;
-    for (const int* d : src) KIFMM_HIP(hipMemcpyAsync(h + k++, d, 4, hipMemcpyDeviceToHost, s));
+    IntPicks a{};
+    for (const int* d : src) {
+        if (a.n == 8) throw Error(KIFMM_ERR_STATE, "too many values in one read-back");
+        a.p[a.n++] = d;
+    }
+    if (a.n == 1) {
+        KIFMM_HIP(hipMemcpyAsync(h, a.p[0], 4, hipMemcpyDeviceToHost, s));
+    } else {
+        P->readback.ensure(64);
+        hipLaunchKernelGGL(k_pick_ints, dim3(1), dim3(64), 0, s, a, P->readback.as<int>());
+        KIFMM_HIP(hipMemcpyAsync(h, P->readback.as<int>(), size_t(a.n) * 4, hipMemcpyDeviceToHost, s));
+    }
     KIFMM_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < k; ++i) dst[i] = h[i];
+    for (int i = 0; i < a.n; ++i) dst[i] = h[i];
 }
 
 static int read_int(kifmm_plan* P, const int* dptr, hipStream_t s) {
@@ -1451,19 +1478,21 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                            P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->bx_parent.as<int>(),
                            P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->bx_mkey.as<uint64_t>(),
                            P->nonleaf.as<int>(), levt, levn, P->leaf, o.adaptive, o.max_depth, Lu, 1);
+        // the level table and, right after it, the two counters in one copy
+        static_assert((kMaxLevels + 1) * 16 + 8 <= 512, "host words");
         int* hw = reinterpret_cast<int*>(P->host.get());
-        KIFMM_HIP(hipMemcpyAsync(hw, levn, 8, hipMemcpyDeviceToHost, s));
-        KIFMM_HIP(hipMemcpyAsync(hw + 4, levt, size_t(kMaxLevels + 1) * 16, hipMemcpyDeviceToHost, s));
+        KIFMM_HIP(hipMemcpyAsync(hw, levt, size_t(kMaxLevels + 1) * 16 + 8, hipMemcpyDeviceToHost, s));
         KIFMM_HIP(hipStreamSynchronize(s));
-        if (hw[1] == 0) {
-            const int nlev = hw[0];
+        const int* hn = hw + 4 * (kMaxLevels + 1);
+        if (hn[1] == 0) {
+            const int nlev = hn[0];
             P->lev.clear();
             for (int l = 0; l < nlev; ++l) {
                 LevelInfo li;
-                li.start = hw[4 + 4 * l];
-                li.count = hw[5 + 4 * l];
-                li.nl_start = hw[6 + 4 * l];
-                li.nl_count = hw[7 + 4 * l];
+                li.start = hw[4 * l];
+                li.count = hw[1 + 4 * l];
+                li.nl_start = hw[2 + 4 * l];
+                li.nl_count = hw[3 + 4 * l];
                 P->lev.push_back(li);
             }
             total = P->lev.back().start + P->lev.back().count;
@@ -1548,7 +1577,15 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     // X lists (rows over all boxes; non-empty from the first far-field level)
     P->x_off.ensure(size_t(B + 1) * 4);
     int* xoff = P->x_off.as<int>();
-    KIFMM_HIP(hipMemsetAsync(xoff, 0, size_t(B + 1) * 4, s));
+    P->u_off.ensure(size_t(B + 1) * 4);
+    int* uoff = P->u_off.as<int>();
+    P->tmp_e.ensure(size_t(B + 1) * 4 * 2);
+    int* cursor = P->tmp_e.as<int>();
+    int* fcnt = cursor + (B + 1);
+    P->w_off.ensure(size_t(B + 1) * 4);
+    int* woff = P->w_off.as<int>();
+    // the X, U, finer-U and W counts start at zero: one launch for the four
+    hipLaunchKernelGGL(k_zero4, dim3(nblocks(B + 1)), dim3(TB), 0, s, B + 1, xoff, uoff, fcnt, woff);
     if (nvb > 0)
         hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
                            P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
@@ -1567,13 +1604,6 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
                            P->x_idx.as<int>(), 1);
     }
     // U lists
-    P->u_off.ensure(size_t(B + 1) * 4);
-    int* uoff = P->u_off.as<int>();
-    P->tmp_e.ensure(size_t(B + 1) * 4 * 2);
-    int* cursor = P->tmp_e.as<int>();
-    int* fcnt = cursor + (B + 1);
-    KIFMM_HIP(hipMemsetAsync(uoff, 0, size_t(B + 1) * 4, s));
-    KIFMM_HIP(hipMemsetAsync(fcnt, 0, size_t(B + 1) * 4, s));
     hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
                        P->cal.as<int>(), uoff, (int*)nullptr, (int*)nullptr, 0);
     hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
@@ -1585,9 +1615,6 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
                        (int*)nullptr, P->u_idx.as<int>(), cursor, 1);
     // W lists = transpose of X
-    P->w_off.ensure(size_t(B + 1) * 4);
-    int* woff = P->w_off.as<int>();
-    KIFMM_HIP(hipMemsetAsync(woff, 0, size_t(B + 1) * 4, s));
     if (nvb > 0)
         hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(), woff,
                            (int*)nullptr, (int*)nullptr, 0);
@@ -1667,8 +1694,12 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         P->tmp_c.ensure(size_t(ni) * 8);
         hipLaunchKernelGGL(k_item_fill, dim3(nblocks(nl, 4)), dim3(TB), 0, s, nl, P->leaves.as<int>(),
                            P->bx_range.as<int2>(), noff, P->n_idx.as<int>(), wfoff, b2, ioff, items, kn, kf, idn, idf);
-        radix_sort(P, kn, idn, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
-        radix_sort(P, kf, idf, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
+        // a grid this small runs in one round on the chip, where the order
+        // of the items does not matter: leaf order (the identity ids)
+        if (ni > kItemOrderMin) {
+            radix_sort(P, kn, idn, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
+            radix_sort(P, kf, idf, P->tmp_c.as<uint64_t>(), vtmp, ni, 8, s);
+        }
         P->items_near.ensure(size_t(ni) * 8);
         P->items_far.ensure(size_t(ni) * 8);
         hipLaunchKernelGGL(k_item_gather, dim3(nblocks(ni)), dim3(TB), 0, s, ni, items, idn, idf,
