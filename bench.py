@@ -411,7 +411,7 @@ def summarize_counters(csv_a, counts_json, out, cmd_a):
         for (k, t, mf, iv, im) in rows[:16]:
             f.write(f"| `{k[0]}` | {k[1]} | {t * 1e6:.1f} | {mf:.3f} | {iv:.4g} | {im:.4g} |" + nl)
         m2l = [r for r in rows if r[0][0].startswith("void k_m2l")]
-        p2p = [r for r in rows if r[0][0] == "k_p2p"]
+        p2p = [r for r in rows if r[0][0].split("<")[0].split()[-1] == "k_p2p"]
         f.write(nl + "Achieved rates in this run (algorithmic work over the dispatch's own duration):" + nl + nl)
         if m2l:
             t = m2l[0][1]
