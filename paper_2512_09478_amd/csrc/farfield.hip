@@ -386,12 +386,14 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
     __shared__ short sop[kVPerOct];   // operator index of each V slot of octant o
     __builtin_amdgcn_s_setprio(2);   // issue ahead of the near-field waves sharing the SIMD
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
-    // logical tile order (split, octant, level, parent group): the blocks an XCD
-    // runs together share one window of operators and neighbouring sources
+    // logical tile order (split, level, parent group, octant): the blocks an
+    // XCD runs together are the eight octants of neighbouring parent groups,
+    // which read the same source boxes (the children of the parents'
+    // colleagues) through one slot range; this reuse of sources in L2 paid
+    // more than the octant-major order's reuse of operators
     const int lid = xcd_remap(blockIdx.x, nblk);
     const int split = lid / ntile, rest = lid % ntile;
-    const int ngroups = ntile / 8;
-    const int o = rest / ngroups, bid = rest % ngroups;
+    const int o = rest % 8, bid = rest / 8;
     const int j_lo = split * kVPerOct / nsplit, j_hi = (split + 1) * kVPerOct / nsplit;
     int e = 0;
     while (e + 1 < tt.nlev && bid >= tt.first[e + 1]) ++e;
