@@ -720,16 +720,25 @@ __global__ __launch_bounds__(LB_THREADS) void k_levels_block(
     unsigned long long* __restrict__ cnt, unsigned long long* __restrict__ off, int4* __restrict__ anchor,
     int2* __restrict__ range, int* __restrict__ parent, int2* __restrict__ child, int* __restrict__ leafflag,
     uint64_t* __restrict__ mkey, int* __restrict__ nonleaf, int4* __restrict__ lev, int* __restrict__ lev_n,
-    int leaf_size, int adaptive, int max_depth, int Lu, int root_nl) {
+    int leaf_size, int adaptive, int max_depth, int Lu, int root_nl, int N) {
     __shared__ unsigned long long wsum[LB_THREADS / 64];
     __shared__ unsigned long long carry;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = LB_THREADS / 64;
     int start = 0, count = 1, nl_start = 0, nl_count = root_nl;
     int total = 1, nl_total = root_nl;
     if (t == 0) {
+        // the root box (a non-leaf here), as k_root writes it for the general build
+        anchor[0] = make_int4(0, 0, 0, 0);
+        range[0] = make_int2(0, N);
+        parent[0] = -1;
+        child[0] = make_int2(-1, 0);
+        leafflag[0] = 0;
+        mkey[0] = 0;
+        nonleaf[0] = 0;
         lev[0] = make_int4(0, 1, 0, root_nl);
         lev_n[1] = 0;
     }
+    __syncthreads();
     int l = 0;
     for (; nl_count > 0; ++l) {
         if (l + 1 >= kMaxLevels || nl_count > nf_cap) {
@@ -1452,9 +1461,12 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     };
     ensure_boxes(cap, 0);
     int root_leaf = o.adaptive ? (N <= P->leaf || o.max_depth == 0) : (Lu == 0);
-    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, int(N), root_leaf, P->bx_anchor.as<int4>(),
-                       P->bx_range.as<int2>(), P->bx_parent.as<int>(), P->bx_child.as<int2>(),
-                       P->bx_leaf.as<int>(), P->bx_mkey.as<uint64_t>(), P->nonleaf.as<int>());
+    // a small tree builds every level in one block, which writes the root too
+    const bool small_tree = N <= kSmallTreeN && !root_leaf;
+    if (!small_tree)
+        hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, int(N), root_leaf, P->bx_anchor.as<int4>(),
+                           P->bx_range.as<int2>(), P->bx_parent.as<int>(), P->bx_child.as<int2>(),
+                           P->bx_leaf.as<int>(), P->bx_mkey.as<uint64_t>(), P->nonleaf.as<int>());
     P->lev.clear();
     LevelInfo L0;
     L0.start = 0;
@@ -1465,7 +1477,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     int64_t total = 1, nl_total = L0.nl_count;
     // a small tree: every level in one block, one read-back of the level table
     bool levels_done = false;
-    if (N <= kSmallTreeN && !root_leaf) {
+    if (small_tree) {
         const int ncap = int(cap);
         P->tmp_a.ensure(size_t(ncap) * 9 * 4 + size_t(ncap + 1) * 16 + size_t(kMaxLevels + 1) * 16 + 256);
         char* base = P->tmp_a.as<char>();
@@ -1477,7 +1489,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
         hipLaunchKernelGGL(k_levels_block, dim3(1), dim3(LB_THREADS), 0, s, keys, ncap, ncap, bounds, cnt, offs,
                            P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->bx_parent.as<int>(),
                            P->bx_child.as<int2>(), P->bx_leaf.as<int>(), P->bx_mkey.as<uint64_t>(),
-                           P->nonleaf.as<int>(), levt, levn, P->leaf, o.adaptive, o.max_depth, Lu, 1);
+                           P->nonleaf.as<int>(), levt, levn, P->leaf, o.adaptive, o.max_depth, Lu, 1, int(N));
         // the level table and, right after it, the two counters in one copy
         static_assert((kMaxLevels + 1) * 16 + 8 <= 512, "host words");
         int* hw = reinterpret_cast<int*>(P->host.get());
