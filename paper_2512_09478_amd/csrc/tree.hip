@@ -369,10 +369,15 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* __restrict__
     }
 }
 
+// Keys per wave when n keys are dealt to nw waves in contiguous runs of whole
+// rounds of 64 (at most RS_WAVE_ITEMS): a small sort takes only the rounds
+// it needs, on every wave alike.
+__device__ inline int rs_chunk(int n, int nw) { return ((n + 64 * nw - 1) / (64 * nw)) * 64; }
+
 // The whole sort of at most RS_TILE keys in one block: each pass ranks the
-// keys as k_rs_scatter does (wave w owns the quarter [w*1024, (w+1)*1024),
+// keys as k_rs_scatter does (wave w owns the contiguous run [w*cw, (w+1)*cw),
 // peers by ballots), takes the digit offsets from the block's own counts and
-// scatters into LDS, from where the next pass reloads its quarter.
+// scatters into LDS, from where the next pass reloads its run.
 __global__ __launch_bounds__(256) void k_rs_block(uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, int n,
                                                   int passes) {
     __shared__ uint64_t sk[RS_TILE];
@@ -380,28 +385,33 @@ __global__ __launch_bounds__(256) void k_rs_block(uint64_t* __restrict__ keys, u
     __shared__ uint32_t cnt[4][256];
     __shared__ uint32_t base[4][256];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int b0 = w * RS_WAVE_ITEMS;
+    const int cw = rs_chunk(n, 4), nr = cw / 64;
+    const int b0 = w * cw;
     uint64_t k[RS_ITEMS];
     uint32_t v[RS_ITEMS];
+#pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
         const int i = b0 + r * 64 + lane;
-        k[r] = i < n ? keys[i] : 0;
-        v[r] = i < n ? vals[i] : 0;
+        k[r] = (r < nr && i < n) ? keys[i] : 0;
+        v[r] = (r < nr && i < n) ? vals[i] : 0;
     }
     const uint64_t lt = lane_lt_mask();
     for (int ps = 0; ps < passes; ++ps) {
         const int shift = 8 * ps;
         for (int d = threadIdx.x; d < 4 * 256; d += TB) (&cnt[0][0])[d] = 0;
         __syncthreads();
+#pragma unroll
         for (int r = 0; r < RS_ITEMS; ++r) {
-            const bool valid = b0 + r * 64 + lane < n;
-            const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
-            uint64_t peers = __ballot(valid);
-            for (int bt = 0; bt < 8; ++bt) {
-                const uint64_t m = __ballot((dg >> bt) & 1u);
-                peers &= ((dg >> bt) & 1u) ? m : ~m;
+            if (r < nr) {
+                const bool valid = b0 + r * 64 + lane < n;
+                const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+                uint64_t peers = __ballot(valid);
+                for (int bt = 0; bt < 8; ++bt) {
+                    const uint64_t m = __ballot((dg >> bt) & 1u);
+                    peers &= ((dg >> bt) & 1u) ? m : ~m;
+                }
+                if (valid && (peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
             }
-            if (valid && (peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
         }
         __syncthreads();
         {
@@ -417,37 +427,42 @@ __global__ __launch_bounds__(256) void k_rs_block(uint64_t* __restrict__ keys, u
             }
         }
         __syncthreads();
+#pragma unroll
         for (int r = 0; r < RS_ITEMS; ++r) {
-            const bool valid = b0 + r * 64 + lane < n;
-            const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
-            uint64_t peers = __ballot(valid);
-            for (int bt = 0; bt < 8; ++bt) {
-                const uint64_t m = __ballot((dg >> bt) & 1u);
-                peers &= ((dg >> bt) & 1u) ? m : ~m;
+            if (r < nr) {
+                const bool valid = b0 + r * 64 + lane < n;
+                const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+                uint64_t peers = __ballot(valid);
+                for (int bt = 0; bt < 8; ++bt) {
+                    const uint64_t m = __ballot((dg >> bt) & 1u);
+                    peers &= ((dg >> bt) & 1u) ? m : ~m;
+                }
+                uint32_t pos = 0;
+                if (valid) pos = base[w][dg] + uint32_t(__popcll(peers & lt));
+                __builtin_amdgcn_wave_barrier();
+                if (valid) {
+                    sk[pos] = k[r];
+                    sv[pos] = v[r];
+                    if ((peers & lt) == 0) base[w][dg] += uint32_t(__popcll(peers));
+                }
+                __builtin_amdgcn_wave_barrier();
             }
-            uint32_t pos = 0;
-            if (valid) pos = base[w][dg] + uint32_t(__popcll(peers & lt));
-            __builtin_amdgcn_wave_barrier();
-            if (valid) {
-                sk[pos] = k[r];
-                sv[pos] = v[r];
-                if ((peers & lt) == 0) base[w][dg] += uint32_t(__popcll(peers));
-            }
-            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
+#pragma unroll
         for (int r = 0; r < RS_ITEMS; ++r) {
             const int i = b0 + r * 64 + lane;
-            if (i < n) {
+            if (r < nr && i < n) {
                 k[r] = sk[i];
                 v[r] = sv[i];
             }
         }
         __syncthreads();
     }
+#pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
         const int i = b0 + r * 64 + lane;
-        if (i < n) {
+        if (r < nr && i < n) {
             keys[i] = k[r];
             vals[i] = v[r];
         }
@@ -455,7 +470,7 @@ __global__ __launch_bounds__(256) void k_rs_block(uint64_t* __restrict__ keys, u
 }
 
 // The whole sort of at most RS_SMALL keys in one block of RS_SMALL_WAVES
-// waves (one launch): wave w holds keys [1024 w, 1024 (w + 1)) in registers,
+// waves (one launch): wave w holds the run [w cw, (w + 1) cw) in registers,
 // ranks them as k_rs_scatter does and scatters each pass into the other of two
 // global buffers (keys/vals and ktmp/vtmp), from which the next pass reloads
 // its share; an even number of passes ends in keys/vals.
@@ -469,13 +484,15 @@ __global__ __launch_bounds__(RS_SMALL_WAVES * 64) void k_rs_small(uint64_t* __re
     __shared__ uint32_t cnt[RS_SMALL_WAVES][256];
     __shared__ uint32_t scan[256];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, t = threadIdx.x;
-    const int b0 = w * RS_WAVE_ITEMS;
+    const int cw = rs_chunk(n, RS_SMALL_WAVES), nr = cw / 64;
+    const int b0 = w * cw;
     uint64_t k[RS_ITEMS];
     uint32_t v[RS_ITEMS];
+#pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
         const int i = b0 + r * 64 + lane;
-        k[r] = i < n ? keys[i] : 0;
-        v[r] = i < n ? vals[i] : 0;
+        k[r] = (r < nr && i < n) ? keys[i] : 0;
+        v[r] = (r < nr && i < n) ? vals[i] : 0;
     }
     const uint64_t lt = lane_lt_mask();
     for (int ps = 0; ps < passes; ++ps) {
@@ -484,15 +501,18 @@ __global__ __launch_bounds__(RS_SMALL_WAVES * 64) void k_rs_small(uint64_t* __re
         uint32_t* vout = (ps & 1) ? vals : vtmp;
         for (int d = t; d < RS_SMALL_WAVES * 256; d += RS_SMALL_WAVES * 64) (&cnt[0][0])[d] = 0;
         __syncthreads();
+#pragma unroll
         for (int r = 0; r < RS_ITEMS; ++r) {
-            const bool valid = b0 + r * 64 + lane < n;
-            const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
-            uint64_t peers = __ballot(valid);
-            for (int bt = 0; bt < 8; ++bt) {
-                const uint64_t m = __ballot((dg >> bt) & 1u);
-                peers &= ((dg >> bt) & 1u) ? m : ~m;
+            if (r < nr) {
+                const bool valid = b0 + r * 64 + lane < n;
+                const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+                uint64_t peers = __ballot(valid);
+                for (int bt = 0; bt < 8; ++bt) {
+                    const uint64_t m = __ballot((dg >> bt) & 1u);
+                    peers &= ((dg >> bt) & 1u) ? m : ~m;
+                }
+                if (valid && (peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
             }
-            if (valid && (peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
         }
         __syncthreads();
         // exclusive scan over the digits of the totals, then per wave
@@ -516,28 +536,32 @@ __global__ __launch_bounds__(RS_SMALL_WAVES * 64) void k_rs_small(uint64_t* __re
             }
         }
         __syncthreads();
+#pragma unroll
         for (int r = 0; r < RS_ITEMS; ++r) {
-            const bool valid = b0 + r * 64 + lane < n;
-            const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
-            uint64_t peers = __ballot(valid);
-            for (int bt = 0; bt < 8; ++bt) {
-                const uint64_t m = __ballot((dg >> bt) & 1u);
-                peers &= ((dg >> bt) & 1u) ? m : ~m;
+            if (r < nr) {
+                const bool valid = b0 + r * 64 + lane < n;
+                const uint32_t dg = uint32_t(k[r] >> shift) & 255u;
+                uint64_t peers = __ballot(valid);
+                for (int bt = 0; bt < 8; ++bt) {
+                    const uint64_t m = __ballot((dg >> bt) & 1u);
+                    peers &= ((dg >> bt) & 1u) ? m : ~m;
+                }
+                uint32_t pos = 0;
+                if (valid) pos = cnt[w][dg] + uint32_t(__popcll(peers & lt));
+                __builtin_amdgcn_wave_barrier();
+                if (valid) {
+                    kout[pos] = k[r];
+                    vout[pos] = v[r];
+                    if ((peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
+                }
+                __builtin_amdgcn_wave_barrier();
             }
-            uint32_t pos = 0;
-            if (valid) pos = cnt[w][dg] + uint32_t(__popcll(peers & lt));
-            __builtin_amdgcn_wave_barrier();
-            if (valid) {
-                kout[pos] = k[r];
-                vout[pos] = v[r];
-                if ((peers & lt) == 0) cnt[w][dg] += uint32_t(__popcll(peers));
-            }
-            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();   // the pass's stores are visible to the whole block
+#pragma unroll
         for (int r = 0; r < RS_ITEMS; ++r) {
             const int i = b0 + r * 64 + lane;
-            if (i < n) {
+            if (r < nr && i < n) {
                 k[r] = kout[i];
                 v[r] = vout[i];
             }
@@ -549,11 +573,14 @@ __global__ __launch_bounds__(RS_SMALL_WAVES * 64) void k_rs_small(uint64_t* __re
 void radix_sort(kifmm_plan* P, uint64_t* keys, uint32_t* vals, uint64_t* ktmp, uint32_t* vtmp, int64_t n,
                 int bits, hipStream_t s) {
     if (n <= 0) return;
-    if (n <= RS_TILE) {   // one block, one launch
+    const bool even = ((bits + 7) / 8) % 2 == 0;
+    // one launch: up to 1,024 keys (or an odd number of passes) four waves
+    // exchanging through LDS, else sixteen waves exchanging through L2
+    if (n <= RS_TILE && (n <= 1024 || !even)) {
         hipLaunchKernelGGL(k_rs_block, dim3(1), dim3(TB), 0, s, keys, vals, int(n), (bits + 7) / 8);
         return;
     }
-    if (n <= RS_SMALL && ((bits + 7) / 8) % 2 == 0) {   // one larger block, one launch
+    if (n <= RS_SMALL && even) {
         hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(RS_SMALL_WAVES * 64), 0, s, keys, vals, ktmp, vtmp, int(n),
                            (bits + 7) / 8);
         return;
