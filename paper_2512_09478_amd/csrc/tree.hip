@@ -137,14 +137,16 @@ __global__ void k_keys_prev(const double* __restrict__ x, int64_t N, double lo0,
 
 // flag[i] = 1 when element i is out of order with any element at most
 // kResortWindow places away (so that a group of up to that many points that
-// moved together past others is taken out whole); flag[N] = 0
+// moved together past others is taken out whole); flag[N] = 0, and the error
+// word of the later order check starts at 0
 constexpr int kResortWindow = 8;
 __global__ void k_displaced(const uint64_t* __restrict__ k, const uint32_t* __restrict__ v, int64_t N,
-                            int* __restrict__ flag) {
+                            int* __restrict__ flag, int* __restrict__ err) {
     int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x;
     if (i > N) return;
     if (i == N) {
         flag[N] = 0;
+        *err = 0;
         return;
     }
     const uint64_t ki = k[i];
@@ -269,11 +271,55 @@ __global__ void k_scan_add(T* __restrict__ out, int64_t n, const T* __restrict__
         if (base + k < n) out[base + k] += a;
 }
 
+// Exclusive scan of at most SCAN_ONE values in one block of 1,024 threads
+// (one launch): thread t scans its run of 16 in registers, the run totals are
+// scanned across the wave by shuffles and across the 16 waves in LDS.
+constexpr int SCAN_ONE_THREADS = 1024, SCAN_ONE_ITEMS = 16;
+constexpr int SCAN_ONE = SCAN_ONE_THREADS * SCAN_ONE_ITEMS;   // 16384 values
+template <class T>
+__global__ __launch_bounds__(SCAN_ONE_THREADS) void k_scan_one(const T* __restrict__ in, T* __restrict__ out, int n) {
+    __shared__ T wsum[SCAN_ONE_THREADS / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int base = t * SCAN_ONE_ITEMS;
+    T v[SCAN_ONE_ITEMS];
+    T run = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ONE_ITEMS; ++k) {
+        const T x = base + k < n ? in[base + k] : T(0);
+        v[k] = run;
+        run += x;
+    }
+    T incl = run;   // inclusive scan of the run totals within the wave
+    for (int d = 1; d < 64; d <<= 1) {
+        const T y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+        T x = lane < SCAN_ONE_THREADS / 64 ? wsum[lane] : T(0);
+        for (int d = 1; d < 16; d <<= 1) {
+            const T y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane < SCAN_ONE_THREADS / 64) wsum[lane] = x;   // inclusive over the waves
+    }
+    __syncthreads();
+    const T off = (incl - run) + (w > 0 ? wsum[w - 1] : T(0));
+#pragma unroll
+    for (int k = 0; k < SCAN_ONE_ITEMS; ++k)
+        if (base + k < n) out[base + k] = v[k] + off;
+}
+
 // Exclusive scan of n values (in may equal out).  The tile sums of nested
 // levels live in four equal slabs of P->scan_tmp, sized at the top level.
 template <class T>
 void exclusive_scan(kifmm_plan* P, const T* in, T* out, int64_t n, hipStream_t s, int depth = 0) {
     if (n <= 0) return;
+    if (depth == 0 && n > SCAN_TILE && n <= SCAN_ONE) {
+        hipLaunchKernelGGL(k_scan_one<T>, dim3(1), dim3(SCAN_ONE_THREADS), 0, s, in, out, int(n));
+        return;
+    }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (depth == 0) P->scan_tmp.ensure(4 * (size_t(nb) * 8 + 256));
     if (depth >= 4) throw Error(KIFMM_ERR_STATE, "scan too deep");
@@ -1382,10 +1428,9 @@ static bool resort(kifmm_plan* P, double scale, hipStream_t s) {
     uint64_t* ka = P->tmp_c.as<uint64_t>();
     uint32_t* va = P->tmp_d.as<uint32_t>();
     int* bad = P->flag.as<int>();
-    KIFMM_HIP(hipMemsetAsync(err, 0, 4, s));
     hipLaunchKernelGGL(k_keys_prev, dim3(nblocks(N)), dim3(TB), 0, s, P->x64.as<double>(), N, P->lo[0], P->lo[1],
                        P->lo[2], scale, P->side, o.explicit_root, P->perm.as<int>(), ka, va, bad);
-    hipLaunchKernelGGL(k_displaced, dim3(nblocks(N + 1)), dim3(TB), 0, s, ka, va, N, flag);
+    hipLaunchKernelGGL(k_displaced, dim3(nblocks(N + 1)), dim3(TB), 0, s, ka, va, N, flag, err);
     exclusive_scan<int>(P, flag, dpos, N + 1, s);
     hipLaunchKernelGGL(k_split_dr, dim3(nblocks(N)), dim3(TB), 0, s, ka, va, N, flag, dpos, dk, dv, rk, rv);
     hipLaunchKernelGGL(k_check_sorted, dim3(nblocks(N)), dim3(TB), 0, s, rk, rv, N, dpos, err);
