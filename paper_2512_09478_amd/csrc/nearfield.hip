@@ -302,16 +302,21 @@ __global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items
 //   qbar_k = psi_k,  xbar_k = -ubar_k E_k - H_k Ebar_k - q_k E_psi,k
 // where E, H come from the charges q and psi, E_psi from monopoles ubar and
 // dipoles Ebar (psi = sum ubar K - Ebar . G).
+// Eight blocks per CU: the wave reduction of a small item reuses the staging
+// LDS (its first barrier follows the item's last batch), so a block holds
+// 16 KB, and the register budget is 64.
 template <bool EXCL>
-__global__ __launch_bounds__(256) void k_p2p_bwd(const int2* __restrict__ items, int n_items, const int2* __restrict__ range,
-                                                 const int* __restrict__ uoff, const int* __restrict__ uidx,
-                                                 const float4* __restrict__ pts, const float4* __restrict__ src2,
-                                                 float cst, float cell, float4* __restrict__ nearv,
-                                                 const int* __restrict__ ckey) {
-    __shared__ float4 sh[NF_STAGE];
-    __shared__ float4 sh2[NF_STAGE];
+__global__ __launch_bounds__(256, 8) void k_p2p_bwd(const int2* __restrict__ items, int n_items,
+                                                    const int2* __restrict__ range, const int* __restrict__ uoff,
+                                                    const int* __restrict__ uidx, const float4* __restrict__ pts,
+                                                    const float4* __restrict__ src2, float cst, float cell,
+                                                    float4* __restrict__ nearv, const int* __restrict__ ckey) {
+    __shared__ float4 stage[2 * NF_STAGE];
     __shared__ int shk[EXCL ? NF_STAGE : 1];
-    __shared__ float red[4][9][64];
+    float4* sh = stage;
+    float4* sh2 = stage + NF_STAGE;
+    static_assert(sizeof(float) * 4 * 9 * 64 <= sizeof(float4) * 2 * NF_STAGE, "reduction fits the staging");
+    float(*red)[9][64] = reinterpret_cast<float(*)[9][64]>(stage);
     // the grid strides over the items (launched with one block per item)
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int2 it = items[item];
