@@ -277,7 +277,7 @@ __global__ void k_scan_add(T* __restrict__ out, int64_t n, const T* __restrict__
 constexpr int SCAN_ONE_THREADS = 1024, SCAN_ONE_ITEMS = 16;
 constexpr int SCAN_ONE = SCAN_ONE_THREADS * SCAN_ONE_ITEMS;   // 16384 values
 template <class T>
-__global__ __launch_bounds__(SCAN_ONE_THREADS) void k_scan_one(const T* __restrict__ in, T* __restrict__ out, int n) {
+__device__ inline void scan_one_body(const T* __restrict__ in, T* __restrict__ out, T* __restrict__ out2, int n) {
     __shared__ T wsum[SCAN_ONE_THREADS / 64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int base = t * SCAN_ONE_ITEMS;
@@ -308,7 +308,26 @@ __global__ __launch_bounds__(SCAN_ONE_THREADS) void k_scan_one(const T* __restri
     const T off = (incl - run) + (w > 0 ? wsum[w - 1] : T(0));
 #pragma unroll
     for (int k = 0; k < SCAN_ONE_ITEMS; ++k)
-        if (base + k < n) out[base + k] = v[k] + off;
+        if (base + k < n) {
+            out[base + k] = v[k] + off;
+            if (out2) out2[base + k] = v[k] + off;
+        }
+}
+
+template <class T>
+__global__ __launch_bounds__(SCAN_ONE_THREADS) void k_scan_one(const T* __restrict__ in, T* __restrict__ out, int n) {
+    scan_one_body<T>(in, out, nullptr, n);
+}
+
+// Two independent scans of at most SCAN_ONE values, one block each; the first
+// may also write a copy of its result (out2, nullable).
+template <class T>
+__global__ __launch_bounds__(SCAN_ONE_THREADS) void k_scan_one2(const T* __restrict__ in0, T* __restrict__ out0,
+                                                                T* __restrict__ copy0, int n0,
+                                                                const T* __restrict__ in1, T* __restrict__ out1,
+                                                                int n1) {
+    if (blockIdx.x == 0) scan_one_body<T>(in0, out0, copy0, n0);
+    else scan_one_body<T>(in1, out1, nullptr, n1);
 }
 
 // Exclusive scan of n values (in may equal out).  The tile sums of nested
@@ -330,6 +349,28 @@ void exclusive_scan(kifmm_plan* P, const T* in, T* out, int64_t n, hipStream_t s
         exclusive_scan<T>(P, sums, sums, nb, s, depth + 1);
         hipLaunchKernelGGL(k_scan_add<T>, dim3(unsigned(nb)), dim3(TB), 0, s, out, n, sums);
     }
+}
+
+template <class T>
+__global__ void k_copy_int_t(const T* __restrict__ a, T* __restrict__ b, int64_t n) {
+    const int64_t i = blockIdx.x * int64_t(TB) + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// Two exclusive scans (in may equal out), in one launch when both fit one
+// block; copy0 (nullable) receives a copy of the first result; n1 = 0 scans
+// only the first.
+template <class T>
+void exclusive_scan2(kifmm_plan* P, const T* in0, T* out0, T* copy0, int64_t n0, const T* in1, T* out1, int64_t n1,
+                     hipStream_t s) {
+    if (n0 <= SCAN_ONE && n1 <= SCAN_ONE && n0 > 0) {
+        hipLaunchKernelGGL(k_scan_one2<T>, dim3(n1 > 0 ? 2 : 1), dim3(SCAN_ONE_THREADS), 0, s, in0, out0, copy0,
+                           int(n0), in1, out1, int(n1));
+        return;
+    }
+    exclusive_scan<T>(P, in0, out0, n0, s);
+    if (copy0 && n0 > 0) hipLaunchKernelGGL(k_copy_int_t<T>, dim3(nblocks(n0)), dim3(TB), 0, s, out0, copy0, n0);
+    exclusive_scan<T>(P, in1, out1, n1, s);
 }
 
 // ----------------------------------------------------------------- radix sort
@@ -1031,11 +1072,14 @@ __global__ __launch_bounds__(256) void k_cal(int b0, int nb, const int4* __restr
 
 // X(b), level >= 2: leaves adjacent to parent(b) of its level or coarser that
 // are not adjacent to b.  mode 0 counts, mode 1 fills.
-__global__ __launch_bounds__(256) void k_xlist(int b0, int nb, const int4* __restrict__ anchor,
-                                               const int* __restrict__ parent, const int* __restrict__ leafflag,
-                                               const int* __restrict__ coll, const int* __restrict__ cal,
-                                               int* __restrict__ cnt_or_off, int* __restrict__ idx, int mode) {
-    const int lane = threadIdx.x & 63, i = blockIdx.x * 4 + int(threadIdx.x >> 6);
+// The list bodies below take the block index `vb` as an argument, so that
+// independent passes can share one launch (the fused kernels further down);
+// each wave handles one box and returns on its own (no block barriers).
+__device__ inline void xlist_body(int vb, int b0, int nb, const int4* __restrict__ anchor,
+                                  const int* __restrict__ parent, const int* __restrict__ leafflag,
+                                  const int* __restrict__ coll, const int* __restrict__ cal,
+                                  int* __restrict__ cnt_or_off, int* __restrict__ idx, int mode) {
+    const int lane = threadIdx.x & 63, i = vb * 4 + int(threadIdx.x >> 6);
     if (i >= nb) return;   // whole wave
     const int b = b0 + i;
     const int P = parent[b];
@@ -1059,11 +1103,12 @@ __global__ __launch_bounds__(256) void k_xlist(int b0, int nb, const int4* __res
 }
 
 // U(b) own part: leaf colleagues (b included) and coarse adjacent leaves.
-__global__ __launch_bounds__(256) void k_ulist_own(int B, const int* __restrict__ leafflag,
-                                                   const int* __restrict__ coll, const int* __restrict__ cal,
-                                                   int* __restrict__ cnt_or_off, int* __restrict__ idx,
-                                                   int* __restrict__ cursor, int mode) {
-    const int lane = threadIdx.x & 63, b = blockIdx.x * 4 + int(threadIdx.x >> 6);
+// The count is added (the finer part's count may run in the same launch).
+__device__ inline void ulist_own_body(int vb, int B, const int* __restrict__ leafflag,
+                                      const int* __restrict__ coll, const int* __restrict__ cal,
+                                      int* __restrict__ cnt_or_off, int* __restrict__ idx,
+                                      int* __restrict__ cursor, int mode) {
+    const int lane = threadIdx.x & 63, b = vb * 4 + int(threadIdx.x >> 6);
     if (b >= B || !leafflag[b]) return;   // whole wave
     const int Q = wave_candidate(lane, b, b > 0, coll, cal);
     const bool keep = Q >= 0 && (lane >= 27 || leafflag[img_box(Q)]);
@@ -1074,17 +1119,17 @@ __global__ __launch_bounds__(256) void k_ulist_own(int B, const int* __restrict_
         if (keep) idx[at + __popcll(m & lane_lt_mask())] = Q;
         if (lane == 0) cursor[b] = at + c;
     } else if (lane == 0) {
-        cnt_or_off[b] = c;
+        atomicAdd(&cnt_or_off[b], c);
     }
 }
 
 // U(b) finer part: every leaf A lists b in cal[A]  ->  A in U(b) (an image
 // of b seen from A is A seen from b with the shift negated).  One wave per
 // leaf A, one lane per cal entry (the row sort undoes the atomics' order).
-__global__ __launch_bounds__(256) void k_ulist_fine(int B, const int* __restrict__ leafflag,
-                                                    const int* __restrict__ cal, int* __restrict__ cnt,
-                                                    int* __restrict__ idx, int* __restrict__ cursor, int mode) {
-    const int lane = threadIdx.x & 63, a = blockIdx.x * 4 + int(threadIdx.x >> 6);
+__device__ inline void ulist_fine_body(int vb, int B, const int* __restrict__ leafflag,
+                                       const int* __restrict__ cal, int* __restrict__ cnt,
+                                       int* __restrict__ idx, int* __restrict__ cursor, int mode) {
+    const int lane = threadIdx.x & 63, a = vb * 4 + int(threadIdx.x >> 6);
     if (a >= B || a == 0 || !leafflag[a] || lane >= 26) return;   // a root leaf has no coarse adjacent leaves
     const int e = cal[26 * int64_t(a) + lane];
     if (e < 0) return;   // the row ends at its first -1
@@ -1095,10 +1140,10 @@ __global__ __launch_bounds__(256) void k_ulist_fine(int B, const int* __restrict
 
 // W(b) = {A : b in X(A)}.  One wave per box A, one lane per X(A) entry (the
 // order the atomics give is undone by the row sort).
-__global__ __launch_bounds__(256) void k_wlist(int b0, int nb, const int* __restrict__ xoff,
-                                               const int* __restrict__ xidx, int* __restrict__ cnt,
-                                               int* __restrict__ idx, int* __restrict__ cursor, int mode) {
-    const int lane = threadIdx.x & 63, i = blockIdx.x * 4 + int(threadIdx.x >> 6);
+__device__ inline void wlist_body(int vb, int b0, int nb, const int* __restrict__ xoff,
+                                  const int* __restrict__ xidx, int* __restrict__ cnt,
+                                  int* __restrict__ idx, int* __restrict__ cursor, int mode) {
+    const int lane = threadIdx.x & 63, i = vb * 4 + int(threadIdx.x >> 6);
     if (i >= nb) return;
     const int A = b0 + i;
     for (int k = xoff[A] + lane; k < xoff[A + 1]; k += 64) {
@@ -1107,6 +1152,58 @@ __global__ __launch_bounds__(256) void k_wlist(int b0, int nb, const int* __rest
         if (mode) idx[atomicAdd(&cursor[b], 1)] = img_flip((e & ~kBoxMask) | A);
         else atomicAdd(&cnt[b], 1);
     }
+}
+
+// Inputs shared by the fused list passes.
+struct ListArgs {
+    int b2, nvb, B;
+    const int4* anchor;
+    const int* parent;
+    const int* leafflag;
+    const int* coll;
+    const int* cal;
+    int* xoff;
+    int* xidx;
+    int* uoff;
+    int* uidx;
+    int* woff;
+    int* widx;
+    int* cursor;
+};
+
+// Counts of X, of the own part of U and of its finer part: three passes over
+// disjoint block ranges of one launch (nbx blocks for X, nbu for each U part).
+__global__ __launch_bounds__(256) void k_list_counts(ListArgs a, int nbx, int nbu) {
+    const int vb = blockIdx.x;
+    if (vb < nbx)
+        xlist_body(vb, a.b2, a.nvb, a.anchor, a.parent, a.leafflag, a.coll, a.cal, a.xoff, nullptr, 0);
+    else if (vb < nbx + nbu)
+        ulist_own_body(vb - nbx, a.B, a.leafflag, a.coll, a.cal, a.uoff, nullptr, nullptr, 0);
+    else
+        ulist_fine_body(vb - nbx - nbu, a.B, a.leafflag, a.cal, a.uoff, nullptr, nullptr, 0);
+}
+
+// X entries and the own part of U (which sets the cursor of the finer part).
+__global__ __launch_bounds__(256) void k_list_fill_a(ListArgs a, int nbx) {
+    const int vb = blockIdx.x;
+    if (vb < nbx)
+        xlist_body(vb, a.b2, a.nvb, a.anchor, a.parent, a.leafflag, a.coll, a.cal, a.xoff, a.xidx, 1);
+    else
+        ulist_own_body(vb - nbx, a.B, a.leafflag, a.coll, a.cal, a.uoff, a.uidx, a.cursor, 1);
+}
+
+// The finer part of U (from the cursor) and the W counts (from the X lists).
+__global__ __launch_bounds__(256) void k_list_fill_b(ListArgs a, int nbu) {
+    const int vb = blockIdx.x;
+    if (vb < nbu)
+        ulist_fine_body(vb, a.B, a.leafflag, a.cal, nullptr, a.uidx, a.cursor, 1);
+    else
+        wlist_body(vb - nbu, a.b2, a.nvb, a.xoff, a.xidx, a.woff, nullptr, nullptr, 0);
+}
+
+// W entries (from the cursor, a copy of the W offsets).
+__global__ __launch_bounds__(256) void k_list_fill_w(ListArgs a) {
+    wlist_body(blockIdx.x, a.b2, a.nvb, a.xoff, a.xidx, nullptr, a.widx, a.cursor, 1);
 }
 
 // Sort each CSR row ascending (entries of a row are distinct).  One wave per
@@ -1201,11 +1298,6 @@ __global__ __launch_bounds__(256) void k_near(int B, int n, const int* __restric
     }
 }
 
-__global__ void k_copy_int(const int* __restrict__ a, int* __restrict__ b, int n) {
-    int i = blockIdx.x * TB + threadIdx.x;
-    if (i < n) b[i] = a[i];
-}
-
 // Leaves, and boxes that take P2L (an X list, and not summed point to point).
 __global__ void k_flags(int B, const int* __restrict__ leafflag, const int2* __restrict__ range, int n,
                         const int* __restrict__ xcnt, int b2, int* __restrict__ fl, int* __restrict__ fx) {
@@ -1221,9 +1313,13 @@ __global__ void k_zero4(int n, int* __restrict__ a, int* __restrict__ b, int* __
     if (i < n) a[i] = b[i] = c[i] = d[i] = 0;
 }
 
-__global__ void k_compact(int B, const int* __restrict__ flag, const int* __restrict__ off, int* __restrict__ out) {
+__global__ void k_compact2(int B, const int* __restrict__ flag0, const int* __restrict__ off0, int* __restrict__ out0,
+                           const int* __restrict__ flag1, const int* __restrict__ off1, int* __restrict__ out1) {
     int b = blockIdx.x * TB + threadIdx.x;
     if (b >= B) return;
+    const int* flag = blockIdx.y ? flag1 : flag0;
+    const int* off = blockIdx.y ? off1 : off0;
+    int* out = blockIdx.y ? out1 : out0;
     if (flag[b]) out[off[b]] = b;
 }
 
@@ -1670,11 +1766,6 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     int* woff = P->w_off.as<int>();
     // the X, U, finer-U and W counts start at zero: one launch for the four
     hipLaunchKernelGGL(k_zero4, dim3(nblocks(B + 1)), dim3(TB), 0, s, B + 1, xoff, uoff, fcnt, woff);
-    if (nvb > 0)
-        hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
-                           P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
-                           (int*)nullptr, 0);
-    exclusive_scan<int>(P, xoff, xoff, B + 1, s);
     // List storage is sized by bounds, so that no size is read back here:
     // X(b) <= 26 leaf colleagues of the parent + 26 coarse adjacent leaves of
     // the parent; U(b) <= 27 + 26 of its own, and the finer part adds one
@@ -1682,33 +1773,22 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     // transposed.  The sizes themselves are read with the final counts.
     const size_t xcap = size_t(std::max(nvb, 1)) * 52, ucap = size_t(B) * (53 + 26);
     P->x_idx.ensure(xcap * 4);
-    if (nvb > 0) {
-        hipLaunchKernelGGL(k_xlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, P->bx_anchor.as<int4>(),
-                           P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(), P->cal.as<int>(), xoff,
-                           P->x_idx.as<int>(), 1);
-    }
-    // U lists
-    hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
-                       P->cal.as<int>(), uoff, (int*)nullptr, (int*)nullptr, 0);
-    hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
-                       uoff, (int*)nullptr, (int*)nullptr, 0);
-    exclusive_scan<int>(P, uoff, uoff, B + 1, s);
     P->u_idx.ensure(ucap * 4);
-    hipLaunchKernelGGL(k_ulist_own, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->coll.as<int>(),
-                       P->cal.as<int>(), uoff, P->u_idx.as<int>(), cursor, 1);
-    hipLaunchKernelGGL(k_ulist_fine, dim3(nblocks(B, 4)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->cal.as<int>(),
-                       (int*)nullptr, P->u_idx.as<int>(), cursor, 1);
-    // W lists = transpose of X
-    if (nvb > 0)
-        hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(), woff,
-                           (int*)nullptr, (int*)nullptr, 0);
-    exclusive_scan<int>(P, woff, woff, B + 1, s);
     P->w_idx.ensure(xcap * 4);
-    if (nvb > 0) {
-        hipLaunchKernelGGL(k_copy_int, dim3(nblocks(B + 1)), dim3(TB), 0, s, woff, cursor, B + 1);
-        hipLaunchKernelGGL(k_wlist, dim3(nblocks(nvb, 4)), dim3(TB), 0, s, b2, nvb, xoff, P->x_idx.as<int>(),
-                           (int*)nullptr, P->w_idx.as<int>(), cursor, 1);
-    }
+    ListArgs la{b2, nvb, B, P->bx_anchor.as<int4>(), P->bx_parent.as<int>(), P->bx_leaf.as<int>(), P->coll.as<int>(),
+                P->cal.as<int>(), xoff, P->x_idx.as<int>(), uoff, P->u_idx.as<int>(), woff, P->w_idx.as<int>(),
+                cursor};
+    const int nbx = nvb > 0 ? nblocks(nvb, 4) : 0, nbu = nblocks(B, 4);
+    // counts of X, of the own and the finer part of U (one launch), their scans
+    // (one launch when small), the X entries with the own part of U, then the
+    // finer part of U with the W counts (which read the X entries)
+    hipLaunchKernelGGL(k_list_counts, dim3(nbx + 2 * nbu), dim3(TB), 0, s, la, nbx, nbu);
+    exclusive_scan2<int>(P, xoff, xoff, nullptr, B + 1, uoff, uoff, B + 1, s);
+    hipLaunchKernelGGL(k_list_fill_a, dim3(nbx + nbu), dim3(TB), 0, s, la, nbx);
+    hipLaunchKernelGGL(k_list_fill_b, dim3(nbu + nbx), dim3(TB), 0, s, la, nbu);
+    // W = X transposed: the scan also leaves the cursor (a copy of the offsets)
+    exclusive_scan2<int>(P, woff, woff, cursor, B + 1, nullptr, nullptr, 0, s);
+    if (nvb > 0) hipLaunchKernelGGL(k_list_fill_w, dim3(nbx), dim3(TB), 0, s, la);
     // every row of X, U and W ascending (U and W were filled through atomics)
     hipLaunchKernelGGL(k_sort_rows, dim3(B, 3), dim3(64), 0, s, B, xoff, P->x_idx.as<int>(), uoff,
                        P->u_idx.as<int>(), woff, P->w_idx.as<int>());
@@ -1721,8 +1801,7 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     hipLaunchKernelGGL(k_near, dim3(nblocks(B + 1, 4)), dim3(TB), 0, s, B, P->n, P->bx_leaf.as<int>(),
                        P->bx_range.as<int2>(), uoff, P->u_idx.as<int>(), xoff, P->x_idx.as<int>(), woff,
                        P->w_idx.as<int>(), noff, (int*)nullptr, wfoff, (int*)nullptr, 0);
-    exclusive_scan<int>(P, noff, noff, B + 1, s);
-    exclusive_scan<int>(P, wfoff, wfoff, B + 1, s);
+    exclusive_scan2<int>(P, noff, noff, nullptr, B + 1, wfoff, wfoff, B + 1, s);
     P->n_idx.ensure((ucap + 2 * xcap) * 4);
     P->wf_idx.ensure(xcap * 4);
     hipLaunchKernelGGL(k_near, dim3(nblocks(B + 1, 4)), dim3(TB), 0, s, B, P->n, P->bx_leaf.as<int>(),
@@ -1739,14 +1818,14 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     int* fx = P->xflag.as<int>();
     hipLaunchKernelGGL(k_flags, dim3(nblocks(B + 1)), dim3(TB), 0, s, B, P->bx_leaf.as<int>(), P->bx_range.as<int2>(),
                        P->n, xoff, b2, fl, fx);
-    exclusive_scan<int>(P, fl, ol, B + 1, s);
-    exclusive_scan<int>(P, fx, ox, B + 1, s);
+    exclusive_scan2<int>(P, fl, ol, nullptr, B + 1, fx, ox, B + 1, s);
     // the leaf and X-box lists are sized by B, so that every size of the build
     // is read back once, below
     P->leaves.ensure(size_t(B) * 4);
     P->xboxes.ensure(size_t(B) * 4);
-    hipLaunchKernelGGL(k_compact, dim3(nblocks(B)), dim3(TB), 0, s, B, fl, ol, P->leaves.as<int>());
-    hipLaunchKernelGGL(k_compact, dim3(nblocks(B)), dim3(TB), 0, s, B, fx, ox, P->xboxes.as<int>());
+    if (B > 0)
+        hipLaunchKernelGGL(k_compact2, dim3(nblocks(B), 2), dim3(TB), 0, s, B, fl, ol, P->leaves.as<int>(), fx, ox,
+                           P->xboxes.as<int>());
     // work items per leaf (at most 64 targets each)
     P->tmp_a.ensure(size_t(B + 1) * 8 + 64);
     int* icnt = P->tmp_a.as<int>();
