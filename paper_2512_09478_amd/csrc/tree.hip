@@ -1308,9 +1308,9 @@ __global__ void k_flags(int B, const int* __restrict__ leafflag, const int2* __r
     fx[b] = (b >= b2 && xcnt[b + 1] > xcnt[b] && !direct_xw(b, leafflag, range, n)) ? 1 : 0;
 }
 
-__global__ void k_zero4(int n, int* __restrict__ a, int* __restrict__ b, int* __restrict__ c, int* __restrict__ d) {
+__global__ void k_zero3(int n, int* __restrict__ a, int* __restrict__ b, int* __restrict__ c) {
     const int i = blockIdx.x * TB + threadIdx.x;
-    if (i < n) a[i] = b[i] = c[i] = d[i] = 0;
+    if (i < n) a[i] = b[i] = c[i] = 0;
 }
 
 __global__ void k_compact2(int B, const int* __restrict__ flag0, const int* __restrict__ off0, int* __restrict__ out0,
@@ -1759,13 +1759,12 @@ void build_tree(kifmm_plan* P, const double* positions, hipStream_t s) {
     int* xoff = P->x_off.as<int>();
     P->u_off.ensure(size_t(B + 1) * 4);
     int* uoff = P->u_off.as<int>();
-    P->tmp_e.ensure(size_t(B + 1) * 4 * 2);
+    P->tmp_e.ensure(size_t(B + 1) * 4);
     int* cursor = P->tmp_e.as<int>();
-    int* fcnt = cursor + (B + 1);
     P->w_off.ensure(size_t(B + 1) * 4);
     int* woff = P->w_off.as<int>();
-    // the X, U, finer-U and W counts start at zero: one launch for the four
-    hipLaunchKernelGGL(k_zero4, dim3(nblocks(B + 1)), dim3(TB), 0, s, B + 1, xoff, uoff, fcnt, woff);
+    // the X, U and W counts start at zero: one launch for the three
+    hipLaunchKernelGGL(k_zero3, dim3(nblocks(B + 1)), dim3(TB), 0, s, B + 1, xoff, uoff, woff);
     // List storage is sized by bounds, so that no size is read back here:
     // X(b) <= 26 leaf colleagues of the parent + 26 coarse adjacent leaves of
     // the parent; U(b) <= 27 + 26 of its own, and the finer part adds one
