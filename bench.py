@@ -295,6 +295,89 @@ def run_largest(Plan, steps, warmup, m2l_rtol):
             "roofline": roofline(r, r["counts"]["surface_points"], "split_bf16", w.name, w.n)}
 
 
+def run_f4(Plan, steps, warmup, m2l_rtol, paths=("split_bf16", "fp32"), check=True, nsample=256):
+    """The sums beyond charges on the clustered workload (1,048,576 points,
+    p = 6): point dipoles with charges (u, E), the same with dE/dx, and the
+    Stokeslet velocity of point forces.  Per path: ms per call on a fixed plan
+    (no re-tree), then with `check` the oracle on the same plan at `nsample`
+    sampled targets, and the Stokes velocity also against its direct sum there."""
+    import torch
+    import workloads
+    w = workloads.make(2)
+    n = w.n
+    pos = torch.tensor(w.positions, dtype=torch.float64, device="cuda")
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(81)
+    # dipole moments of the size of a charge times a tenth of the mean spacing,
+    # so charges and dipoles both carry weight in the sums
+    m = workloads.round_f32(rng.standard_normal((n, 3)) * 0.1 * n ** (-1.0 / 3.0))
+    f = workloads.round_f32(rng.standard_normal((n, 3)))
+    mu = 0.7
+    md = torch.tensor(m, dtype=torch.float32, device="cuda")
+    fd = torch.tensor(f, dtype=torch.float32, device="cuda")
+    calls = {"dipoles": lambda P: P.evaluate_dipoles(q, md),
+             "gradient": lambda P: P.evaluate_gradient(q, md),
+             "stokes": lambda P: (P.evaluate_stokes(fd, mu),)}
+    res, outs = {}, {}
+    for prec in paths:
+        plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=prec, root=w.root,
+                    m2l_rtol=m2l_rtol)
+        r = {}
+        for name, fn in calls.items():
+            for _ in range(warmup):
+                fn(plan)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                o = fn(plan)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / steps
+            r[name] = {"ms_per_call": t * 1e3, "points_per_s": n / t}
+            outs[(prec, name)] = [x.double().cpu().numpy() for x in o]
+            log(f"[bench] f4 {prec} {name}: {t * 1e3:.3f} ms/call")
+        res[prec] = r
+        plan.close()
+    out = {"workload": WORKLOADS[2] + "; dipoles N(0,1)*0.1*N^(-1/3) per axis, forces N(0,1) per axis, "
+                                      f"viscosity {mu}; call = one evaluation on a fixed plan",
+           "n": n, "steps": steps, "warmup": warmup, "m2l_rtol": m2l_rtol, "timing": res,
+           "outputs": {"dipoles": "u, E", "gradient": "u, E, dE/dx", "stokes": "velocity"}}
+    if not check:
+        return out
+    from oracle import kifmm, stokes
+    t0 = time.perf_counter()
+    P = kifmm.plan(w.positions, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, w.root,
+                   periodic=w.periodic, m2l_rtol=m2l_rtol)
+    idx = np.sort(np.random.default_rng(21).choice(n, nsample, replace=False))
+    uo, Eo, Go = kifmm.forward_dipoles(P, w.charges, m, targets=idx, grad=True)
+    vo, vmag = stokes.kifmm(P, f, mu, targets=idx, terms=True)
+    t_oracle = time.perf_counter() - t0
+    # how much the four-potential combination amplifies relative errors of
+    # its far fields: the far terms' magnitudes over the velocity
+    kappa = float(np.linalg.norm(vmag) / np.linalg.norm(vo))
+    vd = stokes.direct(w.positions, f, mu, targets=idx, chunk=4)
+
+    def err(a, b):
+        return {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                "worst": float(np.max(np.abs(a - b)) / np.max(np.abs(b)))}
+
+    acc = {"sample": f"{nsample} sampled targets of the timed plan; oracle {t_oracle:.1f} s",
+           "tolerance": {"fp32": 1e-5, "split_bf16": 1e-4}}
+    for prec in paths:
+        d = outs[(prec, "dipoles")]
+        g = outs[(prec, "gradient")]
+        s = outs[(prec, "stokes")][0]
+        acc[prec] = {"dipoles": {"u": err(d[0][idx], uo), "E": err(d[1][idx], Eo)},
+                     "gradient": {"u": err(g[0][idx], uo), "E": err(g[1][idx], Eo), "dE/dx": err(g[2][idx], Go)},
+                     "stokes": {"velocity": err(s[idx], vo), "velocity_vs_direct_sum": err(s[idx], vd)}}
+    acc["oracle_stokes_vs_direct_sum"] = err(vo, vd)
+    acc["stokes_amplification"] = kappa
+    acc["stokes_tolerance"] = {"rel_l2": 1e-5 * kappa,
+                               "reading": "each of the four Laplace far fields within the 1e-5 bound of the "
+                                          "charge sums, amplified by the combination (stokes_amplification)"}
+    out["accuracy_vs_oracle"] = acc
+    return out
+
+
 # the workload --counter-run evaluates (its name and size, as recorded with the counters)
 COUNTER_WORKLOAD = ("clustered_1M_p6", 1_048_576)
 # M2L basis cut-off of the timed configuration (singular values below 1e-6
@@ -501,6 +584,9 @@ def main():
                     help="M2L in the truncated common basis of the offset operators (0: exact operators)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (CPU baseline and accuracy check)")
     ap.add_argument("--no-largest", action="store_true", help="skip the largest workload beside the headline")
+    ap.add_argument("--f4", action="store_true",
+                    help="time the dipole, field-gradient and Stokeslet sums on the clustered 1M workload "
+                         "and check them against the oracle at sampled targets (prints its own JSON line)")
     ap.add_argument("--counter-run", metavar="PRECISION", help="short run for rocprofv3 counter passes")
     ap.add_argument("--summarize-trace", nargs="+", metavar="DB OUT CMD [TITLE]")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("CSV", "COUNTS_LOG", "OUT", "CMD"))
@@ -527,6 +613,10 @@ def main():
     import torch
     import workloads
     from paper_2512_09478_amd import Plan
+    if args.f4:
+        print(json.dumps({"f4": run_f4(Plan, args.steps, args.warmup, args.m2l_rtol, check=not args.no_cpu)}),
+              flush=True)
+        return
     w = workloads.make(args.workload, n=args.n)
     n = w.n
     pos = torch.tensor(w.positions, dtype=torch.float64, device="cuda")

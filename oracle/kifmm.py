@@ -213,11 +213,15 @@ def downward(P: Plan, s, m, phi_u, needed: np.ndarray) -> np.ndarray:
     return phi
 
 
-def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
+def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False, part="all"):
     """FMM outputs at sorted targets (all points by default).
 
-    Returns (u [nt], E [nt,3], H [nt,6] or None) for the sorted indices ``targets``.
+    Returns (u [nt], E [nt,3], H [nt,6] or None) for the sorted indices
+    ``targets``; ``part`` "far" keeps only the expansions (local and W list),
+    "near" only the point-to-point sum over the near lists.
     """
+    if part not in ("all", "far", "near"):
+        raise ValueError(f"unknown part {part!r}")
     t, ops, c, L = P.tree, P.ops, P.c, P.lists
     s = np.asarray(s, dtype=np.float64)
     m = None if m is None else np.asarray(m, dtype=np.float64)
@@ -238,15 +242,15 @@ def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
         while a >= 0 and not needed[a]:
             needed[a] = True
             a = int(t.parent[a])
-    phi_u = upward(P, s, m)
-    phi_d = downward(P, s, m, phi_u, needed)
-
     u = np.zeros(nt)
     E = np.zeros((nt, 3))
     H = np.zeros((nt, 6)) if hess else None
+    if part != "near":
+        phi_u = upward(P, s, m)
+        phi_d = downward(P, s, m, phi_u, needed)
     order = np.argsort(tleaf, kind="stable")
     bounds = np.nonzero(np.diff(tleaf[order]))[0] + 1
-    for grp in np.split(order, bounds):
+    for grp in (np.split(order, bounds) if part != "near" else []):
         if grp.size == 0:
             continue
         b = int(tleaf[grp[0]])
@@ -272,6 +276,22 @@ def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
         E[grp] += El
         if hess:
             H[grp] += Hl
+
+    def periodic_part():
+        # the non-harmonic part of the periodic kernel, summed in closed form
+        # (relative to the cell centre)
+        o = t.lo + 0.5 * t.s
+        uc, Ec = moment_correction(P.x[targets] - o, P.x - o, s, m, t.s, c)
+        u[:] += uc
+        E[:] += Ec
+        if hess:
+            # grad grad of (2 pi c / 3V) Q |x|^2
+            H[:, :3] += 4.0 * np.pi * c / (3.0 * t.s ** 3) * s.sum()
+
+    if part == "far":
+        if P.periodic:
+            periodic_part()
+        return u, E, H
     near = near_lists(P)
     uoff = np.zeros(len(near) + 1, dtype=np.int64)
     uoff[1:] = np.cumsum([len(r) for r in near])
@@ -285,33 +305,26 @@ def evaluate_sorted(P: Plan, s, m=None, targets=None, hess=False):
     E += En
     if hess:
         H += Hn
-    if P.periodic:
-        # the non-harmonic part of the periodic kernel, summed in closed form
-        # (relative to the cell centre)
-        o = t.lo + 0.5 * t.s
-        uc, Ec = moment_correction(P.x[targets] - o, P.x - o, s, m, t.s, c)
-        u += uc
-        E += Ec
-        if hess:
-            # grad grad of (2 pi c / 3V) Q |x|^2
-            H[:, :3] += 4.0 * np.pi * c / (3.0 * t.s ** 3) * s.sum()
+    if P.periodic and part == "all":
+        periodic_part()
     return u, E, H
 
 
-def forward(P: Plan, q, targets=None):
-    """Potential and field in caller order (or at caller indices ``targets``)."""
+def forward(P: Plan, q, targets=None, part="all"):
+    """Potential and field in caller order (or at caller indices ``targets``);
+    ``part`` as in ``evaluate_sorted``."""
     q = np.asarray(q, dtype=np.float64)
     inv = np.empty_like(P.tree.perm)
     inv[P.tree.perm] = np.arange(P.n)
     qs = q[P.tree.perm]
     if targets is None:
-        u, E, _ = evaluate_sorted(P, qs)
+        u, E, _ = evaluate_sorted(P, qs, part=part)
         out_u = np.empty(P.n)
         out_E = np.empty((P.n, 3))
         out_u[P.tree.perm] = u
         out_E[P.tree.perm] = E
         return out_u, out_E
-    u, E, _ = evaluate_sorted(P, qs, targets=inv[np.asarray(targets)])
+    u, E, _ = evaluate_sorted(P, qs, targets=inv[np.asarray(targets)], part=part)
     return u, E
 
 

@@ -52,11 +52,17 @@ def origin(P):
     return P.tree.lo + 0.5 * P.tree.s
 
 
-def kifmm(P, f, mu=1.0, targets=None):
+def kifmm(P, f, mu=1.0, targets=None, terms=False):
     """The Stokeslet sum through four Laplace evaluations of the oracle plan
     ``P`` (its kernel constant c = P.c): u = (1/(8 pi mu c)) [psi_a +
     x'_k E(k)_a - E(4)_a], psi_k and E(k) = -grad psi_k the plan's potential
-    and field of the charges f_k (k = 1, 2, 3) and x'.f (k = 4)."""
+    and field of the charges f_k (k = 1, 2, 3) and x'.f (k = 4).
+
+    With ``terms`` also the sum of the magnitudes of the far-field parts of
+    those terms (the expansions' share of each evaluation, its whole minus its
+    near-list sum), scaled alike: its ratio to |u| bounds how much the
+    combination amplifies relative errors of the four far fields (the terms
+    grow as |x'| over the distance to the sources, u does not)."""
     from . import kifmm as K
     f = np.asarray(f, dtype=np.float64).reshape(-1, 3)
     o = origin(P)
@@ -69,4 +75,12 @@ def kifmm(P, f, mu=1.0, targets=None):
     for k in range(3):
         u += xt[:, k:k + 1] * res[k][1]
     u -= res[3][1]
-    return u / (8.0 * math.pi * mu * P.c)
+    s = 1.0 / (8.0 * math.pi * mu * P.c)
+    if not terms:
+        return u * s
+    near = [K.forward(P, q, targets=targets, part="near") for q in charges]
+    far = [(r[0] - n[0], r[1] - n[1]) for r, n in zip(res, near)]
+    mag = np.abs(np.stack([far[a][0] for a in range(3)], axis=1)) + np.abs(far[3][1])
+    for k in range(3):
+        mag += np.abs(xt[:, k:k + 1] * far[k][1])
+    return u * s, mag * abs(s)

@@ -259,3 +259,41 @@ def test_small_leaf_w_x_pairs_are_direct():
             ud, Ed, _ = direct.potential_field(w.positions, q)
             tid = t.perm[t.begin[dst]:t.end[dst]]
             assert rel(u[tid], ud[tid]) < 1e-12 and rel(E[tid], Ed[tid]) < 1e-12
+
+
+def test_far_and_near_parts_add_up():
+    """The near part at a target is the direct sum over the points of its
+    leaf's near-list boxes (brute force here); far and near add up to the
+    whole evaluation."""
+    w = workloads.make(2, n=3000)
+    P = kifmm.plan(w.positions, "laplace", 4, 32, True, 21, w.root)
+    idx = np.random.default_rng(4).choice(w.n, 40, replace=False)
+    u, E = kifmm.forward(P, w.charges, targets=idx)
+    uf, Ef = kifmm.forward(P, w.charges, targets=idx, part="far")
+    un, En = kifmm.forward(P, w.charges, targets=idx, part="near")
+    np.testing.assert_allclose(uf + un, u, rtol=0, atol=1e-12 * np.abs(u).max())
+    np.testing.assert_allclose(Ef + En, E, rtol=0, atol=1e-12 * np.abs(E).max())
+    assert np.abs(uf).max() > 1e-3 * np.abs(u).max()
+    t = P.tree
+    inv = np.empty_like(t.perm)
+    inv[t.perm] = np.arange(P.n)
+    qs = np.asarray(w.charges, dtype=np.float64)[t.perm]
+    leaves = t.leaves()
+    near = kifmm.near_lists(P)
+    for k, i in enumerate(idx):
+        si = inv[i]
+        leaf = next(int(b) for b in leaves if t.begin[b] <= si < t.end[b])
+        src = np.concatenate([np.arange(t.begin[a], t.end[a]) for a in (kifmm.decode(e)[0] for e in near[leaf])])
+        r = P.x[si] - P.x[src]
+        d = np.linalg.norm(r, axis=1)
+        keep = d > 0
+        assert np.isclose(un[k], P.c * np.sum(qs[src][keep] / d[keep]), rtol=1e-12)
+        np.testing.assert_allclose(En[k], P.c * (qs[src][keep, None] * r[keep] / d[keep, None] ** 3).sum(axis=0),
+                                   rtol=1e-11, atol=1e-12 * np.abs(En[k]).max())
+
+
+def test_unknown_part_is_refused():
+    w = workloads.make(4, n=100)
+    P = kifmm.plan(w.positions, "laplace", 4, 128)
+    with pytest.raises(ValueError):
+        kifmm.forward(P, w.charges, part="middle")

@@ -126,3 +126,31 @@ def test_kifmm_stokes_converges_to_the_direct_sum():
         err.append(rel(stokes.kifmm(P, f), ud))
     assert err[0] > 10 * err[1] > 10 * err[2]
     assert err[1] < 5e-5 and err[2] < 5e-6
+
+
+def test_kifmm_stokes_terms_bound_the_far_velocity():
+    """With terms, the same velocity, and magnitudes that bound its far part
+    (the velocity minus the Stokeslet summed directly over the near lists)
+    term by term."""
+    w = workloads.make(2, n=4000)
+    f = workloads.round_f32(np.random.default_rng(9).standard_normal((w.n, 3)))
+    P = kifmm.plan(w.positions, "laplace", 4, 32, True, 21, w.root)
+    idx = np.random.default_rng(10).choice(w.n, 30, replace=False)
+    u = stokes.kifmm(P, f, 0.7, targets=idx)
+    u2, mag = stokes.kifmm(P, f, 0.7, targets=idx, terms=True)
+    assert np.array_equal(u, u2)
+    t = P.tree
+    inv = np.empty_like(t.perm)
+    inv[t.perm] = np.arange(P.n)
+    leaves = t.leaves()
+    near = kifmm.near_lists(P)
+    for k, i in enumerate(idx):
+        si = inv[i]
+        leaf = next(int(b) for b in leaves if t.begin[b] <= si < t.end[b])
+        src = np.concatenate([np.arange(t.begin[a], t.end[a]) for a in (kifmm.decode(e)[0] for e in near[leaf])])
+        # caller indices of the near sources (the direct sum skips the target itself)
+        un = stokes.direct(np.concatenate([w.positions[t.perm[src]], w.positions[i:i + 1]]),
+                           np.concatenate([f[t.perm[src]], np.zeros((1, 3))]), 0.7, targets=[len(src)])[0]
+        far = u[k] - un
+        assert np.all(np.abs(far) <= mag[k] * (1 + 1e-9) + 1e-12 * np.abs(u[k]).max())
+        assert np.abs(far).max() > 1e-3 * np.abs(u[k]).max()
