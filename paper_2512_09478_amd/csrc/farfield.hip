@@ -545,8 +545,9 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
 }
 
 // ------------------------------------------------------------------ upward and downward translations
-// Upward (UP): for the boxes of one level, psi = P2M result (leaves) or
-// sum_o M2M[o] phi_u(child o) (non-leaves), then phi_u = V (W1 psi).
+// Upward (UP): for the boxes list[b0 .. b0+nb) (the leaves of every level, or
+// the non-leaves of one), psi = P2M result (leaves) or sum_o M2M[o]
+// phi_u(child o) (non-leaves), then phi_u = V (W1 psi).
 // Downward: for the children at octant o of non-leaf parents, psi = the summed
 // M2L partials (+ X list) + L2L[o] phi_d(parent) (from level 3), then
 // phi_d = U (W1d psi).
@@ -557,7 +558,8 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
 // check-to-equivalent factors need the whole intermediate vector: it is
 // exchanged through LDS in accumulator layout.
 template <int NP, bool UP>
-__global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl_start, int nl_count, int has_l2l,
+__global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, const int* __restrict__ list, int nl_start,
+                                                int nl_count, int has_l2l,
                                                 const int* __restrict__ nonleaf, const int2* __restrict__ child,
                                                 const int* __restrict__ leafflag, const float* __restrict__ psi_in,
                                                 int nsplit, size_t split_stride, const float* __restrict__ gsrc,
@@ -573,7 +575,7 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, int nl
     if (UP) {
         const int idx = bid * 16 + (lane & 15);
         if (idx < nb) {
-            tgt = b0 + idx;
+            tgt = list[b0 + idx];
             if (!leafflag[tgt]) {
                 const int2 ch = child[tgt];
                 cfirst = ch.x;
@@ -1385,17 +1387,26 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
                            r ? P->src2.as<float4>() : nullptr, surf, op.n, geo, P->psi_u.as<float>() + r * stride);
     if (rec) record_phase(P, 0, s);
     between();
-    // upward M2M + UC2E, deepest level first
-    for (int r = r0; r < r1; ++r)
-        for (int l = depth; l >= ld; --l) {
-            const int nb = int(P->lev[l].count);
+    // upward UC2E of the leaves (every level from ld in one launch), then
+    // M2M + UC2E of the non-leaves, deepest level first; a column block holds
+    // leaves only or non-leaves only, so no leaf waits on the M2M terms of
+    // the children of others
+    int64_t lf0 = 0;   // leaves above level ld, at the front of the leaf list
+    for (int l = 0; l < ld; ++l) lf0 += P->lev[l].count - P->lev[l].nl_count;
+    const int nlf = int(P->nleaves - lf0);
+    for (int r = r0; r < r1; ++r) {
+        auto up = [&](const int* list, int b0, int nb) {
             const int blocks = nblk(nb, 16);
-            hipLaunchKernelGGL((k_updown<NP, true>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks,
-                               int(P->lev[l].start), nb, 0, 0, 0, P->nonleaf.as<int>(), P->bx_child.as<int2>(),
-                               P->bx_leaf.as<int>(), P->psi_u.as<float>() + r * stride, 1, size_t(0),
-                               P->phi_u.as<float>() + r * stride, P->phi_u.as<float>() + r * stride,
-                               op.m2m.as<uint4>(), op.uc2e_w1.as<uint4>(), op.uc2e_v.as<uint4>());
-        }
+            if (blocks == 0) return;
+            hipLaunchKernelGGL((k_updown<NP, true>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, b0, nb, list, 0,
+                               0, 0, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(),
+                               P->psi_u.as<float>() + r * stride, 1, size_t(0), P->phi_u.as<float>() + r * stride,
+                               P->phi_u.as<float>() + r * stride, op.m2m.as<uint4>(), op.uc2e_w1.as<uint4>(),
+                               op.uc2e_v.as<uint4>());
+        };
+        up(P->leaves.as<int>(), int(lf0), nlf);
+        for (int l = depth; l >= ld; --l) up(P->nonleaf.as<int>(), int(P->lev[l].nl_start), int(P->lev[l].nl_count));
+    }
     // periodic root: every image beyond the root's neighbours
     if (P->periodic) {
         const DBuf& R = get_lattice_operator(P->p, P->opt.pinv_rtol);
@@ -1437,7 +1448,7 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
             const int blocks = nblk(pl.nl_count, 16) * 8;
             if (blocks == 0) continue;
             hipLaunchKernelGGL((k_updown<NP, false>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, 0, 0,
-                               int(pl.nl_start), int(pl.nl_count), l > ld ? 1 : 0, P->nonleaf.as<int>(),
+                               (const int*)nullptr, int(pl.nl_start), int(pl.nl_count), l > ld ? 1 : 0, P->nonleaf.as<int>(),
                                P->bx_child.as<int2>(), P->bx_leaf.as<int>(),
                                // the check potentials: M2L partials (with the X list in the first), or,
                                // compressed, the expanded sum already in psi_d
