@@ -277,3 +277,45 @@ def test_uniform_65536_adjoint_against_finite_differences():
         check("dL/dx (64 coordinates)", np.array([gx[k, a] for k, a, _ in xs]), np.array([r for _, _, r in xs]), tol)
         check("dL/dq (64 charges)", np.array([gq[k] for k, _, _ in qs]), np.array([r for _, _, r in qs]), tol)
         G.close()
+
+
+def test_clustered_1M_dipoles_gradient_and_stokes():
+    """The other sums of eq. (1) at the headline size, with the inputs that
+    `bench.py --f4` times: charges with point dipoles (u, E and dE/dx) and
+    the Stokeslet velocity of point forces, sampled against the oracle on
+    the same plan.  The Stokes tolerance is the charge sums' FP32 bound times
+    the amplification of the one-origin decomposition, measured from the
+    oracle's far and near parts at these targets."""
+    from oracle import stokes
+    say("clustered 1,048,576 points: dipoles, field gradient and Stokeslet")
+    w = workloads.make(2)
+    P = oracle_plan(w)
+    idx = sample(w.n, 21)
+    rng = np.random.default_rng(81)
+    m = workloads.round_f32(rng.standard_normal((w.n, 3)) * 0.1 * w.n ** (-1.0 / 3.0))
+    f = workloads.round_f32(rng.standard_normal((w.n, 3)))
+    mu = 0.7
+    t = time.time()
+    uo, Eo, Go = kifmm.forward_dipoles(P, w.charges, m, targets=idx, grad=True)
+    say(f"  oracle sampled dipole sweep {time.time() - t:.1f} s")
+    t = time.time()
+    vo, vmag = stokes.kifmm(P, f, mu, targets=idx, terms=True)
+    kappa = float(np.linalg.norm(vmag) / np.linalg.norm(vo))
+    say(f"  oracle sampled Stokes sum {time.time() - t:.1f} s; amplification of the combination {kappa:.2f}")
+    q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
+    md = torch.tensor(m, dtype=torch.float32, device="cuda")
+    fd = torch.tensor(f, dtype=torch.float32, device="cuda")
+    for precision, tol in (("fp32", 1e-5), ("split_bf16", 1e-4)):
+        G = gpu_plan(w, precision)
+        u, E = G.evaluate_dipoles(q, md)
+        u2, E2, Gr = G.evaluate_gradient(q, md)
+        v = G.evaluate_stokes(fd, mu)
+        torch.cuda.synchronize()
+        say(f"  {precision}:")
+        check("u (dipoles)", u.cpu().numpy()[idx], uo, tol)
+        check("E (dipoles)", E.cpu().numpy()[idx], Eo, tol)
+        check("u (gradient call)", u2.cpu().numpy()[idx], uo, tol)
+        check("E (gradient call)", E2.cpu().numpy()[idx], Eo, tol)
+        check("dE/dx", Gr.cpu().numpy()[idx], Go, tol)
+        check("Stokes velocity", v.cpu().numpy()[idx], vo, max(tol, 1e-5 * kappa))
+        G.close()
