@@ -349,10 +349,11 @@ def run_f4(Plan, steps, warmup, m2l_rtol, paths=("split_bf16", "fp32"), check=Tr
                    periodic=w.periodic, m2l_rtol=m2l_rtol)
     idx = np.sort(np.random.default_rng(21).choice(n, nsample, replace=False))
     uo, Eo, Go = kifmm.forward_dipoles(P, w.charges, m, targets=idx, grad=True)
-    vo, vmag = stokes.kifmm(P, f, mu, targets=idx, terms=True)
+    vo, vmag = stokes.kifmm(P, f, mu, targets=idx, terms=True, frame="leaf")
     t_oracle = time.perf_counter() - t0
-    # how much the four-potential combination amplifies relative errors of
-    # its far fields: the far terms' magnitudes over the velocity
+    # how much the four-potential combination, about each target's leaf
+    # centre as the library forms it, amplifies relative errors of its far
+    # fields: the far terms' magnitudes over the velocity
     kappa = float(np.linalg.norm(vmag) / np.linalg.norm(vo))
     vd = stokes.direct(w.positions, f, mu, targets=idx, chunk=4)
 
@@ -371,9 +372,10 @@ def run_f4(Plan, steps, warmup, m2l_rtol, paths=("split_bf16", "fp32"), check=Tr
                      "stokes": {"velocity": err(s[idx], vo), "velocity_vs_direct_sum": err(s[idx], vd)}}
     acc["oracle_stokes_vs_direct_sum"] = err(vo, vd)
     acc["stokes_amplification"] = kappa
-    acc["stokes_tolerance"] = {"rel_l2": 1e-5 * kappa,
-                               "reading": "each of the four Laplace far fields within the 1e-5 bound of the "
-                                          "charge sums, amplified by the combination (stokes_amplification)"}
+    acc["stokes_tolerance"] = {"fp32": 2e-5, "split_bf16": 1e-4,
+                               "reading": "the far fields carry about stokes_amplification of the velocity and "
+                                          "are accurate to about 1e-5 of their own size in FP32 (the charge "
+                                          "sums' field, 7 % far, meets 6e-7 overall)"}
     out["accuracy_vs_oracle"] = acc
     return out
 

@@ -52,7 +52,20 @@ def origin(P):
     return P.tree.lo + 0.5 * P.tree.s
 
 
-def kifmm(P, f, mu=1.0, targets=None, terms=False):
+def leaf_centres(P, targets=None):
+    """Centre of the leaf holding each point (caller order, or at caller
+    indices ``targets``)."""
+    t = P.tree
+    leaf_of = np.empty(P.n, dtype=np.int64)
+    for b in t.leaves():
+        leaf_of[t.begin[b]:t.end[b]] = b
+    inv = np.empty_like(t.perm)
+    inv[t.perm] = np.arange(P.n)
+    idx = inv if targets is None else inv[np.asarray(targets)]
+    return np.array([t.center(int(b)) for b in leaf_of[idx]]).reshape(-1, 3)
+
+
+def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root"):
     """The Stokeslet sum through four Laplace evaluations of the oracle plan
     ``P`` (its kernel constant c = P.c): u = (1/(8 pi mu c)) [psi_a +
     x'_k E(k)_a - E(4)_a], psi_k and E(k) = -grad psi_k the plan's potential
@@ -62,7 +75,10 @@ def kifmm(P, f, mu=1.0, targets=None, terms=False):
     those terms (the expansions' share of each evaluation, its whole minus its
     near-list sum), scaled alike: its ratio to |u| bounds how much the
     combination amplifies relative errors of the four far fields (the terms
-    grow as |x'| over the distance to the sources, u does not)."""
+    grow as |x'| over the distance to the sources, u does not).  ``frame``
+    names the origin of those terms: "root" (the one origin used here) or
+    "leaf", each target's leaf centre c, for which the fourth field is
+    E(4) + (o - c)_k E(k) and x' = x - c (the same velocity)."""
     from . import kifmm as K
     f = np.asarray(f, dtype=np.float64).reshape(-1, 3)
     o = origin(P)
@@ -78,9 +94,16 @@ def kifmm(P, f, mu=1.0, targets=None, terms=False):
     s = 1.0 / (8.0 * math.pi * mu * P.c)
     if not terms:
         return u * s
+    if frame not in ("root", "leaf"):
+        raise ValueError(f"unknown frame {frame!r}")
     near = [K.forward(P, q, targets=targets, part="near") for q in charges]
     far = [(r[0] - n[0], r[1] - n[1]) for r, n in zip(res, near)]
-    mag = np.abs(np.stack([far[a][0] for a in range(3)], axis=1)) + np.abs(far[3][1])
+    e4, xf = far[3][1], xt
+    if frame == "leaf":
+        c = leaf_centres(P, targets)
+        e4 = e4 + sum((o[k] - c[:, k:k + 1]) * far[k][1] for k in range(3))
+        xf = xt + o - c
+    mag = np.abs(np.stack([far[a][0] for a in range(3)], axis=1)) + np.abs(e4)
     for k in range(3):
-        mag += np.abs(xt[:, k:k + 1] * far[k][1])
+        mag += np.abs(xf[:, k:k + 1] * far[k][1])
     return u * s, mag * abs(s)

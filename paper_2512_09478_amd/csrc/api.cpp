@@ -315,11 +315,36 @@ int kifmm_evaluate_stokes(kifmm_handle h, const float* forces, double viscosity,
         launch_gather_stokes(P, forces, 0, s);
         run_sweep(P, 0, 2, s, true, [&] { fork_near(P, NEAR_STOKES, s, viscosity); });
         for (int r = 0; r < 2; ++r) run_far_eval(P, false, pot + r * N, fld + 3 * r * N, s, r, false, false);
-        // charges f_z and x'.f
+        // the first sweep's upward, compressed and downward densities of f_x
+        // and f_y, which the second sweep's framed charge needs after the
+        // second sweep has overwritten them
+        const size_t sU = size_t(P->B) * P->npad, sK = P->cm ? size_t(P->B) * P->cm->kp : 0;
+        float* keep = static_cast<float*>(P->stk_keep.ensure((4 * sU + 2 * sK) * sizeof(float)));
+        float* keep_u = keep;
+        float* keep_d = keep + 2 * sU;
+        float* keep_k = keep + 4 * sU;
+        KIFMM_HIP(hipMemcpyAsync(keep_u, P->phi_u.p, 2 * sU * sizeof(float), hipMemcpyDeviceToDevice, s));
+        KIFMM_HIP(hipMemcpyAsync(keep_d, P->phi_d.p, 2 * sU * sizeof(float), hipMemcpyDeviceToDevice, s));
+        if (sK) KIFMM_HIP(hipMemcpyAsync(keep_k, P->phi_k.p, 2 * sK * sizeof(float), hipMemcpyDeviceToDevice, s));
+        // charges f_z and (x - c).f about each box's centre c
         launch_gather_stokes(P, forces, 1, s);
-        run_sweep(P, 0, 2, s, false, [] {});
-        for (int r = 0; r < 2; ++r)
-            run_far_eval(P, false, pot + (2 + r) * N, fld + 3 * (2 + r) * N, s, r, false, false);
+        StokesFrames sf;
+        sf.frc = P->stk.as<float4>();
+        const float* cur_u = P->phi_u.as<float>();
+        const float* cur_d = P->phi_d.as<float>();
+        const float* cur_k = sK ? P->phi_k.as<float>() : nullptr;
+        for (int k = 0; k < 2; ++k) {
+            sf.up[k] = keep_u + k * sU;
+            sf.dn[k] = keep_d + k * sU;
+            sf.kp[k] = sK ? keep_k + k * sK : nullptr;
+        }
+        sf.up[2] = cur_u;   // f_z: right-hand side 0 of this sweep, done before right-hand side 1
+        sf.dn[2] = cur_d;
+        sf.kp[2] = cur_k;
+        run_sweep(P, 0, 2, s, false, [] {}, &sf);
+        run_far_eval(P, false, pot + 2 * N, fld + 3 * 2 * N, s, 0, false, false);
+        run_far_eval(P, false, pot + 3 * N, fld + 3 * 3 * N, s, 1, false, false, &sf);
+        launch_stokes_frames(P, s);
         join_near(P, s);
         launch_stokes_combine(P, viscosity, velocity, s);
         record_phase(P, 6, s);

@@ -304,6 +304,8 @@ struct kifmm_plan {
     kifmm::DBuf stk;          // float4 [N] sorted forces
     kifmm::DBuf stk_near;     // float4 [N] sorted near-field velocity
     kifmm::DBuf stk_far;      // float [4][N] potentials, [4][N][3] fields of the harmonic charges (caller order)
+    kifmm::DBuf stk_keep;     // float: the first sweep's upward, compressed and downward densities of f_x, f_y
+    kifmm::DBuf stk_frame;    // float4 [N] sorted x - (centre of the point's leaf)
 };
 
 namespace kifmm {
@@ -316,12 +318,26 @@ void count_pairs(kifmm_plan* P, hipStream_t s);
 // offset (in box widths) from a box at octant o to the source of its V slot j
 void v_slot_offset(int o, int j, int d[3]);
 // ---- farfield.hip
-void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between);
+// Per-box frames of the Stokeslet's fourth harmonic charge (x - c).f, the
+// right-hand side 1 of the second Stokes sweep: its sources are formed about
+// each box's own centre c, and each translation from box A to box B adds
+// (c_A - c_B) times A's densities of the three force components, so that no
+// value carries the distance to a distant origin.
+struct StokesFrames {
+    const float4* frc = nullptr;   // sorted forces (x, y, z, -)
+    const float* up[3] = {};       // upward equivalent densities of f_x, f_y, f_z, [B][NP]
+    const float* kp[3] = {};       // their compressed M2L sources, [B][KP] (compressed M2L only)
+    const float* dn[3] = {};       // downward equivalent densities, [B][NP]
+};
+void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between,
+               const StokesFrames* sf = nullptr);
 // leaf evaluation; adds the near-field part and writes the caller-order
 // outputs (forward: potential, field; backward: grad_charges, grad_positions)
 // (near = false: the near-field part is not added)
+// (sf: the W-list sources of right-hand side rhs are shifted into the
+// target leaf's frame as for the Stokes sweep)
 void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs = 0,
-                  bool accumulate = false, bool near = true);
+                  bool accumulate = false, bool near = true, const StokesFrames* sf = nullptr);
 // leaf evaluation with the field gradient (densities of right-hand side rhs)
 void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs);
 // ---- nearfield.hip
@@ -333,10 +349,13 @@ void launch_gather(kifmm_plan* P, const float* charges, const float* gpot, const
 void launch_p2p_forward(kifmm_plan* P, hipStream_t s, bool excl = false);
 void launch_p2p_backward(kifmm_plan* P, hipStream_t s, bool excl = false);
 void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s);
-// Stokeslet sources (pass 0: f_x, f_y; pass 1: f_z, x'.f) and the Stokeslet near field
+// Stokeslet sources (pass 0: f_x, f_y and the sorted forces; pass 1: f_z) and the Stokeslet near field
 void launch_gather_stokes(kifmm_plan* P, const float* forces, int pass, hipStream_t s);
 void launch_p2p_stokes(kifmm_plan* P, double viscosity, hipStream_t s);
-// velocity from the harmonic potentials and fields (caller order) and the near part
+// x - (centre of its leaf) of every sorted point, into stk_frame
+void launch_stokes_frames(kifmm_plan* P, hipStream_t s);
+// velocity from the harmonic potentials and fields (caller order, the fourth
+// about each point's leaf centre) and the near part
 void launch_stokes_combine(kifmm_plan* P, double viscosity, float* velocity, hipStream_t s);
 // u, E and dE/dx of monopoles (pts.w, or src2.x with `dipoles`) and dipoles (src2.yzw)
 void launch_p2p_gradient(kifmm_plan* P, bool dipoles, hipStream_t s);

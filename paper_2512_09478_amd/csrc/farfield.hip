@@ -57,6 +57,14 @@ __device__ inline void box_frame(const BoxGeom& g, int4 a, float c[3], float& in
     invw = float(ldexp(1.0, a.w) / g.side);
 }
 
+// c_a - c_b of two boxes of the cell (no image shift): FP64, then FP32
+__device__ inline void centre_diff(const BoxGeom& g, int4 a, int4 b, float d[3]) {
+    const double wa = ldexp(g.side, -a.w), wb = ldexp(g.side, -b.w);
+    d[0] = float((double(a.x) + 0.5) * wa - (double(b.x) + 0.5) * wb);
+    d[1] = float((double(a.y) + 0.5) * wa - (double(b.y) + 0.5) * wb);
+    d[2] = float((double(a.z) + 0.5) * wa - (double(b.z) + 0.5) * wb);
+}
+
 __device__ inline float rsq(float r2) { return r2 > 0.f ? __frsqrt_rn(r2) : 0.f; }
 
 // ------------------------------------------------------------------ MFMA engine
@@ -193,7 +201,8 @@ __device__ inline void c2e_apply(v4f* acc, const float* __restrict__ W1, const f
 
 // ------------------------------------------------------------------ P2M / P2L
 // Check potential of leaf points on a surface of box `b` (normalised):
-// psi[i] = sum_j q_j K1(s_i - x'_j) - (1/w) Ebar_j . G1(s_i - x'_j)   (dipole part optional).
+// psi[i] = sum_j q_j K1(s_i - x'_j) - (1/w) Ebar_j . G1(s_i - x'_j)   (dipole part optional);
+// with frc (the Stokeslet's fourth charge) q_j = (x_j - c) . f_j about this box's centre.
 // A block has 2 NP threads: thread (slice, i) takes check point i and every
 // other staged source point; the two slices are added in a fixed order.  No
 // distance vanishes: the points of a leaf lie inside the upward check surface
@@ -201,14 +210,20 @@ __device__ inline void c2e_apply(v4f* acc, const float* __restrict__ W1, const f
 // surface of its target box.
 template <int NP>
 __device__ void points_to_surface(float& acc, const float4* __restrict__ pts, const float4* __restrict__ src2,
-                                  int j0, int j1, const float c[3], float invw, float4 s, bool active, int slice,
-                                  float4* sh, float4* sh2) {
+                                  const float4* __restrict__ frc, int j0, int j1, const float c[3], float invw,
+                                  float4 s, bool active, int slice, float4* sh, float4* sh2) {
     for (int base = j0; base < j1; base += 256) {
         const int m = min(256, j1 - base);
         __syncthreads();
         for (int k = threadIdx.x; k < m; k += blockDim.x) {
             const float4 p = pts[base + k];
-            sh[k] = make_float4((p.x - c[0]) * invw, (p.y - c[1]) * invw, (p.z - c[2]) * invw, p.w);
+            const float px = p.x - c[0], py = p.y - c[1], pz = p.z - c[2];
+            float q = p.w;
+            if (frc) {
+                const float4 f = frc[base + k];
+                q = px * f.x + py * f.y + pz * f.z;
+            }
+            sh[k] = make_float4(px * invw, py * invw, pz * invw, q);
             if (src2) {
                 const float4 a = src2[base + k];
                 sh2[k] = make_float4(a.x, a.y * invw, a.z * invw, a.w * invw);
@@ -249,8 +264,8 @@ template <int NP>
 __global__ __launch_bounds__(2 * NP) void k_p2m(const int* __restrict__ leaves, int nleaves, int b2,
                                                 const int4* __restrict__ anchor, const int2* __restrict__ range,
                                                 const float4* __restrict__ pts, const float4* __restrict__ src2,
-                                                const float4* __restrict__ surf, int n, BoxGeom geo,
-                                                float* __restrict__ psi_u) {
+                                                const float4* __restrict__ frc, const float4* __restrict__ surf,
+                                                int n, BoxGeom geo, float* __restrict__ psi_u) {
     __shared__ float4 sh[256];
     __shared__ float4 sh2[256];
     __shared__ float red[NP];
@@ -264,7 +279,7 @@ __global__ __launch_bounds__(2 * NP) void k_p2m(const int* __restrict__ leaves, 
     const bool act = i < n;
     const float4 s = act ? surf[NP + i] : make_float4(0, 0, 0, 0);   // upward check surface
     float acc = 0.f;
-    points_to_surface<NP>(acc, pts, src2, r.x, r.y, c, invw, s, act, slice, sh, sh2);
+    points_to_surface<NP>(acc, pts, src2, frc, r.x, r.y, c, invw, s, act, slice, sh, sh2);
     acc = add_slices<NP>(acc, i, slice, red);
     if (slice == 0) psi_u[size_t(b) * NP + i] = act ? acc : 0.f;
 }
@@ -273,8 +288,9 @@ template <int NP>
 __global__ __launch_bounds__(2 * NP) void k_p2l(const int* __restrict__ xboxes, const int* __restrict__ xoff,
                                                 const int* __restrict__ xidx, const int4* __restrict__ anchor,
                                                 const int2* __restrict__ range, const float4* __restrict__ pts,
-                                                const float4* __restrict__ src2, const float4* __restrict__ surf,
-                                                int n, BoxGeom geo, float* __restrict__ psi_d) {
+                                                const float4* __restrict__ src2, const float4* __restrict__ frc,
+                                                const float4* __restrict__ surf, int n, BoxGeom geo,
+                                                float* __restrict__ psi_d) {
     __shared__ float4 sh[256];
     __shared__ float4 sh2[256];
     __shared__ float red[NP];
@@ -291,7 +307,7 @@ __global__ __launch_bounds__(2 * NP) void k_p2l(const int* __restrict__ xboxes, 
         // a source image shifted by +s cell widths is the target frame shifted by -s
         float c[3], invw, w;
         box_frame(geo, a, c, invw, w, e, -1);
-        points_to_surface<NP>(acc, pts, src2, r.x, r.y, c, invw, s, act, slice, sh, sh2);
+        points_to_surface<NP>(acc, pts, src2, frc, r.x, r.y, c, invw, s, act, slice, sh, sh2);
     }
     acc = add_slices<NP>(acc, i, slice, red);
     if (slice == 0) psi_d[size_t(b) * NP + i] = act ? acc : 0.f;
@@ -372,13 +388,19 @@ __device__ inline void load8(float* b, const float* __restrict__ p) {
 // 32-column chunks (fragment order, NP/16*128 words) through a double-buffered
 // LDS tile shared by the four waves, while the next chunk and the next source
 // columns are already in flight.
-template <int NP, bool SPLIT, int CB>
-__global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntile, int nsplit, int nrhs,
+// STK (the Stokeslet's fourth charge in per-box frames, one right-hand side):
+// each source column adds (c_source - c_target) times the source box's
+// columns of the three force components (s0, s1, s2).
+template <int NP, bool SPLIT, int CB, bool STK>
+__global__ __launch_bounds__(256, STK ? 2 : 3) void k_m2l(TaskTable tt, int nblk, int ntile, int nsplit, int nrhs,
                                              const int* __restrict__ nonleaf, const int2* __restrict__ child,
                                              const int* __restrict__ vdense, int b2, const VOps* __restrict__ vops,
                                              const float* __restrict__ phi_u, const float* __restrict__ psi_d,
                                              const int* __restrict__ xflag, float* __restrict__ psi_m,
-                                             size_t rhs_stride, size_t split_stride, const uint4* __restrict__ ops) {
+                                             size_t rhs_stride, size_t split_stride, const uint4* __restrict__ ops,
+                                             const int4* __restrict__ anchor, BoxGeom geo,
+                                             const float* __restrict__ s0, const float* __restrict__ s1,
+                                             const float* __restrict__ s2) {
     constexpr int RB = NP / 16, KC = NP / 32, WORDS = RB * 128;
     __shared__ uint4 lds0[WORDS];
     __shared__ uint4 lds1[WORDS];
@@ -446,6 +468,11 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
         int kc = 0;
         float breg[CB][8];
         const float* col[CB];
+        // STK: the source box of each column at the current slot, its shift
+        // into the target's frame, and its force-component columns
+        int sidx[CB];
+        float dsh[CB][3];
+        float bxr[CB][8], byr[CB][8], bzr[CB][8];
         // source index of each column at the slot after the current one, read
         // one slot ahead so that a slot change never waits for it
         int pre[CB];
@@ -457,11 +484,27 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
         auto issue = [&](int jj, int kk, bool newslot, uint4* dst) {
             if (newslot) {
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) col[cb] = pre[cb] >= 0 ? bsrc[cb] + size_t(pre[cb]) * NP : nullptr;
+                for (int cb = 0; cb < CB; ++cb) {
+                    col[cb] = pre[cb] >= 0 ? bsrc[cb] + size_t(pre[cb]) * NP : nullptr;
+                    if constexpr (STK) {
+                        sidx[cb] = pre[cb];
+                        dsh[cb][0] = dsh[cb][1] = dsh[cb][2] = 0.f;
+                        if (pre[cb] >= 0) centre_diff(geo, anchor[pre[cb]], anchor[tgt[cb]], dsh[cb]);
+                    }
+                }
             }
             dma_chunk<WORDS>(ops + (size_t(sop[jj]) * KC + kk) * WORDS, dst, tid);
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) load8(breg[cb], col[cb] ? col[cb] + kk * 32 + g8 : nullptr);
+            if constexpr (STK) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const size_t o8 = size_t(sidx[cb] >= 0 ? sidx[cb] : 0) * NP + kk * 32 + g8;
+                    load8(bxr[cb], sidx[cb] >= 0 ? s0 + o8 : nullptr);
+                    load8(byr[cb], sidx[cb] >= 0 ? s1 + o8 : nullptr);
+                    load8(bzr[cb], sidx[cb] >= 0 ? s2 + o8 : nullptr);
+                }
+            }
             if (newslot) read_pre(next_slot(vmask, jj));
         };
         // one chunk: wait until it has landed (all waves), start the next one
@@ -473,7 +516,11 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-                for (int i = 0; i < 8; ++i) cur[cb][i] = breg[cb][i];
+                for (int i = 0; i < 8; ++i) {
+                    cur[cb][i] = breg[cb][i];
+                    if constexpr (STK)
+                        cur[cb][i] += dsh[cb][0] * bxr[cb][i] + dsh[cb][1] * byr[cb][i] + dsh[cb][2] * bzr[cb][i];
+                }
             int nkc = kc + 1, nj = j;
             if (nkc == KC) {
                 nkc = 0;
@@ -557,14 +604,21 @@ __global__ __launch_bounds__(256, 3) void k_m2l(TaskTable tt, int nblk, int ntil
 // 1 MB) are read as MFMA fragments straight from L2.  The chained
 // check-to-equivalent factors need the whole intermediate vector: it is
 // exchanged through LDS in accumulator layout.
-template <int NP, bool UP>
+// STK (the Stokeslet's fourth charge in per-box frames): every gathered
+// source column adds (c_source - c_target) times the same box's densities of
+// the three force components (s0, s1, s2), which moves it into the target's
+// frame.
+template <int NP, bool UP, bool STK>
 __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, const int* __restrict__ list, int nl_start,
                                                 int nl_count, int has_l2l,
                                                 const int* __restrict__ nonleaf, const int2* __restrict__ child,
                                                 const int* __restrict__ leafflag, const float* __restrict__ psi_in,
                                                 int nsplit, size_t split_stride, const float* __restrict__ gsrc,
                                                 float* __restrict__ out, const uint4* __restrict__ gops,
-                                                const uint4* __restrict__ w1c, const uint4* __restrict__ vc) {
+                                                const uint4* __restrict__ w1c, const uint4* __restrict__ vc,
+                                                const int4* __restrict__ anchor, BoxGeom geo,
+                                                const float* __restrict__ s0, const float* __restrict__ s1,
+                                                const float* __restrict__ s2) {
     constexpr int RB = NP / 16, KC = NP / 32, NR = (RB + 3) / 4;
     __shared__ v4f xa[RB][64];
     __builtin_amdgcn_s_setprio(2);   // issue ahead of the near-field waves sharing the SIMD
@@ -623,7 +677,7 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, const 
     // source values already in flight
     const int nterm = UP ? __popc(flags) : (has_l2l ? 1 : 0);
     const int nst = nterm * KC;
-    auto step_src = [&](int st, const uint4*& A, const float*& b) {
+    auto step_src = [&](int st, const uint4*& A, const float*& b, int& sb) {
         const int t = st / KC, kc = st % KC;
         int op = o;
         if (UP) {
@@ -631,22 +685,35 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, const 
             for (int k = 0; k < t; ++k) f &= f - 1;
             op = __builtin_ctz(f);
         }
-        const float* src = nullptr;
+        sb = -1;
         if (UP) {
-            if ((cmask >> op) & 1) src = gsrc + size_t(cfirst + __popc(cmask & ((1 << op) - 1))) * NP;
+            if ((cmask >> op) & 1) sb = cfirst + __popc(cmask & ((1 << op) - 1));
         } else if (par >= 0) {
-            src = gsrc + size_t(par) * NP;
+            sb = par;
         }
         A = gops + (size_t(op) * KC + kc) * RB * 128 + lane;
-        b = src ? src + kc * 32 + g8 : nullptr;
+        b = sb >= 0 ? gsrc + size_t(sb) * NP + kc * 32 + g8 : nullptr;
     };
     uint4 an[NR][2];
     float bn[8];
     auto fetch = [&](int st) {
         const uint4* A;
         const float* b;
-        step_src(st, A, b);
+        int sb;
+        step_src(st, A, b, sb);
         load8(bn, b);
+        if constexpr (STK) {
+            if (sb >= 0) {
+                const size_t o8 = size_t(sb) * NP + (st % KC) * 32 + g8;
+                float bx[8], by[8], bz[8], d[3];
+                load8(bx, s0 + o8);
+                load8(by, s1 + o8);
+                load8(bz, s2 + o8);
+                centre_diff(geo, anchor[sb], anchor[tgt], d);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) bn[k] += d[0] * bx[k] + d[1] * by[k] + d[2] * bz[k];
+            }
+        }
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             const int rb = wave + 4 * i;
@@ -739,6 +806,10 @@ struct FarOut {
     double o[3];
     double k1;
     int acc;               // 1: outputs are added to instead of overwritten
+    // the Stokeslet's fourth charge in per-box frames: upward densities of the
+    // three force components, whose (c_A - c_leaf) multiples move a W-list
+    // density into the target leaf's frame (null otherwise)
+    const float* wsh[3];
 };
 
 // The non-harmonic part k1 |x - y|^2 of the periodic kernel summed over the
@@ -798,11 +869,19 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
         const int A = img_box(e);
         const float* D = (own ? phi_d : phi_u) + size_t(A) * NP;
         const float4* SF = own ? surf + NP : surf;   // downward (2.95) or upward (1.05) equivalent surface
+        float dsh[3] = {0.f, 0.f, 0.f};
+        const bool shift = !own && out.wsh[0];
+        if (shift) centre_diff(geo, anchor[A], anchor[b], dsh);
         __syncthreads();   // the previous source is no longer read
         for (int t = tid; t < NP; t += 256) {
             const bool real = t < n;
             const float4 sp = SF[real ? t : 0];
-            stage[t] = make_float4(sp.x, sp.y, sp.z, real ? D[t] : 0.f);
+            float dv = real ? D[t] : 0.f;
+            if (shift && real) {
+                const size_t at = size_t(A) * NP + t;
+                dv += dsh[0] * out.wsh[0][at] + dsh[1] * out.wsh[1][at] + dsh[2] * out.wsh[2][at];
+            }
+            stage[t] = make_float4(sp.x, sp.y, sp.z, dv);
             if (BWD) stage2[t] = real ? D[rhs_stride + t] : 0.f;
         }
         __syncthreads();
@@ -1246,7 +1325,7 @@ int first_down_level(const kifmm_plan* P) { return P->periodic ? 0 : 2; }
 // check potentials; null for zero), partials out [split][rhs][B][NP].
 template <int NP>
 void launch_m2l_tile(kifmm_plan* P, int nrhs, int rhs, hipStream_t s, const float* src, const float* init,
-                     float* out, const uint4* ops_f32, const uint4* ops_bf16) {
+                     float* out, const uint4* ops_f32, const uint4* ops_bf16, const float* const* stk3) {
     const int depth = P->depth;
     const int lv = first_v_level(P);
     if (depth < lv) return;
@@ -1279,28 +1358,39 @@ void launch_m2l_tile(kifmm_plan* P, int nrhs, int rhs, hipStream_t s, const floa
     const float* psi_d = init ? init + size_t(rhs) * stride : nullptr;
     float* psi_m = out + size_t(rhs) * stride;
     const int total = blocks * nsplit;
-#define KIFMM_M2L_LAUNCH(SPL, CBV, OPS)                                                                          \
-    hipLaunchKernelGGL((k_m2l<NP, SPL, CBV>), dim3(total), dim3(WAVES * 64), 0, s, tt, total, blocks, nsplit,  \
-                       nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2, vops_device(), \
-                       phi_u, psi_d, P->xflag.as<int>(), psi_m, stride, sstride, OPS)
+    const BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
+    const float* const none[3] = {nullptr, nullptr, nullptr};
+    const float* const* s3 = stk3 ? stk3 : none;
+#define KIFMM_M2L_LAUNCH(SPL, CBV, OPS, STKV)                                                                    \
+    hipLaunchKernelGGL((k_m2l<NP, SPL, CBV, STKV>), dim3(total), dim3(WAVES * 64), 0, s, tt, total, blocks,     \
+                       nsplit, nrhs, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->vdense.as<int>(), b2,     \
+                       vops_device(), phi_u, psi_d, P->xflag.as<int>(), psi_m, stride, sstride, OPS,            \
+                       P->bx_anchor.as<int4>(), geo, s3[0], s3[1], s3[2])
     const bool split = P->opt.precision == KIFMM_SPLIT_BF16;
-    if (split) KIFMM_M2L_LAUNCH(true, M2L_CB, ops_bf16);
-    else KIFMM_M2L_LAUNCH(false, M2L_CB, ops_f32);
+    if (stk3) {
+        if (nrhs != 1) throw Error(KIFMM_ERR_STATE, "the framed Stokes M2L takes one right-hand side");
+        if (split) KIFMM_M2L_LAUNCH(true, M2L_CB, ops_bf16, true);
+        else KIFMM_M2L_LAUNCH(false, M2L_CB, ops_f32, true);
+    } else {
+        if (split) KIFMM_M2L_LAUNCH(true, M2L_CB, ops_bf16, false);
+        else KIFMM_M2L_LAUNCH(false, M2L_CB, ops_f32, false);
+    }
 #undef KIFMM_M2L_LAUNCH
 }
 
+// sf: right-hand side `rhs` is the Stokeslet's fourth charge in per-box frames
 template <int NP>
-void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s) {
+void launch_m2l(kifmm_plan* P, int nrhs, int rhs, hipStream_t s, const StokesFrames* sf = nullptr) {
     if (!P->cm) {
         const Operators& op = *P->ops;
         launch_m2l_tile<NP>(P, nrhs, rhs, s, P->phi_u.as<float>(), P->psi_d.as<float>(), P->psi_m.as<float>(),
-                            op.m2l_f32.as<uint4>(), op.m2l_bf16.as<uint4>());
+                            op.m2l_f32.as<uint4>(), op.m2l_bf16.as<uint4>(), sf ? sf->up : nullptr);
         return;
     }
     const M2LBasis& cm = *P->cm;
 #define KIFMM_M2L_TILE(KP)                                                                                     \
     launch_m2l_tile<KP>(P, nrhs, rhs, s, P->phi_k.as<float>(), nullptr, P->psi_m.as<float>(),               \
-                        cm.core_f32.as<uint4>(), cm.core_bf16.as<uint4>())
+                        cm.core_f32.as<uint4>(), cm.core_bf16.as<uint4>(), sf ? sf->kp : nullptr)
     switch (cm.kp) {
         case 32: KIFMM_M2L_TILE(32); break;
         case 64: KIFMM_M2L_TILE(64); break;
@@ -1353,8 +1443,12 @@ void project_expand(kifmm_plan* P, bool project, int r, hipStream_t s) {
 // dL/dE).  With both, M2L carries the two columns through each operator load.
 // `between` runs after P2M (the caller forks the near field there).
 template <int NP>
-void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const std::function<void()>& between) {
+void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const std::function<void()>& between,
+                const StokesFrames* sf) {
     const Operators& op = *P->ops;
+    // right-hand side 1 of a Stokes sweep carries the fourth charge in per-box frames
+    auto stk = [&](int r) { return sf != nullptr && r == 1; };
+    const int4* anc = P->bx_anchor.as<int4>();
     const int B = int(P->B);
     const size_t stride = size_t(B) * NP;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
@@ -1384,7 +1478,8 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
     for (int r = r0; r < r1; ++r)
         hipLaunchKernelGGL(k_p2m<NP>, dim3(unsigned(P->nleaves)), dim3(tpb), 0, s, P->leaves.as<int>(),
                            int(P->nleaves), b2, P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), pts,
-                           r ? P->src2.as<float4>() : nullptr, surf, op.n, geo, P->psi_u.as<float>() + r * stride);
+                           (r && !stk(r)) ? P->src2.as<float4>() : nullptr, stk(r) ? sf->frc : nullptr, surf, op.n,
+                           geo, P->psi_u.as<float>() + r * stride);
     if (rec) record_phase(P, 0, s);
     between();
     // upward UC2E of the leaves (every level from ld in one launch), then
@@ -1395,17 +1490,22 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
     for (int l = 0; l < ld; ++l) lf0 += P->lev[l].count - P->lev[l].nl_count;
     const int nlf = int(P->nleaves - lf0);
     for (int r = r0; r < r1; ++r) {
-        auto up = [&](const int* list, int b0, int nb) {
+        auto up = [&](const int* list, int b0, int nb, bool shift) {
             const int blocks = nblk(nb, 16);
             if (blocks == 0) return;
-            hipLaunchKernelGGL((k_updown<NP, true>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, b0, nb, list, 0,
-                               0, 0, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(),
-                               P->psi_u.as<float>() + r * stride, 1, size_t(0), P->phi_u.as<float>() + r * stride,
-                               P->phi_u.as<float>() + r * stride, op.m2m.as<uint4>(), op.uc2e_w1.as<uint4>(),
-                               op.uc2e_v.as<uint4>());
+#define KIFMM_UP(STKV, S0, S1, S2)                                                                                 \
+    hipLaunchKernelGGL((k_updown<NP, true, STKV>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, b0, nb, list, 0, 0, \
+                       0, P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(),                       \
+                       P->psi_u.as<float>() + r * stride, 1, size_t(0), P->phi_u.as<float>() + r * stride,         \
+                       P->phi_u.as<float>() + r * stride, op.m2m.as<uint4>(), op.uc2e_w1.as<uint4>(),               \
+                       op.uc2e_v.as<uint4>(), anc, geo, S0, S1, S2)
+            if (shift) KIFMM_UP(true, sf->up[0], sf->up[1], sf->up[2]);
+            else KIFMM_UP(false, (const float*)nullptr, (const float*)nullptr, (const float*)nullptr);
+#undef KIFMM_UP
         };
-        up(P->leaves.as<int>(), int(lf0), nlf);
-        for (int l = depth; l >= ld; --l) up(P->nonleaf.as<int>(), int(P->lev[l].nl_start), int(P->lev[l].nl_count));
+        up(P->leaves.as<int>(), int(lf0), nlf, false);
+        for (int l = depth; l >= ld; --l)
+            up(P->nonleaf.as<int>(), int(P->lev[l].nl_start), int(P->lev[l].nl_count), stk(r));
     }
     // periodic root: every image beyond the root's neighbours
     if (P->periodic) {
@@ -1426,15 +1526,15 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
         if (P->n_xboxes > 0)
             hipLaunchKernelGGL(k_p2l<NP>, dim3(unsigned(P->n_xboxes)), dim3(tpb), 0, s, P->xboxes.as<int>(),
                                P->x_off.as<int>(), P->x_idx.as<int>(), P->bx_anchor.as<int4>(),
-                               P->bx_range.as<int2>(), pts, r ? P->src2.as<float4>() : nullptr, surf, op.n, geo,
-                               psi_d);
+                               P->bx_range.as<int2>(), pts, (r && !stk(r)) ? P->src2.as<float4>() : nullptr,
+                               stk(r) ? sf->frc : nullptr, surf, op.n, geo, psi_d);
     }
     if (rec) record_phase(P, 2, s);
-    // V list
-    if (r1 - r0 == 2) {
+    // V list (a Stokes sweep's two right-hand sides differ in kernel: one launch each)
+    if (r1 - r0 == 2 && !sf) {
         launch_m2l<NP>(P, 2, 0, s);
     } else {
-        for (int r = r0; r < r1; ++r) launch_m2l<NP>(P, 1, r, s);
+        for (int r = r0; r < r1; ++r) launch_m2l<NP>(P, 1, r, s, stk(r) ? sf : nullptr);
     }
     if (rec) record_phase(P, 3, s);
     // compressed M2L: its results back on the check surfaces, added to the X
@@ -1447,26 +1547,33 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
             const LevelInfo& pl = P->lev[l - 1];
             const int blocks = nblk(pl.nl_count, 16) * 8;
             if (blocks == 0) continue;
-            hipLaunchKernelGGL((k_updown<NP, false>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, 0, 0,
-                               (const int*)nullptr, int(pl.nl_start), int(pl.nl_count), l > ld ? 1 : 0, P->nonleaf.as<int>(),
-                               P->bx_child.as<int2>(), P->bx_leaf.as<int>(),
-                               // the check potentials: M2L partials (with the X list in the first), or,
-                               // compressed, the expanded sum already in psi_d
-                               P->cm ? P->psi_d.as<float>() + r * stride : P->psi_m.as<float>() + r * stride,
-                               P->cm ? 1 : P->m2l_split_used, 2 * stride, P->phi_d.as<float>() + r * stride,
-                               P->phi_d.as<float>() + r * stride, op.l2l.as<uint4>(), op.dc2e_w1.as<uint4>(),
-                               op.dc2e_v.as<uint4>());
+#define KIFMM_DOWN(STKV, S0, S1, S2)                                                                              \
+    hipLaunchKernelGGL((k_updown<NP, false, STKV>), dim3(blocks), dim3(WAVES * 64), 0, s, blocks, 0, 0,           \
+                       (const int*)nullptr, int(pl.nl_start), int(pl.nl_count), l > ld ? 1 : 0,                    \
+                       P->nonleaf.as<int>(), P->bx_child.as<int2>(), P->bx_leaf.as<int>(),                         \
+                       P->cm ? P->psi_d.as<float>() + r * stride : P->psi_m.as<float>() + r * stride,              \
+                       P->cm ? 1 : P->m2l_split_used, 2 * stride, P->phi_d.as<float>() + r * stride,               \
+                       P->phi_d.as<float>() + r * stride, op.l2l.as<uint4>(), op.dc2e_w1.as<uint4>(),              \
+                       op.dc2e_v.as<uint4>(), anc, geo, S0, S1, S2)
+            // the check potentials: M2L partials (with the X list in the first), or,
+            // compressed, the expanded sum already in psi_d
+            if (stk(r)) KIFMM_DOWN(true, sf->dn[0], sf->dn[1], sf->dn[2]);
+            else KIFMM_DOWN(false, (const float*)nullptr, (const float*)nullptr, (const float*)nullptr);
+#undef KIFMM_DOWN
         }
     if (rec) record_phase(P, 4, s);
 }
 
 template <int NP>
-void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc, bool near) {
+void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc, bool near,
+              const StokesFrames* sf) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
     const int b2 = int(P->bfar);
     FarOut fo{near ? P->nearv.as<float4>() : nullptr, P->perm.as<int>(), out_a, out_b, nullptr, {0, 0, 0}, 0.0,
-              acc ? 1 : 0};
+              acc ? 1 : 0, {nullptr, nullptr, nullptr}};
+    if (sf)
+        for (int d = 0; d < 3; ++d) fo.wsh[d] = sf->up[d];
     if (P->periodic) {
         fo.mom = P->mom.as<double>() + (bwd ? 0 : 16 * rhs);
         for (int d = 0; d < 3; ++d) fo.o[d] = P->lo[d] + 0.5 * P->side;
@@ -1490,7 +1597,7 @@ template <int NP>
 void far_grad_impl(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
-    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), pot, field, nullptr, {0, 0, 0}, 0.0, 0};
+    FarOut fo{P->nearv.as<float4>(), P->perm.as<int>(), pot, field, nullptr, {0, 0, 0}, 0.0, 0, {nullptr, nullptr, nullptr}};
     if (P->periodic) {
         fo.mom = P->mom.as<double>() + 16 * rhs;
         for (int d = 0; d < 3; ++d) fo.o[d] = P->lo[d] + 0.5 * P->side;
@@ -1507,16 +1614,36 @@ void far_grad_impl(kifmm_plan* P, float* pot, float* field, float* grad, hipStre
 }  // namespace
 
 namespace {
+// Offset of every sorted point from the centre of its leaf (FP64, then FP32):
+// the frame of the fourth harmonic charge at the targets.
+__global__ __launch_bounds__(256) void k_stokes_frames(const int* __restrict__ leaves, const int4* __restrict__ anchor,
+                                                       const int2* __restrict__ range, const int* __restrict__ perm,
+                                                       const double* __restrict__ x64, BoxGeom geo,
+                                                       float4* __restrict__ frame) {
+    const int b = leaves[blockIdx.x];
+    const int4 a = anchor[b];
+    const int2 r = range[b];
+    const double wd = ldexp(geo.side, -a.w);
+    const double c0 = geo.lo[0] + (double(a.x) + 0.5) * wd, c1 = geo.lo[1] + (double(a.y) + 0.5) * wd,
+                 c2 = geo.lo[2] + (double(a.z) + 0.5) * wd;
+    for (int i = r.x + threadIdx.x; i < r.y; i += 256) {
+        const size_t j = size_t(perm[i]);
+        frame[i] = make_float4(float(x64[3 * j] - c0), float(x64[3 * j + 1] - c1), float(x64[3 * j + 2] - c2), 0.f);
+    }
+}
+
 // Stokeslet velocity from the four harmonic charges' potentials psi_k and
-// fields E(k) (caller order) and the near part (sorted):
-//   u_a = cf (psi_a + x'_k E(k)_a - E(4)_a) + near_a,  x' = x - o.
-__global__ void k_stokes_combine(int64_t N, const int* __restrict__ perm, const double* __restrict__ x64, double o0,
-                                 double o1, double o2, const float* __restrict__ pot, const float* __restrict__ fld,
+// fields E(k) (caller order; the fourth about each target's leaf centre) and
+// the near part (sorted):
+//   u_a = cf (psi_a + x'_k E(k)_a - E(4)_a) + near_a,  x' = x - (leaf centre).
+__global__ void k_stokes_combine(int64_t N, const int* __restrict__ perm, const float4* __restrict__ frame,
+                                 const float* __restrict__ pot, const float* __restrict__ fld,
                                  const float4* __restrict__ near, float cf, float* __restrict__ u) {
     int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
     if (i >= N) return;
     const size_t j = size_t(perm[i]);
-    const float xp[3] = {float(x64[3 * j] - o0), float(x64[3 * j + 1] - o1), float(x64[3 * j + 2] - o2)};
+    const float4 fr = frame[i];
+    const float xp[3] = {fr.x, fr.y, fr.z};
     const float4 nr = near[i];
     const float na[3] = {nr.x, nr.y, nr.z};
     const size_t sN = size_t(N);
@@ -1528,13 +1655,21 @@ __global__ void k_stokes_combine(int64_t N, const int* __restrict__ perm, const 
 }
 }  // namespace
 
+void launch_stokes_frames(kifmm_plan* P, hipStream_t s) {
+    P->stk_frame.ensure(size_t(P->N) * 16);
+    const BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
+    if (P->nleaves > 0)
+        hipLaunchKernelGGL(k_stokes_frames, dim3(unsigned(P->nleaves)), dim3(256), 0, s, P->leaves.as<int>(),
+                           P->bx_anchor.as<int4>(), P->bx_range.as<int2>(), P->perm.as<int>(), P->x64.as<double>(),
+                           geo, P->stk_frame.as<float4>());
+}
+
 void launch_stokes_combine(kifmm_plan* P, double viscosity, float* velocity, hipStream_t s) {
     const int64_t N = P->N;
     const float* pot = P->stk_far.as<float>();
     const float* fld = pot + 4 * size_t(N);
-    const double o[3] = {P->lo[0] + 0.5 * P->side, P->lo[1] + 0.5 * P->side, P->lo[2] + 0.5 * P->side};
     hipLaunchKernelGGL(k_stokes_combine, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, N, P->perm.as<int>(),
-                       P->x64.as<double>(), o[0], o[1], o[2], pot, fld, P->stk_near.as<float4>(),
+                       P->stk_frame.as<float4>(), pot, fld, P->stk_near.as<float4>(),
                        float(1.0 / (8.0 * M_PI * viscosity * P->c)), velocity);
 }
 
@@ -1550,27 +1685,28 @@ void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStrea
     }
 }
 
-void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between) {
+void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const std::function<void()>& between,
+               const StokesFrames* sf) {
     switch (P->npad) {
-        case 32: sweep_impl<32>(P, r0, r1, s, record, between); break;
-        case 64: sweep_impl<64>(P, r0, r1, s, record, between); break;
-        case 128: sweep_impl<128>(P, r0, r1, s, record, between); break;
-        case 160: sweep_impl<160>(P, r0, r1, s, record, between); break;
-        case 224: sweep_impl<224>(P, r0, r1, s, record, between); break;
-        case 320: sweep_impl<320>(P, r0, r1, s, record, between); break;
+        case 32: sweep_impl<32>(P, r0, r1, s, record, between, sf); break;
+        case 64: sweep_impl<64>(P, r0, r1, s, record, between, sf); break;
+        case 128: sweep_impl<128>(P, r0, r1, s, record, between, sf); break;
+        case 160: sweep_impl<160>(P, r0, r1, s, record, between, sf); break;
+        case 224: sweep_impl<224>(P, r0, r1, s, record, between, sf); break;
+        case 320: sweep_impl<320>(P, r0, r1, s, record, between, sf); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }
 
 void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc,
-                  bool near) {
+                  bool near, const StokesFrames* sf) {
     switch (P->npad) {
-        case 32: far_impl<32>(P, backward, out_a, out_b, s, rhs, acc, near); break;
-        case 64: far_impl<64>(P, backward, out_a, out_b, s, rhs, acc, near); break;
-        case 128: far_impl<128>(P, backward, out_a, out_b, s, rhs, acc, near); break;
-        case 160: far_impl<160>(P, backward, out_a, out_b, s, rhs, acc, near); break;
-        case 224: far_impl<224>(P, backward, out_a, out_b, s, rhs, acc, near); break;
-        case 320: far_impl<320>(P, backward, out_a, out_b, s, rhs, acc, near); break;
+        case 32: far_impl<32>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
+        case 64: far_impl<64>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
+        case 128: far_impl<128>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
+        case 160: far_impl<160>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
+        case 224: far_impl<224>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
+        case 320: far_impl<320>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }

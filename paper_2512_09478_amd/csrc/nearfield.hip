@@ -370,13 +370,12 @@ __global__ __launch_bounds__(256, 8) void k_p2p_bwd(const int2* __restrict__ ite
 }
 
 // Stokeslet sources: pass 0 sets pts.w = f_x, src2 = (f_y, 0, 0, 0) and the
-// sorted forces stk = (f_x, f_y, f_z, 0); pass 1 sets pts.w = f_z and
-// src2 = (x' . f, 0, 0, 0), x' = x - o (FP64 positions), the charges of the
-// four harmonic potentials of the decomposition.
-__global__ void k_gather_stokes(int64_t N, const float4* __restrict__ xs, const double* __restrict__ x64,
-                                const int* __restrict__ perm, const float* __restrict__ f, double o0, double o1,
-                                double o2, int pass, float4* __restrict__ pts, float4* __restrict__ src2,
-                                float4* __restrict__ stk) {
+// sorted forces stk = (f_x, f_y, f_z, 0); pass 1 sets pts.w = f_z.  The
+// fourth harmonic charge, (x - c) . f about each box's centre c, is formed
+// from stk where a box's sources are summed.
+__global__ void k_gather_stokes(int64_t N, const float4* __restrict__ xs, const int* __restrict__ perm,
+                                const float* __restrict__ f, int pass, float4* __restrict__ pts,
+                                float4* __restrict__ src2, float4* __restrict__ stk) {
     int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
     if (i >= N) return;
     const size_t j = size_t(perm[i]);
@@ -388,9 +387,6 @@ __global__ void k_gather_stokes(int64_t N, const float4* __restrict__ xs, const 
         stk[i] = make_float4(fx, fy, fz, 0.f);
     } else {
         x.w = fz;
-        const double m = (x64[3 * j] - o0) * double(fx) + (x64[3 * j + 1] - o1) * double(fy) +
-                         (x64[3 * j + 2] - o2) * double(fz);
-        src2[i] = make_float4(float(m), 0.f, 0.f, 0.f);
     }
     pts[i] = x;
 }
@@ -465,10 +461,9 @@ void launch_gather_stokes(kifmm_plan* P, const float* forces, int pass, hipStrea
     P->pts.ensure(size_t(N) * 16);
     P->src2.ensure(size_t(N) * 16);
     P->stk.ensure(size_t(N) * 16);
-    const double o[3] = {P->lo[0] + 0.5 * P->side, P->lo[1] + 0.5 * P->side, P->lo[2] + 0.5 * P->side};
     hipLaunchKernelGGL(k_gather_stokes, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, N, P->xs.as<float4>(),
-                       P->x64.as<double>(), P->perm.as<int>(), forces, o[0], o[1], o[2], pass, P->pts.as<float4>(),
-                       P->src2.as<float4>(), P->stk.as<float4>());
+                       P->perm.as<int>(), forces, pass, P->pts.as<float4>(), P->src2.as<float4>(),
+                       P->stk.as<float4>());
 }
 
 void launch_p2p_stokes(kifmm_plan* P, double viscosity, hipStream_t s) {

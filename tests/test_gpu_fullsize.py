@@ -283,9 +283,12 @@ def test_clustered_1M_dipoles_gradient_and_stokes():
     """The other sums of eq. (1) at the headline size, with the inputs that
     `bench.py --f4` times: charges with point dipoles (u, E and dE/dx) and
     the Stokeslet velocity of point forces, sampled against the oracle on
-    the same plan.  The Stokes tolerance is the charge sums' FP32 bound times
-    the amplification of the one-origin decomposition, measured from the
-    oracle's far and near parts at these targets."""
+    the same plan.  The library forms the Stokeslet's fourth harmonic charge
+    about each box's own centre; the oracle's far and near parts show that
+    the combination about the targets' leaf centres does not amplify errors
+    of the far fields (about 0.9 here, against 12.5 about the root's centre),
+    and the velocity is held to 2e-5 (FP32), the FP32 accuracy of far fields
+    that make up most of it, and 1e-4 (split)."""
     from oracle import stokes
     say("clustered 1,048,576 points: dipoles, field gradient and Stokeslet")
     w = workloads.make(2)
@@ -299,9 +302,11 @@ def test_clustered_1M_dipoles_gradient_and_stokes():
     uo, Eo, Go = kifmm.forward_dipoles(P, w.charges, m, targets=idx, grad=True)
     say(f"  oracle sampled dipole sweep {time.time() - t:.1f} s")
     t = time.time()
-    vo, vmag = stokes.kifmm(P, f, mu, targets=idx, terms=True)
+    vo, vmag = stokes.kifmm(P, f, mu, targets=idx, terms=True, frame="leaf")
     kappa = float(np.linalg.norm(vmag) / np.linalg.norm(vo))
-    say(f"  oracle sampled Stokes sum {time.time() - t:.1f} s; amplification of the combination {kappa:.2f}")
+    say(f"  oracle sampled Stokes sum {time.time() - t:.1f} s; amplification of the leaf-frame combination "
+        f"{kappa:.2f}")
+    assert kappa < 1.5
     q = torch.tensor(w.charges, dtype=torch.float32, device="cuda")
     md = torch.tensor(m, dtype=torch.float32, device="cuda")
     fd = torch.tensor(f, dtype=torch.float32, device="cuda")
@@ -317,5 +322,5 @@ def test_clustered_1M_dipoles_gradient_and_stokes():
         check("u (gradient call)", u2.cpu().numpy()[idx], uo, tol)
         check("E (gradient call)", E2.cpu().numpy()[idx], Eo, tol)
         check("dE/dx", Gr.cpu().numpy()[idx], Go, tol)
-        check("Stokes velocity", v.cpu().numpy()[idx], vo, max(tol, 1e-5 * kappa))
+        check("Stokes velocity", v.cpu().numpy()[idx], vo, 2e-5 if precision == "fp32" else tol)
         G.close()

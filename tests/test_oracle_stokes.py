@@ -131,14 +131,17 @@ def test_kifmm_stokes_converges_to_the_direct_sum():
 def test_kifmm_stokes_terms_bound_the_far_velocity():
     """With terms, the same velocity, and magnitudes that bound its far part
     (the velocity minus the Stokeslet summed directly over the near lists)
-    term by term."""
+    term by term, about the root's centre and about each target's leaf
+    centre."""
     w = workloads.make(2, n=4000)
     f = workloads.round_f32(np.random.default_rng(9).standard_normal((w.n, 3)))
     P = kifmm.plan(w.positions, "laplace", 4, 32, True, 21, w.root)
     idx = np.random.default_rng(10).choice(w.n, 30, replace=False)
     u = stokes.kifmm(P, f, 0.7, targets=idx)
     u2, mag = stokes.kifmm(P, f, 0.7, targets=idx, terms=True)
-    assert np.array_equal(u, u2)
+    u3, mag_leaf = stokes.kifmm(P, f, 0.7, targets=idx, terms=True, frame="leaf")
+    assert np.array_equal(u, u2) and np.array_equal(u, u3)
+    c = stokes.leaf_centres(P, idx)
     t = P.tree
     inv = np.empty_like(t.perm)
     inv[t.perm] = np.arange(P.n)
@@ -153,4 +156,9 @@ def test_kifmm_stokes_terms_bound_the_far_velocity():
                            np.concatenate([f[t.perm[src]], np.zeros((1, 3))]), 0.7, targets=[len(src)])[0]
         far = u[k] - un
         assert np.all(np.abs(far) <= mag[k] * (1 + 1e-9) + 1e-12 * np.abs(u[k]).max())
+        assert np.all(np.abs(far) <= mag_leaf[k] * (1 + 1e-9) + 1e-12 * np.abs(u[k]).max())
         assert np.abs(far).max() > 1e-3 * np.abs(u[k]).max()
+        # the leaf frame's origin is the centre of the target's own leaf
+        wl = P.tree.width(int(P.tree.level[leaf]))
+        np.testing.assert_allclose(c[k], P.tree.center(leaf), rtol=0, atol=1e-15)
+        assert np.all(np.abs(w.positions[i] - c[k]) <= 0.5 * wl * (1 + 1e-12))
