@@ -201,18 +201,21 @@ int kifmm_evaluate_gradient(kifmm_handle h, const float* charges, const float* d
  *   u_i = 1/(8 pi mu) sum_{j : x_j != x_i} [ f_j / r + (r . f_j) r / r^3 ],  r = x_i - x_j.
  * The near lists are summed point to point with this kernel; the rest comes
  * from four charge evaluations of the plan's Laplace method (the harmonic
- * decomposition of the Stokeslet: with x' = x - o, o the root cube's centre,
- * the charges f_x, f_y, f_z and x' . f give potentials psi_k and fields E(k),
+ * decomposition of the Stokeslet: with x' = x - o for any fixed o, the
+ * charges f_x, f_y, f_z and x' . f give potentials psi_k and fields E(k),
  * and sum S f = (psi_a + x'_k E(k)_a - E(4)_a) / c).
  *   forces     device [N][3] float, caller order.
  *   viscosity  mu > 0.
  *   velocity   device [N][3] float, caller order.
  * Needs a free-space Laplace plan (KIFMM_ERR_STATE otherwise).  Two sweeps of
  * two right-hand sides each; afterwards kifmm_backward needs its charges.
- * Accuracy: the far terms x'_k E(k) and E(4) exceed their difference by up to
- * |x'| over the distance to the far sources, so the relative rounding of the
- * four FP32 far fields is amplified by that ratio; it grows as the leaves
- * shrink (about 12 at a million clustered points, below 1 at ten thousand).
+ * The fourth charge is formed about each box's own centre c, (y - c) . f,
+ * and every translation adds the shift of centres times the box's densities
+ * of f_x, f_y, f_z; each target combines about its leaf centre, so no term
+ * carries the distance to a far origin (with one origin the far terms grow
+ * as |x - o| over the distance to the sources, about 12-fold at a million
+ * clustered points).  Workspace beyond kifmm_evaluate: the first sweep's
+ * densities of f_x, f_y and one float4 per point, kept by the plan.
  */
 int kifmm_evaluate_stokes(kifmm_handle h, const float* forces, double viscosity, float* velocity, void* stream);
 
