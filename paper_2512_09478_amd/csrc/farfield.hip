@@ -388,9 +388,10 @@ __device__ inline void load8(float* b, const float* __restrict__ p) {
 // 32-column chunks (fragment order, NP/16*128 words) through a double-buffered
 // LDS tile shared by the four waves, while the next chunk and the next source
 // columns are already in flight.
-// STK (the Stokeslet's fourth charge in per-box frames, one right-hand side):
-// each source column adds (c_source - c_target) times the source box's
-// columns of the three force components (s0, s1, s2).
+// STK (a Stokes sweep, two right-hand sides: f_z, then the fourth charge in
+// per-box frames): each source column of the second adds (c_source -
+// c_target) times the source box's columns of f_x, f_y (s0, s1) and of f_z,
+// the first right-hand side's column of the same source (s2 is not read).
 template <int NP, bool SPLIT, int CB, bool STK>
 __global__ __launch_bounds__(256, STK ? 2 : 3) void k_m2l(TaskTable tt, int nblk, int ntile, int nsplit, int nrhs,
                                              const int* __restrict__ nonleaf, const int2* __restrict__ child,
@@ -469,10 +470,10 @@ __global__ __launch_bounds__(256, STK ? 2 : 3) void k_m2l(TaskTable tt, int nblk
         float breg[CB][8];
         const float* col[CB];
         // STK: the source box of each column at the current slot, its shift
-        // into the target's frame, and its force-component columns
+        // into the target's frame, and its f_x, f_y columns (odd columns)
         int sidx[CB];
         float dsh[CB][3];
-        float bxr[CB][8], byr[CB][8], bzr[CB][8];
+        float bxr[CB][8], byr[CB][8];
         // source index of each column at the slot after the current one, read
         // one slot ahead so that a slot change never waits for it
         int pre[CB];
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(256, STK ? 2 : 3) void k_m2l(TaskTable tt, int nblk
                     if constexpr (STK) {
                         sidx[cb] = pre[cb];
                         dsh[cb][0] = dsh[cb][1] = dsh[cb][2] = 0.f;
-                        if (pre[cb] >= 0) centre_diff(geo, anchor[pre[cb]], anchor[tgt[cb]], dsh[cb]);
+                        if ((cb & 1) && pre[cb] >= 0) centre_diff(geo, anchor[pre[cb]], anchor[tgt[cb]], dsh[cb]);
                     }
                 }
             }
@@ -498,11 +499,10 @@ __global__ __launch_bounds__(256, STK ? 2 : 3) void k_m2l(TaskTable tt, int nblk
             for (int cb = 0; cb < CB; ++cb) load8(breg[cb], col[cb] ? col[cb] + kk * 32 + g8 : nullptr);
             if constexpr (STK) {
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
+                for (int cb = 1; cb < CB; cb += 2) {
                     const size_t o8 = size_t(sidx[cb] >= 0 ? sidx[cb] : 0) * NP + kk * 32 + g8;
                     load8(bxr[cb], sidx[cb] >= 0 ? s0 + o8 : nullptr);
                     load8(byr[cb], sidx[cb] >= 0 ? s1 + o8 : nullptr);
-                    load8(bzr[cb], sidx[cb] >= 0 ? s2 + o8 : nullptr);
                 }
             }
             if (newslot) read_pre(next_slot(vmask, jj));
@@ -519,7 +519,9 @@ __global__ __launch_bounds__(256, STK ? 2 : 3) void k_m2l(TaskTable tt, int nblk
                 for (int i = 0; i < 8; ++i) {
                     cur[cb][i] = breg[cb][i];
                     if constexpr (STK)
-                        cur[cb][i] += dsh[cb][0] * bxr[cb][i] + dsh[cb][1] * byr[cb][i] + dsh[cb][2] * bzr[cb][i];
+                        if (cb & 1)
+                            cur[cb][i] += dsh[cb][0] * bxr[cb][i] + dsh[cb][1] * byr[cb][i] +
+                                          dsh[cb][2] * breg[cb - 1][i];
                 }
             int nkc = kc + 1, nj = j;
             if (nkc == KC) {
@@ -1368,7 +1370,7 @@ void launch_m2l_tile(kifmm_plan* P, int nrhs, int rhs, hipStream_t s, const floa
                        P->bx_anchor.as<int4>(), geo, s3[0], s3[1], s3[2])
     const bool split = P->opt.precision == KIFMM_SPLIT_BF16;
     if (stk3) {
-        if (nrhs != 1) throw Error(KIFMM_ERR_STATE, "the framed Stokes M2L takes one right-hand side");
+        if (nrhs != 2) throw Error(KIFMM_ERR_STATE, "the framed Stokes M2L takes the sweep's two right-hand sides");
         if (split) KIFMM_M2L_LAUNCH(true, M2L_CB, ops_bf16, true);
         else KIFMM_M2L_LAUNCH(false, M2L_CB, ops_f32, true);
     } else {
@@ -1530,11 +1532,12 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
                                stk(r) ? sf->frc : nullptr, surf, op.n, geo, psi_d);
     }
     if (rec) record_phase(P, 2, s);
-    // V list (a Stokes sweep's two right-hand sides differ in kernel: one launch each)
-    if (r1 - r0 == 2 && !sf) {
-        launch_m2l<NP>(P, 2, 0, s);
+    // V list (a Stokes sweep's second right-hand side in per-box frames)
+    if (sf && (r0 != 0 || r1 != 2)) throw Error(KIFMM_ERR_STATE, "a Stokes sweep has right-hand sides 0 and 1");
+    if (r1 - r0 == 2) {
+        launch_m2l<NP>(P, 2, 0, s, sf);
     } else {
-        for (int r = r0; r < r1; ++r) launch_m2l<NP>(P, 1, r, s, stk(r) ? sf : nullptr);
+        for (int r = r0; r < r1; ++r) launch_m2l<NP>(P, 1, r, s);
     }
     if (rec) record_phase(P, 3, s);
     // compressed M2L: its results back on the check surfaces, added to the X
