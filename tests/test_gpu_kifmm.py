@@ -588,7 +588,8 @@ def test_operators_and_ranks_match_oracle(built, p):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
-@pytest.mark.parametrize("k,n,leaf,p,m2l_rtol", [(2, 8000, 48, 6, 0.0), (4, 9000, 32, 6, 1e-6), (5, 6000, 64, 8, 0.0)])
+@pytest.mark.parametrize("k,n,leaf,p,m2l_rtol", [(2, 8000, 48, 6, 0.0), (4, 9000, 32, 6, 1e-6), (5, 6000, 64, 8, 0.0),
+                                                (5, 6000, 64, 8, 1e-6), (2, 12000, 16, 4, 0.0)])
 def test_stokes_parity(built, k, n, leaf, p, m2l_rtol, precision):
     """Velocities of point forces (Stokeslet sum) against the oracle's same
     method (four Laplace evaluations of the same plan through the harmonic
