@@ -14,10 +14,12 @@ FP32); the plain FP32 path is measured beside it.  The roofline object is for
 the kernel with the most time per step, timed with HIP events that the
 library records on the stream the kernel is launched on (read after the
 timed region).  The line also carries the largest single-GPU workload (8.4M
-Plummer masses, p = 8) on the headline path, the oracle's check of the timed
-outputs on 256 sampled targets (rel-L2 and worst element per output and
-path), and the CPU baseline: the FP64 oracle (test infrastructure) timed on a
-bounded sample of the same workload.
+Plummer masses, p = 8) on the headline path, the timing of the dipole,
+field-gradient and Stokeslet sums on the headline workload (`--f4` adds their
+oracle check), the oracle's check of the timed outputs on 256 sampled targets
+(rel-L2 and worst element per output and path), and the CPU baseline: the
+FP64 oracle (test infrastructure) timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -333,7 +335,8 @@ def run_f4(Plan, steps, warmup, m2l_rtol, paths=("split_bf16", "fp32"), check=Tr
             torch.cuda.synchronize()
             t = (time.perf_counter() - t0) / steps
             r[name] = {"ms_per_call": t * 1e3, "points_per_s": n / t}
-            outs[(prec, name)] = [x.double().cpu().numpy() for x in o]
+            if check:
+                outs[(prec, name)] = [x.double().cpu().numpy() for x in o]
             log(f"[bench] f4 {prec} {name}: {t * 1e3:.3f} ms/call")
         res[prec] = r
         plan.close()
@@ -681,6 +684,10 @@ def main():
         log("[bench] largest workload (Plummer, 8,388,608 points, p = 8), split-bf16 path")
         out["largest_config"] = run_largest(Plan, 5, 2, args.m2l_rtol)
         log(f"[bench] largest: {out['largest_config']['ms_per_step']:.2f} ms/step")
+        # the other sums of eq. (1) on the same workload, timed only (their
+        # oracle check is `--f4` and the full-size GPU test)
+        log("[bench] dipole, field-gradient and Stokeslet sums (timing)")
+        out["f4"] = run_f4(Plan, 5, 2, args.m2l_rtol, check=False)
     if not args.no_cpu:
         if w.clump_offsets is None and not args.move:
             log("[bench] oracle check of the timed outputs (256 sampled targets)")
