@@ -38,6 +38,9 @@ PEAK = {"fp32": 157.3, "bf16": 2500.0, "hbm": 8000.0}     # TFLOP/s, TFLOP/s, GB
 CSRC = os.path.join(ROOT, "paper_2512_09478_amd", "csrc")
 KERNEL_SOURCE = {"k_m2l": "farfield.hip", "k_p2p": "nearfield.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kifmm_clustered_1M_p6_hbm_traffic.md")
+# the counter summary of each path (the headline's split path in TRAFFIC_FILE)
+TRAFFIC_FILES = {"split_bf16": TRAFFIC_FILE,
+                 "fp32": os.path.join(ROOT, "profiles", "kifmm_clustered_1M_p6_fp32_hbm_traffic.md")}
 CALIB_BYTES = 256 << 20     # the plain copy used to calibrate the byte counters
 P2P_FLOP_PER_PAIR = 20
 METRIC = "FMM particles/sec fwd+adjoint at rel-L2<=1e-5; %FP32/MFMA peak vs plain FP32"
@@ -169,7 +172,7 @@ def stored_traffic(kernel, precision, workload, n):
     there is none for this kernel, path and workload, or the kernel's source
     file changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES.get(precision, TRAFFIC_FILE)) as f:
             for line in f:
                 if line.startswith("traffic_json: "):
                     rec = json.loads(line[len("traffic_json: "):])
