@@ -162,3 +162,36 @@ def test_kifmm_stokes_terms_bound_the_far_velocity():
         wl = P.tree.width(int(P.tree.level[leaf]))
         np.testing.assert_allclose(c[k], P.tree.center(leaf), rtol=0, atol=1e-15)
         assert np.all(np.abs(w.positions[i] - c[k]) <= 0.5 * wl * (1 + 1e-12))
+
+
+def test_harmonic_decomposition_is_frame_independent():
+    """The identity the per-box frames rest on, with direct Laplace sums: the
+    fourth potential about any centre c equals that about o plus (o - c)
+    times the three force potentials (and so for the fields), and the
+    velocity combined about a per-target centre c (x' = x - c, the fourth
+    charge (y - c).f) is the direct Stokeslet sum."""
+    rng = np.random.default_rng(14)
+    x = rng.random((250, 3))
+    f = rng.standard_normal((250, 3))
+    o = np.array([0.5, 0.5, 0.5])
+    c = np.array([0.13, 0.71, 0.42])
+    pot = [direct.potential_field(x, f[:, k]) for k in range(3)]
+    p4o = direct.potential_field(x, np.einsum("ij,ij->i", x - o, f))
+    p4c = direct.potential_field(x, np.einsum("ij,ij->i", x - c, f))
+    shifted_u = p4o[0] + sum((o - c)[k] * pot[k][0] for k in range(3))
+    shifted_E = p4o[1] + sum((o - c)[k] * pot[k][1] for k in range(3))
+    assert rel(shifted_u, p4c[0]) <= 1e-12 and rel(shifted_E, p4c[1]) <= 1e-12
+    # every target about its own centre (a different c per target)
+    cs = x + 0.05 * rng.standard_normal(x.shape)
+    u = np.zeros((250, 3))
+    for i in range(250):
+        q4 = np.einsum("ij,ij->i", x - cs[i], f)   # the fourth charge about this target's centre
+        keep = np.arange(250) != i
+        r = x[i] - x[keep]
+        d = np.linalg.norm(r, axis=1)
+        e4 = (q4[keep][:, None] * r / d[:, None] ** 3).sum(0) / (4 * math.pi)   # its field at x_i
+        u[i] = np.array([pot[a][0][i] for a in range(3)]) - e4
+        for k in range(3):
+            u[i] += (x[i] - cs[i])[k] * pot[k][1][i]
+    u /= 8 * math.pi / (4 * math.pi)
+    assert rel(u, stokes.direct(x, f)) <= 1e-12
