@@ -263,6 +263,25 @@ def test_field_gradient_fp32_parity(built):
     check("dE/dx", Gr, Go, TOL["fp32"])
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_field_gradient_gravity_parity(built, precision):
+    """u, E and dE/dx of unit masses with the gravity kernel (c = -1) on the
+    Plummer shape, with point dipoles beside them, against the oracle's sweep
+    (tidal tensor of the cluster)."""
+    say(f"field gradient, gravity, {precision}")
+    w = workloads.make(5, n=7000)
+    rng = np.random.default_rng(45)
+    m = workloads.round_f32(rng.standard_normal((w.n, 3)) * 1e-3)
+    G = gpu_plan(w, 64, precision, p=6)
+    O = oracle_plan(w, 64, 6)
+    u, E, Gr = G.evaluate_gradient(torch.tensor(w.charges, dtype=torch.float32, device="cuda"),
+                                   torch.tensor(m, dtype=torch.float32, device="cuda"))
+    uo, Eo, Go = kifmm.forward_dipoles(O, w.charges, m, grad=True)
+    check("u", u, uo, TOL[precision])
+    check("E", E, Eo, TOL[precision])
+    check("dE/dx", Gr, Go, TOL[precision])
+
+
 def test_deterministic_repeat(built):
     say("repeatability")
     w = workloads.make(2, n=8000)
