@@ -246,13 +246,14 @@ __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items,
 // part of the Hessian being 3 (m_a r_b + m_b r_a + (m.r) delta_ab)/r^5
 // - 15 (m.r) r_a r_b / r^7.  (u, E) go to nearv, dE/dx (xx yy zz xy xz yz)
 // to nearg.
+template <bool DIP>
 __global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items, int n_items,
                                                   const int2* __restrict__ range, const int* __restrict__ uoff,
                                                   const int* __restrict__ uidx, const float4* __restrict__ pts,
                                                   const float4* __restrict__ src2, float cst, float cell,
                                                   float4* __restrict__ nearv, float* __restrict__ nearg) {
     __shared__ float4 sh[NF_STAGE];
-    __shared__ float4 sh2[NF_STAGE];
+    __shared__ float4 sh2[DIP ? NF_STAGE : 1];
     __shared__ float red[4][10][64];
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int2 it = items[item];
@@ -263,30 +264,52 @@ __global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items
         const bool act = nm.act;
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // u, E xyz, dE/dx xx yy zz xy xz yz
-        stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
+        stream_sources(uoff, uidx, range, b, pts, DIP ? src2 : nullptr, cell, sh, sh2, [&](int m) {
             for_sources<1>(nm, m, [&](int j) {
                 const float4 y = sh[j];
-                const float4 bj = src2 ? sh2[j] : make_float4(y.w, 0.f, 0.f, 0.f);
-                const float d[3] = {x.x - y.x, x.y - y.y, x.z - y.z};
-                const float ri = rsq(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                const float d0 = x.x - y.x, d1 = x.y - y.y, d2 = x.z - y.z;
+                const float ri = rsq(d0 * d0 + d1 * d1 + d2 * d2);
                 const float ri2 = ri * ri;
                 const float ri3 = ri2 * ri;
-                const float ri5 = ri3 * ri2;
-                const float mr = d[0] * bj.y + d[1] * bj.z + d[2] * bj.w;
-                const float mv[3] = {bj.y, bj.z, bj.w};
-                v[0] += bj.x * ri - mr * ri3;
-                const float gh = bj.x * ri3 - 3.f * mr * ri5;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) v[1 + a] += gh * d[a] + mv[a] * ri3;
-                // dE_a/dx_b = q (delta_ab/r^3 - 3 d_a d_b/r^5) - dipole Hessian
-                const float t3 = 3.f * bj.x * ri5, t15 = 15.f * mr * ri5 * ri2;
-                constexpr int A[6] = {0, 1, 2, 0, 0, 1}, Bc[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    const int a = A[k], c = Bc[k];
-                    float t = -t3 * d[a] * d[c] - 3.f * ri5 * (mv[a] * d[c] + mv[c] * d[a]) + t15 * d[a] * d[c];
-                    if (a == c) t += bj.x * ri3 - 3.f * mr * ri5;
-                    v[4 + k] += t;
+                if constexpr (!DIP) {
+                    // charge q: u = q/r, E = g d, dE_a/dx_c = g delta_ac - 3 g d_a d_c / r^2, g = q/r^3
+                    const float g = y.w * ri3;
+                    const float c = -3.f * g * ri2;
+                    v[0] += y.w * ri;
+                    v[1] += g * d0;
+                    v[2] += g * d1;
+                    v[3] += g * d2;
+                    const float e0 = c * d0, e1 = c * d1, e2 = c * d2;
+                    v[4] += e0 * d0 + g;
+                    v[5] += e1 * d1 + g;
+                    v[6] += e2 * d2 + g;
+                    v[7] += e0 * d1;
+                    v[8] += e0 * d2;
+                    v[9] += e1 * d2;
+                } else {
+                    // charge q and dipole m (u += q/r - m.d/r^3): with t = 3 (m.d)/r^5,
+                    // E = gh d + m/r^3, gh = q/r^3 - t, and
+                    // dE_a/dx_c = coef d_a d_c - p_a d_c - p_c d_a + gh delta_ac,
+                    // coef = 5 t/r^2 - 3 q/r^5, p = 3 m/r^5
+                    const float4 bj = sh2[j];
+                    const float ri5 = ri3 * ri2;
+                    const float mr = d0 * bj.y + d1 * bj.z + d2 * bj.w;
+                    const float t = 3.f * mr * ri5;
+                    const float gh = bj.x * ri3 - t;
+                    v[0] += bj.x * ri - mr * ri3;
+                    v[1] += gh * d0 + bj.y * ri3;
+                    v[2] += gh * d1 + bj.z * ri3;
+                    v[3] += gh * d2 + bj.w * ri3;
+                    const float coef = 5.f * t * ri2 - 3.f * bj.x * ri5;
+                    const float p0 = 3.f * ri5 * bj.y, p1 = 3.f * ri5 * bj.z, p2 = 3.f * ri5 * bj.w;
+                    // e_a = coef d_a - p_a, so that dE_a/dx_c = e_a d_c - p_c d_a (+ gh on the diagonal)
+                    const float e0 = coef * d0 - p0, e1 = coef * d1 - p1, e2 = coef * d2 - p2;
+                    v[4] += (e0 - p0) * d0 + gh;
+                    v[5] += (e1 - p1) * d1 + gh;
+                    v[6] += (e2 - p2) * d2 + gh;
+                    v[7] += e0 * d1 - p1 * d0;
+                    v[8] += e0 * d2 - p2 * d0;
+                    v[9] += e1 * d2 - p2 * d1;
                 }
             });
         });
@@ -483,10 +506,16 @@ void launch_p2p_dipoles(kifmm_plan* P, hipStream_t s) {
 
 void launch_p2p_gradient(kifmm_plan* P, bool dipoles, hipStream_t s) {
     P->nearg.ensure(size_t(P->N) * 24);
-    hipLaunchKernelGGL(k_p2p_grad, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
-                       int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
-                       P->pts.as<float4>(), dipoles ? P->src2.as<float4>() : nullptr, float(P->c), float(P->side),
-                       P->nearv.as<float4>(), P->nearg.as<float>());
+    if (dipoles)
+        hipLaunchKernelGGL(k_p2p_grad<true>, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
+                           int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
+                           P->pts.as<float4>(), P->src2.as<float4>(), float(P->c), float(P->side),
+                           P->nearv.as<float4>(), P->nearg.as<float>());
+    else
+        hipLaunchKernelGGL(k_p2p_grad<false>, dim3(unsigned(P->n_items)), dim3(256), 0, s, P->items_near.as<int2>(),
+                           int(P->n_items), P->bx_range.as<int2>(), P->n_off.as<int>(), P->n_idx.as<int>(),
+                           P->pts.as<float4>(), (const float4*)nullptr, float(P->c), float(P->side),
+                           P->nearv.as<float4>(), P->nearg.as<float>());
 }
 
 void launch_p2p_backward(kifmm_plan* P, hipStream_t s, bool excl) {
