@@ -314,7 +314,8 @@ int kifmm_evaluate_stokes(kifmm_handle h, const float* forces, double viscosity,
         // near field on the side stream beside it
         launch_gather_stokes(P, forces, 0, s);
         run_sweep(P, 0, 2, s, true, [&] { fork_near(P, NEAR_STOKES, s, viscosity); });
-        for (int r = 0; r < 2; ++r) run_far_eval(P, false, pot + r * N, fld + 3 * r * N, s, r, false, false);
+        for (int r = 0; r < 2; ++r)
+            run_far_eval(P, false, pot + r * N, fld + 3 * r * N, s, r, false, false, nullptr, true);
         // the first sweep's upward, compressed and downward densities of f_x
         // and f_y, which the second sweep's framed charge needs after the
         // second sweep has overwritten them
@@ -342,8 +343,8 @@ int kifmm_evaluate_stokes(kifmm_handle h, const float* forces, double viscosity,
         sf.dn[2] = cur_d;
         sf.kp[2] = cur_k;
         run_sweep(P, 0, 2, s, false, [] {}, &sf);
-        run_far_eval(P, false, pot + 2 * N, fld + 3 * 2 * N, s, 0, false, false);
-        run_far_eval(P, false, pot + 3 * N, fld + 3 * 3 * N, s, 1, false, false, &sf);
+        run_far_eval(P, false, pot + 2 * N, fld + 3 * 2 * N, s, 0, false, false, nullptr, true);
+        run_far_eval(P, false, pot + 3 * N, fld + 3 * 3 * N, s, 1, false, false, &sf, true);
         launch_stokes_frames(P, s);
         join_near(P, s);
         launch_stokes_combine(P, viscosity, velocity, s);

@@ -303,7 +303,7 @@ struct kifmm_plan {
     // Stokeslet evaluation
     kifmm::DBuf stk;          // float4 [N] sorted forces
     kifmm::DBuf stk_near;     // float4 [N] sorted near-field velocity
-    kifmm::DBuf stk_far;      // float [4][N] potentials, [4][N][3] fields of the harmonic charges (caller order)
+    kifmm::DBuf stk_far;      // float [4][N] potentials, [4][N][3] fields of the harmonic charges (sorted order)
     kifmm::DBuf stk_keep;     // float: the first sweep's upward, compressed and downward densities of f_x, f_y
     kifmm::DBuf stk_frame;    // float4 [N] sorted x - (centre of the point's leaf)
 };
@@ -336,8 +336,10 @@ void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const 
 // (near = false: the near-field part is not added)
 // (sf: the W-list sources of right-hand side rhs are shifted into the
 // target leaf's frame as for the Stokes sweep)
+// (sorted: the outputs are written in sorted point order, not caller order)
 void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs = 0,
-                  bool accumulate = false, bool near = true, const StokesFrames* sf = nullptr);
+                  bool accumulate = false, bool near = true, const StokesFrames* sf = nullptr,
+                  bool sorted = false);
 // leaf evaluation with the field gradient (densities of right-hand side rhs)
 void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs);
 // ---- nearfield.hip

@@ -798,7 +798,7 @@ __global__ __launch_bounds__(256) void k_updown(int nblk, int b0, int nb, const 
 // split the surface points and are summed by shuffles.
 struct FarOut {
     const float4* nearv;   // sorted near-field part: forward (u, E), backward (xbar, psi); or null
-    const int* perm;       // sorted position -> caller index
+    const int* perm;       // sorted position -> caller index; null: outputs in sorted order
     float* a;              // forward: potential [N] | backward: grad_charges [N] (either may be null)
     float* b;              // forward: field [N][3]  | backward: grad_positions [N][3]
     // periodic: source moments (Q, M, S2, D, D.y) about the cell centre o of
@@ -968,9 +968,9 @@ __device__ __forceinline__ void far_item(int b, int first, int nt, int b2, const
                 v[3] = float(double(v[3]) + u1);
             }
         }
-        // far + near, written in caller order
+        // far + near, written in caller order (sorted order without perm)
         const float4 nr = out.nearv ? out.nearv[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const size_t j = size_t(out.perm[i]);
+        const size_t j = out.perm ? size_t(out.perm[i]) : size_t(i);
         float oa, ob[3];
         if (!BWD) {
             oa = v[0] + nr.x;
@@ -1569,12 +1569,12 @@ void sweep_impl(kifmm_plan* P, int r0, int r1, hipStream_t s, bool rec, const st
 
 template <int NP>
 void far_impl(kifmm_plan* P, bool bwd, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc, bool near,
-              const StokesFrames* sf) {
+              const StokesFrames* sf, bool sorted) {
     const Operators& op = *P->ops;
     BoxGeom geo{{P->lo[0], P->lo[1], P->lo[2]}, P->side};
     const int b2 = int(P->bfar);
-    FarOut fo{near ? P->nearv.as<float4>() : nullptr, P->perm.as<int>(), out_a, out_b, nullptr, {0, 0, 0}, 0.0,
-              acc ? 1 : 0, {nullptr, nullptr, nullptr}};
+    FarOut fo{near ? P->nearv.as<float4>() : nullptr, sorted ? nullptr : P->perm.as<int>(), out_a, out_b, nullptr,
+              {0, 0, 0}, 0.0, acc ? 1 : 0, {nullptr, nullptr, nullptr}};
     if (sf)
         for (int d = 0; d < 3; ++d) fo.wsh[d] = sf->up[d];
     if (P->periodic) {
@@ -1636,8 +1636,8 @@ __global__ __launch_bounds__(256) void k_stokes_frames(const int* __restrict__ l
 }
 
 // Stokeslet velocity from the four harmonic charges' potentials psi_k and
-// fields E(k) (caller order; the fourth about each target's leaf centre) and
-// the near part (sorted):
+// fields E(k) (the fourth about each target's leaf centre) and the near part,
+// all in sorted order, written in caller order:
 //   u_a = cf (psi_a + x'_k E(k)_a - E(4)_a) + near_a,  x' = x - (leaf centre).
 __global__ void k_stokes_combine(int64_t N, const int* __restrict__ perm, const float4* __restrict__ frame,
                                  const float* __restrict__ pot, const float* __restrict__ fld,
@@ -1651,8 +1651,8 @@ __global__ void k_stokes_combine(int64_t N, const int* __restrict__ perm, const 
     const float na[3] = {nr.x, nr.y, nr.z};
     const size_t sN = size_t(N);
     for (int a = 0; a < 3; ++a) {
-        float v = pot[a * sN + j] - fld[(3 * sN + j) * 3 + a];
-        for (int k = 0; k < 3; ++k) v += xp[k] * fld[(k * sN + j) * 3 + a];
+        float v = pot[a * sN + i] - fld[(3 * sN + i) * 3 + a];
+        for (int k = 0; k < 3; ++k) v += xp[k] * fld[(k * sN + i) * 3 + a];
         u[3 * j + a] = cf * v + na[a];
     }
 }
@@ -1702,14 +1702,14 @@ void run_sweep(kifmm_plan* P, int r0, int r1, hipStream_t s, bool record, const 
 }
 
 void run_far_eval(kifmm_plan* P, bool backward, float* out_a, float* out_b, hipStream_t s, int rhs, bool acc,
-                  bool near, const StokesFrames* sf) {
+                  bool near, const StokesFrames* sf, bool sorted) {
     switch (P->npad) {
-        case 32: far_impl<32>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
-        case 64: far_impl<64>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
-        case 128: far_impl<128>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
-        case 160: far_impl<160>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
-        case 224: far_impl<224>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
-        case 320: far_impl<320>(P, backward, out_a, out_b, s, rhs, acc, near, sf); break;
+        case 32: far_impl<32>(P, backward, out_a, out_b, s, rhs, acc, near, sf, sorted); break;
+        case 64: far_impl<64>(P, backward, out_a, out_b, s, rhs, acc, near, sf, sorted); break;
+        case 128: far_impl<128>(P, backward, out_a, out_b, s, rhs, acc, near, sf, sorted); break;
+        case 160: far_impl<160>(P, backward, out_a, out_b, s, rhs, acc, near, sf, sorted); break;
+        case 224: far_impl<224>(P, backward, out_a, out_b, s, rhs, acc, near, sf, sorted); break;
+        case 320: far_impl<320>(P, backward, out_a, out_b, s, rhs, acc, near, sf, sorted); break;
         default: throw Error(KIFMM_ERR_ARG, "unsupported surface size");
     }
 }
