@@ -222,16 +222,17 @@ __global__ __launch_bounds__(256) void k_p2p_dip(const int2* __restrict__ items,
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[4] = {0.f, 0.f, 0.f, 0.f};   // u, ex, ey, ez
         stream_sources(uoff, uidx, range, b, pts, src2, cell, sh, sh2, [&](int m) {
-            for_sources<1>(nm, m, [&](int j) {
+            for_sources<2>(nm, m, [&](int j) {
                 const float4 y = sh[j];
                 const float4 bj = sh2[j];
                 const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
                 const float ri = rsq(dx * dx + dy * dy + dz * dz);
                 const float ri2 = ri * ri;
                 const float ri3 = ri2 * ri;
-                const float rj = dx * bj.y + dy * bj.z + dz * bj.w;
-                v[0] += bj.x * ri - rj * ri3;
-                const float gh = bj.x * ri3 - 3.f * rj * ri3 * ri2;
+                // with c = m.r/r^2: u term (q - c)/r, radial field (q - 3c)/r^3
+                const float c = (dx * bj.y + dy * bj.z + dz * bj.w) * ri2;
+                v[0] += ri * (bj.x - c);
+                const float gh = ri3 * (bj.x - 3.f * c);
                 v[1] += gh * dx + bj.y * ri3;
                 v[2] += gh * dy + bj.z * ri3;
                 v[3] += gh * dz + bj.w * ri3;
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(256) void k_p2p_grad(const int2* __restrict__ items
         const float4 x = act ? pts[i] : make_float4(0, 0, 0, 0);
         float v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // u, E xyz, dE/dx xx yy zz xy xz yz
         stream_sources(uoff, uidx, range, b, pts, DIP ? src2 : nullptr, cell, sh, sh2, [&](int m) {
-            for_sources<1>(nm, m, [&](int j) {
+            for_sources<DIP ? 2 : 4>(nm, m, [&](int j) {
                 const float4 y = sh[j];
                 const float d0 = x.x - y.x, d1 = x.y - y.y, d2 = x.z - y.z;
                 const float ri = rsq(d0 * d0 + d1 * d1 + d2 * d2);
