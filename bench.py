@@ -205,6 +205,14 @@ def roofline(res, n, precision, workload, npts):
         return dict(kernel="k_m2l", bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
                     traffic=stored_traffic("k_m2l", precision, workload, npts), per_launch_ms=per,
                     work=f"2 k^2 x {c['v_pairs']} V pairs, k = {k} (surface size {n})")
+    return near_roofline(res, precision, workload, npts)
+
+
+def near_roofline(res, precision, workload, npts):
+    """Roofline of the forward near field (`k_p2p`, one launch per forward
+    pass): 20 FLOP per pair against the FP32 vector peak, timed by the
+    library's HIP events on the near-field stream."""
+    ph, c = res["phases_fwd_ms"], res["counts"]
     flops = P2P_FLOP_PER_PAIR * c["p2p_pairs"]
     ach = flops / (ph["p2p"] * 1e-3) / 1e12
     return dict(kernel="k_p2p", bound="alu", achieved=ach, peak=PEAK["fp32"], unit="TFLOP/s",
@@ -670,6 +678,8 @@ def main():
                    "name": w.name, "n": n, "p": w.p, "leaf_size": w.leaf_size, "path": head,
                    "m2l_rtol": args.m2l_rtol},
         "roofline": roofline(H, ops_n, head, wkey, n),
+        # the forward near field beside it (the other kernel of the step)
+        "roofline_near": near_roofline(H, head, wkey, n),
         "paths": {k: {"particles_per_s": n / (v["ms_per_step"] * 1e-3), "ms_per_step": v["ms_per_step"],
                       "particles_per_s_without_tree": n / ((v["t_fwd_ms"] + v["t_adj_ms"]) * 1e-3),
                       "particles_per_s_forward": n / (v["t_fwd_ms"] * 1e-3),
@@ -677,7 +687,8 @@ def main():
                       "t_tree_ms": v["t_tree_ms"], "t_fwd_ms": v["t_fwd_ms"], "t_adj_ms": v["t_adj_ms"],
                       "phases_fwd_ms": v["phases_fwd_ms"], "phases_adj_ms": v["phases_adj_ms"],
                       "tree_builds": v["builds"],
-                      "roofline": roofline(v, ops_n, k, wkey, n)}
+                      "roofline": roofline(v, ops_n, k, wkey, n),
+                      "roofline_near": near_roofline(v, k, wkey, n)}
                   for k, v in paths.items()},
         "counts": H["counts"],
         "timed_launches_per_path": H["timed_launches"],

@@ -35,6 +35,10 @@ def test_roofline_takes_the_kernel_with_most_time_per_step():
     assert r["kernel"] == "k_p2p" and r["bound"] == "alu" and r["per_launch_ms"] == 2.0
     assert r["achieved"] == pytest.approx(20 * 5000 / 2.0e-3 / 1e12)
     assert r["traffic"] is None   # nothing stored for this workload
+    # the near-field roofline is reported beside the M2L's whichever dominates
+    q = bench.near_roofline(_res(1.0, 1.4, 0.9), "split_bf16", "none", 1)
+    assert q["kernel"] == "k_p2p" and q["per_launch_ms"] == 0.9
+    assert q["frac"] == pytest.approx(20 * 5000 / 0.9e-3 / 1e12 / 157.3)
 
 
 def test_stored_traffic_follows_the_sources():
