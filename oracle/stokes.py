@@ -21,6 +21,15 @@ x' = x - o for a fixed origin o,
 since -x'_k d_a(f_k/r) + d_a((x'_j . f)/r) = (r . f) r_a / r^3 for each pair.
 Each phi is one charge evaluation of the plan (charges f_x, f_y, f_z and
 x'.f); the origin is the root cube's centre.
+
+The pressure that goes with this velocity (the Stokes equations
+mu lap u = grad p, div u = 0 hold away from the forces) is
+
+    p(x_i) = 1/(4 pi) sum_{j : x_j != x_i} (r . f_j) / r^3,
+
+``pressure_direct`` written out; through the same decomposition it is
+-(1/4 pi) sum_k d_k phi_k, the trace of the fields of the first three
+charges, which ``kifmm`` returns with ``pressure``.
 """
 from __future__ import annotations
 
@@ -47,6 +56,23 @@ def direct(x, f, mu=1.0, targets=None, chunk=512):
     return out / (8.0 * math.pi * mu)
 
 
+def pressure_direct(x, f, targets=None, chunk=512):
+    """Pressure [nt] at the points ``targets`` (all by default)."""
+    x = np.asarray(x, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64).reshape(-1, 3)
+    t = np.arange(x.shape[0]) if targets is None else np.asarray(targets)
+    out = np.zeros(t.shape[0])
+    for a in range(0, t.shape[0], chunk):
+        xt = x[t[a:a + chunk]]
+        r = xt[:, None, :] - x[None, :, :]
+        r2 = np.einsum("ijk,ijk->ij", r, r)
+        inv3 = np.zeros_like(r2)
+        nz = r2 > 0
+        inv3[nz] = r2[nz] ** -1.5
+        out[a:a + chunk] = np.einsum("ij,ij->i", np.einsum("ijk,jk->ij", r, f), inv3)
+    return out / (4.0 * math.pi)
+
+
 def origin(P):
     """The fixed origin of the decomposition: the root cube's centre."""
     return P.tree.lo + 0.5 * P.tree.s
@@ -65,7 +91,7 @@ def leaf_centres(P, targets=None):
     return np.array([t.center(int(b)) for b in leaf_of[idx]]).reshape(-1, 3)
 
 
-def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root"):
+def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root", pressure=False):
     """The Stokeslet sum through four Laplace evaluations of the oracle plan
     ``P`` (its kernel constant c = P.c): u = (1/(8 pi mu c)) [psi_a +
     x'_k E(k)_a - E(4)_a], psi_k and E(k) = -grad psi_k the plan's potential
@@ -78,7 +104,10 @@ def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root"):
     grow as |x'| over the distance to the sources, u does not).  ``frame``
     names the origin of those terms: "root" (the one origin used here) or
     "leaf", each target's leaf centre c, for which the fourth field is
-    E(4) + (o - c)_k E(k) and x' = x - c (the same velocity)."""
+    E(4) + (o - c)_k E(k) and x' = x - c (the same velocity).
+
+    With ``pressure`` the pressure p = (1/(4 pi c)) sum_k E(k)_k (k = 1, 2,
+    3) is returned last."""
     from . import kifmm as K
     f = np.asarray(f, dtype=np.float64).reshape(-1, 3)
     o = origin(P)
@@ -92,8 +121,11 @@ def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root"):
         u += xt[:, k:k + 1] * res[k][1]
     u -= res[3][1]
     s = 1.0 / (8.0 * math.pi * mu * P.c)
+    extra = ()
+    if pressure:
+        extra = (sum(res[k][1][:, k] for k in range(3)) / (4.0 * math.pi * P.c),)
     if not terms:
-        return u * s
+        return (u * s,) + extra if extra else u * s
     if frame not in ("root", "leaf"):
         raise ValueError(f"unknown frame {frame!r}")
     near = [K.forward(P, q, targets=targets, part="near") for q in charges]
@@ -106,4 +138,4 @@ def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root"):
     mag = np.abs(np.stack([far[a][0] for a in range(3)], axis=1)) + np.abs(e4)
     for k in range(3):
         mag += np.abs(xf[:, k:k + 1] * far[k][1])
-    return u * s, mag * abs(s)
+    return (u * s, mag * abs(s)) + extra

@@ -1,6 +1,7 @@
 """Pins of the Stokeslet oracle (CPU only): the direct sum against closed
-forms of Stokes flow, the divergence-free velocity, the kernel's symmetry,
-and the harmonic decomposition that the fast evaluation uses."""
+forms of Stokes flow, the divergence-free velocity, the pressure through the
+Stokes equations, the kernel's symmetry, and the harmonic decomposition that
+the fast evaluation uses."""
 import math
 
 import numpy as np
@@ -77,6 +78,51 @@ def test_velocity_is_divergence_free():
     assert np.max(np.abs(div)) <= 1e-7 * np.max(scale)
 
 
+def _richardson(fun, p, h):
+    """Central-difference gradient and Laplacian of ``fun`` (values [m] at a
+    point) at p, Richardson-extrapolated from steps 2h and h."""
+    def diffs(hh):
+        f0 = fun(p)
+        g, lap = [], 0.0
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = hh
+            fp, fm = fun(p + e), fun(p - e)
+            g.append((fp - fm) / (2 * hh))
+            lap = lap + (fp - 2 * f0 + fm) / hh ** 2
+        return np.array(g), lap
+    g2, l2 = diffs(2 * h)
+    g1, l1 = diffs(h)
+    return (4 * g1 - g2) / 3, (4 * l1 - l2) / 3
+
+
+def test_pressure_satisfies_the_stokes_equations():
+    """Away from the forces the direct velocity and pressure satisfy
+    mu lap u = grad p, and p is harmonic (finite differences of the direct
+    sums, Richardson-extrapolated); a wrong factor or sign in either sum
+    leaves a residual of the size of grad p."""
+    rng = np.random.default_rng(14)
+    x = rng.random((150, 3))
+    f = rng.standard_normal((150, 3))
+    mu, h = 0.7, 2e-3
+    X = np.concatenate([x, np.zeros((1, 3))])
+    F = np.concatenate([f, np.zeros((1, 3))])
+
+    def at(p, which):
+        X[-1] = p
+        if which == "u":
+            return stokes.direct(X, F, mu, targets=[150])[0]
+        return stokes.pressure_direct(X, F, targets=[150])
+
+    for p in rng.random((4, 3)) * 0.3 + 1.25:          # at least 0.25 from every force
+        _, lap_u = _richardson(lambda q: at(q, "u"), p, h)
+        grad_p, lap_p = _richardson(lambda q: at(q, "p"), p, h)
+        grad_p = grad_p[:, 0]
+        scale = np.linalg.norm(grad_p)
+        assert np.linalg.norm(mu * lap_u - grad_p) <= 1e-6 * scale
+        assert abs(lap_p[0]) <= 1e-6 * scale / 0.25
+
+
 def test_symmetry_of_the_kernel():
     rng = np.random.default_rng(5)
     x = rng.random((400, 3))
@@ -114,18 +160,27 @@ def test_harmonic_decomposition_with_direct_laplace_sums():
     u = np.stack([res[k][0] for k in range(3)], axis=1) + sum(xp[:, k:k + 1] * res[k][1] for k in range(3))
     u = (u - res[3][1]) / (8 * math.pi / (4 * math.pi))
     assert rel(u, stokes.direct(x, f)) <= 1e-13
+    # the pressure is the trace of the first three charges' fields
+    pr = sum(res[k][1][:, k] for k in range(3))
+    assert rel(pr, stokes.pressure_direct(x, f)) <= 1e-13
 
 
 def test_kifmm_stokes_converges_to_the_direct_sum():
     w = workloads.make(2, n=6000)
     f = workloads.round_f32(np.random.default_rng(8).standard_normal((w.n, 3)))
     ud = stokes.direct(w.positions, f)
-    err = []
+    pd = stokes.pressure_direct(w.positions, f)
+    err, perr = [], []
     for p in (4, 6, 8):
         P = kifmm.plan(w.positions, "laplace", p, 64, True, 21, w.root)
-        err.append(rel(stokes.kifmm(P, f), ud))
+        u, pr = stokes.kifmm(P, f, pressure=True)
+        err.append(rel(u, ud))
+        perr.append(rel(pr, pd))
     assert err[0] > 10 * err[1] > 10 * err[2]
     assert err[1] < 5e-5 and err[2] < 5e-6
+    # the pressure (fields only: 9.7e-5, 1.8e-6, 1.6e-7 at p = 4, 6, 8)
+    assert perr[0] > 10 * perr[1] > 5 * perr[2]
+    assert perr[1] < 1e-5 and perr[2] < 1e-6
 
 
 def test_kifmm_stokes_terms_bound_the_far_velocity():
