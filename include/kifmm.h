@@ -220,6 +220,21 @@ int kifmm_evaluate_gradient(kifmm_handle h, const float* charges, const float* d
 int kifmm_evaluate_stokes(kifmm_handle h, const float* forces, double viscosity, float* velocity, void* stream);
 
 /*
+ * The same Stokeslet sum together with the pressure of the flow,
+ *   p_i = 1/(4 pi) sum_{j : x_j != x_i} (r . f_j) / r^3,  r = x_i - x_j,
+ * which with the velocity satisfies mu lap u = grad p away from the forces.
+ * Through the harmonic decomposition it is the trace of the fields of the
+ * charges f_x, f_y, f_z, (E(1)_x + E(2)_y + E(3)_z) / (4 pi c), which the
+ * velocity already computes; the near part is summed with the velocity's
+ * pairs.
+ *   pressure   device [N] float, caller order, or NULL (then exactly
+ *              kifmm_evaluate_stokes).
+ * Other arguments, requirements and errors as kifmm_evaluate_stokes.
+ */
+int kifmm_evaluate_stokes_ex(kifmm_handle h, const float* forces, double viscosity, float* velocity,
+                             float* pressure, void* stream);
+
+/*
  * Vector-Jacobian product of the discrete map (q, x) -> (u, E) of
  * kifmm_evaluate at the plan's positions with the tree frozen: given
  * grad_potential = dL/du and grad_field = dL/dE (either may be NULL = 0),

@@ -35,7 +35,7 @@ _lib = None
 
 EXPORTS = ["kifmm_default_options", "kifmm_setup", "kifmm_setup_ex", "kifmm_rebuild", "kifmm_set_precision",
            "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient", "kifmm_evaluate_stokes",
-           "kifmm_backward",
+           "kifmm_evaluate_stokes_ex", "kifmm_backward",
            "kifmm_clump_reduce", "kifmm_clump_reduce_noalloc", "kifmm_clump_backward", "kifmm_set_clumps", "kifmm_clump_forces",
            "kifmm_clump_forces_backward", "kifmm_synchronize", "kifmm_get_counts", "kifmm_get_m2l_rank",
            "kifmm_get_build_stats", "kifmm_get_operator", "kifmm_copy_tree", "kifmm_copy_list", "kifmm_get_phase_times",
@@ -63,6 +63,7 @@ def lib():
             L.kifmm_evaluate_dipoles.argtypes = [H, P, P, P, P, P]
             L.kifmm_evaluate_gradient.argtypes = [H, P, P, P, P, P, P]
             L.kifmm_evaluate_stokes.argtypes = [H, P, D, P, P]
+            L.kifmm_evaluate_stokes_ex.argtypes = [H, P, D, P, P, P]
             L.kifmm_backward.argtypes = [H, P, P, P, P, P, P]
             L.kifmm_clump_reduce.argtypes = [H, P, P, P, I64, P, P, P, P]
             L.kifmm_clump_reduce_noalloc.argtypes = [H, P, P, P, I64, P, P, P, P]
@@ -85,7 +86,7 @@ def lib():
             L.kifmm_status_string.restype = ctypes.c_char_p
             for name in ("kifmm_setup", "kifmm_setup_ex", "kifmm_rebuild", "kifmm_set_precision",
                          "kifmm_evaluate", "kifmm_evaluate_dipoles", "kifmm_evaluate_gradient",
-                         "kifmm_evaluate_stokes", "kifmm_backward",
+                         "kifmm_evaluate_stokes", "kifmm_evaluate_stokes_ex", "kifmm_backward",
                          "kifmm_clump_reduce", "kifmm_clump_reduce_noalloc", "kifmm_clump_backward", "kifmm_set_clumps", "kifmm_clump_forces",
                          "kifmm_clump_forces_backward", "kifmm_synchronize",
                          "kifmm_get_counts", "kifmm_get_m2l_rank", "kifmm_get_operator", "kifmm_get_build_stats",

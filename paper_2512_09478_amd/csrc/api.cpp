@@ -296,6 +296,11 @@ int kifmm_evaluate_gradient(kifmm_handle h, const float* charges, const float* d
 }
 
 int kifmm_evaluate_stokes(kifmm_handle h, const float* forces, double viscosity, float* velocity, void* stream) {
+    return kifmm_evaluate_stokes_ex(h, forces, viscosity, velocity, nullptr, stream);
+}
+
+int kifmm_evaluate_stokes_ex(kifmm_handle h, const float* forces, double viscosity, float* velocity, float* pressure,
+                             void* stream) {
     return guarded([&] {
         kifmm_plan* P = checked(h);
         if (!forces || !velocity) throw Error(KIFMM_ERR_ARG, "null forces or velocity");
@@ -347,7 +352,7 @@ int kifmm_evaluate_stokes(kifmm_handle h, const float* forces, double viscosity,
         run_far_eval(P, false, pot + 3 * N, fld + 3 * 3 * N, s, 1, false, false, &sf, true);
         launch_stokes_frames(P, s);
         join_near(P, s);
-        launch_stokes_combine(P, viscosity, velocity, s);
+        launch_stokes_combine(P, viscosity, velocity, pressure, s);
         record_phase(P, 6, s);
         end_phases(P);
         KIFMM_HIP(hipGetLastError());

@@ -358,7 +358,7 @@ void launch_p2p_stokes(kifmm_plan* P, double viscosity, hipStream_t s);
 void launch_stokes_frames(kifmm_plan* P, hipStream_t s);
 // velocity from the harmonic potentials and fields (caller order, the fourth
 // about each point's leaf centre) and the near part
-void launch_stokes_combine(kifmm_plan* P, double viscosity, float* velocity, hipStream_t s);
+void launch_stokes_combine(kifmm_plan* P, double viscosity, float* velocity, float* pressure, hipStream_t s);
 // u, E and dE/dx of monopoles (pts.w, or src2.x with `dipoles`) and dipoles (src2.yzw)
 void launch_p2p_gradient(kifmm_plan* P, bool dipoles, hipStream_t s);
 // ---- clump.hip

@@ -1638,10 +1638,12 @@ __global__ __launch_bounds__(256) void k_stokes_frames(const int* __restrict__ l
 // Stokeslet velocity from the four harmonic charges' potentials psi_k and
 // fields E(k) (the fourth about each target's leaf centre) and the near part,
 // all in sorted order, written in caller order:
-//   u_a = cf (psi_a + x'_k E(k)_a - E(4)_a) + near_a,  x' = x - (leaf centre).
+//   u_a = cf (psi_a + x'_k E(k)_a - E(4)_a) + near_a,  x' = x - (leaf centre),
+// and, when p is set, the pressure p = cpf (E(1)_x + E(2)_y + E(3)_z) + cpn near_w.
 __global__ void k_stokes_combine(int64_t N, const int* __restrict__ perm, const float4* __restrict__ frame,
                                  const float* __restrict__ pot, const float* __restrict__ fld,
-                                 const float4* __restrict__ near, float cf, float* __restrict__ u) {
+                                 const float4* __restrict__ near, float cf, float cpf, float cpn,
+                                 float* __restrict__ u, float* __restrict__ p) {
     int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
     if (i >= N) return;
     const size_t j = size_t(perm[i]);
@@ -1655,6 +1657,7 @@ __global__ void k_stokes_combine(int64_t N, const int* __restrict__ perm, const 
         for (int k = 0; k < 3; ++k) v += xp[k] * fld[(k * sN + i) * 3 + a];
         u[3 * j + a] = cf * v + na[a];
     }
+    if (p) p[j] = cpf * ((fld[3 * i] + fld[(sN + i) * 3 + 1]) + fld[(2 * sN + i) * 3 + 2]) + cpn * nr.w;
 }
 }  // namespace
 
@@ -1667,13 +1670,14 @@ void launch_stokes_frames(kifmm_plan* P, hipStream_t s) {
                            geo, P->stk_frame.as<float4>());
 }
 
-void launch_stokes_combine(kifmm_plan* P, double viscosity, float* velocity, hipStream_t s) {
+void launch_stokes_combine(kifmm_plan* P, double viscosity, float* velocity, float* pressure, hipStream_t s) {
     const int64_t N = P->N;
     const float* pot = P->stk_far.as<float>();
     const float* fld = pot + 4 * size_t(N);
     hipLaunchKernelGGL(k_stokes_combine, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, N, P->perm.as<int>(),
                        P->stk_frame.as<float4>(), pot, fld, P->stk_near.as<float4>(),
-                       float(1.0 / (8.0 * M_PI * viscosity * P->c)), velocity);
+                       float(1.0 / (8.0 * M_PI * viscosity * P->c)), float(1.0 / (4.0 * M_PI * P->c)),
+                       float(1.0 / (4.0 * M_PI)), velocity, pressure);
 }
 
 void run_far_grad(kifmm_plan* P, float* pot, float* field, float* grad, hipStream_t s, int rhs) {

@@ -417,7 +417,9 @@ __global__ void k_gather_stokes(int64_t N, const float4* __restrict__ xs, const 
 
 // Near field of point forces (the Stokeslet): u += f/r + (r.f) r/r^3 over
 // the near lists, pairs at distance zero skipped; positions from xs, forces
-// from stk (sorted); written as cst * u to out (sorted).
+// from stk (sorted); written as cst * u to out (sorted), with the unscaled sum
+// of (r.f)/r^3 (the near part of the pressure, times 4 pi) in the fourth
+// component.
 __global__ __launch_bounds__(256) void k_p2p_stokes(const int2* __restrict__ items, int n_items,
                                                     const int2* __restrict__ range, const int* __restrict__ uoff,
                                                     const int* __restrict__ uidx, const float4* __restrict__ xs,
@@ -425,7 +427,7 @@ __global__ __launch_bounds__(256) void k_p2p_stokes(const int2* __restrict__ ite
                                                     float4* __restrict__ out) {
     __shared__ float4 sh[NF_STAGE];
     __shared__ float4 sh2[NF_STAGE];
-    __shared__ float red[4][3][64];
+    __shared__ float red[4][4][64];
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int2 it = items[item];
         const int b = it.x;
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(256) void k_p2p_stokes(const int2* __restrict__ ite
         const NearMap nm = near_map(it.y, nt);
         const int i = nm.i;
         const float4 x = nm.act ? xs[i] : make_float4(0, 0, 0, 0);
-        float v[3] = {0.f, 0.f, 0.f};
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
         stream_sources(uoff, uidx, range, b, xs, stk, 0.f, sh, sh2, [&](int m) {
             for_sources<1>(nm, m, [&](int j) {
                 const float4 y = sh[j];
@@ -444,9 +446,10 @@ __global__ __launch_bounds__(256) void k_p2p_stokes(const int2* __restrict__ ite
                 v[0] += fj.x * ri + t * dx;
                 v[1] += fj.y * ri + t * dy;
                 v[2] += fj.z * ri + t * dz;
+                v[3] += t;
             });
         });
-        if (near_finish<3>(v, nm, red)) out[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], 0.f);
+        if (near_finish<4>(v, nm, red)) out[i] = make_float4(cst * v[0], cst * v[1], cst * v[2], v[3]);
     }
 }
 

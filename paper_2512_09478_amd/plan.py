@@ -139,13 +139,20 @@ class Plan:
                                                  _stream(stream)))
         return u, E, G
 
-    def evaluate_stokes(self, forces, viscosity=1.0, stream=None):
-        """Velocity [N, 3] of point forces [N, 3] (Stokeslet sum) at the plan's points."""
+    def evaluate_stokes(self, forces, viscosity=1.0, stream=None, pressure=False):
+        """Velocity [N, 3] of point forces [N, 3] (Stokeslet sum) at the plan's
+        points; with ``pressure`` also the pressure [N] of the flow."""
         f = _need(forces, torch.float32, (self.n, 3), "forces")
         u = torch.empty((self.n, 3), dtype=torch.float32, device=f.device)
         self._fwd_token = None
-        check(_lib.lib().kifmm_evaluate_stokes(self.handle, _ptr(f), float(viscosity), _ptr(u), _stream(stream)))
-        return u
+        if not pressure:
+            check(_lib.lib().kifmm_evaluate_stokes(self.handle, _ptr(f), float(viscosity), _ptr(u),
+                                                   _stream(stream)))
+            return u
+        p = torch.empty((self.n,), dtype=torch.float32, device=f.device)
+        check(_lib.lib().kifmm_evaluate_stokes_ex(self.handle, _ptr(f), float(viscosity), _ptr(u), _ptr(p),
+                                                  _stream(stream)))
+        return u, p
 
     def backward(self, charges, grad_potential=None, grad_field=None, stream=None):
         """dL/dq, dL/dx.  ``charges=None`` reuses the charges and forward

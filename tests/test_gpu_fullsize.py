@@ -282,8 +282,8 @@ def test_uniform_65536_adjoint_against_finite_differences():
 def test_clustered_1M_dipoles_gradient_and_stokes():
     """The other sums of eq. (1) at the headline size, with the inputs that
     `bench.py --f4` times: charges with point dipoles (u, E and dE/dx) and
-    the Stokeslet velocity of point forces, sampled against the oracle on
-    the same plan.  The library forms the Stokeslet's fourth harmonic charge
+    the Stokeslet velocity and pressure of point forces, sampled against the
+    oracle on the same plan.  The library forms the Stokeslet's fourth harmonic charge
     about each box's own centre; the oracle's far and near parts show that
     the combination about the targets' leaf centres does not amplify errors
     of the far fields (about 0.9 here, against 12.5 about the root's centre),
@@ -302,7 +302,7 @@ def test_clustered_1M_dipoles_gradient_and_stokes():
     uo, Eo, Go = kifmm.forward_dipoles(P, w.charges, m, targets=idx, grad=True)
     say(f"  oracle sampled dipole sweep {time.time() - t:.1f} s")
     t = time.time()
-    vo, vmag = stokes.kifmm(P, f, mu, targets=idx, terms=True, frame="leaf")
+    vo, vmag, po = stokes.kifmm(P, f, mu, targets=idx, terms=True, frame="leaf", pressure=True)
     kappa = float(np.linalg.norm(vmag) / np.linalg.norm(vo))
     say(f"  oracle sampled Stokes sum {time.time() - t:.1f} s; amplification of the leaf-frame combination "
         f"{kappa:.2f}")
@@ -314,7 +314,7 @@ def test_clustered_1M_dipoles_gradient_and_stokes():
         G = gpu_plan(w, precision)
         u, E = G.evaluate_dipoles(q, md)
         u2, E2, Gr = G.evaluate_gradient(q, md)
-        v = G.evaluate_stokes(fd, mu)
+        v, pr = G.evaluate_stokes(fd, mu, pressure=True)
         torch.cuda.synchronize()
         say(f"  {precision}:")
         check("u (dipoles)", u.cpu().numpy()[idx], uo, tol)
@@ -323,4 +323,5 @@ def test_clustered_1M_dipoles_gradient_and_stokes():
         check("E (gradient call)", E2.cpu().numpy()[idx], Eo, tol)
         check("dE/dx", Gr.cpu().numpy()[idx], Go, tol)
         check("Stokes velocity", v.cpu().numpy()[idx], vo, 2e-5 if precision == "fp32" else tol)
+        check("Stokes pressure", pr.cpu().numpy()[idx], po, tol)
         G.close()

@@ -610,9 +610,10 @@ def test_operators_and_ranks_match_oracle(built, p):
 @pytest.mark.parametrize("k,n,leaf,p,m2l_rtol", [(2, 8000, 48, 6, 0.0), (4, 9000, 32, 6, 1e-6), (5, 6000, 64, 8, 0.0),
                                                 (5, 6000, 64, 8, 1e-6), (2, 12000, 16, 4, 0.0)])
 def test_stokes_parity(built, k, n, leaf, p, m2l_rtol, precision):
-    """Velocities of point forces (Stokeslet sum) against the oracle's same
-    method (four Laplace evaluations of the same plan through the harmonic
-    decomposition, FP64) and, at the method's accuracy, the direct sum."""
+    """Velocities and pressures of point forces (Stokeslet sum) against the
+    oracle's same method (four Laplace evaluations of the same plan through
+    the harmonic decomposition, FP64) and, at the method's accuracy, the
+    direct sums."""
     from oracle import stokes
     say(f"stokes workload {k} n={n} p={p} m2l_rtol={m2l_rtol} {precision}")
     w = workloads.make(k, n=n)
@@ -622,9 +623,11 @@ def test_stokes_parity(built, k, n, leaf, p, m2l_rtol, precision):
     G = Plan(torch.tensor(w.positions, dtype=torch.float64, device="cuda"), "laplace", p, leaf, True, w.max_depth,
              precision=precision, root=w.root, m2l_rtol=m2l_rtol)
     mu = 0.7
-    u = G.evaluate_stokes(torch.tensor(f, dtype=torch.float32, device="cuda"), mu)
+    u, pr = G.evaluate_stokes(torch.tensor(f, dtype=torch.float32, device="cuda"), mu, pressure=True)
     O = kifmm.plan(w.positions, "laplace", p, leaf, True, w.max_depth, w.root, m2l_rtol=m2l_rtol)
-    uo = stokes.kifmm(O, f, mu)
+    uo, po = stokes.kifmm(O, f, mu, pressure=True)
     tol = 1e-4 if (p == 8 or precision == "split_bf16") else 1e-5
     check("u", u, uo, tol)
-    say(f"  against the direct sum: rel-L2 {rel(u.cpu().numpy(), stokes.direct(w.positions, f, mu)):.2e}")
+    check("p", pr, po, tol)
+    say(f"  against the direct sum: rel-L2 u {rel(u.cpu().numpy(), stokes.direct(w.positions, f, mu)):.2e}, "
+        f"p {rel(pr.cpu().numpy(), stokes.pressure_direct(w.positions, f)):.2e}")

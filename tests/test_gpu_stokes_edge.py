@@ -1,8 +1,9 @@
-"""GPU edge cases of the Stokeslet entry point, whose fourth harmonic charge
-is carried about each box's own centre: trees without a far field, shallow
-and deep adaptive trees, repeated calls, rebuilds and the error paths; values
-against the FP64 direct sum where the method is exact there, else against the
-oracle's KIFMM on the same plan."""
+"""GPU edge cases of the Stokeslet entry points (velocity, and velocity with
+pressure), whose fourth harmonic charge is carried about each box's own
+centre: trees without a far field, shallow and deep adaptive trees, repeated
+calls, rebuilds and the error paths; values against the FP64 direct sums
+where the method is exact there, else against the oracle's KIFMM on the same
+plan."""
 import sys
 
 import numpy as np
@@ -33,19 +34,30 @@ def velocity(G, f, mu):
     return v.cpu().numpy()
 
 
+def flow(G, f, mu):
+    v, p = G.evaluate_stokes(torch.tensor(f, dtype=torch.float32, device="cuda"), mu, pressure=True)
+    torch.cuda.synchronize()
+    return v.cpu().numpy(), p.cpu().numpy()
+
+
 def test_stokes_without_far_field():
-    """One point has no velocity; two points and a single leaf of 100 are
-    summed point to point (the Stokeslet pair sum itself)."""
+    """One point has no velocity or pressure; two points and a single leaf of
+    100 are summed point to point (the Stokeslet pair sum itself)."""
     say("Stokes: N = 1, N = 2, one leaf of 100")
     G = gpu_plan(np.array([[0.3, 0.4, 0.5]]))
-    assert np.all(velocity(G, np.array([[1.0, -2.0, 0.5]]), 0.9) == 0.0)
+    v, p = flow(G, np.array([[1.0, -2.0, 0.5]]), 0.9)
+    assert np.all(v == 0.0) and np.all(p == 0.0)
     x = workloads.round_f32(np.array([[0.1, 0.2, 0.3], [0.7, 0.6, 0.2]]))
     f = np.array([[1.0, 0.5, -0.25], [-0.5, 2.0, 1.0]])
-    np.testing.assert_allclose(velocity(gpu_plan(x), f, 0.9), stokes.direct(x, f, 0.9), rtol=1e-6)
+    v, p = flow(gpu_plan(x), f, 0.9)
+    np.testing.assert_allclose(v, stokes.direct(x, f, 0.9), rtol=1e-6)
+    np.testing.assert_allclose(p, stokes.pressure_direct(x, f), rtol=1e-6)
     rng = np.random.default_rng(11)
     x = workloads.round_f32(rng.random((100, 3)))
     f = workloads.round_f32(rng.standard_normal((100, 3)))
-    check("u (one leaf)", velocity(gpu_plan(x, leaf=128), f, 0.9), stokes.direct(x, f, 0.9), 1e-5)
+    v, p = flow(gpu_plan(x, leaf=128), f, 0.9)
+    check("u (one leaf)", v, stokes.direct(x, f, 0.9), 1e-5)
+    check("p (one leaf)", p, stokes.pressure_direct(x, f), 1e-5)
 
 
 @pytest.mark.parametrize("n,leaf,p,precision", [(300, 64, 4, "fp32"), (1200, 64, 4, "fp32"),
@@ -62,7 +74,11 @@ def test_stokes_shallow_and_deep_trees(n, leaf, p, precision):
     depth = G.counts()["depth"]
     say(f"  depth {depth}")
     O = kifmm.plan(w.positions, "laplace", p, leaf, True, 21, w.root)
-    check("u", velocity(G, f, 0.7), stokes.kifmm(O, f, 0.7), 1e-5 if precision == "fp32" else 1e-4)
+    uo, po = stokes.kifmm(O, f, 0.7, pressure=True)
+    u, pr = flow(G, f, 0.7)
+    tol = 1e-5 if precision == "fp32" else 1e-4
+    check("u", u, uo, tol)
+    check("p", pr, po, tol)
 
 
 def test_stokes_repeat_rebuild_and_errors():
@@ -77,6 +93,10 @@ def test_stokes_repeat_rebuild_and_errors():
     G = gpu_plan(w.positions, 6, 32, root=w.root, m2l_rtol=1e-6)
     v1 = velocity(G, f, 0.7)
     assert np.array_equal(v1, velocity(G, f, 0.7))
+    # asking for the pressure leaves the velocity's bits alone; its own repeat
+    v2, p2 = flow(G, f, 0.7)
+    assert np.array_equal(v2, v1)
+    assert np.array_equal(flow(G, f, 0.7)[1], p2)
     x2 = np.clip(workloads.round_f32(w.positions + 0.01 * rng.standard_normal(w.positions.shape)), 0, 0.999)
     G.rebuild(torch.tensor(x2, dtype=torch.float64, device="cuda"))
     H = gpu_plan(x2, 6, 32, root=w.root, m2l_rtol=1e-6)
