@@ -311,9 +311,10 @@ def run_largest(Plan, steps, warmup, m2l_rtol):
 def run_f4(Plan, steps, warmup, m2l_rtol, paths=("split_bf16", "fp32"), check=True, nsample=256):
     """The sums beyond charges on the clustered workload (1,048,576 points,
     p = 6): point dipoles with charges (u, E), the same with dE/dx, and the
-    Stokeslet velocity of point forces.  Per path: ms per call on a fixed plan
-    (no re-tree), then with `check` the oracle on the same plan at `nsample`
-    sampled targets, and the Stokes velocity also against its direct sum there."""
+    Stokeslet velocity of point forces, alone and with the pressure.  Per
+    path: ms per call on a fixed plan (no re-tree), then with `check` the
+    oracle on the same plan at `nsample` sampled targets, and the Stokes
+    velocity and pressure also against their direct sums there."""
     import torch
     import workloads
     w = workloads.make(2)
@@ -330,7 +331,8 @@ def run_f4(Plan, steps, warmup, m2l_rtol, paths=("split_bf16", "fp32"), check=Tr
     fd = torch.tensor(f, dtype=torch.float32, device="cuda")
     calls = {"dipoles": lambda P: P.evaluate_dipoles(q, md),
              "gradient": lambda P: P.evaluate_gradient(q, md),
-             "stokes": lambda P: (P.evaluate_stokes(fd, mu),)}
+             "stokes": lambda P: (P.evaluate_stokes(fd, mu),),
+             "stokes_pressure": lambda P: P.evaluate_stokes(fd, mu, pressure=True)}
     res, outs = {}, {}
     for prec in paths:
         plan = Plan(pos, w.kernel, w.p, w.leaf_size, w.adaptive, w.max_depth, precision=prec, root=w.root,
@@ -354,7 +356,8 @@ def run_f4(Plan, steps, warmup, m2l_rtol, paths=("split_bf16", "fp32"), check=Tr
     out = {"workload": WORKLOADS[2] + "; dipoles N(0,1)*0.1*N^(-1/3) per axis, forces N(0,1) per axis, "
                                       f"viscosity {mu}; call = one evaluation on a fixed plan",
            "n": n, "steps": steps, "warmup": warmup, "m2l_rtol": m2l_rtol, "timing": res,
-           "outputs": {"dipoles": "u, E", "gradient": "u, E, dE/dx", "stokes": "velocity"}}
+           "outputs": {"dipoles": "u, E", "gradient": "u, E, dE/dx", "stokes": "velocity",
+                       "stokes_pressure": "velocity, pressure"}}
     if not check:
         return out
     from oracle import kifmm, stokes
@@ -363,13 +366,14 @@ def run_f4(Plan, steps, warmup, m2l_rtol, paths=("split_bf16", "fp32"), check=Tr
                    periodic=w.periodic, m2l_rtol=m2l_rtol)
     idx = np.sort(np.random.default_rng(21).choice(n, nsample, replace=False))
     uo, Eo, Go = kifmm.forward_dipoles(P, w.charges, m, targets=idx, grad=True)
-    vo, vmag = stokes.kifmm(P, f, mu, targets=idx, terms=True, frame="leaf")
+    vo, vmag, po = stokes.kifmm(P, f, mu, targets=idx, terms=True, frame="leaf", pressure=True)
     t_oracle = time.perf_counter() - t0
     # how much the four-potential combination, about each target's leaf
     # centre as the library forms it, amplifies relative errors of its far
     # fields: the far terms' magnitudes over the velocity
     kappa = float(np.linalg.norm(vmag) / np.linalg.norm(vo))
     vd = stokes.direct(w.positions, f, mu, targets=idx, chunk=4)
+    pd = stokes.pressure_direct(w.positions, f, targets=idx, chunk=4)
 
     def err(a, b):
         return {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
@@ -381,10 +385,14 @@ def run_f4(Plan, steps, warmup, m2l_rtol, paths=("split_bf16", "fp32"), check=Tr
         d = outs[(prec, "dipoles")]
         g = outs[(prec, "gradient")]
         s = outs[(prec, "stokes")][0]
+        sp = outs[(prec, "stokes_pressure")]
         acc[prec] = {"dipoles": {"u": err(d[0][idx], uo), "E": err(d[1][idx], Eo)},
                      "gradient": {"u": err(g[0][idx], uo), "E": err(g[1][idx], Eo), "dE/dx": err(g[2][idx], Go)},
-                     "stokes": {"velocity": err(s[idx], vo), "velocity_vs_direct_sum": err(s[idx], vd)}}
+                     "stokes": {"velocity": err(s[idx], vo), "velocity_vs_direct_sum": err(s[idx], vd)},
+                     "stokes_pressure": {"velocity": err(sp[0][idx], vo), "pressure": err(sp[1][idx], po),
+                                         "pressure_vs_direct_sum": err(sp[1][idx], pd)}}
     acc["oracle_stokes_vs_direct_sum"] = err(vo, vd)
+    acc["oracle_pressure_vs_direct_sum"] = err(po, pd)
     acc["stokes_amplification"] = kappa
     acc["stokes_tolerance"] = {"fp32": 2e-5, "split_bf16": 1e-4,
                                "reading": "the far fields carry about stokes_amplification of the velocity and "
