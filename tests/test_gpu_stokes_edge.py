@@ -84,7 +84,7 @@ def test_stokes_shallow_and_deep_trees(n, leaf, p, precision):
 def test_stokes_repeat_rebuild_and_errors():
     """The same bits on a repeated call and after a rebuild equal to a fresh
     plan's; periodic and gravity plans and a non-positive viscosity are
-    refused with the documented codes."""
+    refused with the documented codes, with and without the pressure."""
     say("Stokes: repeat, rebuild, errors")
     from paper_2512_09478_amd import KifmmError
     w = workloads.make(4, n=6000)
@@ -101,17 +101,20 @@ def test_stokes_repeat_rebuild_and_errors():
     G.rebuild(torch.tensor(x2, dtype=torch.float64, device="cuda"))
     H = gpu_plan(x2, 6, 32, root=w.root, m2l_rtol=1e-6)
     assert np.array_equal(velocity(G, f, 0.7), velocity(H, f, 0.7))
+    assert np.array_equal(flow(G, f, 0.7)[1], flow(H, f, 0.7)[1])
     fd = torch.tensor(f, dtype=torch.float32, device="cuda")
     with pytest.raises(KifmmError) as ei:
         G.evaluate_stokes(fd, 0.0)
     assert ei.value.code == -1
+    with pytest.raises(KifmmError) as ei:
+        G.evaluate_stokes(fd, -1.0, pressure=True)
+    assert ei.value.code == -1
     P = gpu_plan(w.positions, 4, 32, root=w.root, periodic=True)
-    with pytest.raises(KifmmError) as ei:
-        P.evaluate_stokes(fd, 1.0)
-    assert ei.value.code == -5
     Q = gpu_plan(w.positions, 4, 32, root=w.root, kernel="gravity")
-    with pytest.raises(KifmmError) as ei:
-        Q.evaluate_stokes(fd, 1.0)
-    assert ei.value.code == -5
+    for plan in (P, Q):
+        for pressure in (False, True):
+            with pytest.raises(KifmmError) as ei:
+                plan.evaluate_stokes(fd, 1.0, pressure=pressure)
+            assert ei.value.code == -5
     # the refused calls leave the plan usable
     assert np.array_equal(velocity(H, f, 0.7), velocity(G, f, 0.7))
