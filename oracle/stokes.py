@@ -30,6 +30,16 @@ mu lap u = grad p, div u = 0 hold away from the forces) is
 ``pressure_direct`` written out; through the same decomposition it is
 -(1/4 pi) sum_k d_k phi_k, the trace of the fields of the first three
 charges, which ``kifmm`` returns with ``pressure``.
+
+The velocity gradient g_ab = d u_a / d x_b of the Stokeslet sum,
+
+    g_ab = 1/(8 pi mu) sum_j [ (f_b r_a - f_a r_b + (r . f) delta_ab) / r^3
+                               - 3 (r . f) r_a r_b / r^5 ],
+
+is ``gradient_direct``; differentiating the decomposition gives
+g_ab = (-E(a)_b + E(b)_a + x'_k dE(k)_a/dx_b - dE(4)_a/dx_b) / (8 pi mu c),
+the fields and field gradients of the four charges, which ``kifmm`` returns
+with ``grad``.
 """
 from __future__ import annotations
 
@@ -73,6 +83,30 @@ def pressure_direct(x, f, targets=None, chunk=512):
     return out / (4.0 * math.pi)
 
 
+def gradient_direct(x, f, mu=1.0, targets=None, chunk=256):
+    """Velocity gradient [nt, 3, 3], entry [a, b] = d u_a / d x_b, at the
+    points ``targets`` (all by default)."""
+    x = np.asarray(x, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64).reshape(-1, 3)
+    t = np.arange(x.shape[0]) if targets is None else np.asarray(targets)
+    out = np.zeros((t.shape[0], 3, 3))
+    eye = np.eye(3)
+    for a in range(0, t.shape[0], chunk):
+        xt = x[t[a:a + chunk]]
+        r = xt[:, None, :] - x[None, :, :]
+        r2 = np.einsum("ijk,ijk->ij", r, r)
+        inv3 = np.zeros_like(r2)
+        nz = r2 > 0
+        inv3[nz] = r2[nz] ** -1.5
+        inv5 = np.zeros_like(r2)
+        inv5[nz] = r2[nz] ** -2.5
+        rf = np.einsum("ijk,jk->ij", r, f)
+        g = (np.einsum("ij,jb,ija->iab", inv3, f, r) - np.einsum("ij,ja,ijb->iab", inv3, f, r)
+             + np.einsum("ij,ab->iab", rf * inv3, eye) - 3.0 * np.einsum("ij,ija,ijb->iab", rf * inv5, r, r))
+        out[a:a + chunk] = g
+    return out / (8.0 * math.pi * mu)
+
+
 def origin(P):
     """The fixed origin of the decomposition: the root cube's centre."""
     return P.tree.lo + 0.5 * P.tree.s
@@ -91,7 +125,7 @@ def leaf_centres(P, targets=None):
     return np.array([t.center(int(b)) for b in leaf_of[idx]]).reshape(-1, 3)
 
 
-def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root", pressure=False):
+def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root", pressure=False, grad=False):
     """The Stokeslet sum through four Laplace evaluations of the oracle plan
     ``P`` (its kernel constant c = P.c): u = (1/(8 pi mu c)) [psi_a +
     x'_k E(k)_a - E(4)_a], psi_k and E(k) = -grad psi_k the plan's potential
@@ -107,14 +141,19 @@ def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root", pressure=False)
     E(4) + (o - c)_k E(k) and x' = x - c (the same velocity).
 
     With ``pressure`` the pressure p = (1/(4 pi c)) sum_k E(k)_k (k = 1, 2,
-    3) is returned last."""
+    3) is returned after those; with ``grad`` last the velocity gradient
+    [.., 3, 3] (entry [a, b] = d u_a / d x_b) from the four charges' fields
+    and field gradients (one sweep with the field gradient per charge)."""
     from . import kifmm as K
     f = np.asarray(f, dtype=np.float64).reshape(-1, 3)
     o = origin(P)
     xs = P.x[np.argsort(P.tree.perm)]          # caller order
     xp = xs - o
     charges = [f[:, 0], f[:, 1], f[:, 2], np.einsum("ij,ij->i", xp, f)]
-    res = [K.forward(P, q, targets=targets) for q in charges]
+    if grad:
+        res = [K.forward_dipoles(P, q, None, targets=targets, grad=True) for q in charges]
+    else:
+        res = [K.forward(P, q, targets=targets) for q in charges]
     xt = xp if targets is None else xp[np.asarray(targets)]
     u = np.stack([res[a][0] for a in range(3)], axis=1)
     for k in range(3):
@@ -124,6 +163,22 @@ def kifmm(P, f, mu=1.0, targets=None, terms=False, frame="root", pressure=False)
     extra = ()
     if pressure:
         extra = (sum(res[k][1][:, k] for k in range(3)) / (4.0 * math.pi * P.c),)
+    if grad:
+        def full(G6):
+            # (xx yy zz xy xz yz) -> symmetric [.., 3, 3]
+            G = np.empty(G6.shape[:-1] + (3, 3))
+            for a, b, c in ((0, 0, 0), (1, 1, 1), (2, 2, 2), (0, 1, 3), (0, 2, 4), (1, 2, 5)):
+                G[..., a, b] = G[..., b, a] = G6[..., c]
+            return G
+        E = [res[k][1] for k in range(4)]
+        Gk = [full(res[k][2]) for k in range(4)]
+        g = np.zeros(E[0].shape[:-1] + (3, 3))
+        for a in range(3):
+            for b in range(3):
+                g[:, a, b] = -E[a][:, b] + E[b][:, a] - Gk[3][:, a, b]
+        for k in range(3):
+            g += xt[:, k, None, None] * Gk[k]
+        extra = extra + (g * s,)
     if not terms:
         return (u * s,) + extra if extra else u * s
     if frame not in ("root", "leaf"):

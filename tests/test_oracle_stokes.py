@@ -1,7 +1,8 @@
 """Pins of the Stokeslet oracle (CPU only): the direct sum against closed
 forms of Stokes flow, the divergence-free velocity, the pressure through the
-Stokes equations, the kernel's symmetry, and the harmonic decomposition that
-the fast evaluation uses."""
+Stokes equations, the velocity gradient as the velocity's derivative, the
+kernel's symmetry, and the harmonic decomposition that the fast evaluation
+uses."""
 import math
 
 import numpy as np
@@ -121,6 +122,43 @@ def test_pressure_satisfies_the_stokes_equations():
         scale = np.linalg.norm(grad_p)
         assert np.linalg.norm(mu * lap_u - grad_p) <= 1e-6 * scale
         assert abs(lap_p[0]) <= 1e-6 * scale / 0.25
+
+
+def test_velocity_gradient_is_the_derivative_of_the_velocity():
+    """The direct velocity gradient equals Richardson differences of the
+    direct velocity, and its trace (the divergence) vanishes."""
+    rng = np.random.default_rng(15)
+    x = rng.random((120, 3))
+    f = rng.standard_normal((120, 3))
+    mu = 0.7
+    X = np.concatenate([x, np.zeros((1, 3))])
+    F = np.concatenate([f, np.zeros((1, 3))])
+
+    def vel(q):
+        X[-1] = q
+        return stokes.direct(X, F, mu, targets=[120])[0]
+
+    for p in rng.random((3, 3)) * 0.3 + 1.25:
+        fd, _ = _richardson(vel, p, 2e-3)
+        X[-1] = p
+        g = stokes.gradient_direct(X, F, mu, targets=[120])[0]
+        assert np.abs(fd.T - g).max() <= 1e-8 * np.abs(g).max()
+        assert abs(np.trace(g)) <= 1e-12 * np.abs(g).max()
+
+
+def test_kifmm_velocity_gradient_converges_to_the_direct_sum():
+    """The oracle KIFMM's velocity gradient (fields and field gradients of
+    the four harmonic charges) converges to the direct one with p."""
+    w = workloads.make(2, n=3000)
+    f = workloads.round_f32(np.random.default_rng(16).standard_normal((w.n, 3)))
+    idx = np.arange(0, w.n, 23)
+    gd = stokes.gradient_direct(w.positions, f, 0.7, targets=idx)
+    err = []
+    for p in (4, 6, 8):
+        P = kifmm.plan(w.positions, "laplace", p, 64, True, 21, w.root)
+        err.append(rel(stokes.kifmm(P, f, 0.7, targets=idx, grad=True)[1], gd))
+    assert err[0] > 10 * err[1] > 5 * err[2]
+    assert err[1] < 5e-5 and err[2] < 5e-6
 
 
 def test_symmetry_of_the_kernel():
